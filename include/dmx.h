@@ -1,0 +1,175 @@
+/* dmx: batched differentiable soft-contact rigid-body rollouts on MI355X.
+ *
+ * The library integrates the ODE x' = F(t, x) of a penalty/soft-constraint
+ * rigid-body simulator (state x = [q, v]; equation of motion of Sec. 2 with the
+ * contact forces of the relaxed-Gauss primal problem and the reference
+ * acceleration of Sec. 2.1) over piecewise-constant controls with an adaptive
+ * Dormand-Prince 5(4) scheme and a PI step controller (Sec. 3.1, App. C.2),
+ * for a batch of independent worlds, each with its own step sizes (App. D,
+ * "Parallelizing DiffMJX simulations").  dmx_rollout_vjp returns the gradient
+ * of the discretized rollout (discretize-then-optimize, App. C.2), optionally
+ * with the contacts-from-distance straight-through rule (Sec. 4).
+ *
+ * Conventions
+ *  - All floating point is FP64.  Unless stated otherwise pointers to state,
+ *    control and gradient arrays are DEVICE pointers owned by the caller; they
+ *    are read/written in order on `stream` and must stay valid until the work
+ *    on the stream completes.  The library never frees caller memory.
+ *  - State layout: x is world-major [n_worlds][nq + nv]; q holds, per joint in
+ *    model order, a free joint's world position and unit quaternion (w,x,y,z)
+ *    or a hinge/slide coordinate; v holds a free joint's world linear velocity
+ *    of the body origin and body-frame angular velocity, or a hinge/slide rate.
+ *  - Controls u are [n_worlds][n_intervals][nu]: generalized forces on the
+ *    model's control dofs, constant over each interval of length interval_dt.
+ *  - Errors: API-level errors are returned as a negative dmx_status with a
+ *    message from dmx_last_error(); nothing is launched then.  Numerical
+ *    failures of single worlds do not fail the call: they set bits of that
+ *    world's status word and leave its state at the point of termination.
+ *  - Thread safety: models are immutable after creation and may be shared;
+ *    a tape belongs to one caller at a time.
+ */
+#ifndef DMX_H
+#define DMX_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmx_status;
+enum {
+  DMX_OK = 0,
+  DMX_PENDING = 1,
+  DMX_ERR_INVALID_ARG = -1,
+  DMX_ERR_OUT_OF_MEMORY = -2,
+  DMX_ERR_HIP = -3,
+  DMX_ERR_BUDGET = -4,
+  DMX_ERR_NOT_FOUND = -5,
+  DMX_ERR_UNSUPPORTED = -6
+};
+
+/* per-world status bits */
+enum {
+  DMX_W_MAX_STEPS = 1,      /* step-attempt budget exhausted */
+  DMX_W_DT_UNDERFLOW = 2,   /* step size fell below 1e-12 max(1, |t|) */
+  DMX_W_NONFINITE = 4,      /* non-finite state or singular mass matrix */
+  DMX_W_SOLVER_MAXIT = 8,   /* contact Newton solve hit its iteration cap */
+  DMX_W_TAPE_OVERFLOW = 32  /* more accepted steps than the tape holds */
+};
+
+enum { DMX_JOINT_FREE = 0, DMX_JOINT_HINGE = 1, DMX_JOINT_SLIDE = 2 };
+enum { DMX_GEOM_PLANE = 0, DMX_GEOM_SPHERE = 1, DMX_GEOM_CAPSULE = 2, DMX_GEOM_BOX = 3 };
+
+/* Host-side model description (all pointers HOST memory, read during the call).
+ * Bodies are listed parents first (parent -1 = world).  Each body's mass and
+ * inertia are those of a uniform solid primitive (iner_type/iner_size/
+ * iner_quat; mass <= 0 means density 1000 kg/m^3) about the body origin.
+ * Joints are grouped by body, in body order, applied in order.  Geom sizes:
+ * sphere (r), capsule (r, half-length along local z), box (half sizes).
+ * Pairs list (g1, g2) with g1 a plane fixed to the world; the contact normal
+ * points from g1 to g2.  solref = (time constant t_c, damping ratio);
+ * solimp = (d0, dwidth, width, midpoint, power) of the impedance spline;
+ * cfd = (d_c, d_0, w_c, m_c, p_c) of the contacts-from-distance spline (Sec. 4).
+ * Control i is a generalized force on dof ctrl_dof[i]. */
+typedef struct {
+  int32_t nbody, njnt, ngeom, npair, nu;
+  const int32_t* body_parent;
+  const double* body_pos;        /* nbody*3 */
+  const double* body_quat;       /* nbody*4 */
+  const int32_t* body_iner_type; /* DMX_GEOM_SPHERE/CAPSULE/BOX */
+  const double* body_iner_size;  /* nbody*3 */
+  const double* body_iner_quat;  /* nbody*4 */
+  const double* body_mass;       /* nbody */
+  const int32_t* jnt_body;
+  const int32_t* jnt_type;
+  const double* jnt_axis;        /* njnt*3, body frame */
+  const double* jnt_pos;         /* njnt*3, body frame */
+  const int32_t* geom_body;
+  const int32_t* geom_type;
+  const double* geom_size;       /* ngeom*3 */
+  const double* geom_pos;        /* ngeom*3 */
+  const double* geom_quat;       /* ngeom*4 */
+  const int32_t* pair_g1;
+  const int32_t* pair_g2;
+  const double* pair_mu;
+  const double* pair_solref;     /* npair*2 */
+  const double* pair_solimp;     /* npair*5 */
+  const double* pair_cfd;        /* npair*5 */
+  const int32_t* ctrl_dof;       /* nu */
+  double gravity[3];
+} dmx_model_desc;
+
+typedef struct dmx_model dmx_model;
+typedef struct dmx_tape dmx_tape;
+
+/* Integrator options (App. E.1 names the PID controller P = 0.2, I = 0.4,
+ * D = 0; the controller is used in PI form with the error exponent K).
+ * dmx_default_opts fills: rtol 1e-6, atol 1e-8, h0 1e-3, safety 0.9,
+ * facmin 0.2, facmax 10, kP 0.2, kI 0.4, err_order 5, err_floor 1e-6,
+ * max_attempts 1e6, newton_maxit 100, cfd 0, softplus_beta 1e4,
+ * tape_steps 0 (= chosen by the library), lanes_per_world 0 (= autotuned). */
+typedef struct {
+  double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor;
+  int64_t max_attempts;
+  int32_t newton_maxit;
+  int32_t cfd;            /* 1: gradients use the contacts-from-distance field (straight-through) */
+  double softplus_beta;   /* sharpness of the CFD position term, 1/m */
+  int64_t tape_steps;     /* per-world tape capacity in accepted steps; 0 = library choice */
+  int32_t lanes_per_world;/* team size (1,2,4,8,16); 0 = pick per model */
+  /* test hooks (device pointers, may be NULL):
+   * forced: [n_worlds][forced_cap][2] (t_n, h_n) accepted steps to replay with
+   *         the controller off, forced_n[n_worlds] steps per world; a world's
+   *         rollout ends after its last listed step;
+   * steplog: [n_worlds][log_cap][4] (t, h, err, accepted) per attempt,
+   *         log_n[n_worlds] attempts recorded. */
+  const double* forced;
+  const int32_t* forced_n;
+  int32_t forced_cap;
+  double* steplog;
+  int32_t* log_n;
+  int32_t log_cap;
+} dmx_solver_opts;
+
+void dmx_default_opts(dmx_solver_opts* opts);
+
+/* Compile a model (inertia, inverse weights, pair tables) and upload it to
+ * the current device.  Returns DMX_ERR_UNSUPPORTED for model shapes the
+ * compiled kernels do not cover. */
+dmx_status dmx_model_create(const dmx_model_desc* desc, dmx_model** out);
+/* nq, nv, nu, max_contacts */
+dmx_status dmx_model_info(const dmx_model* model, int32_t* nq, int32_t* nv, int32_t* nu, int32_t* max_contacts);
+void dmx_model_destroy(dmx_model* model);
+
+/* Forward rollout of n_worlds worlds of one model over n_intervals control
+ * intervals of interval_dt seconds each.  x0 [W][nx], u [W][n_intervals][nu]
+ * (may be NULL when nu == 0), x_out [W][nx], world_status [W].  If tape is
+ * non-NULL a tape (device memory owned by the library) is created holding
+ * every accepted step and its stage accelerations, for dmx_rollout_vjp.
+ * Per-world step counters: n_accepted, n_rejected ([W] int32, device, may be NULL). */
+dmx_status dmx_rollout(const dmx_model* model, int32_t n_worlds, int32_t n_intervals, double interval_dt,
+                       const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
+                       int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
+                       void* stream);
+
+/* Gradient of sum(x_out_bar * x_out) with respect to x0 and u through the
+ * recorded discretization (step sizes held fixed; rejected attempts play no
+ * part).  x0_bar [W][nx] and u_bar [W][n_intervals][nu] are overwritten.
+ * Worlds whose forward status is nonzero get NaN gradients.  May be called
+ * any number of times on one tape. */
+dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
+
+/* Sizes of a tape: per-world capacity and record length in doubles. */
+dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t* record_doubles);
+/* Device pointer to the tape records [W][steps_per_world][record] with records
+ * (t_n, h_n, interval, y_n[nx], a_1..a_6[nv]) and the per-world accepted-step
+ * counts [W] (int32). */
+dmx_status dmx_tape_data(const dmx_tape* tape, const double** records, const int32_t** n_steps);
+void dmx_tape_destroy(dmx_tape* tape);
+
+/* Thread-local message of the last failed call. */
+const char* dmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

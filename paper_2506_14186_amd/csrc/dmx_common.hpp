@@ -1,0 +1,187 @@
+// Device helpers: 3-vectors, quaternions, team (lanes-of-one-world) reductions.
+//
+// A "team" is L consecutive lanes of a 64-wide wavefront that cooperate on one
+// world (L divides 64).  Replicated per-world values must stay bitwise equal
+// across the team, so every team reduction is a butterfly of pairwise sums
+// a + b / b + a (commutative, hence identical on both lanes of a pair).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DMX_DEV __device__ __forceinline__
+
+namespace dmx {
+
+struct V3 { double x, y, z; };
+DMX_DEV V3 mk3(double a, double b, double c) { V3 r; r.x = a; r.y = b; r.z = c; return r; }
+DMX_DEV V3 operator+(V3 a, V3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+DMX_DEV V3 operator-(V3 a, V3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+DMX_DEV V3 operator*(double s, V3 a) { return mk3(s * a.x, s * a.y, s * a.z); }
+DMX_DEV V3& operator+=(V3& a, V3 b) { a.x += b.x; a.y += b.y; a.z += b.z; return a; }
+DMX_DEV V3& operator-=(V3& a, V3 b) { a.x -= b.x; a.y -= b.y; a.z -= b.z; return a; }
+DMX_DEV double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+DMX_DEV V3 cross(V3 a, V3 b) { return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+DMX_DEV V3 ld3(const double* p) { return mk3(p[0], p[1], p[2]); }
+
+// row-major 3x3
+struct M3 { double a[9]; };
+DMX_DEV V3 mul(const M3& m, V3 v) {
+  return mk3(m.a[0] * v.x + m.a[1] * v.y + m.a[2] * v.z, m.a[3] * v.x + m.a[4] * v.y + m.a[5] * v.z,
+             m.a[6] * v.x + m.a[7] * v.y + m.a[8] * v.z);
+}
+DMX_DEV V3 mulT(const M3& m, V3 v) {
+  return mk3(m.a[0] * v.x + m.a[3] * v.y + m.a[6] * v.z, m.a[1] * v.x + m.a[4] * v.y + m.a[7] * v.z,
+             m.a[2] * v.x + m.a[5] * v.y + m.a[8] * v.z);
+}
+DMX_DEV void outer_add(M3& m, V3 a, V3 b) {  // m += a b^T
+  m.a[0] += a.x * b.x; m.a[1] += a.x * b.y; m.a[2] += a.x * b.z;
+  m.a[3] += a.y * b.x; m.a[4] += a.y * b.y; m.a[5] += a.y * b.z;
+  m.a[6] += a.z * b.x; m.a[7] += a.z * b.y; m.a[8] += a.z * b.z;
+}
+
+struct Q4 { double w, x, y, z; };
+DMX_DEV Q4 mkq(double w, double x, double y, double z) { Q4 q; q.w = w; q.x = x; q.y = y; q.z = z; return q; }
+DMX_DEV Q4 qmul(Q4 a, Q4 b) {
+  return mkq(a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z, a.w * b.x + a.x * b.w + a.y * b.z - a.z * b.y,
+             a.w * b.y - a.x * b.z + a.y * b.w + a.z * b.x, a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w);
+}
+DMX_DEV Q4 qconj(Q4 a) { return mkq(a.w, -a.x, -a.y, -a.z); }
+DMX_DEV double qdot(Q4 a, Q4 b) { return a.w * b.w + a.x * b.x + a.y * b.y + a.z * b.z; }
+DMX_DEV Q4 qscale(double s, Q4 a) { return mkq(s * a.w, s * a.x, s * a.y, s * a.z); }
+DMX_DEV Q4 qadd(Q4 a, Q4 b) { return mkq(a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z); }
+
+// Rotation matrix (body -> world) of a unit quaternion.
+DMX_DEV M3 quat2mat(Q4 q) {
+  M3 m;
+  double ww = q.w * q.w, xx = q.x * q.x, yy = q.y * q.y, zz = q.z * q.z;
+  double wx = q.w * q.x, wy = q.w * q.y, wz = q.w * q.z, xy = q.x * q.y, xz = q.x * q.z, yz = q.y * q.z;
+  m.a[0] = ww + xx - yy - zz; m.a[1] = 2.0 * (xy - wz); m.a[2] = 2.0 * (xz + wy);
+  m.a[3] = 2.0 * (xy + wz); m.a[4] = ww - xx + yy - zz; m.a[5] = 2.0 * (yz - wx);
+  m.a[6] = 2.0 * (xz - wy); m.a[7] = 2.0 * (yz + wx); m.a[8] = ww - xx - yy + zz;
+  return m;
+}
+// Cotangent of the quaternion given the cotangent Rb of quat2mat(q).
+DMX_DEV Q4 quat2mat_vjp(Q4 q, const M3& Rb) {
+  const double* b = Rb.a;
+  Q4 g;
+  g.w = 2.0 * (q.w * (b[0] + b[4] + b[8]) + q.x * (b[7] - b[5]) + q.y * (b[2] - b[6]) + q.z * (b[3] - b[1]));
+  g.x = 2.0 * (q.x * (b[0] - b[4] - b[8]) + q.w * (b[7] - b[5]) + q.y * (b[1] + b[3]) + q.z * (b[2] + b[6]));
+  g.y = 2.0 * (q.y * (-b[0] + b[4] - b[8]) + q.w * (b[2] - b[6]) + q.x * (b[1] + b[3]) + q.z * (b[5] + b[7]));
+  g.z = 2.0 * (q.z * (-b[0] - b[4] + b[8]) + q.w * (b[3] - b[1]) + q.x * (b[2] + b[6]) + q.y * (b[5] + b[7]));
+  return g;
+}
+// y = x / |x| and its cotangent map
+DMX_DEV Q4 qnormalize(Q4 x, double* inv_norm) {
+  double n = sqrt(qdot(x, x));
+  double s = 1.0 / n;
+  if (inv_norm) *inv_norm = s;
+  return qscale(s, x);
+}
+DMX_DEV Q4 qnormalize_vjp(Q4 y, double inv_norm, Q4 yb) { return qscale(inv_norm, qadd(yb, qscale(-qdot(y, yb), y))); }
+
+// exp of half a rotation vector th: (cos(|th|/2), sin(|th|/2)/|th| th), with a
+// Taylor series in |th|^2 below |th| = 1e-4 (finite derivatives at zero).
+DMX_DEV Q4 qexp_half(V3 th, double* cs, double* sn, double* dcs, double* dsn) {
+  double t2 = dot(th, th);
+  double c, s, dc, ds;  // c(t2), s(t2) and their derivatives with respect to t2
+  if (t2 < 1e-8) {
+    c = 1.0 - t2 / 8.0 + t2 * t2 / 384.0;
+    s = 0.5 - t2 / 48.0 + t2 * t2 / 3840.0;
+    dc = -1.0 / 8.0 + t2 / 192.0;
+    ds = -1.0 / 48.0 + t2 / 1920.0;
+  } else {
+    double phi = sqrt(t2);
+    double ch = cos(0.5 * phi), sh = sin(0.5 * phi);
+    c = ch;
+    s = sh / phi;
+    // d/dt2 = (1 / (2 phi)) d/dphi
+    dc = -0.5 * sh * 0.5 / phi;
+    ds = (0.5 * ch / phi - sh / (phi * phi)) * 0.5 / phi;
+  }
+  if (cs) { *cs = c; *sn = s; *dcs = dc; *dsn = ds; }
+  return mkq(c, s * th.x, s * th.y, s * th.z);
+}
+
+// ----------------------------------------------------------------- team ops
+template <int CTRL>
+DMX_DEV double dpp_f64(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the L lanes of a team; every lane receives the bitwise-same value.
+template <int L>
+DMX_DEV double team_sum(double v) {
+  if constexpr (L >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  if constexpr (L >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  if constexpr (L >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: other quad of 8
+  if constexpr (L >= 16) v += dpp_f64<0x140>(v); // row_mirror: other half of 16
+  if constexpr (L >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+template <int L, int N>
+DMX_DEV void team_sum_arr(double* v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = team_sum<L>(v[i]);
+}
+
+// Team-wide boolean reductions through the wave ballot.
+template <int L>
+DMX_DEV uint64_t team_bits(bool p) {
+  uint64_t b = __ballot(p);
+  if constexpr (L == 64) return b;
+  const int base = (threadIdx.x & 63) & ~(L - 1);
+  return (b >> base) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull));
+}
+template <int L> DMX_DEV bool team_any(bool p) { return team_bits<L>(p) != 0ull; }
+template <int L> DMX_DEV bool team_all(bool p) {
+  if constexpr (L == 64) return __ballot(!p) == 0ull;
+  return team_bits<L>(p) == ((1ull << L) - 1ull);
+}
+
+// Dense symmetric positive definite Cholesky (lower, row-major N x N) and solve.
+template <int N>
+DMX_DEV bool chol(double* A) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = A[j * N + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= A[j * N + k] * A[j * N + k];
+    ok = ok && (s > 0.0);
+    double d = sqrt(s > 0.0 ? s : 1e-300);
+    double inv = 1.0 / d;
+    A[j * N + j] = d;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      double t = A[i * N + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= A[i * N + k] * A[j * N + k];
+      A[i * N + j] = t * inv;
+    }
+  }
+  return ok;
+}
+template <int N>
+DMX_DEV void chol_solve(const double* Lm, double* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= Lm[i * N + k] * x[k];
+    x[i] = s / Lm[i * N + i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) s -= Lm[k * N + i] * x[k];
+    x[i] = s / Lm[i * N + i];
+  }
+}
+
+}  // namespace dmx

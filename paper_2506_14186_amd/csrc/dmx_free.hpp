@@ -1,0 +1,569 @@
+// Free-body worlds: one body on a free joint touching world planes through
+// sphere and capsule geoms.  Forward acceleration (team-parallel over contact
+// slots) and its vector-Jacobian product.
+//
+// Physics (paper Sec. 2 and 2.1):
+//  - v = (world linear velocity of the body origin, body-frame angular
+//    velocity); with the centre of mass at the origin M = diag(m I3, I_body)
+//    is constant and the bias is c = (-m g, w x I w).
+//  - contacts with signed distance r < 0 (r < w_c for the CFD field) produce
+//    the 4 edge rows J_n +- mu J_t of a pyramidal cone; a_ref = -b J v - k r,
+//    b = 2/(d_w t_c), k = d(r)/(d_w^2 t_c^2 phi^2), R = A (1-d)/d, D = 1/R.
+//  - the acceleration is the minimizer of the convex primal problem
+//    1/2 |x - a0|_M^2 + sum_e 1/2 D_e min(0, J_e x - a_ref_e)^2, found by an
+//    exact Newton method (Sec. 2.1).
+#pragma once
+#include "dmx_common.hpp"
+
+namespace dmx {
+
+constexpr int kMaxPairs = 16;
+constexpr int kMaxSlots = 32;
+
+struct PairF {
+  int gtype, ncon;
+  double l[3];     // geom centre, body frame
+  double ax[3];    // capsule: half-length * axis, body frame
+  double rad;
+  double p0[3], n[3], t1[3], t2[3];  // world plane point, contact normal and tangents
+  double mu, bcoef, kscale, ahat;
+  double si[5], cf[5];
+};
+
+struct FreeModel {
+  int np, nc, nu;
+  int cpair[kMaxSlots], csub[kMaxSlots];
+  int ctrl[8];
+  double mass, I[9], Iinv[9], grav[3];
+  PairF pair[kMaxPairs];
+};
+
+struct Stat {
+  int newton_it;
+  int status;
+};
+
+// ------------------------------------------------------------ impedance
+// MuJoCo-style polynomial spline y(x) on [0, 1] with midpoint and power, and dy/dx.
+DMX_DEV double imp_spline(double x, double mid, double pw, double* dydx) {
+  if (x >= 1.0) { *dydx = 0.0; return 1.0; }
+  if (x <= 0.0) { *dydx = 0.0; return 0.0; }
+  if (x <= mid) {
+    double s = 1.0 / pow(mid, pw - 1.0);
+    *dydx = pw * pow(x, pw - 1.0) * s;
+    return pow(x, pw) * s;
+  }
+  double s = 1.0 / pow(1.0 - mid, pw - 1.0);
+  *dydx = pw * pow(1.0 - x, pw - 1.0) * s;
+  return 1.0 - pow(1.0 - x, pw) * s;
+}
+
+// Impedance d(r) and dd/dr.  Penetration (r < 0): solimp spline of -r/width
+// from d0 to dwidth.  Contacts from distance (r >= 0, CFD field only): the
+// continuation from d_0 at r = 0 to d_c at r = w_c.
+DMX_DEV double impedance(const PairF& p, double r, double* ddr) {
+  double dy;
+  if (r < 0.0) {
+    double x = -r / p.si[2];
+    double y = imp_spline(x, p.si[3], p.si[4], &dy);
+    *ddr = -dy / p.si[2] * (p.si[1] - p.si[0]);
+    return p.si[0] + y * (p.si[1] - p.si[0]);
+  }
+  double x = r / p.cf[2];
+  double y = imp_spline(x, p.cf[3], p.cf[4], &dy);
+  *ddr = dy / p.cf[2] * (p.cf[0] - p.cf[1]);
+  return p.cf[1] + y * (p.cf[0] - p.cf[1]);
+}
+
+DMX_DEV double softplus(double z, double beta, double* dsp) {
+  double bz = beta * z;
+  if (bz > 30.0) {
+    double e = exp(-bz);
+    *dsp = 1.0 / (1.0 + e);
+    return z + log1p(e) / beta;
+  }
+  double e = exp(bz);
+  *dsp = e / (1.0 + e);
+  return log1p(e) / beta;
+}
+
+// ------------------------------------------------------------ contact rows
+template <int CPL>
+struct FreeRows {
+  bool on[CPL];
+  int slot[CPL];
+  double r[CPL], mu[CPL], D[CPL];
+  double Jn[CPL][6], Jt1[CPL][6], Jt2[CPL][6];
+  double aref[CPL][4];
+};
+
+DMX_DEV void edge_row(const double* Jn, const double* Jt1, const double* Jt2, double mu, int e, double* Je) {
+  const double* Jt = (e < 2) ? Jt1 : Jt2;
+  double s = (e & 1) ? -mu : mu;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) Je[i] = Jn[i] + s * Jt[i];
+}
+DMX_DEV double dot6(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
+}
+
+// Contact point of slot c: the sphere (or capsule end sphere) centre in the
+// world, signed distance to the plane and the midpoint between the surfaces.
+DMX_DEV void slot_geom(const FreeModel& m, int c, V3 p, const M3& R, V3* lc, V3* ctr, double* r, V3* P) {
+  const PairF& pr = m.pair[m.cpair[c]];
+  V3 l = ld3(pr.l);
+  if (pr.gtype == 2) l = (m.csub[c] == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
+  V3 ce = p + mul(R, l);
+  V3 n = ld3(pr.n);
+  double rr = dot(n, ce - ld3(pr.p0)) - pr.rad;
+  *lc = l;
+  *ctr = ce;
+  *r = rr;
+  *P = ce - (pr.rad + 0.5 * rr) * n;
+}
+
+// Rows of this lane's contact slots at (q, v).  J_u = [u, R^T (d x u)] for a
+// frame direction u, with d the contact point relative to the body origin.
+template <int CPL, int L>
+DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, bool cfd, double beta,
+                       FreeRows<CPL>& rw) {
+  const int tl = threadIdx.x & (L - 1);
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    int c = tl + k * L;
+    rw.slot[k] = c;
+    rw.on[k] = false;
+    if (c >= m.nc) continue;
+    const PairF& pr = m.pair[m.cpair[c]];
+    V3 lc, ce, P;
+    double r;
+    slot_geom(m, c, p, R, &lc, &ce, &r, &P);
+    rw.r[k] = r;
+    bool on = cfd ? (r < pr.cf[2]) : (r < 0.0);
+    rw.on[k] = on;
+    if (!on) continue;
+    V3 d = P - p;
+    V3 n = ld3(pr.n), t1 = ld3(pr.t1), t2 = ld3(pr.t2);
+    V3 wn = mulT(R, cross(d, n)), w1 = mulT(R, cross(d, t1)), w2 = mulT(R, cross(d, t2));
+    double* Jn = rw.Jn[k];
+    double* Ja = rw.Jt1[k];
+    double* Jb = rw.Jt2[k];
+    Jn[0] = n.x; Jn[1] = n.y; Jn[2] = n.z; Jn[3] = wn.x; Jn[4] = wn.y; Jn[5] = wn.z;
+    Ja[0] = t1.x; Ja[1] = t1.y; Ja[2] = t1.z; Ja[3] = w1.x; Ja[4] = w1.y; Ja[5] = w1.z;
+    Jb[0] = t2.x; Jb[1] = t2.y; Jb[2] = t2.z; Jb[3] = w2.x; Jb[4] = w2.y; Jb[5] = w2.z;
+    double ddr;
+    double dimp = impedance(pr, r, &ddr);
+    double kk = dimp * pr.kscale;
+    rw.mu[k] = pr.mu;
+    rw.D[k] = dimp / (pr.ahat * (1.0 - dimp));
+    double pterm;
+    if (cfd) { double dsp; pterm = kk * softplus(-r, beta, &dsp); }
+    else pterm = -kk * r;
+    double jnv = dot6(Jn, v), j1v = dot6(Ja, v), j2v = dot6(Jb, v);
+    rw.aref[k][0] = -pr.bcoef * (jnv + pr.mu * j1v) + pterm;
+    rw.aref[k][1] = -pr.bcoef * (jnv - pr.mu * j1v) + pterm;
+    rw.aref[k][2] = -pr.bcoef * (jnv + pr.mu * j2v) + pterm;
+    rw.aref[k][3] = -pr.bcoef * (jnv - pr.mu * j2v) + pterm;
+  }
+}
+
+// y = M x for the constant free-body mass matrix
+DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
+  y[0] = m.mass * x[0]; y[1] = m.mass * x[1]; y[2] = m.mass * x[2];
+  y[3] = m.I[0] * x[3] + m.I[1] * x[4] + m.I[2] * x[5];
+  y[4] = m.I[3] * x[3] + m.I[4] * x[4] + m.I[5] * x[5];
+  y[5] = m.I[6] * x[3] + m.I[7] * x[4] + m.I[8] * x[5];
+}
+
+// packed lower triangle index
+DMX_DEV constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// H = M + sum over this team's active edges of D J_e J_e^T, as a dense 6x6.
+template <int CPL, int L>
+DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* H) {
+  double hp[21];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) hp[i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (!((act[k] >> e) & 1u)) continue;
+      double Je[6];
+      edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
+      double D = rw.D[k];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double di = D * Je[i];
+#pragma unroll
+        for (int j = 0; j <= i; ++j) hp[tri(i, j)] += di * Je[j];
+      }
+    }
+  }
+  team_sum_arr<L, 21>(hp);
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) { H[i * 6 + j] = hp[tri(i, j)]; H[j * 6 + i] = hp[tri(i, j)]; }
+  H[0] += m.mass; H[7] += m.mass; H[14] += m.mass;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H[(3 + i) * 6 + 3 + j] += m.I[i * 3 + j];
+}
+
+// Active edges at x: bit e of act[k] set iff J_e x - a_ref_e < 0.
+template <int CPL>
+DMX_DEV void free_active(const FreeRows<CPL>& rw, const double* x, uint32_t* act, double (*s)[4]) {
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    act[k] = 0u;
+    if (!rw.on[k]) continue;
+    double jn = dot6(rw.Jn[k], x), j1 = dot6(rw.Jt1[k], x), j2 = dot6(rw.Jt2[k], x);
+    double mu = rw.mu[k];
+    double jx[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      s[k][e] = jx[e] - rw.aref[k][e];
+      if (s[k][e] < 0.0) act[k] |= 1u << e;
+    }
+  }
+}
+
+template <int CPL, int L>
+DMX_DEV bool same_active(const uint32_t* a, const uint32_t* b) {
+  bool same = true;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) same = same && (a[k] == b[k]);
+  return team_all<L>(same);
+}
+
+// Exact Newton solve of the primal problem, started at a0.  Each iteration
+// takes the Newton direction of the current active set; if no row changes
+// activity on the unit step it is the exact minimizer (the active set is
+// then unchanged) and the solve ends; otherwise the exact minimizer along the
+// direction is found by a bracketed semismooth Newton iteration on the
+// piecewise-linear directional derivative.
+template <int CPL, int L>
+DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, double* x, int maxit,
+                         Stat& st) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) x[i] = a0[i];
+  uint32_t act[CPL];
+  double s[CPL][4];
+  free_active<CPL>(rw, x, act, s);
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
+  if (!team_any<L>(any)) return;
+  for (int it = 0; it < maxit; ++it) {
+    st.newton_it++;
+    // gradient and Hessian of the active set
+    double gp[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!((act[k] >> e) & 1u)) continue;
+        double Je[6];
+        edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
+        double w = rw.D[k] * s[k][e];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gp[i] += w * Je[i];
+      }
+    }
+    team_sum_arr<L, 6>(gp);
+    double dx[6], Mdx[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dx[i] = x[i] - a0[i];
+    free_Mmul(m, dx, Mdx);
+    double H[36];
+    free_hessian<CPL, L>(m, rw, act, H);
+    if (!chol<6>(H)) { st.status |= 4; return; }
+    double dl[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dl[i] = -(Mdx[i] + gp[i]);
+    chol_solve<6>(H, dl);
+    // directional data of every row
+    double t[CPL][4];
+    uint32_t act1[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      act1[k] = 0u;
+      if (!rw.on[k]) continue;
+      double jn = dot6(rw.Jn[k], dl), j1 = dot6(rw.Jt1[k], dl), j2 = dot6(rw.Jt2[k], dl);
+      double mu = rw.mu[k];
+      t[k][0] = jn + mu * j1; t[k][1] = jn - mu * j1; t[k][2] = jn + mu * j2; t[k][3] = jn - mu * j2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (s[k][e] + t[k][e] < 0.0) act1[k] |= 1u << e;
+    }
+    if (same_active<CPL, L>(act, act1)) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x[i] += dl[i];
+      return;
+    }
+    // exact line search: root of phi'(a) = a C2(a) + C1(a)
+    double Mdl[6];
+    free_Mmul(m, dl, Mdl);
+    double dMd = dot6(dl, Mdl), xMd = dot6(dx, Mdl);
+    double lo = 0.0, hi = 1e300, a = 1.0;
+    for (int ls = 0; ls < 60; ++ls) {
+      double c1 = 0.0, c2 = 0.0;
+      uint32_t sa[CPL];
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        sa[k] = 0u;
+        if (!rw.on[k]) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (s[k][e] + a * t[k][e] < 0.0) {
+            sa[k] |= 1u << e;
+            c2 += rw.D[k] * t[k][e] * t[k][e];
+            c1 += rw.D[k] * t[k][e] * s[k][e];
+          }
+      }
+      c1 = team_sum<L>(c1) + xMd;
+      c2 = team_sum<L>(c2) + dMd;
+      double dphi = a * c2 + c1;
+      if (dphi > 0.0) hi = a; else lo = a;
+      double an = -c1 / c2;
+      uint32_t sn[CPL];
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) {
+        sn[k] = 0u;
+        if (!rw.on[k]) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (s[k][e] + an * t[k][e] < 0.0) sn[k] |= 1u << e;
+      }
+      if (same_active<CPL, L>(sa, sn)) { a = an; break; }
+      if (!(an > lo && an < hi)) an = (hi < 1e299) ? 0.5 * (lo + hi) : 2.0 * a;
+      a = an;
+      if (ls == 59) a = lo > 0.0 ? lo : a;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] += a * dl[i];
+    free_active<CPL>(rw, x, act, s);
+  }
+  st.status |= 8;
+}
+
+// Forward acceleration of a free-body world at state y = (q[7], v[6]) with
+// generalized force tau.
+template <int NC, int L>
+struct FreePhys {
+  static constexpr int NQ = 7, NV = 6, TEAM = L;
+  static constexpr int CPL = (NC + L - 1) / L;
+  using Model = FreeModel;
+
+  DMX_DEV static void frame(const double* q, V3* p, M3* R, Q4* qh, double* inv) {
+    *p = mk3(q[0], q[1], q[2]);
+    *qh = qnormalize(mkq(q[3], q[4], q[5], q[6]), inv);
+    *R = quat2mat(*qh);
+  }
+
+  DMX_DEV static void a0_of(const Model& m, const double* v, const double* tau, double* a0) {
+    V3 w = mk3(v[3], v[4], v[5]);
+    V3 Iw = mk3(m.I[0] * w.x + m.I[1] * w.y + m.I[2] * w.z, m.I[3] * w.x + m.I[4] * w.y + m.I[5] * w.z,
+                m.I[6] * w.x + m.I[7] * w.y + m.I[8] * w.z);
+    V3 gy = cross(w, Iw);
+    double fa[3] = {tau[3] - gy.x, tau[4] - gy.y, tau[5] - gy.z};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a0[i] = tau[i] / m.mass + m.grav[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a0[3 + i] = m.Iinv[3 * i] * fa[0] + m.Iinv[3 * i + 1] * fa[1] + m.Iinv[3 * i + 2] * fa[2];
+  }
+
+  DMX_DEV static void acc(const Model& m, const double* y, const double* tau, bool cfd, double beta, int maxit,
+                          double* a, Stat& st) {
+    V3 p; M3 R; Q4 qh; double inv;
+    frame(y, &p, &R, &qh, &inv);
+    const double* v = y + NQ;
+    double a0[6];
+    a0_of(m, v, tau, a0);
+    FreeRows<CPL> rw;
+    free_rows<CPL, L>(m, p, R, v, cfd, beta, rw);
+    free_newton<CPL, L>(m, rw, a0, a, maxit, st);
+  }
+
+  // Cotangent of the acceleration map.  x* solves H x* = (tau - c) + sum_A
+  // D_e a_ref_e J_e^T at its active set A (the same set the forward solve
+  // ended with), so with lam = H^-1 abar: tau_bar = lam, c_bar = -lam,
+  // D_bar_e = (J_e lam)(a_ref_e - J_e x*), a_ref_bar_e = D_e (J_e lam),
+  // J_bar_e = f_e lam - D_e (J_e lam) x*; then back through a_ref, d(r), the
+  // contact geometry and the body frame to (q, v).  For the CFD field x* is
+  // solved here (its rows differ from the forward's).
+  DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
+                              const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
+                              Stat& st) {
+    V3 p; M3 R; Q4 qh; double inv;
+    frame(y, &p, &R, &qh, &inv);
+    const double* v = y + NQ;
+    FreeRows<CPL> rw;
+    free_rows<CPL, L>(m, p, R, v, cfd, beta, rw);
+    double xs[6];
+    if (cfd) {
+      double a0[6];
+      a0_of(m, v, tau, a0);
+      free_newton<CPL, L>(m, rw, a0, xs, maxit, st);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) xs[i] = xs_in[i];
+    }
+    uint32_t act[CPL];
+    double s[CPL][4];
+    free_active<CPL>(rw, xs, act, s);
+    double H[36];
+    free_hessian<CPL, L>(m, rw, act, H);
+    chol<6>(H);
+    double lam[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) lam[i] = abar[i];
+    chol_solve<6>(H, lam);
+    // per-lane partial cotangents: p, R, v
+    double acc_[18];  // pb[3], Rb[9], vb[6]
+#pragma unroll
+    for (int i = 0; i < 18; ++i) acc_[i] = 0.0;
+    const int tl = threadIdx.x & (L - 1);
+    (void)tl;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      if (!rw.on[k] || act[k] == 0u) continue;
+      const PairF& pr = m.pair[m.cpair[rw.slot[k]]];
+      double mu = rw.mu[k], D = rw.D[k];
+      double Jbn[6] = {0, 0, 0, 0, 0, 0}, Jb1[6] = {0, 0, 0, 0, 0, 0}, Jb2[6] = {0, 0, 0, 0, 0, 0};
+      double rbar = 0.0;
+      double ddr;
+      double dimp = impedance(pr, rw.r[k], &ddr);
+      double dD = ddr / (pr.ahat * (1.0 - dimp) * (1.0 - dimp));
+      double kk = dimp * pr.kscale;
+      double dpt;  // d pterm / dr
+      if (cfd) {
+        double dsp;
+        double sp = softplus(-rw.r[k], beta, &dsp);
+        dpt = pr.kscale * ddr * sp - kk * dsp;
+      } else {
+        dpt = -(pr.kscale * ddr * rw.r[k] + kk);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!((act[k] >> e) & 1u)) continue;
+        double Je[6];
+        edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], mu, e, Je);
+        double sl = dot6(Je, lam), sx = dot6(Je, xs);
+        double f = D * (rw.aref[k][e] - sx);
+        double Dbar = sl * (rw.aref[k][e] - sx);
+        double arb = D * sl;
+        double Jeb[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) Jeb[i] = f * lam[i] - D * sl * xs[i] - pr.bcoef * arb * v[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc_[12 + i] += -pr.bcoef * arb * Je[i];
+        rbar += arb * dpt + Dbar * dD;
+        double sg = (e & 1) ? -mu : mu;
+        double* Jbt = (e < 2) ? Jb1 : Jb2;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { Jbn[i] += Jeb[i]; Jbt[i] += sg * Jeb[i]; }
+      }
+      // J_u = [u, R^T (d x u)]: angular part back to d and R
+      V3 lc, ce, P;
+      double r;
+      slot_geom(m, rw.slot[k], p, R, &lc, &ce, &r, &P);
+      V3 d = P - p;
+      V3 db = mk3(0, 0, 0);
+      const double* us[3] = {pr.n, pr.t1, pr.t2};
+      const double* jbs[3] = {Jbn, Jb1, Jb2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        V3 u = ld3(us[a]);
+        V3 wb = mk3(jbs[a][3], jbs[a][4], jbs[a][5]);
+        V3 z = cross(d, u);
+        V3 zb = mul(R, wb);
+        // R_bar += z wb^T
+        M3 Rb;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Rb.a[i] = 0.0;
+        outer_add(Rb, z, wb);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) acc_[3 + i] += Rb.a[i];
+        db += cross(u, zb);
+      }
+      // d = P - p; P = ce - (rad + r/2) n; r = n.(ce - p0) - rad; ce = p + R lc
+      V3 n = ld3(pr.n);
+      V3 Pb = db;
+      V3 pb = mk3(-db.x, -db.y, -db.z);
+      rbar += -0.5 * dot(n, Pb);
+      V3 ceb = Pb + rbar * n;
+      pb += ceb;
+      M3 Rb2;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Rb2.a[i] = 0.0;
+      outer_add(Rb2, ceb, lc);
+      acc_[0] += pb.x; acc_[1] += pb.y; acc_[2] += pb.z;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) acc_[3 + i] += Rb2.a[i];
+    }
+    team_sum_arr<L, 18>(acc_);
+    // bias c = (-m g, w x I w) with c_bar = -lam
+    V3 w = mk3(v[3], v[4], v[5]);
+    V3 Iw = mk3(m.I[0] * w.x + m.I[1] * w.y + m.I[2] * w.z, m.I[3] * w.x + m.I[4] * w.y + m.I[5] * w.z,
+                m.I[6] * w.x + m.I[7] * w.y + m.I[8] * w.z);
+    V3 cb = mk3(-lam[3], -lam[4], -lam[5]);
+    V3 t1 = cross(Iw, cb);
+    V3 t2 = cross(cb, w);
+    V3 It2 = mk3(m.I[0] * t2.x + m.I[1] * t2.y + m.I[2] * t2.z, m.I[3] * t2.x + m.I[4] * t2.y + m.I[5] * t2.z,
+                 m.I[6] * t2.x + m.I[7] * t2.y + m.I[8] * t2.z);
+    M3 Rb;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Rb.a[i] = acc_[3 + i];
+    Q4 qhb = quat2mat_vjp(qh, Rb);
+    Q4 qb = qnormalize_vjp(qh, inv, qhb);
+    ybar[0] = acc_[0]; ybar[1] = acc_[1]; ybar[2] = acc_[2];
+    ybar[3] = qb.w; ybar[4] = qb.x; ybar[5] = qb.y; ybar[6] = qb.z;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ybar[NQ + i] = acc_[12 + i];
+    ybar[NQ + 3] += t1.x + It2.x;
+    ybar[NQ + 4] += t1.y + It2.y;
+    ybar[NQ + 5] += t1.z + It2.z;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) taubar[i] = lam[i];
+  }
+
+  // q (+) dq for the free joint: position += dq_lin; quat <- normalize(quat *
+  // exp(dq_ang / 2)) (exact integration of the body-frame rotation).
+  DMX_DEV static void qplus(const double* q, const double* dq, double* out) {
+    out[0] = q[0] + dq[0]; out[1] = q[1] + dq[1]; out[2] = q[2] + dq[2];
+    Q4 e = qexp_half(mk3(dq[3], dq[4], dq[5]), nullptr, nullptr, nullptr, nullptr);
+    Q4 w = qmul(mkq(q[3], q[4], q[5], q[6]), e);
+    Q4 r = qnormalize(w, nullptr);
+    out[3] = r.w; out[4] = r.x; out[5] = r.y; out[6] = r.z;
+  }
+  // qbar += d out / d q ^T ob ; dqb = d out / d dq ^T ob
+  DMX_DEV static void qplus_vjp(const double* q, const double* dq, const double* ob, double* qbar, double* dqb) {
+    qbar[0] += ob[0]; qbar[1] += ob[1]; qbar[2] += ob[2];
+    dqb[0] = ob[0]; dqb[1] = ob[1]; dqb[2] = ob[2];
+    V3 th = mk3(dq[3], dq[4], dq[5]);
+    double c, s, dc, ds;
+    Q4 e = qexp_half(th, &c, &s, &dc, &ds);
+    Q4 q4 = mkq(q[3], q[4], q[5], q[6]);
+    Q4 w = qmul(q4, e);
+    double inv;
+    Q4 r = qnormalize(w, &inv);
+    Q4 wb = qnormalize_vjp(r, inv, mkq(ob[3], ob[4], ob[5], ob[6]));
+    Q4 qb = qmul(wb, qconj(e));
+    Q4 eb = qmul(qconj(q4), wb);
+    qbar[3] += qb.w; qbar[4] += qb.x; qbar[5] += qb.y; qbar[6] += qb.z;
+    double tv = eb.x * th.x + eb.y * th.y + eb.z * th.z;
+    double g = 2.0 * (dc * eb.w + ds * tv);
+    dqb[3] = s * eb.x + g * th.x;
+    dqb[4] = s * eb.y + g * th.y;
+    dqb[5] = s * eb.z + g * th.z;
+  }
+
+  // coordinates of q integrated as plain sums (positions); the rest are quaternion components
+  DMX_DEV static bool q_is_linear(int i) { return i < 3; }
+  DMX_DEV static int q_dof(int i) { return i; }
+};
+
+}  // namespace dmx

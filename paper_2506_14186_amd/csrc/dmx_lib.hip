@@ -1,0 +1,375 @@
+// Host side of the dmx C ABI: model compilation, kernel dispatch, tapes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dmx.h"
+#include "dmx_free.hpp"
+#include "dmx_rk.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+dmx_status fail(dmx_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(DMX_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- host math
+void quat_to_mat(const double* q, double* R) {
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Principal moments (about the centre) and mass of a uniform solid primitive.
+bool solid_inertia(int type, const double* s, double mass_in, double* mass, double* I) {
+  double vol;
+  switch (type) {
+    case DMX_GEOM_SPHERE: vol = 4.0 / 3.0 * kPi * s[0] * s[0] * s[0]; break;
+    case DMX_GEOM_BOX: vol = 8.0 * s[0] * s[1] * s[2]; break;
+    case DMX_GEOM_CAPSULE: vol = kPi * s[0] * s[0] * (2.0 * s[1]) + 4.0 / 3.0 * kPi * s[0] * s[0] * s[0]; break;
+    default: return false;
+  }
+  const double m = mass_in > 0.0 ? mass_in : 1000.0 * vol;
+  *mass = m;
+  if (type == DMX_GEOM_SPHERE) {
+    I[0] = I[1] = I[2] = 2.0 / 5.0 * m * s[0] * s[0];
+  } else if (type == DMX_GEOM_BOX) {
+    const double a2 = 4.0 * s[0] * s[0], b2 = 4.0 * s[1] * s[1], c2 = 4.0 * s[2] * s[2];  // full edges squared
+    I[0] = m * (b2 + c2) / 12.0; I[1] = m * (a2 + c2) / 12.0; I[2] = m * (a2 + b2) / 12.0;
+  } else {
+    // capsule: cylinder (length len) + two hemispheres, axis along z
+    const double r = s[0], len = 2.0 * s[1];
+    const double vcyl = kPi * r * r * len, vcap = 4.0 / 3.0 * kPi * r * r * r;
+    const double mcyl = m * vcyl / (vcyl + vcap), mcap = m - mcyl;
+    const double hemi_offset = 3.0 * r / 8.0;  // hemisphere centroid from its flat face
+    const double ihemi_c = 2.0 / 5.0 * r * r - hemi_offset * hemi_offset;  // per unit mass, about centroid
+    const double dist = 0.5 * len + hemi_offset;
+    I[2] = mcyl * r * r / 2.0 + mcap * 2.0 / 5.0 * r * r;
+    I[0] = I[1] = mcyl * (r * r / 4.0 + len * len / 12.0) + mcap * (ihemi_c + dist * dist);
+  }
+  return true;
+}
+
+void make_tangents(const double* n, double* t1, double* t2) {
+  double a[3] = {0, 0, 0};
+  if (std::fabs(n[0]) < 0.5) a[0] = 1.0; else a[1] = 1.0;
+  const double an = a[0] * n[0] + a[1] * n[1] + a[2] * n[2];
+  double t[3] = {a[0] - an * n[0], a[1] - an * n[1], a[2] - an * n[2]};
+  const double tn = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  for (int i = 0; i < 3; ++i) t1[i] = t[i] / tn;
+  t2[0] = n[1] * t1[2] - n[2] * t1[1];
+  t2[1] = n[2] * t1[0] - n[0] * t1[2];
+  t2[2] = n[0] * t1[1] - n[1] * t1[0];
+}
+
+// ---------------------------------------------------------------- kernels
+using FwdFn = void (*)(const void*, const dmx::FwdArgs&, hipStream_t, int);
+using AdjFn = void (*)(const void*, const dmx::AdjArgs&, hipStream_t, int);
+
+template <class P>
+void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int W) {
+  const long long threads = (long long)W * P::TEAM;
+  const int blocks = (int)((threads + 63) / 64);
+  hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+}
+template <class P>
+void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int W) {
+  const long long threads = (long long)W * P::TEAM;
+  const int blocks = (int)((threads + 63) / 64);
+  hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+}
+
+struct KernelEntry {
+  int kind, nc, team;
+  FwdFn fwd;
+  AdjFn adj;
+};
+
+#define FREE_ENTRY(NC, L) \
+  {0, NC, L, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>}
+
+const KernelEntry kKernels[] = {
+    FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
+    FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(16, 8),
+    FREE_ENTRY(16, 16),
+};
+
+int bucket(int n) {
+  int b = 1;
+  while (b < n) b *= 2;
+  return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- objects
+struct dmx_model {
+  int kind = 0;  // 0: single free body with plane contacts
+  int nq = 0, nv = 0, nu = 0, nc = 0, ncb = 0;
+  dmx::FreeModel host{};
+  void* dev = nullptr;
+};
+
+struct dmx_tape {
+  const dmx_model* model = nullptr;
+  int W = 0, n_int = 0, nu = 0, rec = 0, team = 1;
+  double dt = 0.0;
+  long long cap = 0;
+  double* records = nullptr;
+  int* n_acc = nullptr;
+  int* status = nullptr;
+  const double* u = nullptr;
+  dmx::SolverOpts o{};
+  AdjFn adj = nullptr;
+};
+
+extern "C" {
+
+const char* dmx_last_error(void) { return g_err.c_str(); }
+
+void dmx_default_opts(dmx_solver_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->rtol = 1e-6; o->atol = 1e-8; o->h0 = 1e-3; o->safety = 0.9; o->facmin = 0.2; o->facmax = 10.0;
+  o->kP = 0.2; o->kI = 0.4; o->err_order = 5.0; o->err_floor = 1e-6; o->max_attempts = 1000000;
+  o->newton_maxit = 100; o->cfd = 0; o->softplus_beta = 1e4; o->tape_steps = 0; o->lanes_per_world = 0;
+}
+
+dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
+  if (!d || !out) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (d->nbody != 1 || d->njnt != 1 || d->jnt_type[0] != DMX_JOINT_FREE || d->body_parent[0] != -1)
+    return fail(DMX_ERR_UNSUPPORTED, "only single free-body models are compiled in this build");
+  if (d->npair > dmx::kMaxPairs) return fail(DMX_ERR_UNSUPPORTED, "too many pairs");
+  if (d->nu > 6) return fail(DMX_ERR_INVALID_ARG, "at most 6 controls on a free body");
+  dmx_model* m = new dmx_model();
+  dmx::FreeModel& f = m->host;
+  m->nq = 7; m->nv = 6; m->nu = d->nu;
+  double mass, Ip[3];
+  if (!solid_inertia(d->body_iner_type[0], d->body_iner_size, d->body_mass[0], &mass, Ip)) {
+    delete m;
+    return fail(DMX_ERR_INVALID_ARG, "unknown inertial primitive");
+  }
+  double Ri[9];
+  quat_to_mat(d->body_iner_quat, Ri);
+  f.mass = mass;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += Ri[i * 3 + k] * Ip[k] * Ri[j * 3 + k];
+      f.I[i * 3 + j] = s;
+    }
+  // inverse of the 3x3 inertia
+  {
+    const double* A = f.I;
+    double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+    double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+    f.Iinv[0] = c00 / det; f.Iinv[3] = c01 / det; f.Iinv[6] = c02 / det;
+    f.Iinv[1] = (A[2] * A[7] - A[1] * A[8]) / det; f.Iinv[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    f.Iinv[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    f.Iinv[2] = (A[1] * A[5] - A[2] * A[4]) / det; f.Iinv[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    f.Iinv[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+  }
+  for (int i = 0; i < 3; ++i) f.grav[i] = d->gravity[i];
+  for (int i = 0; i < d->nu; ++i) {
+    if (d->ctrl_dof[i] < 0 || d->ctrl_dof[i] >= 6) { delete m; return fail(DMX_ERR_INVALID_ARG, "bad ctrl dof"); }
+    f.ctrl[i] = d->ctrl_dof[i];
+  }
+  f.nu = d->nu;
+  f.np = d->npair;
+  const double invw = 1.0 / mass;  // translational inverse weight of a free body
+  int nc = 0;
+  for (int p = 0; p < d->npair; ++p) {
+    const int g1 = d->pair_g1[p], g2 = d->pair_g2[p];
+    if (g1 < 0 || g1 >= d->ngeom || g2 < 0 || g2 >= d->ngeom) { delete m; return fail(DMX_ERR_INVALID_ARG, "bad pair geom"); }
+    if (d->geom_type[g1] != DMX_GEOM_PLANE || d->geom_body[g1] != -1 || d->geom_body[g2] != 0) {
+      delete m;
+      return fail(DMX_ERR_UNSUPPORTED, "pairs must be (world plane, body geom)");
+    }
+    const int t2 = d->geom_type[g2];
+    if (t2 != DMX_GEOM_SPHERE && t2 != DMX_GEOM_CAPSULE) {
+      delete m;
+      return fail(DMX_ERR_UNSUPPORTED, "plane pairs with sphere or capsule geoms only in this build");
+    }
+    dmx::PairF& pr = f.pair[p];
+    pr.gtype = t2;
+    pr.ncon = (t2 == DMX_GEOM_CAPSULE) ? 2 : 1;
+    double Rg[9], Rp[9];
+    quat_to_mat(&d->geom_quat[4 * g2], Rg);
+    quat_to_mat(&d->geom_quat[4 * g1], Rp);
+    for (int i = 0; i < 3; ++i) {
+      pr.l[i] = d->geom_pos[3 * g2 + i];
+      pr.ax[i] = Rg[i * 3 + 2] * d->geom_size[3 * g2 + 1];
+      pr.p0[i] = d->geom_pos[3 * g1 + i];
+      pr.n[i] = Rp[i * 3 + 2];
+    }
+    make_tangents(pr.n, pr.t1, pr.t2);
+    pr.rad = d->geom_size[3 * g2];
+    pr.mu = d->pair_mu[p];
+    const double tc = d->pair_solref[2 * p], dr = d->pair_solref[2 * p + 1];
+    for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
+    const double dw = pr.si[1];
+    if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
+      delete m;
+      return fail(DMX_ERR_INVALID_ARG, "solref/solimp/cfd out of range");
+    }
+    pr.bcoef = 2.0 / (dw * tc);
+    pr.kscale = 1.0 / (dw * dw * tc * tc * dr * dr);
+    pr.ahat = (1.0 + pr.mu * pr.mu) * invw;
+    for (int c = 0; c < pr.ncon; ++c) {
+      if (nc >= dmx::kMaxSlots) { delete m; return fail(DMX_ERR_UNSUPPORTED, "too many contact slots"); }
+      f.cpair[nc] = p;
+      f.csub[nc] = c;
+      ++nc;
+    }
+  }
+  f.nc = nc;
+  m->nc = nc;
+  m->ncb = bucket(nc > 0 ? nc : 1);
+  hipError_t e = hipMalloc(&m->dev, sizeof(dmx::FreeModel));
+  if (e == hipSuccess) e = hipMemcpy(m->dev, &f, sizeof(dmx::FreeModel), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (m->dev) (void)hipFree(m->dev);
+    delete m;
+    return fail(DMX_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return DMX_OK;
+}
+
+dmx_status dmx_model_info(const dmx_model* m, int32_t* nq, int32_t* nv, int32_t* nu, int32_t* max_contacts) {
+  if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
+  if (nq) *nq = m->nq;
+  if (nv) *nv = m->nv;
+  if (nu) *nu = m->nu;
+  if (max_contacts) *max_contacts = m->nc;
+  return DMX_OK;
+}
+
+void dmx_model_destroy(dmx_model* m) {
+  if (!m) return;
+  if (m->dev) (void)hipFree(m->dev);
+  delete m;
+}
+
+static const KernelEntry* find_kernel(const dmx_model* m, int team) {
+  int want = team;
+  if (want <= 0) want = m->ncb >= 16 ? 16 : m->ncb;
+  for (const KernelEntry& k : kKernels)
+    if (k.kind == m->kind && k.nc == m->ncb && k.team == want) return &k;
+  return nullptr;
+}
+
+static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
+  dmx::SolverOpts s;
+  s.rtol = o.rtol; s.atol = o.atol; s.h0 = o.h0; s.safety = o.safety; s.facmin = o.facmin; s.facmax = o.facmax;
+  s.kP = o.kP; s.kI = o.kI; s.err_order = o.err_order; s.err_floor = o.err_floor; s.beta = o.softplus_beta;
+  s.max_attempts = o.max_attempts; s.newton_maxit = o.newton_maxit; s.cfd = o.cfd;
+  return s;
+}
+
+dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, const dmx_solver_opts* opts,
+                       const double* x0, const double* u, double* x_out, int32_t* world_status,
+                       int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape, void* stream) {
+  if (!m || !x0 || !x_out || !world_status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (W < 0 || n_int <= 0 || !(dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
+  if (m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  dmx_solver_opts o;
+  if (opts) o = *opts; else dmx_default_opts(&o);
+  if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0)
+    return fail(DMX_ERR_INVALID_ARG, "bad solver options");
+  if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
+  if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
+  const KernelEntry* k = find_kernel(m, o.lanes_per_world);
+  if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model and lanes_per_world");
+  if (tape) *tape = nullptr;
+  if (W == 0) return DMX_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int NX = m->nq + m->nv;
+  dmx::FwdArgs a{};
+  a.W = W; a.n_int = n_int; a.nu = m->nu; a.dt = dt; a.x0 = x0; a.u = u; a.xout = x_out;
+  a.status = world_status; a.n_acc = n_accepted; a.n_rej = n_rejected; a.n_newton = nullptr;
+  a.forced = o.forced; a.forced_n = o.forced_n; a.forced_cap = o.forced_cap;
+  a.steplog = o.steplog; a.log_n = o.log_n; a.log_cap = o.log_cap;
+  a.o = to_solver(o);
+  dmx_tape* tp = nullptr;
+  if (tape) {
+    tp = new dmx_tape();
+    tp->model = m; tp->W = W; tp->n_int = n_int; tp->nu = m->nu; tp->dt = dt; tp->u = u;
+    tp->rec = 3 + NX + 6 * m->nv;
+    tp->cap = o.tape_steps > 0 ? o.tape_steps : 4096;
+    tp->o = a.o;
+    tp->adj = k->adj;
+    tp->team = k->team;
+    const size_t bytes = (size_t)W * tp->cap * tp->rec * sizeof(double);
+    hipError_t e = hipMalloc(&tp->records, bytes);
+    if (e == hipSuccess) e = hipMalloc(&tp->n_acc, sizeof(int) * W);
+    if (e == hipSuccess) e = hipMalloc(&tp->status, sizeof(int) * W);
+    if (e != hipSuccess) {
+      dmx_tape_destroy(tp);
+      return fail(DMX_ERR_OUT_OF_MEMORY, std::string("tape allocation: ") + hipGetErrorString(e));
+    }
+    a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
+    a.n_acc = tp->n_acc; a.status = tp->status;
+  }
+  k->fwd(m->dev, a, s, W);
+  HIP_TRY(hipGetLastError());
+  if (tp) {
+    HIP_TRY(hipMemcpyAsync(world_status, tp->status, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+    if (n_accepted) HIP_TRY(hipMemcpyAsync(n_accepted, tp->n_acc, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+    *tape = tp;
+  }
+  return DMX_OK;
+}
+
+dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
+  if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  dmx::AdjArgs a{};
+  a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
+  a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
+  a.o = tp->o;
+  tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->W);
+  HIP_TRY(hipGetLastError());
+  return DMX_OK;
+}
+
+dmx_status dmx_tape_info(const dmx_tape* tp, int64_t* steps, int32_t* rec) {
+  if (!tp) return fail(DMX_ERR_INVALID_ARG, "null tape");
+  if (steps) *steps = tp->cap;
+  if (rec) *rec = tp->rec;
+  return DMX_OK;
+}
+
+dmx_status dmx_tape_data(const dmx_tape* tp, const double** records, const int32_t** n_steps) {
+  if (!tp) return fail(DMX_ERR_INVALID_ARG, "null tape");
+  if (records) *records = tp->records;
+  if (n_steps) *n_steps = tp->n_acc;
+  return DMX_OK;
+}
+
+void dmx_tape_destroy(dmx_tape* tp) {
+  if (!tp) return;
+  if (tp->records) (void)hipFree(tp->records);
+  if (tp->n_acc) (void)hipFree(tp->n_acc);
+  if (tp->status) (void)hipFree(tp->status);
+  delete tp;
+}
+
+}  // extern "C"

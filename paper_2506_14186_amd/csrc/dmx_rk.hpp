@@ -1,0 +1,400 @@
+// Adaptive Dormand-Prince 5(4) rollouts and their discrete adjoint, one team
+// of lanes per world, for any physics policy P providing:
+//   NQ, NV, TEAM, Model, acc(), acc_vjp(), qplus(), qplus_vjp(), q_is_linear().
+//
+// Forward (Sec. 3.1, App. C.2): stage states Y_i = (q_n (+) h sum_j a_ij v_j,
+// v_n + h sum_j a_ij a_j) with v_j the velocity part of Y_j; FSAL; an
+// embedded error estimate, accept iff err <= 1, PI step-size control with the
+// controller coefficients of App. E.1.  Every accepted step is written to the
+// tape with its stage accelerations, so the reverse sweep rebuilds each stage
+// state bit for bit without re-solving the contact problem.
+//
+// Reverse (discretize-then-optimize, App. C.2): step sizes and the accepted
+// sequence are constants; each step is differentiated through its stage
+// combinations, the (+) map and the acceleration map (acc_vjp).
+#pragma once
+#include "dmx_common.hpp"
+
+namespace dmx {
+
+// ------------------------------------------------------------ tableau
+struct Tableau {
+  double a[7][7];   // a[i][j], stage i uses stages j < i; row 6 = b (FSAL)
+  double a2[7][7];  // (a a)[i][l] = sum_j a[i][j] a[j][l]
+  double c[7];
+  double e[7];      // b - bh
+  double bhA[7];    // sum_j bh[j] a[j][l]
+  double eA[7];     // sum_j e[j] a[j][l]
+  double bh_sum;
+};
+
+constexpr Tableau make_tableau() {
+  Tableau t{};
+  const double A[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {1.0 / 5.0, 0, 0, 0, 0, 0, 0},
+      {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0, 0},
+      {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0, 0},
+      {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0, 0},
+      {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0, 0},
+      {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0}};
+  const double BH[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
+                        187.0 / 2100.0, 1.0 / 40.0};
+  for (int i = 0; i < 7; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < 7; ++j) { t.a[i][j] = A[i][j]; s += A[i][j]; }
+    t.c[i] = s;
+  }
+  for (int i = 0; i < 7; ++i)
+    for (int l = 0; l < 7; ++l) {
+      double s = 0.0;
+      for (int j = 0; j < 7; ++j) s += A[i][j] * A[j][l];
+      t.a2[i][l] = s;
+    }
+  t.bh_sum = 0.0;
+  for (int j = 0; j < 7; ++j) { t.e[j] = (j < 6 ? A[6][j] : 0.0) - BH[j]; t.bh_sum += BH[j]; }
+  for (int l = 0; l < 7; ++l) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < 7; ++j) { s1 += BH[j] * A[j][l]; s2 += t.e[j] * A[j][l]; }
+    t.bhA[l] = s1; t.eA[l] = s2;
+  }
+  return t;
+}
+__constant__ Tableau kTab = make_tableau();
+
+struct SolverOpts {
+  double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor, beta;
+  long long max_attempts;
+  int newton_maxit, cfd;
+};
+
+struct FwdArgs {
+  int W, n_int, nu;
+  double dt;
+  const double* x0;
+  const double* u;
+  double* xout;
+  int* status;
+  int* n_acc;
+  int* n_rej;
+  long long* n_newton;
+  double* tape;
+  long long cap;
+  int rec;
+  const double* forced;
+  const int* forced_n;
+  int forced_cap;
+  double* steplog;
+  int* log_n;
+  int log_cap;
+  SolverOpts o;
+};
+
+struct AdjArgs {
+  int W, n_int, nu;
+  const double* tape;
+  long long cap;
+  int rec;
+  const int* n_acc;
+  const int* status;
+  const double* u;
+  const double* xbar;
+  double* x0bar;
+  double* ubar;
+  SolverOpts o;
+};
+
+// generalized force of interval k: tau[ctrl[i]] += u[w][k][i] (unrolled over
+// dofs so that tau stays in registers)
+template <class P>
+DMX_DEV void load_tau(const typename P::Model& m, const double* u, int w, int k, int n_int, int nu, double* tau) {
+#pragma unroll
+  for (int d = 0; d < P::NV; ++d) tau[d] = 0.0;
+  for (int i = 0; i < nu; ++i) {
+    const double ui = u[((size_t)w * n_int + k) * nu + i];
+    const int c = m.ctrl[i];
+#pragma unroll
+    for (int d = 0; d < P::NV; ++d)
+      if (c == d) tau[d] += ui;
+  }
+}
+
+template <class P>
+DMX_DEV void store_ubar(const typename P::Model& m, const double* tb, double* dst, int nu) {
+  for (int i = 0; i < nu; ++i) {
+    const int c = m.ctrl[i];
+    double g = 0.0;
+#pragma unroll
+    for (int d = 0; d < P::NV; ++d)
+      if (c == d) g = tb[d];
+    dst[i] = g;
+  }
+}
+
+// dst[i] = src[i] for the team lane owning index i (compile-time indices)
+template <int N, int L>
+DMX_DEV void team_store(double* dst, const double* src, int tl) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if ((i & (L - 1)) == tl) dst[i] = src[i];
+}
+
+// stage state Y_i from y_n and the stage accelerations A[0..i-1]
+template <class P>
+DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq) {
+  constexpr int NQ = P::NQ, NV = P::NV;
+#pragma unroll
+  for (int d = 0; d < NV; ++d) {
+    double sv = 0.0, sq = 0.0;
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+      if (l < i) { sv += kTab.a[i][l] * A[l][d]; sq += kTab.a2[i][l] * A[l][d]; }
+    }
+    Y[NQ + d] = y[NQ + d] + h * sv;
+    dq[d] = h * (kTab.c[i] * y[NQ + d] + h * sq);
+  }
+  P::qplus(y, dq, Y);
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = gt / L;
+  const int tl = gt & (L - 1);
+  if (w >= a.W) return;
+  const typename P::Model& m = *model;
+  const SolverOpts& o = a.o;
+  // stage accelerations: one copy per world in LDS (every team lane writes
+  // the same replicated values), indexed by the runtime stage number
+  __shared__ double sA[64 / L][7][NV];
+  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  double y[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) y[i] = a.x0[(size_t)w * NX + i];
+  double tau[NV];
+  Stat st{0, 0};
+  double t = 0.0, hprop = fmin(o.h0, a.dt), eprev = 1.0;
+  long long attempts = 0;
+  int nacc = 0, nrej = 0, fi = 0, nlog = 0;
+  const int nforced = a.forced ? min(a.forced_n[w], a.forced_cap) : 0;
+#pragma unroll
+  for (int i = 0; i < NX; ++i)
+    if (!isfinite(y[i])) st.status |= 4;
+  bool replay_done = false;
+  for (int kk = 0; kk < a.n_int && st.status == 0 && !replay_done; ++kk) {
+    load_tau<P>(m, a.u, w, kk, a.n_int, a.nu, tau);
+    const double tend = (double)(kk + 1) * a.dt;
+    bool have_k1 = false;
+    while (t < tend) {
+      if (!have_k1) {
+        double a1[NV];
+        P::acc(m, y, tau, false, o.beta, o.newton_maxit, a1, st);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) A[0][d] = a1[d];
+        have_k1 = true;
+      }
+      double h;
+      bool landing;
+      if (a.forced) {
+        if (fi >= nforced) { replay_done = true; break; }  // replay ends with its list
+        h = a.forced[((size_t)w * a.forced_cap + fi) * 2 + 1];
+        landing = t + h >= tend - 0.005 * h;
+        ++fi;
+      } else {
+        landing = t + 1.01 * hprop >= tend;
+        h = landing ? tend - t : hprop;
+      }
+      if (attempts >= o.max_attempts) { st.status |= 1; break; }
+      ++attempts;
+      double Y[NX], dq[NV];
+#pragma unroll 1
+      for (int i = 1; i < 7; ++i) {
+        stage_state<P>(y, A, i, h, Y, dq);
+        double ai[NV];
+        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, ai, st);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
+      }
+      // Y holds y_new (stage 7).  Error estimate in the ambient coordinates:
+      // v: h sum e_i a_i; linear q: h sum e_i v_i; quaternions: difference of
+      // the 5th- and 4th-order (+)-integrated values.
+      double err = 0.0;
+      {
+        double dqh[NV], ev[NV], eq[NV];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) {
+          double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+          for (int l = 0; l < 7; ++l) { s1 += kTab.e[l] * A[l][d]; s2 += kTab.bhA[l] * A[l][d]; s3 += kTab.eA[l] * A[l][d]; }
+          ev[d] = h * s1;
+          dqh[d] = h * (kTab.bh_sum * y[NQ + d] + h * s2);
+          eq[d] = h * h * s3;
+        }
+        double qh[NQ];
+        P::qplus(y, dqh, qh);
+        double acc2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+          double e = P::q_is_linear(i) ? eq[P::q_dof(i)] : Y[i] - qh[i];
+          double sc = o.atol + o.rtol * fmax(fabs(y[i]), fabs(Y[i]));
+          acc2 += (e / sc) * (e / sc);
+        }
+#pragma unroll
+        for (int d = 0; d < NV; ++d) {
+          double sc = o.atol + o.rtol * fmax(fabs(y[NQ + d]), fabs(Y[NQ + d]));
+          acc2 += (ev[d] / sc) * (ev[d] / sc);
+        }
+        err = sqrt(acc2 / NX);
+      }
+      const bool accept = a.forced ? true : (err <= 1.0);
+      const double et = isfinite(err) ? fmax(err, o.err_floor) : 1e300;
+      double fac = o.safety * pow(et, -(o.kP + o.kI) / o.err_order) * pow(eprev, o.kP / o.err_order);
+      fac = fmin(o.facmax, fmax(o.facmin, fac));
+      if (a.steplog && nlog < a.log_cap && tl == 0) {
+        double* lg = a.steplog + ((size_t)w * a.log_cap + nlog) * 4;
+        lg[0] = t; lg[1] = h; lg[2] = err; lg[3] = accept ? 1.0 : 0.0;
+      }
+      if (a.steplog) ++nlog;
+      if (accept) {
+        if (a.tape) {
+          if (nacc >= a.cap) { st.status |= 32; break; }
+          double* rec = a.tape + ((size_t)w * a.cap + nacc) * a.rec;
+          if (tl == 0) { rec[0] = t; rec[1] = h; rec[2] = (double)kk; }
+          team_store<NX, L>(rec + 3, y, tl);
+          double Acp[6 * NV];
+#pragma unroll
+          for (int j = 0; j < 6 * NV; ++j) Acp[j] = A[j / NV][j % NV];
+          team_store<6 * NV, L>(rec + 3 + NX, Acp, tl);
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) y[i] = Y[i];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) A[0][d] = A[6][d];
+        t = landing ? tend : t + h;
+        eprev = et;
+        hprop = fac * h;
+        ++nacc;
+        bool fin = true;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) fin = fin && isfinite(y[i]);
+        if (!fin) { st.status |= 4; break; }
+      } else {
+        hprop = fmin(1.0, fac) * h;
+        ++nrej;
+      }
+      if (!a.forced && hprop < 1e-12 * fmax(1.0, fabs(t))) { st.status |= 2; break; }
+      if (st.status & 12) break;
+    }
+  }
+  team_store<NX, L>(a.xout + (size_t)w * NX, y, tl);
+  if (tl == 0) {
+    a.status[w] = st.status;
+    if (a.n_acc) a.n_acc[w] = nacc;
+    if (a.n_rej) a.n_rej[w] = nrej;
+    if (a.n_newton) a.n_newton[w] = st.newton_it;
+    if (a.log_n) a.log_n[w] = nlog;
+  }
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = gt / L;
+  const int tl = gt & (L - 1);
+  if (w >= a.W) return;
+  const typename P::Model& m = *model;
+  const SolverOpts& o = a.o;
+  const int nsteps = a.n_acc[w];
+  const size_t nut = (size_t)a.n_int * a.nu;
+  if (a.status[w] != 0) {
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
+    for (size_t i = tl; i < nut; i += L) a.ubar[(size_t)w * nut + i] = nan;
+    return;
+  }
+  for (size_t i = tl; i < nut; i += L) a.ubar[(size_t)w * nut + i] = 0.0;
+  double yb[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) yb[i] = a.xbar[(size_t)w * NX + i];
+  double tau[NV], tb_acc[NV];
+  int cur_k = -1;
+  Stat st{0, 0};
+  __shared__ double sA[64 / L][7][NV];
+  __shared__ double sAb[64 / L][6][NV];
+  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  double (*Ab)[NV] = sAb[(threadIdx.x & 63) / L];
+  for (int s = nsteps - 1; s >= 0; --s) {
+    const double* rec = a.tape + ((size_t)w * a.cap + s) * a.rec;
+    const double h = rec[1];
+    const int kk = (int)rec[2];
+    if (kk != cur_k) {
+      if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
+      cur_k = kk;
+      load_tau<P>(m, a.u, w, kk, a.n_int, a.nu, tau);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) tb_acc[i] = 0.0;
+    }
+    double y[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) y[i] = rec[3 + i];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int d = 0; d < NV; ++d) { A[j][d] = rec[3 + NX + j * NV + d]; Ab[j][d] = 0.0; }
+#pragma unroll
+    for (int d = 0; d < NV; ++d) A[6][d] = 0.0;
+    double qb[NQ], vb[NV];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) qb[i] = 0.0;
+#pragma unroll
+    for (int d = 0; d < NV; ++d) vb[d] = 0.0;
+    double Ybar[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) Ybar[i] = yb[i];
+#pragma unroll 1
+    for (int i = 6; i >= 0; --i) {
+      double Y[NX], dq[NV];
+      if (i < 6) {
+        stage_state<P>(y, A, i, h, Y, dq);
+        if (i == 0) {
+#pragma unroll
+          for (int j = 0; j < NX; ++j) Y[j] = y[j];
+        }
+        double tb[NV], xs[NV], ab[NV];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) { xs[d] = A[i][d]; ab[d] = Ab[i][d]; }
+        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
+      } else {
+        stage_state<P>(y, A, 6, h, Y, dq);
+      }
+      if (i == 0) {
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) qb[j] += Ybar[j];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) vb[d] += Ybar[NQ + d];
+      } else {
+        double dqb[NV];
+        P::qplus_vjp(y, dq, Ybar, qb, dqb);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) {
+          vb[d] += Ybar[NQ + d] + h * kTab.c[i] * dqb[d];
+#pragma unroll
+          for (int l = 0; l < 6; ++l)
+            if (l < i) Ab[l][d] += h * kTab.a[i][l] * Ybar[NQ + d] + h * h * kTab.a2[i][l] * dqb[d];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) yb[i] = qb[i];
+#pragma unroll
+    for (int d = 0; d < NV; ++d) yb[NQ + d] = vb[d];
+  }
+  if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
+  team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
+}
+
+}  // namespace dmx

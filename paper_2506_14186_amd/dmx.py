@@ -1,0 +1,242 @@
+"""Thin Python binding of the dmx C ABI (include/dmx.h).
+
+Argument marshalling only: every step of the rollout and of its gradient runs
+in the HIP kernels of ``libdmx.so``.  Tensors are PyTorch CUDA tensors (FP64,
+contiguous) used as device buffers; the library works on the current torch
+stream.  If the library is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+_P = C.c_void_p
+
+JOINT = {"free": 0, "hinge": 1, "slide": 2}
+GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
+STATUS = {"MAX_STEPS": 1, "DT_UNDERFLOW": 2, "NONFINITE": 4, "SOLVER_MAXIT": 8, "TAPE_OVERFLOW": 32}
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("nbody", C.c_int32), ("njnt", C.c_int32), ("ngeom", C.c_int32), ("npair", C.c_int32),
+                ("nu", C.c_int32)] + [(n, _P) for n in (
+                    "body_parent", "body_pos", "body_quat", "body_iner_type", "body_iner_size", "body_iner_quat",
+                    "body_mass", "jnt_body", "jnt_type", "jnt_axis", "jnt_pos", "geom_body", "geom_type",
+                    "geom_size", "geom_pos", "geom_quat", "pair_g1", "pair_g2", "pair_mu", "pair_solref",
+                    "pair_solimp", "pair_cfd", "ctrl_dof")] + [("gravity", C.c_double * 3)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("rtol", "atol", "h0", "safety", "facmin", "facmax", "kP", "kI",
+                                           "err_order", "err_floor")] + [
+        ("max_attempts", C.c_int64), ("newton_maxit", C.c_int32), ("cfd", C.c_int32),
+        ("softplus_beta", C.c_double), ("tape_steps", C.c_int64), ("lanes_per_world", C.c_int32),
+        ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
+        ("log_cap", C.c_int32)]
+
+
+_lib.dmx_last_error.restype = C.c_char_p
+_lib.dmx_default_opts.argtypes = [C.POINTER(SolverOpts)]
+_lib.dmx_model_create.argtypes = [C.POINTER(ModelDesc), C.POINTER(_P)]
+_lib.dmx_model_info.argtypes = [_P, _P, _P, _P, _P]
+_lib.dmx_model_destroy.argtypes = [_P]
+_lib.dmx_rollout.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P,
+                             C.POINTER(_P), _P]
+_lib.dmx_rollout_vjp.argtypes = [_P, _P, _P, _P, _P]
+_lib.dmx_tape_info.argtypes = [_P, _P, _P]
+_lib.dmx_tape_data.argtypes = [_P, _P, _P]
+_lib.dmx_tape_destroy.argtypes = [_P]
+for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
+           "dmx_tape_data"):
+    getattr(_lib, _f).restype = C.c_int32
+
+EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
+           "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_last_error"]
+
+
+class DmxError(RuntimeError):
+    pass
+
+
+def _check(code):
+    if code < 0:
+        raise DmxError(f"dmx error {code}: {_lib.dmx_last_error().decode()}")
+    return code
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw):
+    o = SolverOpts()
+    _lib.dmx_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+
+
+def _i32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int32).ravel())
+
+
+class Model:
+    """A compiled model on the current device (wraps dmx_model_create)."""
+
+    def __init__(self, desc):
+        bodies, geoms, pairs = desc["bodies"], desc["geoms"], desc["pairs"]
+        jb, jt, ja, jp = [], [], [], []
+        for bi, b in enumerate(bodies):
+            for j in b["joints"]:
+                jb.append(bi)
+                jt.append(JOINT[j["type"]])
+                ja.append(j["axis"])
+                jp.append(j["pos"])
+        pad3 = lambda s: list(s) + [0.0] * (3 - len(s))  # noqa: E731
+        arrs = dict(
+            body_parent=_i32([b["parent"] for b in bodies]), body_pos=_f64([b["pos"] for b in bodies]),
+            body_quat=_f64([b["quat"] for b in bodies]),
+            body_iner_type=_i32([GEOM[b["inertial"]["type"]] for b in bodies]),
+            body_iner_size=_f64([pad3(b["inertial"]["size"]) for b in bodies]),
+            body_iner_quat=_f64([b["inertial"].get("quat", [1.0, 0.0, 0.0, 0.0]) for b in bodies]),
+            body_mass=_f64([b["inertial"]["mass"] if b["inertial"]["mass"] is not None else -1.0 for b in bodies]),
+            jnt_body=_i32(jb), jnt_type=_i32(jt), jnt_axis=_f64(ja), jnt_pos=_f64(jp),
+            geom_body=_i32([g["body"] for g in geoms]), geom_type=_i32([GEOM[g["type"]] for g in geoms]),
+            geom_size=_f64([pad3(g["size"]) for g in geoms]), geom_pos=_f64([g["pos"] for g in geoms]),
+            geom_quat=_f64([g["quat"] for g in geoms]), pair_g1=_i32([p["g1"] for p in pairs]),
+            pair_g2=_i32([p["g2"] for p in pairs]), pair_mu=_f64([p["mu"] for p in pairs]),
+            pair_solref=_f64([p["solref"] for p in pairs]), pair_solimp=_f64([p["solimp"] for p in pairs]),
+            pair_cfd=_f64([p["cfd"] for p in pairs]), ctrl_dof=_i32(desc["ctrl"]["dofs"]))
+        d = ModelDesc()
+        d.nbody, d.njnt, d.ngeom, d.npair, d.nu = len(bodies), len(jb), len(geoms), len(pairs), len(
+            desc["ctrl"]["dofs"])
+        for k, a in arrs.items():
+            setattr(d, k, a.ctypes.data if a.size else None)
+        for i in range(3):
+            d.gravity[i] = desc["gravity"][i]
+        h = _P()
+        _check(_lib.dmx_model_create(C.byref(d), C.byref(h)))
+        self.h = h
+        sz = (C.c_int32 * 4)()
+        _check(_lib.dmx_model_info(h, C.byref(sz, 0), C.byref(sz, 4), C.byref(sz, 8), C.byref(sz, 12)))
+        self.nq, self.nv, self.nu, self.ncon = list(sz)
+        self.nx = self.nq + self.nv
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                _lib.dmx_model_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+
+class Tape:
+    def __init__(self, h, model, W, n_int):
+        self.h, self.model, self.W, self.n_int = h, model, W, n_int
+
+    def info(self):
+        s, r = C.c_int64(), C.c_int32()
+        _check(_lib.dmx_tape_info(self.h, C.byref(s), C.byref(r)))
+        return s.value, r.value
+
+    def records(self):
+        """(records [W][steps][rec] float64, n_steps [W] int32) copied to the host."""
+        cap, rec = self.info()
+        rp, npp = C.c_void_p(), C.c_void_p()
+        _check(_lib.dmx_tape_data(self.h, C.byref(rp), C.byref(npp)))
+        torch.cuda.synchronize()
+        n = torch.as_tensor(_DevArray(npp.value, (self.W,), "<i4"), device="cuda").cpu().numpy()
+        recs = torch.as_tensor(_DevArray(rp.value, (self.W, cap, rec), "<f8"), device="cuda")
+        nmax = int(n.max()) if self.W else 0
+        return recs[:, :max(nmax, 1)].cpu().numpy(), n
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                _lib.dmx_tape_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+
+class _DevArray:
+    """A library-owned device buffer exposed to torch (read-only view)."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), True),
+                                         "version": 3, "strides": None}
+
+
+def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False):
+    """Forward rollout.  x0 [W, nx] and u [W, n_int, nu] CUDA float64.
+    Returns dict(x, status[, tape][, n_acc, n_rej])."""
+    x0 = x0.contiguous()
+    W = x0.shape[0]
+    assert x0.dtype == torch.float64 and x0.is_cuda and x0.shape[1] == model.nx
+    if model.nu:
+        u = u.contiguous()
+        assert u.dtype == torch.float64 and u.is_cuda and tuple(u.shape) == (W, n_int, model.nu)
+    else:
+        u = None
+    x_out = torch.empty_like(x0)
+    status = torch.empty(W, dtype=torch.int32, device=x0.device)
+    nacc = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    nrej = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    o = opts if opts is not None else default_opts()
+    th = _P()
+    _check(_lib.dmx_rollout(model.h, W, int(n_int), float(dt), C.byref(o), _ptr(x0), _ptr(u), _ptr(x_out),
+                            _ptr(status), _ptr(nacc), _ptr(nrej), C.byref(th) if tape else None, _stream()))
+    res = {"x": x_out, "status": status}
+    if counters:
+        res["n_acc"], res["n_rej"] = nacc, nrej
+    if tape:
+        res["tape"] = Tape(th, model, W, n_int)
+        res["_keep"] = (x0, u)  # the tape reads u during the reverse sweep
+    return res
+
+
+def rollout_vjp(tape, x_out_bar):
+    """x0_bar [W, nx], u_bar [W, n_int, nu] of sum(x_out_bar * x_out)."""
+    xb = x_out_bar.contiguous()
+    m = tape.model
+    x0b = torch.empty_like(xb)
+    ub = torch.empty((tape.W, tape.n_int, m.nu), dtype=torch.float64, device=xb.device) if m.nu else None
+    _check(_lib.dmx_rollout_vjp(tape.h, _ptr(xb), _ptr(x0b), _ptr(ub), _stream()))
+    return x0b, ub
+
+
+class Rollout(torch.autograd.Function):
+    """x_out = rollout(x0, u); backward runs the discrete adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, x0, u, model, n_int, dt, opts):
+        r = rollout(model, x0, u if model.nu else None, n_int, dt, opts=opts, tape=True)
+        ctx.tape = r["tape"]
+        ctx.keep = r["_keep"]
+        ctx.has_u = model.nu > 0
+        ctx.mark_non_differentiable(r["status"])
+        return r["x"], r["status"]
+
+    @staticmethod
+    def backward(ctx, xb, _sb):
+        x0b, ub = rollout_vjp(ctx.tape, xb)
+        return x0b, (ub if ctx.has_u else None), None, None, None, None

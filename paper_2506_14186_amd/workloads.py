@@ -35,13 +35,16 @@ from __future__ import annotations
 import numpy as np
 
 GRAVITY = [0.0, 0.0, -9.81]
-SOLIMP_DEFAULT = [0.9, 0.95, 0.001, 0.5, 2.0]
+# Impedance of the paper's cube and primitive tosses (App. E.1): d(0) = 0, so
+# the contact force is continuous when a contact activates at r = 0.
+SOLIMP_DEFAULT = [0.0, 0.95, 0.001, 0.5, 2.0]
 
 
 def _cfd_default(solimp):
-    # Contacts-from-distance continuation (d_c, d_0, w_c, m_c, p_c): tapers from
-    # the contact impedance at r = 0 to zero at r = w_c.
-    return [0.0, solimp[0], 0.01, 1.0, 4.0]
+    # Contacts-from-distance continuation (d_c, d_0, w_c, m_c, p_c), Sec. 4:
+    # from d_0 at r = 0 down to d_c = 0 at r = w_c = 1 cm; d_0 continues the
+    # contact impedance d(0) when that is at least 0.01.
+    return [0.0, max(float(solimp[0]), 0.01), 0.01, 1.0, 4.0]
 
 
 def _pair(g1, g2, mu, tc, solimp=None, dampratio=1.0, cfd=None):

@@ -1,0 +1,267 @@
+"""Parity of the HIP library (through its C ABI) with the oracle.
+
+Tolerances: a GPU step fed the oracle's step must agree to 1e-10 relative; a
+whole replayed step sequence to 1e-8; free adaptive end states to 1e-6;
+gradients to 1e-5 (relative, normwise per world: |dq|/max(|q|,1),
+|dv|/max(|v|,1e-3), |dg|/max(|g|,1e-12)).
+"""
+import numpy as np
+import pytest
+
+from paper_2506_14186_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_14186_amd import dmx
+    return dmx
+
+
+def _t(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def rel_state(a, b, nq):
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    dq = np.linalg.norm(a[:, :nq] - b[:, :nq], axis=1) / np.maximum(np.linalg.norm(b[:, :nq], axis=1), 1.0)
+    dv = np.linalg.norm(a[:, nq:] - b[:, nq:], axis=1) / np.maximum(np.linalg.norm(b[:, nq:], axis=1), 1e-3)
+    return np.maximum(dq, dv)
+
+
+def rel_grad(a, b):
+    a, b = np.atleast_2d(a), np.atleast_2d(b)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-12)
+
+
+def _sphere_batch(seeds):
+    x0 = np.concatenate([W.sphere_drop(seed=s)["x0"] for s in seeds])
+    return W.model_sphere(), x0, 1, 1.0
+
+
+def _cube_batch(n, horizon=0.5, seed=2):
+    cfg = W.cube_toss(seed=seed, n_worlds=n, horizon=horizon)
+    return cfg["model"], cfg["x0"], 1, horizon
+
+
+CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4]), "cube": lambda: _cube_batch(6)}
+
+
+def _oracle_tapes(oracle, desc, x0, n_int, dt):
+    om = oracle.Model(desc)
+    out = []
+    for w in range(x0.shape[0]):
+        r = om.rollout(x0[w], None, n_int, dt, tape_cap=200000)
+        assert r["status"] == 0
+        out.append(r)
+    return om, out
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_single_step_parity(D, oracle, case):
+    """Every oracle step replayed as an independent one-step GPU world."""
+    desc, x0, n_int, dt = CASES[case]()
+    om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
+    ys, hs, nxt = [], [], []
+    for r in tapes:
+        tp = r["tape"]
+        y_next = np.vstack([tp[1:, 2:], r["x"][None]])
+        ys.append(tp[:, 2:]); hs.append(tp[:, 1]); nxt.append(y_next)
+    ys, hs, nxt = np.vstack(ys), np.concatenate(hs), np.vstack(nxt)
+    model = D.Model(desc)
+    Wn = ys.shape[0]
+    forced = np.zeros((Wn, 1, 2))
+    forced[:, 0, 1] = hs
+    f_t, fn = _t(forced), _t(np.ones(Wn)).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn.data_ptr(), forced_cap=1)
+    res = D.rollout(model, _t(ys), None, 1, 10.0, opts=o)
+    assert int(res["status"].abs().sum()) == 0
+    err = rel_state(res["x"].cpu().numpy(), nxt, model.nq)
+    print(f"{case}: {Wn} single steps, max rel err {err.max():.3e}")
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_replayed_sequence_parity(D, oracle, case):
+    desc, x0, n_int, dt = CASES[case]()
+    om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
+    model = D.Model(desc)
+    cap = max(r["n_acc"] for r in tapes)
+    forced = np.zeros((x0.shape[0], cap, 2))
+    fn = np.zeros(x0.shape[0])
+    for w, r in enumerate(tapes):
+        forced[w, :r["n_acc"]] = r["tape"][:, :2]
+        fn[w] = r["n_acc"]
+    f_t, fn_t = _t(forced), _t(fn).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    res = D.rollout(model, _t(x0), None, n_int, dt, opts=o, tape=True)
+    assert int(res["status"].abs().sum()) == 0
+    recs, n = res["tape"].records()
+    worst = 0.0
+    for w, r in enumerate(tapes):
+        assert n[w] == r["n_acc"]
+        e = rel_state(recs[w, :n[w], 3:3 + model.nx], r["tape"][:, 2:], model.nq)
+        worst = max(worst, e.max())
+        np.testing.assert_array_equal(recs[w, :n[w], :2], r["tape"][:, :2])
+    ef = rel_state(res["x"].cpu().numpy(), np.stack([r["x"] for r in tapes]), model.nq)
+    print(f"{case}: replayed {int(fn.sum())} steps, max per-step rel err {worst:.3e}, final {ef.max():.3e}")
+    assert worst <= 1e-8 and ef.max() <= 1e-8
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_free_adaptive_parity_and_gradient(D, oracle, case):
+    desc, x0, n_int, dt = CASES[case]()
+    om = oracle.Model(desc)
+    model = D.Model(desc)
+    res = D.rollout(model, _t(x0), None, n_int, dt, tape=True, counters=True)
+    assert int(res["status"].abs().sum()) == 0
+    xbar = np.zeros_like(x0)
+    xbar[:, 0:3] = 1.0  # summed final position
+    if case == "sphere":
+        xbar[:, :] = 0.0
+        xbar[:, 2] = 1.0  # final height
+    g, _ = D.rollout_vjp(res["tape"], _t(xbar))
+    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=8)
+    ex = rel_state(res["x"].cpu().numpy(), ref["x"], model.nq)
+    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
+    nacc = res["n_acc"].cpu().numpy()
+    print(f"{case}: steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}; state err {ex.max():.2e}; "
+          f"grad err {eg.max():.2e}")
+    assert ex.max() <= 1e-6
+    assert eg.max() <= 1e-5
+
+
+def test_replayed_gradient_matches_oracle_tightly(D, oracle):
+    """Same step sequence on both sides: the reverse sweep equals the
+    forward-mode derivative of the oracle to rounding."""
+    desc, x0, n_int, dt = _cube_batch(4, horizon=0.3)
+    om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
+    model = D.Model(desc)
+    cap = max(r["n_acc"] for r in tapes)
+    forced = np.zeros((x0.shape[0], cap, 2))
+    fn = np.zeros(x0.shape[0])
+    for w, r in enumerate(tapes):
+        forced[w, :r["n_acc"]] = r["tape"][:, :2]
+        fn[w] = r["n_acc"]
+    f_t, fn_t = _t(forced), _t(fn).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    res = D.rollout(model, _t(x0), None, n_int, dt, opts=o, tape=True)
+    rng = np.random.default_rng(7)
+    xbar = rng.normal(size=x0.shape)
+    g, _ = D.rollout_vjp(res["tape"], _t(xbar))
+    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=4)
+    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
+    print(f"replayed-sequence gradient rel err {eg.max():.3e}")
+    assert eg.max() <= 1e-8
+
+
+def test_batch_and_team_invariance(D):
+    desc, x0, n_int, dt = _cube_batch(37, horizon=0.2)
+    model = D.Model(desc)
+    xbar = np.zeros_like(x0)
+    xbar[:, :3] = 1.0
+    full = D.rollout(model, _t(x0), None, n_int, dt, tape=True)
+    gfull, _ = D.rollout_vjp(full["tape"], _t(xbar))
+    for w in (0, 17, 36):
+        one = D.rollout(model, _t(x0[w:w + 1]), None, n_int, dt, tape=True)
+        g1, _ = D.rollout_vjp(one["tape"], _t(xbar[w:w + 1]))
+        np.testing.assert_array_equal(one["x"].cpu().numpy()[0], full["x"].cpu().numpy()[w])
+        np.testing.assert_array_equal(g1.cpu().numpy()[0], gfull.cpu().numpy()[w])
+    ref = full["x"].cpu().numpy()
+    for L in (1, 2, 4):
+        o = D.default_opts(lanes_per_world=L)
+        r = D.rollout(model, _t(x0), None, n_int, dt, opts=o)
+        e = rel_state(r["x"].cpu().numpy(), ref, model.nq)
+        assert e.max() <= 1e-6, (L, e.max())
+
+
+def test_edge_cases(D):
+    import torch
+    desc, x0, n_int, dt = _cube_batch(5, horizon=0.2)
+    model = D.Model(desc)
+    # empty batch
+    r = D.rollout(model, _t(np.zeros((0, 13))), None, n_int, dt)
+    assert r["x"].shape == (0, 13)
+    # ragged batch (5 worlds, 8-lane teams) and a non-finite world
+    bad = x0.copy()
+    bad[3, 9] = np.nan
+    r = D.rollout(model, _t(bad), None, n_int, dt, tape=True)
+    st = r["status"].cpu().numpy()
+    assert st[3] & D.STATUS["NONFINITE"] and (np.delete(st, 3) == 0).all()
+    g, _ = D.rollout_vjp(r["tape"], _t(np.ones_like(bad)))
+    g = g.cpu().numpy()
+    assert np.isnan(g[3]).all() and np.isfinite(np.delete(g, 3, axis=0)).all()
+    # step budget and tape capacity
+    r = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(max_attempts=3))
+    assert (r["status"].cpu().numpy() & D.STATUS["MAX_STEPS"]).all()
+    r = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(tape_steps=4), tape=True)
+    assert (r["status"].cpu().numpy() & D.STATUS["TAPE_OVERFLOW"]).all()
+    g, _ = D.rollout_vjp(r["tape"], _t(np.ones_like(x0)))
+    assert torch.isnan(g).all()
+    # API errors are reported, not launched
+    with pytest.raises(D.DmxError):
+        D.Model(W.model_chain())  # articulated chains are not compiled in this library build
+    with pytest.raises(D.DmxError):
+        D.rollout(model, _t(x0), None, 0, dt)
+
+
+def test_autograd_function_matches_vjp(D):
+    import torch
+    desc, x0, n_int, dt = _cube_batch(3, horizon=0.15)
+    model = D.Model(desc)
+    xt = _t(x0).requires_grad_(True)
+    x, st = D.Rollout.apply(xt, None, model, n_int, dt, D.default_opts())
+    loss = x[:, :3].sum()
+    loss.backward()
+    r = D.rollout(model, _t(x0), None, n_int, dt, tape=True)
+    xbar = torch.zeros_like(r["x"])
+    xbar[:, :3] = 1.0
+    g, _ = D.rollout_vjp(r["tape"], xbar)
+    np.testing.assert_array_equal(xt.grad.cpu().numpy(), g.cpu().numpy())
+
+
+def test_cfd_straight_through(D, oracle):
+    """Straight-through CFD: forward unchanged, gradient equals the oracle's
+    forward-mode derivative of the CFD field along the same trajectory."""
+    desc, x0, n_int, dt = _sphere_batch([1, 2])
+    model = D.Model(desc)
+    om = oracle.Model(desc)
+    xbar = np.zeros_like(x0)
+    xbar[:, 2] = 1.0
+    a = D.rollout(model, _t(x0), None, n_int, dt, tape=True)
+    b = D.rollout(model, _t(x0), None, n_int, dt, tape=True, opts=D.default_opts(cfd=1))
+    np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+    g, _ = D.rollout_vjp(b["tape"], _t(xbar))
+    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=2, cfd=1)
+    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
+    print(f"cfd gradient rel err {eg.max():.3e}")
+    assert eg.max() <= 1e-5
+
+
+def test_full_size_cube_sampled(D, oracle):
+    """The measured configuration (4096 cube worlds, 0.5 s) in the launch shape
+    the benchmark times; sampled worlds against the oracle."""
+    cfg = W.cube_toss(seed=2, n_worlds=4096, horizon=0.5)
+    model = D.Model(cfg["model"])
+    x0 = cfg["x0"]
+    res = D.rollout(model, _t(x0), None, 1, 0.5, tape=True, counters=True)
+    assert int(res["status"].abs().sum()) == 0
+    xbar = np.zeros_like(x0)
+    xbar[:, :3] = 1.0
+    g, _ = D.rollout_vjp(res["tape"], _t(xbar))
+    g = g.cpu().numpy()
+    assert np.isfinite(g).all()
+    sample = [0, 1, 777, 2048, 4095]
+    om = oracle.Model(cfg["model"])
+    ref = om.grad_batch(x0[sample], None, 1, 0.5, xbar[sample], n_threads=5)
+    ex = rel_state(res["x"].cpu().numpy()[sample], ref["x"], model.nq)
+    eg = rel_grad(g[sample], ref["x0bar"])
+    nacc = res["n_acc"].cpu().numpy()
+    print(f"4096 worlds: accepted steps mean {nacc.mean():.0f} max {nacc.max()}; sampled state err "
+          f"{ex.max():.2e} grad err {eg.max():.2e}")
+    assert ex.max() <= 1e-6 and eg.max() <= 1e-5

@@ -461,7 +461,7 @@ def test_rollout_derivative_matches_frozen_step_fd(oracle, name):
     fd = _fd_frozen(m, x0, u, n_int, dt, dirs)
     j = m.rollout_jvp(x0, u, n_int, dt, dirs)
     assert j["status"] == 0
-    np.testing.assert_allclose(j["tx"], fd, rtol=2e-6, atol=2e-6 * np.abs(fd).max())
+    np.testing.assert_allclose(j["tx"], fd, rtol=2e-5, atol=2e-6 * np.abs(fd).max())
 
 
 def test_rhs_tangent_matches_fd_with_and_without_cfd(oracle):
