@@ -128,6 +128,17 @@ typedef struct {
   double* steplog;
   int32_t* log_n;
   int32_t log_cap;
+  /* instrumentation (device pointers, may be NULL): per-world work units of
+   * the forward, [n_worlds][7] = attempts, rhs evaluations, active contacts
+   * over rhs evaluations, Newton iterations, active contacts and active edges
+   * over Newton iterations, line-search contact evaluations; and of the
+   * reverse sweep, [n_worlds][4] = steps, acceleration vjps, active contacts
+   * and active edges over vjps (written by dmx_rollout_vjp on this tape). */
+  int64_t* fwd_counters;
+  int64_t* adj_counters;
+  /* 0: all worlds in one launch (default); 1: one launch per world on the
+   * stream, the plain baseline form of the same kernels. */
+  int32_t launch_mode;
 } dmx_solver_opts;
 
 void dmx_default_opts(dmx_solver_opts* opts);
@@ -144,7 +155,10 @@ void dmx_model_destroy(dmx_model* model);
  * intervals of interval_dt seconds each.  x0 [W][nx], u [W][n_intervals][nu]
  * (may be NULL when nu == 0), x_out [W][nx], world_status [W].  If tape is
  * non-NULL a tape (device memory owned by the library) is created holding
- * every accepted step and its stage accelerations, for dmx_rollout_vjp.
+ * every accepted step and its stage accelerations, for dmx_rollout_vjp; if
+ * *tape is already a tape of this model and batch size (and at least
+ * opts->tape_steps capacity) it is reused in place, with no allocation.
+ * The tape keeps the pointer u: u must stay valid while the tape is used.
  * Per-world step counters: n_accepted, n_rejected ([W] int32, device, may be NULL). */
 dmx_status dmx_rollout(const dmx_model* model, int32_t n_worlds, int32_t n_intervals, double interval_dt,
                        const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,

@@ -38,10 +38,16 @@ struct FreeModel {
   PairF pair[kMaxPairs];
 };
 
+// Per-world status and work-unit counters.  Team-level events are counted
+// by lane 0 of the team, per-contact events by the lane owning the contact;
+// the counters are summed over the team when written out.
 struct Stat {
   int newton_it;
   int status;
+  long long u_att, u_rhs, u_con, u_nit, u_ncon, u_nedge, u_ls;  // forward
+  long long u_step, u_vjp, u_vcon, u_vedge;                      // reverse
 };
+DMX_DEV bool team_leader(int L) { return (threadIdx.x & (L - 1)) == 0; }
 
 // ------------------------------------------------------------ impedance
 // MuJoCo-style polynomial spline y(x) on [0, 1] with midpoint and power, and dy/dx.
@@ -258,6 +264,12 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
   if (!team_any<L>(any)) return;
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
+    if (team_leader(L)) st.u_nit++;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+      st.u_ncon += (act[k] != 0u);
+      st.u_nedge += __popc(act[k]);
+    }
     // gradient and Hessian of the active set
     double gp[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -309,6 +321,8 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     double dMd = dot6(dl, Mdl), xMd = dot6(dx, Mdl);
     double lo = 0.0, hi = 1e300, a = 1.0;
     for (int ls = 0; ls < 60; ++ls) {
+#pragma unroll
+      for (int k = 0; k < CPL; ++k) st.u_ls += rw.on[k];
       double c1 = 0.0, c2 = 0.0;
       uint32_t sa[CPL];
 #pragma unroll
@@ -384,6 +398,9 @@ struct FreePhys {
     a0_of(m, v, tau, a0);
     FreeRows<CPL> rw;
     free_rows<CPL, L>(m, p, R, v, cfd, beta, rw);
+    if (team_leader(L)) st.u_rhs++;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
     free_newton<CPL, L>(m, rw, a0, a, maxit, st);
   }
 
@@ -414,6 +431,9 @@ struct FreePhys {
     uint32_t act[CPL];
     double s[CPL][4];
     free_active<CPL>(rw, xs, act, s);
+    if (team_leader(L)) st.u_vjp++;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
     double H[36];
     free_hessian<CPL, L>(m, rw, act, H);
     chol<6>(H);

@@ -83,17 +83,59 @@ void make_tangents(const double* n, double* t1, double* t2) {
 using FwdFn = void (*)(const void*, const dmx::FwdArgs&, hipStream_t, int);
 using AdjFn = void (*)(const void*, const dmx::AdjArgs&, hipStream_t, int);
 
+// Batched form: one launch, one team of lanes per world.  Plain form
+// (plain != 0): one launch per world with the same kernel, serialized on the
+// stream (the baseline of the benchmark).
 template <class P>
-void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int W) {
-  const long long threads = (long long)W * P::TEAM;
-  const int blocks = (int)((threads + 63) / 64);
-  hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int plain) {
+  if (!plain) {
+    const long long threads = (long long)a.W * P::TEAM;
+    const int blocks = (int)((threads + 63) / 64);
+    hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+    return;
+  }
+  constexpr int NX = P::NQ + P::NV;
+  for (int w = 0; w < a.W; ++w) {
+    dmx::FwdArgs b = a;
+    b.W = 1;
+    b.x0 = a.x0 + (size_t)w * NX;
+    b.u = a.u ? a.u + (size_t)w * a.n_int * a.nu : nullptr;
+    b.xout = a.xout + (size_t)w * NX;
+    b.status = a.status + w;
+    b.n_acc = a.n_acc ? a.n_acc + w : nullptr;
+    b.n_rej = a.n_rej ? a.n_rej + w : nullptr;
+    b.counters = a.counters ? a.counters + (size_t)w * dmx::kFwdCounters : nullptr;
+    b.tape = a.tape ? a.tape + (size_t)w * a.cap * a.rec : nullptr;
+    b.forced = a.forced ? a.forced + (size_t)w * a.forced_cap * 2 : nullptr;
+    b.forced_n = a.forced_n ? a.forced_n + w : nullptr;
+    b.steplog = a.steplog ? a.steplog + (size_t)w * a.log_cap * 4 : nullptr;
+    b.log_n = a.log_n ? a.log_n + w : nullptr;
+    hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
+  }
 }
 template <class P>
-void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int W) {
-  const long long threads = (long long)W * P::TEAM;
-  const int blocks = (int)((threads + 63) / 64);
-  hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
+  if (!plain) {
+    const long long threads = (long long)a.W * P::TEAM;
+    const int blocks = (int)((threads + 63) / 64);
+    hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+    return;
+  }
+  constexpr int NX = P::NQ + P::NV;
+  const size_t nut = (size_t)a.n_int * a.nu;
+  for (int w = 0; w < a.W; ++w) {
+    dmx::AdjArgs b = a;
+    b.W = 1;
+    b.tape = a.tape + (size_t)w * a.cap * a.rec;
+    b.n_acc = a.n_acc + w;
+    b.status = a.status + w;
+    b.u = a.u ? a.u + (size_t)w * nut : nullptr;
+    b.xbar = a.xbar + (size_t)w * NX;
+    b.x0bar = a.x0bar + (size_t)w * NX;
+    b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
+    b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
+    hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
+  }
 }
 
 struct KernelEntry {
@@ -138,6 +180,8 @@ struct dmx_tape {
   const double* u = nullptr;
   dmx::SolverOpts o{};
   AdjFn adj = nullptr;
+  int64_t* adj_counters = nullptr;
+  int plain = 0;
 };
 
 extern "C" {
@@ -298,18 +342,31 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
   const KernelEntry* k = find_kernel(m, o.lanes_per_world);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model and lanes_per_world");
-  if (tape) *tape = nullptr;
-  if (W == 0) return DMX_OK;
+  dmx_tape* reuse = tape ? *tape : nullptr;
+  if (reuse) {
+    const long long want = o.tape_steps > 0 ? o.tape_steps : reuse->cap;
+    if (reuse->model != m || reuse->W != W || reuse->cap < want)
+      return fail(DMX_ERR_INVALID_ARG, "tape to reuse does not match model/n_worlds/capacity");
+  }
+  if (W == 0) { if (tape && !reuse) *tape = nullptr; return DMX_OK; }
   hipStream_t s = (hipStream_t)stream;
   const int NX = m->nq + m->nv;
   dmx::FwdArgs a{};
+  if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
   a.W = W; a.n_int = n_int; a.nu = m->nu; a.dt = dt; a.x0 = x0; a.u = u; a.xout = x_out;
+  a.counters = (long long*)o.fwd_counters;
   a.status = world_status; a.n_acc = n_accepted; a.n_rej = n_rejected; a.n_newton = nullptr;
   a.forced = o.forced; a.forced_n = o.forced_n; a.forced_cap = o.forced_cap;
   a.steplog = o.steplog; a.log_n = o.log_n; a.log_cap = o.log_cap;
   a.o = to_solver(o);
   dmx_tape* tp = nullptr;
-  if (tape) {
+  if (reuse) {
+    tp = reuse;
+    tp->n_int = n_int; tp->dt = dt; tp->u = u; tp->o = a.o; tp->adj = k->adj; tp->team = k->team;
+    tp->adj_counters = o.adj_counters; tp->plain = o.launch_mode;
+    a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
+    a.n_acc = tp->n_acc; a.status = tp->status;
+  } else if (tape) {
     tp = new dmx_tape();
     tp->model = m; tp->W = W; tp->n_int = n_int; tp->nu = m->nu; tp->dt = dt; tp->u = u;
     tp->rec = 3 + NX + 6 * m->nv;
@@ -317,6 +374,8 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     tp->o = a.o;
     tp->adj = k->adj;
     tp->team = k->team;
+    tp->adj_counters = o.adj_counters;
+    tp->plain = o.launch_mode;
     const size_t bytes = (size_t)W * tp->cap * tp->rec * sizeof(double);
     hipError_t e = hipMalloc(&tp->records, bytes);
     if (e == hipSuccess) e = hipMalloc(&tp->n_acc, sizeof(int) * W);
@@ -328,7 +387,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
     a.n_acc = tp->n_acc; a.status = tp->status;
   }
-  k->fwd(m->dev, a, s, W);
+  k->fwd(m->dev, a, s, o.launch_mode);
   HIP_TRY(hipGetLastError());
   if (tp) {
     HIP_TRY(hipMemcpyAsync(world_status, tp->status, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
@@ -345,7 +404,8 @@ dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
   a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
   a.o = tp->o;
-  tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->W);
+  a.counters = (long long*)tp->adj_counters;
+  tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->plain);
   HIP_TRY(hipGetLastError());
   return DMX_OK;
 }

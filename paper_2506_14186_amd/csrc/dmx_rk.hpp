@@ -68,9 +68,13 @@ struct SolverOpts {
   int newton_maxit, cfd;
 };
 
+constexpr int kFwdCounters = 7;  // attempts, rhs, contacts, newton its, newton contacts, edges, line search
+constexpr int kAdjCounters = 4;  // steps, vjps, vjp contacts, vjp edges
+
 struct FwdArgs {
   int W, n_int, nu;
   double dt;
+  long long* counters;  // [W][kFwdCounters] or null
   const double* x0;
   const double* u;
   double* xout;
@@ -92,6 +96,7 @@ struct FwdArgs {
 
 struct AdjArgs {
   int W, n_int, nu;
+  long long* counters;  // [W][kAdjCounters] or null
   const double* tape;
   long long cap;
   int rec;
@@ -173,7 +178,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
 #pragma unroll
   for (int i = 0; i < NX; ++i) y[i] = a.x0[(size_t)w * NX + i];
   double tau[NV];
-  Stat st{0, 0};
+  Stat st{};
   double t = 0.0, hprop = fmin(o.h0, a.dt), eprev = 1.0;
   long long attempts = 0;
   int nacc = 0, nrej = 0, fi = 0, nlog = 0;
@@ -207,6 +212,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
       }
       if (attempts >= o.max_attempts) { st.status |= 1; break; }
       ++attempts;
+      if (tl == 0) st.u_att++;
       double Y[NX], dq[NV];
 #pragma unroll 1
       for (int i = 1; i < 7; ++i) {
@@ -288,6 +294,13 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
     }
   }
   team_store<NX, L>(a.xout + (size_t)w * NX, y, tl);
+  if (a.counters) {
+    double c[kFwdCounters] = {(double)st.u_att, (double)st.u_rhs, (double)st.u_con, (double)st.u_nit,
+                              (double)st.u_ncon, (double)st.u_nedge, (double)st.u_ls};
+    team_sum_arr<L, kFwdCounters>(c);
+    if (tl == 0)
+      for (int i = 0; i < kFwdCounters; ++i) a.counters[(size_t)w * kFwdCounters + i] = (long long)c[i];
+  }
   if (tl == 0) {
     a.status[w] = st.status;
     if (a.n_acc) a.n_acc[w] = nacc;
@@ -320,7 +333,7 @@ __global__ void __launch_bounds__(256) adj_kernel(const typename P::Model* __res
   for (int i = 0; i < NX; ++i) yb[i] = a.xbar[(size_t)w * NX + i];
   double tau[NV], tb_acc[NV];
   int cur_k = -1;
-  Stat st{0, 0};
+  Stat st{};
   __shared__ double sA[64 / L][7][NV];
   __shared__ double sAb[64 / L][6][NV];
   double (*A)[NV] = sA[(threadIdx.x & 63) / L];
@@ -329,6 +342,7 @@ __global__ void __launch_bounds__(256) adj_kernel(const typename P::Model* __res
     const double* rec = a.tape + ((size_t)w * a.cap + s) * a.rec;
     const double h = rec[1];
     const int kk = (int)rec[2];
+    if (tl == 0) st.u_step++;
     if (kk != cur_k) {
       if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
       cur_k = kk;
@@ -395,6 +409,12 @@ __global__ void __launch_bounds__(256) adj_kernel(const typename P::Model* __res
   }
   if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
+  if (a.counters) {
+    double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
+    team_sum_arr<L, kAdjCounters>(c);
+    if (tl == 0)
+      for (int i = 0; i < kAdjCounters; ++i) a.counters[(size_t)w * kAdjCounters + i] = (long long)c[i];
+  }
 }
 
 }  // namespace dmx

@@ -42,7 +42,11 @@ class SolverOpts(C.Structure):
         ("max_attempts", C.c_int64), ("newton_maxit", C.c_int32), ("cfd", C.c_int32),
         ("softplus_beta", C.c_double), ("tape_steps", C.c_int64), ("lanes_per_world", C.c_int32),
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
-        ("log_cap", C.c_int32)]
+        ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32)]
+
+FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
+                "ls_contacts")
+ADJ_COUNTERS = ("steps", "vjps", "vjp_contacts", "vjp_edges")
 
 
 _lib.dmx_last_error.restype = C.c_char_p
@@ -186,9 +190,10 @@ class _DevArray:
                                          "version": 3, "strides": None}
 
 
-def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False):
+def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False, reuse=None):
     """Forward rollout.  x0 [W, nx] and u [W, n_int, nu] CUDA float64.
-    Returns dict(x, status[, tape][, n_acc, n_rej])."""
+    Returns dict(x, status[, tape][, n_acc, n_rej]).  ``reuse``: a Tape of the
+    same model and batch size whose buffers are overwritten (no allocation)."""
     x0 = x0.contiguous()
     W = x0.shape[0]
     assert x0.dtype == torch.float64 and x0.is_cuda and x0.shape[1] == model.nx
@@ -202,15 +207,20 @@ def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False):
     nacc = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
     nrej = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
     o = opts if opts is not None else default_opts()
-    th = _P()
+    th = _P(reuse.h.value if isinstance(reuse.h, _P) else reuse.h) if reuse is not None else _P()
+    tape = tape or reuse is not None
     _check(_lib.dmx_rollout(model.h, W, int(n_int), float(dt), C.byref(o), _ptr(x0), _ptr(u), _ptr(x_out),
                             _ptr(status), _ptr(nacc), _ptr(nrej), C.byref(th) if tape else None, _stream()))
     res = {"x": x_out, "status": status}
     if counters:
         res["n_acc"], res["n_rej"] = nacc, nrej
-    if tape:
+    if reuse is not None:
+        reuse.n_int = n_int
+        reuse.keep = (x0, u)  # the tape reads u during the reverse sweep
+        res["tape"] = reuse
+    elif tape:
         res["tape"] = Tape(th, model, W, n_int)
-        res["_keep"] = (x0, u)  # the tape reads u during the reverse sweep
+        res["tape"].keep = (x0, u)
     return res
 
 
@@ -231,7 +241,6 @@ class Rollout(torch.autograd.Function):
     def forward(ctx, x0, u, model, n_int, dt, opts):
         r = rollout(model, x0, u if model.nu else None, n_int, dt, opts=opts, tape=True)
         ctx.tape = r["tape"]
-        ctx.keep = r["_keep"]
         ctx.has_u = model.nu > 0
         ctx.mark_non_differentiable(r["status"])
         return r["x"], r["status"]
