@@ -139,6 +139,10 @@ typedef struct {
   /* 0: all worlds in one launch (default); 1: one launch per world on the
    * stream, the plain baseline form of the same kernels. */
   int32_t launch_mode;
+  /* failure capture (device, may be NULL): [n_worlds][nq + nv + nv] receives
+   * the stage state and generalized force at which a world's contact solve
+   * first failed (status bits NONFINITE or SOLVER_MAXIT). */
+  double* fail_state;
 } dmx_solver_opts;
 
 void dmx_default_opts(dmx_solver_opts* opts);
@@ -179,6 +183,14 @@ dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t
  * counts [W] (int32). */
 dmx_status dmx_tape_data(const dmx_tape* tape, const double** records, const int32_t** n_steps);
 void dmx_tape_destroy(dmx_tape* tape);
+
+/* Acceleration of the right-hand side F(x) = (v, qacc) at n independent states
+ * (Sec. 2: the equation of motion with the soft-contact solve of Sec. 2.1).
+ * x [n][nq+nv], tau [n][nv] generalized forces (NULL = zero), acc_out
+ * [n][nv], status [n] (device pointers).  cfd = 1 evaluates the
+ * contacts-from-distance field instead. */
+dmx_status dmx_accel(const dmx_model* model, int32_t n, const double* x, const double* tau, int32_t cfd,
+                     double* acc_out, int32_t* status, void* stream);
 
 /* Thread-local message of the last failed call. */
 const char* dmx_last_error(void);

@@ -769,7 +769,15 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
       }
       if (attempts >= o.max_attempts) { st->status |= ORC_MAX_STEPS; break; }
       ++attempts;
+      const int status_before = st->status;
       double err = dopri_attempt(m, y.data(), uk, k1, h, o, !forced || !is_dual<S>(), yn.data(), k7, st);
+      // reading: a contact solve that fails at a trial stage rejects the
+      // attempt (as an infinite error estimate); it is fatal only at an
+      // accepted state or in a replay
+      if (!forced && (st->status & (ORC_NONFINITE | ORC_SOLVER_MAXIT))) {
+        st->status = status_before;
+        err = HUGE_VAL;
+      }
       bool accept = forced ? true : (err <= 1.0);
       double et = std::isfinite(err) ? std::max(err, o.err_floor) : 1e300;
       double fac = o.safety * std::pow(et, -(o.kP + o.kI) / o.err_order) * std::pow(eprev, o.kP / o.err_order);

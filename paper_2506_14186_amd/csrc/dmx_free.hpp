@@ -296,6 +296,16 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
 #pragma unroll
     for (int i = 0; i < 6; ++i) dl[i] = -(Mdx[i] + gp[i]);
     chol_solve<6>(H, dl);
+    // a step at rounding level of the iterate: x + dl is the minimizer to
+    // working precision (an activity flip there is a rounding artefact)
+    double dmax = 0.0, xmax = 1.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { dmax = fmax(dmax, fabs(dl[i])); xmax = fmax(xmax, fmax(fabs(x[i]), fabs(a0[i]))); }
+    if (dmax <= 1e-13 * xmax) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) x[i] += dl[i];
+      return;
+    }
     // directional data of every row
     double t[CPL][4];
     uint32_t act1[CPL];
@@ -341,7 +351,8 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
       c2 = team_sum<L>(c2) + dMd;
       double dphi = a * c2 + c1;
       if (dphi > 0.0) hi = a; else lo = a;
-      double an = -c1 / c2;
+      double an = (c2 > 0.0) ? -c1 / c2 : a;
+      if (!isfinite(an)) an = a;
       uint32_t sn[CPL];
 #pragma unroll
       for (int k = 0; k < CPL; ++k) {
@@ -354,6 +365,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
       if (same_active<CPL, L>(sa, sn)) { a = an; break; }
       if (!(an > lo && an < hi)) an = (hi < 1e299) ? 0.5 * (lo + hi) : 2.0 * a;
       a = an;
+      if (hi - lo <= 1e-15 * hi) break;  // root at a kink of the piecewise-linear derivative
       if (ls == 59) a = lo > 0.0 ? lo : a;
     }
 #pragma unroll

@@ -110,6 +110,7 @@ void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int pla
     b.forced_n = a.forced_n ? a.forced_n + w : nullptr;
     b.steplog = a.steplog ? a.steplog + (size_t)w * a.log_cap * 4 : nullptr;
     b.log_n = a.log_n ? a.log_n + w : nullptr;
+    b.fail_state = a.fail_state ? a.fail_state + (size_t)w * (NX + P::NV) : nullptr;
     hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }
@@ -138,14 +139,27 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
   }
 }
 
+using AccFn = void (*)(const void*, int, const double*, const double*, int, const dmx::SolverOpts&, double*, int*,
+                       hipStream_t);
+
+template <class P>
+void launch_acc(const void* model, int n, const double* x, const double* tau, int cfd, const dmx::SolverOpts& o,
+                double* acc, int* status, hipStream_t s) {
+  const long long threads = (long long)n * P::TEAM;
+  const int blocks = (int)((threads + 63) / 64);
+  hipLaunchKernelGGL(dmx::accel_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, n, x, tau,
+                     cfd, o.beta, o.newton_maxit, acc, status);
+}
+
 struct KernelEntry {
   int kind, nc, team;
   FwdFn fwd;
   AdjFn adj;
+  AccFn acc;
 };
 
 #define FREE_ENTRY(NC, L) \
-  {0, NC, L, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>}
+  {0, NC, L, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, &launch_acc<dmx::FreePhys<NC, L>>}
 
 const KernelEntry kKernels[] = {
     FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
@@ -331,9 +345,10 @@ static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
 dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, const dmx_solver_opts* opts,
                        const double* x0, const double* u, double* x_out, int32_t* world_status,
                        int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape, void* stream) {
-  if (!m || !x0 || !x_out || !world_status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
   if (W < 0 || n_int <= 0 || !(dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
-  if (m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  if (W > 0 && (!x0 || !x_out || !world_status)) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (W > 0 && m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
   dmx_solver_opts o;
   if (opts) o = *opts; else dmx_default_opts(&o);
   if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0)
@@ -355,6 +370,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
   a.W = W; a.n_int = n_int; a.nu = m->nu; a.dt = dt; a.x0 = x0; a.u = u; a.xout = x_out;
   a.counters = (long long*)o.fwd_counters;
+  a.fail_state = o.fail_state;
   a.status = world_status; a.n_acc = n_accepted; a.n_rej = n_rejected; a.n_newton = nullptr;
   a.forced = o.forced; a.forced_n = o.forced_n; a.forced_cap = o.forced_cap;
   a.steplog = o.steplog; a.log_n = o.log_n; a.log_cap = o.log_cap;
@@ -394,6 +410,21 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     if (n_accepted) HIP_TRY(hipMemcpyAsync(n_accepted, tp->n_acc, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
     *tape = tp;
   }
+  return DMX_OK;
+}
+
+dmx_status dmx_accel(const dmx_model* m, int32_t n, const double* x, const double* tau, int32_t cfd, double* acc,
+                     int32_t* status, void* stream) {
+  if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
+  if (n < 0) return fail(DMX_ERR_INVALID_ARG, "bad count");
+  if (n == 0) return DMX_OK;
+  if (!x || !acc || !status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  const KernelEntry* k = find_kernel(m, 0);
+  if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  dmx_solver_opts oo;
+  dmx_default_opts(&oo);
+  k->acc(m->dev, n, x, tau, cfd, to_solver(oo), acc, status, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
   return DMX_OK;
 }
 

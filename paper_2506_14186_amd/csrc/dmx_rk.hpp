@@ -91,6 +91,7 @@ struct FwdArgs {
   double* steplog;
   int* log_n;
   int log_cap;
+  double* fail_state;
   SolverOpts o;
 };
 
@@ -162,6 +163,35 @@ DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, doubl
 }
 
 template <class P>
+DMX_DEV void capture_failure(double* dst, int w, const double* Y, const double* tau, int tl) {
+  constexpr int NX = P::NQ + P::NV, L = P::TEAM;
+  double* d = dst + (size_t)w * (NX + P::NV);
+  team_store<NX, L>(d, Y, tl);
+  team_store<P::NV, L>(d + NX, tau, tl);
+}
+
+// Accelerations at independent states (one team per state).
+template <class P>
+__global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __restrict__ model, int n,
+                                                   const double* x, const double* tau_in, int cfd, double beta,
+                                                   int maxit, double* acc_out, int* status) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = gt / L;
+  const int tl = gt & (L - 1);
+  if (w >= n) return;
+  double y[NX], tau[NV], acc[NV];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) y[i] = x[(size_t)w * NX + i];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) tau[i] = tau_in ? tau_in[(size_t)w * NV + i] : 0.0;
+  Stat st{};
+  P::acc(*model, y, tau, cfd != 0, beta, maxit, acc, st);
+  team_store<NV, L>(acc_out + (size_t)w * NV, acc, tl);
+  if (tl == 0) status[w] = st.status;
+}
+
+template <class P>
 __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,6 +225,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
       if (!have_k1) {
         double a1[NV];
         P::acc(m, y, tau, false, o.beta, o.newton_maxit, a1, st);
+        if ((st.status & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, y, tau, tl);
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[0][d] = a1[d];
         have_k1 = true;
@@ -214,11 +245,14 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
       ++attempts;
       if (tl == 0) st.u_att++;
       double Y[NX], dq[NV];
+      const int status_before = st.status;
 #pragma unroll 1
       for (int i = 1; i < 7; ++i) {
         stage_state<P>(y, A, i, h, Y, dq);
         double ai[NV];
+        const int before = st.status;
         P::acc(m, Y, tau, false, o.beta, o.newton_maxit, ai, st);
+        if ((st.status & 12) && !(before & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, Y, tau, tl);
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
       }
@@ -252,6 +286,12 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
           acc2 += (ev[d] / sc) * (ev[d] / sc);
         }
         err = sqrt(acc2 / NX);
+      }
+      // a contact solve that failed at a trial stage rejects the attempt
+      // (the step shrinks); only a failure at an accepted state is fatal
+      if ((st.status & 12) && !a.forced) {
+        st.status = status_before;
+        err = __longlong_as_double(0x7ff0000000000000ll);
       }
       const bool accept = a.forced ? true : (err <= 1.0);
       const double et = isfinite(err) ? fmax(err, o.err_floor) : 1e300;

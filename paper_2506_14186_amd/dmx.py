@@ -42,7 +42,8 @@ class SolverOpts(C.Structure):
         ("max_attempts", C.c_int64), ("newton_maxit", C.c_int32), ("cfd", C.c_int32),
         ("softplus_beta", C.c_double), ("tape_steps", C.c_int64), ("lanes_per_world", C.c_int32),
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
-        ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32)]
+        ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32),
+        ("fail_state", _P)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
                 "ls_contacts")
@@ -57,15 +58,16 @@ _lib.dmx_model_destroy.argtypes = [_P]
 _lib.dmx_rollout.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P,
                              C.POINTER(_P), _P]
 _lib.dmx_rollout_vjp.argtypes = [_P, _P, _P, _P, _P]
+_lib.dmx_accel.argtypes = [_P, C.c_int32, _P, _P, C.c_int32, _P, _P, _P]
 _lib.dmx_tape_info.argtypes = [_P, _P, _P]
 _lib.dmx_tape_data.argtypes = [_P, _P, _P]
 _lib.dmx_tape_destroy.argtypes = [_P]
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
-           "dmx_tape_data"):
+           "dmx_tape_data", "dmx_accel"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
-           "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_last_error"]
+           "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_last_error"]
 
 
 class DmxError(RuntimeError):
@@ -186,7 +188,7 @@ class _DevArray:
     """A library-owned device buffer exposed to torch (read-only view)."""
 
     def __init__(self, ptr, shape, typestr):
-        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), True),
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
                                          "version": 3, "strides": None}
 
 
@@ -222,6 +224,17 @@ def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False, reus
         res["tape"] = Tape(th, model, W, n_int)
         res["tape"].keep = (x0, u)
     return res
+
+
+def accel(model, x, tau=None, cfd=False):
+    """Accelerations F(x) at independent states x [n, nx] (and generalized forces tau [n, nv])."""
+    x = x.contiguous()
+    n = x.shape[0]
+    acc = torch.empty((n, model.nv), dtype=torch.float64, device=x.device)
+    st = torch.empty(n, dtype=torch.int32, device=x.device)
+    tau = tau.contiguous() if tau is not None else None
+    _check(_lib.dmx_accel(model.h, n, _ptr(x), _ptr(tau), int(cfd), _ptr(acc), _ptr(st), _stream()))
+    return acc, st
 
 
 def rollout_vjp(tape, x_out_bar):
