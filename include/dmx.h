@@ -192,6 +192,59 @@ void dmx_tape_destroy(dmx_tape* tape);
 dmx_status dmx_accel(const dmx_model* model, int32_t n, const double* x, const double* tau, int32_t cfd,
                      double* acc_out, int32_t* status, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop for model-predictive-control style work (the gradient-based
+ * MPC of Sec. 5.2 evaluates many candidate control sequences and their
+ * gradients per planning step): each request is N candidate control
+ * sequences of one model from one initial state over H intervals; the result
+ * is each candidate's cost
+ *   cost = |q_T[0:3] - target|^2 + ctrl_weight * sum_k |u_k|^2 * interval_dt
+ * (q_T[0:3]: the first three position coordinates of the final state) and
+ * its gradient with respect to the controls.  Requests are admitted in
+ * arrival order while the device-memory budget and the in-flight limit allow,
+ * and run concurrently on several streams; results are bitwise independent of
+ * what else is in flight.  All request/result pointers are HOST memory; the
+ * request's inputs are copied by dmx_submit. */
+typedef struct dmx_server dmx_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device arena the server allocates once (default 8 GiB) */
+  int32_t max_inflight;      /* requests on the device at once (default 64) */
+  int32_t n_streams;         /* HIP streams, default priority (default 8) */
+  int32_t steps_per_interval;/* tape capacity per world = this * n_intervals + 64 (default 40) */
+} dmx_server_opts;
+
+typedef struct {
+  const dmx_model* model;
+  int32_t n_worlds;          /* N candidates */
+  int32_t n_intervals;       /* H */
+  double interval_dt;
+  const double* x0;          /* [nq+nv], shared by the candidates */
+  const double* u;           /* [N][H][nu] */
+  double target[3];
+  double ctrl_weight;
+  int32_t want_grad;         /* 0: costs only */
+} dmx_request;
+
+typedef struct {
+  double* cost;              /* [N] (caller buffers, filled by dmx_poll) */
+  double* grad_u;            /* [N][H][nu] or NULL */
+  int32_t* world_status;     /* [N] or NULL */
+  double t_submit, t_start, t_done;  /* seconds on the server's monotonic clock */
+} dmx_result;
+
+void dmx_default_server_opts(dmx_server_opts* opts);
+dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out);
+/* Queue a request; DMX_ERR_BUDGET if it can never fit the budget. */
+dmx_status dmx_submit(dmx_server* server, const dmx_request* req, uint64_t* ticket);
+/* DMX_PENDING until the request is done, then DMX_OK with the result copied
+ * out (the ticket is then released); DMX_ERR_NOT_FOUND for unknown tickets. */
+dmx_status dmx_poll(dmx_server* server, uint64_t ticket, dmx_result* out);
+/* Requests queued and in flight, and bytes of the budget in use. */
+dmx_status dmx_server_stats(const dmx_server* server, int32_t* queued, int32_t* inflight, int64_t* bytes_in_use);
+/* Waits for in-flight work, then frees everything. */
+void dmx_server_destroy(dmx_server* server);
+
 /* Thread-local message of the last failed call. */
 const char* dmx_last_error(void);
 

@@ -10,6 +10,7 @@
 #include "../../include/dmx.h"
 #include "dmx_free.hpp"
 #include "dmx_rk.hpp"
+#include "dmx_server.hpp"
 
 namespace {
 
@@ -461,6 +462,277 @@ void dmx_tape_destroy(dmx_tape* tp) {
   if (tp->n_acc) (void)hipFree(tp->n_acc);
   if (tp->status) (void)hipFree(tp->status);
   delete tp;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- serving
+namespace {
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct SrvReq {
+  uint64_t id = 0;
+  const dmx_model* model = nullptr;
+  int N = 0, H = 0, nu = 0, nx = 0, rec = 0;
+  long long cap = 0;
+  double dt = 0.0, cw = 0.0, target[3] = {0, 0, 0};
+  int want_grad = 0;
+  std::vector<double> x0, u;
+  // device block layout (offsets in bytes from the block start)
+  size_t off = 0, bytes = 0;
+  size_t o_x0, o_x0s, o_u, o_xout, o_status, o_nacc, o_xbar, o_x0bar, o_ubar, o_cost, o_tape;
+  void* pin_in = nullptr;
+  void* pin_out = nullptr;
+  size_t in_bytes = 0, out_bytes = 0;
+  hipEvent_t ev = nullptr;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+void layout(SrvReq& r) {
+  size_t o = 0;
+  auto take = [&](size_t n) { size_t at = o; o += align256(n); return at; };
+  r.o_x0 = take(sizeof(double) * r.nx);
+  r.o_x0s = take(sizeof(double) * (size_t)r.N * r.nx);
+  r.o_u = take(sizeof(double) * (size_t)r.N * r.H * r.nu + 8);
+  r.o_xout = take(sizeof(double) * (size_t)r.N * r.nx);
+  r.o_status = take(sizeof(int) * (size_t)r.N);
+  r.o_nacc = take(sizeof(int) * (size_t)r.N);
+  r.o_xbar = take(sizeof(double) * (size_t)r.N * r.nx);
+  r.o_x0bar = take(sizeof(double) * (size_t)r.N * r.nx);
+  r.o_ubar = take(sizeof(double) * (size_t)r.N * r.H * r.nu + 8);
+  r.o_cost = take(sizeof(double) * (size_t)r.N);
+  r.o_tape = take(sizeof(double) * (size_t)r.N * r.cap * r.rec);
+  r.bytes = o;
+  r.in_bytes = sizeof(double) * (r.nx + (size_t)r.N * r.H * r.nu);
+  r.out_bytes = sizeof(double) * ((size_t)r.N + (size_t)r.N * r.H * r.nu) + sizeof(int) * (size_t)r.N;
+}
+}  // namespace
+
+struct dmx_server {
+  dmx_server_opts opts{};
+  int device = 0;
+  srv::Arena arena;
+  srv::PinnedPool pinned;
+  std::vector<hipStream_t> streams;
+  size_t next_stream = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<SrvReq*> queue;
+  std::vector<SrvReq*> inflight;
+  std::unordered_map<uint64_t, SrvReq*> all;
+  uint64_t next_id = 1;
+  std::atomic<bool> stop{false};
+  std::thread worker;
+
+  bool launch(SrvReq* r) {
+    hipStream_t s = streams[next_stream++ % streams.size()];
+    char* b = arena.base + r->off;
+    double* x0 = (double*)(b + r->o_x0);
+    double* x0s = (double*)(b + r->o_x0s);
+    double* u = (double*)(b + r->o_u);
+    double* xout = (double*)(b + r->o_xout);
+    int* st = (int*)(b + r->o_status);
+    int* nacc = (int*)(b + r->o_nacc);
+    double* xbar = (double*)(b + r->o_xbar);
+    double* x0bar = (double*)(b + r->o_x0bar);
+    double* ubar = (double*)(b + r->o_ubar);
+    double* cost = (double*)(b + r->o_cost);
+    double* tape = (double*)(b + r->o_tape);
+    const size_t nut = (size_t)r->N * r->H * r->nu;
+    double* pin = (double*)r->pin_in;
+    std::memcpy(pin, r->x0.data(), sizeof(double) * r->nx);
+    if (nut) std::memcpy(pin + r->nx, r->u.data(), sizeof(double) * nut);
+    if (hipMemcpyAsync(x0, pin, sizeof(double) * r->nx, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    if (nut && hipMemcpyAsync(u, pin + r->nx, sizeof(double) * nut, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    hipLaunchKernelGGL(srv::broadcast_x0, dim3(((size_t)r->N * r->nx + 255) / 256), dim3(256), 0, s, x0s, x0, r->N, r->nx);
+    const KernelEntry* k = find_kernel(r->model, 0);
+    dmx_solver_opts oo;
+    dmx_default_opts(&oo);
+    dmx::FwdArgs a{};
+    a.W = r->N; a.n_int = r->H; a.nu = r->nu; a.dt = r->dt; a.x0 = x0s; a.u = nut ? u : nullptr; a.xout = xout;
+    a.status = st; a.n_acc = nacc; a.tape = tape; a.cap = r->cap; a.rec = r->rec; a.o = to_solver(oo);
+    k->fwd(r->model->dev, a, s, 0);
+    hipLaunchKernelGGL(srv::cost_kernel, dim3((r->N + 63) / 64), dim3(64), 0, s, xout, st, u, r->N, r->nx,
+                       r->model->nq, r->H, r->nu, r->dt, r->cw, r->target[0], r->target[1], r->target[2], cost, xbar);
+    if (r->want_grad) {
+      dmx::AdjArgs g{};
+      g.W = r->N; g.n_int = r->H; g.nu = r->nu; g.tape = tape; g.cap = r->cap; g.rec = r->rec; g.n_acc = nacc;
+      g.status = st; g.u = nut ? u : nullptr; g.xbar = xbar; g.x0bar = x0bar; g.ubar = nut ? ubar : nullptr;
+      g.o = to_solver(oo);
+      k->adj(r->model->dev, g, s, 0);
+      if (nut)
+        hipLaunchKernelGGL(srv::ctrl_grad_kernel, dim3((unsigned)std::min<size_t>((nut + 255) / 256, 4096)),
+                           dim3(256), 0, s, ubar, u, (long long)nut, 2.0 * r->cw * r->dt);
+    }
+    char* po = (char*)r->pin_out;
+    if (hipMemcpyAsync(po, cost, sizeof(double) * r->N, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+    if (r->want_grad && nut &&
+        hipMemcpyAsync(po + sizeof(double) * r->N, ubar, sizeof(double) * nut, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return false;
+    if (hipMemcpyAsync(po + sizeof(double) * (r->N + nut), st, sizeof(int) * r->N, hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return false;
+    if (hipEventRecord(r->ev, s) != hipSuccess) return false;
+    return hipGetLastError() == hipSuccess;
+  }
+
+  void loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop.load()) {
+      bool progress = false;
+      // admit in arrival order while the budget and the in-flight limit allow
+      while (!queue.empty() && (int)inflight.size() < opts.max_inflight) {
+        SrvReq* r = queue.front();
+        size_t off;
+        if (!arena.alloc(r->bytes, &off)) break;
+        r->pin_in = pinned.get(r->in_bytes);
+        r->pin_out = pinned.get(r->out_bytes);
+        if (!r->pin_in || !r->pin_out || hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+          arena.release(off, r->bytes);
+          break;
+        }
+        r->off = off;
+        queue.pop_front();
+        r->t_start = now_s();
+        r->state = 1;
+        if (!launch(r)) r->t_done = -1.0;
+        inflight.push_back(r);
+        progress = true;
+      }
+      for (size_t i = 0; i < inflight.size();) {
+        SrvReq* r = inflight[i];
+        if (hipEventQuery(r->ev) == hipSuccess) {
+          r->t_done = now_s();
+          r->state = 2;
+          arena.release(r->off, r->bytes);
+          (void)hipEventDestroy(r->ev);
+          r->ev = nullptr;
+          inflight[i] = inflight.back();
+          inflight.pop_back();
+          progress = true;
+        } else {
+          ++i;
+        }
+      }
+      if (progress) cv.notify_all();
+      if (!progress) cv.wait_for(lk, std::chrono::microseconds(50));
+    }
+  }
+};
+
+extern "C" {
+
+void dmx_default_server_opts(dmx_server_opts* o) {
+  o->hbm_budget_bytes = 8ll << 30;
+  o->max_inflight = 64;
+  o->n_streams = 8;
+  o->steps_per_interval = 40;
+}
+
+dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out) {
+  if (!out) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  dmx_server_opts o;
+  if (opts) o = *opts; else dmx_default_server_opts(&o);
+  if (o.hbm_budget_bytes <= 0 || o.max_inflight <= 0 || o.n_streams <= 0 || o.steps_per_interval <= 0)
+    return fail(DMX_ERR_INVALID_ARG, "bad server options");
+  dmx_server* sv = new dmx_server();
+  sv->opts = o;
+  HIP_TRY(hipGetDevice(&sv->device));
+  hipError_t e = hipMalloc((void**)&sv->arena.base, (size_t)o.hbm_budget_bytes);
+  if (e != hipSuccess) { delete sv; return fail(DMX_ERR_OUT_OF_MEMORY, "server arena: " + std::string(hipGetErrorString(e))); }
+  sv->arena.size = (size_t)o.hbm_budget_bytes;
+  sv->arena.free_[0] = sv->arena.size & ~size_t(255);
+  for (int i = 0; i < o.n_streams; ++i) {
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+    if (e != hipSuccess) { dmx_server_destroy(sv); return fail(DMX_ERR_HIP, "stream creation failed"); }
+    sv->streams.push_back(s);
+  }
+  sv->worker = std::thread([sv]() { sv->loop(); });
+  *out = sv;
+  return DMX_OK;
+}
+
+dmx_status dmx_submit(dmx_server* sv, const dmx_request* q, uint64_t* ticket) {
+  if (!sv || !q || !ticket || !q->model || !q->x0) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (q->n_worlds <= 0 || q->n_intervals <= 0 || !(q->interval_dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad sizes");
+  const dmx_model* m = q->model;
+  if (m->nu > 0 && !q->u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  if (!find_kernel(m, 0)) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  SrvReq* r = new SrvReq();
+  r->model = m; r->N = q->n_worlds; r->H = q->n_intervals; r->nu = m->nu; r->nx = m->nq + m->nv;
+  r->rec = 3 + r->nx + 6 * m->nv;
+  r->cap = (long long)sv->opts.steps_per_interval * r->H + 64;
+  r->dt = q->interval_dt; r->cw = q->ctrl_weight; r->want_grad = q->want_grad;
+  for (int i = 0; i < 3; ++i) r->target[i] = q->target[i];
+  r->x0.assign(q->x0, q->x0 + r->nx);
+  if (m->nu > 0) r->u.assign(q->u, q->u + (size_t)r->N * r->H * r->nu);
+  layout(*r);
+  if (r->bytes > sv->arena.size) { delete r; return fail(DMX_ERR_BUDGET, "request larger than the device budget"); }
+  r->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    r->id = sv->next_id++;
+    sv->all[r->id] = r;
+    sv->queue.push_back(r);
+  }
+  sv->cv.notify_all();
+  *ticket = r->id;
+  return DMX_OK;
+}
+
+dmx_status dmx_poll(dmx_server* sv, uint64_t ticket, dmx_result* out) {
+  if (!sv || !out) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  SrvReq* r;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    auto it = sv->all.find(ticket);
+    if (it == sv->all.end()) return fail(DMX_ERR_NOT_FOUND, "unknown ticket");
+    r = it->second;
+    if (r->state != 2) return DMX_PENDING;
+    sv->all.erase(it);
+  }
+  const size_t nut = (size_t)r->N * r->H * r->nu;
+  const char* po = (const char*)r->pin_out;
+  if (out->cost) std::memcpy(out->cost, po, sizeof(double) * r->N);
+  if (out->grad_u && r->want_grad && nut) std::memcpy(out->grad_u, po + sizeof(double) * r->N, sizeof(double) * nut);
+  if (out->world_status) std::memcpy(out->world_status, po + sizeof(double) * (r->N + nut), sizeof(int) * r->N);
+  out->t_submit = r->t_submit; out->t_start = r->t_start; out->t_done = r->t_done;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->pinned.put(r->pin_in, r->in_bytes);
+    sv->pinned.put(r->pin_out, r->out_bytes);
+  }
+  const bool ok = r->t_done >= 0.0;
+  delete r;
+  return ok ? DMX_OK : fail(DMX_ERR_HIP, "request launch failed");
+}
+
+dmx_status dmx_server_stats(const dmx_server* sv, int32_t* queued, int32_t* inflight, int64_t* bytes) {
+  if (!sv) return fail(DMX_ERR_INVALID_ARG, "null server");
+  std::lock_guard<std::mutex> g(const_cast<dmx_server*>(sv)->mu);
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (inflight) *inflight = (int32_t)sv->inflight.size();
+  if (bytes) *bytes = (int64_t)sv->arena.used;
+  return DMX_OK;
+}
+
+void dmx_server_destroy(dmx_server* sv) {
+  if (!sv) return;
+  sv->stop.store(true);
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (hipStream_t s : sv->streams) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+  for (auto& kv : sv->all) { if (kv.second->ev) (void)hipEventDestroy(kv.second->ev); delete kv.second; }
+  if (sv->arena.base) (void)hipFree(sv->arena.base);
+  delete sv;
 }
 
 }  // extern "C"

@@ -262,3 +262,90 @@ class Rollout(torch.autograd.Function):
     def backward(ctx, xb, _sb):
         x0b, ub = rollout_vjp(ctx.tape, xb)
         return x0b, (ub if ctx.has_u else None), None, None, None, None
+
+
+# ------------------------------------------------------------------ serving
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
+                ("steps_per_interval", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("model", _P), ("n_worlds", C.c_int32), ("n_intervals", C.c_int32), ("interval_dt", C.c_double),
+                ("x0", _P), ("u", _P), ("target", C.c_double * 3), ("ctrl_weight", C.c_double),
+                ("want_grad", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("cost", _P), ("grad_u", _P), ("world_status", _P), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+_lib.dmx_default_server_opts.argtypes = [C.POINTER(ServerOpts)]
+_lib.dmx_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(_P)]
+_lib.dmx_submit.argtypes = [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]
+_lib.dmx_poll.argtypes = [_P, C.c_uint64, C.POINTER(Result)]
+_lib.dmx_server_stats.argtypes = [_P, _P, _P, _P]
+_lib.dmx_server_destroy.argtypes = [_P]
+for _f in ("dmx_server_create", "dmx_submit", "dmx_poll", "dmx_server_stats"):
+    getattr(_lib, _f).restype = C.c_int32
+EXPORTS += ["dmx_default_server_opts", "dmx_server_create", "dmx_submit", "dmx_poll", "dmx_server_stats",
+            "dmx_server_destroy"]
+DMX_PENDING = 1
+
+
+class Server:
+    """Request loop on the current device (wraps dmx_server_*)."""
+
+    def __init__(self, **kw):
+        o = ServerOpts()
+        _lib.dmx_default_server_opts(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        h = _P()
+        _check(_lib.dmx_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self._pending = {}
+
+    def submit(self, model, x0, u, dt, target=(0.0, 0.0, 0.0), ctrl_weight=1e-3, want_grad=True):
+        x0 = _f64(x0)
+        u = np.ascontiguousarray(u, dtype=np.float64) if model.nu else np.zeros((1, 1, 0))
+        N, H = u.shape[0], u.shape[1]
+        q = Request()
+        q.model, q.n_worlds, q.n_intervals, q.interval_dt = model.h, N, H, float(dt)
+        q.x0, q.u = x0.ctypes.data, (u.ctypes.data if u.size else None)
+        for i in range(3):
+            q.target[i] = float(target[i])
+        q.ctrl_weight, q.want_grad = float(ctrl_weight), int(want_grad)
+        t = C.c_uint64()
+        _check(_lib.dmx_submit(self.h, C.byref(q), C.byref(t)))
+        self._pending[t.value] = (N, H, model.nu)
+        return t.value
+
+    def poll(self, ticket):
+        N, H, nu = self._pending.get(ticket, (1, 1, 0))
+        cost, grad, st = np.zeros(N), np.zeros((N, H, nu)), np.zeros(N, np.int32)
+        r = Result()
+        r.cost, r.grad_u, r.world_status = cost.ctypes.data, (grad.ctypes.data if grad.size else None), st.ctypes.data
+        code = _check(_lib.dmx_poll(self.h, C.c_uint64(ticket), C.byref(r)))
+        if code == DMX_PENDING:
+            return None
+        del self._pending[ticket]
+        return {"cost": cost, "grad_u": grad, "status": st, "t_submit": r.t_submit, "t_start": r.t_start,
+                "t_done": r.t_done}
+
+    def stats(self):
+        q, i, b = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(_lib.dmx_server_stats(self.h, C.byref(q), C.byref(i), C.byref(b)))
+        return q.value, i.value, b.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.dmx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

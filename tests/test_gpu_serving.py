@@ -1,0 +1,129 @@
+"""The serving loop (dmx_server_*) on the GPU: results identical alone and in
+a concurrent mix, admission under a device-memory budget, error paths, and
+served costs/gradients against the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2506_14186_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_14186_amd import dmx
+    return dmx
+
+
+def _requests(rng, n):
+    cube = W.model_cube_corners(ctrl=True)
+    out = []
+    for i in range(n):
+        N = int(rng.integers(16, 65))
+        H = int(rng.integers(5, 21))
+        x0 = np.zeros(13)
+        x0[2], x0[3] = 0.111, 1.0
+        u = rng.uniform(-1.0, 1.0, size=(N, H, 6))
+        target = [float(rng.normal(0, 0.1)), float(rng.normal(0, 0.1)), 0.11]
+        out.append((cube, x0, u, target))
+    return out
+
+
+def _wait(srv, tickets, timeout=120.0):
+    res, t0 = {}, time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+        assert time.time() - t0 < timeout, "serving timed out"
+        time.sleep(0.001)
+    return [res[t] for t in tickets]
+
+
+def test_results_identical_alone_and_in_mix(D):
+    rng = np.random.default_rng(5)
+    reqs = _requests(rng, 24)
+    models = {}
+    srv = D.Server(hbm_budget_bytes=4 << 30, max_inflight=16, n_streams=8)
+    try:
+        m = D.Model(reqs[0][0])
+        mix = _wait(srv, [srv.submit(m, x0, u, 0.01, target) for (_, x0, u, target) in reqs])
+        for i in (0, 7, 23):
+            _, x0, u, target = reqs[i]
+            alone = _wait(srv, [srv.submit(m, x0, u, 0.01, target)])[0]
+            np.testing.assert_array_equal(alone["cost"], mix[i]["cost"])
+            np.testing.assert_array_equal(alone["grad_u"], mix[i]["grad_u"])
+        for r in mix:
+            assert (r["status"] == 0).all() and np.isfinite(r["cost"]).all() and np.isfinite(r["grad_u"]).all()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in mix])
+        print(f"24 mixed requests: latency p50 {np.percentile(lat, 50) * 1e3:.1f} ms p99 "
+              f"{np.percentile(lat, 99) * 1e3:.1f} ms")
+    finally:
+        srv.close()
+
+
+def test_served_matches_rollout_and_oracle(D, oracle):
+    import torch
+    rng = np.random.default_rng(9)
+    desc, x0, u, target = _requests(rng, 1)[0]
+    u = u[:8, :6]
+    m = D.Model(desc)
+    srv = D.Server(hbm_budget_bytes=1 << 30)
+    try:
+        r = _wait(srv, [srv.submit(m, x0, u, 0.01, target, ctrl_weight=1e-3)])[0]
+    finally:
+        srv.close()
+    N, H = u.shape[:2]
+    X0 = np.tile(x0, (N, 1))
+    res = D.rollout(m, torch.tensor(X0, device="cuda"), torch.tensor(u, device="cuda"), H, 0.01, tape=True)
+    xT = res["x"].cpu().numpy()
+    cost = ((xT[:, :3] - np.array(target)) ** 2).sum(1) + 1e-3 * 0.01 * (u ** 2).sum((1, 2))
+    np.testing.assert_allclose(r["cost"], cost, rtol=1e-13)
+    xbar = np.zeros_like(xT)
+    xbar[:, :3] = 2 * (xT[:, :3] - np.array(target))
+    _, ub = D.rollout_vjp(res["tape"], torch.tensor(xbar, device="cuda"))
+    g = ub.cpu().numpy() + 2e-3 * 0.01 * u
+    np.testing.assert_allclose(r["grad_u"], g, rtol=1e-12, atol=1e-15)
+    om = oracle.Model(desc)
+    ref = om.grad_batch(X0, u, H, 0.01, xbar, n_threads=8)
+    err = np.linalg.norm((r["grad_u"] - 2e-3 * 0.01 * u - ref["ubar"]).reshape(N, -1), axis=1) / \
+        np.linalg.norm(ref["ubar"].reshape(N, -1), axis=1)
+    print(f"served control gradients vs oracle: max rel err {err.max():.2e}")
+    assert err.max() <= 1e-5
+
+
+def test_budget_admission_and_errors(D):
+    rng = np.random.default_rng(11)
+    reqs = _requests(rng, 12)
+    m = D.Model(reqs[0][0])
+    budget = 96 << 20  # a few requests at a time
+    srv = D.Server(hbm_budget_bytes=budget, max_inflight=64, n_streams=4)
+    try:
+        tickets = [srv.submit(m, x0, u, 0.01, target) for (_, x0, u, target) in reqs]
+        peak = 0
+        res = {}
+        t0 = time.time()
+        while len(res) < len(tickets):
+            q, i, b = srv.stats()
+            peak = max(peak, b)
+            assert b <= budget
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t)
+                    if r is not None:
+                        res[t] = r
+            assert time.time() - t0 < 120
+        assert peak > 0
+        with pytest.raises(D.DmxError):
+            srv.submit(m, reqs[0][1], rng.uniform(-1, 1, size=(4096, 400, 6)), 0.01)  # larger than the budget
+        with pytest.raises(D.DmxError):
+            srv.poll(10 ** 9)
+    finally:
+        srv.close()
