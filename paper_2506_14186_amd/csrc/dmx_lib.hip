@@ -9,6 +9,7 @@
 
 #include "../../include/dmx.h"
 #include "dmx_free.hpp"
+#include "dmx_tree.hpp"
 #include "dmx_rk.hpp"
 #include "dmx_server.hpp"
 
@@ -153,19 +154,25 @@ void launch_acc(const void* model, int n, const double* x, const double* tau, in
 }
 
 struct KernelEntry {
-  int kind, nc, team;
+  int kind, nc, team, nv, nb;
   FwdFn fwd;
   AdjFn adj;
   AccFn acc;
 };
 
 #define FREE_ENTRY(NC, L) \
-  {0, NC, L, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, &launch_acc<dmx::FreePhys<NC, L>>}
+  {0, NC, L, 6, 1, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, \
+   &launch_acc<dmx::FreePhys<NC, L>>}
+#define TREE_ENTRY(NV, NB, NC, L) \
+  {1, NC, L, NV, NB, &launch_fwd<dmx::TreePhys<NV, NB, NC, L>>, &launch_adj<dmx::TreePhys<NV, NB, NC, L>>, \
+   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>}
 
 const KernelEntry kKernels[] = {
     FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
     FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(16, 8),
     FREE_ENTRY(16, 16),
+    // planar legged chain (7 joints, 5 bodies, 4 foot contact slots); 3-link test pendulum
+    TREE_ENTRY(7, 5, 4, 4), TREE_ENTRY(7, 5, 4, 8), TREE_ENTRY(4, 3, 1, 4),
 };
 
 int bucket(int n) {
@@ -178,9 +185,10 @@ int bucket(int n) {
 
 // ---------------------------------------------------------------- objects
 struct dmx_model {
-  int kind = 0;  // 0: single free body with plane contacts
-  int nq = 0, nv = 0, nu = 0, nc = 0, ncb = 0;
+  int kind = 0;  // 0: single free body, 1: hinge/slide tree; plane contacts
+  int nq = 0, nv = 0, nu = 0, nc = 0, ncb = 0, nb = 1;
   dmx::FreeModel host{};
+  dmx::TreeModel tree{};
   void* dev = nullptr;
 };
 
@@ -210,11 +218,16 @@ void dmx_default_opts(dmx_solver_opts* o) {
   o->newton_maxit = 100; o->cfd = 0; o->softplus_beta = 1e4; o->tape_steps = 0; o->lanes_per_world = 0;
 }
 
+static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out);
+
 dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
   if (!d || !out) return fail(DMX_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
+  bool any_free = false;
+  for (int j = 0; j < d->njnt; ++j) any_free = any_free || d->jnt_type[j] == DMX_JOINT_FREE;
+  if (!any_free) return create_tree_model(d, out);
   if (d->nbody != 1 || d->njnt != 1 || d->jnt_type[0] != DMX_JOINT_FREE || d->body_parent[0] != -1)
-    return fail(DMX_ERR_UNSUPPORTED, "only single free-body models are compiled in this build");
+    return fail(DMX_ERR_UNSUPPORTED, "free joints are supported as the single joint of a single body");
   if (d->npair > dmx::kMaxPairs) return fail(DMX_ERR_UNSUPPORTED, "too many pairs");
   if (d->nu > 6) return fail(DMX_ERR_INVALID_ARG, "at most 6 controls on a free body");
   dmx_model* m = new dmx_model();
@@ -312,6 +325,229 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
   return DMX_OK;
 }
 
+// host-side forward kinematics of a tree at q (body origins, rotations, joint axes/anchors)
+static void host_tree_fk(const dmx::TreeModel& t, const double* q, double (*P)[3], double (*R)[9], double (*A)[3],
+                         double (*O)[3]) {
+  auto mm = [](const double* a, const double* b, double* r) {
+    double tmp[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) tmp[i * 3 + j] = a[i * 3] * b[j] + a[i * 3 + 1] * b[3 + j] + a[i * 3 + 2] * b[6 + j];
+    std::memcpy(r, tmp, sizeof(tmp));
+  };
+  auto mv = [](const double* a, const double* v, double* r) {
+    double tmp[3];
+    for (int i = 0; i < 3; ++i) tmp[i] = a[i * 3] * v[0] + a[i * 3 + 1] * v[1] + a[i * 3 + 2] * v[2];
+    std::memcpy(r, tmp, sizeof(tmp));
+  };
+  for (int b = 0; b < t.nb; ++b) {
+    double pp[3] = {0, 0, 0}, Rp[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (t.bparent[b] >= 0) { std::memcpy(pp, P[t.bparent[b]], sizeof(pp)); std::memcpy(Rp, R[t.bparent[b]], sizeof(Rp)); }
+    double p[3], Rb[9], off[3];
+    mv(Rp, t.bpos[b], off);
+    for (int i = 0; i < 3; ++i) p[i] = pp[i] + off[i];
+    mm(Rp, t.bR[b], Rb);
+    for (int j = t.bj0[b]; j < t.bj0[b] + t.bjn[b]; ++j) {
+      double a[3], o[3];
+      mv(Rb, t.jaxis[j], a);
+      mv(Rb, t.jpos[j], o);
+      for (int i = 0; i < 3; ++i) o[i] += p[i];
+      std::memcpy(A[j], a, sizeof(a));
+      std::memcpy(O[j], o, sizeof(o));
+      if (t.jtype[j] == DMX_JOINT_HINGE) {
+        const double* k = t.jaxis[j];
+        const double c = std::cos(q[j]), s = std::sin(q[j]), u = 1.0 - c;
+        const double Rot[9] = {u * k[0] * k[0] + c, u * k[0] * k[1] - s * k[2], u * k[0] * k[2] + s * k[1],
+                               u * k[0] * k[1] + s * k[2], u * k[1] * k[1] + c, u * k[1] * k[2] - s * k[0],
+                               u * k[0] * k[2] - s * k[1], u * k[1] * k[2] + s * k[0], u * k[2] * k[2] + c};
+        mm(Rb, Rot, Rb);
+        double rp[3];
+        mv(Rb, t.jpos[j], rp);
+        for (int i = 0; i < 3; ++i) p[i] = o[i] - rp[i];
+      } else {
+        for (int i = 0; i < 3; ++i) p[i] += a[i] * q[j];
+      }
+    }
+    std::memcpy(P[b], p, sizeof(p));
+    std::memcpy(R[b], Rb, sizeof(Rb));
+  }
+}
+
+static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out) {
+  if (d->nbody < 1 || d->nbody > dmx::kTreeBodies || d->njnt < 1 || d->njnt > dmx::kTreeJoints)
+    return fail(DMX_ERR_UNSUPPORTED, "tree models take 1..8 bodies and 1..8 hinge/slide joints");
+  if (d->npair > dmx::kMaxPairs || d->nu > 8) return fail(DMX_ERR_UNSUPPORTED, "too many pairs or controls");
+  dmx_model* m = new dmx_model();
+  m->kind = 1;
+  dmx::TreeModel& t = m->tree;
+  t.nb = d->nbody; t.nj = d->njnt; t.nu = d->nu;
+  m->nb = t.nb; m->nq = m->nv = t.nj; m->nu = d->nu;
+  for (int b = 0; b < t.nb; ++b) {
+    t.bparent[b] = d->body_parent[b];
+    if (t.bparent[b] >= b) { delete m; return fail(DMX_ERR_INVALID_ARG, "bodies must follow their parents"); }
+    for (int i = 0; i < 3; ++i) t.bpos[b][i] = d->body_pos[3 * b + i];
+    quat_to_mat(&d->body_quat[4 * b], t.bR[b]);
+    double mass, Ip[3], Ri[9];
+    if (!solid_inertia(d->body_iner_type[b], &d->body_iner_size[3 * b], d->body_mass[b], &mass, Ip)) {
+      delete m;
+      return fail(DMX_ERR_INVALID_ARG, "unknown inertial primitive");
+    }
+    quat_to_mat(&d->body_iner_quat[4 * b], Ri);
+    t.bmass[b] = mass;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Ri[i * 3 + k] * Ip[k] * Ri[j * 3 + k];
+        t.bI[b][i * 3 + j] = acc;
+      }
+    t.bj0[b] = 0; t.bjn[b] = 0;
+  }
+  for (int j = 0; j < t.nj; ++j) {
+    const int b = d->jnt_body[j];
+    if (d->jnt_type[j] != DMX_JOINT_HINGE && d->jnt_type[j] != DMX_JOINT_SLIDE) {
+      delete m;
+      return fail(DMX_ERR_UNSUPPORTED, "tree joints must be hinge or slide");
+    }
+    if (b < 0 || b >= t.nb || (j > 0 && b < d->jnt_body[j - 1])) { delete m; return fail(DMX_ERR_INVALID_ARG, "joints must be grouped by body in body order"); }
+    if (t.bjn[b] == 0) t.bj0[b] = j;
+    t.bjn[b]++;
+    t.jtype[j] = d->jnt_type[j];
+    double n = 0.0;
+    for (int i = 0; i < 3; ++i) n += d->jnt_axis[3 * j + i] * d->jnt_axis[3 * j + i];
+    n = std::sqrt(n);
+    for (int i = 0; i < 3; ++i) { t.jaxis[j][i] = d->jnt_axis[3 * j + i] / n; t.jpos[j][i] = d->jnt_pos[3 * j + i]; }
+  }
+  for (int b = 0; b < t.nb; ++b) {
+    unsigned mask = 0u;
+    for (int c = b; c >= 0; c = t.bparent[c])
+      for (int j = t.bj0[c]; j < t.bj0[c] + t.bjn[c]; ++j) mask |= 1u << j;
+    t.banc[b] = mask;
+  }
+  for (int i = 0; i < 3; ++i) t.grav[i] = d->gravity[i];
+  for (int i = 0; i < d->nu; ++i) {
+    if (d->ctrl_dof[i] < 0 || d->ctrl_dof[i] >= t.nj) { delete m; return fail(DMX_ERR_INVALID_ARG, "bad ctrl dof"); }
+    t.ctrl[i] = d->ctrl_dof[i];
+  }
+  // translational inverse weights at the reference configuration q = 0:
+  // w_b = trace(Jp_b M^-1 Jp_b^T) / 3
+  const int nv = t.nj;
+  double q0[dmx::kTreeJoints] = {0};
+  double P[dmx::kTreeBodies][3], R[dmx::kTreeBodies][9], A[dmx::kTreeJoints][3], O[dmx::kTreeJoints][3];
+  host_tree_fk(t, q0, P, R, A, O);
+  std::vector<double> M(nv * nv, 0.0), Jall(t.nb * 3 * nv, 0.0);
+  for (int b = 0; b < t.nb; ++b) {
+    double Jp[3][dmx::kTreeJoints] = {{0}}, Jr[3][dmx::kTreeJoints] = {{0}};
+    for (int dd = 0; dd < nv; ++dd) {
+      if (!((t.banc[b] >> dd) & 1u)) continue;
+      const double* a = A[dd];
+      if (t.jtype[dd] == DMX_JOINT_HINGE) {
+        const double r[3] = {P[b][0] - O[dd][0], P[b][1] - O[dd][1], P[b][2] - O[dd][2]};
+        Jp[0][dd] = a[1] * r[2] - a[2] * r[1]; Jp[1][dd] = a[2] * r[0] - a[0] * r[2]; Jp[2][dd] = a[0] * r[1] - a[1] * r[0];
+        for (int i = 0; i < 3; ++i) Jr[i][dd] = a[i];
+      } else {
+        for (int i = 0; i < 3; ++i) Jp[i][dd] = a[i];
+      }
+    }
+    double Iw[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) acc += R[b][i * 3 + k] * t.bI[b][k * 3 + l] * R[b][j * 3 + l];
+        Iw[i * 3 + j] = acc;
+      }
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j) {
+        double acc = 0.0;
+        for (int r = 0; r < 3; ++r) acc += t.bmass[b] * Jp[r][i] * Jp[r][j];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) acc += Jr[r][i] * Iw[r * 3 + c] * Jr[c][j];
+        M[i * nv + j] += acc;
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int i = 0; i < nv; ++i) Jall[(b * 3 + r) * nv + i] = Jp[r][i];
+  }
+  // Cholesky of M and the inverse weights
+  std::vector<double> Lm = M;
+  for (int j = 0; j < nv; ++j) {
+    double sj = Lm[j * nv + j];
+    for (int k = 0; k < j; ++k) sj -= Lm[j * nv + k] * Lm[j * nv + k];
+    if (!(sj > 0.0)) { delete m; return fail(DMX_ERR_INVALID_ARG, "singular joint-space inertia"); }
+    Lm[j * nv + j] = std::sqrt(sj);
+    for (int i = j + 1; i < nv; ++i) {
+      double v = Lm[i * nv + j];
+      for (int k = 0; k < j; ++k) v -= Lm[i * nv + k] * Lm[j * nv + k];
+      Lm[i * nv + j] = v / Lm[j * nv + j];
+    }
+  }
+  double invw[dmx::kTreeBodies];
+  for (int b = 0; b < t.nb; ++b) {
+    double tr = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      std::vector<double> x(Jall.begin() + (b * 3 + r) * nv, Jall.begin() + (b * 3 + r + 1) * nv);
+      for (int i = 0; i < nv; ++i) { for (int k = 0; k < i; ++k) x[i] -= Lm[i * nv + k] * x[k]; x[i] /= Lm[i * nv + i]; }
+      for (int i = nv - 1; i >= 0; --i) { for (int k = i + 1; k < nv; ++k) x[i] -= Lm[k * nv + i] * x[k]; x[i] /= Lm[i * nv + i]; }
+      for (int i = 0; i < nv; ++i) tr += Jall[(b * 3 + r) * nv + i] * x[i];
+    }
+    invw[b] = tr / 3.0;
+  }
+  int nc = 0;
+  t.np = d->npair;
+  for (int p = 0; p < d->npair; ++p) {
+    const int g1 = d->pair_g1[p], g2 = d->pair_g2[p];
+    if (g1 < 0 || g1 >= d->ngeom || g2 < 0 || g2 >= d->ngeom || d->geom_type[g1] != DMX_GEOM_PLANE ||
+        d->geom_body[g1] != -1 || d->geom_body[g2] < 0) {
+      delete m;
+      return fail(DMX_ERR_UNSUPPORTED, "pairs must be (world plane, body geom)");
+    }
+    const int t2 = d->geom_type[g2];
+    if (t2 != DMX_GEOM_SPHERE && t2 != DMX_GEOM_CAPSULE) { delete m; return fail(DMX_ERR_UNSUPPORTED, "sphere/capsule pairs only"); }
+    dmx::PairF& pr = t.pair[p];
+    pr.gtype = t2;
+    pr.ncon = (t2 == DMX_GEOM_CAPSULE) ? 2 : 1;
+    t.pbody[p] = d->geom_body[g2];
+    double Rg[9], Rp[9];
+    quat_to_mat(&d->geom_quat[4 * g2], Rg);
+    quat_to_mat(&d->geom_quat[4 * g1], Rp);
+    for (int i = 0; i < 3; ++i) {
+      pr.l[i] = d->geom_pos[3 * g2 + i];
+      pr.ax[i] = Rg[i * 3 + 2] * d->geom_size[3 * g2 + 1];
+      pr.p0[i] = d->geom_pos[3 * g1 + i];
+      pr.n[i] = Rp[i * 3 + 2];
+    }
+    make_tangents(pr.n, pr.t1, pr.t2);
+    pr.rad = d->geom_size[3 * g2];
+    pr.mu = d->pair_mu[p];
+    const double tc = d->pair_solref[2 * p], dr = d->pair_solref[2 * p + 1];
+    for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
+    const double dw = pr.si[1];
+    if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
+      delete m;
+      return fail(DMX_ERR_INVALID_ARG, "solref/solimp/cfd out of range");
+    }
+    pr.bcoef = 2.0 / (dw * tc);
+    pr.kscale = 1.0 / (dw * dw * tc * tc * dr * dr);
+    pr.ahat = (1.0 + pr.mu * pr.mu) * invw[t.pbody[p]];
+    for (int c = 0; c < pr.ncon; ++c) {
+      if (nc >= dmx::kMaxSlots) { delete m; return fail(DMX_ERR_UNSUPPORTED, "too many contact slots"); }
+      t.cpair[nc] = p;
+      t.csub[nc] = c;
+      ++nc;
+    }
+  }
+  t.nc = nc;
+  m->nc = nc;
+  m->ncb = bucket(nc > 0 ? nc : 1);
+  hipError_t e = hipMalloc(&m->dev, sizeof(dmx::TreeModel));
+  if (e == hipSuccess) e = hipMemcpy(m->dev, &t, sizeof(dmx::TreeModel), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (m->dev) (void)hipFree(m->dev);
+    delete m;
+    return fail(DMX_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return DMX_OK;
+}
+
 dmx_status dmx_model_info(const dmx_model* m, int32_t* nq, int32_t* nv, int32_t* nu, int32_t* max_contacts) {
   if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
   if (nq) *nq = m->nq;
@@ -329,9 +565,12 @@ void dmx_model_destroy(dmx_model* m) {
 
 static const KernelEntry* find_kernel(const dmx_model* m, int team) {
   int want = team;
-  if (want <= 0) want = m->ncb >= 16 ? 16 : m->ncb;
+  // default team: one contact slot per lane (up to 16); tree worlds keep their
+  // kinematic workspace in LDS and take at least 4 lanes
+  if (want <= 0) want = m->kind == 1 ? 4 : (m->ncb >= 16 ? 16 : m->ncb);
   for (const KernelEntry& k : kKernels)
-    if (k.kind == m->kind && k.nc == m->ncb && k.team == want) return &k;
+    if (k.kind == m->kind && k.nc == m->ncb && k.team == want && (m->kind == 0 || (k.nv == m->nv && k.nb == m->nb)))
+      return &k;
   return nullptr;
 }
 

@@ -248,8 +248,12 @@ def test_edge_cases(D):
     g, _ = D.rollout_vjp(r["tape"], _t(np.ones_like(x0)))
     assert torch.isnan(g).all()
     # API errors are reported, not launched
-    with pytest.raises(D.DmxError):
-        D.Model(W.model_chain())  # articulated chains are not compiled in this library build
+    with pytest.raises(D.DmxError):  # a free joint below another body is not a compiled model shape
+        desc2 = W.model_free_box()
+        desc2["bodies"].append({"parent": 0, "pos": [0, 0, 0.3], "quat": [1, 0, 0, 0],
+                                "inertial": {"type": "sphere", "size": [0.05, 0, 0], "mass": 1.0},
+                                "joints": [{"type": "hinge", "axis": [1, 0, 0], "pos": [0, 0, 0]}]})
+        D.Model(desc2)
     with pytest.raises(D.DmxError):
         D.rollout(model, _t(x0), None, 0, dt)
 
@@ -334,3 +338,82 @@ def test_full_size_cube_sampled(D, oracle):
     print(f"4096 worlds: accepted steps mean {nacc.mean():.0f} max {nacc.max()}; sampled replay state err "
           f"{ex.max():.2e} grad err {eg.max():.2e}")
     assert ex.max() <= 1e-6 and eg.max() <= 1e-5
+
+
+# ------------------------------------------------------------------ articulated chain
+def _chain(n_worlds=4, n_int=6, z=0.535, seed=3):
+    cfg = W.chain_walk(seed=seed, n_worlds=n_worlds, n_intervals=n_int)
+    x0 = cfg["x0"].copy()
+    x0[:, 1] = z
+    rng = np.random.default_rng(seed)
+    x0[:, 2:7] += rng.normal(0.0, 0.05, size=(n_worlds, 5))
+    return cfg["model"], x0, cfg["u"], n_int, cfg["interval_dt"]
+
+
+def test_chain_accel_and_single_step_parity(D, oracle):
+    desc, x0, u, n_int, dt = _chain()
+    om = oracle.Model(desc)
+    model = D.Model(desc)
+    ys, taus, hs, nxt = [], [], [], []
+    for w in range(x0.shape[0]):
+        r = om.rollout(x0[w], u[w], n_int, dt, tape_cap=100000)
+        assert r["status"] == 0
+        tp = r["tape"]
+        ys.append(tp[:, 2:]); hs.append(tp[:, 1])
+        nxt.append(np.vstack([tp[1:, 2:], r["x"][None]]))
+        k = np.minimum((tp[:, 0] / dt + 1e-9).astype(int), n_int - 1)
+        tau = np.zeros((len(tp), 7))
+        tau[:, 3:7] = u[w][k]
+        taus.append(tau)
+    ys, taus, hs, nxt = np.vstack(ys), np.vstack(taus), np.concatenate(hs), np.vstack(nxt)
+    acc, st = D.accel(model, _t(ys), _t(taus))
+    assert int(st.abs().sum()) == 0
+    ref = np.stack([om.rhs(y, t[3:7])[0][7:] for y, t in zip(ys, taus)])
+    ea = np.linalg.norm(acc.cpu().numpy() - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-3)
+    # one forced step per state, with the interval's torques
+    Wn = ys.shape[0]
+    forced = np.zeros((Wn, 1, 2))
+    forced[:, 0, 1] = hs
+    f_t, fn = _t(forced), _t(np.ones(Wn)).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn.data_ptr(), forced_cap=1)
+    res = D.rollout(model, _t(ys), _t(taus[:, None, 3:7]), 1, 10.0, opts=o)
+    assert int(res["status"].abs().sum()) == 0
+    es = rel_state(res["x"].cpu().numpy(), nxt, model.nq)
+    print(f"chain: {Wn} states, accel max rel err {ea.max():.2e}; single-step max rel err {es.max():.2e}")
+    assert ea.max() <= 1e-10 and es.max() <= 1e-10
+
+
+@pytest.mark.parametrize("case", ["chain", "pendulum"])
+def test_tree_replayed_gradient(D, oracle, case):
+    if case == "chain":
+        desc, x0, u, n_int, dt = _chain(n_worlds=3, n_int=5)
+    else:
+        desc = W.model_pendulum(3)
+        rng = np.random.default_rng(4)
+        x0 = np.zeros((3, 8))
+        x0[:, :4] = rng.uniform(-0.8, 0.8, size=(3, 4))
+        x0[:, 4:] = rng.normal(0, 1.0, size=(3, 4))
+        n_int, dt = 5, 0.02
+        u = rng.uniform(-0.2, 0.2, size=(3, n_int, 4))
+    om = oracle.Model(desc)
+    model = D.Model(desc)
+    tapes = [om.rollout(x0[w], u[w], n_int, dt, tape_cap=100000) for w in range(x0.shape[0])]
+    cap = max(r["n_acc"] for r in tapes)
+    forced = np.zeros((x0.shape[0], cap, 2))
+    fn = np.zeros(x0.shape[0])
+    for w, r in enumerate(tapes):
+        forced[w, :r["n_acc"]] = r["tape"][:, :2]
+        fn[w] = r["n_acc"]
+    f_t, fn_t = _t(forced), _t(fn).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    res = D.rollout(model, _t(x0), _t(u), n_int, dt, opts=o, tape=True)
+    assert int(res["status"].abs().sum()) == 0
+    rng = np.random.default_rng(8)
+    xbar = rng.normal(size=x0.shape)
+    g, ub = D.rollout_vjp(res["tape"], _t(xbar))
+    ref = om.grad_batch(x0, u, n_int, dt, xbar, n_threads=4)
+    ex = rel_state(res["x"].cpu().numpy(), ref["x"], model.nq)
+    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
+    eu = rel_grad(ub.cpu().numpy().reshape(x0.shape[0], -1), ref["ubar"].reshape(x0.shape[0], -1))
+    print(f"{case}: replayed {int(fn.sum())} steps; state {ex.max():.2e}, x0 grad {eg.max():.2e}, u grad {eu.max():.2e}")
+    assert ex.max() <= 1e-6 and eg.max() <= 1e-5 and eu.max() <= 1e-5
