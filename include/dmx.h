@@ -107,7 +107,8 @@ typedef struct dmx_tape dmx_tape;
  * dmx_default_opts fills: rtol 1e-6, atol 1e-8, h0 1e-3, safety 0.9,
  * facmin 0.2, facmax 10, kP 0.2, kI 0.4, err_order 5, err_floor 1e-6,
  * max_attempts 1e6, newton_maxit 100, cfd 0, softplus_beta 1e4,
- * tape_steps 0 (= chosen by the library), lanes_per_world 0 (= autotuned). */
+ * tape_steps 0 (= chosen by the library), lanes_per_world 0 (= per model),
+ * h_levels 16. */
 typedef struct {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor;
   int64_t max_attempts;
@@ -139,6 +140,9 @@ typedef struct {
   /* 0: all worlds in one launch (default); 1: one launch per world on the
    * stream, the plain baseline form of the same kernels. */
   int32_t launch_mode;
+  /* step-size grid: the controller's proposed steps are rounded down to
+   * h_levels mantissa values per octave (0: continuous); default 16. */
+  int32_t h_levels;
   /* failure capture (device, may be NULL): [n_worlds][nq + nv + nv] receives
    * the stage state and generalized force at which a world's contact solve
    * first failed (status bits NONFINITE or SOLVER_MAXIT). */

@@ -50,6 +50,7 @@ typedef struct {
   int newton_maxit;
   int cfd;              /* 1: straight-through contacts-from-distance in the derivative */
   double softplus_beta; /* sharpness of the softplus position term of the CFD force */
+  int h_levels;         /* proposed step sizes rounded down to this many mantissa levels per octave (0: off) */
 } orc_opts;
 
 enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8 };

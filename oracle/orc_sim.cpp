@@ -528,7 +528,21 @@ struct Opts {
   int newton_maxit = 100;
   bool cfd = false;
   double beta = 1e4;
+  int h_levels = 16;
 };
+
+// reading: the controller's proposed step is rounded down to a grid of
+// `levels` mantissa values per octave, h = floor(m * 2 levels) / (2 levels) * 2^e
+// with h = m * 2^e, m in [0.5, 1) (exact in binary floating point).  Step
+// sequences then do not depend on rounding-level differences of the error
+// estimate between implementations.
+static double quantize_step(double h, int levels) {
+  if (levels <= 0 || !(h > 0.0) || !std::isfinite(h)) return h;
+  int e;
+  double m = std::frexp(h, &e);
+  double k = std::floor(m * (2.0 * levels));
+  return std::ldexp(k / (2.0 * levels), e);
+}
 
 struct Stats { long long rhs = 0, newton_it = 0; int status = 0; int nrows = 0, nactive = 0; };
 
@@ -743,7 +757,7 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
                    const double* forced, int n_forced, S* xout, Log* lg, Stats* st) {
   int nq = m.nq, nv = m.nv, nx = nq + nv;
   std::vector<S> y(x0, x0 + nx), yn(nx), k1(2 * nv), k7(2 * nv);
-  double t = 0.0, hprop = std::min(o.h0, dt), eprev = 1.0;
+  double t = 0.0, hprop = quantize_step(std::min(o.h0, dt), o.h_levels), eprev = 1.0;
   long long attempts = 0;
   int fi = 0;
   std::vector<double> yv(nx);
@@ -793,12 +807,12 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
         k1 = k7;
         t = landing ? tend : t + h;
         eprev = et;
-        hprop = fac * h;
+        hprop = quantize_step(fac * h, o.h_levels);
         for (int i = 0; i < nx; ++i) yv[i] = val(y[i]);
         if (!finite_vec(yv.data(), nx)) { st->status |= ORC_NONFINITE; break; }
       } else {
         if (lg) lg->n_rej++;
-        hprop = std::min(1.0, fac) * h;
+        hprop = quantize_step(std::min(1.0, fac) * h, o.h_levels);
       }
       if (!forced && hprop < 1e-12 * std::max(1.0, std::fabs(t))) { st->status |= ORC_DT_UNDERFLOW; break; }
     }
@@ -818,7 +832,7 @@ static Opts to_opts(const orc_opts* p) {
   o.rtol = p->rtol; o.atol = p->atol; o.h0 = p->h0; o.safety = p->safety; o.facmin = p->facmin;
   o.facmax = p->facmax; o.kP = p->kP; o.kI = p->kI; o.err_order = p->err_order; o.err_floor = p->err_floor;
   o.max_attempts = p->max_attempts; o.newton_maxit = p->newton_maxit; o.cfd = p->cfd != 0;
-  o.beta = p->softplus_beta;
+  o.beta = p->softplus_beta; o.h_levels = p->h_levels;
   return o;
 }
 

@@ -216,6 +216,7 @@ void dmx_default_opts(dmx_solver_opts* o) {
   o->rtol = 1e-6; o->atol = 1e-8; o->h0 = 1e-3; o->safety = 0.9; o->facmin = 0.2; o->facmax = 10.0;
   o->kP = 0.2; o->kI = 0.4; o->err_order = 5.0; o->err_floor = 1e-6; o->max_attempts = 1000000;
   o->newton_maxit = 100; o->cfd = 0; o->softplus_beta = 1e4; o->tape_steps = 0; o->lanes_per_world = 0;
+  o->h_levels = 16;
 }
 
 static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out);
@@ -578,7 +579,7 @@ static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
   dmx::SolverOpts s;
   s.rtol = o.rtol; s.atol = o.atol; s.h0 = o.h0; s.safety = o.safety; s.facmin = o.facmin; s.facmax = o.facmax;
   s.kP = o.kP; s.kI = o.kI; s.err_order = o.err_order; s.err_floor = o.err_floor; s.beta = o.softplus_beta;
-  s.max_attempts = o.max_attempts; s.newton_maxit = o.newton_maxit; s.cfd = o.cfd;
+  s.max_attempts = o.max_attempts; s.newton_maxit = o.newton_maxit; s.cfd = o.cfd; s.h_levels = o.h_levels;
   return s;
 }
 
@@ -591,7 +592,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   if (W > 0 && m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
   dmx_solver_opts o;
   if (opts) o = *opts; else dmx_default_opts(&o);
-  if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0)
+  if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0 || o.h_levels < 0)
     return fail(DMX_ERR_INVALID_ARG, "bad solver options");
   if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
   if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");

@@ -65,8 +65,19 @@ __constant__ Tableau kTab = make_tableau();
 struct SolverOpts {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor, beta;
   long long max_attempts;
-  int newton_maxit, cfd;
+  int newton_maxit, cfd, h_levels;
 };
+
+// Proposed steps rounded down to h_levels mantissa values per octave (exact
+// binary arithmetic), so that step sequences are insensitive to rounding-level
+// differences of the error estimate.
+DMX_DEV double quantize_step(double h, int levels) {
+  if (levels <= 0 || !(h > 0.0) || !isfinite(h)) return h;
+  int e;
+  const double m = frexp(h, &e);
+  const double k = floor(m * (2.0 * levels));
+  return ldexp(k / (2.0 * levels), e);
+}
 
 constexpr int kFwdCounters = 7;  // attempts, rhs, contacts, newton its, newton contacts, edges, line search
 constexpr int kAdjCounters = 4;  // steps, vjps, vjp contacts, vjp edges
@@ -209,7 +220,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
   for (int i = 0; i < NX; ++i) y[i] = a.x0[(size_t)w * NX + i];
   double tau[NV];
   Stat st{};
-  double t = 0.0, hprop = fmin(o.h0, a.dt), eprev = 1.0;
+  double t = 0.0, hprop = quantize_step(fmin(o.h0, a.dt), o.h_levels), eprev = 1.0;
   long long attempts = 0;
   int nacc = 0, nrej = 0, fi = 0, nlog = 0;
   const int nforced = a.forced ? min(a.forced_n[w], a.forced_cap) : 0;
@@ -319,14 +330,14 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
         for (int d = 0; d < NV; ++d) A[0][d] = A[6][d];
         t = landing ? tend : t + h;
         eprev = et;
-        hprop = fac * h;
+        hprop = quantize_step(fac * h, o.h_levels);
         ++nacc;
         bool fin = true;
 #pragma unroll
         for (int i = 0; i < NX; ++i) fin = fin && isfinite(y[i]);
         if (!fin) { st.status |= 4; break; }
       } else {
-        hprop = fmin(1.0, fac) * h;
+        hprop = quantize_step(fmin(1.0, fac) * h, o.h_levels);
         ++nrej;
       }
       if (!a.forced && hprop < 1e-12 * fmax(1.0, fabs(t))) { st.status |= 2; break; }

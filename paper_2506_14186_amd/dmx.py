@@ -43,7 +43,7 @@ class SolverOpts(C.Structure):
         ("softplus_beta", C.c_double), ("tape_steps", C.c_int64), ("lanes_per_world", C.c_int32),
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
         ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32),
-        ("fail_state", _P)]
+        ("h_levels", C.c_int32), ("fail_state", _P)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
                 "ls_contacts")
@@ -91,7 +91,10 @@ def _stream():
 def default_opts(**kw):
     o = SolverOpts()
     _lib.dmx_default_opts(C.byref(o))
+    names = {f[0] for f in SolverOpts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown solver option {k!r}")
         setattr(o, k, v)
     return o
 

@@ -93,6 +93,9 @@ def test_served_matches_rollout_and_oracle(D, oracle):
     np.testing.assert_allclose(r["grad_u"], g, rtol=1e-12, atol=1e-15)
     om = oracle.Model(desc)
     ref = om.grad_batch(X0, u, H, 0.01, xbar, n_threads=8)
+    nacc = res["n_acc"].cpu().numpy()
+    print(f"accepted steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}")
+    assert (nacc == ref["n_acc"]).all()
     err = np.linalg.norm((r["grad_u"] - 2e-3 * 0.01 * u - ref["ubar"]).reshape(N, -1), axis=1) / \
         np.linalg.norm(ref["ubar"].reshape(N, -1), axis=1)
     print(f"served control gradients vs oracle: max rel err {err.max():.2e}")

@@ -64,7 +64,7 @@ def test_controller_free_fall_step_sequence(oracle):
     growth factor 0.9 * floor^(-0.12) * eprev^(0.04), first with eprev = 1."""
     m = oracle.Model(W.model_sphere())
     x0 = sphere_state(50.0)
-    r = m.rollout(x0, None, 1, 2.0, log_cap=100)
+    r = m.rollout(x0, None, 1, 2.0, log_cap=100, h_levels=0)
     log = r["log"]
     assert np.all(log[:, 3] == 1.0)  # nothing rejected
     h = log[:, 1]
@@ -75,6 +75,15 @@ def test_controller_free_fall_step_sequence(oracle):
     for k in range(2, len(h) - 1):  # the last step is clipped onto t_end
         assert h[k] / h[k - 1] == pytest.approx(min(f2, 10.0), rel=1e-12)
     assert log[-1, 0] + h[-1] == pytest.approx(2.0, rel=1e-15)
+    # with the step grid (16 mantissa levels per octave) every proposed step is
+    # the largest grid value not above the continuous proposal
+    r = m.rollout(x0, None, 1, 2.0, log_cap=100, h_levels=16)
+    hq = r["log"][:, 1]
+    grid = lambda x: 2.0 ** np.floor(np.log2(x)) * np.floor(x / 2.0 ** np.floor(np.log2(x)) * 16) / 16  # noqa: E731
+    assert hq[0] == grid(1e-3)
+    for k in range(1, len(hq) - 1):
+        f = f1 if k == 1 else min(f2, 10.0)
+        assert hq[k] == grid(f * hq[k - 1])
 
 
 def test_fifth_order_convergence(oracle):
