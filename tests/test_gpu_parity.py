@@ -170,7 +170,7 @@ def test_free_run_full_horizon(D, oracle, levels):
     desc, x0, n_int, dt = _cube_batch(32)
     om = oracle.Model(desc)
     model = D.Model(desc)
-    res = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(h_levels=levels))
+    res = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(h_levels=levels), counters=True)
     ref = om.rollout_batch(x0, None, n_int, dt, n_threads=8, h_levels=levels)
     ex = rel_state(res["x"].cpu().numpy(), ref["x"], model.nq)
     same = res["n_acc"].cpu().numpy() == ref["n_acc"]

@@ -82,7 +82,8 @@ def test_served_matches_rollout_and_oracle(D, oracle):
         srv.close()
     N, H = u.shape[:2]
     X0 = np.tile(x0, (N, 1))
-    res = D.rollout(m, torch.tensor(X0, device="cuda"), torch.tensor(u, device="cuda"), H, 0.01, tape=True)
+    res = D.rollout(m, torch.tensor(X0, device="cuda"), torch.tensor(u, device="cuda"), H, 0.01, tape=True,
+                    counters=True)
     xT = res["x"].cpu().numpy()
     cost = ((xT[:, :3] - np.array(target)) ** 2).sum(1) + 1e-3 * 0.01 * (u ** 2).sum((1, 2))
     np.testing.assert_allclose(r["cost"], cost, rtol=1e-13)
