@@ -144,6 +144,7 @@ template <int L> DMX_DEV bool team_all(bool p) {
 }
 
 // Dense symmetric positive definite Cholesky (lower, row-major N x N) and solve.
+// The diagonal holds the reciprocals 1/L_jj (the solve multiplies by them).
 template <int N>
 DMX_DEV bool chol(double* A) {
   bool ok = true;
@@ -155,7 +156,7 @@ DMX_DEV bool chol(double* A) {
     ok = ok && (s > 0.0);
     double d = sqrt(s > 0.0 ? s : 1e-300);
     double inv = 1.0 / d;
-    A[j * N + j] = d;
+    A[j * N + j] = inv;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       double t = A[i * N + j];
@@ -173,14 +174,14 @@ DMX_DEV void chol_solve(const double* Lm, double* x) {
     double s = x[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= Lm[i * N + k] * x[k];
-    x[i] = s / Lm[i * N + i];
+    x[i] = s * Lm[i * N + i];
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     double s = x[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) s -= Lm[k * N + i] * x[k];
-    x[i] = s / Lm[i * N + i];
+    x[i] = s * Lm[i * N + i];
   }
 }
 

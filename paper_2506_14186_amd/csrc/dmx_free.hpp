@@ -28,6 +28,7 @@ struct PairF {
   double p0[3], n[3], t1[3], t2[3];  // world plane point, contact normal and tangents
   double mu, bcoef, kscale, ahat;
   double si[5], cf[5];
+  double ssc[4];  // spline scales 1/mid^(p-1), 1/(1-mid)^(p-1): penetration (0, 1) and CFD (2, 3)
 };
 
 struct FreeModel {
@@ -50,18 +51,30 @@ struct Stat {
 DMX_DEV bool team_leader(int L) { return (threadIdx.x & (L - 1)) == 0; }
 
 // ------------------------------------------------------------ impedance
-// MuJoCo-style polynomial spline y(x) on [0, 1] with midpoint and power, and dy/dx.
-DMX_DEV double imp_spline(double x, double mid, double pw, double* dydx) {
+// x^e for the spline exponent e = power - 1 (small integer exponents by
+// multiplication; the exponent is a model constant, so the branch is uniform).
+DMX_DEV double spline_pow(double x, double e) {
+  if (e == 1.0) return x;
+  if (e == 2.0) return x * x;
+  if (e == 0.0) return 1.0;
+  if (e == 3.0) return x * x * x;
+  return pow(x, e);
+}
+
+// MuJoCo-style polynomial spline y(x) on [0, 1] with midpoint and power, and
+// dy/dx; s_lo = 1/mid^(pw-1) and s_hi = 1/(1-mid)^(pw-1) are precomputed.
+DMX_DEV double imp_spline(double x, double mid, double pw, double s_lo, double s_hi, double* dydx) {
   if (x >= 1.0) { *dydx = 0.0; return 1.0; }
   if (x <= 0.0) { *dydx = 0.0; return 0.0; }
   if (x <= mid) {
-    double s = 1.0 / pow(mid, pw - 1.0);
-    *dydx = pw * pow(x, pw - 1.0) * s;
-    return pow(x, pw) * s;
+    const double xp = spline_pow(x, pw - 1.0) * s_lo;
+    *dydx = pw * xp;
+    return xp * x;
   }
-  double s = 1.0 / pow(1.0 - mid, pw - 1.0);
-  *dydx = pw * pow(1.0 - x, pw - 1.0) * s;
-  return 1.0 - pow(1.0 - x, pw) * s;
+  const double z = 1.0 - x;
+  const double zp = spline_pow(z, pw - 1.0) * s_hi;
+  *dydx = pw * zp;
+  return 1.0 - zp * z;
 }
 
 // Impedance d(r) and dd/dr.  Penetration (r < 0): solimp spline of -r/width
@@ -71,12 +84,12 @@ DMX_DEV double impedance(const PairF& p, double r, double* ddr) {
   double dy;
   if (r < 0.0) {
     double x = -r / p.si[2];
-    double y = imp_spline(x, p.si[3], p.si[4], &dy);
+    double y = imp_spline(x, p.si[3], p.si[4], p.ssc[0], p.ssc[1], &dy);
     *ddr = -dy / p.si[2] * (p.si[1] - p.si[0]);
     return p.si[0] + y * (p.si[1] - p.si[0]);
   }
   double x = r / p.cf[2];
-  double y = imp_spline(x, p.cf[3], p.cf[4], &dy);
+  double y = imp_spline(x, p.cf[3], p.cf[4], p.ssc[2], p.ssc[3], &dy);
   *ddr = dy / p.cf[2] * (p.cf[0] - p.cf[1]);
   return p.cf[1] + y * (p.cf[0] - p.cf[1]);
 }

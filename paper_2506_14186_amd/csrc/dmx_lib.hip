@@ -69,6 +69,14 @@ bool solid_inertia(int type, const double* s, double mass_in, double* mass, doub
   return true;
 }
 
+// 1/mid^(p-1) and 1/(1-mid)^(p-1) of the penetration and CFD impedance splines
+void spline_scales(dmx::PairF& pr) {
+  pr.ssc[0] = 1.0 / std::pow(pr.si[3], pr.si[4] - 1.0);
+  pr.ssc[1] = 1.0 / std::pow(1.0 - pr.si[3], pr.si[4] - 1.0);
+  pr.ssc[2] = 1.0 / std::pow(pr.cf[3], pr.cf[4] - 1.0);
+  pr.ssc[3] = 1.0 / std::pow(1.0 - pr.cf[3], pr.cf[4] - 1.0);
+}
+
 void make_tangents(const double* n, double* t1, double* t2) {
   double a[3] = {0, 0, 0};
   if (std::fabs(n[0]) < 0.5) a[0] = 1.0; else a[1] = 1.0;
@@ -169,7 +177,7 @@ struct KernelEntry {
 
 const KernelEntry kKernels[] = {
     FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
-    FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(16, 8),
+    FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(8, 16), FREE_ENTRY(16, 8),
     FREE_ENTRY(16, 16),
     // planar legged chain (7 joints, 5 bodies, 4 foot contact slots); 3-link test pendulum
     TREE_ENTRY(7, 5, 4, 4), TREE_ENTRY(7, 5, 4, 8), TREE_ENTRY(4, 3, 1, 4),
@@ -297,6 +305,7 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     pr.mu = d->pair_mu[p];
     const double tc = d->pair_solref[2 * p], dr = d->pair_solref[2 * p + 1];
     for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
+    spline_scales(pr);
     const double dw = pr.si[1];
     if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
       delete m;
@@ -520,6 +529,7 @@ static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out) {
     pr.mu = d->pair_mu[p];
     const double tc = d->pair_solref[2 * p], dr = d->pair_solref[2 * p + 1];
     for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
+    spline_scales(pr);
     const double dw = pr.si[1];
     if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
       delete m;
@@ -564,15 +574,27 @@ void dmx_model_destroy(dmx_model* m) {
   delete m;
 }
 
-static const KernelEntry* find_kernel(const dmx_model* m, int team) {
-  int want = team;
-  // default team: one contact slot per lane (up to 16); tree worlds keep their
-  // kinematic workspace in LDS and take at least 4 lanes
-  if (want <= 0) want = m->kind == 1 ? 4 : (m->ncb >= 16 ? 16 : m->ncb);
+static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
   for (const KernelEntry& k : kKernels)
-    if (k.kind == m->kind && k.nc == m->ncb && k.team == want && (m->kind == 0 || (k.nv == m->nv && k.nb == m->nb)))
+    if (k.kind == m->kind && k.nc == m->ncb && k.team == team && (m->kind == 0 || (k.nv == m->nv && k.nb == m->nb)))
       return &k;
   return nullptr;
+}
+
+// Kernel for a model and team size (lanes per world).  Default team: tree
+// worlds keep their kinematic workspace in LDS and take 4 lanes; free bodies
+// take one contact slot per lane (up to 16), and a batch too small to give
+// every SIMD of the chip (1024 of them) a wavefront spreads each world over
+// more lanes, up to 16, so that fewer worlds share a wavefront's control flow.
+static const KernelEntry* find_kernel(const dmx_model* m, int team, long long W = 0) {
+  if (team > 0) return lookup_kernel(m, team);
+  if (m->kind == 1) return lookup_kernel(m, 4);
+  const int base = m->ncb >= 16 ? 16 : m->ncb;
+  int want = base;
+  while (want < 16 && W * want < 65536) want *= 2;
+  for (; want > base; want /= 2)
+    if (const KernelEntry* k = lookup_kernel(m, want)) return k;
+  return lookup_kernel(m, base);
 }
 
 static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
@@ -596,7 +618,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     return fail(DMX_ERR_INVALID_ARG, "bad solver options");
   if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
   if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
-  const KernelEntry* k = find_kernel(m, o.lanes_per_world);
+  const KernelEntry* k = find_kernel(m, o.lanes_per_world, W);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model and lanes_per_world");
   dmx_tape* reuse = tape ? *tape : nullptr;
   if (reuse) {
@@ -660,7 +682,7 @@ dmx_status dmx_accel(const dmx_model* m, int32_t n, const double* x, const doubl
   if (n < 0) return fail(DMX_ERR_INVALID_ARG, "bad count");
   if (n == 0) return DMX_OK;
   if (!x || !acc || !status) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  const KernelEntry* k = find_kernel(m, 0);
+  const KernelEntry* k = find_kernel(m, 0, n);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
   dmx_solver_opts oo;
   dmx_default_opts(&oo);
@@ -791,7 +813,7 @@ struct dmx_server {
     if (hipMemcpyAsync(x0, pin, sizeof(double) * r->nx, hipMemcpyHostToDevice, s) != hipSuccess) return false;
     if (nut && hipMemcpyAsync(u, pin + r->nx, sizeof(double) * nut, hipMemcpyHostToDevice, s) != hipSuccess) return false;
     hipLaunchKernelGGL(srv::broadcast_x0, dim3(((size_t)r->N * r->nx + 255) / 256), dim3(256), 0, s, x0s, x0, r->N, r->nx);
-    const KernelEntry* k = find_kernel(r->model, 0);
+    const KernelEntry* k = find_kernel(r->model, 0, r->N);
     dmx_solver_opts oo;
     dmx_default_opts(&oo);
     dmx::FwdArgs a{};

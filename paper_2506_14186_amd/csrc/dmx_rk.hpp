@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __re
 }
 
 template <class P>
-__global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
+__global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = gt / L;
@@ -233,14 +233,6 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
     const double tend = (double)(kk + 1) * a.dt;
     bool have_k1 = false;
     while (t < tend) {
-      if (!have_k1) {
-        double a1[NV];
-        P::acc(m, y, tau, false, o.beta, o.newton_maxit, a1, st);
-        if ((st.status & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, y, tau, tl);
-#pragma unroll
-        for (int d = 0; d < NV; ++d) A[0][d] = a1[d];
-        have_k1 = true;
-      }
       double h;
       bool landing;
       if (a.forced) {
@@ -255,18 +247,31 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
       if (attempts >= o.max_attempts) { st.status |= 1; break; }
       ++attempts;
       if (tl == 0) st.u_att++;
+      // stages: 0 (only after an accepted step's interval end or at the
+      // start, FSAL otherwise) and 1..6; one call site of the acceleration map
       double Y[NX], dq[NV];
       const int status_before = st.status;
+      bool fatal = false;
 #pragma unroll 1
-      for (int i = 1; i < 7; ++i) {
-        stage_state<P>(y, A, i, h, Y, dq);
+      for (int i = have_k1 ? 1 : 0; i < 7; ++i) {
+        if (i == 0) {
+#pragma unroll
+          for (int j = 0; j < NX; ++j) Y[j] = y[j];
+        } else {
+          stage_state<P>(y, A, i, h, Y, dq);
+        }
         double ai[NV];
         const int before = st.status;
         P::acc(m, Y, tau, false, o.beta, o.newton_maxit, ai, st);
         if ((st.status & 12) && !(before & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, Y, tau, tl);
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
+        if (i == 0) {
+          have_k1 = true;
+          if (st.status & 12) { fatal = true; break; }  // a failed solve at an accepted state ends the world
+        }
       }
+      if (fatal) break;
       // Y holds y_new (stage 7).  Error estimate in the ambient coordinates:
       // v: h sum e_i a_i; linear q: h sum e_i v_i; quaternions: difference of
       // the 5th- and 4th-order (+)-integrated values.
@@ -362,7 +367,7 @@ __global__ void __launch_bounds__(256) fwd_kernel(const typename P::Model* __res
 }
 
 template <class P>
-__global__ void __launch_bounds__(256) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
+__global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = gt / L;
