@@ -116,7 +116,7 @@ typedef struct {
   int32_t cfd;            /* 1: gradients use the contacts-from-distance field (straight-through) */
   double softplus_beta;   /* sharpness of the CFD position term, 1/m */
   int64_t tape_steps;     /* per-world tape capacity in accepted steps; 0 = library choice */
-  int32_t lanes_per_world;/* team size (1,2,4,8,16); 0 = pick per model and batch size */
+  int32_t lanes_per_world;/* team size (1,2,4,8,16); 0 = pick per model */
   /* test hooks (device pointers, may be NULL):
    * forced: [n_worlds][forced_cap][2] (t_n, h_n) accepted steps to replay with
    *         the controller off, forced_n[n_worlds] steps per world; a world's

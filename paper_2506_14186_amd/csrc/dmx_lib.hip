@@ -583,18 +583,14 @@ static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
 
 // Kernel for a model and team size (lanes per world).  Default team: tree
 // worlds keep their kinematic workspace in LDS and take 4 lanes; free bodies
-// take one contact slot per lane (up to 16), and a batch too small to give
-// every SIMD of the chip (1024 of them) a wavefront spreads each world over
-// more lanes, up to 16, so that fewer worlds share a wavefront's control flow.
-static const KernelEntry* find_kernel(const dmx_model* m, int team, long long W = 0) {
+// take one contact slot per lane (up to 16).  Wider teams for small batches
+// (more wavefronts, fewer worlds per wavefront) measured slower on the cube
+// batch: the per-wavefront instruction stream is the same and the extra
+// wavefronts contend for their compute units' shared front end.
+static const KernelEntry* find_kernel(const dmx_model* m, int team) {
   if (team > 0) return lookup_kernel(m, team);
   if (m->kind == 1) return lookup_kernel(m, 4);
-  const int base = m->ncb >= 16 ? 16 : m->ncb;
-  int want = base;
-  while (want < 16 && W * want < 65536) want *= 2;
-  for (; want > base; want /= 2)
-    if (const KernelEntry* k = lookup_kernel(m, want)) return k;
-  return lookup_kernel(m, base);
+  return lookup_kernel(m, m->ncb >= 16 ? 16 : m->ncb);
 }
 
 static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
@@ -618,7 +614,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     return fail(DMX_ERR_INVALID_ARG, "bad solver options");
   if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
   if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
-  const KernelEntry* k = find_kernel(m, o.lanes_per_world, W);
+  const KernelEntry* k = find_kernel(m, o.lanes_per_world);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model and lanes_per_world");
   dmx_tape* reuse = tape ? *tape : nullptr;
   if (reuse) {
@@ -682,7 +678,7 @@ dmx_status dmx_accel(const dmx_model* m, int32_t n, const double* x, const doubl
   if (n < 0) return fail(DMX_ERR_INVALID_ARG, "bad count");
   if (n == 0) return DMX_OK;
   if (!x || !acc || !status) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  const KernelEntry* k = find_kernel(m, 0, n);
+  const KernelEntry* k = find_kernel(m, 0);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
   dmx_solver_opts oo;
   dmx_default_opts(&oo);
@@ -813,7 +809,7 @@ struct dmx_server {
     if (hipMemcpyAsync(x0, pin, sizeof(double) * r->nx, hipMemcpyHostToDevice, s) != hipSuccess) return false;
     if (nut && hipMemcpyAsync(u, pin + r->nx, sizeof(double) * nut, hipMemcpyHostToDevice, s) != hipSuccess) return false;
     hipLaunchKernelGGL(srv::broadcast_x0, dim3(((size_t)r->N * r->nx + 255) / 256), dim3(256), 0, s, x0s, x0, r->N, r->nx);
-    const KernelEntry* k = find_kernel(r->model, 0, r->N);
+    const KernelEntry* k = find_kernel(r->model, 0);
     dmx_solver_opts oo;
     dmx_default_opts(&oo);
     dmx::FwdArgs a{};
