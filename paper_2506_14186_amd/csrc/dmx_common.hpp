@@ -185,4 +185,48 @@ DMX_DEV void chol_solve(const double* Lm, double* x) {
   }
 }
 
+// packed lower triangle index (i >= j)
+DMX_DEV constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// Cholesky of a symmetric positive definite matrix in packed lower-triangle
+// storage P[tri(i, j)]; the diagonal receives the reciprocals 1/L_jj.
+template <int N>
+DMX_DEV bool chol_packed(double* P) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double s = P[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= P[tri(j, k)] * P[tri(j, k)];
+    ok = ok && (s > 0.0);
+    const double inv = 1.0 / sqrt(s > 0.0 ? s : 1e-300);
+    P[tri(j, j)] = inv;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      double t = P[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= P[tri(i, k)] * P[tri(j, k)];
+      P[tri(i, j)] = t * inv;
+    }
+  }
+  return ok;
+}
+template <int N>
+DMX_DEV void chol_solve_packed(const double* P, double* x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= P[tri(i, k)] * x[k];
+    x[i] = s * P[tri(i, i)];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) s -= P[tri(k, i)] * x[k];
+    x[i] = s * P[tri(i, i)];
+  }
+}
+
 }  // namespace dmx

@@ -194,41 +194,34 @@ DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
   y[5] = m.I[6] * x[3] + m.I[7] * x[4] + m.I[8] * x[5];
 }
 
-// packed lower triangle index
-DMX_DEV constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
-
-// H = M + sum over this team's active edges of D J_e J_e^T, as a dense 6x6.
+// H = M + sum over this team's active edges of D J_e J_e^T, packed lower
+// triangle (21 entries).  Inactive edges enter with weight 0 (no branches).
 template <int CPL, int L>
-DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* H) {
-  double hp[21];
+DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
 #pragma unroll
   for (int i = 0; i < 21; ++i) hp[i] = 0.0;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
+    if (act[k] == 0u) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if (!((act[k] >> e) & 1u)) continue;
+      const double D = ((act[k] >> e) & 1u) ? rw.D[k] : 0.0;
       double Je[6];
       edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
-      double D = rw.D[k];
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        double di = D * Je[i];
+        const double di = D * Je[i];
 #pragma unroll
         for (int j = 0; j <= i; ++j) hp[tri(i, j)] += di * Je[j];
       }
     }
   }
   team_sum_arr<L, 21>(hp);
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) { H[i * 6 + j] = hp[tri(i, j)]; H[j * 6 + i] = hp[tri(i, j)]; }
-  H[0] += m.mass; H[7] += m.mass; H[14] += m.mass;
+  hp[tri(0, 0)] += m.mass; hp[tri(1, 1)] += m.mass; hp[tri(2, 2)] += m.mass;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) H[(3 + i) * 6 + 3 + j] += m.I[i * 3 + j];
+    for (int j = 0; j <= i; ++j) hp[tri(3 + i, 3 + j)] += m.I[i * 3 + j];
 }
 
 // Active edges at x: bit e of act[k] set iff J_e x - a_ref_e < 0.
@@ -264,8 +257,8 @@ DMX_DEV bool same_active(const uint32_t* a, const uint32_t* b) {
 // direction is found by a bracketed semismooth Newton iteration on the
 // piecewise-linear directional derivative.
 template <int CPL, int L>
-DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, double* x, int maxit,
-                         Stat& st) {
+DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, const double* xw, double* x,
+                         int maxit, Stat& st) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) x[i] = a0[i];
   uint32_t act[CPL];
@@ -274,7 +267,14 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
-  if (!team_any<L>(any)) return;
+  if (!team_any<L>(any)) return;  // no row active at a0: a0 is the minimizer
+  // warm start (a nearby solution, e.g. the previous stage's): the iteration
+  // below converges to the same unique minimizer from any start
+  if (xw) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] = xw[i];
+    free_active<CPL>(rw, x, act, s);
+  }
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
     if (team_leader(L)) st.u_nit++;
@@ -287,28 +287,28 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     double gp[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
+      if (act[k] == 0u) continue;
+      // sum_e w_e (J_n + s_e J_t) = (sum w_e) J_n + mu (w0 - w1) J_t1 + mu (w2 - w3) J_t2
+      double we[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!((act[k] >> e) & 1u)) continue;
-        double Je[6];
-        edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
-        double w = rw.D[k] * s[k][e];
+      for (int e = 0; e < 4; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
+      const double cn = (we[0] + we[1]) + (we[2] + we[3]);
+      const double c1 = rw.mu[k] * (we[0] - we[1]), c2 = rw.mu[k] * (we[2] - we[3]);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) gp[i] += w * Je[i];
-      }
+      for (int i = 0; i < 6; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
     }
     team_sum_arr<L, 6>(gp);
     double dx[6], Mdx[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) dx[i] = x[i] - a0[i];
     free_Mmul(m, dx, Mdx);
-    double H[36];
+    double H[21];
     free_hessian<CPL, L>(m, rw, act, H);
-    if (!chol<6>(H)) { st.status |= 4; return; }
+    if (!chol_packed<6>(H)) { st.status |= 4; return; }
     double dl[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) dl[i] = -(Mdx[i] + gp[i]);
-    chol_solve<6>(H, dl);
+    chol_solve_packed<6>(H, dl);
     // a step at rounding level of the iterate: x + dl is the minimizer to
     // working precision (an activity flip there is a rounding artefact)
     double dmax = 0.0, xmax = 1.0;
@@ -353,12 +353,13 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
         sa[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (s[k][e] + a * t[k][e] < 0.0) {
-            sa[k] |= 1u << e;
-            c2 += rw.D[k] * t[k][e] * t[k][e];
-            c1 += rw.D[k] * t[k][e] * s[k][e];
-          }
+        for (int e = 0; e < 4; ++e) {
+          const bool on = s[k][e] + a * t[k][e] < 0.0;
+          sa[k] |= on ? (1u << e) : 0u;
+          const double dt = on ? rw.D[k] * t[k][e] : 0.0;
+          c2 += dt * t[k][e];
+          c1 += dt * s[k][e];
+        }
       }
       c1 = team_sum<L>(c1) + xMd;
       c2 = team_sum<L>(c2) + dMd;
@@ -415,7 +416,7 @@ struct FreePhys {
   }
 
   DMX_DEV static void acc(const Model& m, const double* y, const double* tau, bool cfd, double beta, int maxit,
-                          double* a, Stat& st) {
+                          const double* xw, double* a, Stat& st) {
     V3 p; M3 R; Q4 qh; double inv;
     frame(y, &p, &R, &qh, &inv);
     const double* v = y + NQ;
@@ -426,7 +427,7 @@ struct FreePhys {
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    free_newton<CPL, L>(m, rw, a0, a, maxit, st);
+    free_newton<CPL, L>(m, rw, a0, xw, a, maxit, st);
   }
 
   // Cotangent of the acceleration map.  x* solves H x* = (tau - c) + sum_A
@@ -448,7 +449,7 @@ struct FreePhys {
     if (cfd) {
       double a0[6];
       a0_of(m, v, tau, a0);
-      free_newton<CPL, L>(m, rw, a0, xs, maxit, st);
+      free_newton<CPL, L>(m, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < 6; ++i) xs[i] = xs_in[i];
@@ -459,13 +460,13 @@ struct FreePhys {
     if (team_leader(L)) st.u_vjp++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
-    double H[36];
+    double H[21];
     free_hessian<CPL, L>(m, rw, act, H);
-    chol<6>(H);
+    chol_packed<6>(H);
     double lam[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) lam[i] = abar[i];
-    chol_solve<6>(H, lam);
+    chol_solve_packed<6>(H, lam);
     // per-lane partial cotangents: p, R, v
     double acc_[18];  // pb[3], Rb[9], vb[6]
 #pragma unroll

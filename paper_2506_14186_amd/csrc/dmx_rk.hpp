@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __re
 #pragma unroll
   for (int i = 0; i < NV; ++i) tau[i] = tau_in ? tau_in[(size_t)w * NV + i] : 0.0;
   Stat st{};
-  P::acc(*model, y, tau, cfd != 0, beta, maxit, acc, st);
+  P::acc(*model, y, tau, cfd != 0, beta, maxit, nullptr, acc, st);
   team_store<NV, L>(acc_out + (size_t)w * NV, acc, tl);
   if (tl == 0) status[w] = st.status;
 }
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
 #pragma unroll
   for (int i = 0; i < NX; ++i)
     if (!isfinite(y[i])) st.status |= 4;
-  bool replay_done = false;
+  bool replay_done = false, have_prev = false;
   for (int kk = 0; kk < a.n_int && st.status == 0 && !replay_done; ++kk) {
     load_tau<P>(m, a.u, w, kk, a.n_int, a.nu, tau);
     const double tend = (double)(kk + 1) * a.dt;
@@ -262,7 +262,11 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
         }
         double ai[NV];
         const int before = st.status;
-        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, ai, st);
+        // warm start from the previous stage (stage 0: the last accepted
+        // step's final stage, at the same state)
+        const double* xw = i > 0 ? A[i - 1] : (have_prev ? A[0] : nullptr);
+        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, xw, ai, st);
+        have_prev = true;
         if ((st.status & 12) && !(before & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, Y, tau, tl);
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[i][d] = ai[d];

@@ -347,8 +347,8 @@ DMX_DEV bool tree_same(const uint32_t* a, const uint32_t* b) {
 
 // exact Newton on the primal problem with dense M (see free_newton)
 template <int NV, int CPL, int L>
-DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const double* a0, double* x, int maxit,
-                         Stat& st) {
+DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const double* a0, const double* xw, double* x,
+                         int maxit, Stat& st) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) x[i] = a0[i];
   uint32_t act[CPL];
@@ -357,7 +357,12 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
-  if (!team_any<L>(any)) return;
+  if (!team_any<L>(any)) return;  // no row active at a0: a0 is the minimizer
+  if (xw) {  // warm start; the iteration converges to the same minimizer
+#pragma unroll
+    for (int i = 0; i < NV; ++i) x[i] = xw[i];
+    tree_active<NV, CPL>(rw, x, act, s);
+  }
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
     if (team_leader(L)) st.u_nit++;
@@ -476,7 +481,7 @@ struct TreePhys {
   }
 
   DMX_DEV static void acc(const Model& m, const double* y, const double* tau, bool cfd, double beta, int maxit,
-                          double* a, Stat& st) {
+                          const double* xw, double* a, Stat& st) {
     TreeWs<NV, NB>& w = ws();
     const double* v = y + NQ;
     tree_kin<NV, NB>(m, y, v, nullptr, nullptr, w, false);
@@ -494,7 +499,7 @@ struct TreePhys {
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    tree_newton<NV, CPL, L>(M, rw, a0, a, maxit, st);
+    tree_newton<NV, CPL, L>(M, rw, a0, xw, a, maxit, st);
   }
 
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
@@ -518,7 +523,7 @@ struct TreePhys {
 #pragma unroll
       for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
       chol_solve<NV>(Lm, a0);
-      tree_newton<NV, CPL, L>(M, rw, a0, xs, maxit, st);
+      tree_newton<NV, CPL, L>(M, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < NV; ++i) xs[i] = xs_in[i];
