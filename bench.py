@@ -58,6 +58,68 @@ def algorithmic_flops(counters, table, nc):
     return total
 
 
+def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
+    """MPC requests arriving as a Poisson stream: each picks the controlled
+    cube or the legged chain, N ~ U{16..256} candidate control sequences
+    u ~ U(-1, 1) over H ~ U{50..500} intervals of 10 ms, and asks for the
+    candidates' costs and control gradients.  Latency = completion - arrival
+    (submission happens at the arrival time)."""
+    rng = np.random.default_rng(seed)
+    models = {"cube": D.Model(W.model_cube_corners(ctrl=True)), "chain": D.Model(W.model_chain())}
+    chain_x0 = W.chain_walk(n_worlds=1, n_intervals=1)["x0"][0]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 2) + 16))
+    arrivals = arrivals[arrivals < seconds]
+    srv = D.Server(hbm_budget_bytes=200 * 10 ** 9, max_batch_worlds=16384)
+    pending, lat, done_kinds, work = {}, [], [], 0.0
+    t0 = time.perf_counter()
+    nxt = 0
+    backlog_at_end = None
+    t_last = t0
+    try:
+        while nxt < len(arrivals) or pending:
+            now = time.perf_counter() - t0
+            while nxt < len(arrivals) and arrivals[nxt] <= now:
+                kind = "cube" if rng.random() < 0.5 else "chain"
+                m = models[kind]
+                N, H = int(rng.integers(16, 257)), int(rng.integers(50, 501))
+                if kind == "cube":
+                    x0 = W.cube_toss(seed=int(rng.integers(1 << 30)), n_worlds=1, horizon=0.1)["x0"][0]
+                else:
+                    x0 = chain_x0
+                u = rng.uniform(-1.0, 1.0, size=(N, H, m.nu))
+                target = [float(rng.normal(0, 0.2)), float(rng.normal(0, 0.2)), 0.3]
+                pending[srv.submit(m, x0, u, 0.01, target, ctrl_weight=1e-3)] = (arrivals[nxt], kind, N * H * 0.01)
+                nxt += 1
+            if backlog_at_end is None and now >= seconds:
+                backlog_at_end = len(pending)
+            for t in list(pending):
+                r = srv.poll(t)
+                if r is not None:
+                    arr, kind, ws = pending.pop(t)
+                    lat.append(time.perf_counter() - t0 - arr)
+                    done_kinds.append(kind)
+                    work += ws
+                    t_last = time.perf_counter()
+            if now > seconds + drain_s:
+                break
+            time.sleep(0.0005)
+    finally:
+        srv.close()
+    if backlog_at_end is None:
+        backlog_at_end = len(pending)
+    elapsed = t_last - t0
+    lat = np.array(lat) if lat else np.array([np.nan])
+    return {"offered_rate_per_s": rate, "arrival_window_s": seconds, "requests": int(len(arrivals)),
+            "completed": int(len(done_kinds)), "unfinished": len(pending),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+            "served_req_per_s": round(len(done_kinds) / elapsed, 2) if elapsed > 0 else None,
+            "served_world_sim_s_per_s": round(work / elapsed, 1) if elapsed > 0 else None,
+            "backlog_at_window_end": int(backlog_at_end),
+            "mix": {"cube": done_kinds.count("cube"), "chain": done_kinds.count("chain")},
+            "requests_shape": "N~U{16..256} candidates, H~U{50..500} x 10 ms, cost+control gradient"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,9 +129,12 @@ def main():
     ap.add_argument("--horizon", type=float, default=0.5)
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--plain-worlds", type=int, default=64)
-    ap.add_argument("--cpu-worlds", type=int, default=256)
+    ap.add_argument("--cpu-worlds", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg, s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -192,6 +257,10 @@ def main():
                          f"(forward-mode over the 13 initial-state directions), {tc:.1f} s wall on "
                          f"{nthreads} threads"}
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_leg(D, W, args.serve_rate, args.serve_seconds)
+
     out = {
         "metric": "sim-seconds/s fwd+adjoint at rtol 1e-6 vs plain GPU form; p99 request latency",
         "value": round(value, 2),
@@ -212,6 +281,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_gpu": plain,
+        "serving": serving,
         "work": {"fwd": fc, "adj": ac, "accepted_steps_mean": float(n_acc.mean()),
                  "accepted_steps_max": int(n_acc.max()), "failed_worlds": int((status != 0).sum()),
                  "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)},

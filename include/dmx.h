@@ -147,6 +147,19 @@ typedef struct {
    * the stage state and generalized force at which a world's contact solve
    * first failed (status bits NONFINITE or SOLVER_MAXIT). */
   double* fail_state;
+  /* ragged batches and work distribution (device pointers, may be NULL; the
+   * tape keeps both pointers, so they must stay valid while it is used):
+   * world_intervals [n_worlds]: control intervals world w simulates (at most
+   * n_intervals; its controls are the first entries of u[w], its x_out is the
+   * state at world_intervals[w] * interval_dt, its u_bar beyond them is 0);
+   * world_order [n_worlds]: a permutation giving the order in which worlds
+   * are taken from the work queue (longest first balances the load). */
+  const int32_t* world_intervals;
+  const int32_t* world_order;
+  /* persistent launch with a device work queue: 0 = library choice (when the
+   * batch exceeds the teams the device holds at once, or is ragged), 1 =
+   * always, -1 = never (one world per team). */
+  int32_t work_queue;
 } dmx_solver_opts;
 
 void dmx_default_opts(dmx_solver_opts* opts);
@@ -204,18 +217,25 @@ dmx_status dmx_accel(const dmx_model* model, int32_t n, const double* x, const d
  * is each candidate's cost
  *   cost = |q_T[0:3] - target|^2 + ctrl_weight * sum_k |u_k|^2 * interval_dt
  * (q_T[0:3]: the first three position coordinates of the final state) and
- * its gradient with respect to the controls.  Requests are admitted in
- * arrival order while the device-memory budget and the in-flight limit allow,
- * and run concurrently on several streams; results are bitwise independent of
- * what else is in flight.  All request/result pointers are HOST memory; the
- * request's inputs are copied by dmx_submit. */
+ * its gradient with respect to the controls.
+ *
+ * Continuous batching: whenever one of the server's streams is free, the
+ * oldest waiting request and every other waiting request of the same model,
+ * interval_dt and want_grad (in arrival order, up to max_batch_worlds worlds
+ * and the free device budget) are merged into one batch: one persistent
+ * forward launch and one reverse launch over all their worlds, with ragged
+ * horizons and a device work queue taking the longest worlds first.  Requests
+ * arriving while batches run join the next batch.  Every world is computed
+ * independently, so results are bitwise the same alone and in any mix.  All
+ * request/result pointers are HOST memory; dmx_submit copies the inputs. */
 typedef struct dmx_server dmx_server;
 
 typedef struct {
   int64_t hbm_budget_bytes;  /* device arena the server allocates once (default 8 GiB) */
-  int32_t max_inflight;      /* requests on the device at once (default 64) */
-  int32_t n_streams;         /* HIP streams, default priority (default 8) */
+  int32_t max_inflight;      /* batches on the device at once (default 4, at most n_streams) */
+  int32_t n_streams;         /* HIP streams, default priority (default 4) */
   int32_t steps_per_interval;/* tape capacity per world = this * n_intervals + 64 (default 40) */
+  int32_t max_batch_worlds;  /* worlds merged into one batch (default 16384) */
 } dmx_server_opts;
 
 typedef struct {
@@ -244,7 +264,7 @@ dmx_status dmx_submit(dmx_server* server, const dmx_request* req, uint64_t* tick
 /* DMX_PENDING until the request is done, then DMX_OK with the result copied
  * out (the ticket is then released); DMX_ERR_NOT_FOUND for unknown tickets. */
 dmx_status dmx_poll(dmx_server* server, uint64_t ticket, dmx_result* out);
-/* Requests queued and in flight, and bytes of the budget in use. */
+/* Requests waiting and in flight, and bytes of the budget in use. */
 dmx_status dmx_server_stats(const dmx_server* server, int32_t* queued, int32_t* inflight, int64_t* bytes_in_use);
 /* Waits for in-flight work, then frees everything. */
 void dmx_server_destroy(dmx_server* server);

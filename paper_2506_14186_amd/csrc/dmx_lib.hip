@@ -1,6 +1,9 @@
 // Host side of the dmx C ABI: model compilation, kernel dispatch, tapes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <set>
+
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -96,11 +99,39 @@ using AdjFn = void (*)(const void*, const dmx::AdjArgs&, hipStream_t, int);
 // Batched form: one launch, one team of lanes per world.  Plain form
 // (plain != 0): one launch per world with the same kernel, serialized on the
 // stream (the baseline of the benchmark).
+// Teams of a kernel the device holds at once (occupancy x compute units).
+template <class K>
+long long resident_teams(K kernel, int team) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess) return 0;
+  return (long long)cus * per_cu * (64 / team);
+}
+
+// Grid of a batched launch: one team per world, or with a work queue as many
+// teams as the device holds at once (at most one per world).
+template <class P, class K>
+int grid_blocks(K kernel, int W, bool queue) {
+  long long teams = W;
+  if (queue) {
+    const long long r = resident_teams(kernel, P::TEAM);
+    if (r > 0 && r < teams) teams = r;
+  }
+  return (int)((teams * P::TEAM + 63) / 64);
+}
+
+template <class P>
+long long fwd_resident_teams() {
+  static long long r = resident_teams(dmx::fwd_kernel<P>, P::TEAM);
+  return r;
+}
+
 template <class P>
 void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int plain) {
   if (!plain) {
-    const long long threads = (long long)a.W * P::TEAM;
-    const int blocks = (int)((threads + 63) / 64);
+    const int blocks = grid_blocks<P>(dmx::fwd_kernel<P>, a.W, a.g.queue != nullptr);
+    if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
     hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
     return;
   }
@@ -127,8 +158,8 @@ void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int pla
 template <class P>
 void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
   if (!plain) {
-    const long long threads = (long long)a.W * P::TEAM;
-    const int blocks = (int)((threads + 63) / 64);
+    const int blocks = grid_blocks<P>(dmx::adj_kernel<P>, a.W, a.g.queue != nullptr);
+    if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
     hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
     return;
   }
@@ -166,14 +197,15 @@ struct KernelEntry {
   FwdFn fwd;
   AdjFn adj;
   AccFn acc;
+  long long (*resident)();
 };
 
 #define FREE_ENTRY(NC, L) \
   {0, NC, L, 6, 1, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, \
-   &launch_acc<dmx::FreePhys<NC, L>>}
+   &launch_acc<dmx::FreePhys<NC, L>>, &fwd_resident_teams<dmx::FreePhys<NC, L>>}
 #define TREE_ENTRY(NV, NB, NC, L) \
   {1, NC, L, NV, NB, &launch_fwd<dmx::TreePhys<NV, NB, NC, L>>, &launch_adj<dmx::TreePhys<NV, NB, NC, L>>, \
-   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>}
+   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>, &fwd_resident_teams<dmx::TreePhys<NV, NB, NC, L>>}
 
 const KernelEntry kKernels[] = {
     FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
@@ -213,6 +245,10 @@ struct dmx_tape {
   AdjFn adj = nullptr;
   int64_t* adj_counters = nullptr;
   int plain = 0;
+  const int32_t* world_intervals = nullptr;
+  const int32_t* world_order = nullptr;
+  int* queue = nullptr;   // [2] work counters of the forward and reverse launches
+  bool use_queue = false;
 };
 
 extern "C" {
@@ -627,14 +663,21 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   const int NX = m->nq + m->nv;
   dmx::FwdArgs a{};
   if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
+  if (o.work_queue < -1 || o.work_queue > 1) return fail(DMX_ERR_INVALID_ARG, "bad work_queue");
+  if (o.launch_mode == 1 && (o.world_intervals || o.world_order || o.work_queue == 1))
+    return fail(DMX_ERR_INVALID_ARG, "the plain launch form takes uniform batches without a work queue");
+  const bool use_queue = o.launch_mode == 0 && (o.work_queue == 1 || (o.work_queue == 0 &&
+                         (o.world_intervals != nullptr || (long long)W > k->resident())));
   a.W = W; a.n_int = n_int; a.nu = m->nu; a.dt = dt; a.x0 = x0; a.u = u; a.xout = x_out;
   a.counters = (long long*)o.fwd_counters;
   a.fail_state = o.fail_state;
   a.status = world_status; a.n_acc = n_accepted; a.n_rej = n_rejected; a.n_newton = nullptr;
   a.forced = o.forced; a.forced_n = o.forced_n; a.forced_cap = o.forced_cap;
   a.steplog = o.steplog; a.log_n = o.log_n; a.log_cap = o.log_cap;
+  a.g.n_int_w = o.world_intervals; a.g.order = o.world_order;
   a.o = to_solver(o);
   dmx_tape* tp = nullptr;
+  int* tmp_queue = nullptr;
   if (reuse) {
     tp = reuse;
     tp->n_int = n_int; tp->dt = dt; tp->u = u; tp->o = a.o; tp->adj = k->adj; tp->team = k->team;
@@ -655,6 +698,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     hipError_t e = hipMalloc(&tp->records, bytes);
     if (e == hipSuccess) e = hipMalloc(&tp->n_acc, sizeof(int) * W);
     if (e == hipSuccess) e = hipMalloc(&tp->status, sizeof(int) * W);
+    if (e == hipSuccess) e = hipMalloc(&tp->queue, 2 * sizeof(int));
     if (e != hipSuccess) {
       dmx_tape_destroy(tp);
       return fail(DMX_ERR_OUT_OF_MEMORY, std::string("tape allocation: ") + hipGetErrorString(e));
@@ -662,8 +706,16 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
     a.n_acc = tp->n_acc; a.status = tp->status;
   }
+  if (tp) {
+    tp->world_intervals = o.world_intervals; tp->world_order = o.world_order; tp->use_queue = use_queue;
+    if (use_queue) a.g.queue = tp->queue;
+  } else if (use_queue) {
+    HIP_TRY(hipMallocAsync((void**)&tmp_queue, sizeof(int), s));
+    a.g.queue = tmp_queue;
+  }
   k->fwd(m->dev, a, s, o.launch_mode);
   HIP_TRY(hipGetLastError());
+  if (tmp_queue) HIP_TRY(hipFreeAsync(tmp_queue, s));
   if (tp) {
     HIP_TRY(hipMemcpyAsync(world_status, tp->status, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
     if (n_accepted) HIP_TRY(hipMemcpyAsync(n_accepted, tp->n_acc, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
@@ -695,6 +747,8 @@ dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
   a.o = tp->o;
   a.counters = (long long*)tp->adj_counters;
+  a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
+  a.g.queue = tp->use_queue ? tp->queue + 1 : nullptr;
   tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->plain);
   HIP_TRY(hipGetLastError());
   return DMX_OK;
@@ -719,6 +773,7 @@ void dmx_tape_destroy(dmx_tape* tp) {
   if (tp->records) (void)hipFree(tp->records);
   if (tp->n_acc) (void)hipFree(tp->n_acc);
   if (tp->status) (void)hipFree(tp->status);
+  if (tp->queue) (void)hipFree(tp->queue);
   delete tp;
 }
 
@@ -731,44 +786,80 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+struct SrvBatch;
+
 struct SrvReq {
   uint64_t id = 0;
   const dmx_model* model = nullptr;
-  int N = 0, H = 0, nu = 0, nx = 0, rec = 0;
-  long long cap = 0;
+  int N = 0, H = 0, nu = 0, nx = 0;
   double dt = 0.0, cw = 0.0, target[3] = {0, 0, 0};
   int want_grad = 0;
   std::vector<double> x0, u;
-  // device block layout (offsets in bytes from the block start)
-  size_t off = 0, bytes = 0;
-  size_t o_x0, o_x0s, o_u, o_xout, o_status, o_nacc, o_xbar, o_x0bar, o_ubar, o_cost, o_tape;
-  void* pin_in = nullptr;
-  void* pin_out = nullptr;
-  size_t in_bytes = 0, out_bytes = 0;
-  hipEvent_t ev = nullptr;
-  int state = 0;  // 0 queued, 1 running, 2 done
+  size_t bytes = 0;     // device bytes this request adds to a batch
+  SrvBatch* batch = nullptr;
+  int w0 = 0;           // first world in the batch
+  long long u0 = 0;     // first control element in the batch
+  int state = 0;        // 0 queued, 1 running, 2 done
   double t_submit = 0, t_start = 0, t_done = 0;
 };
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
-void layout(SrvReq& r) {
-  size_t o = 0;
-  auto take = [&](size_t n) { size_t at = o; o += align256(n); return at; };
-  r.o_x0 = take(sizeof(double) * r.nx);
-  r.o_x0s = take(sizeof(double) * (size_t)r.N * r.nx);
-  r.o_u = take(sizeof(double) * (size_t)r.N * r.H * r.nu + 8);
-  r.o_xout = take(sizeof(double) * (size_t)r.N * r.nx);
-  r.o_status = take(sizeof(int) * (size_t)r.N);
-  r.o_nacc = take(sizeof(int) * (size_t)r.N);
-  r.o_xbar = take(sizeof(double) * (size_t)r.N * r.nx);
-  r.o_x0bar = take(sizeof(double) * (size_t)r.N * r.nx);
-  r.o_ubar = take(sizeof(double) * (size_t)r.N * r.H * r.nu + 8);
-  r.o_cost = take(sizeof(double) * (size_t)r.N);
-  r.o_tape = take(sizeof(double) * (size_t)r.N * r.cap * r.rec);
-  r.bytes = o;
-  r.in_bytes = sizeof(double) * (r.nx + (size_t)r.N * r.H * r.nu);
-  r.out_bytes = sizeof(double) * ((size_t)r.N + (size_t)r.N * r.H * r.nu) + sizeof(int) * (size_t)r.N;
+// Device and pinned layout of a batch.  The inputs (x0 per world, controls,
+// per-world tables) are one contiguous region copied host-to-device in one
+// transfer; the outputs (cost, u_bar, status) one region copied back.
+struct SrvBatch {
+  const dmx_model* model = nullptr;
+  double dt = 0.0;
+  int want_grad = 0, nx = 0, nu = 0, rec = 0, W = 0;
+  long long n_u = 0, n_rec = 0;
+  std::vector<SrvReq*> reqs;
+  size_t off = 0, bytes = 0;
+  size_t o_x0, o_u, o_nint, o_uoff, o_toff, o_cap, o_order, o_target, o_cw, in_end;
+  size_t o_cost, o_ubar, o_status, out_end;
+  size_t o_xout, o_nacc, o_xbar, o_x0bar, o_queue, o_tape;
+  void* pin_in = nullptr;
+  void* pin_out = nullptr;
+  hipEvent_t ev = nullptr;
+  int unpolled = 0;
+
+  void layout() {
+    size_t o = 0;
+    auto take = [&](size_t n) { size_t at = o; o += align256(n); return at; };
+    o_x0 = take(sizeof(double) * (size_t)W * nx);
+    o_u = take(sizeof(double) * (size_t)(n_u + 1));
+    o_nint = take(sizeof(int) * W);
+    o_uoff = take(sizeof(long long) * W);
+    o_toff = take(sizeof(long long) * W);
+    o_cap = take(sizeof(int) * W);
+    o_order = take(sizeof(int) * W);
+    o_target = take(sizeof(double) * 3 * W);
+    o_cw = take(sizeof(double) * W);
+    in_end = o;
+    o_cost = take(sizeof(double) * W);
+    o_ubar = take(sizeof(double) * (size_t)(n_u + 1));
+    o_status = take(sizeof(int) * W);
+    out_end = o;
+    o_xout = take(sizeof(double) * (size_t)W * nx);
+    o_nacc = take(sizeof(int) * W);
+    o_xbar = take(sizeof(double) * (size_t)W * nx);
+    o_x0bar = take(sizeof(double) * (size_t)W * nx);
+    o_queue = take(2 * sizeof(int));
+    o_tape = take(sizeof(double) * (size_t)n_rec * rec);
+    bytes = o;
+  }
+};
+
+long long request_records(const SrvReq& r, int steps_per_interval) {
+  return (long long)r.N * ((long long)steps_per_interval * r.H + 64);
+}
+
+// device bytes a request adds to a batch (its share of every array, with the
+// per-array alignment of the batch layout as slack)
+size_t request_bytes(const SrvReq& r, int steps_per_interval) {
+  const size_t W = r.N, nu_tot = (size_t)r.N * r.H * r.nu, rec = 3 + r.nx + 6 * r.model->nv;
+  return sizeof(double) * (W * r.nx * 4 + nu_tot * 2 + W * 5) + sizeof(long long) * 2 * W + sizeof(int) * 5 * W +
+         sizeof(double) * rec * (size_t)request_records(r, steps_per_interval) + 20 * 256;
 }
 }  // namespace
 
@@ -778,109 +869,171 @@ struct dmx_server {
   srv::Arena arena;
   srv::PinnedPool pinned;
   std::vector<hipStream_t> streams;
-  size_t next_stream = 0;
+  std::vector<SrvBatch*> stream_batch;  // batch running on each stream (or null)
   std::mutex mu;
   std::condition_variable cv;
   std::deque<SrvReq*> queue;
-  std::vector<SrvReq*> inflight;
   std::unordered_map<uint64_t, SrvReq*> all;
   uint64_t next_id = 1;
+  int running_reqs = 0;
   std::atomic<bool> stop{false};
   std::thread worker;
 
-  bool launch(SrvReq* r) {
-    hipStream_t s = streams[next_stream++ % streams.size()];
-    char* b = arena.base + r->off;
-    double* x0 = (double*)(b + r->o_x0);
-    double* x0s = (double*)(b + r->o_x0s);
-    double* u = (double*)(b + r->o_u);
-    double* xout = (double*)(b + r->o_xout);
-    int* st = (int*)(b + r->o_status);
-    int* nacc = (int*)(b + r->o_nacc);
-    double* xbar = (double*)(b + r->o_xbar);
-    double* x0bar = (double*)(b + r->o_x0bar);
-    double* ubar = (double*)(b + r->o_ubar);
-    double* cost = (double*)(b + r->o_cost);
-    double* tape = (double*)(b + r->o_tape);
-    const size_t nut = (size_t)r->N * r->H * r->nu;
-    double* pin = (double*)r->pin_in;
-    std::memcpy(pin, r->x0.data(), sizeof(double) * r->nx);
-    if (nut) std::memcpy(pin + r->nx, r->u.data(), sizeof(double) * nut);
-    if (hipMemcpyAsync(x0, pin, sizeof(double) * r->nx, hipMemcpyHostToDevice, s) != hipSuccess) return false;
-    if (nut && hipMemcpyAsync(u, pin + r->nx, sizeof(double) * nut, hipMemcpyHostToDevice, s) != hipSuccess) return false;
-    hipLaunchKernelGGL(srv::broadcast_x0, dim3(((size_t)r->N * r->nx + 255) / 256), dim3(256), 0, s, x0s, x0, r->N, r->nx);
-    const KernelEntry* k = find_kernel(r->model, 0);
+  // Oldest waiting request plus every waiting request it can batch with.
+  SrvBatch* form_batch() {
+    if (queue.empty()) return nullptr;
+    SrvReq* head = queue.front();
+    SrvBatch* b = new SrvBatch();
+    b->model = head->model; b->dt = head->dt; b->want_grad = head->want_grad;
+    b->nx = head->nx; b->nu = head->nu; b->rec = 3 + head->nx + 6 * head->model->nv;
+    size_t need = 0;
+    for (SrvReq* r : queue) {
+      if (r->model != b->model || r->dt != b->dt || r->want_grad != b->want_grad) continue;
+      if (!b->reqs.empty() && b->W + r->N > opts.max_batch_worlds) break;
+      if (need + r->bytes > arena.largest_free()) break;
+      need += r->bytes;
+      r->w0 = b->W; r->u0 = b->n_u;
+      b->W += r->N;
+      b->n_u += (long long)r->N * r->H * r->nu;
+      b->n_rec += request_records(*r, opts.steps_per_interval);
+      b->reqs.push_back(r);
+    }
+    if (b->reqs.empty()) { delete b; return nullptr; }  // the head waits for budget
+    b->layout();
+    if (!arena.alloc(b->bytes, &b->off)) { delete b; return nullptr; }
+    b->pin_in = pinned.get(b->in_end);
+    b->pin_out = pinned.get(b->out_end - b->o_cost);
+    if (!b->pin_in || !b->pin_out || hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+      arena.release(b->off, b->bytes);
+      if (b->pin_in) pinned.put(b->pin_in, b->in_end);
+      if (b->pin_out) pinned.put(b->pin_out, b->out_end - b->o_cost);
+      delete b;
+      return nullptr;
+    }
+    for (SrvReq* r : b->reqs) {
+      queue.erase(std::find(queue.begin(), queue.end(), r));
+      r->batch = b;
+      r->state = 1;
+      r->t_start = now_s();
+    }
+    b->unpolled = (int)b->reqs.size();
+    running_reqs += (int)b->reqs.size();
+    return b;
+  }
+
+  bool launch(SrvBatch* b, hipStream_t s) {
+    char* pin = (char*)b->pin_in;
+    double* x0 = (double*)(pin + b->o_x0);
+    double* u = (double*)(pin + b->o_u);
+    int* nint = (int*)(pin + b->o_nint);
+    long long* uoff = (long long*)(pin + b->o_uoff);
+    long long* toff = (long long*)(pin + b->o_toff);
+    int* cap = (int*)(pin + b->o_cap);
+    int* order = (int*)(pin + b->o_order);
+    double* target = (double*)(pin + b->o_target);
+    double* cw = (double*)(pin + b->o_cw);
+    long long rec0 = 0;
+    for (SrvReq* r : b->reqs) {
+      const long long wcap = (long long)opts.steps_per_interval * r->H + 64;
+      for (int i = 0; i < r->N; ++i) {
+        const int w = r->w0 + i;
+        std::memcpy(x0 + (size_t)w * b->nx, r->x0.data(), sizeof(double) * b->nx);
+        nint[w] = r->H;
+        uoff[w] = r->u0 + (long long)i * r->H * r->nu;
+        toff[w] = rec0;
+        cap[w] = (int)wcap;
+        rec0 += wcap;
+        for (int j = 0; j < 3; ++j) target[3 * w + j] = r->target[j];
+        cw[w] = r->cw;
+      }
+      if (!r->u.empty()) std::memcpy(u + r->u0, r->u.data(), sizeof(double) * r->u.size());
+    }
+    // longest horizons first
+    for (int w = 0; w < b->W; ++w) order[w] = w;
+    std::stable_sort(order, order + b->W, [&](int p, int q) { return nint[p] > nint[q]; });
+
+    char* d = arena.base + b->off;
+    if (hipMemcpyAsync(d, pin, b->in_end, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    auto D = [&](size_t o) { return (void*)(d + o); };
+    const KernelEntry* k = find_kernel(b->model, 0);
     dmx_solver_opts oo;
     dmx_default_opts(&oo);
+    dmx::Ragged g{};
+    g.n_int_w = (const int*)D(b->o_nint);
+    g.u_off = (const long long*)D(b->o_uoff);
+    g.tape_off = (const long long*)D(b->o_toff);
+    g.cap_w = (const int*)D(b->o_cap);
+    g.order = (const int*)D(b->o_order);
+    const bool has_u = b->nu > 0;
     dmx::FwdArgs a{};
-    a.W = r->N; a.n_int = r->H; a.nu = r->nu; a.dt = r->dt; a.x0 = x0s; a.u = nut ? u : nullptr; a.xout = xout;
-    a.status = st; a.n_acc = nacc; a.tape = tape; a.cap = r->cap; a.rec = r->rec; a.o = to_solver(oo);
-    k->fwd(r->model->dev, a, s, 0);
-    hipLaunchKernelGGL(srv::cost_kernel, dim3((r->N + 63) / 64), dim3(64), 0, s, xout, st, u, r->N, r->nx,
-                       r->model->nq, r->H, r->nu, r->dt, r->cw, r->target[0], r->target[1], r->target[2], cost, xbar);
-    if (r->want_grad) {
-      dmx::AdjArgs g{};
-      g.W = r->N; g.n_int = r->H; g.nu = r->nu; g.tape = tape; g.cap = r->cap; g.rec = r->rec; g.n_acc = nacc;
-      g.status = st; g.u = nut ? u : nullptr; g.xbar = xbar; g.x0bar = x0bar; g.ubar = nut ? ubar : nullptr;
-      g.o = to_solver(oo);
-      k->adj(r->model->dev, g, s, 0);
-      if (nut)
-        hipLaunchKernelGGL(srv::ctrl_grad_kernel, dim3((unsigned)std::min<size_t>((nut + 255) / 256, 4096)),
-                           dim3(256), 0, s, ubar, u, (long long)nut, 2.0 * r->cw * r->dt);
+    int max_h = 0;
+    for (SrvReq* r : b->reqs) max_h = std::max(max_h, r->H);
+    a.W = b->W; a.n_int = max_h; a.nu = b->nu; a.dt = b->dt; a.x0 = (const double*)D(b->o_x0);
+    a.u = has_u ? (const double*)D(b->o_u) : nullptr; a.xout = (double*)D(b->o_xout);
+    a.status = (int*)D(b->o_status); a.n_acc = (int*)D(b->o_nacc); a.tape = (double*)D(b->o_tape);
+    a.cap = 0; a.rec = b->rec; a.o = to_solver(oo);
+    a.g = g; a.g.queue = (int*)D(b->o_queue);
+    k->fwd(b->model->dev, a, s, 0);
+    hipLaunchKernelGGL(srv::cost_kernel, dim3((b->W + 63) / 64), dim3(64), 0, s, a.xout, a.status,
+                       (const double*)D(b->o_u), b->W, b->nx, b->model->nq, b->nu, g.n_int_w, g.u_off,
+                       (const double*)D(b->o_target), (const double*)D(b->o_cw), b->dt, (double*)D(b->o_cost),
+                       (double*)D(b->o_xbar));
+    if (b->want_grad) {
+      dmx::AdjArgs ga{};
+      ga.W = b->W; ga.n_int = max_h; ga.nu = b->nu; ga.tape = a.tape; ga.cap = 0; ga.rec = b->rec;
+      ga.n_acc = a.n_acc; ga.status = a.status; ga.u = a.u; ga.xbar = (const double*)D(b->o_xbar);
+      ga.x0bar = (double*)D(b->o_x0bar); ga.ubar = has_u ? (double*)D(b->o_ubar) : nullptr; ga.o = a.o;
+      ga.g = g; ga.g.queue = (int*)D(b->o_queue) + 1;
+      k->adj(b->model->dev, ga, s, 0);
+      if (has_u)
+        hipLaunchKernelGGL(srv::ctrl_grad_kernel, dim3(b->W), dim3(64), 0, s, (double*)D(b->o_ubar),
+                           (const double*)D(b->o_u), b->nu, g.n_int_w, g.u_off, (const double*)D(b->o_cw), b->dt);
     }
-    char* po = (char*)r->pin_out;
-    if (hipMemcpyAsync(po, cost, sizeof(double) * r->N, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
-    if (r->want_grad && nut &&
-        hipMemcpyAsync(po + sizeof(double) * r->N, ubar, sizeof(double) * nut, hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(b->pin_out, D(b->o_cost), b->out_end - b->o_cost, hipMemcpyDeviceToHost, s) != hipSuccess)
       return false;
-    if (hipMemcpyAsync(po + sizeof(double) * (r->N + nut), st, sizeof(int) * r->N, hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return false;
-    if (hipEventRecord(r->ev, s) != hipSuccess) return false;
+    if (hipEventRecord(b->ev, s) != hipSuccess) return false;
     return hipGetLastError() == hipSuccess;
+  }
+
+  void finish(SrvBatch* b, bool ok) {
+    const double t = now_s();
+    for (SrvReq* r : b->reqs) { r->state = 2; r->t_done = ok ? t : -1.0; }
+    running_reqs -= (int)b->reqs.size();
+    arena.release(b->off, b->bytes);
+    (void)hipEventDestroy(b->ev);
+    b->ev = nullptr;
   }
 
   void loop() {
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
+    int inflight = 0;
     while (!stop.load()) {
       bool progress = false;
-      // admit in arrival order while the budget and the in-flight limit allow
-      while (!queue.empty() && (int)inflight.size() < opts.max_inflight) {
-        SrvReq* r = queue.front();
-        size_t off;
-        if (!arena.alloc(r->bytes, &off)) break;
-        r->pin_in = pinned.get(r->in_bytes);
-        r->pin_out = pinned.get(r->out_bytes);
-        if (!r->pin_in || !r->pin_out || hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
-          arena.release(off, r->bytes);
-          break;
+      for (size_t i = 0; i < streams.size(); ++i) {
+        SrvBatch* b = stream_batch[i];
+        if (b && hipEventQuery(b->ev) == hipSuccess) {
+          finish(b, true);
+          stream_batch[i] = nullptr;
+          --inflight;
+          progress = true;
         }
-        r->off = off;
-        queue.pop_front();
-        r->t_start = now_s();
-        r->state = 1;
-        if (!launch(r)) r->t_done = -1.0;
-        inflight.push_back(r);
+      }
+      for (size_t i = 0; i < streams.size() && inflight < opts.max_inflight; ++i) {
+        if (stream_batch[i]) continue;
+        SrvBatch* b = form_batch();
+        if (!b) break;
+        if (!launch(b, streams[i])) {
+          (void)hipStreamSynchronize(streams[i]);
+          finish(b, false);
+        } else {
+          stream_batch[i] = b;
+          ++inflight;
+        }
         progress = true;
       }
-      for (size_t i = 0; i < inflight.size();) {
-        SrvReq* r = inflight[i];
-        if (hipEventQuery(r->ev) == hipSuccess) {
-          r->t_done = now_s();
-          r->state = 2;
-          arena.release(r->off, r->bytes);
-          (void)hipEventDestroy(r->ev);
-          r->ev = nullptr;
-          inflight[i] = inflight.back();
-          inflight.pop_back();
-          progress = true;
-        } else {
-          ++i;
-        }
-      }
       if (progress) cv.notify_all();
-      if (!progress) cv.wait_for(lk, std::chrono::microseconds(50));
+      else cv.wait_for(lk, std::chrono::microseconds(50));
     }
   }
 };
@@ -889,16 +1042,18 @@ extern "C" {
 
 void dmx_default_server_opts(dmx_server_opts* o) {
   o->hbm_budget_bytes = 8ll << 30;
-  o->max_inflight = 64;
-  o->n_streams = 8;
+  o->max_inflight = 4;
+  o->n_streams = 4;
   o->steps_per_interval = 40;
+  o->max_batch_worlds = 16384;
 }
 
 dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out) {
   if (!out) return fail(DMX_ERR_INVALID_ARG, "null argument");
   dmx_server_opts o;
   if (opts) o = *opts; else dmx_default_server_opts(&o);
-  if (o.hbm_budget_bytes <= 0 || o.max_inflight <= 0 || o.n_streams <= 0 || o.steps_per_interval <= 0)
+  if (o.hbm_budget_bytes <= 0 || o.max_inflight <= 0 || o.n_streams <= 0 || o.steps_per_interval <= 0 ||
+      o.max_batch_worlds <= 0)
     return fail(DMX_ERR_INVALID_ARG, "bad server options");
   dmx_server* sv = new dmx_server();
   sv->opts = o;
@@ -912,6 +1067,7 @@ dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out) {
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
     if (e != hipSuccess) { dmx_server_destroy(sv); return fail(DMX_ERR_HIP, "stream creation failed"); }
     sv->streams.push_back(s);
+    sv->stream_batch.push_back(nullptr);
   }
   sv->worker = std::thread([sv]() { sv->loop(); });
   *out = sv;
@@ -924,15 +1080,15 @@ dmx_status dmx_submit(dmx_server* sv, const dmx_request* q, uint64_t* ticket) {
   const dmx_model* m = q->model;
   if (m->nu > 0 && !q->u) return fail(DMX_ERR_INVALID_ARG, "controls required");
   if (!find_kernel(m, 0)) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  if ((long long)sv->opts.steps_per_interval * q->n_intervals + 64 > INT32_MAX)
+    return fail(DMX_ERR_INVALID_ARG, "horizon too long");
   SrvReq* r = new SrvReq();
   r->model = m; r->N = q->n_worlds; r->H = q->n_intervals; r->nu = m->nu; r->nx = m->nq + m->nv;
-  r->rec = 3 + r->nx + 6 * m->nv;
-  r->cap = (long long)sv->opts.steps_per_interval * r->H + 64;
   r->dt = q->interval_dt; r->cw = q->ctrl_weight; r->want_grad = q->want_grad;
   for (int i = 0; i < 3; ++i) r->target[i] = q->target[i];
   r->x0.assign(q->x0, q->x0 + r->nx);
   if (m->nu > 0) r->u.assign(q->u, q->u + (size_t)r->N * r->H * r->nu);
-  layout(*r);
+  r->bytes = request_bytes(*r, sv->opts.steps_per_interval);
   if (r->bytes > sv->arena.size) { delete r; return fail(DMX_ERR_BUDGET, "request larger than the device budget"); }
   r->t_submit = now_s();
   {
@@ -957,18 +1113,25 @@ dmx_status dmx_poll(dmx_server* sv, uint64_t ticket, dmx_result* out) {
     if (r->state != 2) return DMX_PENDING;
     sv->all.erase(it);
   }
+  SrvBatch* b = r->batch;
   const size_t nut = (size_t)r->N * r->H * r->nu;
-  const char* po = (const char*)r->pin_out;
-  if (out->cost) std::memcpy(out->cost, po, sizeof(double) * r->N);
-  if (out->grad_u && r->want_grad && nut) std::memcpy(out->grad_u, po + sizeof(double) * r->N, sizeof(double) * nut);
-  if (out->world_status) std::memcpy(out->world_status, po + sizeof(double) * (r->N + nut), sizeof(int) * r->N);
+  const char* po = (const char*)b->pin_out;  // region starting at the batch's cost array
+  const size_t base = b->o_cost;
+  if (out->cost) std::memcpy(out->cost, po + (b->o_cost - base) + sizeof(double) * r->w0, sizeof(double) * r->N);
+  if (out->grad_u && r->want_grad && nut)
+    std::memcpy(out->grad_u, po + (b->o_ubar - base) + sizeof(double) * r->u0, sizeof(double) * nut);
+  if (out->world_status)
+    std::memcpy(out->world_status, po + (b->o_status - base) + sizeof(int) * r->w0, sizeof(int) * r->N);
   out->t_submit = r->t_submit; out->t_start = r->t_start; out->t_done = r->t_done;
+  const bool ok = r->t_done >= 0.0;
   {
     std::lock_guard<std::mutex> g(sv->mu);
-    sv->pinned.put(r->pin_in, r->in_bytes);
-    sv->pinned.put(r->pin_out, r->out_bytes);
+    if (--b->unpolled == 0) {
+      sv->pinned.put(b->pin_in, b->in_end);
+      sv->pinned.put(b->pin_out, b->out_end - b->o_cost);
+      delete b;
+    }
   }
-  const bool ok = r->t_done >= 0.0;
   delete r;
   return ok ? DMX_OK : fail(DMX_ERR_HIP, "request launch failed");
 }
@@ -977,7 +1140,7 @@ dmx_status dmx_server_stats(const dmx_server* sv, int32_t* queued, int32_t* infl
   if (!sv) return fail(DMX_ERR_INVALID_ARG, "null server");
   std::lock_guard<std::mutex> g(const_cast<dmx_server*>(sv)->mu);
   if (queued) *queued = (int32_t)sv->queue.size();
-  if (inflight) *inflight = (int32_t)sv->inflight.size();
+  if (inflight) *inflight = (int32_t)sv->running_reqs;
   if (bytes) *bytes = (int64_t)sv->arena.used;
   return DMX_OK;
 }
@@ -988,7 +1151,17 @@ void dmx_server_destroy(dmx_server* sv) {
   sv->cv.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   for (hipStream_t s : sv->streams) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
-  for (auto& kv : sv->all) { if (kv.second->ev) (void)hipEventDestroy(kv.second->ev); delete kv.second; }
+  std::set<SrvBatch*> batches;
+  for (SrvBatch* b : sv->stream_batch)
+    if (b) batches.insert(b);
+  for (auto& kv : sv->all) {
+    if (kv.second->batch) batches.insert(kv.second->batch);
+    delete kv.second;
+  }
+  for (SrvBatch* b : batches) {
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    delete b;  // pinned buffers are freed with the pool
+  }
   if (sv->arena.base) (void)hipFree(sv->arena.base);
   delete sv;
 }

@@ -82,6 +82,48 @@ DMX_DEV double quantize_step(double h, int levels) {
 constexpr int kFwdCounters = 7;  // attempts, rhs, contacts, newton its, newton contacts, edges, line search
 constexpr int kAdjCounters = 4;  // steps, vjps, vjp contacts, vjp edges
 
+// Per-world layout of a batch and its work distribution.  Null arrays mean
+// the uniform layout: n_int intervals per world, controls u[w][n_int][nu],
+// tape records [w][cap], worlds processed once each in index order.
+struct Ragged {
+  const int* n_int_w;         // [W] intervals of world w
+  const long long* u_off;     // [W] first element of world w's controls in u (and u_bar)
+  const long long* tape_off;  // [W] first tape record of world w
+  const int* cap_w;           // [W] tape records available to world w
+  const int* order;           // [W] processing order (longest first)
+  int* queue;                 // work counter, zero at launch (null: one world per team)
+};
+
+DMX_DEV int world_intervals(const Ragged& g, int n_int, int w) { return g.n_int_w ? g.n_int_w[w] : n_int; }
+DMX_DEV size_t world_u(const Ragged& g, int n_int, int nu, int w) {
+  return g.u_off ? (size_t)g.u_off[w] : (size_t)w * n_int * nu;
+}
+DMX_DEV size_t world_tape(const Ragged& g, long long cap, int w) {
+  return g.tape_off ? (size_t)g.tape_off[w] : (size_t)w * cap;
+}
+DMX_DEV long long world_cap(const Ragged& g, long long cap, int w) { return g.cap_w ? g.cap_w[w] : cap; }
+
+// Next world of a team: without a queue the team's own index once; with a
+// queue its leader lane takes the next position from the shared counter and
+// broadcasts it.  Every team leaves once the counter has passed W.
+template <int L>
+DMX_DEV int take_world(const Ragged& g, int W, int team, bool first) {
+  int idx;
+  if (g.queue) {
+    int v = 0;
+    if ((threadIdx.x & (L - 1)) == 0) v = atomicAdd(g.queue, 1);
+    idx = __shfl(v, (int)(threadIdx.x & 63) & ~(L - 1), 64);
+  } else {
+    idx = first ? team : W;
+  }
+  if (idx >= W) return -1;
+  return g.order ? g.order[idx] : idx;
+}
+
+__global__ void reset_queue(int* q) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *q = 0;
+}
+
 struct FwdArgs {
   int W, n_int, nu;
   double dt;
@@ -103,6 +145,7 @@ struct FwdArgs {
   int* log_n;
   int log_cap;
   double* fail_state;
+  Ragged g;
   SolverOpts o;
 };
 
@@ -118,17 +161,18 @@ struct AdjArgs {
   const double* xbar;
   double* x0bar;
   double* ubar;
+  Ragged g;
   SolverOpts o;
 };
 
 // generalized force of interval k: tau[ctrl[i]] += u[w][k][i] (unrolled over
 // dofs so that tau stays in registers)
 template <class P>
-DMX_DEV void load_tau(const typename P::Model& m, const double* u, int w, int k, int n_int, int nu, double* tau) {
+DMX_DEV void load_tau(const typename P::Model& m, const double* uw, int k, int nu, double* tau) {
 #pragma unroll
   for (int d = 0; d < P::NV; ++d) tau[d] = 0.0;
   for (int i = 0; i < nu; ++i) {
-    const double ui = u[((size_t)w * n_int + k) * nu + i];
+    const double ui = uw[(size_t)k * nu + i];
     const int c = m.ctrl[i];
 #pragma unroll
     for (int d = 0; d < P::NV; ++d)
@@ -202,19 +246,16 @@ __global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __re
   if (tl == 0) status[w] = st.status;
 }
 
+// One world's forward rollout by its team; A: the team's stage accelerations
+// in LDS (every team lane writes the same replicated values).
 template <class P>
-__global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
+DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int tl, double (*A)[P::NV]) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = gt / L;
-  const int tl = gt & (L - 1);
-  if (w >= a.W) return;
-  const typename P::Model& m = *model;
   const SolverOpts& o = a.o;
-  // stage accelerations: one copy per world in LDS (every team lane writes
-  // the same replicated values), indexed by the runtime stage number
-  __shared__ double sA[64 / L][7][NV];
-  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  const int n_int = world_intervals(a.g, a.n_int, w);
+  const double* uw = a.u ? a.u + world_u(a.g, a.n_int, a.nu, w) : nullptr;
+  double* tape_w = a.tape ? a.tape + world_tape(a.g, a.cap, w) * a.rec : nullptr;
+  const long long cap = world_cap(a.g, a.cap, w);
   double y[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) y[i] = a.x0[(size_t)w * NX + i];
@@ -228,8 +269,8 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
   for (int i = 0; i < NX; ++i)
     if (!isfinite(y[i])) st.status |= 4;
   bool replay_done = false, have_prev = false;
-  for (int kk = 0; kk < a.n_int && st.status == 0 && !replay_done; ++kk) {
-    load_tau<P>(m, a.u, w, kk, a.n_int, a.nu, tau);
+  for (int kk = 0; kk < n_int && st.status == 0 && !replay_done; ++kk) {
+    load_tau<P>(m, uw, kk, a.nu, tau);
     const double tend = (double)(kk + 1) * a.dt;
     bool have_k1 = false;
     while (t < tend) {
@@ -323,9 +364,9 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
       }
       if (a.steplog) ++nlog;
       if (accept) {
-        if (a.tape) {
-          if (nacc >= a.cap) { st.status |= 32; break; }
-          double* rec = a.tape + ((size_t)w * a.cap + nacc) * a.rec;
+        if (tape_w) {
+          if (nacc >= cap) { st.status |= 32; break; }
+          double* rec = tape_w + (size_t)nacc * a.rec;
           if (tl == 0) { rec[0] = t; rec[1] = h; rec[2] = (double)kk; }
           team_store<NX, L>(rec + 3, y, tl);
           double Acp[6 * NV];
@@ -371,42 +412,54 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
 }
 
 template <class P>
-__global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
-  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
+__global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __restrict__ model, FwdArgs a) {
+  constexpr int L = P::TEAM, NV = P::NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = gt / L;
-  const int tl = gt & (L - 1);
-  if (w >= a.W) return;
-  const typename P::Model& m = *model;
+  const int team = gt / L, tl = gt & (L - 1);
+  __shared__ double sA[64 / L][7][NV];
+  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  for (bool first = true;; first = false) {
+    const int w = take_world<L>(a.g, a.W, team, first);
+    if (w < 0) break;
+    fwd_world<P>(*model, a, w, tl, A);
+  }
+}
+
+template <class P>
+DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
+                       double (*Ab)[P::NV]) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
   const SolverOpts& o = a.o;
   const int nsteps = a.n_acc[w];
-  const size_t nut = (size_t)a.n_int * a.nu;
+  // u_bar entries of this world: its own intervals in a packed layout, the
+  // whole dense row otherwise (intervals beyond the world's count get 0)
+  const size_t nut = (size_t)(a.g.u_off ? world_intervals(a.g, a.n_int, w) : a.n_int) * a.nu;
+  const size_t uoff = world_u(a.g, a.n_int, a.nu, w);
+  const double* uw = a.u ? a.u + uoff : nullptr;
+  double* ubw = a.ubar ? a.ubar + uoff : nullptr;
+  const double* tape_w = a.tape + world_tape(a.g, a.cap, w) * a.rec;
   if (a.status[w] != 0) {
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
-    for (size_t i = tl; i < nut; i += L) a.ubar[(size_t)w * nut + i] = nan;
+    for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
     return;
   }
-  for (size_t i = tl; i < nut; i += L) a.ubar[(size_t)w * nut + i] = 0.0;
+  for (size_t i = tl; i < nut; i += L) ubw[i] = 0.0;
   double yb[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) yb[i] = a.xbar[(size_t)w * NX + i];
   double tau[NV], tb_acc[NV];
   int cur_k = -1;
   Stat st{};
-  __shared__ double sA[64 / L][7][NV];
-  __shared__ double sAb[64 / L][6][NV];
-  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
-  double (*Ab)[NV] = sAb[(threadIdx.x & 63) / L];
   for (int s = nsteps - 1; s >= 0; --s) {
-    const double* rec = a.tape + ((size_t)w * a.cap + s) * a.rec;
+    const double* rec = tape_w + (size_t)s * a.rec;
     const double h = rec[1];
     const int kk = (int)rec[2];
     if (tl == 0) st.u_step++;
     if (kk != cur_k) {
-      if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
+      if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
       cur_k = kk;
-      load_tau<P>(m, a.u, w, kk, a.n_int, a.nu, tau);
+      load_tau<P>(m, uw, kk, a.nu, tau);
 #pragma unroll
       for (int i = 0; i < NV; ++i) tb_acc[i] = 0.0;
     }
@@ -467,13 +520,29 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
 #pragma unroll
     for (int d = 0; d < NV; ++d) yb[NQ + d] = vb[d];
   }
-  if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, a.ubar + (size_t)w * nut + (size_t)cur_k * a.nu, a.nu);
+  if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
     team_sum_arr<L, kAdjCounters>(c);
     if (tl == 0)
       for (int i = 0; i < kAdjCounters; ++i) a.counters[(size_t)w * kAdjCounters + i] = (long long)c[i];
+  }
+}
+
+template <class P>
+__global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
+  constexpr int L = P::TEAM, NV = P::NV;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int team = gt / L, tl = gt & (L - 1);
+  __shared__ double sA[64 / L][7][NV];
+  __shared__ double sAb[64 / L][6][NV];
+  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  double (*Ab)[NV] = sAb[(threadIdx.x & 63) / L];
+  for (bool first = true;; first = false) {
+    const int w = take_world<L>(a.g, a.W, team, first);
+    if (w < 0) break;
+    adj_world<P>(*model, a, w, tl, A, Ab);
   }
 }
 

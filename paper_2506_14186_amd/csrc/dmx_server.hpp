@@ -16,39 +16,40 @@
 namespace srv {
 
 // ---------------------------------------------------------------- kernels
-__global__ void broadcast_x0(double* x0s, const double* x0, int W, int nx) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)W * nx;
-       i += (long long)gridDim.x * blockDim.x)
-    x0s[i] = x0[i % nx];
-}
-
-// cost = |q_T[0:3] - target|^2 + cw * dt * sum |u|^2; cotangent of the final
-// state for the gradient; NaN cost for failed worlds.
-__global__ void cost_kernel(const double* xout, const int* status, const double* u, int W, int nx, int nq, int H,
-                            int nu, double dt, double cw, double t0, double t1, double t2, double* cost,
-                            double* xbar) {
+// Per-world cost of a batch: |q_T[0:3] - target_w|^2 + cw_w * dt * sum |u|^2
+// over the world's own intervals, and the final-state cotangent for the
+// gradient; NaN cost for failed worlds.
+__global__ void cost_kernel(const double* xout, const int* status, const double* u, int W, int nx, int nq, int nu,
+                            const int* n_int_w, const long long* u_off, const double* target, const double* cw,
+                            double dt, double* cost, double* xbar) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  const double tg[3] = {t0, t1, t2};
   const double* x = xout + (size_t)w * nx;
   double c = 0.0;
   for (int i = 0; i < nx; ++i) xbar[(size_t)w * nx + i] = 0.0;
   const int np = nq < 3 ? nq : 3;
   for (int i = 0; i < np; ++i) {
-    const double d = x[i] - tg[i];
+    const double d = x[i] - target[3 * w + i];
     c += d * d;
     xbar[(size_t)w * nx + i] = 2.0 * d;
   }
   double cu = 0.0;
-  const double* uw = u + (size_t)w * H * nu;
-  for (int i = 0; i < H * nu; ++i) cu += uw[i] * uw[i];
-  c += cw * dt * cu;
+  if (nu > 0) {
+    const double* uw = u + u_off[w];
+    const int n = n_int_w[w] * nu;
+    for (int i = 0; i < n; ++i) cu += uw[i] * uw[i];
+  }
+  c += cw[w] * dt * cu;
   cost[w] = status[w] ? __longlong_as_double(0x7ff8000000000000ll) : c;
 }
 
-__global__ void ctrl_grad_kernel(double* ubar, const double* u, long long n, double coef) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    ubar[i] += coef * u[i];
+// u_bar += 2 cw_w dt u over each world's own intervals (one block per world)
+__global__ void ctrl_grad_kernel(double* ubar, const double* u, int nu, const int* n_int_w, const long long* u_off,
+                                 const double* cw, double dt) {
+  const int w = blockIdx.x;
+  const long long off = u_off[w], n = (long long)n_int_w[w] * nu;
+  const double coef = 2.0 * cw[w] * dt;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) ubar[off + i] += coef * u[off + i];
 }
 
 // ---------------------------------------------------------------- arena
@@ -70,6 +71,11 @@ struct Arena {
       }
     }
     return false;
+  }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = kv.second > m ? kv.second : m;
+    return m;
   }
   void release(size_t off, size_t n) {
     n = (n + 255) & ~size_t(255);

@@ -43,7 +43,8 @@ class SolverOpts(C.Structure):
         ("softplus_beta", C.c_double), ("tape_steps", C.c_int64), ("lanes_per_world", C.c_int32),
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
         ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32),
-        ("h_levels", C.c_int32), ("fail_state", _P)]
+        ("h_levels", C.c_int32), ("fail_state", _P), ("world_intervals", _P), ("world_order", _P),
+        ("work_queue", C.c_int32)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
                 "ls_contacts")
@@ -270,7 +271,7 @@ class Rollout(torch.autograd.Function):
 # ------------------------------------------------------------------ serving
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
-                ("steps_per_interval", C.c_int32)]
+                ("steps_per_interval", C.c_int32), ("max_batch_worlds", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -303,7 +304,10 @@ class Server:
     def __init__(self, **kw):
         o = ServerOpts()
         _lib.dmx_default_server_opts(C.byref(o))
+        names = {f[0] for f in ServerOpts._fields_}
         for k, v in kw.items():
+            if k not in names:
+                raise TypeError(f"unknown server option {k!r}")
             setattr(o, k, v)
         h = _P()
         _check(_lib.dmx_server_create(C.byref(o), C.byref(h)))
@@ -322,18 +326,17 @@ class Server:
         q.ctrl_weight, q.want_grad = float(ctrl_weight), int(want_grad)
         t = C.c_uint64()
         _check(_lib.dmx_submit(self.h, C.byref(q), C.byref(t)))
-        self._pending[t.value] = (N, H, model.nu)
+        self._pending[t.value] = (np.zeros(N), np.zeros((N, H, model.nu)), np.zeros(N, np.int32))
         return t.value
 
     def poll(self, ticket):
-        N, H, nu = self._pending.get(ticket, (1, 1, 0))
-        cost, grad, st = np.zeros(N), np.zeros((N, H, nu)), np.zeros(N, np.int32)
+        cost, grad, st = self._pending.get(ticket) or (np.zeros(1), np.zeros((1, 1, 0)), np.zeros(1, np.int32))
         r = Result()
         r.cost, r.grad_u, r.world_status = cost.ctypes.data, (grad.ctypes.data if grad.size else None), st.ctypes.data
         code = _check(_lib.dmx_poll(self.h, C.c_uint64(ticket), C.byref(r)))
         if code == DMX_PENDING:
             return None
-        del self._pending[ticket]
+        self._pending.pop(ticket, None)
         return {"cost": cost, "grad_u": grad, "status": st, "t_submit": r.t_submit, "t_start": r.t_start,
                 "t_done": r.t_done}
 
