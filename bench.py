@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg, s")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -168,6 +169,11 @@ def main():
     nW, horizon = args.worlds, args.horizon
     fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
     adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
+    tuned = None
+    if args.lanes == 0 and not args.no_autotune:
+        # team size picked by timing each compiled one on this batch over a short horizon
+        best, times = D.autotune(model, x0, None, 1, min(0.1, horizon))
+        tuned = {"lanes_per_world": best, "ms_by_lanes_0.1s_horizon": {str(k): round(v, 3) for k, v in times.items()}}
     opts = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes)
 
     # one counted pass (work units), which also allocates the tape reused below
@@ -276,7 +282,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cube_toss: {nW} free cubes x 8 corner contacts, {horizon} s, t_c 1 ms, "
                                f"rtol 1e-6 atol 1e-8, fwd + adjoint of summed final position",
-                   "worlds": nW, "horizon_s": horizon, "lanes_per_world": args.lanes or "auto",
+                   "worlds": nW, "horizon_s": horizon,
+                   "lanes_per_world": args.lanes or (tuned["lanes_per_world"] if tuned else "default"),
+                   "autotune": tuned,
                    "parallelism": "1 GPU, worlds batched in one launch"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -108,7 +108,7 @@ typedef struct dmx_tape dmx_tape;
  * facmin 0.2, facmax 10, kP 0.2, kI 0.4, err_order 5, err_floor 1e-6,
  * max_attempts 1e6, newton_maxit 100, cfd 0, softplus_beta 1e4,
  * tape_steps 0 (= chosen by the library), lanes_per_world 0 (= per model),
- * h_levels 16. */
+ * h_levels 16, tape_stages -1, work_queue 0. */
 typedef struct {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor;
   int64_t max_attempts;
@@ -160,6 +160,12 @@ typedef struct {
    * batch exceeds the teams the device holds at once, or is ragged), 1 =
    * always, -1 = never (one world per team). */
   int32_t work_queue;
+  /* tape contents: 1 = every accepted step with its stage accelerations; 0 =
+   * checkpoints only (the step's start state; the reverse sweep solves the
+   * step's stages again: about a third of the memory, one more forward's
+   * work); -1 (default) = stages unless the tape would take more than half of
+   * the free device memory. */
+  int32_t tape_stages;
 } dmx_solver_opts;
 
 void dmx_default_opts(dmx_solver_opts* opts);
@@ -186,6 +192,16 @@ dmx_status dmx_rollout(const dmx_model* model, int32_t n_worlds, int32_t n_inter
                        int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
                        void* stream);
 
+/* Autotuner: times the forward rollout of this batch (device x0, u) with
+ * every team size (lanes per world) compiled for the model, on the stream,
+ * and makes the fastest the model's default (used when lanes_per_world is 0).
+ * Pass a representative batch with a short horizon.  best_lanes receives the
+ * choice; n_tried, lanes_tried[8] and ms_tried[8] (host, may be NULL) the
+ * candidates and their times.  Synchronizes the stream. */
+dmx_status dmx_autotune(dmx_model* model, int32_t n_worlds, int32_t n_intervals, double interval_dt,
+                        const double* x0, const double* u, void* stream, int32_t* best_lanes, int32_t* n_tried,
+                        int32_t* lanes_tried, double* ms_tried);
+
 /* Gradient of sum(x_out_bar * x_out) with respect to x0 and u through the
  * recorded discretization (step sizes held fixed; rejected attempts play no
  * part).  x0_bar [W][nx] and u_bar [W][n_intervals][nu] are overwritten.
@@ -196,7 +212,8 @@ dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_b
 /* Sizes of a tape: per-world capacity and record length in doubles. */
 dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t* record_doubles);
 /* Device pointer to the tape records [W][steps_per_world][record] with records
- * (t_n, h_n, interval, y_n[nx], a_1..a_6[nv]) and the per-world accepted-step
+ * (t_n, h_n, interval, y_n[nx], then a_1..a_6[nv] unless the tape holds
+ * checkpoints only) and the per-world accepted-step
  * counts [W] (int32). */
 dmx_status dmx_tape_data(const dmx_tape* tape, const double** records, const int32_t** n_steps);
 void dmx_tape_destroy(dmx_tape* tape);

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <set>
 
 #include <cmath>
@@ -157,10 +158,13 @@ void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int pla
 }
 template <class P>
 void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
+  constexpr int NXS = P::NQ + P::NV + 3;
+  const bool recompute = a.rec < NXS + 6 * P::NV;  // checkpoint-only tape
+  auto kernel = recompute ? dmx::adj_kernel<P, true> : dmx::adj_kernel<P, false>;
   if (!plain) {
-    const int blocks = grid_blocks<P>(dmx::adj_kernel<P>, a.W, a.g.queue != nullptr);
+    const int blocks = grid_blocks<P>(kernel, a.W, a.g.queue != nullptr);
     if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
-    hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
     return;
   }
   constexpr int NX = P::NQ + P::NV;
@@ -176,7 +180,7 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
     b.x0bar = a.x0bar + (size_t)w * NX;
     b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
     b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
-    hipLaunchKernelGGL(dmx::adj_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }
 
@@ -230,6 +234,7 @@ struct dmx_model {
   dmx::FreeModel host{};
   dmx::TreeModel tree{};
   void* dev = nullptr;
+  std::atomic<int> tuned_team{0};  // team size chosen by dmx_autotune (0: none)
 };
 
 struct dmx_tape {
@@ -261,6 +266,7 @@ void dmx_default_opts(dmx_solver_opts* o) {
   o->kP = 0.2; o->kI = 0.4; o->err_order = 5.0; o->err_floor = 1e-6; o->max_attempts = 1000000;
   o->newton_maxit = 100; o->cfd = 0; o->softplus_beta = 1e4; o->tape_steps = 0; o->lanes_per_world = 0;
   o->h_levels = 16;
+  o->tape_stages = -1;
 }
 
 static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out);
@@ -625,6 +631,7 @@ static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
 // wavefronts contend for their compute units' shared front end.
 static const KernelEntry* find_kernel(const dmx_model* m, int team) {
   if (team > 0) return lookup_kernel(m, team);
+  if (const int t = m->tuned_team.load()) return lookup_kernel(m, t);
   if (m->kind == 1) return lookup_kernel(m, 4);
   return lookup_kernel(m, m->ncb >= 16 ? 16 : m->ncb);
 }
@@ -687,8 +694,17 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   } else if (tape) {
     tp = new dmx_tape();
     tp->model = m; tp->W = W; tp->n_int = n_int; tp->nu = m->nu; tp->dt = dt; tp->u = u;
-    tp->rec = 3 + NX + 6 * m->nv;
     tp->cap = o.tape_steps > 0 ? o.tape_steps : 4096;
+    // stage accelerations on the tape unless asked otherwise or, by default,
+    // unless the full tape would take more than half the free device memory
+    // (then checkpoints only: the reverse sweep solves the stages again)
+    bool stages = o.tape_stages != 0;
+    if (o.tape_stages < 0) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+        stages = (double)W * tp->cap * (3 + NX + 6 * m->nv) * sizeof(double) <= 0.5 * (double)free_b;
+    }
+    tp->rec = 3 + NX + (stages ? 6 * m->nv : 0);
     tp->o = a.o;
     tp->adj = k->adj;
     tp->team = k->team;
@@ -736,6 +752,58 @@ dmx_status dmx_accel(const dmx_model* m, int32_t n, const double* x, const doubl
   dmx_default_opts(&oo);
   k->acc(m->dev, n, x, tau, cfd, to_solver(oo), acc, status, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  return DMX_OK;
+}
+
+dmx_status dmx_autotune(dmx_model* m, int32_t W, int32_t n_int, double dt, const double* x0, const double* u,
+                        void* stream, int32_t* best_lanes, int32_t* n_tried, int32_t* lanes_tried, double* ms_tried) {
+  if (!m || !x0 || !best_lanes) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (W <= 0 || n_int <= 0 || !(dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
+  if (m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  hipStream_t s = (hipStream_t)stream;
+  const int NX = m->nq + m->nv;
+  double* xo = nullptr;
+  int* st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&xo, sizeof(double) * (size_t)W * NX);
+  if (e == hipSuccess) e = hipMalloc(&st, sizeof(int) * (size_t)W);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    if (xo) (void)hipFree(xo);
+    if (st) (void)hipFree(st);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (e != hipSuccess) { cleanup(); return fail(DMX_ERR_OUT_OF_MEMORY, "autotune buffers"); }
+  int best = 0, tried = 0;
+  float best_ms = 0.0f;
+  for (const KernelEntry& k : kKernels) {
+    if (k.kind != m->kind || k.nc != m->ncb || (m->kind == 1 && (k.nv != m->nv || k.nb != m->nb))) continue;
+    dmx_solver_opts o;
+    dmx_default_opts(&o);
+    o.lanes_per_world = k.team;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run loads the code object
+      if (hipEventRecord(e0, s) != hipSuccess) { cleanup(); return fail(DMX_ERR_HIP, "event record"); }
+      const dmx_status r = dmx_rollout(m, W, n_int, dt, &o, x0, u, xo, st, nullptr, nullptr, nullptr, stream);
+      if (r != DMX_OK) { cleanup(); return r; }
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        cleanup();
+        return fail(DMX_ERR_HIP, "autotune timing");
+      }
+    }
+    if (lanes_tried && tried < 8) lanes_tried[tried] = k.team;
+    if (ms_tried && tried < 8) ms_tried[tried] = ms;
+    ++tried;
+    if (best == 0 || ms < best_ms) { best = k.team; best_ms = ms; }
+  }
+  cleanup();
+  if (!best) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  m->tuned_team.store(best);
+  *best_lanes = best;
+  if (n_tried) *n_tried = tried;
   return DMX_OK;
 }
 

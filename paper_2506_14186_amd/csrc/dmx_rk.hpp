@@ -369,10 +369,12 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
           double* rec = tape_w + (size_t)nacc * a.rec;
           if (tl == 0) { rec[0] = t; rec[1] = h; rec[2] = (double)kk; }
           team_store<NX, L>(rec + 3, y, tl);
-          double Acp[6 * NV];
+          if (a.rec >= 3 + NX + 6 * NV) {  // stage accelerations (else a checkpoint-only tape)
+            double Acp[6 * NV];
 #pragma unroll
-          for (int j = 0; j < 6 * NV; ++j) Acp[j] = A[j / NV][j % NV];
-          team_store<6 * NV, L>(rec + 3 + NX, Acp, tl);
+            for (int j = 0; j < 6 * NV; ++j) Acp[j] = A[j / NV][j % NV];
+            team_store<6 * NV, L>(rec + 3 + NX, Acp, tl);
+          }
         }
 #pragma unroll
         for (int i = 0; i < NX; ++i) y[i] = Y[i];
@@ -425,7 +427,10 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
   }
 }
 
-template <class P>
+// RECOMPUTE: the tape holds only the accepted steps' start states
+// (checkpoints); each step's stage accelerations are solved again, in the
+// forward's order and with its warm starts, before the step is reversed.
+template <class P, bool RECOMPUTE>
 DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
                        double (*Ab)[P::NV]) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
@@ -469,7 +474,27 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll
     for (int j = 0; j < 6; ++j)
 #pragma unroll
-      for (int d = 0; d < NV; ++d) { A[j][d] = rec[3 + NX + j * NV + d]; Ab[j][d] = 0.0; }
+      for (int d = 0; d < NV; ++d) Ab[j][d] = 0.0;
+    if constexpr (RECOMPUTE) {
+#pragma unroll 1
+      for (int i = 0; i < 6; ++i) {
+        double Y[NX], dq[NV], ai[NV];
+        if (i == 0) {
+#pragma unroll
+          for (int j = 0; j < NX; ++j) Y[j] = y[j];
+        } else {
+          stage_state<P>(y, A, i, h, Y, dq);
+        }
+        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, i > 0 ? A[i - 1] : nullptr, ai, st);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+#pragma unroll
+        for (int d = 0; d < NV; ++d) A[j][d] = rec[3 + NX + j * NV + d];
+    }
 #pragma unroll
     for (int d = 0; d < NV; ++d) A[6][d] = 0.0;
     double qb[NQ], vb[NV];
@@ -530,7 +555,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
 }
 
-template <class P>
+template <class P, bool RECOMPUTE = false>
 __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
   constexpr int L = P::TEAM, NV = P::NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -542,7 +567,7 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
-    adj_world<P>(*model, a, w, tl, A, Ab);
+    adj_world<P, RECOMPUTE>(*model, a, w, tl, A, Ab);
   }
 }
 

@@ -171,8 +171,9 @@ DMX_DEV void tree_point_jac(const TreeModel& m, const TreeWs<NV, NB>& ws, int b,
 // M (dense, row-major) and bias c from the body Jacobians.
 template <int NV, int NB>
 DMX_DEV void tree_mass_bias(const TreeModel& m, const TreeWs<NV, NB>& ws, double* M, double* c) {
+  // M: packed lower triangle, M[tri(i, j)] for i >= j
 #pragma unroll
-  for (int i = 0; i < NV * NV; ++i) M[i] = 0.0;
+  for (int i = 0; i < NV * (NV + 1) / 2; ++i) M[i] = 0.0;
 #pragma unroll
   for (int i = 0; i < NV; ++i) c[i] = 0.0;
   for (int b = 0; b < m.nb; ++b) {
@@ -197,13 +198,21 @@ DMX_DEV void tree_mass_bias(const TreeModel& m, const TreeWs<NV, NB>& ws, double
       for (int j = 0; j <= i; ++j) {
         const double s = mb * (Jp[0][i] * Jp[0][j] + Jp[1][i] * Jp[1][j] + Jp[2][i] * Jp[2][j]) +
                          Jr[0][i] * IJ[0][j] + Jr[1][i] * IJ[1][j] + Jr[2][i] * IJ[2][j];
-        M[i * NV + j] += s;
+        M[tri(i, j)] += s;
       }
   }
+}
+
+// y = M x for a packed symmetric M
+template <int NV>
+DMX_DEV void symv_packed(const double* M, const double* x, double* y) {
 #pragma unroll
-  for (int i = 0; i < NV; ++i)
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
 #pragma unroll
-    for (int j = i + 1; j < NV; ++j) M[i * NV + j] = M[j * NV + i];
+    for (int j = 0; j < NV; ++j) s += M[i >= j ? tri(i, j) : tri(j, i)] * x[j];
+    y[i] = s;
+  }
 }
 
 template <int NV, int CPL>
@@ -305,36 +314,32 @@ DMX_DEV void tree_active(const TreeRows<NV, CPL>& rw, const double* x, uint32_t*
   }
 }
 
-// H = M + sum over active edges of D J_e J_e^T (dense NV x NV, team-summed)
+// H = M + sum over active edges of D J_e J_e^T (packed, team-summed;
+// inactive edges enter with weight 0)
 template <int NV, int CPL, int L>
 DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
   constexpr int NT = NV * (NV + 1) / 2;
-  double hp[NT];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) hp[i] = 0.0;
+  for (int i = 0; i < NT; ++i) H[i] = 0.0;
 #pragma unroll
-  for (int k = 0; k < CPL; ++k)
+  for (int k = 0; k < CPL; ++k) {
+    if (act[k] == 0u) continue;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if (!((act[k] >> e) & 1u)) continue;
+      const double D = ((act[k] >> e) & 1u) ? rw.D[k] : 0.0;
       double Je[NV];
       tree_edge<NV>(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        const double di = rw.D[k] * Je[i];
+        const double di = D * Je[i];
 #pragma unroll
-        for (int j = 0; j <= i; ++j) hp[i * (i + 1) / 2 + j] += di * Je[j];
+        for (int j = 0; j <= i; ++j) H[tri(i, j)] += di * Je[j];
       }
     }
-  team_sum_arr<L, NT>(hp);
+  }
+  team_sum_arr<L, NT>(H);
 #pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      const double h = M[i * NV + j] + hp[i * (i + 1) / 2 + j];
-      H[i * NV + j] = h;
-      H[j * NV + i] = h;
-    }
+  for (int i = 0; i < NT; ++i) H[i] += M[i];
 }
 
 template <int NV, int CPL, int L>
@@ -372,26 +377,28 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
 #pragma unroll
     for (int i = 0; i < NV; ++i) gp[i] = 0.0;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k)
+    for (int k = 0; k < CPL; ++k) {
+      if (act[k] == 0u) continue;
+      // sum_e w_e (J_n + s_e J_t) = (sum w_e) J_n + mu (w0 - w1) J_t1 + mu (w2 - w3) J_t2
+      double we[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!((act[k] >> e) & 1u)) continue;
-        double Je[NV];
-        tree_edge<NV>(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
-        const double wgt = rw.D[k] * s[k][e];
+      for (int e = 0; e < 4; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
+      const double cn = (we[0] + we[1]) + (we[2] + we[3]);
+      const double c1 = rw.mu[k] * (we[0] - we[1]), c2 = rw.mu[k] * (we[2] - we[3]);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) gp[i] += wgt * Je[i];
-      }
+      for (int i = 0; i < NV; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
+    }
     team_sum_arr<L, NV>(gp);
     double dx[NV], dl[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) dx[i] = x[i] - a0[i];
+    symv_packed<NV>(M, dx, dl);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) dl[i] = -(dotn<NV>(M + i * NV, dx) + gp[i]);
-    double H[NV * NV];
+    for (int i = 0; i < NV; ++i) dl[i] = -(dl[i] + gp[i]);
+    double H[NV * (NV + 1) / 2];
     tree_hessian<NV, CPL, L>(M, rw, act, H);
-    if (!chol<NV>(H)) { st.status |= 4; return; }
-    chol_solve<NV>(H, dl);
+    if (!chol_packed<NV>(H)) { st.status |= 4; return; }
+    chol_solve_packed<NV>(H, dl);
     double dmax = 0.0, xmax = 1.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) { dmax = fmax(dmax, fabs(dl[i])); xmax = fmax(xmax, fmax(fabs(x[i]), fabs(a0[i]))); }
@@ -419,8 +426,7 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
       return;
     }
     double Mdl[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) Mdl[i] = dotn<NV>(M + i * NV, dl);
+    symv_packed<NV>(M, dl, Mdl);
     const double dMd = dotn<NV>(dl, Mdl), xMd = dotn<NV>(dx, Mdl);
     double lo = 0.0, hi = 1e300, a = 1.0;
     for (int ls = 0; ls < 60; ++ls) {
@@ -433,12 +439,13 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
         sa[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (s[k][e] + a * t[k][e] < 0.0) {
-            sa[k] |= 1u << e;
-            c2 += rw.D[k] * t[k][e] * t[k][e];
-            c1 += rw.D[k] * t[k][e] * s[k][e];
-          }
+        for (int e = 0; e < 4; ++e) {
+          const bool on = s[k][e] + a * t[k][e] < 0.0;
+          sa[k] |= on ? (1u << e) : 0u;
+          const double dt = on ? rw.D[k] * t[k][e] : 0.0;
+          c2 += dt * t[k][e];
+          c1 += dt * s[k][e];
+        }
       }
       c1 = team_sum<L>(c1) + xMd;
       c2 = team_sum<L>(c2) + dMd;
@@ -485,15 +492,15 @@ struct TreePhys {
     TreeWs<NV, NB>& w = ws();
     const double* v = y + NQ;
     tree_kin<NV, NB>(m, y, v, nullptr, nullptr, w, false);
-    double M[NV * NV], c[NV];
+    double M[NV * (NV + 1) / 2], c[NV];
     tree_mass_bias<NV, NB>(m, w, M, c);
-    double a0[NV], L_[NV * NV];
+    double a0[NV], L_[NV * (NV + 1) / 2];
 #pragma unroll
-    for (int i = 0; i < NV * NV; ++i) L_[i] = M[i];
-    if (!chol<NV>(L_)) st.status |= 4;
+    for (int i = 0; i < NV * (NV + 1) / 2; ++i) L_[i] = M[i];
+    if (!chol_packed<NV>(L_)) st.status |= 4;
 #pragma unroll
     for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
-    chol_solve<NV>(L_, a0);
+    chol_solve_packed<NV>(L_, a0);
     TreeRows<NV, CPL> rw;
     tree_rows<NV, NB, CPL, L>(m, w, v, cfd, beta, rw);
     if (team_leader(L)) st.u_rhs++;
@@ -510,19 +517,19 @@ struct TreePhys {
     const double* v = y + NQ;
     // frames and velocities; M, rows, active set at x*, lam
     tree_kin<NV, NB>(m, q, v, nullptr, nullptr, w, false);
-    double M[NV * NV], c[NV];
+    double M[NV * (NV + 1) / 2], c[NV];
     tree_mass_bias<NV, NB>(m, w, M, c);
     TreeRows<NV, CPL> rw;
     tree_rows<NV, NB, CPL, L>(m, w, v, cfd, beta, rw);
     double xs[NV];
     if (cfd) {
-      double Lm[NV * NV], a0[NV];
+      double Lm[NV * (NV + 1) / 2], a0[NV];
 #pragma unroll
-      for (int i = 0; i < NV * NV; ++i) Lm[i] = M[i];
-      chol<NV>(Lm);
+      for (int i = 0; i < NV * (NV + 1) / 2; ++i) Lm[i] = M[i];
+      chol_packed<NV>(Lm);
 #pragma unroll
       for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
-      chol_solve<NV>(Lm, a0);
+      chol_solve_packed<NV>(Lm, a0);
       tree_newton<NV, CPL, L>(M, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
@@ -534,13 +541,13 @@ struct TreePhys {
     if (team_leader(L)) st.u_vjp++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
-    double H[NV * NV];
+    double H[NV * (NV + 1) / 2];
     tree_hessian<NV, CPL, L>(M, rw, act, H);
-    chol<NV>(H);
+    chol_packed<NV>(H);
     double lam[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) lam[i] = abar[i];
-    chol_solve<NV>(H, lam);
+    chol_solve_packed<NV>(H, lam);
     // motion under (v, x*) and the lam velocity field, with reverse storage
     tree_kin<NV, NB>(m, q, v, xs, lam, w, true);
     // zero the cotangent accumulators

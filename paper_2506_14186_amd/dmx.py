@@ -44,7 +44,7 @@ class SolverOpts(C.Structure):
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
         ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32),
         ("h_levels", C.c_int32), ("fail_state", _P), ("world_intervals", _P), ("world_order", _P),
-        ("work_queue", C.c_int32)]
+        ("work_queue", C.c_int32), ("tape_stages", C.c_int32)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
                 "ls_contacts")
@@ -60,15 +60,17 @@ _lib.dmx_rollout.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, C.POINTER(Sol
                              C.POINTER(_P), _P]
 _lib.dmx_rollout_vjp.argtypes = [_P, _P, _P, _P, _P]
 _lib.dmx_accel.argtypes = [_P, C.c_int32, _P, _P, C.c_int32, _P, _P, _P]
+_lib.dmx_autotune.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, _P, _P, _P, _P, _P, _P, _P]
 _lib.dmx_tape_info.argtypes = [_P, _P, _P]
 _lib.dmx_tape_data.argtypes = [_P, _P, _P]
 _lib.dmx_tape_destroy.argtypes = [_P]
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
-           "dmx_tape_data", "dmx_accel"):
+           "dmx_tape_data", "dmx_accel", "dmx_autotune"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
-           "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_last_error"]
+           "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_autotune",
+           "dmx_last_error"]
 
 
 class DmxError(RuntimeError):
@@ -194,6 +196,17 @@ class _DevArray:
     def __init__(self, ptr, shape, typestr):
         self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
                                          "version": 3, "strides": None}
+
+
+def autotune(model, x0, u, n_int, dt):
+    """Time every compiled team size on this batch (CUDA float64 tensors) and
+    make the fastest the model's default.  Returns (best, {lanes: ms})."""
+    W = x0.shape[0]
+    best, n = C.c_int32(), C.c_int32()
+    lanes, ms = (C.c_int32 * 8)(), (C.c_double * 8)()
+    _check(_lib.dmx_autotune(model.h, W, int(n_int), float(dt), _ptr(x0), _ptr(u), _stream(), C.byref(best),
+                             C.byref(n), lanes, ms))
+    return best.value, {lanes[i]: ms[i] for i in range(min(n.value, 8))}
 
 
 def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False, reuse=None):

@@ -478,3 +478,44 @@ def test_ragged_horizons_and_work_queue(D, oracle):
     a = D.rollout(model, _t(x0), _t(u), H, dt, opts=D.default_opts(work_queue=1))
     b = D.rollout(model, _t(x0), _t(u), H, dt, opts=D.default_opts(work_queue=-1))
     np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+
+
+def test_autotune_picks_a_compiled_team(D):
+    desc, x0, n_int, dt = _cube_batch(64, horizon=0.05)
+    model = D.Model(desc)
+    best, times = D.autotune(model, _t(x0), None, n_int, dt)
+    print(f"autotune: {times} -> {best} lanes per world")
+    assert best in times and len(times) >= 2 and all(t > 0 for t in times.values())
+    a = D.rollout(model, _t(x0), None, n_int, dt)
+    b = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(lanes_per_world=best))
+    np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["cube", "chain"])
+def test_checkpoint_tape_recomputes_stages(D, case):
+    """A checkpoint-only tape (start states of the accepted steps) gives the
+    gradient of the full tape: the reverse sweep solves each step's stages
+    again (stage 0 from a cold start, so the bits may differ slightly)."""
+    if case == "cube":
+        desc, x0, n_int, dt = _cube_batch(32)
+        u = None
+    else:
+        cfg = W.chain_walk(n_worlds=16, n_intervals=20)
+        desc, x0, n_int, dt, u = cfg["model"], cfg["x0"], 20, cfg["interval_dt"], cfg["u"]
+    model = D.Model(desc)
+    ut = None if u is None else _t(u)
+    xbar = np.zeros_like(x0)
+    xbar[:, :3] = 1.0
+    out = {}
+    for stages in (1, 0):
+        r = D.rollout(model, _t(x0), ut, n_int, dt, opts=D.default_opts(tape_stages=stages, tape_steps=4096),
+                      tape=True)
+        gx, gu = D.rollout_vjp(r["tape"], _t(xbar))
+        out[stages] = (r["x"].cpu().numpy(), gx.cpu().numpy(), None if gu is None else gu.cpu().numpy(),
+                       r["tape"].info()[1])
+    assert out[1][3] == 3 + model.nx + 6 * model.nv and out[0][3] == 3 + model.nx
+    np.testing.assert_array_equal(out[1][0], out[0][0])
+    eg = rel_grad(out[0][1], out[1][1])
+    eu = 0.0 if u is None else rel_grad(out[0][2].reshape(len(x0), -1), out[1][2].reshape(len(x0), -1)).max()
+    print(f"{case}: checkpoint-only vs full tape: x0 grad {eg.max():.2e}, u grad {eu:.2e}")
+    assert eg.max() <= 1e-9 and eu <= 1e-9
