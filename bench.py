@@ -47,6 +47,23 @@ ADJ_FLOPS = {
 }
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the kernels as built now (same device-code digest)."""
+    import re
+    from paper_2506_14186_amd import build as B
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cube_toss_4096.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    dig = re.search(r"^kernel-digest: (\w+)", text, re.M)
+    val = re.search(rf"^traffic-bytes {kernel}: (\d+)", text, re.M)
+    if not dig or not val or dig.group(1) != B.kernel_digest():
+        return None
+    return int(val.group(1))
+
+
 def algorithmic_flops(counters, table, nc):
     total = 0.0
     for name, per in table.items():
@@ -221,7 +238,9 @@ def main():
         ("adj_kernel", adj_ms, adj_flops)
     achieved = dom_flops / (dom_ms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": None, "kernel": dom_name,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": recorded_traffic(dom_name),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                "kernel": dom_name,
                 "kernel_ms": round(dom_ms, 3), "flops_per_launch": dom_flops,
                 "other_kernel": {"name": "adj_kernel" if dom_name == "fwd_kernel" else "fwd_kernel",
                                  "ms": round(adj_ms if dom_name == "fwd_kernel" else fwd_ms, 3),

@@ -194,7 +194,8 @@ dmx_status dmx_rollout(const dmx_model* model, int32_t n_worlds, int32_t n_inter
 
 /* Autotuner: times the forward rollout of this batch (device x0, u) with
  * every team size (lanes per world) compiled for the model, on the stream,
- * and makes the fastest the model's default (used when lanes_per_world is 0).
+ * and makes the fastest (a wider team must win by 2%) the model's default
+ * (used when lanes_per_world is 0).
  * Pass a representative batch with a short horizon.  best_lanes receives the
  * choice; n_tried, lanes_tried[8] and ms_tried[8] (host, may be NULL) the
  * candidates and their times.  Synchronizes the stream. */

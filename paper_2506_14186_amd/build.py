@@ -21,6 +21,20 @@ FLAGS = [
 ]
 
 
+KERNEL_SOURCES = ["dmx_common.hpp", "dmx_free.hpp", "dmx_tree.hpp", "dmx_rk.hpp"]
+
+
+def kernel_digest():
+    """sha256 of the device-code headers (the forward/reverse kernels), used to
+    tell whether recorded hardware counters still describe the built kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False, extra=()):
     cmd = [HIPCC] + FLAGS + list(extra) + ["-o", LIB] + SOURCES
     if verbose:

@@ -797,7 +797,8 @@ dmx_status dmx_autotune(dmx_model* m, int32_t W, int32_t n_int, double dt, const
     if (lanes_tried && tried < 8) lanes_tried[tried] = k.team;
     if (ms_tried && tried < 8) ms_tried[tried] = ms;
     ++tried;
-    if (best == 0 || ms < best_ms) { best = k.team; best_ms = ms; }
+    // a wider team must be at least 2% faster to be chosen (timing noise)
+    if (best == 0 || ms < 0.98f * best_ms) { best = k.team; best_ms = ms; }
   }
   cleanup();
   if (!best) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
