@@ -254,7 +254,7 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* device arena the server allocates once (default 8 GiB) */
   int32_t max_inflight;      /* batches on the device at once (default 4, at most n_streams) */
   int32_t n_streams;         /* HIP streams, default priority (default 4) */
-  int32_t steps_per_interval;/* tape capacity per world = this * n_intervals + 64 (default 24) */
+  int32_t steps_per_interval;/* tape capacity per world = this * n_intervals + 64 (default 40) */
   int32_t max_batch_worlds;  /* worlds merged into one batch (default 16384) */
 } dmx_server_opts;
 

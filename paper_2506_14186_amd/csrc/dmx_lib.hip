@@ -1119,7 +1119,7 @@ void dmx_default_server_opts(dmx_server_opts* o) {
   o->hbm_budget_bytes = 8ll << 30;
   o->max_inflight = 4;
   o->n_streams = 4;
-  o->steps_per_interval = 24;
+  o->steps_per_interval = 40;
   o->max_batch_worlds = 16384;
 }
 
