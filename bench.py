@@ -45,10 +45,6 @@ ADJ_FLOPS = {
     "vjp_contacts": 490,       # rows, activity, geometry and frame cotangents per active contact
     "vjp_edges": 160,          # Hessian term and implicit-solution cotangents per active edge
 }
-# with the stages' Hessian factors on the tape the reverse sweep assembles and
-# factors no Hessian: 6x6 Cholesky (156) and M terms (21) per vjp, the Hessian
-# term (54) per active edge are not part of its work
-ADJ_FLOPS_FACTORED = dict(ADJ_FLOPS, vjps=(380, 38), vjp_edges=106)
 
 
 def recorded_traffic(kernel):
@@ -209,8 +205,7 @@ def main():
     fc = dict(zip(D.FWD_COUNTERS, fwd_cnt.sum(0).cpu().numpy().tolist()))
     ac = dict(zip(D.ADJ_COUNTERS, adj_cnt.sum(0).cpu().numpy().tolist()))
     fwd_flops = algorithmic_flops(fc, FWD_FLOPS, model.ncon)
-    tape_kind = {16: 0, 52: 1, 178: 2}.get(tape.info()[1])
-    adj_flops = algorithmic_flops(ac, ADJ_FLOPS_FACTORED if tape_kind == 2 else ADJ_FLOPS, model.ncon)
+    adj_flops = algorithmic_flops(ac, ADJ_FLOPS, model.ncon)
 
     stream = torch.cuda.current_stream()
 
@@ -314,7 +309,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_gpu": plain,
         "serving": serving,
-        "work": {"fwd": fc, "adj": ac, "tape_kind": tape_kind, "accepted_steps_mean": float(n_acc.mean()),
+        "work": {"fwd": fc, "adj": ac, "accepted_steps_mean": float(n_acc.mean()),
                  "accepted_steps_max": int(n_acc.max()), "failed_worlds": int((status != 0).sum()),
                  "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)},
     }

@@ -160,12 +160,11 @@ typedef struct {
    * batch exceeds the teams the device holds at once, or is ragged), 1 =
    * always, -1 = never (one world per team). */
   int32_t work_queue;
-  /* tape contents per accepted step: 2 = start state, stage accelerations and
-   * the packed Cholesky factors of the stages' contact Hessians (the reverse
-   * sweep then factors nothing); 1 = start state and stage accelerations;
-   * 0 = start state only (a checkpoint: the reverse sweep solves the step's
-   * stages again, one more forward's work); -1 (default) = the richest kind
-   * that takes at most half of the free device memory. */
+  /* tape contents: 1 = every accepted step with its stage accelerations; 0 =
+   * checkpoints only (the step's start state; the reverse sweep solves the
+   * step's stages again: about a third of the memory, one more forward's
+   * work); -1 (default) = stages unless the tape would take more than half of
+   * the free device memory. */
   int32_t tape_stages;
 } dmx_solver_opts;
 
@@ -215,8 +214,7 @@ dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_b
 dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t* record_doubles);
 /* Device pointer to the tape records [W][steps_per_world][record] with records
  * (t_n, h_n, interval, y_n[nx], then a_1..a_6[nv] unless the tape holds
- * checkpoints only, then six packed factors [nv(nv+1)/2] for kind 2) and the
- * per-world accepted-step
+ * checkpoints only) and the per-world accepted-step
  * counts [W] (int32). */
 dmx_status dmx_tape_data(const dmx_tape* tape, const double** records, const int32_t** n_steps);
 void dmx_tape_destroy(dmx_tape* tape);

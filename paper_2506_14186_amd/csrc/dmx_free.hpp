@@ -257,11 +257,8 @@ DMX_DEV bool same_active(const uint32_t* a, const uint32_t* b) {
 // direction is found by a bracketed semismooth Newton iteration on the
 // piecewise-linear directional derivative.
 template <int CPL, int L>
-// hfac (may be null) receives the packed Cholesky factor of the Hessian at
-// the final active set (the one the reverse sweep differentiates at), or a
-// negative first entry when no row is active (then H = M).
 DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, const double* xw, double* x,
-                         int maxit, double* hfac, Stat& st) {
+                         int maxit, Stat& st) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) x[i] = a0[i];
   uint32_t act[CPL];
@@ -270,10 +267,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
-  if (!team_any<L>(any)) {  // no row active at a0: a0 is the minimizer
-    if (hfac) hfac[0] = -1.0;
-    return;
-  }
+  if (!team_any<L>(any)) return;  // no row active at a0: a0 is the minimizer
   // warm start (a nearby solution, e.g. the previous stage's): the iteration
   // below converges to the same unique minimizer from any start
   if (xw) {
@@ -323,9 +317,6 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     if (dmax <= 1e-13 * xmax) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) x[i] += dl[i];
-      if (hfac)
-#pragma unroll
-        for (int i = 0; i < 21; ++i) hfac[i] = H[i];
       return;
     }
     // directional data of every row
@@ -345,9 +336,6 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     if (same_active<CPL, L>(act, act1)) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) x[i] += dl[i];
-      if (hfac)
-#pragma unroll
-        for (int i = 0; i < 21; ++i) hfac[i] = H[i];
       return;
     }
     // exact line search: root of phi'(a) = a C2(a) + C1(a)
@@ -405,7 +393,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
 // generalized force tau.
 template <int NC, int L>
 struct FreePhys {
-  static constexpr int NQ = 7, NV = 6, TEAM = L, NH = 21;
+  static constexpr int NQ = 7, NV = 6, TEAM = L;
   static constexpr int CPL = (NC + L - 1) / L;
   using Model = FreeModel;
 
@@ -428,7 +416,7 @@ struct FreePhys {
   }
 
   DMX_DEV static void acc(const Model& m, const double* y, const double* tau, bool cfd, double beta, int maxit,
-                          const double* xw, double* a, double* hfac, Stat& st) {
+                          const double* xw, double* a, Stat& st) {
     V3 p; M3 R; Q4 qh; double inv;
     frame(y, &p, &R, &qh, &inv);
     const double* v = y + NQ;
@@ -439,7 +427,7 @@ struct FreePhys {
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    free_newton<CPL, L>(m, rw, a0, xw, a, maxit, hfac, st);
+    free_newton<CPL, L>(m, rw, a0, xw, a, maxit, st);
   }
 
   // Cotangent of the acceleration map.  x* solves H x* = (tau - c) + sum_A
@@ -450,8 +438,8 @@ struct FreePhys {
   // contact geometry and the body frame to (q, v).  For the CFD field x* is
   // solved here (its rows differ from the forward's).
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
-                              const double* abar, bool cfd, double beta, int maxit, const double* hfac,
-                              double* ybar, double* taubar, Stat& st) {
+                              const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
+                              Stat& st) {
     V3 p; M3 R; Q4 qh; double inv;
     frame(y, &p, &R, &qh, &inv);
     const double* v = y + NQ;
@@ -461,7 +449,7 @@ struct FreePhys {
     if (cfd) {
       double a0[6];
       a0_of(m, v, tau, a0);
-      free_newton<CPL, L>(m, rw, a0, nullptr, xs, maxit, nullptr, st);
+      free_newton<CPL, L>(m, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < 6; ++i) xs[i] = xs_in[i];
@@ -473,13 +461,8 @@ struct FreePhys {
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
     double H[21];
-    if (hfac && !cfd && hfac[0] > 0.0) {  // factor of the forward's final Hessian
-#pragma unroll
-      for (int i = 0; i < 21; ++i) H[i] = hfac[i];
-    } else {
-      free_hessian<CPL, L>(m, rw, act, H);
-      chol_packed<6>(H);
-    }
+    free_hessian<CPL, L>(m, rw, act, H);
+    chol_packed<6>(H);
     double lam[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) lam[i] = abar[i];

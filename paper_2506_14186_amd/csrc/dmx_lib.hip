@@ -158,8 +158,9 @@ void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int pla
 }
 template <class P>
 void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
-  auto kernel = a.rec >= dmx::rec_factors<P>() ? dmx::adj_kernel<P, 2>
-                : a.rec >= dmx::rec_stages<P>() ? dmx::adj_kernel<P, 0> : dmx::adj_kernel<P, 1>;
+  constexpr int NXS = P::NQ + P::NV + 3;
+  const bool recompute = a.rec < NXS + 6 * P::NV;  // checkpoint-only tape
+  auto kernel = recompute ? dmx::adj_kernel<P, true> : dmx::adj_kernel<P, false>;
   if (!plain) {
     const int blocks = grid_blocks<P>(kernel, a.W, a.g.queue != nullptr);
     if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
@@ -670,7 +671,6 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   dmx::FwdArgs a{};
   if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
   if (o.work_queue < -1 || o.work_queue > 1) return fail(DMX_ERR_INVALID_ARG, "bad work_queue");
-  if (o.tape_stages < -1 || o.tape_stages > 2) return fail(DMX_ERR_INVALID_ARG, "bad tape_stages");
   if (o.launch_mode == 1 && (o.world_intervals || o.world_order || o.work_queue == 1))
     return fail(DMX_ERR_INVALID_ARG, "the plain launch form takes uniform batches without a work queue");
   const bool use_queue = o.launch_mode == 0 && (o.work_queue == 1 || (o.work_queue == 0 &&
@@ -695,20 +695,16 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     tp = new dmx_tape();
     tp->model = m; tp->W = W; tp->n_int = n_int; tp->nu = m->nu; tp->dt = dt; tp->u = u;
     tp->cap = o.tape_steps > 0 ? o.tape_steps : 4096;
-    // tape kind (2: stage accelerations and Hessian factors, 1: stage
-    // accelerations, 0: checkpoints); by default the richest kind that takes
-    // at most half the free device memory
-    const int nh = m->nv * (m->nv + 1) / 2;
-    const int recs[3] = {3 + NX, 3 + NX + 6 * m->nv, 3 + NX + 6 * m->nv + 6 * nh};
-    int kind = o.tape_stages;
-    if (kind < 0) {
+    // stage accelerations on the tape unless asked otherwise or, by default,
+    // unless the full tape would take more than half the free device memory
+    // (then checkpoints only: the reverse sweep solves the stages again)
+    bool stages = o.tape_stages != 0;
+    if (o.tape_stages < 0) {
       size_t free_b = 0, total_b = 0;
-      kind = 0;
       if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
-        for (int c = 2; c >= 0; --c)
-          if ((double)W * tp->cap * recs[c] * sizeof(double) <= 0.5 * (double)free_b) { kind = c; break; }
+        stages = (double)W * tp->cap * (3 + NX + 6 * m->nv) * sizeof(double) <= 0.5 * (double)free_b;
     }
-    tp->rec = recs[kind];
+    tp->rec = 3 + NX + (stages ? 6 * m->nv : 0);
     tp->o = a.o;
     tp->adj = k->adj;
     tp->team = k->team;
@@ -930,8 +926,7 @@ long long request_records(const SrvReq& r, int steps_per_interval) {
 // device bytes a request adds to a batch (its share of every array, with the
 // per-array alignment of the batch layout as slack)
 size_t request_bytes(const SrvReq& r, int steps_per_interval) {
-  const size_t nv = r.model->nv;
-  const size_t W = r.N, nu_tot = (size_t)r.N * r.H * r.nu, rec = 3 + r.nx + 6 * nv + 3 * nv * (nv + 1);
+  const size_t W = r.N, nu_tot = (size_t)r.N * r.H * r.nu, rec = 3 + r.nx + 6 * r.model->nv;
   return sizeof(double) * (W * r.nx * 4 + nu_tot * 2 + W * 5) + sizeof(long long) * 2 * W + sizeof(int) * 5 * W +
          sizeof(double) * rec * (size_t)request_records(r, steps_per_interval) + 20 * 256;
 }
@@ -959,8 +954,7 @@ struct dmx_server {
     SrvReq* head = queue.front();
     SrvBatch* b = new SrvBatch();
     b->model = head->model; b->dt = head->dt; b->want_grad = head->want_grad;
-    const int nv = head->model->nv;
-    b->nx = head->nx; b->nu = head->nu; b->rec = 3 + head->nx + 6 * nv + 3 * nv * (nv + 1);
+    b->nx = head->nx; b->nu = head->nu; b->rec = 3 + head->nx + 6 * head->model->nv;
     size_t need = 0;
     for (SrvReq* r : queue) {
       if (r->model != b->model || r->dt != b->dt || r->want_grad != b->want_grad) continue;

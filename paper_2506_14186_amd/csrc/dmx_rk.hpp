@@ -241,25 +241,16 @@ __global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __re
 #pragma unroll
   for (int i = 0; i < NV; ++i) tau[i] = tau_in ? tau_in[(size_t)w * NV + i] : 0.0;
   Stat st{};
-  P::acc(*model, y, tau, cfd != 0, beta, maxit, nullptr, acc, nullptr, st);
+  P::acc(*model, y, tau, cfd != 0, beta, maxit, nullptr, acc, st);
   team_store<NV, L>(acc_out + (size_t)w * NV, acc, tl);
   if (tl == 0) status[w] = st.status;
 }
 
-// Tape record kinds by length: checkpoint (t, h, interval, y); + the six
-// stage accelerations; + the packed Hessian factors of those six stages.
-template <class P> constexpr int rec_checkpoint() { return 3 + P::NQ + P::NV; }
-template <class P> constexpr int rec_stages() { return rec_checkpoint<P>() + 6 * P::NV; }
-template <class P> constexpr int rec_factors() { return rec_stages<P>() + 6 * P::NH; }
-
 // One world's forward rollout by its team; A: the team's stage accelerations
-// and F their Hessian factors, in LDS (every team lane writes the same
-// replicated values).
+// in LDS (every team lane writes the same replicated values).
 template <class P>
-DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int tl, double (*A)[P::NV],
-                       double (*F)[P::NH]) {
-  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV, NH = P::NH;
-  const bool want_fac = a.rec >= rec_factors<P>();
+DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int tl, double (*A)[P::NV]) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
   const SolverOpts& o = a.o;
   const int n_int = world_intervals(a.g, a.n_int, w);
   const double* uw = a.u ? a.u + world_u(a.g, a.n_int, a.nu, w) : nullptr;
@@ -315,7 +306,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
         // warm start from the previous stage (stage 0: the last accepted
         // step's final stage, at the same state)
         const double* xw = i > 0 ? A[i - 1] : (have_prev ? A[0] : nullptr);
-        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, xw, ai, want_fac ? F[i] : nullptr, st);
+        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, xw, ai, st);
         have_prev = true;
         if ((st.status & 12) && !(before & 12) && a.fail_state) capture_failure<P>(a.fail_state, w, Y, tau, tl);
 #pragma unroll
@@ -378,22 +369,17 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
           double* rec = tape_w + (size_t)nacc * a.rec;
           if (tl == 0) { rec[0] = t; rec[1] = h; rec[2] = (double)kk; }
           team_store<NX, L>(rec + 3, y, tl);
-          if (a.rec >= rec_stages<P>()) {  // stage accelerations (else a checkpoint-only tape)
+          if (a.rec >= 3 + NX + 6 * NV) {  // stage accelerations (else a checkpoint-only tape)
             double Acp[6 * NV];
 #pragma unroll
             for (int j = 0; j < 6 * NV; ++j) Acp[j] = A[j / NV][j % NV];
             team_store<6 * NV, L>(rec + 3 + NX, Acp, tl);
           }
-          if (want_fac)  // stage Hessian factors, lanes striding over the entries
-            for (int j = tl; j < 6 * NH; j += L) rec[rec_stages<P>() + j] = F[j / NH][j % NH];
         }
 #pragma unroll
         for (int i = 0; i < NX; ++i) y[i] = Y[i];
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[0][d] = A[6][d];
-        if (want_fac)
-#pragma unroll
-          for (int j = 0; j < NH; ++j) F[0][j] = F[6][j];
         t = landing ? tend : t + h;
         eprev = et;
         hprop = quantize_step(fac * h, o.h_levels);
@@ -433,22 +419,18 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int team = gt / L, tl = gt & (L - 1);
   __shared__ double sA[64 / L][7][NV];
-  __shared__ double sF[64 / L][7][P::NH];
   double (*A)[NV] = sA[(threadIdx.x & 63) / L];
-  double (*F)[P::NH] = sF[(threadIdx.x & 63) / L];
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
-    fwd_world<P>(*model, a, w, tl, A, F);
+    fwd_world<P>(*model, a, w, tl, A);
   }
 }
 
-// MODE 0: the tape holds the stage accelerations; 1: only the accepted
-// steps' start states (checkpoints): each step's stage accelerations are
-// solved again, in the forward's order and with its warm starts, before the
-// step is reversed; 2: stage accelerations and the stages' Hessian factors
-// (the reverse sweep then assembles and factors no Hessian).
-template <class P, int MODE>
+// RECOMPUTE: the tape holds only the accepted steps' start states
+// (checkpoints); each step's stage accelerations are solved again, in the
+// forward's order and with its warm starts, before the step is reversed.
+template <class P, bool RECOMPUTE>
 DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
                        double (*Ab)[P::NV]) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
@@ -493,7 +475,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     for (int j = 0; j < 6; ++j)
 #pragma unroll
       for (int d = 0; d < NV; ++d) Ab[j][d] = 0.0;
-    if constexpr (MODE == 1) {
+    if constexpr (RECOMPUTE) {
 #pragma unroll 1
       for (int i = 0; i < 6; ++i) {
         double Y[NX], dq[NV], ai[NV];
@@ -503,7 +485,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         } else {
           stage_state<P>(y, A, i, h, Y, dq);
         }
-        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, i > 0 ? A[i - 1] : nullptr, ai, nullptr, st);
+        P::acc(m, Y, tau, false, o.beta, o.newton_maxit, i > 0 ? A[i - 1] : nullptr, ai, st);
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
       }
@@ -535,8 +517,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         double tb[NV], xs[NV], ab[NV];
 #pragma unroll
         for (int d = 0; d < NV; ++d) { xs[d] = A[i][d]; ab[d] = Ab[i][d]; }
-        const double* hfac = MODE == 2 ? rec + rec_stages<P>() + i * P::NH : nullptr;
-        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, hfac, Ybar, tb, st);
+        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st);
 #pragma unroll
         for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
       } else {
@@ -574,7 +555,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
 }
 
-template <class P, int MODE>
+template <class P, bool RECOMPUTE = false>
 __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
   constexpr int L = P::TEAM, NV = P::NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -586,7 +567,7 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
-    adj_world<P, MODE>(*model, a, w, tl, A, Ab);
+    adj_world<P, RECOMPUTE>(*model, a, w, tl, A, Ab);
   }
 }
 

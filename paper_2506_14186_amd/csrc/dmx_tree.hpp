@@ -352,10 +352,8 @@ DMX_DEV bool tree_same(const uint32_t* a, const uint32_t* b) {
 
 // exact Newton on the primal problem with dense M (see free_newton)
 template <int NV, int CPL, int L>
-// returns true if hfac (may be null) received the packed factor of the
-// Hessian at the final active set; false when no row is active (H = M)
-DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const double* a0, const double* xw, double* x,
-                         int maxit, double* hfac, Stat& st) {
+DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const double* a0, const double* xw, double* x,
+                         int maxit, Stat& st) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) x[i] = a0[i];
   uint32_t act[CPL];
@@ -364,7 +362,7 @@ DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
-  if (!team_any<L>(any)) return false;  // no row active at a0: a0 is the minimizer
+  if (!team_any<L>(any)) return;  // no row active at a0: a0 is the minimizer
   if (xw) {  // warm start; the iteration converges to the same minimizer
 #pragma unroll
     for (int i = 0; i < NV; ++i) x[i] = xw[i];
@@ -399,7 +397,7 @@ DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     for (int i = 0; i < NV; ++i) dl[i] = -(dl[i] + gp[i]);
     double H[NV * (NV + 1) / 2];
     tree_hessian<NV, CPL, L>(M, rw, act, H);
-    if (!chol_packed<NV>(H)) { st.status |= 4; return false; }
+    if (!chol_packed<NV>(H)) { st.status |= 4; return; }
     chol_solve_packed<NV>(H, dl);
     double dmax = 0.0, xmax = 1.0;
 #pragma unroll
@@ -407,10 +405,7 @@ DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     if (dmax <= 1e-13 * xmax) {
 #pragma unroll
       for (int i = 0; i < NV; ++i) x[i] += dl[i];
-      if (hfac)
-#pragma unroll
-        for (int i = 0; i < NV * (NV + 1) / 2; ++i) hfac[i] = H[i];
-      return true;
+      return;
     }
     double t[CPL][4];
     uint32_t act1[CPL];
@@ -428,10 +423,7 @@ DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     if (tree_same<NV, CPL, L>(act, act1)) {
 #pragma unroll
       for (int i = 0; i < NV; ++i) x[i] += dl[i];
-      if (hfac)
-#pragma unroll
-        for (int i = 0; i < NV * (NV + 1) / 2; ++i) hfac[i] = H[i];
-      return true;
+      return;
     }
     double Mdl[NV];
     symv_packed<NV>(M, dl, Mdl);
@@ -479,7 +471,6 @@ DMX_DEV bool tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     tree_active<NV, CPL>(rw, x, act, s);
   }
   st.status |= 8;
-  return false;
 }
 
 // cross-product reverse: c = u x w with cotangent cb -> ub += w x cb, wb += cb x u
@@ -489,7 +480,6 @@ template <int kNV, int NB, int NC, int L>
 struct TreePhys {
   static constexpr int NV = kNV, NQ = kNV, TEAM = L;
   static constexpr int CPL = (NC + L - 1) / L;
-  static constexpr int NH = kNV * (kNV + 1) / 2;
   using Model = TreeModel;
 
   DMX_DEV static TreeWs<NV, NB>& ws() {
@@ -498,7 +488,7 @@ struct TreePhys {
   }
 
   DMX_DEV static void acc(const Model& m, const double* y, const double* tau, bool cfd, double beta, int maxit,
-                          const double* xw, double* a, double* hfac, Stat& st) {
+                          const double* xw, double* a, Stat& st) {
     TreeWs<NV, NB>& w = ws();
     const double* v = y + NQ;
     tree_kin<NV, NB>(m, y, v, nullptr, nullptr, w, false);
@@ -516,14 +506,12 @@ struct TreePhys {
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    if (!tree_newton<NV, CPL, L>(M, rw, a0, xw, a, maxit, hfac, st) && hfac)
-#pragma unroll
-      for (int i = 0; i < NH; ++i) hfac[i] = L_[i];  // no active row: H = M
+    tree_newton<NV, CPL, L>(M, rw, a0, xw, a, maxit, st);
   }
 
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
-                              const double* abar, bool cfd, double beta, int maxit, const double* hfac,
-                              double* ybar, double* taubar, Stat& st) {
+                              const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
+                              Stat& st) {
     TreeWs<NV, NB>& w = ws();
     const double* q = y;
     const double* v = y + NQ;
@@ -542,7 +530,7 @@ struct TreePhys {
 #pragma unroll
       for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
       chol_solve_packed<NV>(Lm, a0);
-      tree_newton<NV, CPL, L>(M, rw, a0, nullptr, xs, maxit, nullptr, st);
+      tree_newton<NV, CPL, L>(M, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < NV; ++i) xs[i] = xs_in[i];
@@ -554,13 +542,8 @@ struct TreePhys {
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
     double H[NV * (NV + 1) / 2];
-    if (hfac && !cfd) {  // factor of the forward's final Hessian
-#pragma unroll
-      for (int i = 0; i < NH; ++i) H[i] = hfac[i];
-    } else {
-      tree_hessian<NV, CPL, L>(M, rw, act, H);
-      chol_packed<NV>(H);
-    }
+    tree_hessian<NV, CPL, L>(M, rw, act, H);
+    chol_packed<NV>(H);
     double lam[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) lam[i] = abar[i];
