@@ -31,6 +31,37 @@ struct PairF {
   double ssc[4];  // spline scales 1/mid^(p-1), 1/(1-mid)^(p-1): penetration (0, 1) and CFD (2, 3)
 };
 
+// Contact-pair constants and the slot -> (pair, capsule end) table, staged in
+// LDS once per block by stage_pairs(): lanes read their own slots' pairs, so
+// from global memory these would be vector loads with a full memory latency
+// each right-hand side.
+DMX_DEV PairF* lds_pairs() {
+  __shared__ PairF s[kMaxPairs];
+  return s;
+}
+DMX_DEV int* lds_slots() {  // [0, kMaxSlots): pair of slot; [kMaxSlots, 2 kMaxSlots): capsule end
+  __shared__ int s[2 * kMaxSlots];
+  return s;
+}
+DMX_DEV const PairF& slot_pair(int c) { return lds_pairs()[lds_slots()[c]]; }
+DMX_DEV int slot_sub(int c) { return lds_slots()[kMaxSlots + c]; }
+
+// Block-wide copy of a model's pair table into LDS (every thread of the block
+// calls it before any thread leaves).
+template <class M>
+DMX_DEV void stage_pairs(const M& mod) {
+  const double* src = (const double*)mod.pair;
+  double* dst = (double*)lds_pairs();
+  constexpr int n = (int)(sizeof(PairF) * kMaxPairs / sizeof(double));
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  int* sl = lds_slots();
+  for (int i = threadIdx.x; i < kMaxSlots; i += blockDim.x) {
+    sl[i] = mod.cpair[i];
+    sl[kMaxSlots + i] = mod.csub[i];
+  }
+  __syncthreads();
+}
+
 struct FreeModel {
   int np, nc, nu;
   int cpair[kMaxSlots], csub[kMaxSlots];
@@ -129,9 +160,9 @@ DMX_DEV double dot6(const double* a, const double* b) {
 // Contact point of slot c: the sphere (or capsule end sphere) centre in the
 // world, signed distance to the plane and the midpoint between the surfaces.
 DMX_DEV void slot_geom(const FreeModel& m, int c, V3 p, const M3& R, V3* lc, V3* ctr, double* r, V3* P) {
-  const PairF& pr = m.pair[m.cpair[c]];
+  const PairF& pr = slot_pair(c);
   V3 l = ld3(pr.l);
-  if (pr.gtype == 2) l = (m.csub[c] == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
+  if (pr.gtype == 2) l = (slot_sub(c) == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
   V3 ce = p + mul(R, l);
   V3 n = ld3(pr.n);
   double rr = dot(n, ce - ld3(pr.p0)) - pr.rad;
@@ -153,7 +184,7 @@ DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, b
     rw.slot[k] = c;
     rw.on[k] = false;
     if (c >= m.nc) continue;
-    const PairF& pr = m.pair[m.cpair[c]];
+    const PairF& pr = slot_pair(c);
     V3 lc, ce, P;
     double r;
     slot_geom(m, c, p, R, &lc, &ce, &r, &P);
@@ -476,7 +507,7 @@ struct FreePhys {
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
       if (!rw.on[k] || act[k] == 0u) continue;
-      const PairF& pr = m.pair[m.cpair[rw.slot[k]]];
+      const PairF& pr = slot_pair(rw.slot[k]);
       double mu = rw.mu[k], D = rw.D[k];
       double Jbn[6] = {0, 0, 0, 0, 0, 0}, Jb1[6] = {0, 0, 0, 0, 0, 0}, Jb2[6] = {0, 0, 0, 0, 0, 0};
       double rbar = 0.0;

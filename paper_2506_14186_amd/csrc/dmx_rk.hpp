@@ -234,6 +234,7 @@ __global__ void __launch_bounds__(64) accel_kernel(const typename P::Model* __re
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = gt / L;
   const int tl = gt & (L - 1);
+  stage_pairs(*model);
   if (w >= n) return;
   double y[NX], tau[NV], acc[NV];
 #pragma unroll
@@ -289,12 +290,15 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
       ++attempts;
       if (tl == 0) st.u_att++;
       // stages: 0 (only after an accepted step's interval end or at the
-      // start, FSAL otherwise) and 1..6; one call site of the acceleration map
+      // start, FSAL otherwise) and 1..6; one call site of the acceleration
+      // map.  The stage index runs from 0 for every team, so that it is
+      // uniform across the wavefront (tableau reads stay scalar).
       double Y[NX], dq[NV];
       const int status_before = st.status;
       bool fatal = false;
 #pragma unroll 1
-      for (int i = have_k1 ? 1 : 0; i < 7; ++i) {
+      for (int i = 0; i < 7; ++i) {
+        if (i == 0 && have_k1) continue;
         if (i == 0) {
 #pragma unroll
           for (int j = 0; j < NX; ++j) Y[j] = y[j];
@@ -420,6 +424,7 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
   const int team = gt / L, tl = gt & (L - 1);
   __shared__ double sA[64 / L][7][NV];
   double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  stage_pairs(*model);
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
@@ -564,6 +569,7 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
   __shared__ double sAb[64 / L][6][NV];
   double (*A)[NV] = sA[(threadIdx.x & 63) / L];
   double (*Ab)[NV] = sAb[(threadIdx.x & 63) / L];
+  stage_pairs(*model);
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;

@@ -233,9 +233,9 @@ DMX_DEV double dotn(const double* a, const double* b) {
 }
 
 DMX_DEV void tree_slot_geom(const TreeModel& m, int c, V3 pb, const M3& Rb, V3* lc, double* r, V3* P) {
-  const PairF& pr = m.pair[m.cpair[c]];
+  const PairF& pr = slot_pair(c);
   V3 l = ld3(pr.l);
-  if (pr.gtype == 2) l = (m.csub[c] == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
+  if (pr.gtype == 2) l = (slot_sub(c) == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
   const V3 ce = pb + mul(Rb, l);
   const V3 n = ld3(pr.n);
   const double rr = dot(n, ce - ld3(pr.p0)) - pr.rad;
@@ -254,8 +254,8 @@ DMX_DEV void tree_rows(const TreeModel& m, const TreeWs<NV, NB>& ws, const doubl
     rw.slot[k] = c;
     rw.on[k] = false;
     if (c >= m.nc) continue;
-    const PairF& pr = m.pair[m.cpair[c]];
-    const int b = m.pbody[m.cpair[c]];
+    const PairF& pr = slot_pair(c);
+    const int b = m.pbody[lds_slots()[c]];
     rw.body[k] = b;
     V3 lc, P;
     double r;
@@ -578,7 +578,7 @@ struct TreePhys {
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
       if (!rw.on[k] || act[k] == 0u) continue;
-      const PairF& pr = m.pair[m.cpair[rw.slot[k]]];
+      const PairF& pr = slot_pair(rw.slot[k]);
       const double mu = rw.mu[k], D = rw.D[k];
       double Jbn[NV], Jb1[NV], Jb2[NV];
 #pragma unroll
