@@ -188,9 +188,9 @@ def main():
     adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
     tuned = None
     if args.lanes == 0 and not args.no_autotune:
-        # team size picked by timing each compiled one on this batch over a short horizon
-        best, times = D.autotune(model, x0, None, 1, min(0.1, horizon))
-        tuned = {"lanes_per_world": best, "ms_by_lanes_0.1s_horizon": {str(k): round(v, 3) for k, v in times.items()}}
+        # team size picked by timing the forward with each compiled one on this batch
+        best, times = D.autotune(model, x0, None, 1, horizon)
+        tuned = {"lanes_per_world": best, "fwd_ms_by_lanes": {str(k): round(v, 3) for k, v in times.items()}}
     opts = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes)
 
     # one counted pass (work units), which also allocates the tape reused below
