@@ -79,16 +79,33 @@ DMX_DEV Q4 qnormalize(Q4 x, double* inv_norm) {
 }
 DMX_DEV Q4 qnormalize_vjp(Q4 y, double inv_norm, Q4 yb) { return qscale(inv_norm, qadd(yb, qscale(-qdot(y, yb), y))); }
 
-// exp of half a rotation vector th: (cos(|th|/2), sin(|th|/2)/|th| th), with a
-// Taylor series in |th|^2 below |th| = 1e-4 (finite derivatives at zero).
+// exp of half a rotation vector th: (cos(|th|/2), sin(|th|/2)/|th| th).  For
+// |th| < 1 (every step of the workloads here) both factors are power series
+// in u = |th|^2/4, cos(phi/2) = sum (-u)^k/(2k)!, sin(phi/2)/phi = 1/2 sum
+// (-u)^k/(2k+1)!, summed to k = 9 (the next term is below 1e-21): no square
+// root, trigonometric call or division, and finite derivatives at zero.
 DMX_DEV Q4 qexp_half(V3 th, double* cs, double* sn, double* dcs, double* dsn) {
   double t2 = dot(th, th);
   double c, s, dc, ds;  // c(t2), s(t2) and their derivatives with respect to t2
-  if (t2 < 1e-8) {
-    c = 1.0 - t2 / 8.0 + t2 * t2 / 384.0;
-    s = 0.5 - t2 / 48.0 + t2 * t2 / 3840.0;
-    dc = -1.0 / 8.0 + t2 / 192.0;
-    ds = -1.0 / 48.0 + t2 / 1920.0;
+  if (t2 < 1.0) {
+    // 1/(2k)! and 1/(2k+1)! for k = 0..9
+    constexpr double ce[10] = {1.0, 1.0 / 2, 1.0 / 24, 1.0 / 720, 1.0 / 40320, 1.0 / 3628800, 1.0 / 479001600,
+                               1.0 / 87178291200.0, 1.0 / 20922789888000.0, 1.0 / 6402373705728000.0};
+    constexpr double se[10] = {1.0, 1.0 / 6, 1.0 / 120, 1.0 / 5040, 1.0 / 362880, 1.0 / 39916800,
+                               1.0 / 6227020800.0, 1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
+                               1.0 / 121645100408832000.0};
+    const double u = 0.25 * t2;
+    double pc = ce[9], ps = se[9], qc = 9.0 * ce[9], qs = 9.0 * se[9];
+#pragma unroll
+    for (int k = 8; k >= 0; --k) {  // Horner; the alternating signs come from "- u *"
+      pc = ce[k] - u * pc;
+      ps = se[k] - u * ps;
+      if (k >= 1) { qc = k * ce[k] - u * qc; qs = k * se[k] - u * qs; }
+    }
+    c = pc;
+    s = 0.5 * ps;
+    dc = -0.25 * qc;
+    ds = -0.125 * qs;
   } else {
     double phi = sqrt(t2);
     double ch = cos(0.5 * phi), sh = sin(0.5 * phi);

@@ -60,7 +60,9 @@ constexpr Tableau make_tableau() {
   }
   return t;
 }
-__constant__ Tableau kTab = make_tableau();
+// compile-time tableau: stage-specialized code reads it with constant
+// indices, so every coefficient is an immediate operand
+constexpr Tableau kTab = make_tableau();
 
 struct SolverOpts {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor, beta;
@@ -200,21 +202,60 @@ DMX_DEV void team_store(double* dst, const double* src, int tl) {
     if ((i & (L - 1)) == tl) dst[i] = src[i];
 }
 
-// stage state Y_i from y_n and the stage accelerations A[0..i-1]
+// Coefficients of stage i (a[i][l], (A A)[i][l], c[i]), selected by a
+// switch on the (uniform) stage index so that they are immediate operands.
+struct StageCoef {
+  double a[6], a2[6], c;
+};
+template <int I>
+DMX_DEV StageCoef stage_coef_c() {
+  StageCoef k;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) { k.a[l] = kTab.a[I][l]; k.a2[l] = kTab.a2[I][l]; }
+  k.c = kTab.c[I];
+  return k;
+}
+DMX_DEV StageCoef stage_coef(int i) {
+  switch (i) {
+    case 1: return stage_coef_c<1>();
+    case 2: return stage_coef_c<2>();
+    case 3: return stage_coef_c<3>();
+    case 4: return stage_coef_c<4>();
+    case 5: return stage_coef_c<5>();
+    default: return stage_coef_c<6>();
+  }
+}
+
+// stage state Y_i from y_n and the stage accelerations A[0..i-1] (i >= 1)
 template <class P>
 DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq) {
   constexpr int NQ = P::NQ, NV = P::NV;
+  const StageCoef k = stage_coef(i);
 #pragma unroll
   for (int d = 0; d < NV; ++d) {
     double sv = 0.0, sq = 0.0;
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      if (l < i) { sv += kTab.a[i][l] * A[l][d]; sq += kTab.a2[i][l] * A[l][d]; }
-    }
+    for (int l = 0; l < 6; ++l)
+      if (l < i) { sv += k.a[l] * A[l][d]; sq += k.a2[l] * A[l][d]; }
     Y[NQ + d] = y[NQ + d] + h * sv;
-    dq[d] = h * (kTab.c[i] * y[NQ + d] + h * sq);
+    dq[d] = h * (k.c * y[NQ + d] + h * sq);
   }
   P::qplus(y, dq, Y);
+}
+
+// cotangents of stage i's combination: v_bar from its velocity part and the
+// (+) increment's velocity term, A_bar[l] for the earlier stages
+template <class P>
+DMX_DEV void stage_distribute(int i, const double* Ybar, const double* dqb, double h, double* vb, double (*Ab)[P::NV]) {
+  constexpr int NQ = P::NQ, NV = P::NV;
+  const StageCoef k = stage_coef(i);
+#pragma unroll
+  for (int d = 0; d < NV; ++d) {
+    vb[d] += Ybar[NQ + d] + h * k.c * dqb[d];
+#pragma unroll
+    for (int l = 0; l < 6; ++l)
+      if (l < i) Ab[l][d] += h * k.a[l] * Ybar[NQ + d] + h * h * k.a2[l] * dqb[d];
+  }
 }
 
 template <class P>
@@ -536,13 +577,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
       } else {
         double dqb[NV];
         P::qplus_vjp(y, dq, Ybar, qb, dqb);
-#pragma unroll
-        for (int d = 0; d < NV; ++d) {
-          vb[d] += Ybar[NQ + d] + h * kTab.c[i] * dqb[d];
-#pragma unroll
-          for (int l = 0; l < 6; ++l)
-            if (l < i) Ab[l][d] += h * kTab.a[i][l] * Ybar[NQ + d] + h * h * kTab.a2[i][l] * dqb[d];
-        }
+        stage_distribute<P>(i, Ybar, dqb, h, vb, Ab);
       }
     }
 #pragma unroll
