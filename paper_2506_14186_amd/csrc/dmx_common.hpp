@@ -70,10 +70,25 @@ DMX_DEV Q4 quat2mat_vjp(Q4 q, const M3& Rb) {
   g.z = 2.0 * (q.z * (-b[0] - b[4] + b[8]) + q.w * (b[3] - b[1]) + q.x * (b[2] + b[6]) + q.y * (b[5] + b[7]));
   return g;
 }
+// 1/sqrt(x), x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2 (a few ulp; no square root and division sequence)
+DMX_DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y * (1.5 - 0.5 * x * y * y);
+}
+
+// 1/x, x != 0 finite: the hardware estimate refined by two Newton steps
+// y <- y (2 - x y) (a few ulp)
+DMX_DEV double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  return y * (2.0 - x * y);
+}
+
 // y = x / |x| and its cotangent map
 DMX_DEV Q4 qnormalize(Q4 x, double* inv_norm) {
-  double n = sqrt(qdot(x, x));
-  double s = 1.0 / n;
+  double s = rsqrt_nr(qdot(x, x));
   if (inv_norm) *inv_norm = s;
   return qscale(s, x);
 }
@@ -171,8 +186,7 @@ DMX_DEV bool chol(double* A) {
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= A[j * N + k] * A[j * N + k];
     ok = ok && (s > 0.0);
-    double d = sqrt(s > 0.0 ? s : 1e-300);
-    double inv = 1.0 / d;
+    const double inv = rsqrt_nr(s > 0.0 ? s : 1e-300);
     A[j * N + j] = inv;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
@@ -216,7 +230,7 @@ DMX_DEV bool chol_packed(double* P) {
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= P[tri(j, k)] * P[tri(j, k)];
     ok = ok && (s > 0.0);
-    const double inv = 1.0 / sqrt(s > 0.0 ? s : 1e-300);
+    const double inv = rsqrt_nr(s > 0.0 ? s : 1e-300);
     P[tri(j, j)] = inv;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {

@@ -29,6 +29,7 @@ struct PairF {
   double mu, bcoef, kscale, ahat;
   double si[5], cf[5];
   double ssc[4];  // spline scales 1/mid^(p-1), 1/(1-mid)^(p-1): penetration (0, 1) and CFD (2, 3)
+  double iwid[2]; // 1/width of the penetration and CFD splines
 };
 
 // Contact-pair constants and the slot -> (pair, capsule end) table, staged in
@@ -66,7 +67,7 @@ struct FreeModel {
   int np, nc, nu;
   int cpair[kMaxSlots], csub[kMaxSlots];
   int ctrl[8];
-  double mass, I[9], Iinv[9], grav[3];
+  double mass, imass, I[9], Iinv[9], grav[3];
   PairF pair[kMaxPairs];
 };
 
@@ -114,14 +115,14 @@ DMX_DEV double imp_spline(double x, double mid, double pw, double s_lo, double s
 DMX_DEV double impedance(const PairF& p, double r, double* ddr) {
   double dy;
   if (r < 0.0) {
-    double x = -r / p.si[2];
+    double x = -r * p.iwid[0];
     double y = imp_spline(x, p.si[3], p.si[4], p.ssc[0], p.ssc[1], &dy);
-    *ddr = -dy / p.si[2] * (p.si[1] - p.si[0]);
+    *ddr = -dy * p.iwid[0] * (p.si[1] - p.si[0]);
     return p.si[0] + y * (p.si[1] - p.si[0]);
   }
-  double x = r / p.cf[2];
+  double x = r * p.iwid[1];
   double y = imp_spline(x, p.cf[3], p.cf[4], p.ssc[2], p.ssc[3], &dy);
-  *ddr = dy / p.cf[2] * (p.cf[0] - p.cf[1]);
+  *ddr = dy * p.iwid[1] * (p.cf[0] - p.cf[1]);
   return p.cf[1] + y * (p.cf[0] - p.cf[1]);
 }
 
@@ -441,7 +442,7 @@ struct FreePhys {
     V3 gy = cross(w, Iw);
     double fa[3] = {tau[3] - gy.x, tau[4] - gy.y, tau[5] - gy.z};
 #pragma unroll
-    for (int i = 0; i < 3; ++i) a0[i] = tau[i] / m.mass + m.grav[i];
+    for (int i = 0; i < 3; ++i) a0[i] = tau[i] * m.imass + m.grav[i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) a0[3 + i] = m.Iinv[3 * i] * fa[0] + m.Iinv[3 * i + 1] * fa[1] + m.Iinv[3 * i + 2] * fa[2];
   }
@@ -524,17 +525,18 @@ struct FreePhys {
         dpt = -(pr.kscale * ddr * rw.r[k] + kk);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!((act[k] >> e) & 1u)) continue;
+      for (int e = 0; e < 4; ++e) {  // inactive edges enter with weight 0 (no branches)
+        const bool on = (act[k] >> e) & 1u;
         double Je[6];
         edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], mu, e, Je);
         double sl = dot6(Je, lam), sx = dot6(Je, xs);
-        double f = D * (rw.aref[k][e] - sx);
-        double Dbar = sl * (rw.aref[k][e] - sx);
-        double arb = D * sl;
+        const double De = on ? D : 0.0;
+        double f = De * (rw.aref[k][e] - sx);
+        double Dbar = on ? sl * (rw.aref[k][e] - sx) : 0.0;
+        double arb = De * sl;
         double Jeb[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) Jeb[i] = f * lam[i] - D * sl * xs[i] - pr.bcoef * arb * v[i];
+        for (int i = 0; i < 6; ++i) Jeb[i] = f * lam[i] - arb * xs[i] - pr.bcoef * arb * v[i];
 #pragma unroll
         for (int i = 0; i < 6; ++i) acc_[12 + i] += -pr.bcoef * arb * Je[i];
         rbar += arb * dpt + Dbar * dD;

@@ -79,6 +79,8 @@ void spline_scales(dmx::PairF& pr) {
   pr.ssc[1] = 1.0 / std::pow(1.0 - pr.si[3], pr.si[4] - 1.0);
   pr.ssc[2] = 1.0 / std::pow(pr.cf[3], pr.cf[4] - 1.0);
   pr.ssc[3] = 1.0 / std::pow(1.0 - pr.cf[3], pr.cf[4] - 1.0);
+  pr.iwid[0] = 1.0 / pr.si[2];
+  pr.iwid[1] = 1.0 / pr.cf[2];
 }
 
 void make_tangents(const double* n, double* t1, double* t2) {
@@ -292,6 +294,7 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
   double Ri[9];
   quat_to_mat(d->body_iner_quat, Ri);
   f.mass = mass;
+  f.imass = 1.0 / mass;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
       double s = 0.0;

@@ -383,13 +383,13 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
           double e = P::q_is_linear(i) ? eq[P::q_dof(i)] : Y[i] - qh[i];
-          double sc = o.atol + o.rtol * fmax(fabs(y[i]), fabs(Y[i]));
-          acc2 += (e / sc) * (e / sc);
+          const double r = e * rcp_nr(o.atol + o.rtol * fmax(fabs(y[i]), fabs(Y[i])));
+          acc2 += r * r;
         }
 #pragma unroll
         for (int d = 0; d < NV; ++d) {
-          double sc = o.atol + o.rtol * fmax(fabs(y[NQ + d]), fabs(Y[NQ + d]));
-          acc2 += (ev[d] / sc) * (ev[d] / sc);
+          const double r = ev[d] * rcp_nr(o.atol + o.rtol * fmax(fabs(y[NQ + d]), fabs(Y[NQ + d])));
+          acc2 += r * r;
         }
         err = sqrt(acc2 / NX);
       }
