@@ -233,10 +233,18 @@ DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, doubl
   const StageCoef k = stage_coef(i);
 #pragma unroll
   for (int d = 0; d < NV; ++d) {
+    // all six LDS reads issued together; entries of later stages (stale,
+    // possibly non-finite after a failed trial) are masked, not branched over
+    double av[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) av[l] = A[l][d];
     double sv = 0.0, sq = 0.0;
 #pragma unroll
-    for (int l = 0; l < 6; ++l)
-      if (l < i) { sv += k.a[l] * A[l][d]; sq += k.a2[l] * A[l][d]; }
+    for (int l = 0; l < 6; ++l) {
+      const double x = l < i ? av[l] : 0.0;
+      sv += k.a[l] * x;
+      sq += k.a2[l] * x;
+    }
     Y[NQ + d] = y[NQ + d] + h * sv;
     dq[d] = h * (k.c * y[NQ + d] + h * sq);
   }
@@ -249,12 +257,16 @@ template <class P>
 DMX_DEV void stage_distribute(int i, const double* Ybar, const double* dqb, double h, double* vb, double (*Ab)[P::NV]) {
   constexpr int NQ = P::NQ, NV = P::NV;
   const StageCoef k = stage_coef(i);
+  // a[i][l] = (A A)[i][l] = 0 for l >= i (explicit tableau): every entry is
+  // updated, without branches (the cotangents are finite)
 #pragma unroll
   for (int d = 0; d < NV; ++d) {
     vb[d] += Ybar[NQ + d] + h * k.c * dqb[d];
+    double ab[6];
 #pragma unroll
-    for (int l = 0; l < 6; ++l)
-      if (l < i) Ab[l][d] += h * k.a[l] * Ybar[NQ + d] + h * h * k.a2[l] * dqb[d];
+    for (int l = 0; l < 6; ++l) ab[l] = Ab[l][d];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) Ab[l][d] = ab[l] + (h * k.a[l] * Ybar[NQ + d] + h * h * k.a2[l] * dqb[d]);
   }
 }
 
