@@ -218,7 +218,7 @@ const KernelEntry kKernels[] = {
     FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(8, 16), FREE_ENTRY(16, 8),
     FREE_ENTRY(16, 16),
     // planar legged chain (7 joints, 5 bodies, 4 foot contact slots); 3-link test pendulum
-    TREE_ENTRY(7, 5, 4, 4), TREE_ENTRY(7, 5, 4, 8), TREE_ENTRY(4, 3, 1, 4),
+    TREE_ENTRY(7, 5, 4, 4), TREE_ENTRY(7, 5, 4, 8), TREE_ENTRY(7, 5, 4, 16), TREE_ENTRY(4, 3, 1, 4),
 };
 
 int bucket(int n) {
@@ -627,7 +627,7 @@ static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
 }
 
 // Kernel for a model and team size (lanes per world).  Default team: tree
-// worlds keep their kinematic workspace in LDS and take 4 lanes; free bodies
+// worlds keep their kinematic workspace in LDS and take 8 lanes; free bodies
 // take one contact slot per lane (up to 16).  Wider teams for small batches
 // (more wavefronts, fewer worlds per wavefront) measured slower on the cube
 // batch: the per-wavefront instruction stream is the same and the extra
@@ -635,7 +635,10 @@ static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
 static const KernelEntry* find_kernel(const dmx_model* m, int team) {
   if (team > 0) return lookup_kernel(m, team);
   if (const int t = m->tuned_team.load()) return lookup_kernel(m, t);
-  if (m->kind == 1) return lookup_kernel(m, 4);
+  if (m->kind == 1) {  // 8 lanes measured fastest on the legged chain (16384 worlds); 4 for small trees
+    if (const KernelEntry* k = lookup_kernel(m, 8)) return k;
+    return lookup_kernel(m, 4);
+  }
   return lookup_kernel(m, m->ncb >= 16 ? 16 : m->ncb);
 }
 
