@@ -352,6 +352,61 @@ def test_full_size_cube_sampled(D, oracle):
     assert ex.max() <= 1e-6 and eg.max() <= 1e-5
 
 
+def test_full_size_chain_sampled(D, oracle):
+    """The legged-chain configuration at full size (16384 worlds, 200
+    intervals of 10 ms, random torques; one persistent launch, default team):
+    every world finishes; the launch then replays, for 3 sampled worlds, the
+    oracle's step sequences, and the sampled end states match the oracle's and
+    the reverse sweep's x0/u cotangents match the oracle's forward-mode
+    derivatives along 16 sampled directions (x0 and u entries)."""
+    import torch
+    cfg = W.chain_walk(n_worlds=16384, n_intervals=200)
+    model = D.Model(cfg["model"])
+    x0, u, H, dt = cfg["x0"], cfg["u"], cfg["n_intervals"], cfg["interval_dt"]
+    res = D.rollout(model, _t(x0), _t(u), H, dt, tape=True, counters=True,
+                    opts=D.default_opts(tape_steps=40 * H + 64))
+    assert int(res["status"].abs().sum()) == 0
+    nacc = res["n_acc"].cpu().numpy()
+    recs_n = res["tape"].info()
+    del res
+    torch.cuda.empty_cache()
+    sample = [0, 8191, 16383]
+    om = oracle.Model(cfg["model"])
+    ref_tapes = [om.rollout(x0[w], u[w], H, dt, tape_cap=40 * H + 64) for w in sample]
+    cap = max(r["n_acc"] for r in ref_tapes)
+    forced = np.zeros((len(sample), cap, 2))
+    fn = np.zeros(len(sample))
+    for i, r in enumerate(ref_tapes):
+        forced[i, :r["n_acc"]] = r["tape"][:, :2]
+        fn[i] = r["n_acc"]
+    f_t, fn_t = _t(forced), _t(fn).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    xs, us = x0[sample], u[sample]
+    rep = D.rollout(model, _t(xs), _t(us), H, dt, tape=True, opts=o)
+    assert int(rep["status"].abs().sum()) == 0
+    rng = np.random.default_rng(17)
+    xbar = rng.normal(size=xs.shape)
+    gx, gu = D.rollout_vjp(rep["tape"], _t(xbar))
+    gx, gu = gx.cpu().numpy(), gu.cpu().numpy()
+    worst_s, worst_g = 0.0, 0.0
+    for i in range(len(sample)):
+        nd, nut = 16, H * model.nu
+        dx0 = np.zeros((nd, model.nx))
+        du = np.zeros((nd, nut))
+        for j in range(6):
+            dx0[j, rng.integers(model.nx)] = 1.0
+        for j in range(6, nd):
+            du[j, rng.integers(nut)] = 1.0
+        jv = om.rollout_jvp(xs[i], us[i], H, dt, dx0, du)
+        worst_s = max(worst_s, rel_state(rep["x"].cpu().numpy()[i], jv["x"], model.nq)[0])
+        lhs = jv["tx"] @ xbar[i]                        # <x_bar, J d>
+        rhs = dx0 @ gx[i] + du @ gu[i].reshape(-1)      # <J^T x_bar, d>
+        worst_g = max(worst_g, np.abs(lhs - rhs).max() / max(np.abs(lhs).max(), 1e-12))
+    print(f"chain 16384 x {H}: accepted steps mean {nacc.mean():.0f} max {nacc.max()}, tape {recs_n}; sampled "
+          f"replay state err {worst_s:.2e}, cotangent vs forward-mode directions {worst_g:.2e}")
+    assert worst_s <= 1e-6 and worst_g <= 1e-5
+
+
 # ------------------------------------------------------------------ articulated chain
 def _chain(n_worlds=4, n_int=6, z=0.535, seed=3):
     cfg = W.chain_walk(seed=seed, n_worlds=n_worlds, n_intervals=n_int)
