@@ -23,7 +23,8 @@ constexpr int kMaxSlots = 32;
 struct PairF {
   int gtype, ncon;
   double l[3];     // geom centre, body frame
-  double ax[3];    // capsule: half-length * axis, body frame
+  double ax[3];    // capsule: half-length * axis, body frame; box: half sizes
+  double gR[9];    // box: geom rotation in the body frame (row-major)
   double rad;
   double p0[3], n[3], t1[3], t2[3];  // world plane point, contact normal and tangents
   double mu, bcoef, kscale, ahat;
@@ -158,14 +159,86 @@ DMX_DEV double dot6(const double* a, const double* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
 }
 
-// Contact point of slot c: the sphere (or capsule end sphere) centre in the
-// world, signed distance to the plane and the midpoint between the surfaces.
+// Vertex k of a box pair in the body frame: centre + geom rotation * (+-h),
+// with the sign of coordinate x from bit 0 of k, y from bit 1, z from bit 2.
+DMX_DEV V3 box_vertex(const PairF& pr, int k) {
+  const V3 v = mk3((k & 1) ? pr.ax[0] : -pr.ax[0], (k & 2) ? pr.ax[1] : -pr.ax[1], (k & 4) ? pr.ax[2] : -pr.ax[2]);
+  const double* g = pr.gR;
+  return ld3(pr.l) + mk3(g[0] * v.x + g[1] * v.y + g[2] * v.z, g[3] * v.x + g[4] * v.y + g[5] * v.z,
+                         g[6] * v.x + g[7] * v.y + g[8] * v.z);
+}
+
+DMX_DEV double smoothstep01(double t, double* dt) {
+  if (t <= 0.0) { *dt = 0.0; return 0.0; }
+  if (t >= 1.0) { *dt = 0.0; return 1.0; }
+  *dt = 6.0 * t * (1.0 - t);
+  return t * t * (3.0 - 2.0 * t);
+}
+
+// Smoothed plane-box detection (App. D.1): vertex supports s_k below the
+// plane, a soft mask (C^1 smoothstep) keeping the vertices within a 1 mm skin
+// of the deepest one, the four largest masked supports in stable descending
+// order (ties to the lower vertex index), contact at the vertex moved to the
+// midpoint, r = -mask * s.  Slot `rank` takes the rank-th vertex.  For the
+// reverse sweep: dr/dg_k (g = height of the vertex above the plane) and
+// dr/dg_deepest through the skin threshold, with the deepest vertex.
+struct BoxSlot {
+  int k, kmax;
+  double r, drdg, drdgmax;
+};
+DMX_DEV BoxSlot box_plane_slot(const PairF& pr, V3 p, const M3& R, int rank) {
+  const V3 n = ld3(pr.n), p0 = ld3(pr.p0);
+  double sup[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sup[k] = -dot(n, p + mul(R, box_vertex(pr, k)) - p0);
+  int kmax = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) kmax = sup[k] > sup[kmax] ? k : kmax;
+  const bool thr_on = sup[kmax] - 1e-3 > 0.0;
+  const double thr = thr_on ? sup[kmax] - 1e-3 : 0.0;
+  const double lo = thr - 1e-3, wdt = thr - lo;
+  double sm[8], msk[8], dmsk[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    msk[k] = smoothstep01((sup[k] - lo) / wdt, &dmsk[k]);
+    sm[k] = msk[k] * sup[k];
+  }
+  BoxSlot b{0, kmax, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int rk = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rk += (sm[j] > sm[k]) || (j < k && sm[j] == sm[k]);
+    if (rk == rank) b.k = k;
+  }
+  // r = -m(u) s with u = (s - lo) / w, s = -g, lo = thr - 1e-3, thr = s_max - 1e-3
+  double sk = 0.0, mk = 0.0, dk = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k == b.k) { sk = sup[k]; mk = msk[k]; dk = dmsk[k]; }
+  b.r = -sm[b.k];
+  b.drdg = mk + sk * dk / wdt;             // d(-m s)/ds * ds/dg, ds/dg = -1
+  b.drdgmax = thr_on ? -sk * dk / wdt : 0.0;  // via thr: du/dthr = -1/w, dthr/dg_max = -1
+  return b;
+}
+
+// Contact point of slot c: the sphere (or capsule end sphere) centre, or the
+// selected box vertex, in the world; signed distance to the plane and the
+// midpoint between the surfaces.
 DMX_DEV void slot_geom(const FreeModel& m, int c, V3 p, const M3& R, V3* lc, V3* ctr, double* r, V3* P) {
   const PairF& pr = slot_pair(c);
+  const V3 n = ld3(pr.n);
+  if (pr.gtype == 3) {
+    const BoxSlot b = box_plane_slot(pr, p, R, slot_sub(c));
+    *lc = box_vertex(pr, b.k);
+    *ctr = p + mul(R, *lc);
+    *r = b.r;
+    *P = *ctr - (0.5 * b.r) * n;
+    return;
+  }
   V3 l = ld3(pr.l);
   if (pr.gtype == 2) l = (slot_sub(c) == 0) ? l + ld3(pr.ax) : l - ld3(pr.ax);
   V3 ce = p + mul(R, l);
-  V3 n = ld3(pr.n);
   double rr = dot(n, ce - ld3(pr.p0)) - pr.rad;
   *lc = l;
   *ctr = ce;
@@ -568,16 +641,26 @@ struct FreePhys {
         for (int i = 0; i < 9; ++i) acc_[3 + i] += Rb.a[i];
         db += cross(u, zb);
       }
-      // d = P - p; P = ce - (rad + r/2) n; r = n.(ce - p0) - rad; ce = p + R lc
+      // d = P - p; P = ce - (rad + r/2) n; r = n.(ce - p0) - rad (sphere,
+      // capsule end) or r = r(g_k, g_deepest) with g = n.(ce - p0) (box
+      // vertex); ce = p + R lc
       V3 n = ld3(pr.n);
       V3 Pb = db;
       V3 pb = mk3(-db.x, -db.y, -db.z);
       rbar += -0.5 * dot(n, Pb);
-      V3 ceb = Pb + rbar * n;
-      pb += ceb;
+      double gbar = rbar;
       M3 Rb2;
 #pragma unroll
       for (int i = 0; i < 9; ++i) Rb2.a[i] = 0.0;
+      if (pr.gtype == 3) {
+        const BoxSlot bs = box_plane_slot(pr, p, R, slot_sub(rw.slot[k]));
+        gbar = rbar * bs.drdg;
+        const V3 cm = (rbar * bs.drdgmax) * n;  // the deepest vertex, through the skin threshold
+        pb += cm;
+        outer_add(Rb2, cm, box_vertex(pr, bs.kmax));
+      }
+      V3 ceb = Pb + gbar * n;
+      pb += ceb;
       outer_add(Rb2, ceb, lc);
       acc_[0] += pb.x; acc_[1] += pb.y; acc_[2] += pb.z;
 #pragma unroll

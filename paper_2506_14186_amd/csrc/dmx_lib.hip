@@ -329,24 +329,25 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
       return fail(DMX_ERR_UNSUPPORTED, "pairs must be (world plane, body geom)");
     }
     const int t2 = d->geom_type[g2];
-    if (t2 != DMX_GEOM_SPHERE && t2 != DMX_GEOM_CAPSULE) {
+    if (t2 != DMX_GEOM_SPHERE && t2 != DMX_GEOM_CAPSULE && t2 != DMX_GEOM_BOX) {
       delete m;
-      return fail(DMX_ERR_UNSUPPORTED, "plane pairs with sphere or capsule geoms only in this build");
+      return fail(DMX_ERR_UNSUPPORTED, "plane pairs with sphere, capsule or box geoms only in this build");
     }
     dmx::PairF& pr = f.pair[p];
     pr.gtype = t2;
-    pr.ncon = (t2 == DMX_GEOM_CAPSULE) ? 2 : 1;
+    pr.ncon = (t2 == DMX_GEOM_CAPSULE) ? 2 : (t2 == DMX_GEOM_BOX) ? 4 : 1;
     double Rg[9], Rp[9];
     quat_to_mat(&d->geom_quat[4 * g2], Rg);
     quat_to_mat(&d->geom_quat[4 * g1], Rp);
+    for (int i = 0; i < 9; ++i) pr.gR[i] = Rg[i];
     for (int i = 0; i < 3; ++i) {
       pr.l[i] = d->geom_pos[3 * g2 + i];
-      pr.ax[i] = Rg[i * 3 + 2] * d->geom_size[3 * g2 + 1];
+      pr.ax[i] = (t2 == DMX_GEOM_BOX) ? d->geom_size[3 * g2 + i] : Rg[i * 3 + 2] * d->geom_size[3 * g2 + 1];
       pr.p0[i] = d->geom_pos[3 * g1 + i];
       pr.n[i] = Rp[i * 3 + 2];
     }
     make_tangents(pr.n, pr.t1, pr.t2);
-    pr.rad = d->geom_size[3 * g2];
+    pr.rad = (t2 == DMX_GEOM_BOX) ? 0.0 : d->geom_size[3 * g2];
     pr.mu = d->pair_mu[p];
     const double tc = d->pair_solref[2 * p], dr = d->pair_solref[2 * p + 1];
     for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }

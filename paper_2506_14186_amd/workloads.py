@@ -106,6 +106,22 @@ def model_cube_corners(half=0.1, mass=1.0, corner_radius=0.01, mu=0.8, tc=0.001,
     }
 
 
+def model_box(half=0.1, mass=1.0, mu=0.8, tc=0.001, solimp=None, ctrl=False):
+    """Free cube (one stack level) whose contacts come from a box geom against
+    the plane (the smoothed plane-box detection: four deepest vertices)."""
+    return {
+        "name": "box",
+        "gravity": list(GRAVITY),
+        "bodies": [{"parent": -1, "pos": [0.0, 0.0, 0.0], "quat": [1.0, 0.0, 0.0, 0.0],
+                    "inertial": {"type": "box", "size": [half, half, half], "mass": mass},
+                    "joints": [{"type": "free", "axis": [0.0, 0.0, 1.0], "pos": [0.0, 0.0, 0.0]}]}],
+        "geoms": [_plane(), {"body": 0, "type": "box", "size": [half, half, half], "pos": [0.0, 0.0, 0.0],
+                             "quat": [1.0, 0.0, 0.0, 0.0]}],
+        "pairs": [_pair(0, 1, mu, tc, solimp)],
+        "ctrl": {"dofs": [0, 1, 2, 3, 4, 5] if ctrl else []},
+    }
+
+
 def model_chain(link_half=0.125, radius=0.03, mu=1.0, tc=0.002, solimp=None):
     """Planar legged chain: a horizontal torso capsule with a planar root
     (slide x, slide z, hinge y) and two legs (thigh + shin capsules, hinge y at
@@ -235,6 +251,20 @@ def cube_toss(seed=2, n_worlds=4096, horizon=0.5):
             "interval_dt": float(horizon)}
 
 
+def box_toss(seed=4, n_worlds=1024, horizon=1.0, mu=0.6, tc=0.003):
+    """Single free cubes (edge 0.2 m, 1 kg) with a box geom on a plane: the
+    one-level stacks of the stack workload; random orientation, height U(0.2,
+    0.6) m, velocity N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    m = model_box(mu=mu, tc=tc)
+    x0 = np.zeros((n_worlds, 13))
+    x0[:, 2] = rng.uniform(0.2, 0.6, size=n_worlds)
+    x0[:, 3:7] = uniform_quat(rng, n_worlds)
+    x0[:, 7:13] = rng.normal(0.0, 1.0, size=(n_worlds, 6))
+    return {"model": m, "x0": x0, "u": np.zeros((n_worlds, 1, 0)), "n_intervals": 1,
+            "interval_dt": float(horizon)}
+
+
 def chain_walk(seed=3, n_worlds=16384, n_intervals=200, interval_dt=0.01):
     """Planar legged chain, torso at 0.55 m, legs vertical, at rest; hinge torques
     piecewise constant U(-1, 1) N m over ``n_intervals`` of ``interval_dt``."""
@@ -250,4 +280,5 @@ CONFIGS = {
     "sphere_drop": sphere_drop,
     "cube_toss": cube_toss,
     "chain_walk": chain_walk,
+    "box_toss": box_toss,
 }

@@ -57,13 +57,20 @@ def _cube_batch(n, horizon=0.5, seed=2):
     return cfg["model"], cfg["x0"], 1, horizon
 
 
-CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4]), "cube": lambda: _cube_batch(6)}
-FREE_CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4, 5, 6]), "cube": lambda: _cube_batch(16)}
+def _box_batch(n, horizon=0.5, seed=4):
+    cfg = W.box_toss(seed=seed, n_worlds=n, horizon=horizon)
+    return cfg["model"], cfg["x0"], 1, horizon
 
 
-def test_accel_parity(D, oracle):
+CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4]), "cube": lambda: _cube_batch(6), "box": lambda: _box_batch(6)}
+FREE_CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4, 5, 6]), "cube": lambda: _cube_batch(16),
+              "box": lambda: _box_batch(16)}
+
+
+@pytest.mark.parametrize("case", ["cube", "box"])
+def test_accel_parity(D, oracle, case):
     """F(x) at states along oracle trajectories (contacts on and off)."""
-    desc, x0, n_int, dt = _cube_batch(6)
+    desc, x0, n_int, dt = _cube_batch(6) if case == "cube" else _box_batch(6)
     om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
     ys = np.vstack([r["tape"][:, 2:] for r in tapes])
     model = D.Model(desc)
@@ -72,7 +79,7 @@ def test_accel_parity(D, oracle):
     ref = np.stack([om.rhs(y)[0][6:] for y in ys])
     err = np.linalg.norm(acc.cpu().numpy() - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-3)
     nc = sum(om.rhs(y)[1]["n_rows"] > 0 for y in ys)
-    print(f"accel: {len(ys)} states ({nc} in contact), max rel err {err.max():.3e}")
+    print(f"{case} accel: {len(ys)} states ({nc} in contact), max rel err {err.max():.3e}")
     assert err.max() <= 1e-10
 
 
@@ -186,10 +193,11 @@ def test_free_run_full_horizon(D, oracle, levels):
         assert ex[same].max() <= 1e-6
 
 
-def test_replayed_gradient_matches_oracle_tightly(D, oracle):
+@pytest.mark.parametrize("case", ["cube", "box"])
+def test_replayed_gradient_matches_oracle_tightly(D, oracle, case):
     """Same step sequence on both sides: the reverse sweep equals the
     forward-mode derivative of the oracle to rounding."""
-    desc, x0, n_int, dt = _cube_batch(4, horizon=0.3)
+    desc, x0, n_int, dt = _cube_batch(4, horizon=0.3) if case == "cube" else _box_batch(4, horizon=0.6)
     om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
     model = D.Model(desc)
     cap = max(r["n_acc"] for r in tapes)
@@ -206,7 +214,7 @@ def test_replayed_gradient_matches_oracle_tightly(D, oracle):
     g, _ = D.rollout_vjp(res["tape"], _t(xbar))
     ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=4)
     eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
-    print(f"replayed-sequence gradient rel err {eg.max():.3e}")
+    print(f"{case}: replayed-sequence gradient rel err {eg.max():.3e}")
     assert eg.max() <= 1e-8
 
 
