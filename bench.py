@@ -77,12 +77,14 @@ def algorithmic_flops(counters, table, nc):
 
 def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
     """MPC requests arriving as a Poisson stream: each picks the controlled
-    cube or the legged chain, N ~ U{16..256} candidate control sequences
+    corner-sphere cube, the legged chain or the box-geom cube (the one-level
+    stack), N ~ U{16..256} candidate control sequences
     u ~ U(-1, 1) over H ~ U{50..500} intervals of 10 ms, and asks for the
     candidates' costs and control gradients.  Latency = completion - arrival
     (submission happens at the arrival time)."""
     rng = np.random.default_rng(seed)
-    models = {"cube": D.Model(W.model_cube_corners(ctrl=True)), "chain": D.Model(W.model_chain())}
+    models = {"cube": D.Model(W.model_cube_corners(ctrl=True)), "chain": D.Model(W.model_chain()),
+              "box": D.Model(W.model_box(ctrl=True, mu=0.6, tc=0.003))}
     chain_x0 = W.chain_walk(n_worlds=1, n_intervals=1)["x0"][0]
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 2) + 16))
     arrivals = arrivals[arrivals < seconds]
@@ -96,11 +98,13 @@ def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
         while nxt < len(arrivals) or pending:
             now = time.perf_counter() - t0
             while nxt < len(arrivals) and arrivals[nxt] <= now:
-                kind = "cube" if rng.random() < 0.5 else "chain"
+                kind = ("cube", "chain", "box")[int(rng.integers(3))]
                 m = models[kind]
                 N, H = int(rng.integers(16, 257)), int(rng.integers(50, 501))
                 if kind == "cube":
                     x0 = W.cube_toss(seed=int(rng.integers(1 << 30)), n_worlds=1, horizon=0.1)["x0"][0]
+                elif kind == "box":
+                    x0 = W.box_toss(seed=int(rng.integers(1 << 30)), n_worlds=1, horizon=0.1)["x0"][0]
                 else:
                     x0 = chain_x0
                 u = rng.uniform(-1.0, 1.0, size=(N, H, m.nu))
@@ -133,7 +137,7 @@ def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
             "served_req_per_s": round(len(done_kinds) / elapsed, 2) if elapsed > 0 else None,
             "served_world_sim_s_per_s": round(work / elapsed, 1) if elapsed > 0 else None,
             "backlog_at_window_end": int(backlog_at_end),
-            "mix": {"cube": done_kinds.count("cube"), "chain": done_kinds.count("chain")},
+            "mix": {k: done_kinds.count(k) for k in ("cube", "chain", "box")},
             "requests_shape": "N~U{16..256} candidates, H~U{50..500} x 10 ms, cost+control gradient"}
 
 
