@@ -149,12 +149,6 @@ struct FreeRows {
   double aref[CPL][4];
 };
 
-DMX_DEV void edge_row(const double* Jn, const double* Jt1, const double* Jt2, double mu, int e, double* Je) {
-  const double* Jt = (e < 2) ? Jt1 : Jt2;
-  double s = (e & 1) ? -mu : mu;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) Je[i] = Jn[i] + s * Jt[i];
-}
 DMX_DEV double dot6(const double* a, const double* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
 }
@@ -300,7 +294,11 @@ DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
 }
 
 // H = M + sum over this team's active edges of D J_e J_e^T, packed lower
-// triangle (21 entries).  Inactive edges enter with weight 0 (no branches).
+// triangle (21 entries).  With J_e = J_n + s_e J_t(e), s = (mu, -mu, mu, -mu)
+// on (J_t1, J_t1, J_t2, J_t2), a contact's four edges sum to
+//   w_nn J_n J_n^T + w_n1 (J_n J_t1^T + J_t1 J_n^T) + w_n2 (J_n J_t2^T + J_t2 J_n^T)
+//   + w_11 J_t1 J_t1^T + w_22 J_t2 J_t2^T
+// with the weights below (an inactive edge has weight 0).
 template <int CPL, int L>
 DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
 #pragma unroll
@@ -308,17 +306,23 @@ DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uin
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     if (act[k] == 0u) continue;
+    const double D = rw.D[k], mu = rw.mu[k];
+    double o[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double D = ((act[k] >> e) & 1u) ? rw.D[k] : 0.0;
-      double Je[6];
-      edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
+    for (int e = 0; e < 4; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
+    const double w11 = o[0] + o[1], w22 = o[2] + o[3];
+    const double wnn = w11 + w22, wn1 = mu * (o[0] - o[1]), wn2 = mu * (o[2] - o[3]);
+    const double mm = mu * mu;
+    const double* Jn = rw.Jn[k];
+    const double* J1 = rw.Jt1[k];
+    const double* J2 = rw.Jt2[k];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const double di = D * Je[i];
+    for (int i = 0; i < 6; ++i) {
+      const double ui = wnn * Jn[i] + wn1 * J1[i] + wn2 * J2[i];
+      const double vi = wn1 * Jn[i] + mm * w11 * J1[i];
+      const double zi = wn2 * Jn[i] + mm * w22 * J2[i];
 #pragma unroll
-        for (int j = 0; j <= i; ++j) hp[tri(i, j)] += di * Je[j];
-      }
+      for (int j = 0; j <= i; ++j) hp[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
     }
   }
   team_sum_arr<L, 21>(hp);
@@ -582,8 +586,10 @@ struct FreePhys {
     for (int k = 0; k < CPL; ++k) {
       if (!rw.on[k] || act[k] == 0u) continue;
       const PairF& pr = slot_pair(rw.slot[k]);
-      double mu = rw.mu[k], D = rw.D[k];
-      double Jbn[6] = {0, 0, 0, 0, 0, 0}, Jb1[6] = {0, 0, 0, 0, 0, 0}, Jb2[6] = {0, 0, 0, 0, 0, 0};
+      const double mu = rw.mu[k], D = rw.D[k];
+      const double* Jn = rw.Jn[k];
+      const double* J1 = rw.Jt1[k];
+      const double* J2 = rw.Jt2[k];
       double rbar = 0.0;
       double ddr;
       double dimp = impedance(pr, rw.r[k], &ddr);
@@ -597,26 +603,35 @@ struct FreePhys {
       } else {
         dpt = -(pr.kscale * ddr * rw.r[k] + kk);
       }
+      // Per edge e (J_e = J_n + s_e J_t(e), force f_e = D (aref_e - J_e x)):
+      // J_e_bar = f_e lam - arb_e (x + bcoef v) with arb_e = D J_e lam, and
+      // v_bar -= bcoef arb_e J_e.  Summed over the four edges these become
+      // combinations of the three frame rows (inactive edges weigh 0).
+      const double ln = dot6(Jn, lam), l1 = dot6(J1, lam), l2 = dot6(J2, lam);
+      const double xn = dot6(Jn, xs), x1 = dot6(J1, xs), x2 = dot6(J2, xs);
+      double fe[4], ae[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {  // inactive edges enter with weight 0 (no branches)
+      for (int e = 0; e < 4; ++e) {
         const bool on = (act[k] >> e) & 1u;
-        double Je[6];
-        edge_row(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], mu, e, Je);
-        double sl = dot6(Je, lam), sx = dot6(Je, xs);
+        const double sg = (e & 1) ? -mu : mu;
+        const double sl = ln + sg * (e < 2 ? l1 : l2), sx = xn + sg * (e < 2 ? x1 : x2);
         const double De = on ? D : 0.0;
-        double f = De * (rw.aref[k][e] - sx);
-        double Dbar = on ? sl * (rw.aref[k][e] - sx) : 0.0;
-        double arb = De * sl;
-        double Jeb[6];
+        const double gap = rw.aref[k][e] - sx;
+        fe[e] = De * gap;
+        ae[e] = De * sl;
+        const double Dbar = on ? sl * gap : 0.0;
+        rbar += ae[e] * dpt + Dbar * dD;
+      }
+      const double Fn = (fe[0] + fe[1]) + (fe[2] + fe[3]), F1 = mu * (fe[0] - fe[1]), F2 = mu * (fe[2] - fe[3]);
+      const double An = (ae[0] + ae[1]) + (ae[2] + ae[3]), A1 = mu * (ae[0] - ae[1]), A2 = mu * (ae[2] - ae[3]);
+      double Jbn[6], Jb1[6], Jb2[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) Jeb[i] = f * lam[i] - arb * xs[i] - pr.bcoef * arb * v[i];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) acc_[12 + i] += -pr.bcoef * arb * Je[i];
-        rbar += arb * dpt + Dbar * dD;
-        double sg = (e & 1) ? -mu : mu;
-        double* Jbt = (e < 2) ? Jb1 : Jb2;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) { Jbn[i] += Jeb[i]; Jbt[i] += sg * Jeb[i]; }
+      for (int i = 0; i < 6; ++i) {
+        const double z = xs[i] + pr.bcoef * v[i];
+        Jbn[i] = Fn * lam[i] - An * z;
+        Jb1[i] = F1 * lam[i] - A1 * z;
+        Jb2[i] = F2 * lam[i] - A2 * z;
+        acc_[12 + i] -= pr.bcoef * (An * Jn[i] + A1 * J1[i] + A2 * J2[i]);
       }
       // J_u = [u, R^T (d x u)]: angular part back to d and R
       V3 lc, ce, P;

@@ -316,6 +316,8 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
   double tau[NV];
   Stat st{};
   double t = 0.0, hprop = quantize_step(fmin(o.h0, a.dt), o.h_levels), eprev = 1.0;
+  // eprev^(kP / order), updated with eprev (one pow per accepted step)
+  double eprev_pow = 1.0;
   long long attempts = 0;
   int nacc = 0, nrej = 0, fi = 0, nlog = 0;
   const int nforced = a.forced ? min(a.forced_n[w], a.forced_cap) : 0;
@@ -413,7 +415,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
       }
       const bool accept = a.forced ? true : (err <= 1.0);
       const double et = isfinite(err) ? fmax(err, o.err_floor) : 1e300;
-      double fac = o.safety * pow(et, -(o.kP + o.kI) / o.err_order) * pow(eprev, o.kP / o.err_order);
+      double fac = o.safety * pow(et, -(o.kP + o.kI) / o.err_order) * eprev_pow;
       fac = fmin(o.facmax, fmax(o.facmin, fac));
       if (a.steplog && nlog < a.log_cap && tl == 0) {
         double* lg = a.steplog + ((size_t)w * a.log_cap + nlog) * 4;
@@ -439,6 +441,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
         for (int d = 0; d < NV; ++d) A[0][d] = A[6][d];
         t = landing ? tend : t + h;
         eprev = et;
+        eprev_pow = pow(et, o.kP / o.err_order);
         hprop = quantize_step(fac * h, o.h_levels);
         ++nacc;
         bool fin = true;

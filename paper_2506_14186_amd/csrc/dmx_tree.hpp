@@ -289,14 +289,6 @@ DMX_DEV void tree_rows(const TreeModel& m, const TreeWs<NV, NB>& ws, const doubl
   }
 }
 
-template <int NV>
-DMX_DEV void tree_edge(const double* Jn, const double* Jt1, const double* Jt2, double mu, int e, double* Je) {
-  const double* Jt = (e < 2) ? Jt1 : Jt2;
-  const double s = (e & 1) ? -mu : mu;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) Je[i] = Jn[i] + s * Jt[i];
-}
-
 template <int NV, int CPL>
 DMX_DEV void tree_active(const TreeRows<NV, CPL>& rw, const double* x, uint32_t* act, double (*s)[4]) {
 #pragma unroll
@@ -324,17 +316,25 @@ DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const ui
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     if (act[k] == 0u) continue;
+    // the four edges J_n + s_e J_t(e) as combinations of the three frame
+    // rows (the free-body Hessian uses the same expansion)
+    const double D = rw.D[k], mu = rw.mu[k];
+    double o[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double D = ((act[k] >> e) & 1u) ? rw.D[k] : 0.0;
-      double Je[NV];
-      tree_edge<NV>(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], rw.mu[k], e, Je);
+    for (int e = 0; e < 4; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
+    const double w11 = o[0] + o[1], w22 = o[2] + o[3];
+    const double wnn = w11 + w22, wn1 = mu * (o[0] - o[1]), wn2 = mu * (o[2] - o[3]);
+    const double mm = mu * mu;
+    const double* Jn = rw.Jn[k];
+    const double* J1 = rw.Jt1[k];
+    const double* J2 = rw.Jt2[k];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const double di = D * Je[i];
+    for (int i = 0; i < NV; ++i) {
+      const double ui = wnn * Jn[i] + wn1 * J1[i] + wn2 * J2[i];
+      const double vi = wn1 * Jn[i] + mm * w11 * J1[i];
+      const double zi = wn2 * Jn[i] + mm * w22 * J2[i];
 #pragma unroll
-        for (int j = 0; j <= i; ++j) H[tri(i, j)] += di * Je[j];
-      }
+      for (int j = 0; j <= i; ++j) H[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
     }
   }
   team_sum_arr<L, NT>(H);
@@ -580,9 +580,6 @@ struct TreePhys {
       if (!rw.on[k] || act[k] == 0u) continue;
       const PairF& pr = slot_pair(rw.slot[k]);
       const double mu = rw.mu[k], D = rw.D[k];
-      double Jbn[NV], Jb1[NV], Jb2[NV];
-#pragma unroll
-      for (int i = 0; i < NV; ++i) { Jbn[i] = 0.0; Jb1[i] = 0.0; Jb2[i] = 0.0; }
       double rbar = 0.0, ddr;
       const double dimp = impedance(pr, rw.r[k], &ddr);
       const double dD = ddr / (pr.ahat * (1.0 - dimp) * (1.0 - dimp));
@@ -590,25 +587,36 @@ struct TreePhys {
       double dpt;
       if (cfd) { double dsp; const double sp = softplus(-rw.r[k], beta, &dsp); dpt = pr.kscale * ddr * sp - kk * dsp; }
       else dpt = -(pr.kscale * ddr * rw.r[k] + kk);
+      // per-edge reverse summed over the four edges as combinations of the
+      // three frame rows (as in the free-body reverse; inactive edges weigh 0)
+      const double* Jn = rw.Jn[k];
+      const double* J1 = rw.Jt1[k];
+      const double* J2 = rw.Jt2[k];
+      const double ln = dotn<NV>(Jn, lam), l1 = dotn<NV>(J1, lam), l2 = dotn<NV>(J2, lam);
+      const double xn = dotn<NV>(Jn, xs), x1 = dotn<NV>(J1, xs), x2 = dotn<NV>(J2, xs);
+      double fe[4], ae[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (!((act[k] >> e) & 1u)) continue;
-        double Je[NV];
-        tree_edge<NV>(rw.Jn[k], rw.Jt1[k], rw.Jt2[k], mu, e, Je);
-        const double sl = dotn<NV>(Je, lam), sx = dotn<NV>(Je, xs);
-        const double f = D * (rw.aref[k][e] - sx);
-        const double Dbar = sl * (rw.aref[k][e] - sx);
-        const double arb = D * sl;
-        double Jeb[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) Jeb[i] = f * lam[i] - D * sl * xs[i] - pr.bcoef * arb * v[i];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) vb[i] += -pr.bcoef * arb * Je[i];
-        rbar += arb * dpt + Dbar * dD;
+        const bool on = (act[k] >> e) & 1u;
         const double sg = (e & 1) ? -mu : mu;
-        double* Jbt = (e < 2) ? Jb1 : Jb2;
+        const double sl = ln + sg * (e < 2 ? l1 : l2), sx = xn + sg * (e < 2 ? x1 : x2);
+        const double De = on ? D : 0.0;
+        const double gap = rw.aref[k][e] - sx;
+        fe[e] = De * gap;
+        ae[e] = De * sl;
+        const double Dbar = on ? sl * gap : 0.0;
+        rbar += ae[e] * dpt + Dbar * dD;
+      }
+      const double Fn = (fe[0] + fe[1]) + (fe[2] + fe[3]), F1 = mu * (fe[0] - fe[1]), F2 = mu * (fe[2] - fe[3]);
+      const double An = (ae[0] + ae[1]) + (ae[2] + ae[3]), A1 = mu * (ae[0] - ae[1]), A2 = mu * (ae[2] - ae[3]);
+      double Jbn[NV], Jb1[NV], Jb2[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) { Jbn[i] += Jeb[i]; Jbt[i] += sg * Jeb[i]; }
+      for (int i = 0; i < NV; ++i) {
+        const double z = xs[i] + pr.bcoef * v[i];
+        Jbn[i] = Fn * lam[i] - An * z;
+        Jb1[i] = F1 * lam[i] - A1 * z;
+        Jb2[i] = F2 * lam[i] - A2 * z;
+        vb[i] -= pr.bcoef * (An * Jn[i] + A1 * J1[i] + A2 * J2[i]);
       }
       // J_u[d] = u . (a_d x (P - o_d)) (hinge) or u . a_d (slide)
       const int b = rw.body[k];
