@@ -135,11 +135,13 @@ DMX_DEV Q4 qexp_half(V3 th, double* cs, double* sn, double* dcs, double* dsn) {
 }
 
 // ----------------------------------------------------------------- team ops
+// Lane permutation within rows of 16 (quad_perm, row_half_mirror,
+// row_mirror): every lane reads a valid lane, so no old value is needed.
 template <int CTRL>
 DMX_DEV double dpp_f64(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -155,10 +157,30 @@ DMX_DEV double team_sum(double v) {
   return v;
 }
 
+// N independent team sums, level by level (the N butterflies interleave
+// instead of running one after another); each result equals team_sum's.
+template <int CTRL, int N>
+DMX_DEV void butterfly_level(double* v) {
+  double t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = dpp_f64<CTRL>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += t[i];
+}
 template <int L, int N>
 DMX_DEV void team_sum_arr(double* v) {
+  if constexpr (L >= 2) butterfly_level<0xB1, N>(v);
+  if constexpr (L >= 4) butterfly_level<0x4E, N>(v);
+  if constexpr (L >= 8) butterfly_level<0x141, N>(v);
+  if constexpr (L >= 16) butterfly_level<0x140, N>(v);
+  if constexpr (L >= 32) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = team_sum<L>(v[i]);
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 16, 64);
+  }
+  if constexpr (L >= 64) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], 32, 64);
+  }
 }
 
 // Team-wide boolean reductions through the wave ballot.
