@@ -299,8 +299,9 @@ DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
 //   w_nn J_n J_n^T + w_n1 (J_n J_t1^T + J_t1 J_n^T) + w_n2 (J_n J_t2^T + J_t2 J_n^T)
 //   + w_11 J_t1 J_t1^T + w_22 J_t2 J_t2^T
 // with the weights below (an inactive edge has weight 0).
-template <int CPL, int L>
-DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
+// This lane's share (its own slots) of the contact part, before the team sum.
+template <int CPL>
+DMX_DEV void free_hessian_lane(const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
 #pragma unroll
   for (int i = 0; i < 21; ++i) hp[i] = 0.0;
 #pragma unroll
@@ -325,12 +326,19 @@ DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uin
       for (int j = 0; j <= i; ++j) hp[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
     }
   }
-  team_sum_arr<L, 21>(hp);
+}
+DMX_DEV void free_add_mass(const FreeModel& m, double* hp) {
   hp[tri(0, 0)] += m.mass; hp[tri(1, 1)] += m.mass; hp[tri(2, 2)] += m.mass;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j <= i; ++j) hp[tri(3 + i, 3 + j)] += m.I[i * 3 + j];
+}
+template <int CPL, int L>
+DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
+  free_hessian_lane<CPL>(rw, act, hp);
+  team_sum_arr<L, 21>(hp);
+  free_add_mass(m, hp);
 }
 
 // Active edges at x: bit e of act[k] set iff J_e x - a_ref_e < 0.
@@ -392,8 +400,12 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
       st.u_ncon += (act[k] != 0u);
       st.u_nedge += __popc(act[k]);
     }
-    // gradient and Hessian of the active set
-    double gp[6] = {0, 0, 0, 0, 0, 0};
+    // gradient and Hessian of the active set, summed over the team together
+    double gh[27];
+    double* gp = gh;
+    double* H = gh + 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gp[i] = 0.0;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
       if (act[k] == 0u) continue;
@@ -406,13 +418,13 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
 #pragma unroll
       for (int i = 0; i < 6; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
     }
-    team_sum_arr<L, 6>(gp);
+    free_hessian_lane<CPL>(rw, act, H);
+    team_sum_arr<L, 27>(gh);
+    free_add_mass(m, H);
     double dx[6], Mdx[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) dx[i] = x[i] - a0[i];
     free_Mmul(m, dx, Mdx);
-    double H[21];
-    free_hessian<CPL, L>(m, rw, act, H);
     if (!chol_packed<6>(H)) { st.status |= 4; return; }
     double dl[6];
 #pragma unroll
@@ -470,8 +482,10 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
           c1 += dt * s[k][e];
         }
       }
-      c1 = team_sum<L>(c1) + xMd;
-      c2 = team_sum<L>(c2) + dMd;
+      double cc[2] = {c1, c2};
+      team_sum_arr<L, 2>(cc);
+      c1 = cc[0] + xMd;
+      c2 = cc[1] + dMd;
       double dphi = a * c2 + c1;
       if (dphi > 0.0) hi = a; else lo = a;
       double an = (c2 > 0.0) ? -c1 / c2 : a;

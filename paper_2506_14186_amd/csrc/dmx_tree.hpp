@@ -308,8 +308,9 @@ DMX_DEV void tree_active(const TreeRows<NV, CPL>& rw, const double* x, uint32_t*
 
 // H = M + sum over active edges of D J_e J_e^T (packed, team-summed;
 // inactive edges enter with weight 0)
-template <int NV, int CPL, int L>
-DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
+// This lane's share (its own slots) of the contact part, before the team sum.
+template <int NV, int CPL>
+DMX_DEV void tree_hessian_lane(const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
   constexpr int NT = NV * (NV + 1) / 2;
 #pragma unroll
   for (int i = 0; i < NT; ++i) H[i] = 0.0;
@@ -337,6 +338,11 @@ DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const ui
       for (int j = 0; j <= i; ++j) H[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
     }
   }
+}
+template <int NV, int CPL, int L>
+DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
+  constexpr int NT = NV * (NV + 1) / 2;
+  tree_hessian_lane<NV, CPL>(rw, act, H);
   team_sum_arr<L, NT>(H);
 #pragma unroll
   for (int i = 0; i < NT; ++i) H[i] += M[i];
@@ -373,7 +379,11 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     if (team_leader(L)) st.u_nit++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_ncon += (act[k] != 0u); st.u_nedge += __popc(act[k]); }
-    double gp[NV];
+    // gradient and Hessian of the active set, summed over the team together
+    constexpr int NT = NV * (NV + 1) / 2;
+    double gh[NV + NT];
+    double* gp = gh;
+    double* H = gh + NV;
 #pragma unroll
     for (int i = 0; i < NV; ++i) gp[i] = 0.0;
 #pragma unroll
@@ -388,15 +398,16 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
 #pragma unroll
       for (int i = 0; i < NV; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
     }
-    team_sum_arr<L, NV>(gp);
+    tree_hessian_lane<NV, CPL>(rw, act, H);
+    team_sum_arr<L, NV + NT>(gh);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) H[i] += M[i];
     double dx[NV], dl[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) dx[i] = x[i] - a0[i];
     symv_packed<NV>(M, dx, dl);
 #pragma unroll
     for (int i = 0; i < NV; ++i) dl[i] = -(dl[i] + gp[i]);
-    double H[NV * (NV + 1) / 2];
-    tree_hessian<NV, CPL, L>(M, rw, act, H);
     if (!chol_packed<NV>(H)) { st.status |= 4; return; }
     chol_solve_packed<NV>(H, dl);
     double dmax = 0.0, xmax = 1.0;
@@ -447,8 +458,10 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
           c1 += dt * s[k][e];
         }
       }
-      c1 = team_sum<L>(c1) + xMd;
-      c2 = team_sum<L>(c2) + dMd;
+      double cc[2] = {c1, c2};
+      team_sum_arr<L, 2>(cc);
+      c1 = cc[0] + xMd;
+      c2 = cc[1] + dMd;
       if (a * c2 + c1 > 0.0) hi = a; else lo = a;
       double an = (c2 > 0.0) ? -c1 / c2 : a;
       if (!isfinite(an)) an = a;
