@@ -157,6 +157,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg, s")
+    ap.add_argument("--no-critical", action="store_true", help="skip the hardest-world-alone leg")
+    ap.add_argument("--hardest-only", action="store_true",
+                    help="after the counted pass, run only the forward of the world with the most attempts "
+                         "(one wavefront; for instruction counters) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,6 +214,35 @@ def main():
     ac = dict(zip(D.ADJ_COUNTERS, adj_cnt.sum(0).cpu().numpy().tolist()))
     fwd_flops = algorithmic_flops(fc, FWD_FLOPS, model.ncon)
     adj_flops = algorithmic_flops(ac, ADJ_FLOPS, model.ncon)
+
+    n_att = n_acc + r["n_rej"].cpu().numpy()
+    hard = int(np.argmax(n_att))
+
+    def alone(reps=3):
+        """The hardest world as a batch of one: forward and reverse launch times
+        (min over reps) -- the serial chain that bounds the batched launches."""
+        x1 = x0[hard:hard + 1].clone()
+        o1 = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes or (tuned or {}).get("lanes_per_world", 0))
+        r1 = D.rollout(model, x1, None, 1, horizon, opts=o1, tape=True)
+        xb1 = xbar[hard:hard + 1].clone()
+        D.rollout_vjp(r1["tape"], xb1)
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        tf, ta = [], []
+        for _ in range(reps):
+            ev1[0].record()
+            D.rollout(model, x1, None, 1, horizon, opts=o1, reuse=r1["tape"])
+            ev1[1].record()
+            D.rollout_vjp(r1["tape"], xb1)
+            ev1[2].record()
+            torch.cuda.synchronize()
+            tf.append(ev1[0].elapsed_time(ev1[1])); ta.append(ev1[1].elapsed_time(ev1[2]))
+        return min(tf), min(ta)
+
+    if args.hardest_only:
+        tf, ta = alone(reps=1)
+        print(json.dumps({"hardest_world": hard, "attempts": int(n_att[hard]), "fwd_ms": round(tf, 3),
+                          "adj_ms": round(ta, 3)}), flush=True)
+        return
 
     stream = torch.cuda.current_stream()
 
@@ -290,6 +323,15 @@ def main():
     if not args.no_serve:
         serving = serve_leg(D, W, args.serve_rate, args.serve_seconds)
 
+    critical = None
+    if not args.no_critical:
+        tf, ta = alone()
+        critical = {"world": hard, "attempts": int(n_att[hard]), "accepted": int(n_acc[hard]),
+                    "attempts_mean": round(float(n_att.mean()), 1),
+                    "alone_fwd_ms": round(tf, 3), "alone_adj_ms": round(ta, 3),
+                    "alone_us_per_attempt": round(tf * 1e3 / float(n_att[hard]), 2),
+                    "batch_fwd_ms": round(fwd_ms, 3), "batch_adj_ms": round(adj_ms, 3)}
+
     out = {
         "metric": "sim-seconds/s fwd+adjoint at rtol 1e-6 vs plain GPU form; p99 request latency",
         "value": round(value, 2),
@@ -313,6 +355,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_gpu": plain,
         "serving": serving,
+        "critical_path": critical,
         "work": {"fwd": fc, "adj": ac, "accepted_steps_mean": float(n_acc.mean()),
                  "accepted_steps_max": int(n_acc.max()), "failed_worlds": int((status != 0).sum()),
                  "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)},
