@@ -353,6 +353,60 @@ def _imp(r, si):
     return d0 + y * (dw - d0)
 
 
+@pytest.mark.parametrize("solimp", [(0.9, 0.95, 0.001, 0.5, 2.0), (0.3, 0.95, 0.002, 0.3, 3.0),
+                                    (0.0, 0.95, 0.001, 0.5, 2.0)])
+def test_impedance_spline_and_reference_acceleration(oracle, solimp):
+    """Sec. 2.1: the rows of a single sphere contact carry the impedance d(r) of
+    the solimp spline through D = d / (A (1 - d)) with A = (1 + mu^2) / m, and
+    a_ref = -b (J v) - k r with b = 2 / (d_w t_c), k = d / (d_w^2 t_c^2 phi^2).
+    Recover d from D at depths on both arms of the spline (and beyond the
+    width) and compare with the spline written out; check a_ref row by row."""
+    mu, tc, phi, mass, rad = 0.7, 0.004, 0.8, 1.7, 0.05
+    desc = W.model_sphere(radius=rad, mass=mass, mu=mu, tc=tc, solimp=solimp, dampratio=phi)
+    m = oracle.Model(desc)
+    d0, dw, wid, mid, pw = solimp
+    A = (1 + mu * mu) / mass
+    b = 2.0 / (dw * tc)
+    for x in (0.05, 0.2, mid - 1e-3, mid, mid + 1e-3, 0.6, 0.95, 1.0, 1.7):
+        r = -x * wid
+        st = sphere_state(rad + r, vz=-0.3, vx=0.2, vy=-0.1)
+        rows = m.rows(st)
+        assert rows["J"].shape[0] == 4 and np.all(rows["D"] == rows["D"][0])
+        Dv = rows["D"][0]
+        d = Dv * A / (1 + Dv * A)
+        assert d == pytest.approx(_imp(r, solimp), rel=1e-12, abs=1e-15), x
+        k = d / (dw * dw * tc * tc * phi * phi)
+        jv = rows["J"] @ st[7:]
+        np.testing.assert_allclose(rows["aref"], -b * jv - k * r, rtol=1e-12, atol=1e-12)
+    # no rows without penetration (the CFD field is off)
+    assert m.rows(sphere_state(rad + 1e-4))["J"].shape[0] == 0
+
+
+def test_cfd_impedance_continues_the_spline(oracle):
+    """Sec. 4: for 0 <= r < w_c the CFD spline takes d from d_0 at r = 0 to d_c
+    at r = w_c (with its own midpoint and power), continuing the penetration
+    spline's value d(0) = d_0 without a jump."""
+    si = (0.1, 0.95, 0.001, 0.5, 2.0)
+    cf = (0.0, 0.1, 0.05, 0.4, 4.0)  # (d_c, d_0, w_c, midpoint, power)
+    mu, mass, rad = 0.5, 1.0, 0.05
+    desc = W.model_sphere(radius=rad, mass=mass, mu=mu, solimp=si, cfd=cf)
+    m = oracle.Model(desc)
+    A = (1 + mu * mu) / mass
+    dc, dz, wc, mc, pc = cf
+    for x in (0.0, 0.1, 0.3, 0.4, 0.5, 0.8, 0.99):
+        r = x * wc
+        rows = m.rows(sphere_state(rad + r), cfd=True)
+        assert rows["J"].shape[0] == 4
+        Dv = rows["D"][0]
+        d = Dv * A / (1 + Dv * A)
+        y = x ** pc / mc ** (pc - 1) if x <= mc else 1 - (1 - x) ** pc / (1 - mc) ** (pc - 1)
+        assert d == pytest.approx(dz + y * (dc - dz), rel=1e-12, abs=1e-15), x
+    # beyond w_c no row; just inside the surface the penetration spline starts at d_0
+    assert m.rows(sphere_state(rad + 1.01 * wc), cfd=True)["J"].shape[0] == 0
+    Dv = m.rows(sphere_state(rad - 1e-12), cfd=True)["D"][0]
+    assert Dv * A / (1 + Dv * A) == pytest.approx(si[0], rel=1e-6)
+
+
 def test_resting_sphere_steady_penetration(oracle):
     """At rest the 4 pyramid edges each carry m g / 4; with f = D (-k r),
     D = d / (A (1 - d)), k = d / (dw^2 tc^2 phi^2), A = (1 + mu^2) / m, the
