@@ -167,6 +167,69 @@ DMX_DEV void butterfly_level(double* v) {
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] += t[i];
 }
+// Team sums of N values (N <= 28) staged through LDS, for teams whose
+// nonzero terms sit on the first LIVE lanes: those lanes write their N terms,
+// lane j then adds value pair (2j, 2j+1) over the LIVE rows in a fixed tree
+// order and writes the sum, and every lane reads all N sums back (the same
+// words, so the results are bitwise equal across the team).  The lanes of a
+// team are one wavefront's lanes and LDS instructions of a wavefront execute
+// in order; the wavefront-scope fences keep the compiler from moving the
+// accesses across the phases.
+constexpr int kLdsSumMax = 28;
+template <int L>
+DMX_DEV double* lds_sum_area() {
+  __shared__ __attribute__((aligned(16))) double s[64 / L][(L + 1) * kLdsSumMax];
+  return s[(threadIdx.x & 63) / L];
+}
+DMX_DEV void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <int L, int LIVE, int N>
+DMX_DEV void team_sum_lds(double* v) {
+  static_assert(N <= kLdsSumMax && LIVE <= L && (LIVE & (LIVE - 1)) == 0, "team_sum_lds sizes");
+  constexpr int NP = (N + 1) / 2;  // value pairs
+  double* area = lds_sum_area<L>();
+  double* S = area + L * kLdsSumMax;  // sums
+  const int tl = threadIdx.x & (L - 1);
+  if (tl < LIVE) {
+    double2* row = (double2*)(area + tl * kLdsSumMax);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) row[k] = make_double2(v[2 * k], 2 * k + 1 < N ? v[2 * k + 1] : 0.0);
+  }
+  wave_fence();
+#pragma unroll
+  for (int k0 = 0; k0 < NP; k0 += L) {
+    const int k = k0 + tl;
+    if (k < NP) {
+      double2 t[LIVE];
+#pragma unroll
+      for (int j = 0; j < LIVE; ++j) t[j] = ((const double2*)(area + j * kLdsSumMax))[k];
+#pragma unroll
+      for (int w = 1; w < LIVE; w *= 2)
+#pragma unroll
+        for (int j = 0; j < LIVE; j += 2 * w) { t[j].x += t[j + w].x; t[j].y += t[j + w].y; }
+      ((double2*)S)[k] = t[0];
+    }
+  }
+  wave_fence();
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double2 t = ((const double2*)S)[k];
+    v[2 * k] = t.x;
+    if (2 * k + 1 < N) v[2 * k + 1] = t.y;
+  }
+  wave_fence();
+}
+// Lanes of a team that hold contact slots when slot c sits on lane c mod L:
+// the slot count rounded up to a power of two, at most the team.
+constexpr int live_lanes(int nc, int L) {
+  int p = 1;
+  while (p < nc) p *= 2;
+  return p < L ? p : L;
+}
+
 template <int L, int N>
 DMX_DEV void team_sum_arr(double* v) {
   if constexpr (L >= 2) butterfly_level<0xB1, N>(v);

@@ -285,6 +285,15 @@ DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, b
   }
 }
 
+// Team sum of a long array: staged through LDS for teams of 8 or more lanes
+// (fewer instructions than log2(L) butterfly levels of N moves and adds),
+// butterflies otherwise.
+template <int L, int LIVE, int N>
+DMX_DEV void team_sum_big(double* v) {
+  if constexpr (L >= 8) team_sum_lds<L, LIVE, N>(v);
+  else team_sum_arr<L, N>(v);
+}
+
 // y = M x for the constant free-body mass matrix
 DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
   y[0] = m.mass * x[0]; y[1] = m.mass * x[1]; y[2] = m.mass * x[2];
@@ -334,10 +343,10 @@ DMX_DEV void free_add_mass(const FreeModel& m, double* hp) {
 #pragma unroll
     for (int j = 0; j <= i; ++j) hp[tri(3 + i, 3 + j)] += m.I[i * 3 + j];
 }
-template <int CPL, int L>
+template <int CPL, int L, int LIVE = L>
 DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
   free_hessian_lane<CPL>(rw, act, hp);
-  team_sum_arr<L, 21>(hp);
+  team_sum_big<L, LIVE, 21>(hp);
   free_add_mass(m, hp);
 }
 
@@ -373,7 +382,7 @@ DMX_DEV bool same_active(const uint32_t* a, const uint32_t* b) {
 // then unchanged) and the solve ends; otherwise the exact minimizer along the
 // direction is found by a bracketed semismooth Newton iteration on the
 // piecewise-linear directional derivative.
-template <int CPL, int L>
+template <int CPL, int L, int LIVE = L>
 DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, const double* xw, double* x,
                          int maxit, Stat& st) {
 #pragma unroll
@@ -419,7 +428,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
       for (int i = 0; i < 6; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
     }
     free_hessian_lane<CPL>(rw, act, H);
-    team_sum_arr<L, 27>(gh);
+    team_sum_big<L, LIVE, 27>(gh);
     free_add_mass(m, H);
     double dx[6], Mdx[6];
 #pragma unroll
@@ -518,6 +527,7 @@ template <int NC, int L>
 struct FreePhys {
   static constexpr int NQ = 7, NV = 6, TEAM = L;
   static constexpr int CPL = (NC + L - 1) / L;
+  static constexpr int LIVE = live_lanes(NC, L);  // lanes that hold slots
   using Model = FreeModel;
 
   DMX_DEV static void frame(const double* q, V3* p, M3* R, Q4* qh, double* inv) {
@@ -550,7 +560,7 @@ struct FreePhys {
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    free_newton<CPL, L>(m, rw, a0, xw, a, maxit, st);
+    free_newton<CPL, L, LIVE>(m, rw, a0, xw, a, maxit, st);
   }
 
   // Cotangent of the acceleration map.  x* solves H x* = (tau - c) + sum_A
@@ -572,7 +582,7 @@ struct FreePhys {
     if (cfd) {
       double a0[6];
       a0_of(m, v, tau, a0);
-      free_newton<CPL, L>(m, rw, a0, nullptr, xs, maxit, st);
+      free_newton<CPL, L, LIVE>(m, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < 6; ++i) xs[i] = xs_in[i];
@@ -584,7 +594,7 @@ struct FreePhys {
 #pragma unroll
     for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
     double H[21];
-    free_hessian<CPL, L>(m, rw, act, H);
+    free_hessian<CPL, L, LIVE>(m, rw, act, H);
     chol_packed<6>(H);
     double lam[6];
 #pragma unroll
@@ -695,7 +705,7 @@ struct FreePhys {
 #pragma unroll
       for (int i = 0; i < 9; ++i) acc_[3 + i] += Rb2.a[i];
     }
-    team_sum_arr<L, 18>(acc_);
+    team_sum_big<L, LIVE, 18>(acc_);
     // bias c = (-m g, w x I w) with c_bar = -lam
     V3 w = mk3(v[3], v[4], v[5]);
     V3 Iw = mk3(m.I[0] * w.x + m.I[1] * w.y + m.I[2] * w.z, m.I[3] * w.x + m.I[4] * w.y + m.I[5] * w.z,
