@@ -222,6 +222,29 @@ DMX_DEV void team_sum_lds(double* v) {
   }
   wave_fence();
 }
+// Per-team LDS slots for values computed one component per lane and then
+// read by the whole team (N doubles per team).
+template <int L, int N>
+DMX_DEV double* lds_dof_area() {
+  __shared__ __attribute__((aligned(16))) double s[64 / L][N];
+  return s[(threadIdx.x & 63) / L];
+}
+// v[d] of a register array at a lane-dependent index d, by selects: each
+// element passes through an empty asm so that the chain is not folded back
+// into an indexed load (which would move the array to scratch memory).
+template <int N>
+DMX_DEV double pick(const double* v, int d) {
+  double r = v[0];
+  asm("" : "+v"(r));
+#pragma unroll
+  for (int e = 1; e < N; ++e) {
+    double ve = v[e];
+    asm("" : "+v"(ve));
+    r = (d == e) ? ve : r;
+  }
+  return r;
+}
+
 // Lanes of a team that hold contact slots when slot c sits on lane c mod L:
 // the slot count rounded up to a power of two, at most the team.
 constexpr int live_lanes(int nc, int L) {

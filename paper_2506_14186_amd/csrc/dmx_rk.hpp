@@ -226,27 +226,58 @@ DMX_DEV StageCoef stage_coef(int i) {
   }
 }
 
+// Teams of at least four lanes split per-component work of the tableau
+// combinations over their lanes (component d on lane d mod L) and share the
+// results through LDS; smaller teams compute every component on each lane.
+template <class P>
+constexpr bool kSplitDofs = P::TEAM >= 4;
+
+// sums over the earlier stages for component d: sv = sum a[i][l] A[l][d],
+// sq = sum (A A)[i][l] A[l][d]; entries of later stages (stale, possibly
+// non-finite after a failed trial) are masked, not branched over; the six LDS
+// reads are issued together
+template <class P>
+DMX_DEV void stage_sums(const double (*A)[P::NV], int i, const StageCoef& k, int d, double* sv_out, double* sq_out) {
+  double av[6];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) av[l] = A[l][d];
+  double sv = 0.0, sq = 0.0;
+#pragma unroll
+  for (int l = 0; l < 6; ++l) {
+    const double x = l < i ? av[l] : 0.0;
+    sv += k.a[l] * x;
+    sq += k.a2[l] * x;
+  }
+  *sv_out = sv;
+  *sq_out = sq;
+}
+
 // stage state Y_i from y_n and the stage accelerations A[0..i-1] (i >= 1)
 template <class P>
 DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq) {
-  constexpr int NQ = P::NQ, NV = P::NV;
+  constexpr int NQ = P::NQ, NV = P::NV, L = P::TEAM;
   const StageCoef k = stage_coef(i);
+  double sv[NV], sq[NV];
+  if constexpr (kSplitDofs<P>) {
+    double* buf = lds_dof_area<L, 3 * NV>();
+    const int tl = threadIdx.x & (L - 1);
+#pragma unroll
+    for (int r = 0; r < (NV + L - 1) / L; ++r) {
+      const int d = tl + r * L;
+      if (d < NV) stage_sums<P>(A, i, k, d, &buf[d], &buf[NV + d]);
+    }
+    wave_fence();
+#pragma unroll
+    for (int d = 0; d < NV; ++d) { sv[d] = buf[d]; sq[d] = buf[NV + d]; }
+    wave_fence();
+  } else {
+#pragma unroll
+    for (int d = 0; d < NV; ++d) stage_sums<P>(A, i, k, d, &sv[d], &sq[d]);
+  }
 #pragma unroll
   for (int d = 0; d < NV; ++d) {
-    // all six LDS reads issued together; entries of later stages (stale,
-    // possibly non-finite after a failed trial) are masked, not branched over
-    double av[6];
-#pragma unroll
-    for (int l = 0; l < 6; ++l) av[l] = A[l][d];
-    double sv = 0.0, sq = 0.0;
-#pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      const double x = l < i ? av[l] : 0.0;
-      sv += k.a[l] * x;
-      sq += k.a2[l] * x;
-    }
-    Y[NQ + d] = y[NQ + d] + h * sv;
-    dq[d] = h * (k.c * y[NQ + d] + h * sq);
+    Y[NQ + d] = y[NQ + d] + h * sv[d];
+    dq[d] = h * (k.c * y[NQ + d] + h * sq[d]);
   }
   P::qplus(y, dq, Y);
 }
@@ -255,18 +286,31 @@ DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, doubl
 // (+) increment's velocity term, A_bar[l] for the earlier stages
 template <class P>
 DMX_DEV void stage_distribute(int i, const double* Ybar, const double* dqb, double h, double* vb, double (*Ab)[P::NV]) {
-  constexpr int NQ = P::NQ, NV = P::NV;
+  constexpr int NQ = P::NQ, NV = P::NV, L = P::TEAM;
   const StageCoef k = stage_coef(i);
-  // a[i][l] = (A A)[i][l] = 0 for l >= i (explicit tableau): every entry is
-  // updated, without branches (the cotangents are finite)
 #pragma unroll
-  for (int d = 0; d < NV; ++d) {
-    vb[d] += Ybar[NQ + d] + h * k.c * dqb[d];
+  for (int d = 0; d < NV; ++d) vb[d] += Ybar[NQ + d] + h * k.c * dqb[d];
+  // a[i][l] = (A A)[i][l] = 0 for l >= i (explicit tableau): every entry is
+  // updated, without branches (the cotangents are finite); component d's
+  // column is updated by lane d mod L (by every lane for small teams)
+  auto column = [&](int d, double ybd, double qbd) {
     double ab[6];
 #pragma unroll
     for (int l = 0; l < 6; ++l) ab[l] = Ab[l][d];
 #pragma unroll
-    for (int l = 0; l < 6; ++l) Ab[l][d] = ab[l] + (h * k.a[l] * Ybar[NQ + d] + h * h * k.a2[l] * dqb[d]);
+    for (int l = 0; l < 6; ++l) Ab[l][d] = ab[l] + (h * k.a[l] * ybd + h * h * k.a2[l] * qbd);
+  };
+  if constexpr (kSplitDofs<P>) {
+    const int tl = threadIdx.x & (L - 1);
+#pragma unroll
+    for (int r = 0; r < (NV + L - 1) / L; ++r) {
+      const int d = tl + r * L;
+      if (d < NV) column(d, pick<NV>(Ybar + NQ, d), pick<NV>(dqb, d));
+    }
+    wave_fence();
+  } else {
+#pragma unroll
+    for (int d = 0; d < NV; ++d) column(d, Ybar[NQ + d], dqb[d]);
   }
 }
 
@@ -381,15 +425,33 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
       // the 5th- and 4th-order (+)-integrated values.
       double err = 0.0;
       {
-        double dqh[NV], ev[NV], eq[NV];
+        double dqh[NV], ev[NV], eq[NV], s1[NV], s2[NV], s3[NV];
+        auto comb = [&](int d, double* s1d, double* s2d, double* s3d) {
+          double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+          for (int l = 0; l < 7; ++l) { a1 += kTab.e[l] * A[l][d]; a2 += kTab.bhA[l] * A[l][d]; a3 += kTab.eA[l] * A[l][d]; }
+          *s1d = a1; *s2d = a2; *s3d = a3;
+        };
+        if constexpr (kSplitDofs<P>) {  // component d on lane d mod L, shared through LDS
+          double* buf = lds_dof_area<L, 3 * NV>();
+#pragma unroll
+          for (int r = 0; r < (NV + L - 1) / L; ++r) {
+            const int d = tl + r * L;
+            if (d < NV) comb(d, &buf[d], &buf[NV + d], &buf[2 * NV + d]);
+          }
+          wave_fence();
+#pragma unroll
+          for (int d = 0; d < NV; ++d) { s1[d] = buf[d]; s2[d] = buf[NV + d]; s3[d] = buf[2 * NV + d]; }
+          wave_fence();
+        } else {
+#pragma unroll
+          for (int d = 0; d < NV; ++d) comb(d, &s1[d], &s2[d], &s3[d]);
+        }
 #pragma unroll
         for (int d = 0; d < NV; ++d) {
-          double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-          for (int l = 0; l < 7; ++l) { s1 += kTab.e[l] * A[l][d]; s2 += kTab.bhA[l] * A[l][d]; s3 += kTab.eA[l] * A[l][d]; }
-          ev[d] = h * s1;
-          dqh[d] = h * (kTab.bh_sum * y[NQ + d] + h * s2);
-          eq[d] = h * h * s3;
+          ev[d] = h * s1[d];
+          dqh[d] = h * (kTab.bh_sum * y[NQ + d] + h * s2[d]);
+          eq[d] = h * h * s3[d];
         }
         double qh[NQ];
         P::qplus(y, dqh, qh);
