@@ -583,6 +583,14 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     const double* rec = tape_w + (size_t)s * a.rec;
     const double h = rec[1];
     const int kk = (int)rec[2];
+    // touch the previous record's cache lines (one word per 128 bytes, one
+    // lane each) so that the next step's loads find them in L2; the word is
+    // consumed at the end of this step, long after it arrived
+    float warm = 0.0f;
+    {
+      const int line = min(tl * 16, a.rec - 1);  // 16 doubles per 128-byte line; the last word too
+      if (s > 0 && tl * 16 < a.rec + 16) warm = *(const float*)(rec - a.rec + line);
+    }
     if (tl == 0) st.u_step++;
     if (kk != cur_k) {
       if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
@@ -661,6 +669,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     for (int i = 0; i < NQ; ++i) yb[i] = qb[i];
 #pragma unroll
     for (int d = 0; d < NV; ++d) yb[NQ + d] = vb[d];
+    asm volatile("" ::"v"(warm));
   }
   if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
