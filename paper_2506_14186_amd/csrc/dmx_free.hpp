@@ -140,13 +140,21 @@ DMX_DEV double softplus(double z, double beta, double* dsp) {
 }
 
 // ------------------------------------------------------------ contact rows
-template <int CPL>
+// Rows of a lane's contact slots: the normal row and NT tangent rows.  NT = 2:
+// both tangent directions and the four pyramid edges J_n + mu J_t1,
+// J_n - mu J_t1, J_n + mu J_t2, J_n - mu J_t2 on one lane.  NT = 1: a contact
+// sits on two lanes of the team, lane half h holding tangent direction t_(h+1)
+// and that direction's two edges; every per-contact sum is linear in the
+// edge terms, so the team sums add the halves.
+template <int CPL, int NT>
 struct FreeRows {
   bool on[CPL];
+  bool first[CPL];  // the lane that counts the contact (one per contact)
   int slot[CPL];
+  int half[CPL];    // NT = 1: tangent direction t1 (0) or t2 (1) of this lane
   double r[CPL], mu[CPL], D[CPL];
-  double Jn[CPL][6], Jt1[CPL][6], Jt2[CPL][6];
-  double aref[CPL][4];
+  double Jn[CPL][6], Jt[CPL][NT][6];
+  double aref[CPL][2 * NT];
 };
 
 DMX_DEV double dot6(const double* a, const double* b) {
@@ -242,14 +250,18 @@ DMX_DEV void slot_geom(const FreeModel& m, int c, V3 p, const M3& R, V3* lc, V3*
 
 // Rows of this lane's contact slots at (q, v).  J_u = [u, R^T (d x u)] for a
 // frame direction u, with d the contact point relative to the body origin.
-template <int CPL, int L>
+template <int CPL, int L, int NT>
 DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, bool cfd, double beta,
-                       FreeRows<CPL>& rw) {
+                       FreeRows<CPL, NT>& rw) {
   const int tl = threadIdx.x & (L - 1);
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
-    int c = tl + k * L;
+    // NT = 2: slot tl + k L; NT = 1 (one slot per lane pair): slot tl mod L/2
+    const int c = NT == 2 ? tl + k * L : (tl & (L / 2 - 1));
+    const int h = NT == 2 ? 0 : tl / (L / 2);
     rw.slot[k] = c;
+    rw.half[k] = h;
+    rw.first[k] = h == 0;
     rw.on[k] = false;
     if (c >= m.nc) continue;
     const PairF& pr = slot_pair(c);
@@ -261,14 +273,17 @@ DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, b
     rw.on[k] = on;
     if (!on) continue;
     V3 d = P - p;
-    V3 n = ld3(pr.n), t1 = ld3(pr.t1), t2 = ld3(pr.t2);
-    V3 wn = mulT(R, cross(d, n)), w1 = mulT(R, cross(d, t1)), w2 = mulT(R, cross(d, t2));
+    V3 n = ld3(pr.n);
+    V3 wn = mulT(R, cross(d, n));
     double* Jn = rw.Jn[k];
-    double* Ja = rw.Jt1[k];
-    double* Jb = rw.Jt2[k];
     Jn[0] = n.x; Jn[1] = n.y; Jn[2] = n.z; Jn[3] = wn.x; Jn[4] = wn.y; Jn[5] = wn.z;
-    Ja[0] = t1.x; Ja[1] = t1.y; Ja[2] = t1.z; Ja[3] = w1.x; Ja[4] = w1.y; Ja[5] = w1.z;
-    Jb[0] = t2.x; Jb[1] = t2.y; Jb[2] = t2.z; Jb[3] = w2.x; Jb[4] = w2.y; Jb[5] = w2.z;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const V3 t = (NT == 2 ? a == 1 : h == 1) ? ld3(pr.t2) : ld3(pr.t1);
+      const V3 wt = mulT(R, cross(d, t));
+      double* Ja = rw.Jt[k][a];
+      Ja[0] = t.x; Ja[1] = t.y; Ja[2] = t.z; Ja[3] = wt.x; Ja[4] = wt.y; Ja[5] = wt.z;
+    }
     double ddr;
     double dimp = impedance(pr, r, &ddr);
     double kk = dimp * pr.kscale;
@@ -277,11 +292,13 @@ DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, b
     double pterm;
     if (cfd) { double dsp; pterm = kk * softplus(-r, beta, &dsp); }
     else pterm = -kk * r;
-    double jnv = dot6(Jn, v), j1v = dot6(Ja, v), j2v = dot6(Jb, v);
-    rw.aref[k][0] = -pr.bcoef * (jnv + pr.mu * j1v) + pterm;
-    rw.aref[k][1] = -pr.bcoef * (jnv - pr.mu * j1v) + pterm;
-    rw.aref[k][2] = -pr.bcoef * (jnv + pr.mu * j2v) + pterm;
-    rw.aref[k][3] = -pr.bcoef * (jnv - pr.mu * j2v) + pterm;
+    const double jnv = dot6(Jn, v);
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const double jtv = dot6(rw.Jt[k][a], v);
+      rw.aref[k][2 * a] = -pr.bcoef * (jnv + pr.mu * jtv) + pterm;
+      rw.aref[k][2 * a + 1] = -pr.bcoef * (jnv - pr.mu * jtv) + pterm;
+    }
   }
 }
 
@@ -309,30 +326,39 @@ DMX_DEV void free_Mmul(const FreeModel& m, const double* x, double* y) {
 //   + w_11 J_t1 J_t1^T + w_22 J_t2 J_t2^T
 // with the weights below (an inactive edge has weight 0).
 // This lane's share (its own slots) of the contact part, before the team sum.
-template <int CPL>
-DMX_DEV void free_hessian_lane(const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
+template <int CPL, int NT>
+DMX_DEV void free_hessian_lane(const FreeRows<CPL, NT>& rw, const uint32_t* act, double* hp) {
 #pragma unroll
   for (int i = 0; i < 21; ++i) hp[i] = 0.0;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     if (act[k] == 0u) continue;
     const double D = rw.D[k], mu = rw.mu[k];
-    double o[4];
+    double o[2 * NT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
-    const double w11 = o[0] + o[1], w22 = o[2] + o[3];
-    const double wnn = w11 + w22, wn1 = mu * (o[0] - o[1]), wn2 = mu * (o[2] - o[3]);
+    for (int e = 0; e < 2 * NT; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
+    double waa[NT], wna[NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) { waa[a] = o[2 * a] + o[2 * a + 1]; wna[a] = mu * (o[2 * a] - o[2 * a + 1]); }
+    const double wnn = NT == 2 ? waa[0] + waa[NT - 1] : waa[0];
     const double mm = mu * mu;
     const double* Jn = rw.Jn[k];
-    const double* J1 = rw.Jt1[k];
-    const double* J2 = rw.Jt2[k];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      const double ui = wnn * Jn[i] + wn1 * J1[i] + wn2 * J2[i];
-      const double vi = wn1 * Jn[i] + mm * w11 * J1[i];
-      const double zi = wn2 * Jn[i] + mm * w22 * J2[i];
+      double ui = wnn * Jn[i];
+      double va[NT];
 #pragma unroll
-      for (int j = 0; j <= i; ++j) hp[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
+      for (int a = 0; a < NT; ++a) {
+        ui += wna[a] * rw.Jt[k][a][i];
+        va[a] = wna[a] * Jn[i] + mm * waa[a] * rw.Jt[k][a][i];
+      }
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        double hij = ui * Jn[j];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) hij += va[a] * rw.Jt[k][a][j];
+        hp[tri(i, j)] += hij;
+      }
     }
   }
 }
@@ -343,29 +369,42 @@ DMX_DEV void free_add_mass(const FreeModel& m, double* hp) {
 #pragma unroll
     for (int j = 0; j <= i; ++j) hp[tri(3 + i, 3 + j)] += m.I[i * 3 + j];
 }
-template <int CPL, int L, int LIVE = L>
-DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL>& rw, const uint32_t* act, double* hp) {
-  free_hessian_lane<CPL>(rw, act, hp);
+template <int CPL, int L, int LIVE, int NT>
+DMX_DEV void free_hessian(const FreeModel& m, const FreeRows<CPL, NT>& rw, const uint32_t* act, double* hp) {
+  free_hessian_lane<CPL, NT>(rw, act, hp);
   team_sum_big<L, LIVE, 21>(hp);
   free_add_mass(m, hp);
 }
 
 // Active edges at x: bit e of act[k] set iff J_e x - a_ref_e < 0.
-template <int CPL>
-DMX_DEV void free_active(const FreeRows<CPL>& rw, const double* x, uint32_t* act, double (*s)[4]) {
+template <int CPL, int NT>
+DMX_DEV void free_active(const FreeRows<CPL, NT>& rw, const double* x, uint32_t* act, double (*s)[4]) {
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     act[k] = 0u;
     if (!rw.on[k]) continue;
-    double jn = dot6(rw.Jn[k], x), j1 = dot6(rw.Jt1[k], x), j2 = dot6(rw.Jt2[k], x);
-    double mu = rw.mu[k];
-    double jx[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
+    const double jn = dot6(rw.Jn[k], x);
+    const double mu = rw.mu[k];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      s[k][e] = jx[e] - rw.aref[k][e];
-      if (s[k][e] < 0.0) act[k] |= 1u << e;
+    for (int a = 0; a < NT; ++a) {
+      const double ja = dot6(rw.Jt[k][a], x);
+      const double jx[2] = {jn + mu * ja, jn - mu * ja};
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int e = 2 * a + b;
+        s[k][e] = jx[b] - rw.aref[k][e];
+        if (s[k][e] < 0.0) act[k] |= 1u << e;
+      }
     }
   }
+}
+
+// Active-edge mask of the contact on this lane and its partner lane (NT = 1
+// splits a contact over lanes l and l + 8 of a 16-lane team).
+template <int NT>
+DMX_DEV uint32_t contact_bits(uint32_t act) {
+  if constexpr (NT == 2) return act;
+  else return act | (uint32_t)__builtin_amdgcn_mov_dpp((int)act, 0x128, 0xF, 0xF, true);  // row_ror:8
 }
 
 template <int CPL, int L>
@@ -382,14 +421,15 @@ DMX_DEV bool same_active(const uint32_t* a, const uint32_t* b) {
 // then unchanged) and the solve ends; otherwise the exact minimizer along the
 // direction is found by a bracketed semismooth Newton iteration on the
 // piecewise-linear directional derivative.
-template <int CPL, int L, int LIVE = L>
-DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const double* a0, const double* xw, double* x,
+template <int CPL, int L, int LIVE, int NT>
+DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL, NT>& rw, const double* a0, const double* xw, double* x,
                          int maxit, Stat& st) {
+  constexpr int NE = 2 * NT;  // edges per lane slot
 #pragma unroll
   for (int i = 0; i < 6; ++i) x[i] = a0[i];
   uint32_t act[CPL];
   double s[CPL][4];
-  free_active<CPL>(rw, x, act, s);
+  free_active<CPL, NT>(rw, x, act, s);
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
@@ -399,14 +439,15 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
   if (xw) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) x[i] = xw[i];
-    free_active<CPL>(rw, x, act, s);
+    free_active<CPL, NT>(rw, x, act, s);
   }
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
     if (team_leader(L)) st.u_nit++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
-      st.u_ncon += (act[k] != 0u);
+      const uint32_t cb = contact_bits<NT>(act[k]);
+      st.u_ncon += rw.first[k] && cb != 0u;
       st.u_nedge += __popc(act[k]);
     }
     // gradient and Hessian of the active set, summed over the team together
@@ -419,15 +460,22 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     for (int k = 0; k < CPL; ++k) {
       if (act[k] == 0u) continue;
       // sum_e w_e (J_n + s_e J_t) = (sum w_e) J_n + mu (w0 - w1) J_t1 + mu (w2 - w3) J_t2
-      double we[4];
+      double we[NE];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
-      const double cn = (we[0] + we[1]) + (we[2] + we[3]);
-      const double c1 = rw.mu[k] * (we[0] - we[1]), c2 = rw.mu[k] * (we[2] - we[3]);
+      for (int e = 0; e < NE; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
+      const double cn = NT == 2 ? (we[0] + we[1]) + (we[NE - 2] + we[NE - 1]) : we[0] + we[1];
+      double ca[NT];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
+      for (int a = 0; a < NT; ++a) ca[a] = rw.mu[k] * (we[2 * a] - we[2 * a + 1]);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double g = cn * rw.Jn[k][i];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) g += ca[a] * rw.Jt[k][a][i];
+        gp[i] += g;
+      }
     }
-    free_hessian_lane<CPL>(rw, act, H);
+    free_hessian_lane<CPL, NT>(rw, act, H);
     team_sum_big<L, LIVE, 27>(gh);
     free_add_mass(m, H);
     double dx[6], Mdx[6];
@@ -456,11 +504,15 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     for (int k = 0; k < CPL; ++k) {
       act1[k] = 0u;
       if (!rw.on[k]) continue;
-      double jn = dot6(rw.Jn[k], dl), j1 = dot6(rw.Jt1[k], dl), j2 = dot6(rw.Jt2[k], dl);
-      double mu = rw.mu[k];
-      t[k][0] = jn + mu * j1; t[k][1] = jn - mu * j1; t[k][2] = jn + mu * j2; t[k][3] = jn - mu * j2;
+      const double jn = dot6(rw.Jn[k], dl);
+      const double mu = rw.mu[k];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int a = 0; a < NT; ++a) {
+        const double ja = dot6(rw.Jt[k][a], dl);
+        t[k][2 * a] = jn + mu * ja; t[k][2 * a + 1] = jn - mu * ja;
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
         if (s[k][e] + t[k][e] < 0.0) act1[k] |= 1u << e;
     }
     if (same_active<CPL, L>(act, act1)) {
@@ -475,7 +527,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     double lo = 0.0, hi = 1e300, a = 1.0;
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) st.u_ls += rw.on[k];
+      for (int k = 0; k < CPL; ++k) st.u_ls += rw.on[k] && rw.first[k];
       double c1 = 0.0, c2 = 0.0;
       uint32_t sa[CPL];
 #pragma unroll
@@ -483,7 +535,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
         sa[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
           const bool on = s[k][e] + a * t[k][e] < 0.0;
           sa[k] |= on ? (1u << e) : 0u;
           const double dt = on ? rw.D[k] * t[k][e] : 0.0;
@@ -505,7 +557,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
         sn[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < NE; ++e)
           if (s[k][e] + an * t[k][e] < 0.0) sn[k] |= 1u << e;
       }
       if (same_active<CPL, L>(sa, sn)) { a = an; break; }
@@ -516,7 +568,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) x[i] += a * dl[i];
-    free_active<CPL>(rw, x, act, s);
+    free_active<CPL, NT>(rw, x, act, s);
   }
   st.status |= 8;
 }
@@ -526,8 +578,11 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL>& rw, const doub
 template <int NC, int L>
 struct FreePhys {
   static constexpr int NQ = 7, NV = 6, TEAM = L;
-  static constexpr int CPL = (NC + L - 1) / L;
-  static constexpr int LIVE = live_lanes(NC, L);  // lanes that hold slots
+  // a team of 16 lanes for 8 slots holds each contact on two lanes (one
+  // tangent direction each); otherwise slot c sits on lane c mod L
+  static constexpr int NT = (L == 16 && 2 * NC == L) ? 1 : 2;
+  static constexpr int CPL = NT == 1 ? 1 : (NC + L - 1) / L;
+  static constexpr int LIVE = NT == 1 ? L : live_lanes(NC, L);  // lanes that hold slots
   using Model = FreeModel;
 
   DMX_DEV static void frame(const double* q, V3* p, M3* R, Q4* qh, double* inv) {
@@ -555,12 +610,12 @@ struct FreePhys {
     const double* v = y + NQ;
     double a0[6];
     a0_of(m, v, tau, a0);
-    FreeRows<CPL> rw;
-    free_rows<CPL, L>(m, p, R, v, cfd, beta, rw);
+    FreeRows<CPL, NT> rw;
+    free_rows<CPL, L, NT>(m, p, R, v, cfd, beta, rw);
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    free_newton<CPL, L, LIVE>(m, rw, a0, xw, a, maxit, st);
+    for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k] && rw.first[k];
+    free_newton<CPL, L, LIVE, NT>(m, rw, a0, xw, a, maxit, st);
   }
 
   // Cotangent of the acceleration map.  x* solves H x* = (tau - c) + sum_A
@@ -576,25 +631,25 @@ struct FreePhys {
     V3 p; M3 R; Q4 qh; double inv;
     frame(y, &p, &R, &qh, &inv);
     const double* v = y + NQ;
-    FreeRows<CPL> rw;
-    free_rows<CPL, L>(m, p, R, v, cfd, beta, rw);
+    FreeRows<CPL, NT> rw;
+    free_rows<CPL, L, NT>(m, p, R, v, cfd, beta, rw);
     double xs[6];
     if (cfd) {
       double a0[6];
       a0_of(m, v, tau, a0);
-      free_newton<CPL, L, LIVE>(m, rw, a0, nullptr, xs, maxit, st);
+      free_newton<CPL, L, LIVE, NT>(m, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < 6; ++i) xs[i] = xs_in[i];
     }
     uint32_t act[CPL];
     double s[CPL][4];
-    free_active<CPL>(rw, xs, act, s);
+    free_active<CPL, NT>(rw, xs, act, s);
     if (team_leader(L)) st.u_vjp++;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
+    for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k] && rw.first[k]; st.u_vedge += __popc(act[k]); }
     double H[21];
-    free_hessian<CPL, L, LIVE>(m, rw, act, H);
+    free_hessian<CPL, L, LIVE, NT>(m, rw, act, H);
     chol_packed<6>(H);
     double lam[6];
 #pragma unroll
@@ -612,8 +667,6 @@ struct FreePhys {
       const PairF& pr = slot_pair(rw.slot[k]);
       const double mu = rw.mu[k], D = rw.D[k];
       const double* Jn = rw.Jn[k];
-      const double* J1 = rw.Jt1[k];
-      const double* J2 = rw.Jt2[k];
       double rbar = 0.0;
       double ddr;
       double dimp = impedance(pr, rw.r[k], &ddr);
@@ -629,16 +682,19 @@ struct FreePhys {
       }
       // Per edge e (J_e = J_n + s_e J_t(e), force f_e = D (aref_e - J_e x)):
       // J_e_bar = f_e lam - arb_e (x + bcoef v) with arb_e = D J_e lam, and
-      // v_bar -= bcoef arb_e J_e.  Summed over the four edges these become
-      // combinations of the three frame rows (inactive edges weigh 0).
-      const double ln = dot6(Jn, lam), l1 = dot6(J1, lam), l2 = dot6(J2, lam);
-      const double xn = dot6(Jn, xs), x1 = dot6(J1, xs), x2 = dot6(J2, xs);
-      double fe[4], ae[4];
+      // v_bar -= bcoef arb_e J_e.  Summed over the lane's edges these become
+      // combinations of the frame rows (inactive edges weigh 0).
+      constexpr int NE = 2 * NT;
+      const double ln = dot6(Jn, lam), xn = dot6(Jn, xs);
+      double la[NT], xa[NT];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int a = 0; a < NT; ++a) { la[a] = dot6(rw.Jt[k][a], lam); xa[a] = dot6(rw.Jt[k][a], xs); }
+      double fe[NE], ae[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
         const bool on = (act[k] >> e) & 1u;
         const double sg = (e & 1) ? -mu : mu;
-        const double sl = ln + sg * (e < 2 ? l1 : l2), sx = xn + sg * (e < 2 ? x1 : x2);
+        const double sl = ln + sg * la[e >> 1], sx = xn + sg * xa[e >> 1];
         const double De = on ? D : 0.0;
         const double gap = rw.aref[k][e] - sx;
         fe[e] = De * gap;
@@ -646,16 +702,23 @@ struct FreePhys {
         const double Dbar = on ? sl * gap : 0.0;
         rbar += ae[e] * dpt + Dbar * dD;
       }
-      const double Fn = (fe[0] + fe[1]) + (fe[2] + fe[3]), F1 = mu * (fe[0] - fe[1]), F2 = mu * (fe[2] - fe[3]);
-      const double An = (ae[0] + ae[1]) + (ae[2] + ae[3]), A1 = mu * (ae[0] - ae[1]), A2 = mu * (ae[2] - ae[3]);
-      double Jbn[6], Jb1[6], Jb2[6];
+      const double Fn = NT == 2 ? (fe[0] + fe[1]) + (fe[NE - 2] + fe[NE - 1]) : fe[0] + fe[1];
+      const double An = NT == 2 ? (ae[0] + ae[1]) + (ae[NE - 2] + ae[NE - 1]) : ae[0] + ae[1];
+      double Fa[NT], Aa[NT];
+#pragma unroll
+      for (int a = 0; a < NT; ++a) { Fa[a] = mu * (fe[2 * a] - fe[2 * a + 1]); Aa[a] = mu * (ae[2 * a] - ae[2 * a + 1]); }
+      double Jb[1 + NT][6];  // cotangents of J_n and the lane's tangent rows
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         const double z = xs[i] + pr.bcoef * v[i];
-        Jbn[i] = Fn * lam[i] - An * z;
-        Jb1[i] = F1 * lam[i] - A1 * z;
-        Jb2[i] = F2 * lam[i] - A2 * z;
-        acc_[12 + i] -= pr.bcoef * (An * Jn[i] + A1 * J1[i] + A2 * J2[i]);
+        Jb[0][i] = Fn * lam[i] - An * z;
+        double vt = An * Jn[i];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+          Jb[1 + a][i] = Fa[a] * lam[i] - Aa[a] * z;
+          vt += Aa[a] * rw.Jt[k][a][i];
+        }
+        acc_[12 + i] -= pr.bcoef * vt;
       }
       // J_u = [u, R^T (d x u)]: angular part back to d and R
       V3 lc, ce, P;
@@ -663,12 +726,11 @@ struct FreePhys {
       slot_geom(m, rw.slot[k], p, R, &lc, &ce, &r, &P);
       V3 d = P - p;
       V3 db = mk3(0, 0, 0);
-      const double* us[3] = {pr.n, pr.t1, pr.t2};
-      const double* jbs[3] = {Jbn, Jb1, Jb2};
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        V3 u = ld3(us[a]);
-        V3 wb = mk3(jbs[a][3], jbs[a][4], jbs[a][5]);
+      for (int a = 0; a < 1 + NT; ++a) {
+        const V3 u = a == 0 ? ld3(pr.n) : ((NT == 2 ? a == 2 : rw.half[k] == 1) ? ld3(pr.t2) : ld3(pr.t1));
+        const double* jb = Jb[a];
+        V3 wb = mk3(jb[3], jb[4], jb[5]);
         V3 z = cross(d, u);
         V3 zb = mul(R, wb);
         // R_bar += z wb^T
