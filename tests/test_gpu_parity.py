@@ -65,6 +65,11 @@ def _box_batch(n, horizon=0.5, seed=4):
 CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4]), "cube": lambda: _cube_batch(6), "box": lambda: _box_batch(6)}
 FREE_CASES = {"sphere": lambda: _sphere_batch([1, 2, 3, 4, 5, 6]), "cube": lambda: _cube_batch(16),
               "box": lambda: _box_batch(16)}
+# (case, lanes per world): 0 = the library's default team; the cube also with
+# 16-lane teams, which hold each of its 8 contacts on two lanes (the team size
+# the autotuner picks for the measured cube batch)
+CASE_LANES = [(c, 0) for c in CASES] + [("cube", 16)]
+FREE_CASE_LANES = [(c, 0) for c in FREE_CASES] + [("cube", 16)]
 
 
 @pytest.mark.parametrize("case", ["cube", "box"])
@@ -112,8 +117,8 @@ def _oracle_tapes(oracle, desc, x0, n_int, dt):
     return om, out
 
 
-@pytest.mark.parametrize("case", list(CASES))
-def test_single_step_parity(D, oracle, case):
+@pytest.mark.parametrize("case,lanes", CASE_LANES)
+def test_single_step_parity(D, oracle, case, lanes):
     """Every oracle step replayed as an independent one-step GPU world."""
     desc, x0, n_int, dt = CASES[case]()
     om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
@@ -128,7 +133,7 @@ def test_single_step_parity(D, oracle, case):
     forced = np.zeros((Wn, 1, 2))
     forced[:, 0, 1] = hs
     f_t, fn = _t(forced), _t(np.ones(Wn)).int()
-    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn.data_ptr(), forced_cap=1)
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn.data_ptr(), forced_cap=1, lanes_per_world=lanes)
     res = D.rollout(model, _t(ys), None, 1, 10.0, opts=o)
     assert int(res["status"].abs().sum()) == 0
     err = rel_state(res["x"].cpu().numpy(), nxt, model.nq)
@@ -144,7 +149,8 @@ def test_single_step_parity(D, oracle, case):
                 r1 = om.rollout(yp, None, 1, 10.0, forced=[[0.0, hs[i]]])
                 sens[i] = max(sens[i], rel_state(r1["x"], nxt[i], model.nq)[0])
     tol = np.maximum(1e-10, 10.0 * sens)
-    print(f"{case}: {Wn} single steps, max rel err {err.max():.3e}; {int((sens > 1e-11).sum())} ill-conditioned "
+    print(f"{case} (lanes {lanes or 'default'}): {Wn} single steps, max rel err {err.max():.3e}; "
+          f"{int((sens > 1e-11).sum())} ill-conditioned "
           f"steps (max {sens.max():.1e}); max err/tol {(err / tol).max():.2f}")
     assert (err <= tol).all()
 
@@ -176,12 +182,13 @@ def test_replayed_sequence_parity(D, oracle, case):
     assert worst <= 1e-6 and ef.max() <= 1e-6
 
 
-@pytest.mark.parametrize("case", list(FREE_CASES))
-def test_free_adaptive_parity_and_gradient(D, oracle, case):
+@pytest.mark.parametrize("case,lanes", FREE_CASE_LANES)
+def test_free_adaptive_parity_and_gradient(D, oracle, case, lanes):
     desc, x0, n_int, dt = FREE_CASES[case]()
     om = oracle.Model(desc)
     model = D.Model(desc)
-    res = D.rollout(model, _t(x0), None, n_int, dt, tape=True, counters=True)
+    res = D.rollout(model, _t(x0), None, n_int, dt, tape=True, counters=True,
+                    opts=D.default_opts(lanes_per_world=lanes))
     assert int(res["status"].abs().sum()) == 0
     xbar = np.zeros_like(x0)
     xbar[:, 0:3] = 1.0  # summed final position
@@ -194,7 +201,8 @@ def test_free_adaptive_parity_and_gradient(D, oracle, case):
     eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
     nacc = res["n_acc"].cpu().numpy()
     same = nacc == ref["n_acc"]
-    print(f"{case}: steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}; state err {ex.max():.2e}; "
+    print(f"{case} (lanes {lanes or 'default'}): steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}; "
+          f"state err {ex.max():.2e}; "
           f"grad err {eg.max():.2e}")
     ok = (ex <= 1e-6) & (eg <= 1e-5)
     # worlds on the same accepted-step sequence agree; a world whose sequence
@@ -225,8 +233,8 @@ def test_free_run_full_horizon(D, oracle, levels):
         assert ex[same].max() <= 1e-6
 
 
-@pytest.mark.parametrize("case", ["cube", "box"])
-def test_replayed_gradient_matches_oracle_tightly(D, oracle, case):
+@pytest.mark.parametrize("case,lanes", [("cube", 0), ("box", 0), ("cube", 16)])
+def test_replayed_gradient_matches_oracle_tightly(D, oracle, case, lanes):
     """Same step sequence on both sides: the reverse sweep equals the
     forward-mode derivative of the oracle to rounding."""
     desc, x0, n_int, dt = _cube_batch(4, horizon=0.3) if case == "cube" else _box_batch(4, horizon=0.6)
@@ -239,14 +247,15 @@ def test_replayed_gradient_matches_oracle_tightly(D, oracle, case):
         forced[w, :r["n_acc"]] = r["tape"][:, :2]
         fn[w] = r["n_acc"]
     f_t, fn_t = _t(forced), _t(fn).int()
-    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8,
+                       lanes_per_world=lanes)
     res = D.rollout(model, _t(x0), None, n_int, dt, opts=o, tape=True)
     rng = np.random.default_rng(7)
     xbar = rng.normal(size=x0.shape)
     g, _ = D.rollout_vjp(res["tape"], _t(xbar))
     ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=4)
     eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
-    print(f"{case}: replayed-sequence gradient rel err {eg.max():.3e}")
+    print(f"{case} (lanes {lanes or 'default'}): replayed-sequence gradient rel err {eg.max():.3e}")
     assert eg.max() <= 1e-8
 
 
@@ -268,7 +277,7 @@ def test_batch_and_team_invariance(D):
     forced = np.ascontiguousarray(recs[:, :cap, :2])
     f_t, fn_t = _t(forced), _t(n.astype(np.float64)).int()
     ref = full["x"].cpu().numpy()
-    for L in (1, 2, 4, 8):
+    for L in (1, 2, 4, 8, 16):
         o = D.default_opts(lanes_per_world=L, forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap)
         r = D.rollout(model, _t(x0), None, n_int, dt, opts=o)
         e = rel_state(r["x"].cpu().numpy(), ref, model.nq)
@@ -352,17 +361,48 @@ def test_cfd_straight_through(D, oracle):
     assert abs(ref["x0bar"][0, 2] - plain["x0bar"][0, 2]) > 1e-3  # CFD informs the non-touching sphere
 
 
-def test_full_size_cube_sampled(D, oracle):
-    """The measured configuration (4096 cube worlds, 0.5 s, one launch, default
-    team size): every world finishes; then the same launch replays, for 8
-    sampled worlds, the oracle's step sequences (the other worlds replay their
-    own), and the sampled end states and gradients match the oracle's."""
+@pytest.mark.parametrize("lanes", [0, 16])
+def test_cfd_straight_through_cube(D, oracle, lanes):
+    """The straight-through CFD gradient of tumbling cubes (8 corner slots,
+    CFD rows for corners within w_c of the plane), on the oracle's step
+    sequences, for the default team and 16-lane teams (two lanes per contact)."""
+    desc, x0, n_int, dt = _cube_batch(4, horizon=0.3)
+    om, tapes = _oracle_tapes(oracle, desc, x0, n_int, dt)
+    model = D.Model(desc)
+    cap = max(r["n_acc"] for r in tapes)
+    forced = np.zeros((x0.shape[0], cap, 2))
+    fn = np.zeros(x0.shape[0])
+    for w, r in enumerate(tapes):
+        forced[w, :r["n_acc"]] = r["tape"][:, :2]
+        fn[w] = r["n_acc"]
+    f_t, fn_t = _t(forced), _t(fn).int()
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8,
+                       lanes_per_world=lanes, cfd=1)
+    res = D.rollout(model, _t(x0), None, n_int, dt, opts=o, tape=True)
+    assert int(res["status"].abs().sum()) == 0
+    rng = np.random.default_rng(11)
+    xbar = rng.normal(size=x0.shape)
+    g, _ = D.rollout_vjp(res["tape"], _t(xbar))
+    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=4, cfd=1)
+    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
+    print(f"cube cfd (lanes {lanes or 'default'}): replayed-sequence gradient rel err {eg.max():.3e}")
+    assert eg.max() <= 1e-5
+
+
+@pytest.mark.parametrize("lanes", [0, 16])
+def test_full_size_cube_sampled(D, oracle, lanes):
+    """The measured configuration (4096 cube worlds, 0.5 s, one launch; the
+    default team size and the 16-lane teams the benchmark's autotuner picks):
+    every world finishes; then the same launch replays, for 8 sampled worlds,
+    the oracle's step sequences (the other worlds replay their own), and the
+    sampled end states and gradients match the oracle's."""
     cfg = W.cube_toss(seed=2, n_worlds=4096, horizon=0.5)
     model = D.Model(cfg["model"])
     x0 = cfg["x0"]
     xbar = np.zeros_like(x0)
     xbar[:, :3] = 1.0
-    res = D.rollout(model, _t(x0), None, 1, 0.5, tape=True, counters=True, opts=D.default_opts(tape_steps=2048))
+    res = D.rollout(model, _t(x0), None, 1, 0.5, tape=True, counters=True,
+                    opts=D.default_opts(tape_steps=2048, lanes_per_world=lanes))
     assert int(res["status"].abs().sum()) == 0
     g, _ = D.rollout_vjp(res["tape"], _t(xbar))
     assert np.isfinite(g.cpu().numpy()).all()
@@ -380,14 +420,16 @@ def test_full_size_cube_sampled(D, oracle):
         forced[w, :ref_tapes[i]["n_acc"]] = ref_tapes[i]["tape"][:, :2]
         fn[w] = ref_tapes[i]["n_acc"]
     f_t, fn_t = _t(forced), _t(fn).int()
-    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8)
+    o = D.default_opts(forced=f_t.data_ptr(), forced_n=fn_t.data_ptr(), forced_cap=cap, tape_steps=cap + 8,
+                       lanes_per_world=lanes)
     rep = D.rollout(model, _t(x0), None, 1, 0.5, tape=True, opts=o)
     assert int(rep["status"].abs().sum()) == 0
     gr, _ = D.rollout_vjp(rep["tape"], _t(xbar))
     ref = om.grad_batch(x0[sample], None, 1, 0.5, xbar[sample], n_threads=8)
     ex = rel_state(rep["x"].cpu().numpy()[sample], ref["x"], model.nq)
     eg = rel_grad(gr.cpu().numpy()[sample], ref["x0bar"])
-    print(f"4096 worlds: accepted steps mean {nacc.mean():.0f} max {nacc.max()}; sampled replay state err "
+    print(f"4096 worlds (lanes {lanes or 'default'}): accepted steps mean {nacc.mean():.0f} max {nacc.max()}; "
+          f"sampled replay state err "
           f"{ex.max():.2e} grad err {eg.max():.2e}")
     assert ex.max() <= 1e-6 and eg.max() <= 1e-5
 
