@@ -215,13 +215,17 @@ DMX_DEV void symv_packed(const double* M, const double* x, double* y) {
   }
 }
 
-template <int NV, int CPL>
+// Rows of a lane's contact slots (the free-body rows' layout): NTG = 2, both
+// tangent directions and four pyramid edges per slot; NTG = 1, a contact on
+// two lanes l and L-1-l, each with one tangent direction and its two edges.
+template <int NV, int CPL, int NTG>
 struct TreeRows {
   bool on[CPL];
-  int slot[CPL], body[CPL];
+  bool first[CPL];  // the lane that counts the contact
+  int slot[CPL], body[CPL], half[CPL];
   double r[CPL], mu[CPL], D[CPL];
-  double Jn[CPL][NV], Jt1[CPL][NV], Jt2[CPL][NV];
-  double aref[CPL][4];
+  double Jn[CPL][NV], Jt[CPL][NTG][NV];
+  double aref[CPL][2 * NTG];
 };
 
 template <int NV>
@@ -244,14 +248,19 @@ DMX_DEV void tree_slot_geom(const TreeModel& m, int c, V3 pb, const M3& Rb, V3* 
   *P = ce - (pr.rad + 0.5 * rr) * n;
 }
 
-template <int NV, int NB, int CPL, int L>
+template <int NV, int NB, int CPL, int L, int NTG>
 DMX_DEV void tree_rows(const TreeModel& m, const TreeWs<NV, NB>& ws, const double* v, bool cfd, double beta,
-                       TreeRows<NV, CPL>& rw) {
+                       TreeRows<NV, CPL, NTG>& rw) {
   const int tl = threadIdx.x & (L - 1);
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
-    const int c = tl + k * L;
+    // NTG = 2: slot tl + k L; NTG = 1: slot tl on the first half of the
+    // team, L - 1 - tl on the second (a lane and its mirror share a slot)
+    const int h = NTG == 2 ? 0 : tl / (L / 2);
+    const int c = NTG == 2 ? tl + k * L : (h ? L - 1 - tl : tl);
     rw.slot[k] = c;
+    rw.half[k] = h;
+    rw.first[k] = h == 0;
     rw.on[k] = false;
     if (c >= m.nc) continue;
     const PairF& pr = slot_pair(c);
@@ -266,12 +275,14 @@ DMX_DEV void tree_rows(const TreeModel& m, const TreeWs<NV, NB>& ws, const doubl
     if (!on) continue;
     double Jp[3][NV];
     tree_point_jac<NV, NB>(m, ws, b, P, Jp, nullptr);
-    const V3 n = ld3(pr.n), t1 = ld3(pr.t1), t2 = ld3(pr.t2);
+    const V3 n = ld3(pr.n);
 #pragma unroll
-    for (int d = 0; d < NV; ++d) {
-      rw.Jn[k][d] = n.x * Jp[0][d] + n.y * Jp[1][d] + n.z * Jp[2][d];
-      rw.Jt1[k][d] = t1.x * Jp[0][d] + t1.y * Jp[1][d] + t1.z * Jp[2][d];
-      rw.Jt2[k][d] = t2.x * Jp[0][d] + t2.y * Jp[1][d] + t2.z * Jp[2][d];
+    for (int d = 0; d < NV; ++d) rw.Jn[k][d] = n.x * Jp[0][d] + n.y * Jp[1][d] + n.z * Jp[2][d];
+#pragma unroll
+    for (int a = 0; a < NTG; ++a) {
+      const V3 t = (NTG == 2 ? a == 1 : h == 1) ? ld3(pr.t2) : ld3(pr.t1);
+#pragma unroll
+      for (int d = 0; d < NV; ++d) rw.Jt[k][a][d] = t.x * Jp[0][d] + t.y * Jp[1][d] + t.z * Jp[2][d];
     }
     double ddr;
     const double dimp = impedance(pr, r, &ddr);
@@ -281,68 +292,96 @@ DMX_DEV void tree_rows(const TreeModel& m, const TreeWs<NV, NB>& ws, const doubl
     double pterm;
     if (cfd) { double dsp; pterm = kk * softplus(-r, beta, &dsp); }
     else pterm = -kk * r;
-    const double jnv = dotn<NV>(rw.Jn[k], v), j1v = dotn<NV>(rw.Jt1[k], v), j2v = dotn<NV>(rw.Jt2[k], v);
-    rw.aref[k][0] = -pr.bcoef * (jnv + pr.mu * j1v) + pterm;
-    rw.aref[k][1] = -pr.bcoef * (jnv - pr.mu * j1v) + pterm;
-    rw.aref[k][2] = -pr.bcoef * (jnv + pr.mu * j2v) + pterm;
-    rw.aref[k][3] = -pr.bcoef * (jnv - pr.mu * j2v) + pterm;
+    const double jnv = dotn<NV>(rw.Jn[k], v);
+#pragma unroll
+    for (int a = 0; a < NTG; ++a) {
+      const double jtv = dotn<NV>(rw.Jt[k][a], v);
+      rw.aref[k][2 * a] = -pr.bcoef * (jnv + pr.mu * jtv) + pterm;
+      rw.aref[k][2 * a + 1] = -pr.bcoef * (jnv - pr.mu * jtv) + pterm;
+    }
   }
 }
 
-template <int NV, int CPL>
-DMX_DEV void tree_active(const TreeRows<NV, CPL>& rw, const double* x, uint32_t* act, double (*s)[4]) {
+template <int NV, int CPL, int NTG>
+DMX_DEV void tree_active(const TreeRows<NV, CPL, NTG>& rw, const double* x, uint32_t* act, double (*s)[4]) {
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     act[k] = 0u;
     if (!rw.on[k]) continue;
-    const double jn = dotn<NV>(rw.Jn[k], x), j1 = dotn<NV>(rw.Jt1[k], x), j2 = dotn<NV>(rw.Jt2[k], x);
+    const double jn = dotn<NV>(rw.Jn[k], x);
     const double mu = rw.mu[k];
-    const double jx[4] = {jn + mu * j1, jn - mu * j1, jn + mu * j2, jn - mu * j2};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      s[k][e] = jx[e] - rw.aref[k][e];
-      if (s[k][e] < 0.0) act[k] |= 1u << e;
+    for (int a = 0; a < NTG; ++a) {
+      const double ja = dotn<NV>(rw.Jt[k][a], x);
+      const double jx[2] = {jn + mu * ja, jn - mu * ja};
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int e = 2 * a + b;
+        s[k][e] = jx[b] - rw.aref[k][e];
+        if (s[k][e] < 0.0) act[k] |= 1u << e;
+      }
     }
+  }
+}
+
+// Active-edge mask of the contact on this lane and on its mirror lane
+// L - 1 - l (NTG = 1 splits a contact over the two).
+template <int NTG, int L>
+DMX_DEV uint32_t tree_contact_bits(uint32_t act) {
+  if constexpr (NTG == 2) {
+    return act;
+  } else {
+    static_assert(L == 8 || L == 16, "mirror exchange within a row of 16");
+    return act | (uint32_t)__builtin_amdgcn_mov_dpp((int)act, L == 8 ? 0x141 : 0x140, 0xF, 0xF, true);
   }
 }
 
 // H = M + sum over active edges of D J_e J_e^T (packed, team-summed;
 // inactive edges enter with weight 0)
 // This lane's share (its own slots) of the contact part, before the team sum.
-template <int NV, int CPL>
-DMX_DEV void tree_hessian_lane(const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
+template <int NV, int CPL, int NTG>
+DMX_DEV void tree_hessian_lane(const TreeRows<NV, CPL, NTG>& rw, const uint32_t* act, double* H) {
   constexpr int NT = NV * (NV + 1) / 2;
 #pragma unroll
   for (int i = 0; i < NT; ++i) H[i] = 0.0;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     if (act[k] == 0u) continue;
-    // the four edges J_n + s_e J_t(e) as combinations of the three frame
-    // rows (the free-body Hessian uses the same expansion)
+    // the lane's edges J_n + s_e J_t(e) as combinations of its frame rows
+    // (the free-body Hessian uses the same expansion)
     const double D = rw.D[k], mu = rw.mu[k];
-    double o[4];
+    double o[2 * NTG];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
-    const double w11 = o[0] + o[1], w22 = o[2] + o[3];
-    const double wnn = w11 + w22, wn1 = mu * (o[0] - o[1]), wn2 = mu * (o[2] - o[3]);
+    for (int e = 0; e < 2 * NTG; ++e) o[e] = ((act[k] >> e) & 1u) ? D : 0.0;
+    double waa[NTG], wna[NTG];
+#pragma unroll
+    for (int a = 0; a < NTG; ++a) { waa[a] = o[2 * a] + o[2 * a + 1]; wna[a] = mu * (o[2 * a] - o[2 * a + 1]); }
+    const double wnn = NTG == 2 ? waa[0] + waa[NTG - 1] : waa[0];
     const double mm = mu * mu;
     const double* Jn = rw.Jn[k];
-    const double* J1 = rw.Jt1[k];
-    const double* J2 = rw.Jt2[k];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const double ui = wnn * Jn[i] + wn1 * J1[i] + wn2 * J2[i];
-      const double vi = wn1 * Jn[i] + mm * w11 * J1[i];
-      const double zi = wn2 * Jn[i] + mm * w22 * J2[i];
+      double ui = wnn * Jn[i];
+      double va[NTG];
 #pragma unroll
-      for (int j = 0; j <= i; ++j) H[tri(i, j)] += ui * Jn[j] + vi * J1[j] + zi * J2[j];
+      for (int a = 0; a < NTG; ++a) {
+        ui += wna[a] * rw.Jt[k][a][i];
+        va[a] = wna[a] * Jn[i] + mm * waa[a] * rw.Jt[k][a][i];
+      }
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        double hij = ui * Jn[j];
+#pragma unroll
+        for (int a = 0; a < NTG; ++a) hij += va[a] * rw.Jt[k][a][j];
+        H[tri(i, j)] += hij;
+      }
     }
   }
 }
-template <int NV, int CPL, int L>
-DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL>& rw, const uint32_t* act, double* H) {
+template <int NV, int CPL, int L, int NTG>
+DMX_DEV void tree_hessian(const double* M, const TreeRows<NV, CPL, NTG>& rw, const uint32_t* act, double* H) {
   constexpr int NT = NV * (NV + 1) / 2;
-  tree_hessian_lane<NV, CPL>(rw, act, H);
+  tree_hessian_lane<NV, CPL, NTG>(rw, act, H);
   team_sum_arr<L, NT>(H);
 #pragma unroll
   for (int i = 0; i < NT; ++i) H[i] += M[i];
@@ -357,14 +396,15 @@ DMX_DEV bool tree_same(const uint32_t* a, const uint32_t* b) {
 }
 
 // exact Newton on the primal problem with dense M (see free_newton)
-template <int NV, int CPL, int L>
-DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const double* a0, const double* xw, double* x,
-                         int maxit, Stat& st) {
+template <int NV, int CPL, int L, int NTG>
+DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL, NTG>& rw, const double* a0, const double* xw,
+                         double* x, int maxit, Stat& st) {
+  constexpr int NE = 2 * NTG;  // edges per lane slot
 #pragma unroll
   for (int i = 0; i < NV; ++i) x[i] = a0[i];
   uint32_t act[CPL];
   double s[CPL][4];
-  tree_active<NV, CPL>(rw, x, act, s);
+  tree_active<NV, CPL, NTG>(rw, x, act, s);
   bool any = false;
 #pragma unroll
   for (int k = 0; k < CPL; ++k) any = any || (act[k] != 0u);
@@ -372,13 +412,16 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
   if (xw) {  // warm start; the iteration converges to the same minimizer
 #pragma unroll
     for (int i = 0; i < NV; ++i) x[i] = xw[i];
-    tree_active<NV, CPL>(rw, x, act, s);
+    tree_active<NV, CPL, NTG>(rw, x, act, s);
   }
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
     if (team_leader(L)) st.u_nit++;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) { st.u_ncon += (act[k] != 0u); st.u_nedge += __popc(act[k]); }
+    for (int k = 0; k < CPL; ++k) {
+      st.u_ncon += rw.first[k] && tree_contact_bits<NTG, L>(act[k]) != 0u;
+      st.u_nedge += __popc(act[k]);
+    }
     // gradient and Hessian of the active set, summed over the team together
     constexpr int NT = NV * (NV + 1) / 2;
     double gh[NV + NT];
@@ -390,15 +433,22 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     for (int k = 0; k < CPL; ++k) {
       if (act[k] == 0u) continue;
       // sum_e w_e (J_n + s_e J_t) = (sum w_e) J_n + mu (w0 - w1) J_t1 + mu (w2 - w3) J_t2
-      double we[4];
+      double we[NE];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
-      const double cn = (we[0] + we[1]) + (we[2] + we[3]);
-      const double c1 = rw.mu[k] * (we[0] - we[1]), c2 = rw.mu[k] * (we[2] - we[3]);
+      for (int e = 0; e < NE; ++e) we[e] = ((act[k] >> e) & 1u) ? rw.D[k] * s[k][e] : 0.0;
+      const double cn = NTG == 2 ? (we[0] + we[1]) + (we[NE - 2] + we[NE - 1]) : we[0] + we[1];
+      double ca[NTG];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) gp[i] += cn * rw.Jn[k][i] + c1 * rw.Jt1[k][i] + c2 * rw.Jt2[k][i];
+      for (int a = 0; a < NTG; ++a) ca[a] = rw.mu[k] * (we[2 * a] - we[2 * a + 1]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        double g = cn * rw.Jn[k][i];
+#pragma unroll
+        for (int a = 0; a < NTG; ++a) g += ca[a] * rw.Jt[k][a][i];
+        gp[i] += g;
+      }
     }
-    tree_hessian_lane<NV, CPL>(rw, act, H);
+    tree_hessian_lane<NV, CPL, NTG>(rw, act, H);
     team_sum_arr<L, NV + NT>(gh);
 #pragma unroll
     for (int i = 0; i < NT; ++i) H[i] += M[i];
@@ -424,11 +474,15 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     for (int k = 0; k < CPL; ++k) {
       act1[k] = 0u;
       if (!rw.on[k]) continue;
-      const double jn = dotn<NV>(rw.Jn[k], dl), j1 = dotn<NV>(rw.Jt1[k], dl), j2 = dotn<NV>(rw.Jt2[k], dl);
+      const double jn = dotn<NV>(rw.Jn[k], dl);
       const double mu = rw.mu[k];
-      t[k][0] = jn + mu * j1; t[k][1] = jn - mu * j1; t[k][2] = jn + mu * j2; t[k][3] = jn - mu * j2;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int a = 0; a < NTG; ++a) {
+        const double ja = dotn<NV>(rw.Jt[k][a], dl);
+        t[k][2 * a] = jn + mu * ja; t[k][2 * a + 1] = jn - mu * ja;
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
         if (s[k][e] + t[k][e] < 0.0) act1[k] |= 1u << e;
     }
     if (tree_same<NV, CPL, L>(act, act1)) {
@@ -442,7 +496,7 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     double lo = 0.0, hi = 1e300, a = 1.0;
     for (int ls = 0; ls < 60; ++ls) {
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) st.u_ls += rw.on[k];
+      for (int k = 0; k < CPL; ++k) st.u_ls += rw.on[k] && rw.first[k];
       double c1 = 0.0, c2 = 0.0;
       uint32_t sa[CPL], sn[CPL];
 #pragma unroll
@@ -450,7 +504,7 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
         sa[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
           const bool on = s[k][e] + a * t[k][e] < 0.0;
           sa[k] |= on ? (1u << e) : 0u;
           const double dt = on ? rw.D[k] * t[k][e] : 0.0;
@@ -470,7 +524,7 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
         sn[k] = 0u;
         if (!rw.on[k]) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < NE; ++e)
           if (s[k][e] + an * t[k][e] < 0.0) sn[k] |= 1u << e;
       }
       if (tree_same<NV, CPL, L>(sa, sn)) { a = an; break; }
@@ -481,7 +535,7 @@ DMX_DEV void tree_newton(const double* M, const TreeRows<NV, CPL>& rw, const dou
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) x[i] += a * dl[i];
-    tree_active<NV, CPL>(rw, x, act, s);
+    tree_active<NV, CPL, NTG>(rw, x, act, s);
   }
   st.status |= 8;
 }
@@ -492,7 +546,10 @@ DMX_DEV void cross_rev(V3 u, V3 w, V3 cb, V3& ub, V3& wb) { ub += cross(w, cb); 
 template <int kNV, int NB, int NC, int L>
 struct TreePhys {
   static constexpr int NV = kNV, NQ = kNV, TEAM = L;
-  static constexpr int CPL = (NC + L - 1) / L;
+  // a team of 8 or 16 lanes for half as many slots holds each contact on a
+  // lane and its mirror lane (one tangent direction each)
+  static constexpr int NTG = ((L == 8 || L == 16) && 2 * NC == L) ? 1 : 2;
+  static constexpr int CPL = NTG == 1 ? 1 : (NC + L - 1) / L;
   using Model = TreeModel;
 
   DMX_DEV static TreeWs<NV, NB>& ws() {
@@ -514,12 +571,12 @@ struct TreePhys {
 #pragma unroll
     for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
     chol_solve_packed<NV>(L_, a0);
-    TreeRows<NV, CPL> rw;
-    tree_rows<NV, NB, CPL, L>(m, w, v, cfd, beta, rw);
+    TreeRows<NV, CPL, NTG> rw;
+    tree_rows<NV, NB, CPL, L, NTG>(m, w, v, cfd, beta, rw);
     if (team_leader(L)) st.u_rhs++;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k];
-    tree_newton<NV, CPL, L>(M, rw, a0, xw, a, maxit, st);
+    for (int k = 0; k < CPL; ++k) st.u_con += rw.on[k] && rw.first[k];
+    tree_newton<NV, CPL, L, NTG>(M, rw, a0, xw, a, maxit, st);
   }
 
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
@@ -532,8 +589,8 @@ struct TreePhys {
     tree_kin<NV, NB>(m, q, v, nullptr, nullptr, w, false);
     double M[NV * (NV + 1) / 2], c[NV];
     tree_mass_bias<NV, NB>(m, w, M, c);
-    TreeRows<NV, CPL> rw;
-    tree_rows<NV, NB, CPL, L>(m, w, v, cfd, beta, rw);
+    TreeRows<NV, CPL, NTG> rw;
+    tree_rows<NV, NB, CPL, L, NTG>(m, w, v, cfd, beta, rw);
     double xs[NV];
     if (cfd) {
       double Lm[NV * (NV + 1) / 2], a0[NV];
@@ -543,19 +600,19 @@ struct TreePhys {
 #pragma unroll
       for (int i = 0; i < NV; ++i) a0[i] = tau[i] - c[i];
       chol_solve_packed<NV>(Lm, a0);
-      tree_newton<NV, CPL, L>(M, rw, a0, nullptr, xs, maxit, st);
+      tree_newton<NV, CPL, L, NTG>(M, rw, a0, nullptr, xs, maxit, st);
     } else {
 #pragma unroll
       for (int i = 0; i < NV; ++i) xs[i] = xs_in[i];
     }
     uint32_t act[CPL];
     double s[CPL][4];
-    tree_active<NV, CPL>(rw, xs, act, s);
+    tree_active<NV, CPL, NTG>(rw, xs, act, s);
     if (team_leader(L)) st.u_vjp++;
 #pragma unroll
-    for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k]; st.u_vedge += __popc(act[k]); }
+    for (int k = 0; k < CPL; ++k) { st.u_vcon += rw.on[k] && rw.first[k]; st.u_vedge += __popc(act[k]); }
     double H[NV * (NV + 1) / 2];
-    tree_hessian<NV, CPL, L>(M, rw, act, H);
+    tree_hessian<NV, CPL, L, NTG>(M, rw, act, H);
     chol_packed<NV>(H);
     double lam[NV];
 #pragma unroll
@@ -600,19 +657,20 @@ struct TreePhys {
       double dpt;
       if (cfd) { double dsp; const double sp = softplus(-rw.r[k], beta, &dsp); dpt = pr.kscale * ddr * sp - kk * dsp; }
       else dpt = -(pr.kscale * ddr * rw.r[k] + kk);
-      // per-edge reverse summed over the four edges as combinations of the
-      // three frame rows (as in the free-body reverse; inactive edges weigh 0)
+      // per-edge reverse summed over the lane's edges as combinations of its
+      // frame rows (as in the free-body reverse; inactive edges weigh 0)
+      constexpr int NE = 2 * NTG;
       const double* Jn = rw.Jn[k];
-      const double* J1 = rw.Jt1[k];
-      const double* J2 = rw.Jt2[k];
-      const double ln = dotn<NV>(Jn, lam), l1 = dotn<NV>(J1, lam), l2 = dotn<NV>(J2, lam);
-      const double xn = dotn<NV>(Jn, xs), x1 = dotn<NV>(J1, xs), x2 = dotn<NV>(J2, xs);
-      double fe[4], ae[4];
+      const double ln = dotn<NV>(Jn, lam), xn = dotn<NV>(Jn, xs);
+      double la[NTG], xa[NTG];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int a = 0; a < NTG; ++a) { la[a] = dotn<NV>(rw.Jt[k][a], lam); xa[a] = dotn<NV>(rw.Jt[k][a], xs); }
+      double fe[NE], ae[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
         const bool on = (act[k] >> e) & 1u;
         const double sg = (e & 1) ? -mu : mu;
-        const double sl = ln + sg * (e < 2 ? l1 : l2), sx = xn + sg * (e < 2 ? x1 : x2);
+        const double sl = ln + sg * la[e >> 1], sx = xn + sg * xa[e >> 1];
         const double De = on ? D : 0.0;
         const double gap = rw.aref[k][e] - sx;
         fe[e] = De * gap;
@@ -620,16 +678,23 @@ struct TreePhys {
         const double Dbar = on ? sl * gap : 0.0;
         rbar += ae[e] * dpt + Dbar * dD;
       }
-      const double Fn = (fe[0] + fe[1]) + (fe[2] + fe[3]), F1 = mu * (fe[0] - fe[1]), F2 = mu * (fe[2] - fe[3]);
-      const double An = (ae[0] + ae[1]) + (ae[2] + ae[3]), A1 = mu * (ae[0] - ae[1]), A2 = mu * (ae[2] - ae[3]);
-      double Jbn[NV], Jb1[NV], Jb2[NV];
+      const double Fn = NTG == 2 ? (fe[0] + fe[1]) + (fe[NE - 2] + fe[NE - 1]) : fe[0] + fe[1];
+      const double An = NTG == 2 ? (ae[0] + ae[1]) + (ae[NE - 2] + ae[NE - 1]) : ae[0] + ae[1];
+      double Fa[NTG], Aa[NTG];
+#pragma unroll
+      for (int a = 0; a < NTG; ++a) { Fa[a] = mu * (fe[2 * a] - fe[2 * a + 1]); Aa[a] = mu * (ae[2 * a] - ae[2 * a + 1]); }
+      double Jb[1 + NTG][NV];  // cotangents of J_n and the lane's tangent rows
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         const double z = xs[i] + pr.bcoef * v[i];
-        Jbn[i] = Fn * lam[i] - An * z;
-        Jb1[i] = F1 * lam[i] - A1 * z;
-        Jb2[i] = F2 * lam[i] - A2 * z;
-        vb[i] -= pr.bcoef * (An * Jn[i] + A1 * J1[i] + A2 * J2[i]);
+        Jb[0][i] = Fn * lam[i] - An * z;
+        double vt = An * Jn[i];
+#pragma unroll
+        for (int a = 0; a < NTG; ++a) {
+          Jb[1 + a][i] = Fa[a] * lam[i] - Aa[a] * z;
+          vt += Aa[a] * rw.Jt[k][a][i];
+        }
+        vb[i] -= pr.bcoef * vt;
       }
       // J_u[d] = u . (a_d x (P - o_d)) (hinge) or u . a_d (slide)
       const int b = rw.body[k];
@@ -637,8 +702,10 @@ struct TreePhys {
       double r;
       tree_slot_geom(m, rw.slot[k], ld3(w.p[b]), ldm(w.R[b]), &lc, &r, &P);
       V3 Pb = mk3(0, 0, 0);
-      const V3 us[3] = {ld3(pr.n), ld3(pr.t1), ld3(pr.t2)};
-      const double* jbs[3] = {Jbn, Jb1, Jb2};
+      V3 us[1 + NTG];
+      us[0] = ld3(pr.n);
+#pragma unroll
+      for (int a = 0; a < NTG; ++a) us[1 + a] = (NTG == 2 ? a == 1 : rw.half[k] == 1) ? ld3(pr.t2) : ld3(pr.t1);
       const unsigned anc = m.banc[b];
 #pragma unroll
       for (int d = 0; d < NV; ++d) {
@@ -648,8 +715,8 @@ struct TreePhys {
         if (m.jtype[d] == 1) {
           const V3 rel = P - ld3(w.an[d]);
 #pragma unroll
-          for (int u = 0; u < 3; ++u) {
-            const double g = jbs[u][d];
+          for (int u = 0; u < 1 + NTG; ++u) {
+            const double g = Jb[u][d];
             ab += g * cross(rel, us[u]);
             const V3 ua = cross(us[u], a);
             Pb += g * ua;
@@ -657,7 +724,7 @@ struct TreePhys {
           }
         } else {
 #pragma unroll
-          for (int u = 0; u < 3; ++u) ab += jbs[u][d] * us[u];
+          for (int u = 0; u < 1 + NTG; ++u) ab += Jb[u][d] * us[u];
         }
         cab[d][0] += ab.x; cab[d][1] += ab.y; cab[d][2] += ab.z;
         cob[d][0] += ob.x; cob[d][1] += ob.y; cob[d][2] += ob.z;
