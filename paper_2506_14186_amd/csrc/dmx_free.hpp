@@ -143,9 +143,10 @@ DMX_DEV double softplus(double z, double beta, double* dsp) {
 // Rows of a lane's contact slots: the normal row and NT tangent rows.  NT = 2:
 // both tangent directions and the four pyramid edges J_n + mu J_t1,
 // J_n - mu J_t1, J_n + mu J_t2, J_n - mu J_t2 on one lane.  NT = 1: a contact
-// sits on two lanes of the team, lane half h holding tangent direction t_(h+1)
-// and that direction's two edges; every per-contact sum is linear in the
-// edge terms, so the team sums add the halves.
+// sits on two lanes of the team, lane l < L/2 and its mirror L-1-l; the first
+// holds tangent direction t1 and its two edges, the second t2 and its two;
+// every per-contact sum is linear in the edge terms, so the team sums add the
+// halves.
 template <int CPL, int NT>
 struct FreeRows {
   bool on[CPL];
@@ -256,9 +257,10 @@ DMX_DEV void free_rows(const FreeModel& m, V3 p, const M3& R, const double* v, b
   const int tl = threadIdx.x & (L - 1);
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
-    // NT = 2: slot tl + k L; NT = 1 (one slot per lane pair): slot tl mod L/2
-    const int c = NT == 2 ? tl + k * L : (tl & (L / 2 - 1));
+    // NT = 2: slot tl + k L; NT = 1 (one slot per lane pair): slot tl on
+    // the first half of the team, L - 1 - tl on the second
     const int h = NT == 2 ? 0 : tl / (L / 2);
+    const int c = NT == 2 ? tl + k * L : (h ? L - 1 - tl : tl);
     rw.slot[k] = c;
     rw.half[k] = h;
     rw.first[k] = h == 0;
@@ -399,12 +401,16 @@ DMX_DEV void free_active(const FreeRows<CPL, NT>& rw, const double* x, uint32_t*
   }
 }
 
-// Active-edge mask of the contact on this lane and its partner lane (NT = 1
-// splits a contact over lanes l and l + 8 of a 16-lane team).
-template <int NT>
+// Active-edge mask of the contact on this lane and on its mirror lane
+// L - 1 - l (NT = 1 splits a contact over the two).
+template <int NT, int L>
 DMX_DEV uint32_t contact_bits(uint32_t act) {
-  if constexpr (NT == 2) return act;
-  else return act | (uint32_t)__builtin_amdgcn_mov_dpp((int)act, 0x128, 0xF, 0xF, true);  // row_ror:8
+  if constexpr (NT == 2) {
+    return act;
+  } else {
+    static_assert(L == 8 || L == 16, "mirror exchange within a row of 16");
+    return act | (uint32_t)__builtin_amdgcn_mov_dpp((int)act, L == 8 ? 0x141 : 0x140, 0xF, 0xF, true);
+  }
 }
 
 template <int CPL, int L>
@@ -446,7 +452,7 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL, NT>& rw, const 
     if (team_leader(L)) st.u_nit++;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
-      const uint32_t cb = contact_bits<NT>(act[k]);
+      const uint32_t cb = contact_bits<NT, L>(act[k]);
       st.u_ncon += rw.first[k] && cb != 0u;
       st.u_nedge += __popc(act[k]);
     }
@@ -578,9 +584,10 @@ DMX_DEV void free_newton(const FreeModel& m, const FreeRows<CPL, NT>& rw, const 
 template <int NC, int L>
 struct FreePhys {
   static constexpr int NQ = 7, NV = 6, TEAM = L;
-  // a team of 16 lanes for 8 slots holds each contact on two lanes (one
-  // tangent direction each); otherwise slot c sits on lane c mod L
-  static constexpr int NT = (L == 16 && 2 * NC == L) ? 1 : 2;
+  // a team of 8 or 16 lanes for half as many slots holds each contact on a
+  // lane and its mirror lane (one tangent direction each); otherwise slot c
+  // sits on lane c mod L
+  static constexpr int NT = ((L == 8 || L == 16) && 2 * NC == L) ? 1 : 2;
   static constexpr int CPL = NT == 1 ? 1 : (NC + L - 1) / L;
   static constexpr int LIVE = NT == 1 ? L : live_lanes(NC, L);  // lanes that hold slots
   using Model = FreeModel;

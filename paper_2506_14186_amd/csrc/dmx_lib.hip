@@ -214,7 +214,7 @@ struct KernelEntry {
    &launch_acc<dmx::TreePhys<NV, NB, NC, L>>, &fwd_resident_teams<dmx::TreePhys<NV, NB, NC, L>>}
 
 const KernelEntry kKernels[] = {
-    FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4),
+    FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4), FREE_ENTRY(4, 8),
     FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(8, 16), FREE_ENTRY(16, 8),
     FREE_ENTRY(16, 16),
     // planar legged chain (7 joints, 5 bodies, 4 foot contact slots); 3-link test pendulum
@@ -629,10 +629,9 @@ static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
 
 // Kernel for a model and team size (lanes per world).  Default team: tree
 // worlds keep their kinematic workspace in LDS and take 8 lanes; free bodies
-// take one contact slot per lane (up to 16).  Wider teams for small batches
-// (more wavefronts, fewer worlds per wavefront) measured slower on the cube
-// batch: the per-wavefront instruction stream is the same and the extra
-// wavefronts contend for their compute units' shared front end.
+// take two lanes per contact slot where such a team is compiled (each lane
+// one tangent direction: the cube with 16 lanes, the box geom with 8),
+// otherwise one slot per lane (up to 16).
 static const KernelEntry* find_kernel(const dmx_model* m, int team) {
   if (team > 0) return lookup_kernel(m, team);
   if (const int t = m->tuned_team.load()) return lookup_kernel(m, t);
@@ -640,6 +639,8 @@ static const KernelEntry* find_kernel(const dmx_model* m, int team) {
     if (const KernelEntry* k = lookup_kernel(m, 8)) return k;
     return lookup_kernel(m, 4);
   }
+  if (2 * m->ncb <= 16)
+    if (const KernelEntry* k = lookup_kernel(m, 2 * m->ncb)) return k;
   return lookup_kernel(m, m->ncb >= 16 ? 16 : m->ncb);
 }
 
