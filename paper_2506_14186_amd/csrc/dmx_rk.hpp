@@ -194,12 +194,14 @@ DMX_DEV void store_ubar(const typename P::Model& m, const double* tb, double* ds
   }
 }
 
-// dst[i] = src[i] for the team lane owning index i (compile-time indices)
+// dst[i] = src[i] for a team-replicated array: every lane of the team stores
+// every element (the lanes hold bitwise-equal values, and one store
+// instruction writes each address once), so no per-element lane selection
 template <int N, int L>
 DMX_DEV void team_store(double* dst, const double* src, int tl) {
+  (void)tl;
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    if ((i & (L - 1)) == tl) dst[i] = src[i];
+  for (int i = 0; i < N; ++i) dst[i] = src[i];
 }
 
 // Coefficients of stage i (a[i][l], (A A)[i][l], c[i]), selected by a
