@@ -493,10 +493,13 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
           if (tl == 0) { rec[0] = t; rec[1] = h; rec[2] = (double)kk; }
           team_store<NX, L>(rec + 3, y, tl);
           if (a.rec >= 3 + NX + 6 * NV) {  // stage accelerations (else a checkpoint-only tape)
-            double Acp[6 * NV];
+            // from LDS, entry j by lane j mod L
+            const double* Af = &A[0][0];
 #pragma unroll
-            for (int j = 0; j < 6 * NV; ++j) Acp[j] = A[j / NV][j % NV];
-            team_store<6 * NV, L>(rec + 3 + NX, Acp, tl);
+            for (int r = 0; r < (6 * NV + L - 1) / L; ++r) {
+              const int j = tl + r * L;
+              if (j < 6 * NV) rec[3 + NX + j] = Af[j];
+            }
           }
         }
 #pragma unroll
@@ -622,11 +625,14 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll
         for (int d = 0; d < NV; ++d) A[i][d] = ai[d];
       }
-    } else {
+    } else {  // stage accelerations into LDS, entry j by lane j mod L
+      double* Af = &A[0][0];
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
-#pragma unroll
-        for (int d = 0; d < NV; ++d) A[j][d] = rec[3 + NX + j * NV + d];
+      for (int r = 0; r < (6 * NV + L - 1) / L; ++r) {
+        const int j = tl + r * L;
+        if (j < 6 * NV) Af[j] = rec[3 + NX + j];
+      }
+      wave_fence();
     }
 #pragma unroll
     for (int d = 0; d < NV; ++d) A[6][d] = 0.0;
