@@ -145,20 +145,12 @@ DMX_DEV double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum over the L lanes of a team; every lane receives the bitwise-same value.
-template <int L>
-DMX_DEV double team_sum(double v) {
-  if constexpr (L >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
-  if constexpr (L >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
-  if constexpr (L >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: other quad of 8
-  if constexpr (L >= 16) v += dpp_f64<0x140>(v); // row_mirror: other half of 16
-  if constexpr (L >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (L >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
-// N independent team sums, level by level (the N butterflies interleave
-// instead of running one after another); each result equals team_sum's.
+// One butterfly level of N independent team sums: each value adds its
+// partner lane's (levels: quad_perm [1,0,3,2] = lane ^ 1, quad_perm [2,3,0,1]
+// = lane ^ 2, row_half_mirror = the other quad of 8, row_mirror = the other
+// half of 16).  Sums are commutative pairwise, so every lane of the team ends
+// with the bitwise-same value; running level by level lets the N butterflies
+// interleave instead of running one after another.
 template <int CTRL, int N>
 DMX_DEV void butterfly_level(double* v) {
   double t[N];
