@@ -59,6 +59,28 @@ def test_free_fall_parabola(oracle):
     np.testing.assert_allclose(r["x"][7:10], v, rtol=1e-14, atol=1e-14)
 
 
+def test_paper_settings_are_the_defaults(oracle):
+    """The printed controller and contact settings (tests/golden/paper_settings.json,
+    App. E.1) are what the oracle, the library and the cube workloads use: the
+    step factor safety * err^-(P+I)/k * err_prev^(P)/k of a PID controller with
+    D = 0 has exponents kP + kI = P + I and kP = P; the cube's pairs carry the
+    printed solimp and damping ratio (its time constant is the benchmark's)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_settings.json")))
+    P, I, Dd = g["pid"]["P"], g["pid"]["I"], g["pid"]["D"]
+    assert Dd == 0.0
+    assert oracle.DEFAULT_OPTS["kP"] == P and oracle.DEFAULT_OPTS["kI"] == I
+    from paper_2506_14186_amd import dmx as D
+    o = D.default_opts()
+    assert (o.kP, o.kI) == (P, I)
+    desc = W.model_cube_corners()
+    for pr in desc["pairs"]:
+        assert pr["solimp"] == g["cube_toss_contact"]["solimp"]
+        assert pr["solref"][1] == g["cube_toss_contact"]["solref"][1]
+    assert W.SOLIMP_DEFAULT == g["cube_toss_contact"]["solimp"]
+
+
 def test_controller_free_fall_step_sequence(oracle):
     """PI controller with P=0.2, I=0.4 (App. E.1) at roundoff-level error:
     growth factor 0.9 * floor^(-0.12) * eprev^(0.04), first with eprev = 1."""
