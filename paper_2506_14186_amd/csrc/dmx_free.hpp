@@ -809,13 +809,30 @@ struct FreePhys {
     Q4 r = qnormalize(w, nullptr);
     out[3] = r.w; out[4] = r.x; out[5] = r.y; out[6] = r.z;
   }
+  // (+) that also keeps the half-angle exponential's coefficients and their
+  // derivatives, for the VJP at the same increment
+  struct QPlusKeep { double c, s, dc, ds; };
+  DMX_DEV static void qplus_keep(const double* q, const double* dq, double* out, QPlusKeep* k) {
+    out[0] = q[0] + dq[0]; out[1] = q[1] + dq[1]; out[2] = q[2] + dq[2];
+    Q4 e = qexp_half(mk3(dq[3], dq[4], dq[5]), &k->c, &k->s, &k->dc, &k->ds);
+    Q4 w = qmul(mkq(q[3], q[4], q[5], q[6]), e);
+    Q4 r = qnormalize(w, nullptr);
+    out[3] = r.w; out[4] = r.x; out[5] = r.y; out[6] = r.z;
+  }
   // qbar += d out / d q ^T ob ; dqb = d out / d dq ^T ob
-  DMX_DEV static void qplus_vjp(const double* q, const double* dq, const double* ob, double* qbar, double* dqb) {
+  DMX_DEV static void qplus_vjp(const double* q, const double* dq, const double* ob, double* qbar, double* dqb,
+                                const QPlusKeep* kept = nullptr) {
     qbar[0] += ob[0]; qbar[1] += ob[1]; qbar[2] += ob[2];
     dqb[0] = ob[0]; dqb[1] = ob[1]; dqb[2] = ob[2];
     V3 th = mk3(dq[3], dq[4], dq[5]);
     double c, s, dc, ds;
-    Q4 e = qexp_half(th, &c, &s, &dc, &ds);
+    Q4 e;
+    if (kept) {
+      c = kept->c; s = kept->s; dc = kept->dc; ds = kept->ds;
+      e = mkq(c, s * th.x, s * th.y, s * th.z);
+    } else {
+      e = qexp_half(th, &c, &s, &dc, &ds);
+    }
     Q4 q4 = mkq(q[3], q[4], q[5], q[6]);
     Q4 w = qmul(q4, e);
     double inv;

@@ -254,9 +254,11 @@ DMX_DEV void stage_sums(const double (*A)[P::NV], int i, const StageCoef& k, int
   *sq_out = sq;
 }
 
-// stage state Y_i from y_n and the stage accelerations A[0..i-1] (i >= 1)
+// stage state Y_i from y_n and the stage accelerations A[0..i-1] (i >= 1);
+// with keep, the (+) map's exponential coefficients for its VJP
 template <class P>
-DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq) {
+DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq,
+                         typename P::QPlusKeep* keep = nullptr) {
   constexpr int NQ = P::NQ, NV = P::NV, L = P::TEAM;
   const StageCoef k = stage_coef(i);
   double sv[NV], sq[NV];
@@ -281,7 +283,8 @@ DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, doubl
     Y[NQ + d] = y[NQ + d] + h * sv[d];
     dq[d] = h * (k.c * y[NQ + d] + h * sq[d]);
   }
-  P::qplus(y, dq, Y);
+  if (keep) P::qplus_keep(y, dq, Y, keep);
+  else P::qplus(y, dq, Y);
 }
 
 // cotangents of stage i's combination: v_bar from its velocity part and the
@@ -647,9 +650,11 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll 1
     for (int i = 6; i >= 0; --i) {
       double Y[NX], dq[NV];
+      typename P::QPlusKeep qk;
       if (i < 6) {
-        stage_state<P>(y, A, i, h, Y, dq);
-        if (i == 0) {
+        if (i > 0) {
+          stage_state<P>(y, A, i, h, Y, dq, &qk);
+        } else {  // stage 0 is the step's start state
 #pragma unroll
           for (int j = 0; j < NX; ++j) Y[j] = y[j];
         }
@@ -660,7 +665,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll
         for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
       } else {
-        stage_state<P>(y, A, 6, h, Y, dq);
+        stage_state<P>(y, A, 6, h, Y, dq, &qk);
       }
       if (i == 0) {
 #pragma unroll
@@ -669,7 +674,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         for (int d = 0; d < NV; ++d) vb[d] += Ybar[NQ + d];
       } else {
         double dqb[NV];
-        P::qplus_vjp(y, dq, Ybar, qb, dqb);
+        P::qplus_vjp(y, dq, Ybar, qb, dqb, &qk);
         stage_distribute<P>(i, Ybar, dqb, h, vb, Ab);
       }
     }

@@ -987,7 +987,10 @@ struct TreePhys {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) out[i] = q[i] + dq[i];
   }
-  DMX_DEV static void qplus_vjp(const double* q, const double* dq, const double* ob, double* qbar, double* dqb) {
+  struct QPlusKeep {};
+  DMX_DEV static void qplus_keep(const double* q, const double* dq, double* out, QPlusKeep*) { qplus(q, dq, out); }
+  DMX_DEV static void qplus_vjp(const double* q, const double* dq, const double* ob, double* qbar, double* dqb,
+                                const QPlusKeep* = nullptr) {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) { qbar[i] += ob[i]; dqb[i] = ob[i]; }
   }
