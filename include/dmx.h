@@ -108,7 +108,7 @@ typedef struct dmx_tape dmx_tape;
  * facmin 0.2, facmax 10, kP 0.2, kI 0.4, err_order 5, err_floor 1e-6,
  * max_attempts 1e6, newton_maxit 100, cfd 0, softplus_beta 1e4,
  * tape_steps 0 (= chosen by the library), lanes_per_world 0 (= per model),
- * h_levels 16, tape_stages -1, work_queue 0. */
+ * h_levels 0 (the continuous controller), tape_stages -1, work_queue 0. */
 typedef struct {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor;
   int64_t max_attempts;
@@ -140,15 +140,19 @@ typedef struct {
   /* 0: all worlds in one launch (default); 1: one launch per world on the
    * stream, the plain baseline form of the same kernels. */
   int32_t launch_mode;
-  /* step-size grid: the controller's proposed steps are rounded down to
-   * h_levels mantissa values per octave (0: continuous); default 16. */
+  /* step-size grid (opt-in reproducibility mode, not part of the paper's
+   * controller): the controller's proposed steps are rounded down to h_levels
+   * mantissa values per octave, so that step sequences do not depend on
+   * rounding-level differences of the error estimate between two
+   * implementations; 0 (default): the continuous controller. */
   int32_t h_levels;
   /* failure capture (device, may be NULL): [n_worlds][nq + nv + nv] receives
    * the stage state and generalized force at which a world's contact solve
    * first failed (status bits NONFINITE or SOLVER_MAXIT). */
   double* fail_state;
-  /* ragged batches and work distribution (device pointers, may be NULL; the
-   * tape keeps both pointers, so they must stay valid while it is used):
+  /* ragged batches and work distribution (device pointers, may be NULL; a
+   * tape keeps its own copies, so they need only stay valid until the
+   * rollout's work on the stream is done):
    * world_intervals [n_worlds]: control intervals world w simulates (at most
    * n_intervals; its controls are the first entries of u[w], its x_out is the
    * state at world_intervals[w] * interval_dt, its u_bar beyond them is 0);

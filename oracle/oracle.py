@@ -52,7 +52,7 @@ class _Opts(C.Structure):
 
 DEFAULT_OPTS = dict(rtol=1e-6, atol=1e-8, h0=1e-3, safety=0.9, facmin=0.2, facmax=10.0, kP=0.2, kI=0.4,
                     err_order=5.0, err_floor=1e-6, max_attempts=1_000_000, newton_maxit=100, cfd=0,
-                    softplus_beta=1e4, h_levels=16)
+                    softplus_beta=1e4, h_levels=0)
 
 _lib = None
 
@@ -73,7 +73,7 @@ def lib():
         L.orc_contacts.argtypes = [P, P, P]
         L.orc_point_jac.argtypes = [P, P, C.c_int, P, P]
         L.orc_rhs.argtypes = [P, P, P, C.c_int, P, P, P]
-        L.orc_rows.argtypes = [P, P, P, C.c_int, P, P, P, P, P]
+        L.orc_rows.argtypes = [P, P, P, C.c_int, C.c_double, P, P, P, P, P]
         L.orc_rhs_jvp.argtypes = [P, P, P, C.c_int, C.c_double, C.c_int, P, P, P, P]
         L.orc_rollout.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, C.c_int, P, P,
                                   C.c_int, P, C.c_int, P]
@@ -81,6 +81,13 @@ def lib():
         L.orc_rollout_batch.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, P, C.c_int]
         L.orc_grad_batch.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, P, P, P, P,
                                      C.c_int]
+        L.orc_grad_forced_batch.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, P, C.c_int,
+                                            P, P, P, P, P, C.c_int]
+        L.orc_rollout_jvp_forced.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, C.c_int, C.c_int,
+                                             P, P, P, P]
+        L.orc_attempt.argtypes = [P, P, P, C.c_double, C.POINTER(_Opts), P, P]
+        L.orc_next_step.argtypes = [C.POINTER(_Opts), C.c_double, C.c_double, C.c_double, C.c_int, P]
+        L.orc_next_step.restype = C.c_double
         _lib = L
     return _lib
 
@@ -192,12 +199,12 @@ class Model:
         return xd, dict(n_rows=int(info[0]), n_active=int(info[1]), newton_it=int(info[2]), status=int(info[3]),
                         forces=forces[:info[0]].copy())
 
-    def rows(self, x, u=None, cfd=False):
+    def rows(self, x, u=None, cfd=False, beta=1e4):
         u = _f64(u if u is not None else np.zeros(max(self.nu, 1)))
         nrmax = 4 * max(self.ncmax, 1)
         M, a0 = np.zeros((self.nv, self.nv)), np.zeros(self.nv)
         J, aref, D = np.zeros((nrmax, self.nv)), np.zeros(nrmax), np.zeros(nrmax)
-        n = lib().orc_rows(self.h, _p(_f64(x)), _p(u), int(cfd), _p(M), _p(a0), _p(J), _p(aref), _p(D))
+        n = lib().orc_rows(self.h, _p(_f64(x)), _p(u), int(cfd), float(beta), _p(M), _p(a0), _p(J), _p(aref), _p(D))
         return dict(M=M, a0=a0, J=J[:n], aref=aref[:n], D=D[:n])
 
     def rhs_jvp(self, x, u, dx, du=None, st=False, beta=1e4):
@@ -243,6 +250,22 @@ class Model:
                               _p(du), _p(xo), _p(tx), _p(cnt))
         return dict(x=xo, tx=tx, n_acc=int(cnt[0]), n_rej=int(cnt[1]), status=int(cnt[4]))
 
+    def rollout_jvp_forced(self, x0, u, n_int, dt, forced, dx0, du=None, **opts):
+        """Tangents [n_dir][nx] of the final state along (dx0, du) for the frozen
+        step sequence forced [n][2]; returns (x_out, tangents)."""
+        o = make_opts(**opts)
+        dx0 = np.ascontiguousarray(np.atleast_2d(np.asarray(dx0, np.float64).reshape(-1, self.nx)))
+        nd = dx0.shape[0]
+        nut = n_int * self.nu
+        du = _f64(du) if du is not None else np.zeros(nd * max(nut, 1))
+        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        fz = np.ascontiguousarray(forced, np.float64)
+        xo, tx = np.zeros(self.nx), np.zeros((nd, self.nx))
+        st = lib().orc_rollout_jvp_forced(self.h, _p(_f64(x0)), _p(u), int(n_int), float(dt), C.byref(o), _p(fz),
+                                          int(fz.shape[0]), nd, _p(dx0), _p(du), _p(xo), _p(tx))
+        assert st == 0, st
+        return xo, tx
+
     def rollout_batch(self, x0, u, n_int, dt, n_threads=1, **opts):
         o = make_opts(**opts)
         x0 = np.ascontiguousarray(x0, np.float64)
@@ -268,3 +291,39 @@ class Model:
                              _p(x0b), _p(ub), _p(cnt), int(n_threads))
         return dict(x=xo, x0bar=x0b, ubar=ub[:, :nut].reshape(W, n_int, self.nu), n_acc=cnt[:, 0],
                     n_rej=cnt[:, 1], n_rhs=cnt[:, 2], status=cnt[:, 4])
+
+    def grad_forced_batch(self, x0, u, n_int, dt, xbar, forced, forced_n, n_threads=1, **opts):
+        """Gradients along given accepted-step sequences: forced [W][cap][2]
+        (t_n, h_n), forced_n [W] steps per world (the controller is off)."""
+        o = make_opts(**opts)
+        x0 = np.ascontiguousarray(x0, np.float64)
+        W = x0.shape[0]
+        nut = n_int * self.nu
+        u = np.ascontiguousarray(u, np.float64) if nut else np.zeros((W, 1))
+        xbar = np.ascontiguousarray(np.broadcast_to(xbar, x0.shape), np.float64)
+        fz = np.ascontiguousarray(forced, np.float64)
+        fn = _i32(forced_n)
+        xo, x0b = np.zeros_like(x0), np.zeros_like(x0)
+        ub = np.zeros((W, max(nut, 1)))
+        cnt = np.zeros((W, 5), np.int64)
+        lib().orc_grad_forced_batch(self.h, W, _p(x0), _p(u), int(n_int), float(dt), C.byref(o), _p(fz), _p(fn),
+                                    int(fz.shape[1]), _p(xbar), _p(xo), _p(x0b), _p(ub), _p(cnt), int(n_threads))
+        return dict(x=xo, x0bar=x0b, ubar=ub[:, :nut].reshape(W, n_int, self.nu), n_acc=cnt[:, 0],
+                    status=cnt[:, 4])
+
+    def attempt(self, y, u, h, **opts):
+        """One attempt from y with step h: (5th-order state, error norm, status)."""
+        o = make_opts(**opts)
+        u = _f64(u if u is not None and np.size(u) else np.zeros(max(self.nu, 1)))
+        yn = np.zeros(self.nx)
+        err = C.c_double()
+        st = lib().orc_attempt(self.h, _p(_f64(y)), _p(u), float(h), C.byref(o), _p(yn), C.byref(err))
+        return yn, err.value, st
+
+
+def next_step(err, eprev, h, accepted, **opts):
+    """The oracle controller's next proposed step and its new memory e_prev."""
+    o = make_opts(**opts)
+    ep = C.c_double()
+    hn = lib().orc_next_step(C.byref(o), float(err), float(eprev), float(h), int(accepted), C.byref(ep))
+    return hn, ep.value

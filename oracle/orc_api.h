@@ -50,7 +50,8 @@ typedef struct {
   int newton_maxit;
   int cfd;              /* 1: straight-through contacts-from-distance in the derivative */
   double softplus_beta; /* sharpness of the softplus position term of the CFD force */
-  int h_levels;         /* proposed step sizes rounded down to this many mantissa levels per octave (0: off) */
+  int h_levels;         /* proposed step sizes rounded down to this many mantissa levels per octave (0: off,
+                           the default: the continuous controller) */
 } orc_opts;
 
 enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8 };
@@ -73,8 +74,9 @@ void orc_point_jac(const void* m, const double* q, int body, const double* point
 /* right-hand side F(x) = (v, qacc); info = n_rows, n_active, newton_iterations, status */
 int orc_rhs(const void* m, const double* x, const double* u, int cfd, double* xdot, int* info,
             double* forces);
-/* the primal problem at x: M (nv*nv), a0 (nv), rows J (n*nv), aref (n), D (n); returns n */
-int orc_rows(const void* m, const double* x, const double* u, int cfd, double* M, double* a0, double* J,
+/* the primal problem at x (cfd: the contacts-from-distance rows with softplus sharpness beta):
+ * M (nv*nv), a0 (nv), rows J (n*nv), aref (n), D (n); returns n */
+int orc_rows(const void* m, const double* x, const double* u, int cfd, double beta, double* M, double* a0, double* J,
              double* aref, double* D);
 /* directional derivatives of F: value of F (cfd=0 rule) and, per direction, the
  * tangent of F (or of the CFD field when st=1: straight-through). */
@@ -93,12 +95,27 @@ int orc_rollout(const void* m, const double* x0, const double* u, int n_int, dou
 int orc_rollout_jvp(const void* m, const double* x0, const double* u, int n_int, double dt_int,
                     const orc_opts* o, int n_dir, const double* dx0, const double* du, double* x_out,
                     double* tx, long long* counters);
+/* the same along a given frozen step sequence forced [n_forced][2] = (t_n, h_n) */
+int orc_rollout_jvp_forced(const void* m, const double* x0, const double* u, int n_int, double dt_int,
+                           const orc_opts* o, const double* forced, int n_forced, int n_dir, const double* dx0,
+                           const double* du, double* x_out, double* tx);
 /* batched value rollouts and batched gradients J^T xbar over worlds, on n_threads host threads */
 int orc_rollout_batch(const void* m, int n_worlds, const double* x0, const double* u, int n_int,
                       double dt_int, const orc_opts* o, double* x_out, long long* counters, int n_threads);
 int orc_grad_batch(const void* m, int n_worlds, const double* x0, const double* u, int n_int, double dt_int,
                    const orc_opts* o, const double* xbar, double* x_out, double* x0bar, double* ubar,
                    long long* counters, int n_threads);
+/* the same along given accepted-step sequences forced [n_worlds][forced_cap][2] = (t_n, h_n),
+ * forced_n [n_worlds] steps each (controller off) */
+int orc_grad_forced_batch(const void* m, int n_worlds, const double* x0, const double* u, int n_int, double dt_int,
+                          const orc_opts* o, const double* forced, const int* forced_n, int forced_cap,
+                          const double* xbar, double* x_out, double* x0bar, double* ubar, long long* counters,
+                          int n_threads);
+/* one attempt from y with step h (first stage evaluated at y): 5th-order state and error norm */
+int orc_attempt(const void* m, const double* y, const double* u, double h, const orc_opts* o, double* ynew,
+                double* err);
+/* the controller's next proposed step after an attempt (eprev_out: its memory for the next one) */
+double orc_next_step(const orc_opts* o, double err, double eprev, double h, int accepted, double* eprev_out);
 
 #ifdef __cplusplus
 }

@@ -256,39 +256,51 @@ template <class S> static S smoothstep01(S t) {
   return t * t * (3.0 - 2.0 * t);
 }
 
-// Smoothed plane-box detection, following the algorithm printed in App. D.1:
-// vertex supports below the plane, a soft mask that keeps the vertices within
-// a 1 mm skin of the deepest one, the four largest masked supports, and
-// contact points moved to the midpoint.  reading: the soft mask is the C^1
-// smoothstep between its bounds; top-4 ties go to the lower vertex index;
-// vertex k has coordinate signs (+ if bit set) x: bit 0, y: bit 1, z: bit 2.
+// Plane-box contacts by the smoothed four-deepest-vertex rule of App. C.1,
+// where the paper replaces the hard case split of plane-box detection by a
+// soft selection.  Stated in the world frame: vertex k sits at
+// x_k = c + R s_k (s_k the half-size corner with coordinate signs from the
+// bits of k: x bit 0, y bit 1, z bit 2) and penetrates the plane by
+// e_k = -n.(x_k - p0).  Vertices within a 1 mm skin of the deepest one keep
+// their depth: with the threshold tau = max(0, e_max - 1e-3), the weight w_k
+// rises smoothly from 0 at depth tau - 1e-3 to 1 at tau (reading: the C^1
+// smoothstep t^2 (3 - 2t) for the unnamed sigmoid), and the contacts are the
+// four largest weighted depths z_k = w_k e_k (reading: equal values go to the
+// lower vertex index), each with signed distance r = -z_k and its point
+// halfway between the vertex and the plane, x_k + (z_k / 2) n.  A vertex
+// whose weighted depth is 0 gives an inactive contact (r = 0).
 template <class S>
 static void box_plane(const V3<S>& p0, const V3<S>& nw, const V3<S>& c, const M3<S>& R, const V3<double>& hs,
                       int pair, std::vector<Contact<S>>& out) {
-  V3<S> ppl = matTvec(R, sub(p0, c));
-  V3<S> nl = matTvec(R, nw);
-  V3<S> vert[8];
-  S sup[8];
+  V3<S> x[8];
+  S depth[8];
   for (int k = 0; k < 8; ++k) {
-    vert[k] = v3<S>(S((k & 1) ? hs.x[0] : -hs.x[0]), S((k & 2) ? hs.x[1] : -hs.x[1]), S((k & 4) ? hs.x[2] : -hs.x[2]));
-    sup[k] = dot(sub(ppl, vert[k]), nl);
+    V3<double> s = v3<double>((k & 1) ? hs.x[0] : -hs.x[0], (k & 2) ? hs.x[1] : -hs.x[1],
+                              (k & 4) ? hs.x[2] : -hs.x[2]);
+    x[k] = add(c, matvec(R, lift<S>(s)));
+    depth[k] = S(0.0) - dot(nw, sub(x[k], p0));
   }
-  int imax = 0;
-  for (int k = 1; k < 8; ++k) if (val(sup[k]) > val(sup[imax])) imax = k;
-  S thr = val(sup[imax]) - 1e-3 > 0.0 ? sup[imax] - 1e-3 : S(0.0);
-  S lo = thr - 1e-3, hi = thr;
-  S sm[8];
+  double emax = val(depth[0]);
+  int kmax = 0;
+  for (int k = 1; k < 8; ++k)
+    if (val(depth[k]) > emax) { emax = val(depth[k]); kmax = k; }
+  const double skin = 1e-3;
+  S tau = emax > skin ? depth[kmax] - skin : S(0.0);
+  S z[8];
   for (int k = 0; k < 8; ++k) {
-    S mask = smoothstep01((sup[k] - lo) / (hi - lo));
-    sm[k] = mask * sup[k] + (1.0 - mask) * 0.0;
+    S w = smoothstep01((depth[k] - (tau - skin)) / skin);
+    z[k] = w * depth[k];
   }
-  int idx[8] = {0, 1, 2, 3, 4, 5, 6, 7};
-  std::stable_sort(idx, idx + 8, [&](int a, int b) { return val(sm[a]) > val(sm[b]); });
+  // rank by weighted depth, deepest first; equal values keep vertex order
+  std::vector<int> order = {0, 1, 2, 3, 4, 5, 6, 7};
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return val(z[a]) > val(z[b]) || (val(z[a]) == val(z[b]) && a < b);
+  });
   for (int i = 0; i < 4; ++i) {
-    int k = idx[i];
+    const int k = order[i];
     Contact<S> ct;
-    ct.r = -sm[k];
-    ct.pos = sub(add(c, matvec(R, vert[k])), scale(nw, ct.r * 0.5));
+    ct.r = S(0.0) - z[k];
+    ct.pos = add(x[k], scale(nw, z[k] * 0.5));
     ct.n = nw;
     make_frame(nw, ct.t1, ct.t2);
     ct.pair = pair;
@@ -299,7 +311,7 @@ static void box_plane(const V3<S>& p0, const V3<S>& nw, const V3<S>& c, const M3
 // Candidate contacts of every listed pair (Sec. 2.1, "Collision detection"),
 // in pair order with a fixed number of slots per pair type.  reading: a
 // capsule against a plane emits both cap-centre spheres (+axis end first),
-// with no case split (the smoothing of App. D.1 is then unnecessary).
+// with no case split (the smoothing of App. C.1 is then unnecessary).
 template <class S>
 static void collide(const Model& m, const Kin<S>& k, std::vector<Contact<S>>& out) {
   out.clear();
@@ -528,7 +540,7 @@ struct Opts {
   int newton_maxit = 100;
   bool cfd = false;
   double beta = 1e4;
-  int h_levels = 16;
+  int h_levels = 0;
 };
 
 // reading: the controller's proposed step is rounded down to a grid of
@@ -741,6 +753,25 @@ static bool finite_vec(const double* x, int n) {
   return true;
 }
 
+// The step-size controller (App. E.1 names Diffrax's PID controller with
+// P = 0.2, I = 0.4, D = 0).  reading (PI form, D = 0): the step factor is
+// fac = safety * e^(-(kP + kI)/K) * e_prev^(kP/K) with K = err_order = 5,
+// clipped to [facmin, facmax]; e = max(eps, err_floor) (a non-finite eps, a
+// failed trial solve, counts as 1e300); e_prev starts at 1 and takes e on
+// acceptance.  The next proposed step is fac h after an acceptance and
+// min(1, fac) h after a rejection, optionally rounded down to the step grid.
+static double next_step(const Opts& o, double err, double eprev, double h, bool accepted, double* eprev_out) {
+  const double et = std::isfinite(err) ? std::max(err, o.err_floor) : 1e300;
+  double fac = o.safety * std::pow(et, -(o.kP + o.kI) / o.err_order) * std::pow(eprev, o.kP / o.err_order);
+  fac = std::min(o.facmax, std::max(o.facmin, fac));
+  if (accepted) {
+    *eprev_out = et;
+    return quantize_step(fac * h, o.h_levels);
+  }
+  *eprev_out = eprev;
+  return quantize_step(std::min(1.0, fac) * h, o.h_levels);
+}
+
 // Adaptive rollout over piecewise-constant control intervals (Sec. 3.1: an
 // embedded pair accepts a step when its error estimate is within tolerance,
 // otherwise retries with a controller-chosen step; App. E.1 names the PID
@@ -793,9 +824,7 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
         err = HUGE_VAL;
       }
       bool accept = forced ? true : (err <= 1.0);
-      double et = std::isfinite(err) ? std::max(err, o.err_floor) : 1e300;
-      double fac = o.safety * std::pow(et, -(o.kP + o.kI) / o.err_order) * std::pow(eprev, o.kP / o.err_order);
-      fac = std::min(o.facmax, std::max(o.facmin, fac));
+      const double hnext = next_step(o, err, eprev, h, accept, &eprev);
       if (lg && lg->keep_log) { lg->steplog.push_back(t); lg->steplog.push_back(h); lg->steplog.push_back(err);
                                 lg->steplog.push_back(accept ? 1.0 : 0.0); }
       if (accept) {
@@ -806,13 +835,12 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
         y = yn;
         k1 = k7;
         t = landing ? tend : t + h;
-        eprev = et;
-        hprop = quantize_step(fac * h, o.h_levels);
+        hprop = hnext;
         for (int i = 0; i < nx; ++i) yv[i] = val(y[i]);
         if (!finite_vec(yv.data(), nx)) { st->status |= ORC_NONFINITE; break; }
       } else {
         if (lg) lg->n_rej++;
-        hprop = quantize_step(std::min(1.0, fac) * h, o.h_levels);
+        hprop = hnext;
       }
       if (!forced && hprop < 1e-12 * std::max(1.0, std::fabs(t))) { st->status |= ORC_DT_UNDERFLOW; break; }
     }
@@ -976,7 +1004,7 @@ extern "C" int orc_rhs(const void* mp, const double* x, const double* u, int cfd
   return st.status;
 }
 
-extern "C" int orc_rows(const void* mp, const double* x, const double* u, int cfd, double* M, double* a0,
+extern "C" int orc_rows(const void* mp, const double* x, const double* u, int cfd, double beta, double* M, double* a0,
                         double* J, double* aref, double* D) {
   const Model& m = *static_cast<const Model*>(mp);
   int nv = m.nv;
@@ -994,7 +1022,7 @@ extern "C" int orc_rows(const void* mp, const double* x, const double* u, int cf
   std::vector<Contact<double>> cons;
   collide(m, kin, cons);
   std::vector<Row<double>> rows;
-  make_rows(m, kin, cons, x + m.nq, cfd != 0, 1e4, rows);
+  make_rows(m, kin, cons, x + m.nq, cfd != 0, beta, rows);
   for (size_t e = 0; e < rows.size(); ++e) {
     for (int i = 0; i < nv; ++i) J[e * nv + i] = rows[e].J[i];
     aref[e] = rows[e].aref; D[e] = rows[e].D;
@@ -1108,8 +1136,50 @@ extern "C" int orc_rollout_batch(const void* mp, int W, const double* x0, const 
   return 0;
 }
 
-// Gradient J^T xbar of the final state w.r.t. (x0, u) per world: the full
-// Jacobian is formed by forward-mode passes of kDir unit directions.
+// Gradient J^T xbar of the final state w.r.t. (x0, u) of one world along the
+// frozen accepted-step sequence f = (t_n, h_n): the full Jacobian is formed by
+// forward-mode passes of kDir unit directions.
+static int grad_world(const Model& m, const double* xw, const double* uw, int n_int, double dt, const Opts& o,
+                      const std::vector<double>& f, const double* xb, double* x0b, double* ub, long long* nrhs) {
+  int nx = m.nq + m.nv;
+  size_t nut = (size_t)n_int * m.nu;
+  size_t nin = nx + nut;
+  int status = 0;
+  std::vector<double> dx0(kDir * nx), du(kDir * std::max<size_t>(nut, 1)), tx(kDir * nx);
+  for (size_t c0 = 0; c0 < nin && !status; c0 += kDir) {
+    int nd = (int)std::min<size_t>(kDir, nin - c0);
+    std::fill(dx0.begin(), dx0.end(), 0.0);
+    std::fill(du.begin(), du.end(), 0.0);
+    for (int d = 0; d < nd; ++d) {
+      size_t idx = c0 + d;
+      if (idx < (size_t)nx) dx0[d * nx + idx] = 1.0; else du[d * nut + (idx - nx)] = 1.0;
+    }
+    Stats s2;
+    jvp_pass(m, xw, uw, n_int, dt, o, f, nd, dx0.data(), du.data(), nullptr, tx.data(), &s2);
+    status |= s2.status; *nrhs += s2.rhs;
+    for (int d = 0; d < nd; ++d) {
+      double g = 0.0;
+      for (int i = 0; i < nx; ++i) g += xb[i] * tx[d * nx + i];
+      size_t idx = c0 + d;
+      if (idx < (size_t)nx) x0b[idx] = g; else ub[idx - nx] = g;
+    }
+  }
+  return status;
+}
+
+// Forward-mode tangents of one rollout along a given frozen step sequence.
+extern "C" int orc_rollout_jvp_forced(const void* mp, const double* x0, const double* u, int n_int, double dt_int,
+                                      const orc_opts* op, const double* forced, int n_forced, int n_dir,
+                                      const double* dx0, const double* du, double* x_out, double* tx) {
+  const Model& m = *static_cast<const Model*>(mp);
+  if (n_dir > kDir) return -1;
+  Opts o = to_opts(op);
+  std::vector<double> f(forced, forced + 2 * (size_t)n_forced);
+  Stats st;
+  return jvp_pass(m, x0, u, n_int, dt_int, o, f, n_dir, dx0, du, x_out, tx, &st);
+}
+
+// Gradients of every world of a batch along the world's own adaptive run.
 extern "C" int orc_grad_batch(const void* mp, int W, const double* x0, const double* u, int n_int, double dt_int,
                               const orc_opts* op, const double* xbar, double* x_out, double* x0bar, double* ubar,
                               long long* counters, int n_threads) {
@@ -1117,7 +1187,6 @@ extern "C" int orc_grad_batch(const void* mp, int W, const double* x0, const dou
   Opts o = to_opts(op);
   int nx = m.nq + m.nv;
   size_t nut = (size_t)n_int * m.nu;
-  size_t nin = nx + nut;
   parallel_for(W, n_threads, [&](int w) {
     const double* xw = x0 + (size_t)w * nx;
     const double* uw = u + w * nut;
@@ -1125,27 +1194,61 @@ extern "C" int orc_grad_batch(const void* mp, int W, const double* x0, const dou
     std::vector<double> f = accepted_steps(m, xw, uw, n_int, dt_int, o, x_out + (size_t)w * nx, &st, &lg);
     long long nit = st.newton_it, nrhs = st.rhs;
     int status = st.status;
-    std::vector<double> dx0(kDir * nx), du(kDir * std::max<size_t>(nut, 1)), tx(kDir * nx);
-    for (size_t c0 = 0; c0 < nin && !status; c0 += kDir) {
-      int nd = (int)std::min<size_t>(kDir, nin - c0);
-      std::fill(dx0.begin(), dx0.end(), 0.0);
-      std::fill(du.begin(), du.end(), 0.0);
-      for (int d = 0; d < nd; ++d) {
-        size_t idx = c0 + d;
-        if (idx < (size_t)nx) dx0[d * nx + idx] = 1.0; else du[d * nut + (idx - nx)] = 1.0;
-      }
-      Stats s2;
-      jvp_pass(m, xw, uw, n_int, dt_int, o, f, nd, dx0.data(), du.data(), nullptr, tx.data(), &s2);
-      status |= s2.status; nrhs += s2.rhs;
-      for (int d = 0; d < nd; ++d) {
-        double g = 0.0;
-        for (int i = 0; i < nx; ++i) g += xbar[(size_t)w * nx + i] * tx[d * nx + i];
-        size_t idx = c0 + d;
-        if (idx < (size_t)nx) x0bar[(size_t)w * nx + idx] = g; else ubar[w * nut + (idx - nx)] = g;
-      }
-    }
+    if (!status) status |= grad_world(m, xw, uw, n_int, dt_int, o, f, xbar + (size_t)w * nx, x0bar + (size_t)w * nx,
+                                      ubar + w * nut, &nrhs);
     long long* c = counters + 5 * (size_t)w;
     c[0] = lg.n_acc; c[1] = lg.n_rej; c[2] = nrhs; c[3] = nit; c[4] = status;
   });
   return 0;
+}
+
+// The same along given accepted-step sequences: world w replays its
+// forced_n[w] steps forced[w][i] = (t_i, h_i) (the controller is off), and its
+// end state and gradient are those of that frozen discretization.
+extern "C" int orc_grad_forced_batch(const void* mp, int W, const double* x0, const double* u, int n_int,
+                                     double dt_int, const orc_opts* op, const double* forced, const int* forced_n,
+                                     int forced_cap, const double* xbar, double* x_out, double* x0bar, double* ubar,
+                                     long long* counters, int n_threads) {
+  const Model& m = *static_cast<const Model*>(mp);
+  Opts o = to_opts(op);
+  int nx = m.nq + m.nv;
+  size_t nut = (size_t)n_int * m.nu;
+  parallel_for(W, n_threads, [&](int w) {
+    const double* xw = x0 + (size_t)w * nx;
+    const double* uw = u + w * nut;
+    std::vector<double> f(forced + (size_t)w * forced_cap * 2, forced + ((size_t)w * forced_cap + forced_n[w]) * 2);
+    Stats st; Log lg;
+    rollout<double>(m, xw, uw, n_int, dt_int, o, f.data(), forced_n[w], x_out + (size_t)w * nx, &lg, &st);
+    long long nrhs = st.rhs;
+    int status = st.status;
+    if (!status) status |= grad_world(m, xw, uw, n_int, dt_int, o, f, xbar + (size_t)w * nx, x0bar + (size_t)w * nx,
+                                      ubar + w * nut, &nrhs);
+    long long* c = counters + 5 * (size_t)w;
+    c[0] = lg.n_acc; c[1] = lg.n_rej; c[2] = nrhs; c[3] = st.newton_it; c[4] = status;
+  });
+  return 0;
+}
+
+// One Dormand-Prince attempt from state y with step h under the controls u
+// (the first stage evaluated at y): the 5th-order state and the error norm.
+extern "C" int orc_attempt(const void* mp, const double* y, const double* u, double h, const orc_opts* op,
+                           double* ynew, double* err) {
+  const Model& m = *static_cast<const Model*>(mp);
+  Opts o = to_opts(op);
+  int nv = m.nv;
+  std::vector<double> k1(2 * nv), k7(2 * nv);
+  double uz = 0.0;
+  const double* uk = m.nu > 0 ? u : &uz;
+  Stats st;
+  rhs_st(m, y, uk, o, k1.data(), &st);
+  *err = dopri_attempt(m, y, uk, k1, h, o, true, ynew, k7, &st);
+  return st.status;
+}
+
+// The controller's next proposed step after an attempt with error norm err
+// (eprev_out receives the controller's memory for the next attempt).
+extern "C" double orc_next_step(const orc_opts* op, double err, double eprev, double h, int accepted,
+                                double* eprev_out) {
+  Opts o = to_opts(op);
+  return next_step(o, err, eprev, h, accepted != 0, eprev_out);
 }

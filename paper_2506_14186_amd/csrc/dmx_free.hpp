@@ -178,7 +178,7 @@ DMX_DEV double smoothstep01(double t, double* dt) {
   return t * t * (3.0 - 2.0 * t);
 }
 
-// Smoothed plane-box detection (App. D.1): vertex supports s_k below the
+// Smoothed plane-box detection (App. C.1): vertex supports s_k below the
 // plane, a soft mask (C^1 smoothstep) keeping the vertices within a 1 mm skin
 // of the deepest one, the four largest masked supports in stable descending
 // order (ties to the lower vertex index), contact at the vertex moved to the

@@ -12,10 +12,11 @@
 #include <vector>
 
 #include "../../include/dmx.h"
-#include "dmx_free.hpp"
 #include "dmx_tree.hpp"
-#include "dmx_rk.hpp"
+#include "dmx_launch.hpp"
 #include "dmx_server.hpp"
+
+using namespace dmx_host;
 
 namespace {
 
@@ -95,132 +96,6 @@ void make_tangents(const double* n, double* t1, double* t2) {
   t2[2] = n[0] * t1[1] - n[1] * t1[0];
 }
 
-// ---------------------------------------------------------------- kernels
-using FwdFn = void (*)(const void*, const dmx::FwdArgs&, hipStream_t, int);
-using AdjFn = void (*)(const void*, const dmx::AdjArgs&, hipStream_t, int);
-
-// Batched form: one launch, one team of lanes per world.  Plain form
-// (plain != 0): one launch per world with the same kernel, serialized on the
-// stream (the baseline of the benchmark).
-// Teams of a kernel the device holds at once (occupancy x compute units).
-template <class K>
-long long resident_teams(K kernel, int team) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0) != hipSuccess) return 0;
-  return (long long)cus * per_cu * (64 / team);
-}
-
-// Grid of a batched launch: one team per world, or with a work queue as many
-// teams as the device holds at once (at most one per world).
-template <class P, class K>
-int grid_blocks(K kernel, int W, bool queue) {
-  long long teams = W;
-  if (queue) {
-    const long long r = resident_teams(kernel, P::TEAM);
-    if (r > 0 && r < teams) teams = r;
-  }
-  return (int)((teams * P::TEAM + 63) / 64);
-}
-
-template <class P>
-long long fwd_resident_teams() {
-  static long long r = resident_teams(dmx::fwd_kernel<P>, P::TEAM);
-  return r;
-}
-
-template <class P>
-void launch_fwd(const void* model, const dmx::FwdArgs& a, hipStream_t s, int plain) {
-  if (!plain) {
-    const int blocks = grid_blocks<P>(dmx::fwd_kernel<P>, a.W, a.g.queue != nullptr);
-    if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
-    hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
-    return;
-  }
-  constexpr int NX = P::NQ + P::NV;
-  for (int w = 0; w < a.W; ++w) {
-    dmx::FwdArgs b = a;
-    b.W = 1;
-    b.x0 = a.x0 + (size_t)w * NX;
-    b.u = a.u ? a.u + (size_t)w * a.n_int * a.nu : nullptr;
-    b.xout = a.xout + (size_t)w * NX;
-    b.status = a.status + w;
-    b.n_acc = a.n_acc ? a.n_acc + w : nullptr;
-    b.n_rej = a.n_rej ? a.n_rej + w : nullptr;
-    b.counters = a.counters ? a.counters + (size_t)w * dmx::kFwdCounters : nullptr;
-    b.tape = a.tape ? a.tape + (size_t)w * a.cap * a.rec : nullptr;
-    b.forced = a.forced ? a.forced + (size_t)w * a.forced_cap * 2 : nullptr;
-    b.forced_n = a.forced_n ? a.forced_n + w : nullptr;
-    b.steplog = a.steplog ? a.steplog + (size_t)w * a.log_cap * 4 : nullptr;
-    b.log_n = a.log_n ? a.log_n + w : nullptr;
-    b.fail_state = a.fail_state ? a.fail_state + (size_t)w * (NX + P::NV) : nullptr;
-    hipLaunchKernelGGL(dmx::fwd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
-  }
-}
-template <class P>
-void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
-  constexpr int NXS = P::NQ + P::NV + 3;
-  const bool recompute = a.rec < NXS + 6 * P::NV;  // checkpoint-only tape
-  auto kernel = recompute ? dmx::adj_kernel<P, true> : dmx::adj_kernel<P, false>;
-  if (!plain) {
-    const int blocks = grid_blocks<P>(kernel, a.W, a.g.queue != nullptr);
-    if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
-    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
-    return;
-  }
-  constexpr int NX = P::NQ + P::NV;
-  const size_t nut = (size_t)a.n_int * a.nu;
-  for (int w = 0; w < a.W; ++w) {
-    dmx::AdjArgs b = a;
-    b.W = 1;
-    b.tape = a.tape + (size_t)w * a.cap * a.rec;
-    b.n_acc = a.n_acc + w;
-    b.status = a.status + w;
-    b.u = a.u ? a.u + (size_t)w * nut : nullptr;
-    b.xbar = a.xbar + (size_t)w * NX;
-    b.x0bar = a.x0bar + (size_t)w * NX;
-    b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
-    b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
-    hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
-  }
-}
-
-using AccFn = void (*)(const void*, int, const double*, const double*, int, const dmx::SolverOpts&, double*, int*,
-                       hipStream_t);
-
-template <class P>
-void launch_acc(const void* model, int n, const double* x, const double* tau, int cfd, const dmx::SolverOpts& o,
-                double* acc, int* status, hipStream_t s) {
-  const long long threads = (long long)n * P::TEAM;
-  const int blocks = (int)((threads + 63) / 64);
-  hipLaunchKernelGGL(dmx::accel_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, n, x, tau,
-                     cfd, o.beta, o.newton_maxit, acc, status);
-}
-
-struct KernelEntry {
-  int kind, nc, team, nv, nb;
-  FwdFn fwd;
-  AdjFn adj;
-  AccFn acc;
-  long long (*resident)();
-};
-
-#define FREE_ENTRY(NC, L) \
-  {0, NC, L, 6, 1, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, \
-   &launch_acc<dmx::FreePhys<NC, L>>, &fwd_resident_teams<dmx::FreePhys<NC, L>>}
-#define TREE_ENTRY(NV, NB, NC, L) \
-  {1, NC, L, NV, NB, &launch_fwd<dmx::TreePhys<NV, NB, NC, L>>, &launch_adj<dmx::TreePhys<NV, NB, NC, L>>, \
-   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>, &fwd_resident_teams<dmx::TreePhys<NV, NB, NC, L>>}
-
-const KernelEntry kKernels[] = {
-    FREE_ENTRY(1, 1), FREE_ENTRY(2, 1), FREE_ENTRY(2, 2), FREE_ENTRY(4, 1), FREE_ENTRY(4, 4), FREE_ENTRY(4, 8),
-    FREE_ENTRY(8, 1), FREE_ENTRY(8, 2), FREE_ENTRY(8, 4), FREE_ENTRY(8, 8), FREE_ENTRY(8, 16), FREE_ENTRY(16, 8),
-    FREE_ENTRY(16, 16),
-    // planar legged chain (7 joints, 5 bodies, 4 foot contact slots); 3-link test pendulum
-    TREE_ENTRY(7, 5, 4, 4), TREE_ENTRY(7, 5, 4, 8), TREE_ENTRY(7, 5, 4, 16), TREE_ENTRY(4, 3, 1, 4),
-};
-
 int bucket(int n) {
   int b = 1;
   while (b < n) b *= 2;
@@ -252,8 +127,9 @@ struct dmx_tape {
   AdjFn adj = nullptr;
   int64_t* adj_counters = nullptr;
   int plain = 0;
-  const int32_t* world_intervals = nullptr;
+  const int32_t* world_intervals = nullptr;  // tape-owned copies of the caller's tables (or null)
   const int32_t* world_order = nullptr;
+  int* tables = nullptr;  // [2][W]: per-world intervals and processing order, copied at each rollout
   int* queue = nullptr;   // [2] work counters of the forward and reverse launches
   bool use_queue = false;
 };
@@ -267,7 +143,7 @@ void dmx_default_opts(dmx_solver_opts* o) {
   o->rtol = 1e-6; o->atol = 1e-8; o->h0 = 1e-3; o->safety = 0.9; o->facmin = 0.2; o->facmax = 10.0;
   o->kP = 0.2; o->kI = 0.4; o->err_order = 5.0; o->err_floor = 1e-6; o->max_attempts = 1000000;
   o->newton_maxit = 100; o->cfd = 0; o->softplus_beta = 1e4; o->tape_steps = 0; o->lanes_per_world = 0;
-  o->h_levels = 16;
+  o->h_levels = 0;
   o->tape_stages = -1;
 }
 
@@ -620,10 +496,21 @@ void dmx_model_destroy(dmx_model* m) {
   delete m;
 }
 
+// every compiled kernel, in table order
+static std::vector<const KernelEntry*> all_kernels() {
+  std::vector<const KernelEntry*> v;
+  for (KernelTable t : {free_kernels_small(), free_kernels(), free_kernels_wide(), tree_kernels()})
+    for (int i = 0; i < t.n; ++i) v.push_back(&t.entries[i]);
+  return v;
+}
+
 static const KernelEntry* lookup_kernel(const dmx_model* m, int team) {
-  for (const KernelEntry& k : kKernels)
+  static const std::vector<const KernelEntry*> table = all_kernels();
+  for (const KernelEntry* kp : table) {
+    const KernelEntry& k = *kp;
     if (k.kind == m->kind && k.nc == m->ncb && k.team == team && (m->kind == 0 || (k.nv == m->nv && k.nb == m->nb)))
       return &k;
+  }
   return nullptr;
 }
 
@@ -723,6 +610,7 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     if (e == hipSuccess) e = hipMalloc(&tp->n_acc, sizeof(int) * W);
     if (e == hipSuccess) e = hipMalloc(&tp->status, sizeof(int) * W);
     if (e == hipSuccess) e = hipMalloc(&tp->queue, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&tp->tables, 2 * sizeof(int) * W);
     if (e != hipSuccess) {
       dmx_tape_destroy(tp);
       return fail(DMX_ERR_OUT_OF_MEMORY, std::string("tape allocation: ") + hipGetErrorString(e));
@@ -731,7 +619,21 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     a.n_acc = tp->n_acc; a.status = tp->status;
   }
   if (tp) {
-    tp->world_intervals = o.world_intervals; tp->world_order = o.world_order; tp->use_queue = use_queue;
+    // the reverse sweep reads the per-world tables later: the tape keeps its
+    // own copies, so the caller's arrays need only live until this call's
+    // work on the stream is done
+    tp->world_intervals = nullptr;
+    tp->world_order = nullptr;
+    if (o.world_intervals) {
+      HIP_TRY(hipMemcpyAsync(tp->tables, o.world_intervals, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+      tp->world_intervals = tp->tables;
+    }
+    if (o.world_order) {
+      HIP_TRY(hipMemcpyAsync(tp->tables + W, o.world_order, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+      tp->world_order = tp->tables + W;
+    }
+    a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
+    tp->use_queue = use_queue;
     if (use_queue) a.g.queue = tp->queue;
   } else if (use_queue) {
     HIP_TRY(hipMallocAsync((void**)&tmp_queue, sizeof(int), s));
@@ -786,7 +688,8 @@ dmx_status dmx_autotune(dmx_model* m, int32_t W, int32_t n_int, double dt, const
   if (e != hipSuccess) { cleanup(); return fail(DMX_ERR_OUT_OF_MEMORY, "autotune buffers"); }
   int best = 0, tried = 0;
   float best_ms = 0.0f;
-  for (const KernelEntry& k : kKernels) {
+  for (const KernelEntry* kp : all_kernels()) {
+    const KernelEntry& k = *kp;
     if (k.kind != m->kind || k.nc != m->ncb || (m->kind == 1 && (k.nv != m->nv || k.nb != m->nb))) continue;
     dmx_solver_opts o;
     dmx_default_opts(&o);
@@ -851,6 +754,7 @@ void dmx_tape_destroy(dmx_tape* tp) {
   if (tp->n_acc) (void)hipFree(tp->n_acc);
   if (tp->status) (void)hipFree(tp->status);
   if (tp->queue) (void)hipFree(tp->queue);
+  if (tp->tables) (void)hipFree(tp->tables);
   delete tp;
 }
 
@@ -1100,8 +1004,14 @@ struct dmx_server {
         if (stream_batch[i]) continue;
         SrvBatch* b = form_batch();
         if (!b) break;
-        if (!launch(b, streams[i])) {
-          (void)hipStreamSynchronize(streams[i]);
+        // the batch's requests left the queue and nothing else writes them
+        // while it runs: pack and launch without holding the lock, so that
+        // submit and poll are not blocked behind the host-side packing
+        lk.unlock();
+        const bool ok = launch(b, streams[i]);
+        if (!ok) (void)hipStreamSynchronize(streams[i]);
+        lk.lock();
+        if (!ok) {
           finish(b, false);
         } else {
           stream_batch[i] = b;

@@ -122,7 +122,7 @@ DMX_DEV int take_world(const Ragged& g, int W, int team, bool first) {
   return g.order ? g.order[idx] : idx;
 }
 
-__global__ void reset_queue(int* q) {
+static __global__ void reset_queue(int* q) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *q = 0;
 }
 

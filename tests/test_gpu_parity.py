@@ -3,20 +3,21 @@
 Tolerances: an acceleration F(x) at the same state agrees to 1e-10; a GPU step
 fed the oracle's step and state agrees to 1e-10 relative; a whole replayed step
 sequence to 1e-6 (stiff contact at large steps amplifies rounding differences
-along a trajectory); free adaptive end states to 1e-6; gradients to 1e-5
-(relative, normwise per world: |dq|/max(|q|,1), |dv|/max(|v|,1e-3),
-|dg|/max(|g|,1e-12)).  Tumbling cubes are chaotic; with a continuous step-size
-controller, rounding-level differences of the error estimate change step
-sequences and end states then differ at 1e-4.  Both sides round proposed steps
-down to a grid of 16 mantissa levels per octave, which makes the step sequences
-of the two implementations identical, so free runs are compared over the full
-horizon; a world whose accepted-step sequence still splits is reported, and
-at most one per batch may then disagree.
+along a trajectory); end states to 1e-6; gradients to 1e-5, normwise and
+element by element (relative, per world: |dq|/max(|q|,1), |dv|/max(|v|,1e-3),
+|dg|/max(|g|,1e-12); entries |dg_i|/max(|g_i|, 1e-3 |g|_inf)).  Free runs use
+the paper's continuous PI controller: each GPU run's accepted-step sequence is
+replayed by the oracle (end state and gradient), and each attempt's
+accept/reject decision and proposed step are checked against the oracle's
+error estimate and controller (tests/replay_check.py).  The opt-in step grid
+(h_levels) is checked separately.
 """
 import numpy as np
 import pytest
 
 from paper_2506_14186_amd import workloads as W
+from replay_check import (GRAD_TOL, STATE_TOL, check_decisions_and_controller, elementwise_grad, rel_grad, rel_state,
+                          replay_and_compare, tape_steps)
 
 pytestmark = pytest.mark.gpu
 
@@ -33,18 +34,6 @@ def D():
 def _t(a):
     import torch
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def rel_state(a, b, nq):
-    a, b = np.atleast_2d(a), np.atleast_2d(b)
-    dq = np.linalg.norm(a[:, :nq] - b[:, :nq], axis=1) / np.maximum(np.linalg.norm(b[:, :nq], axis=1), 1.0)
-    dv = np.linalg.norm(a[:, nq:] - b[:, nq:], axis=1) / np.maximum(np.linalg.norm(b[:, nq:], axis=1), 1e-3)
-    return np.maximum(dq, dv)
-
-
-def rel_grad(a, b):
-    a, b = np.atleast_2d(a), np.atleast_2d(b)
-    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-12)
 
 
 def _sphere_batch(seeds):
@@ -182,54 +171,76 @@ def test_replayed_sequence_parity(D, oracle, case):
     assert worst <= 1e-6 and ef.max() <= 1e-6
 
 
-@pytest.mark.parametrize("case,lanes", FREE_CASE_LANES)
-def test_free_adaptive_parity_and_gradient(D, oracle, case, lanes):
-    desc, x0, n_int, dt = FREE_CASES[case]()
+def _steplog_opts(D, W, cap, **kw):
+    import torch
+    log = torch.zeros((W, cap, 4), dtype=torch.float64, device="cuda")
+    logn = torch.zeros(W, dtype=torch.int32, device="cuda")
+    return D.default_opts(steplog=log.data_ptr(), log_n=logn.data_ptr(), log_cap=cap, **kw), (log, logn)
+
+
+def _free_run_checked(D, oracle, desc, x0, u, n_int, dt, xbar, lanes=0, levels=0, label="", decisions=None):
+    """A free GPU run (the paper's continuous controller unless levels > 0),
+    checked against the oracle replay of its own accepted steps and, for the
+    worlds in `decisions` (default all), attempt by attempt."""
     om = oracle.Model(desc)
     model = D.Model(desc)
-    res = D.rollout(model, _t(x0), None, n_int, dt, tape=True, counters=True,
-                    opts=D.default_opts(lanes_per_world=lanes))
+    Wn = x0.shape[0]
+    o, (log, logn) = _steplog_opts(D, Wn, 8192, lanes_per_world=lanes, h_levels=levels, tape_steps=8192)
+    ut = _t(u) if model.nu else None
+    res = D.rollout(model, _t(x0), ut, n_int, dt, opts=o, tape=True, counters=True)
     assert int(res["status"].abs().sum()) == 0
+    gx, gu = D.rollout_vjp(res["tape"], _t(xbar))
+    forced, n = tape_steps(res["tape"])
+    uu = u if model.nu else None
+    cmp = replay_and_compare(om, model.nq, x0, uu, n_int, dt, res["x"].cpu().numpy(), forced, n, xbar,
+                             gx.cpu().numpy(), None if gu is None else gu.cpu().numpy(), h_levels=levels)
+    logs, logn = log.cpu().numpy(), logn.cpu().numpy()
+    assert (logn < 8192).all()
+    checked, bad_dec, max_rel, bad_ctrl = check_decisions_and_controller(
+        oracle, om, x0, uu, n_int, dt, forced, n, logs, logn, worlds=decisions, h_levels=levels)
+    print(f"{label} (lanes {lanes or 'default'}, levels {levels}): accepted steps {n.tolist() if Wn <= 32 else n.mean()}; "
+          f"replay: state {cmp['state'].max():.2e}, grad {cmp['grad'].max():.2e} (element-wise "
+          f"{cmp['grad_elem'].max():.2e}); {checked} attempts: {bad_dec} decisions differ outside the rounding band, "
+          f"error estimates agree to {max_rel:.1e}, {bad_ctrl} proposed steps differ from the oracle controller")
+    assert cmp["state"].max() <= STATE_TOL
+    assert cmp["grad"].max() <= GRAD_TOL and cmp["grad_elem"].max() <= GRAD_TOL
+    assert bad_dec == 0 and bad_ctrl == 0
+    return res, n, cmp
+
+
+@pytest.mark.parametrize("case,lanes", FREE_CASE_LANES)
+def test_free_adaptive_parity_and_gradient(D, oracle, case, lanes):
+    """Free runs under the paper's continuous PI controller, every world
+    checked: end state and gradient against the oracle replay of the GPU's
+    accepted steps, and every attempt's decision and proposed step."""
+    desc, x0, n_int, dt = FREE_CASES[case]()
     xbar = np.zeros_like(x0)
     xbar[:, 0:3] = 1.0  # summed final position
     if case == "sphere":
         xbar[:, :] = 0.0
         xbar[:, 2] = 1.0  # final height
-    g, _ = D.rollout_vjp(res["tape"], _t(xbar))
-    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=8)
-    ex = rel_state(res["x"].cpu().numpy(), ref["x"], model.nq)
-    eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
-    nacc = res["n_acc"].cpu().numpy()
-    same = nacc == ref["n_acc"]
-    print(f"{case} (lanes {lanes or 'default'}): steps gpu {nacc.tolist()} oracle {ref['n_acc'].tolist()}; "
-          f"state err {ex.max():.2e}; "
-          f"grad err {eg.max():.2e}")
-    ok = (ex <= 1e-6) & (eg <= 1e-5)
-    # worlds on the same accepted-step sequence agree; a world whose sequence
-    # split (rounding at a grid or accept boundary) may differ only if its
-    # dynamics amplify the split (tumbling cubes), and only one per batch
-    assert ok[same].all()
-    assert (~ok).sum() <= 1
+    _free_run_checked(D, oracle, desc, x0, np.zeros((x0.shape[0], n_int, 0)), n_int, dt, xbar, lanes=lanes,
+                      label=case)
 
 
-@pytest.mark.parametrize("levels", [16, 0])
+@pytest.mark.parametrize("levels", [0, 16])
 def test_free_run_full_horizon(D, oracle, levels):
-    """Full 0.5 s free runs of 32 tumbling cubes.  On the step grid the
-    accepted-step sequences agree and end states match to 1e-6; with the
-    continuous controller (levels 0) the divergence is reported only."""
+    """Full 0.5 s free runs of 32 tumbling cubes, every world checked through
+    the replay of its GPU step sequence (continuous controller and the opt-in
+    step grid).  On the grid the two sides' own free runs also take the same
+    steps; how many do is reported for both settings."""
     desc, x0, n_int, dt = _cube_batch(32)
+    xbar = np.zeros_like(x0)
+    xbar[:, :3] = 1.0
+    res, n, cmp = _free_run_checked(D, oracle, desc, x0, np.zeros((32, 1, 0)), n_int, dt, xbar, levels=levels,
+                                    label="32 cubes 0.5 s")
     om = oracle.Model(desc)
-    model = D.Model(desc)
-    res = D.rollout(model, _t(x0), None, n_int, dt, opts=D.default_opts(h_levels=levels), counters=True)
     ref = om.rollout_batch(x0, None, n_int, dt, n_threads=8, h_levels=levels)
-    ex = rel_state(res["x"].cpu().numpy(), ref["x"], model.nq)
-    same = res["n_acc"].cpu().numpy() == ref["n_acc"]
-    print(f"levels {levels}: {int((ex <= 1e-6).sum())}/32 within 1e-6, {int(same.sum())}/32 equal accepted-step "
-          f"counts; median rel err {np.median(ex):.2e}, "
-          f"max over equal sequences {ex[same].max() if same.any() else float('nan'):.2e}")
-    assert int(res["status"].abs().sum()) == 0
+    same = n == ref["n_acc"]
+    ex = rel_state(res["x"].cpu().numpy(), ref["x"], 7)
+    print(f"levels {levels}: own free runs of both sides: {int(same.sum())}/32 equal accepted-step counts, "
+          f"{int((ex <= 1e-6).sum())}/32 end states within 1e-6 (median {np.median(ex):.1e})")
     if levels:
-        assert (~same).sum() <= 1
         assert ex[same].max() <= 1e-6
 
 
@@ -353,11 +364,14 @@ def test_cfd_straight_through(D, oracle):
     b = D.rollout(model, _t(x0), None, n_int, dt, tape=True, opts=D.default_opts(cfd=1))
     np.testing.assert_array_equal(a["x"].cpu().numpy(), b["x"].cpu().numpy())
     g, _ = D.rollout_vjp(b["tape"], _t(xbar))
-    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=3, cfd=1)
-    plain = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=3, cfd=0)
+    forced, n = tape_steps(b["tape"])
+    ref = om.grad_forced_batch(x0, None, n_int, dt, xbar, forced, n, n_threads=3, cfd=1)
+    plain = om.grad_forced_batch(x0, None, n_int, dt, xbar, forced, n, n_threads=3, cfd=0)
     eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
-    print(f"cfd gradient rel err {eg.max():.3e}; dz/dz0 with CFD {ref['x0bar'][:, 2]}, without {plain['x0bar'][:, 2]}")
-    assert eg.max() <= 1e-5
+    ee = elementwise_grad(g.cpu().numpy(), ref["x0bar"])
+    print(f"cfd gradient rel err {eg.max():.3e} (element-wise {ee.max():.2e}); dz/dz0 with CFD "
+          f"{ref['x0bar'][:, 2]}, without {plain['x0bar'][:, 2]}")
+    assert eg.max() <= 1e-5 and ee.max() <= 1e-5
     assert abs(ref["x0bar"][0, 2] - plain["x0bar"][0, 2]) > 1e-3  # CFD informs the non-touching sphere
 
 
@@ -384,10 +398,42 @@ def test_cfd_straight_through_cube(D, oracle, lanes):
     rng = np.random.default_rng(11)
     xbar = rng.normal(size=x0.shape)
     g, _ = D.rollout_vjp(res["tape"], _t(xbar))
-    ref = om.grad_batch(x0, None, n_int, dt, xbar, n_threads=4, cfd=1)
+    ref = om.grad_forced_batch(x0, None, n_int, dt, xbar, forced, fn.astype(np.int32), n_threads=4, cfd=1)
     eg = rel_grad(g.cpu().numpy(), ref["x0bar"])
-    print(f"cube cfd (lanes {lanes or 'default'}): replayed-sequence gradient rel err {eg.max():.3e}")
-    assert eg.max() <= 1e-5
+    ee = elementwise_grad(g.cpu().numpy(), ref["x0bar"])
+    print(f"cube cfd (lanes {lanes or 'default'}): replayed-sequence gradient rel err {eg.max():.3e} "
+          f"(element-wise {ee.max():.2e})")
+    assert eg.max() <= 1e-5 and ee.max() <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["box", "chain"])
+def test_cfd_straight_through_box_and_tree(D, oracle, case):
+    """The straight-through CFD gradient of the box geom (smoothed plane-box
+    rows within w_c) and of the legged chain (foot capsules within w_c), on
+    the GPU's own step sequences replayed by the oracle."""
+    if case == "box":
+        desc, x0, n_int, dt = _box_batch(4, horizon=0.4)
+        u = np.zeros((4, 1, 0))
+    else:
+        desc, x0, u, n_int, dt = _chain(n_worlds=3, n_int=8)
+    model = D.Model(desc)
+    om = oracle.Model(desc)
+    ut = _t(u) if model.nu else None
+    res = D.rollout(model, _t(x0), ut, n_int, dt, opts=D.default_opts(cfd=1, tape_steps=8192), tape=True)
+    assert int(res["status"].abs().sum()) == 0
+    rng = np.random.default_rng(12)
+    xbar = rng.normal(size=x0.shape)
+    gx, gu = D.rollout_vjp(res["tape"], _t(xbar))
+    forced, n = tape_steps(res["tape"])
+    cmp = replay_and_compare(om, model.nq, x0, u if model.nu else None, n_int, dt, res["x"].cpu().numpy(), forced,
+                             n, xbar, gx.cpu().numpy(), None if gu is None else gu.cpu().numpy(), cfd=1)
+    plain = om.grad_forced_batch(x0, u if model.nu else None, n_int, dt, xbar, forced, n, n_threads=4, cfd=0)
+    moved = rel_grad(cmp["ref"]["x0bar"], plain["x0bar"])
+    print(f"{case} cfd: steps {n.tolist()}; state {cmp['state'].max():.2e}, gradient {cmp['grad'].max():.2e} "
+          f"(element-wise {cmp['grad_elem'].max():.2e}); CFD changes the x0 gradient by {moved.max():.2e}")
+    assert cmp["state"].max() <= STATE_TOL
+    assert cmp["grad"].max() <= GRAD_TOL and cmp["grad_elem"].max() <= GRAD_TOL
+    assert moved.max() > 1e-6  # the CFD rows take part in the gradient
 
 
 @pytest.mark.parametrize("lanes", [0, 8])
@@ -410,7 +456,9 @@ def test_full_size_cube_sampled(D, oracle, lanes):
     assert np.isfinite(g.cpu().numpy()).all()
     nacc = res["n_acc"].cpu().numpy()
     recs, n = res["tape"].records()
-    sample = [0, 1, 777, 1500, 2048, 3000, 4000, 4095]
+    n_att = nacc + res["n_rej"].cpu().numpy()
+    hardest = [int(w) for w in np.argsort(-n_att, kind="stable")[:5]]
+    sample = sorted(set([0, 1, 777, 1500, 2048, 3000, 4000, 4095] + hardest))
     om = oracle.Model(cfg["model"])
     ref_tapes = [om.rollout(x0[w], None, 1, 0.5, tape_cap=5000) for w in sample]
     cap = max(int(n.max()), max(r["n_acc"] for r in ref_tapes))
@@ -430,10 +478,11 @@ def test_full_size_cube_sampled(D, oracle, lanes):
     ref = om.grad_batch(x0[sample], None, 1, 0.5, xbar[sample], n_threads=8)
     ex = rel_state(rep["x"].cpu().numpy()[sample], ref["x"], model.nq)
     eg = rel_grad(gr.cpu().numpy()[sample], ref["x0bar"])
+    ee = elementwise_grad(gr.cpu().numpy()[sample], ref["x0bar"])
     print(f"4096 worlds (lanes {lanes or 'default'}): accepted steps mean {nacc.mean():.0f} max {nacc.max()}; "
-          f"sampled replay state err "
-          f"{ex.max():.2e} grad err {eg.max():.2e}")
-    assert ex.max() <= 1e-6 and eg.max() <= 1e-5
+          f"hardest worlds {hardest} ({n_att[hardest].tolist()} attempts); sampled replay state err "
+          f"{ex.max():.2e} grad err {eg.max():.2e} (element-wise {ee.max():.2e})")
+    assert ex.max() <= 1e-6 and eg.max() <= 1e-5 and ee.max() <= 1e-5
 
 
 def test_full_size_chain_sampled(D, oracle):
@@ -489,6 +538,46 @@ def test_full_size_chain_sampled(D, oracle):
     print(f"chain 16384 x {H}: accepted steps mean {nacc.mean():.0f} max {nacc.max()}, tape {recs_n}; sampled "
           f"replay state err {worst_s:.2e}, cotangent vs forward-mode directions {worst_g:.2e}")
     assert worst_s <= 1e-6 and worst_g <= 1e-5
+
+
+def test_chain_free_run_full_horizon(D, oracle):
+    """16 legged chains over the full 2 s (200 intervals of 10 ms, random
+    torques) under the continuous controller: every world's end state against
+    the oracle replay of its GPU step sequence, its x0/u cotangents against the
+    oracle's forward-mode derivatives along 16 random directions (element by
+    element), and the decisions and proposed steps of 4 worlds attempt by
+    attempt."""
+    cfg = W.chain_walk(seed=3, n_worlds=16, n_intervals=200)
+    model = D.Model(cfg["model"])
+    om = oracle.Model(cfg["model"])
+    x0, u, H, dt = cfg["x0"], cfg["u"], cfg["n_intervals"], cfg["interval_dt"]
+    o, (log, logn) = _steplog_opts(D, 16, 16384, tape_steps=40 * H + 64)
+    res = D.rollout(model, _t(x0), _t(u), H, dt, tape=True, opts=o)
+    assert int(res["status"].abs().sum()) == 0
+    rng = np.random.default_rng(31)
+    xbar = rng.normal(size=x0.shape)
+    gx, gu = D.rollout_vjp(res["tape"], _t(xbar))
+    gx, gu = gx.cpu().numpy(), gu.cpu().numpy()
+    forced, n = tape_steps(res["tape"])
+    xs = res["x"].cpu().numpy()
+    worst_s = worst_d = 0.0
+    nd, nut = 16, H * model.nu
+    for w in range(16):
+        dx0 = rng.normal(size=(nd, model.nx))
+        du = rng.normal(size=(nd, nut))
+        rep = om.rollout(x0[w], u[w], H, dt, forced=forced[w, :n[w]])
+        assert rep["status"] == 0
+        worst_s = max(worst_s, rel_state(xs[w], rep["x"], model.nq)[0])
+        _, jv = om.rollout_jvp_forced(x0[w], u[w], H, dt, forced[w, :n[w]], dx0, du)
+        lhs = jv @ xbar[w]                                # <x_bar, J d>
+        rhs = dx0 @ gx[w] + du @ gu[w].reshape(-1)        # <J^T x_bar, d>
+        worst_d = max(worst_d, elementwise_grad(rhs[None], lhs[None])[0])
+    checked, bad_dec, max_rel, bad_ctrl = check_decisions_and_controller(
+        oracle, om, x0, u, H, dt, forced, n, log.cpu().numpy(), logn.cpu().numpy(), worlds=[0, 5, 10, 15])
+    print(f"chain 16 x 2 s: accepted steps {n.tolist()}; replay state {worst_s:.2e}; directional derivatives "
+          f"{worst_d:.2e}; {checked} attempts: {bad_dec} decisions, {bad_ctrl} proposed steps differ; error "
+          f"estimates agree to {max_rel:.1e}")
+    assert worst_s <= STATE_TOL and worst_d <= GRAD_TOL and bad_dec == 0 and bad_ctrl == 0
 
 
 # ------------------------------------------------------------------ articulated chain
@@ -602,17 +691,20 @@ def test_ragged_horizons_and_work_queue(D, oracle):
         np.testing.assert_array_equal(gu[idx, :k], guu.cpu().numpy())
         assert not gu[idx, k:].any()
     om = oracle.Model(desc)
-    nacc = res["n_acc"].cpu().numpy()
-    errs, split = [], 0
+    # each world against the oracle replay of its own accepted steps
+    recs, nrec = res["tape"].records()
+    worst_s = worst_g = 0.0
     for w in range(n):
-        r = om.rollout(x0[w], u[w, :nint[w]], int(nint[w]), dt)
-        if r["n_acc"] == nacc[w]:
-            errs.append(rel_state(xr[w], r["x"], model.nq)[0])
-        else:
-            split += 1
-    print(f"ragged: horizons {np.bincount(nint).tolist()}; {split} split step sequences; max rel err vs oracle "
-          f"{max(errs):.2e}")
-    assert split <= 1 and max(errs) <= 1e-6
+        k = int(nint[w])
+        f = np.ascontiguousarray(recs[w:w + 1, :nrec[w], :2])
+        ref = om.grad_forced_batch(x0[w:w + 1], u[w:w + 1, :k], k, dt, xbar[w:w + 1], f, nrec[w:w + 1])
+        worst_s = max(worst_s, rel_state(xr[w], ref["x"], model.nq).max())
+        g = np.concatenate([gx[w], gu[w, :k].ravel()])[None]
+        r = np.concatenate([ref["x0bar"][0], ref["ubar"][0].ravel()])[None]
+        worst_g = max(worst_g, rel_grad(g, r).max(), elementwise_grad(g, r).max())
+    print(f"ragged: horizons {np.bincount(nint).tolist()}; vs the oracle replay of each world's steps: state "
+          f"{worst_s:.2e}, gradient {worst_g:.2e}")
+    assert worst_s <= 1e-6 and worst_g <= 1e-5
     # the queue on and off give the same bits on a uniform batch
     a = D.rollout(model, _t(x0), _t(u), H, dt, opts=D.default_opts(work_queue=1))
     b = D.rollout(model, _t(x0), _t(u), H, dt, opts=D.default_opts(work_queue=-1))

@@ -636,3 +636,118 @@ def test_box_plane_flat_face_gives_four_equal_corners(oracle):
         expect = q[:3] + bottom @ R.T + np.array([0, 0, delta / 2])
         np.testing.assert_allclose(c[:, 1:4], expect, atol=1e-14)
         np.testing.assert_allclose(c[:, 4:7], [[0, 0, 1]] * 4, atol=0)
+
+
+# ------------------------------------------------------------------ CFD position term (softplus)
+def _sphere_rows(oracle, z, beta, vz=-0.3):
+    desc = W.model_sphere()
+    om = oracle.Model(desc)
+    x = sphere_state(z, vz=vz)
+    rows = om.rows(x, cfd=True, beta=beta)
+    plain = om.rows(x, cfd=False)
+    pr = desc["pairs"][0]
+    return om, x, rows, plain, pr
+
+
+def test_cfd_position_term_limits(oracle):
+    """The CFD field replaces F's position term k relu(-r) of a_ref by a
+    softplus (Sec. 4).  Pinned by its limits, which fix its sign and scale
+    without the softplus formula: (i) deep in penetration (beta |r| = 50) the
+    CFD rows equal F's rows; (ii) at a gap r = +5 mm inside the CFD width the
+    position term vanishes (a_ref = -b J v, the damping term alone); (iii) at
+    r = 0 it equals k(0) log(2) / beta, the value of any softplus at 0, with
+    k(0) = d_0 / (d_w^2 t_c^2 phi^2) and d_0 the CFD spline's value at the
+    surface; (iv) between, it decreases with r and grows as beta falls."""
+    beta = 1e4
+    tc, phi = 0.002, 1.0
+    # (i) penetration 5 mm: identical rows (softplus(-r) = -r to rounding)
+    om, x, rows, plain, pr = _sphere_rows(oracle, 0.1 - 5e-3, beta)
+    assert len(rows["aref"]) == 4 and len(plain["aref"]) == 4
+    np.testing.assert_allclose(rows["aref"], plain["aref"], rtol=1e-13)
+    np.testing.assert_allclose(rows["D"], plain["D"], rtol=1e-13)
+    # (ii) gap 5 mm: F has no rows, the CFD rows carry only the damping term
+    om, x, rows, plain, pr = _sphere_rows(oracle, 0.1 + 5e-3, beta)
+    assert len(plain["aref"]) == 0 and len(rows["aref"]) == 4
+    dw = pr["solimp"][1]
+    b = 2.0 / (dw * tc)
+    jv = rows["J"] @ x[7:]
+    pos = rows["aref"] + b * jv
+    assert np.abs(pos).max() <= 1e-12 * np.abs(b * jv).max()
+    # (iii) touching: position term k(0) log 2 / beta on every edge
+    d0 = pr["cfd"][1]
+    om, x, rows, plain, pr = _sphere_rows(oracle, 0.1, beta)
+    pos0 = rows["aref"] + b * (rows["J"] @ x[7:])
+    k0 = d0 / (dw ** 2 * tc ** 2 * phi ** 2)
+    np.testing.assert_allclose(pos0, k0 * np.log(2.0) / beta, rtol=1e-12)
+    # (iv) monotone in r and in 1/beta
+    vals = []
+    for gap in (-2e-4, -5e-5, 0.0, 5e-5, 2e-4):
+        _, x, rows, _, _ = _sphere_rows(oracle, 0.1 + gap, beta)
+        vals.append((rows["aref"] + b * (rows["J"] @ x[7:]))[0])
+    assert all(a > c for a, c in zip(vals, vals[1:]))
+    _, x, soft, _, _ = _sphere_rows(oracle, 0.1 + 5e-5, 1e3)
+    assert (soft["aref"] + b * (soft["J"] @ x[7:]))[0] > vals[3]
+
+
+# ------------------------------------------------------------------ failed trial solves
+def test_failed_trial_solve_rejects_the_attempt(oracle):
+    """Reading of a contact solve that fails at a trial stage (its Newton
+    iteration budget is spent): the attempt is rejected as if its error were
+    infinite and the step shrinks by the controller's minimum factor; an
+    accepted step never contains a failed solve.  With a budget of 4
+    iterations some trial stages of tumbling cubes fail; every world still
+    finishes, each failed attempt is a rejection followed by a step of
+    facmin h (or the landing step), and replaying the accepted steps with the
+    full budget reproduces the end state bit for bit (every accepted stage
+    solve had converged)."""
+    cfg = W.cube_toss(seed=2, n_worlds=8, horizon=0.5)
+    om = oracle.Model(cfg["model"])
+    failed = 0
+    for w in range(8):
+        r = om.rollout(cfg["x0"][w], None, 1, 0.5, log_cap=20000, tape_cap=20000, newton_maxit=4)
+        assert r["status"] == 0
+        lg = r["log"]
+        bad = np.where(np.isinf(lg[:, 2]))[0]
+        failed += len(bad)
+        for i in bad:
+            assert lg[i, 3] == 0.0
+            t1, h1 = lg[i + 1, 0], lg[i + 1, 1]
+            assert t1 == lg[i, 0]
+            assert h1 == 0.2 * lg[i, 1] or abs(t1 + h1 - 0.5) < 1e-15
+        rep = om.rollout(cfg["x0"][w], None, 1, 0.5, forced=r["tape"][:, :2], newton_maxit=100)
+        np.testing.assert_array_equal(rep["x"], r["x"])
+    assert failed > 0
+
+
+# ------------------------------------------------------------------ capsule-plane
+def _free_capsule(radius=0.03, half=0.125):
+    return {"name": "capsule", "gravity": [0.0, 0.0, -9.81],
+            "bodies": [{"parent": -1, "pos": [0.0, 0.0, 0.0], "quat": [1.0, 0.0, 0.0, 0.0],
+                        "inertial": {"type": "capsule", "size": [radius, half, 0.0], "mass": None},
+                        "joints": [{"type": "free", "axis": [0.0, 0.0, 1.0], "pos": [0.0, 0.0, 0.0]}]}],
+            "geoms": [{"body": -1, "type": "plane", "size": [0, 0, 0], "pos": [0, 0, 0], "quat": [1, 0, 0, 0]},
+                      {"body": 0, "type": "capsule", "size": [radius, half, 0.0], "pos": [0, 0, 0],
+                       "quat": [1, 0, 0, 0]}],
+            "pairs": [W._pair(0, 1, 1.0, 0.002)], "ctrl": {"dofs": []}}
+
+
+@pytest.mark.parametrize("tilt", [0.0, 0.3, np.pi / 2])
+def test_capsule_plane_end_spheres(oracle, tilt):
+    """Capsule against a plane (reading: both cap-end spheres, +axis end
+    first, no case split): for a capsule of radius a and half-length h with
+    its centre at height z and its axis tilted by th from the vertical, the
+    +axis end sphere is centred at height z + h cos(th) and the other at
+    z - h cos(th); the signed distances are those heights minus a, the points
+    lie halfway between each end sphere's lowest point and the plane, and the
+    normal is the plane's."""
+    a, h, z = 0.03, 0.125, 0.2
+    om = oracle.Model(_free_capsule(a, h))
+    q = np.array([0.1, -0.2, z, np.cos(tilt / 2), np.sin(tilt / 2), 0.0, 0.0])
+    c = om.contacts(q)
+    assert c.shape[0] == 2
+    for row, sgn in zip(c, (1.0, -1.0)):
+        end = np.array([0.1, -0.2, z]) + sgn * h * np.array([0.0, -np.sin(tilt), np.cos(tilt)])
+        r = end[2] - a
+        np.testing.assert_allclose(row[0], r, atol=1e-15)
+        np.testing.assert_allclose(row[1:4], end - np.array([0, 0, a + r / 2]), atol=1e-15)
+        np.testing.assert_allclose(row[4:7], [0, 0, 1], atol=0)
