@@ -21,7 +21,7 @@ _HEADERS = ["orc_api.h", "orc_math.hpp"]
 JOINT = {"free": 0, "hinge": 1, "slide": 2}
 GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
 
-STATUS_BITS = {"MAX_STEPS": 1, "DT_UNDERFLOW": 2, "NONFINITE": 4, "SOLVER_MAXIT": 8}
+STATUS_BITS = {"MAX_STEPS": 1, "DT_UNDERFLOW": 2, "NONFINITE": 4, "SOLVER_MAXIT": 8, "CONTACT_OVERFLOW": 16}
 
 
 def build(force=True):
@@ -71,6 +71,7 @@ def lib():
         L.orc_model_inertia.argtypes = [P, P, P, P]
         L.orc_kinematics.argtypes = [P, P, P, P, P, P, P, P]
         L.orc_contacts.argtypes = [P, P, P]
+        L.orc_contacts_cfd.argtypes = [P, P, C.c_int, P]
         L.orc_point_jac.argtypes = [P, P, C.c_int, P, P]
         L.orc_rhs.argtypes = [P, P, P, C.c_int, P, P, P]
         L.orc_rows.argtypes = [P, P, P, C.c_int, C.c_double, P, P, P, P, P]
@@ -180,9 +181,10 @@ class Model:
         lib().orc_kinematics(self.h, _p(q), _p(v), _p(xpos), _p(xmat), _p(M), _p(c), _p(tw))
         return dict(xpos=xpos, xmat=xmat, M=M, c=c, twist=tw)
 
-    def contacts(self, q):
+    def contacts(self, q, cfd=False):
+        """Candidate contacts at q, rows (r, pos[3], n[3], t1[3], t2[3])."""
         out = np.zeros((max(self.ncmax, 1), 13))
-        n = lib().orc_contacts(self.h, _p(_f64(q)), _p(out))
+        n = lib().orc_contacts_cfd(self.h, _p(_f64(q)), int(cfd), _p(out))
         return out[:n]
 
     def point_jac(self, q, body, point):

@@ -54,7 +54,9 @@ typedef struct {
                            the default: the continuous controller) */
 } orc_opts;
 
-enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8 };
+/* CONTACT_OVERFLOW: more than 256 contacts within reach at some evaluation; the
+ * first 256 in pair order were used (not fatal: the world continues). */
+enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8, ORC_CONTACT_OVERFLOW = 16 };
 
 void* orc_model_new(const orc_model_def* def);
 void orc_model_free(void* m);
@@ -69,6 +71,8 @@ int orc_kinematics(const void* m, const double* q, const double* v, double* xpos
                    double* M, double* c, double* twist);
 /* all candidate contacts at q: rows of 13 = r, pos[3], n[3], t1[3], t2[3]; returns count */
 int orc_contacts(const void* m, const double* q, double* out);
+/* the same with cfd = 1: box-box pairs also emit contacts within the CFD width w_c */
+int orc_contacts_cfd(const void* m, const double* q, int cfd, double* out);
 /* point Jacobian (3*nv) of a point attached to body b */
 void orc_point_jac(const void* m, const double* q, int body, const double* point, double* jac);
 /* right-hand side F(x) = (v, qacc); info = n_rows, n_active, newton_iterations, status */

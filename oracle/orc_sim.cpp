@@ -308,15 +308,163 @@ static void box_plane(const V3<S>& p0, const V3<S>& nw, const V3<S>& c, const M3
   }
 }
 
-// Candidate contacts of every listed pair (Sec. 2.1, "Collision detection"),
-// in pair order with a fixed number of slots per pair type.  reading: a
-// capsule against a plane emits both cap-centre spheres (+axis end first),
-// with no case split (the smoothing of App. C.1 is then unnecessary).
+template <class S> static S sabs(const S& x) { return val(x) < 0.0 ? S(0.0) - x : x; }
+
+// Box-box contacts.  reading (the paper names primitive-vs-primitive
+// detection in Sec. 2.1 but prints no box-box routine): the separating-axis
+// test over the 15 candidate axes (the three face normals of each box and the
+// nine cross products of an edge direction of each, skipping crosses shorter
+// than 1e-6).  The overlap of the boxes' projections on a unit axis L is
+// o(L) = sum_i a_i |L.u_i| + sum_j b_j |L.w_j| - |L.(c_B - c_A)|, with u_i, w_j
+// the box axes and a_i, b_j the half sizes; the contact axis is the one of
+// least overlap, a face axis unless the least edge overlap is smaller than the
+// least face overlap by more than 5% of its magnitude plus 1e-6 (ties: the
+// lower axis index).  Face axis: the box that owns it is the reference, the
+// other the incident box; the reference normal points from the reference box
+// toward the incident one; the incident face is the incident box's face most
+// opposed to it; its four corners, clipped against the four side planes of
+// the reference face (Sutherland-Hodgman), give up to 8 points, and each point
+// p with signed distance r = n.(p - f) to the reference face plane (through f)
+// below the margin is a contact at the midpoint p - (r/2) n.  Edge axis: one
+// contact between the two supporting edges (the edges of each box that
+// point along the axis' factors and lie furthest toward the other box), r the
+// signed distance between their lines along the axis, at the midpoint of the
+// lines' closest points.  The normal is reported from box A (geom 1) toward
+// box B; all decisions (axis, faces, clipping) are taken on values, so a
+// derivative holds them fixed.
 template <class S>
-static void collide(const Model& m, const Kin<S>& k, std::vector<Contact<S>>& out) {
+static void box_box(const V3<S>& cA, const M3<S>& RA, const V3<double>& ha, const V3<S>& cB, const M3<S>& RB,
+                    const V3<double>& hb, double margin, int pair, std::vector<Contact<S>>& out) {
+  V3<S> uA[3], uB[3];
+  for (int i = 0; i < 3; ++i) { uA[i] = col(RA, i); uB[i] = col(RB, i); }
+  const V3<S> d = sub(cB, cA);
+  auto overlap = [&](const V3<S>& L) {
+    S pa = S(0.0), pb = S(0.0);
+    for (int i = 0; i < 3; ++i) { pa += sabs(dot(L, uA[i])) * ha.x[i]; pb += sabs(dot(L, uB[i])) * hb.x[i]; }
+    return pa + pb - sabs(dot(L, d));
+  };
+  int face = 0, edge = -1;
+  double of = HUGE_VAL, oe = HUGE_VAL;
+  for (int i = 0; i < 6; ++i) {
+    const double o = val(overlap(i < 3 ? uA[i] : uB[i - 3]));
+    if (o < of) { of = o; face = i; }
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const V3<S> c = cross(uA[i], uB[j]);
+      const S cn = sqrt_(dot(c, c));
+      if (val(cn) < 1e-6) continue;
+      const double o = val(overlap(scale(c, S(1.0) / cn)));
+      if (o < oe) { oe = o; edge = 3 * i + j; }
+    }
+  const bool use_edge = edge >= 0 && oe < of - (0.05 * std::fabs(of) + 1e-6);
+  if (std::min(of, oe) <= -margin) return;  // separated by at least the margin along some axis
+  if (!use_edge) {
+    const bool refA = face < 3;
+    const int ax = face % 3;
+    const V3<S>* uR = refA ? uA : uB;
+    const V3<S>* uI = refA ? uB : uA;
+    const V3<double>& hR = refA ? ha : hb;
+    const V3<double>& hI = refA ? hb : ha;
+    const V3<S> cR = refA ? cA : cB, cI = refA ? cB : cA;
+    V3<S> nR = uR[ax];
+    if (val(dot(nR, sub(cI, cR))) < 0.0) nR = scale(nR, -1.0);
+    int fj = 0;
+    double best = -1.0;
+    for (int j = 0; j < 3; ++j) {
+      const double a = std::fabs(val(dot(nR, uI[j])));
+      if (a > best) { best = a; fj = j; }
+    }
+    // outward normal of the incident face points against nR
+    const double sg = val(dot(nR, uI[fj])) > 0.0 ? -1.0 : 1.0;
+    const V3<S> fc = add(cI, scale(uI[fj], sg * hI.x[fj]));
+    const int j1 = (fj + 1) % 3, j2 = (fj + 2) % 3;
+    std::vector<V3<S>> poly;
+    const double s1[4] = {1.0, -1.0, -1.0, 1.0}, s2[4] = {1.0, 1.0, -1.0, -1.0};
+    for (int c = 0; c < 4; ++c)
+      poly.push_back(add(fc, add(scale(uI[j1], s1[c] * hI.x[j1]), scale(uI[j2], s2[c] * hI.x[j2]))));
+    for (int kk = 1; kk <= 2; ++kk) {
+      const int k2 = (ax + kk) % 3;
+      for (int sgn = 1; sgn >= -1; sgn -= 2) {
+        // keep the side where sgn u_k.(p - c_R) <= h_k
+        auto f = [&](const V3<S>& P) { return dot(uR[k2], sub(P, cR)) * (double)sgn - hR.x[k2]; };
+        std::vector<V3<S>> nxt;
+        const size_t np = poly.size();
+        for (size_t i = 0; i < np; ++i) {
+          const V3<S>& P = poly[i];
+          const V3<S>& Q = poly[(i + 1) % np];
+          const S fP = f(P), fQ = f(Q);
+          const bool inP = val(fP) <= 0.0, inQ = val(fQ) <= 0.0;
+          if (inP) nxt.push_back(P);
+          if (inP != inQ) nxt.push_back(add(P, scale(sub(Q, P), fP / (fP - fQ))));
+        }
+        poly.swap(nxt);
+      }
+    }
+    const V3<S> pf = add(cR, scale(nR, hR.x[ax]));
+    for (const V3<S>& P : poly) {
+      const S r = dot(nR, sub(P, pf));
+      if (val(r) >= margin) continue;
+      Contact<S> ct;
+      ct.r = r;
+      ct.pos = sub(P, scale(nR, r * 0.5));
+      ct.n = refA ? nR : scale(nR, -1.0);
+      make_frame(ct.n, ct.t1, ct.t2);
+      ct.pair = pair;
+      out.push_back(ct);
+    }
+    return;
+  }
+  const int i = edge / 3, j = edge % 3;
+  V3<S> n = cross(uA[i], uB[j]);
+  n = scale(n, S(1.0) / sqrt_(dot(n, n)));
+  if (val(dot(n, d)) < 0.0) n = scale(n, -1.0);
+  V3<S> pA = cA, pB = cB;
+  for (int k2 = 0; k2 < 3; ++k2) {
+    if (k2 != i) pA = add(pA, scale(uA[k2], (val(dot(n, uA[k2])) >= 0.0 ? 1.0 : -1.0) * ha.x[k2]));
+    if (k2 != j) pB = add(pB, scale(uB[k2], (val(dot(n, uB[k2])) >= 0.0 ? -1.0 : 1.0) * hb.x[k2]));
+  }
+  // closest points of the lines pA + s uA_i and pB + t uB_j
+  const V3<S> w = sub(pA, pB);
+  const S b = dot(uA[i], uB[j]), dd = dot(uA[i], w), e = dot(uB[j], w);
+  const S den = S(1.0) - b * b;
+  const S sA = (b * e - dd) / den, tB = (e - b * dd) / den;
+  const V3<S> PA = add(pA, scale(uA[i], sA)), PB = add(pB, scale(uB[j], tB));
+  const S r = dot(n, sub(PB, PA));
+  if (val(r) >= margin) return;
+  Contact<S> ct;
+  ct.r = r;
+  ct.pos = scale(add(PA, PB), 0.5);
+  ct.n = n;
+  make_frame(n, ct.t1, ct.t2);
+  ct.pair = pair;
+  out.push_back(ct);
+}
+
+// Candidate contacts of every listed pair (Sec. 2.1, "Collision detection"),
+// in pair order; plane pairs with a fixed number of slots per pair type.
+// reading: a capsule against a plane emits both cap-centre spheres (+axis end
+// first), with no case split (the smoothing of App. C.1 is then
+// unnecessary).  Box-box pairs are first culled by their bounding spheres
+// (radius |half sizes|; kept if the centres are closer than the radii plus
+// the margin) and emit only contacts with r below the margin (the CFD width
+// w_c of the pair when cfd, else 0).
+template <class S>
+static void collide(const Model& m, const Kin<S>& k, std::vector<Contact<S>>& out, bool cfd = false) {
   out.clear();
   for (int p = 0; p < m.np; ++p) {
     int g1 = m.pg1[p], g2 = m.pg2[p];
+    if (m.gtype[g1] == G_BOX && m.gtype[g2] == G_BOX) {
+      const double margin = cfd ? m.pcfd[5 * p + 2] : 0.0;
+      const V3<double>& ha = m.gsize[g1];
+      const V3<double>& hb = m.gsize[g2];
+      const double ra = std::sqrt(ha.x[0] * ha.x[0] + ha.x[1] * ha.x[1] + ha.x[2] * ha.x[2]);
+      const double rb = std::sqrt(hb.x[0] * hb.x[0] + hb.x[1] * hb.x[1] + hb.x[2] * hb.x[2]);
+      const V3<S> dc = sub(k.gpos[g2], k.gpos[g1]);
+      if (std::sqrt(val(dot(dc, dc))) >= ra + rb + margin) continue;
+      box_box(k.gpos[g1], k.gmat[g1], ha, k.gpos[g2], k.gmat[g2], hb, margin, p, out);
+      continue;
+    }
     V3<S> n = col(k.gmat[g1], 2), p0 = k.gpos[g1];
     if (m.gtype[g2] == G_SPHERE) {
       out.push_back(sphere_plane(p0, n, k.gpos[g2], m.gsize[g2].x[0], p));
@@ -365,11 +513,16 @@ template <class S> static S softplus(S z, double beta) {
 // (reading).  With cfd (Sec. 4): rows for every contact with r < w_c, the
 // impedance continued for r >= 0 by the CFD spline from d_0 at r = 0 to d_c at
 // r = w_c, and the position term k*relu(-r) replaced by k*softplus(-r).
+// reading (capacity): at most kMaxContacts contacts make rows, taken in
+// candidate (pair) order; further ones are dropped and flagged.
+constexpr int kMaxContacts = 256;
+
 template <class S>
 static void make_rows(const Model& m, const Kin<S>& k, const std::vector<Contact<S>>& cons, const S* v,
-                      bool cfd, double beta, std::vector<Row<S>>& rows) {
+                      bool cfd, double beta, std::vector<Row<S>>& rows, bool* overflow = nullptr) {
   rows.clear();
   int nv = m.nv;
+  int n_on = 0;
   std::vector<S> J1(3 * nv), J2(3 * nv);
   for (const Contact<S>& ct : cons) {
     int p = ct.pair;
@@ -378,6 +531,8 @@ static void make_rows(const Model& m, const Kin<S>& k, const std::vector<Contact
     double r = val(ct.r);
     bool on = cfd ? (r < cf[2]) : (r < 0.0);
     if (!on) continue;
+    if (n_on == kMaxContacts) { if (overflow) *overflow = true; continue; }
+    ++n_on;
     int b1 = m.gbody[m.pg1[p]], b2 = m.gbody[m.pg2[p]];
     for (int i = 0; i < 3 * nv; ++i) { J1[i] = S(0.0); J2[i] = S(0.0); }
     if (b1 >= 0) point_jac(m, k, b1, ct.pos, J1.data(), (S*)nullptr);
@@ -582,9 +737,11 @@ static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, i
   std::vector<S> a0 = f0;
   chol_solve(L, nv, a0);
   std::vector<Contact<S>> cons;
-  collide(m, kin, cons);
+  collide(m, kin, cons, cfd);
   std::vector<Row<S>> rows;
-  make_rows(m, kin, cons, v, cfd, beta, rows);
+  bool overflow = false;
+  make_rows(m, kin, cons, v, cfd, beta, rows, &overflow);
+  if (overflow) st->status |= ORC_CONTACT_OVERFLOW;
   st->rhs += 1;
   st->nrows = (int)rows.size();
   for (int i = 0; i < nv; ++i) kout[i] = v[i];
@@ -795,7 +952,7 @@ static int rollout(const Model& m, const S* x0, const S* u, int n_int, double dt
   for (int i = 0; i < nx; ++i) yv[i] = val(y[i]);
   if (!finite_vec(yv.data(), nx)) { st->status |= ORC_NONFINITE; }
   std::vector<S> uz(1, S(0.0));
-  for (int kk = 0; kk < n_int && st->status == 0; ++kk) {
+  for (int kk = 0; kk < n_int && (st->status & ~ORC_CONTACT_OVERFLOW) == 0; ++kk) {
     const S* uk = m.nu > 0 ? u + (size_t)kk * m.nu : uz.data();
     double tend = (double)(kk + 1) * dt;
     bool have_k1 = false;
@@ -908,8 +1065,8 @@ extern "C" void* orc_model_new(const orc_model_def* d) {
     m->pg1.push_back(d->pair_g1[p]); m->pg2.push_back(d->pair_g2[p]); m->pmu.push_back(d->pair_mu[p]);
     for (int i = 0; i < 2; ++i) m->psolref.push_back(d->pair_solref[2 * p + i]);
     for (int i = 0; i < 5; ++i) { m->psolimp.push_back(d->pair_solimp[5 * p + i]); m->pcfd.push_back(d->pair_cfd[5 * p + i]); }
-    int t2 = d->geom_type[d->pair_g2[p]];
-    int nc = t2 == G_SPHERE ? 1 : t2 == G_CAPSULE ? 2 : 4;
+    int t1 = d->geom_type[d->pair_g1[p]], t2 = d->geom_type[d->pair_g2[p]];
+    int nc = t1 == G_BOX ? 8 : t2 == G_SPHERE ? 1 : t2 == G_CAPSULE ? 2 : 4;
     m->pncon.push_back(nc); m->pcadr.push_back(m->ncmax); m->ncmax += nc;
   }
   for (int i = 0; i < m->nu; ++i) m->ctrl.push_back(d->ctrl_dof[i]);
@@ -972,11 +1129,15 @@ extern "C" int orc_kinematics(const void* mp, const double* q, const double* v, 
 }
 
 extern "C" int orc_contacts(const void* mp, const double* q, double* out) {
+  return orc_contacts_cfd(mp, q, 0, out);
+}
+
+extern "C" int orc_contacts_cfd(const void* mp, const double* q, int cfd, double* out) {
   const Model& m = *static_cast<const Model*>(mp);
   Kin<double> k;
   kinematics(m, q, (const double*)nullptr, k);
   std::vector<Contact<double>> cons;
-  collide(m, k, cons);
+  collide(m, k, cons, cfd != 0);
   for (size_t i = 0; i < cons.size(); ++i) {
     double* o = out + 13 * i;
     o[0] = cons[i].r;
@@ -1020,7 +1181,7 @@ extern "C" int orc_rows(const void* mp, const double* x, const double* u, int cf
   chol_solve(L, nv, f0);
   for (int i = 0; i < nv; ++i) a0[i] = f0[i];
   std::vector<Contact<double>> cons;
-  collide(m, kin, cons);
+  collide(m, kin, cons, cfd != 0);
   std::vector<Row<double>> rows;
   make_rows(m, kin, cons, x + m.nq, cfd != 0, beta, rows);
   for (size_t e = 0; e < rows.size(); ++e) {

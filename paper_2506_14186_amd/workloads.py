@@ -122,6 +122,57 @@ def model_box(half=0.1, mass=1.0, mu=0.8, tc=0.001, solimp=None, ctrl=False):
     }
 
 
+def model_stack(k, half=0.1, mass=1.0, mu=0.6, tc=0.003, solimp=None, ctrl=False):
+    """Stack of k free cubes (edge 2 half, mass each) with box geoms: pairs are
+    every cube against the plane (cube order), then every cube pair (i, j),
+    i < j, in lexicographic order.  With ctrl, the 6 generalized forces act on
+    the top cube's free joint."""
+    bodies, geoms, pairs = [], [_plane()], []
+    for i in range(k):
+        bodies.append({"parent": -1, "pos": [0.0, 0.0, 0.0], "quat": [1.0, 0.0, 0.0, 0.0],
+                       "inertial": {"type": "box", "size": [half, half, half], "mass": mass},
+                       "joints": [{"type": "free", "axis": [0.0, 0.0, 1.0], "pos": [0.0, 0.0, 0.0]}]})
+        geoms.append({"body": i, "type": "box", "size": [half, half, half], "pos": [0.0, 0.0, 0.0],
+                      "quat": [1.0, 0.0, 0.0, 0.0]})
+    for i in range(k):
+        pairs.append(_pair(0, 1 + i, mu, tc, solimp))
+    for i in range(k):
+        for j in range(i + 1, k):
+            pairs.append(_pair(1 + i, 1 + j, mu, tc, solimp))
+    return {"name": f"stack{k}", "gravity": list(GRAVITY), "bodies": bodies, "geoms": geoms, "pairs": pairs,
+            "ctrl": {"dofs": [6 * (k - 1) + d for d in range(6)] if ctrl else []}}
+
+
+def stack_state(offsets, half=0.1, gap=0.001):
+    """Initial state of a stack: cube i centred at (offsets[i], (i + 1/2) edge +
+    (i + 1) gap), identity orientation, at rest."""
+    k = len(offsets)
+    x = np.zeros(13 * k)
+    for i in range(k):
+        x[7 * i + 0:7 * i + 2] = offsets[i]
+        x[7 * i + 2] = half + gap + i * (2.0 * half + gap)
+        x[7 * i + 3] = 1.0
+    return x
+
+
+def cube_stacks(seed=4, n_worlds=1024, kmax=32, horizon=1.0, mu=0.6, tc_range=(0.001, 0.005)):
+    """Uneven batch of cube stacks: k ~ U{1..kmax} cubes per world, each cube
+    offset laterally by N(0, 0.02^2) per axis (independently, not cumulative),
+    1 mm gaps, at rest, identity orientation; per-world contact time constant
+    t_c ~ U(tc_range); mu as given.  Returns per-world model descriptions and
+    states (ragged: 13 k doubles each)."""
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(1, kmax + 1, size=n_worlds)
+    tcs = rng.uniform(tc_range[0], tc_range[1], size=n_worlds)
+    models, x0 = [], []
+    for w in range(n_worlds):
+        k = int(ks[w])
+        off = rng.normal(0.0, 0.02, size=(k, 2))
+        models.append(model_stack(k, mu=mu, tc=float(tcs[w])))
+        x0.append(stack_state(off))
+    return {"models": models, "x0": x0, "k": ks, "tc": tcs, "n_intervals": 1, "interval_dt": float(horizon)}
+
+
 def model_chain(link_half=0.125, radius=0.03, mu=1.0, tc=0.002, solimp=None):
     """Planar legged chain: a horizontal torso capsule with a planar root
     (slide x, slide z, hinge y) and two legs (thigh + shin capsules, hinge y at
@@ -281,4 +332,5 @@ CONFIGS = {
     "cube_toss": cube_toss,
     "chain_walk": chain_walk,
     "box_toss": box_toss,
+    "cube_stacks": cube_stacks,
 }
