@@ -1,17 +1,20 @@
 """Benchmark: batched forward + adjoint rollouts on one MI355X.
 
-A step is one pass of the whole hot path over one batch: dmx_rollout (adaptive
-Dormand-Prince 5(4) with the soft-contact Newton solve, tape of accepted steps)
-followed by dmx_rollout_vjp (discrete adjoint of the summed final position),
-on the cube-on-plane workload: 4096 free cubes (edge 0.2 m, 1 kg) with 8
-corner-sphere contacts, stiff contact (t_c 1 ms), random pose and velocity,
-0.5 s horizon, rtol 1e-6, atol 1e-8, FP64 throughout.
+A step is one pass of the whole hot path over one batch: dmx_rollout_batch
+(adaptive Dormand-Prince 5(4) with the soft-contact Newton solve, tape of
+accepted steps) followed by dmx_rollout_vjp (discrete adjoint of the summed
+final cube positions), on the uneven stack batch: 1024 worlds, each a stack of
+k ~ U{1..32} free cubes (edge 0.2 m, 1 kg) with plane-box and box-box
+contacts, lateral offsets N(0, 0.02) m, mu 0.6, t_c ~ U(1, 5) ms per world,
+1 s horizon, rtol 1e-6, atol 1e-8, FP64 throughout, all worlds in one
+persistent launch.
 
-Prints one JSON line with the throughput in world-simulated seconds per wall
+Prints one JSON line: the throughput in world-simulated seconds per wall
 second, the roofline of the dominant kernel (FP64 ALU bound, algorithmic
 FLOPs from per-unit counts x work units counted by the kernels), the plain
-one-world-per-launch GPU form of the same kernels, and the CPU oracle timed on
-this host.
+one-world-per-launch GPU form of the same kernels, the CPU oracle timed on
+this host, the other workloads (single-sphere latency, cube tosses, legged
+chains) and the serving leg.
 """
 import argparse
 import json
@@ -47,12 +50,40 @@ ADJ_FLOPS = {
 }
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    if it was taken on the kernels as built now (same device-code digest)."""
+# Cube-stack worlds: per-unit algorithmic FP64 operations; units counted by
+# the kernels per world and scaled by the world's cube count k on the host.
+STACK_FWD_FLOPS = {
+    "body_attempts": 1650,     # 6 stage combinations of 6 dofs, 6 (+)-maps, error terms of 13 coordinates
+    "body_rhs": 850,           # frame, twist, a0; the neighbour pair's separating-axis test and face clipping
+    "rhs_contacts": 100,       # frame, impedance, reference acceleration of a contact
+    "body_newton_iters": 1300, # block assembly, 6x6 block Cholesky step, forward and backward block solves
+    "newton_contacts": 500,    # rows, edge slacks, Hessian and gradient sums of an active contact
+    "ls_contacts": 250,        # line-search slopes of a contact per iteration
+}
+STACK_ADJ_FLOPS = {
+    "body_steps": 2000,        # 7 stage rebuilds, (+)-map VJPs and tableau distribution of 6 dofs
+    "body_vjps": 2300,         # frames, contacts, Hessian assembly, block Cholesky and solve for lambda, bias VJP
+    "vjp_contacts": 1000,      # reverse of the rows and of the contact geometry of an active contact
+}
+
+
+def stack_units(fc, ac, ks):
+    """Per-world counters [W][7] and [W][4] to the stack units."""
+    fc, ac, ks = np.asarray(fc, float), np.asarray(ac, float), np.asarray(ks, float)
+    return ({"body_attempts": float((fc[:, 0] * ks).sum()), "body_rhs": float((fc[:, 1] * ks).sum()),
+             "rhs_contacts": float(fc[:, 2].sum()), "body_newton_iters": float((fc[:, 3] * ks).sum()),
+             "newton_contacts": float(fc[:, 4].sum()), "ls_contacts": float(fc[:, 6].sum())},
+            {"body_steps": float((ac[:, 0] * ks).sum()), "body_vjps": float((ac[:, 1] * ks).sum()),
+             "vjp_contacts": float(ac[:, 2].sum())})
+
+
+def recorded_traffic(kernel, fname):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    `profiles/<fname>`, if it was taken on the kernels as built now (same
+    device-code digest)."""
     import re
     from paper_2506_14186_amd import build as B
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_cube_toss_4096.md")
+    path = os.path.join(ROOT, "profiles", fname)
     try:
         text = open(path).read()
     except OSError:
@@ -141,26 +172,286 @@ def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
             "requests_shape": "N~U{16..256} candidates, H~U{50..500} x 10 ms, cost+control gradient"}
 
 
+def timed_steps(step, steps, warmup, stream):
+    """W untimed warm-up steps, then K timed steps between synchronizations;
+    per-step forward/reverse times from events on the library's stream."""
+    import torch
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    adj = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    return (t1 - t0) * 1e3 / steps, fwd, adj
+
+
+def roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, fwd_name, adj_name, traffic_file):
+    dom_name, dom_ms, dom_flops = (fwd_name, fwd_ms, fwd_flops) if fwd_ms >= adj_ms else (adj_name, adj_ms, adj_flops)
+    oth_name, oth_ms, oth_flops = (adj_name, adj_ms, adj_flops) if fwd_ms >= adj_ms else (fwd_name, fwd_ms, fwd_flops)
+    achieved = dom_flops / (dom_ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": recorded_traffic(dom_name, traffic_file),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": dom_name, "kernel_ms": round(dom_ms, 3), "flops_per_launch": dom_flops,
+            "other_kernel": {"name": oth_name, "ms": round(oth_ms, 3),
+                             "achieved_tflops": round(oth_flops / (oth_ms / 1e3) / 1e12, 4)}}
+
+
+def stack_leg(D, W, args, dev):
+    """The uneven stack batch (headline): 1024 worlds of 1..32 cubes."""
+    import torch
+    cfg = W.cube_stacks(seed=4, n_worlds=args.stack_worlds, kmax=args.kmax, horizon=args.stack_horizon)
+    models = [D.Model(m) for m in cfg["models"]]
+    ks = np.asarray(cfg["k"])
+    nW, T = len(models), cfg["interval_dt"]
+    x0 = torch.tensor(np.concatenate(cfg["x0"]), dtype=torch.float64, device=dev)
+    xb = np.concatenate([np.tile([1, 1, 1, 0, 0, 0, 0], k).astype(float).tolist() + [0.0] * (6 * k) for k in ks])
+    xbar = torch.tensor(xb, dtype=torch.float64, device=dev)
+    fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
+    adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
+    copts = D.default_opts(tape_steps=args.stack_tape, fwd_counters=fwd_cnt.data_ptr(),
+                           adj_counters=adj_cnt.data_ptr())
+    r = D.rollout_batch(models, x0, None, 1, T, opts=copts, tape=True, counters=True)
+    tape = r["tape"]
+    D.rollout_batch_vjp(tape, xbar)
+    torch.cuda.synchronize()
+    status = r["status"].cpu().numpy()
+    n_acc = r["n_acc"].cpu().numpy()
+    n_att = n_acc + r["n_rej"].cpu().numpy()
+    fu, au = stack_units(fwd_cnt.cpu().numpy(), adj_cnt.cpu().numpy(), ks)
+    fwd_flops = algorithmic_flops(fu, STACK_FWD_FLOPS, 0)
+    adj_flops = algorithmic_flops(au, STACK_ADJ_FLOPS, 0)
+    opts = D.default_opts(tape_steps=args.stack_tape)
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        if ev:
+            ev[0].record(stream)
+        D.rollout_batch(models, x0, None, 1, T, opts=opts, reuse=tape)
+        if ev:
+            ev[1].record(stream)
+        D.rollout_batch_vjp(tape, xbar)
+        if ev:
+            ev[2].record(stream)
+
+    ms, fwd_ms, adj_ms = timed_steps(step, args.steps, args.warmup, stream)
+    value = float(nW * T / (ms / 1e3))
+    out = {"value": value, "ms_per_step": ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms, "worlds": nW, "horizon": T,
+           "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
+                                   "hbm_traffic_stacks_1024.md"),
+           "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
+                    "accepted_steps_max": int(n_acc.max()), "attempts_max": int(n_att.max()),
+                    "cubes_mean": float(ks.mean()), "cubes_total": int(ks.sum()),
+                    "failed_worlds": int(((status & ~D.STATUS["CONTACT_OVERFLOW"]) != 0).sum()),
+                    "overflow_worlds": int(((status & D.STATUS["CONTACT_OVERFLOW"]) != 0).sum()),
+                    "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}}
+    if not args.no_plain:
+        # plain GPU form: the same kernels, one world per launch, on a seeded sample
+        rng = np.random.default_rng(11)
+        sel = np.sort(rng.choice(nW, size=min(args.plain_worlds, nW), replace=False))
+        pm = [models[w] for w in sel]
+        px = torch.tensor(np.concatenate([cfg["x0"][w] for w in sel]), dtype=torch.float64, device=dev)
+        pxb = torch.tensor(np.concatenate([xb[int(sum(13 * ks[:w])):int(sum(13 * ks[:w + 1]))] for w in sel]),
+                           dtype=torch.float64, device=dev)
+        popts = D.default_opts(tape_steps=args.stack_tape, launch_mode=1)
+        rp = D.rollout_batch(pm, px, None, 1, T, opts=popts, tape=True)
+        D.rollout_batch_vjp(rp["tape"], pxb)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        D.rollout_batch(pm, px, None, 1, T, opts=popts, reuse=rp["tape"])
+        D.rollout_batch_vjp(rp["tape"], pxb)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp0
+        share = float(ks[sel].sum()) / float(ks.sum())  # of the batch's cubes
+        pv = len(sel) * T / tp
+        out["plain"] = {"value": round(pv, 3), "unit": "world-sim-s/s", "worlds_timed": int(len(sel)),
+                        "cubes_timed": int(ks[sel].sum()), "ms_for_subset": round(tp * 1e3, 2),
+                        "extrapolated_ms_full_batch": round(tp * 1e3 / share, 1),
+                        "speedup_batched_over_plain": round((tp / share) / (ms / 1e3), 2)}
+    if not args.no_cpu:
+        out["cpu"] = stack_cpu_baseline(cfg, args.cpu_seconds)
+    return out
+
+
+def stack_cpu_baseline(cfg, budget_s):
+    """The oracle (forward plus forward-mode gradient of the same loss) on
+    a bounded sample of the stack batch: worlds in a seeded random order, the
+    first 0.02 s of each, on the host's threads, until the time budget is
+    spent; the rate is simulated seconds per wall second."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    nthreads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(17)
+    order = rng.permutation(len(cfg["models"]))
+    T = 0.02
+    done, sim, ks = [], 0.0, []
+    t0 = time.perf_counter()
+
+    def one(w):
+        om = O.Model(cfg["models"][w])
+        x = cfg["x0"][w]
+        k = x.size // 13
+        xb = np.zeros((1, x.size))
+        for i in range(k):
+            xb[0, 7 * i:7 * i + 3] = 1.0
+        om.grad_batch(x[None], None, 1, T, xb, n_threads=1)
+        return k
+
+    with ThreadPoolExecutor(max_workers=nthreads) as ex:
+        it = iter(order)
+        futs = [ex.submit(one, int(next(it))) for _ in range(nthreads)]
+        while futs:
+            f = futs.pop(0)
+            ks.append(f.result())
+            done.append(1)
+            sim += T
+            if time.perf_counter() - t0 < budget_s:
+                try:
+                    futs.append(ex.submit(one, int(next(it))))
+                except StopIteration:
+                    pass
+    wall = time.perf_counter() - t0
+    return {"value": round(sim / wall, 4), "unit": "world-sim-s/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{len(done)} stack worlds in a seeded random order (cubes mean {np.mean(ks):.1f}), the "
+                      f"first {T} s of each, forward + gradient (forward-mode over all initial-state directions), "
+                      f"{wall:.1f} s wall on {nthreads} threads"}
+
+
+def cube_leg(D, W, args, dev):
+    """Cube tosses: 4096 free cubes with 8 corner contacts, 0.5 s."""
+    import torch
+    cfg = W.cube_toss(seed=2, n_worlds=4096, horizon=0.5)
+    model = D.Model(cfg["model"])
+    x0 = torch.tensor(cfg["x0"], dtype=torch.float64, device=dev)
+    xbar = torch.zeros_like(x0)
+    xbar[:, 0:3] = 1.0
+    nW, horizon = x0.shape[0], 0.5
+    best, times = (None, None)
+    if not args.no_autotune:
+        best, times = D.autotune(model, x0, None, 1, horizon)
+    fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
+    adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
+    copts = D.default_opts(tape_steps=2048, fwd_counters=fwd_cnt.data_ptr(), adj_counters=adj_cnt.data_ptr())
+    r = D.rollout(model, x0, None, 1, horizon, opts=copts, tape=True, counters=True)
+    tape = r["tape"]
+    D.rollout_vjp(tape, xbar)
+    torch.cuda.synchronize()
+    fc = dict(zip(D.FWD_COUNTERS, fwd_cnt.sum(0).cpu().numpy().tolist()))
+    ac = dict(zip(D.ADJ_COUNTERS, adj_cnt.sum(0).cpu().numpy().tolist()))
+    opts = D.default_opts(tape_steps=2048)
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        if ev:
+            ev[0].record(stream)
+        D.rollout(model, x0, None, 1, horizon, opts=opts, reuse=tape)
+        if ev:
+            ev[1].record(stream)
+        D.rollout_vjp(tape, xbar)
+        if ev:
+            ev[2].record(stream)
+
+    ms, fwd_ms, adj_ms = timed_steps(step, args.other_steps, 1, stream)
+    fwd_flops = algorithmic_flops(fc, FWD_FLOPS, model.ncon)
+    adj_flops = algorithmic_flops(ac, ADJ_FLOPS, model.ncon)
+    return {"workload": "cube_toss: 4096 free cubes x 8 corner contacts, 0.5 s, t_c 1 ms",
+            "value": round(nW * horizon / (ms / 1e3), 2), "unit": "world-sim-s/s", "ms_per_step": round(ms, 3),
+            "autotune": {"lanes_per_world": best, "fwd_ms_by_lanes": {str(k): round(v, 3) for k, v in times.items()}}
+            if times else None,
+            "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "fwd_kernel", "adj_kernel",
+                                    "hbm_traffic_cube_toss_4096.md")}
+
+
+def chain_leg(D, W, args, dev):
+    """Legged chains: 16384 worlds, 200 torque intervals of 10 ms."""
+    import torch
+    cfg = W.chain_walk(seed=3, n_worlds=16384)
+    model = D.Model(cfg["model"])
+    x0 = torch.tensor(cfg["x0"], dtype=torch.float64, device=dev)
+    u = torch.tensor(cfg["u"], dtype=torch.float64, device=dev)
+    xbar = torch.zeros_like(x0)
+    xbar[:, 0] = 2.0 * x0[:, 0]
+    nW, n_int, dt = x0.shape[0], cfg["n_intervals"], cfg["interval_dt"]
+    opts = D.default_opts(tape_steps=8192)
+    r = D.rollout(model, x0, u, n_int, dt, opts=opts, tape=True)
+    tape = r["tape"]
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        if ev:
+            ev[0].record(stream)
+        rr = D.rollout(model, x0, u, n_int, dt, opts=opts, reuse=tape)
+        if ev:
+            ev[1].record(stream)
+        # L = sum over worlds of x_root^2 + z_root^2: cotangent 2 (x, z) at the end
+        xb = torch.zeros_like(x0)
+        xb[:, 0:2] = 2.0 * rr["x"][:, 0:2]
+        D.rollout_vjp(tape, xb)
+        if ev:
+            ev[2].record(stream)
+
+    ms, fwd_ms, adj_ms = timed_steps(step, 1, 1, stream)
+    return {"workload": "chain_walk: 16384 planar legged chains, 200 x 10 ms torque intervals, checkpointed tape",
+            "value": round(nW * n_int * dt / (ms / 1e3), 2), "unit": "world-sim-s/s", "ms_per_step": round(ms, 3),
+            "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}
+
+
+def sphere_leg(D, W, args, dev):
+    """One sphere dropped onto a plane, 1 s: latency of forward + adjoint."""
+    import torch
+    cfg = W.sphere_drop(seed=1)
+    model = D.Model(cfg["model"])
+    x0 = torch.tensor(cfg["x0"], dtype=torch.float64, device=dev)
+    xbar = torch.zeros_like(x0)
+    xbar[:, 2] = 1.0
+    r = D.rollout(model, x0, None, 1, 1.0, tape=True)
+    tape = r["tape"]
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        if ev:
+            ev[0].record(stream)
+        D.rollout(model, x0, None, 1, 1.0, reuse=tape)
+        if ev:
+            ev[1].record(stream)
+        g, _ = D.rollout_vjp(tape, xbar)
+        if ev:
+            ev[2].record(stream)
+        return g
+
+    ms, fwd_ms, adj_ms = timed_steps(step, 5, 2, stream)
+    g = step(None)
+    torch.cuda.synchronize()
+    return {"workload": "sphere_drop: 1 sphere, 1 s, fwd + adjoint of the final height",
+            "latency_ms": round(ms, 3), "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3),
+            "dz_dv0": [float(v) for v in g[0, 7:10].cpu().numpy()]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--worlds", type=int, default=4096)
-    ap.add_argument("--horizon", type=float, default=0.5)
-    ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--plain-worlds", type=int, default=64)
-    ap.add_argument("--cpu-worlds", type=int, default=2048)
+    ap.add_argument("--stack-worlds", type=int, default=1024)
+    ap.add_argument("--kmax", type=int, default=32)
+    ap.add_argument("--stack-horizon", type=float, default=1.0)
+    ap.add_argument("--stack-tape", type=int, default=4096)
+    ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the cube and sphere legs")
+    ap.add_argument("--plain-worlds", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-others", action="store_true", help="skip the cube, chain and sphere legs")
+    ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg, s")
-    ap.add_argument("--no-critical", action="store_true", help="skip the hardest-world-alone leg")
-    ap.add_argument("--hardest-only", action="store_true",
-                    help="after the counted pass, run only the forward of the world with the most attempts "
-                         "(one wavefront; for instruction counters) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -186,179 +477,45 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
         return
-    cfg = W.cube_toss(seed=2, n_worlds=args.worlds, horizon=args.horizon)
-    model = D.Model(cfg["model"])
-    x0 = torch.tensor(cfg["x0"], dtype=torch.float64, device=dev)
-    xbar = torch.zeros_like(x0)
-    xbar[:, 0:3] = 1.0  # gradient of the summed final positions
-    nW, horizon = args.worlds, args.horizon
-    fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
-    adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
-    tuned = None
-    if args.lanes == 0 and not args.no_autotune:
-        # team size picked by timing the forward with each compiled one on this batch
-        best, times = D.autotune(model, x0, None, 1, horizon)
-        tuned = {"lanes_per_world": best, "fwd_ms_by_lanes": {str(k): round(v, 3) for k, v in times.items()}}
-    opts = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes)
-
-    # one counted pass (work units), which also allocates the tape reused below
-    copts = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes, fwd_counters=fwd_cnt.data_ptr(),
-                           adj_counters=adj_cnt.data_ptr())
-    r = D.rollout(model, x0, None, 1, horizon, opts=copts, tape=True, counters=True)
-    tape = r["tape"]
-    g, _ = D.rollout_vjp(tape, xbar)
-    torch.cuda.synchronize()
-    status = r["status"].cpu().numpy()
-    n_acc = r["n_acc"].cpu().numpy()
-    fc = dict(zip(D.FWD_COUNTERS, fwd_cnt.sum(0).cpu().numpy().tolist()))
-    ac = dict(zip(D.ADJ_COUNTERS, adj_cnt.sum(0).cpu().numpy().tolist()))
-    fwd_flops = algorithmic_flops(fc, FWD_FLOPS, model.ncon)
-    adj_flops = algorithmic_flops(ac, ADJ_FLOPS, model.ncon)
-
-    n_att = n_acc + r["n_rej"].cpu().numpy()
-    hard = int(np.argmax(n_att))
-
-    def alone(reps=3):
-        """The hardest world as a batch of one: forward and reverse launch times
-        (min over reps) -- the serial chain that bounds the batched launches."""
-        x1 = x0[hard:hard + 1].clone()
-        o1 = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes or (tuned or {}).get("lanes_per_world", 0))
-        r1 = D.rollout(model, x1, None, 1, horizon, opts=o1, tape=True)
-        xb1 = xbar[hard:hard + 1].clone()
-        D.rollout_vjp(r1["tape"], xb1)
-        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        tf, ta = [], []
-        for _ in range(reps):
-            ev1[0].record()
-            D.rollout(model, x1, None, 1, horizon, opts=o1, reuse=r1["tape"])
-            ev1[1].record()
-            D.rollout_vjp(r1["tape"], xb1)
-            ev1[2].record()
-            torch.cuda.synchronize()
-            tf.append(ev1[0].elapsed_time(ev1[1])); ta.append(ev1[1].elapsed_time(ev1[2]))
-        return min(tf), min(ta)
-
-    if args.hardest_only:
-        tf, ta = alone(reps=1)
-        print(json.dumps({"hardest_world": hard, "attempts": int(n_att[hard]), "fwd_ms": round(tf, 3),
-                          "adj_ms": round(ta, 3)}), flush=True)
-        return
-
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        rr = D.rollout(model, x0, None, 1, horizon, opts=opts, reuse=tape)
-        if ev:
-            ev[1].record(stream)
-        gg, _ = D.rollout_vjp(rr["tape"], xbar)
-        if ev:
-            ev[2].record(stream)
-        return rr, gg
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    value = nW * horizon / (ms_per_step / 1e3)
-
-    dom_name, dom_ms, dom_flops = ("fwd_kernel", fwd_ms, fwd_flops) if fwd_ms >= adj_ms else \
-        ("adj_kernel", adj_ms, adj_flops)
-    achieved = dom_flops / (dom_ms / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": recorded_traffic(dom_name),
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-                "kernel": dom_name,
-                "kernel_ms": round(dom_ms, 3), "flops_per_launch": dom_flops,
-                "other_kernel": {"name": "adj_kernel" if dom_name == "fwd_kernel" else "fwd_kernel",
-                                 "ms": round(adj_ms if dom_name == "fwd_kernel" else fwd_ms, 3),
-                                 "achieved_tflops": round((adj_flops / adj_ms if dom_name == "fwd_kernel"
-                                                           else fwd_flops / fwd_ms) / 1e9, 4)}}
-
-    # plain GPU form: the same kernels, one world per launch, on a subset
-    plain = None
-    if not args.no_plain:
-        P = min(args.plain_worlds, nW)
-        xs, xbs = x0[:P].contiguous(), xbar[:P].contiguous()
-        popts = D.default_opts(tape_steps=2048, lanes_per_world=args.lanes, launch_mode=1)
-        rp = D.rollout(model, xs, None, 1, horizon, opts=popts, tape=True)
-        D.rollout_vjp(rp["tape"], xbs)
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        rp = D.rollout(model, xs, None, 1, horizon, opts=popts, reuse=rp["tape"])
-        D.rollout_vjp(rp["tape"], xbs)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - tp0
-        plain_value = P * horizon / tp
-        plain = {"value": round(plain_value, 2), "unit": "world-sim-s/s", "worlds_timed": P,
-                 "ms_for_subset": round(tp * 1e3, 2), "extrapolated_ms_full_batch": round(tp * 1e3 * nW / P, 1),
-                 "speedup_batched_over_plain": round(value / plain_value, 2)}
-
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as O
-        S = min(args.cpu_worlds, nW)
-        om = O.Model(cfg["model"])
-        nthreads = min(16, os.cpu_count() or 1)
-        xb = np.zeros((S, 13))
-        xb[:, :3] = 1.0
-        tc0 = time.perf_counter()
-        om.grad_batch(cfg["x0"][:S], None, 1, horizon, xb, n_threads=nthreads)
-        tc = time.perf_counter() - tc0
-        cpu = {"value": round(S * horizon / tc, 3), "unit": "world-sim-s/s", "cores": nthreads, "kind": "oracle",
-               "sample": f"first {S} of the {nW} worlds, full {horizon} s horizon, forward + gradient "
-                         f"(forward-mode over the 13 initial-state directions), {tc:.1f} s wall on "
-                         f"{nthreads} threads"}
-
+    print(f"bench: stack batch ({args.stack_worlds} worlds) ...", file=sys.stderr, flush=True)
+    st = stack_leg(D, W, args, dev)
+    others = {}
+    if not args.no_others:
+        print("bench: sphere latency, cube tosses ...", file=sys.stderr, flush=True)
+        others["sphere_latency"] = sphere_leg(D, W, args, dev)
+        others["cube_toss"] = cube_leg(D, W, args, dev)
+        if not args.no_chain:
+            print("bench: legged chains ...", file=sys.stderr, flush=True)
+            others["chain_walk"] = chain_leg(D, W, args, dev)
     serving = None
     if not args.no_serve:
+        print("bench: serving ...", file=sys.stderr, flush=True)
         serving = serve_leg(D, W, args.serve_rate, args.serve_seconds)
-
-    critical = None
-    if not args.no_critical:
-        tf, ta = alone()
-        critical = {"world": hard, "attempts": int(n_att[hard]), "accepted": int(n_acc[hard]),
-                    "attempts_mean": round(float(n_att.mean()), 1),
-                    "alone_fwd_ms": round(tf, 3), "alone_adj_ms": round(ta, 3),
-                    "alone_us_per_attempt": round(tf * 1e3 / float(n_att[hard]), 2),
-                    "batch_fwd_ms": round(fwd_ms, 3), "batch_adj_ms": round(adj_ms, 3)}
-
     out = {
         "metric": "sim-seconds/s fwd+adjoint at rtol 1e-6 vs plain GPU form; p99 request latency",
-        "value": round(value, 2),
+        "value": round(st["value"], 3),
         "unit": "world-sim-s/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(st["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"cube_toss: {nW} free cubes x 8 corner contacts, {horizon} s, t_c 1 ms, "
-                               f"rtol 1e-6 atol 1e-8, fwd + adjoint of summed final position",
-                   "worlds": nW, "horizon_s": horizon,
-                   "lanes_per_world": args.lanes or (tuned["lanes_per_world"] if tuned else "default"),
-                   "autotune": tuned,
-                   "parallelism": "1 GPU, worlds batched in one launch"},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "plain_gpu": plain,
+        "config": {"workload": f"cube_stacks: {st['worlds']} worlds of k ~ U{{1..{args.kmax}}} free cubes "
+                               f"(plane-box and box-box contacts), lateral offsets N(0, 0.02) m, mu 0.6, "
+                               f"t_c ~ U(1, 5) ms, {st['horizon']} s, rtol 1e-6 atol 1e-8, fwd + adjoint of the "
+                               f"summed final cube positions, one persistent launch",
+                   "worlds": st["worlds"], "horizon_s": st["horizon"], "cubes_total": st["work"]["cubes_total"],
+                   "parallelism": "1 GPU, one wavefront per world, device work queue (most cubes first)"},
+        "roofline": st["roofline"],
+        "cpu_baseline": st.get("cpu"),
+        "plain_gpu": st.get("plain"),
+        "work": st["work"],
+        "other_workloads": others,
         "serving": serving,
-        "critical_path": critical,
-        "work": {"fwd": fc, "adj": ac, "accepted_steps_mean": float(n_acc.mean()),
-                 "accepted_steps_max": int(n_acc.max()), "failed_worlds": int((status != 0).sum()),
-                 "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)},
     }
     print(json.dumps(out), flush=True)
 

@@ -54,7 +54,12 @@ enum {
   DMX_W_DT_UNDERFLOW = 2,   /* step size fell below 1e-12 max(1, |t|) */
   DMX_W_NONFINITE = 4,      /* non-finite state or singular mass matrix */
   DMX_W_SOLVER_MAXIT = 8,   /* contact Newton solve hit its iteration cap */
-  DMX_W_TAPE_OVERFLOW = 32  /* more accepted steps than the tape holds */
+  DMX_W_CONTACT_OVERFLOW = 16, /* more than 256 contacts at some evaluation of a stack world; the
+                                  first 256 in pair order were used (not fatal: the world goes on
+                                  and its gradient is computed) */
+  DMX_W_TAPE_OVERFLOW = 32, /* more accepted steps than the tape holds */
+  DMX_W_CONTACT_GRAPH = 64  /* stack world: cubes that are not neighbours in the model's body order
+                               touched (the solver takes block-tridiagonal Hessians); the world stops */
 };
 
 enum { DMX_JOINT_FREE = 0, DMX_JOINT_HINGE = 1, DMX_JOINT_SLIDE = 2 };
@@ -195,6 +200,51 @@ dmx_status dmx_rollout(const dmx_model* model, int32_t n_worlds, int32_t n_inter
                        const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
                        int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
                        void* stream);
+
+/* ------------------------------------------------------------ uneven batches
+ * A batch of worlds of different models in one persistent launch (App. D,
+ * "Parallelizing DiffMJX simulations": every world takes its own steps, so
+ * worlds of different size and step count share a launch; a device work
+ * queue hands out worlds, the ones with the most bodies first).  Every model
+ * of the batch must be a stack of free cubes (k = 1..32 cubes, as built by a
+ * model description with k bodies, one free joint and one box geom each, a
+ * world plane, and every plane-cube and cube-cube pair with equal parameters:
+ * the primitive-vs-primitive contacts of Sec. 2.1 with the box-box contact
+ * reading of the separating-axis test and face clipping).  State, control and
+ * gradient arrays are packed world after world: world w's state starts at
+ * x_off[w] (13 k_w doubles: q = 7 k_w then v = 6 k_w) and its controls at
+ * u_off[w] ([n_intervals][nu_w]); dmx_batch_layout gives the offsets. */
+typedef struct {
+  int32_t n_worlds;
+  const dmx_model* const* models;  /* host array [n_worlds]: the model of each world */
+  int32_t n_intervals;             /* control intervals (all worlds) */
+  double interval_dt;              /* seconds per interval */
+} dmx_batch;
+
+/* Offsets (host arrays [n_worlds], may be NULL) and totals of the packed
+ * state and control arrays of a batch. */
+dmx_status dmx_batch_layout(const dmx_batch* batch, int64_t* x_off, int64_t* u_off, int64_t* nx_total,
+                            int64_t* nu_total);
+
+/* Forward rollout of an uneven batch (the calls and conventions of
+ * dmx_rollout, with packed arrays): x0, x_out packed states, u packed
+ * controls (NULL if no model has controls), world_status, n_accepted,
+ * n_rejected [n_worlds].  With tape != NULL the tape holds every world's
+ * accepted steps for dmx_rollout_vjp, whose x_out_bar, x0_bar and u_bar are
+ * then packed the same way; a tape is reused in place when *tape is a tape of
+ * the same models in the same order.  DMX_ERR_UNSUPPORTED if a model is not a
+ * stack of cubes; forced steps, step logs and counters as for dmx_rollout;
+ * ragged horizons (world_intervals) are not taken. */
+dmx_status dmx_rollout_batch(const dmx_batch* batch, const dmx_solver_opts* opts, const double* x0,
+                             const double* u, double* x_out, int32_t* world_status, int32_t* n_accepted,
+                             int32_t* n_rejected, dmx_tape** tape, void* stream);
+
+/* Per-world layout of a tape's records (host arrays [n_worlds]): world w's
+ * records start at records + t_off[w] and are rec[w] doubles long (t_n, h_n,
+ * interval, y_n, then the stage accelerations a_1..a_6 unless the tape holds
+ * checkpoints only); dmx_tape_info's steps_per_world is each world's
+ * capacity. */
+dmx_status dmx_tape_layout(const dmx_tape* tape, int64_t* t_off, int32_t* rec);
 
 /* Autotuner: times the forward rollout of this batch (device x0, u) with
  * every team size (lanes per world) compiled for the model, on the stream,

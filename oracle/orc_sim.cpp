@@ -44,6 +44,7 @@ struct Model {
   std::vector<double> pmu, psolref, psolimp, pcfd;
   std::vector<int> ctrl;
   V3<double> grav;
+  std::vector<std::vector<int>> bdofs;  // dofs that move body b (its joints and its ancestors'), ascending
 };
 
 // Solid primitive of uniform density: mass and the principal inertia about its
@@ -203,9 +204,10 @@ static void mass_bias(const Model& m, const Kin<S>& k, S* M, S* c) {
     point_jac(m, k, b, k.xpos[b], Jp.data(), Jr.data());
     M3<S> Iw = matmul(matmul(k.xmat[b], liftm<S>(m.biner[b])), transpose(k.xmat[b]));
     double mb = m.bmass[b];
-    // M += m Jp^T Jp + Jr^T Iw Jr
-    for (int i = 0; i < nv; ++i)
-      for (int j = 0; j < nv; ++j) {
+    // M += m Jp^T Jp + Jr^T Iw Jr (the body's Jacobians vanish outside the
+    // dofs that move it)
+    for (int i : m.bdofs[b])
+      for (int j : m.bdofs[b]) {
         S s = S(0.0);
         for (int r = 0; r < 3; ++r) s += Jp[r * nv + i] * Jp[r * nv + j] * mb;
         for (int r = 0; r < 3; ++r)
@@ -214,7 +216,7 @@ static void mass_bias(const Model& m, const Kin<S>& k, S* M, S* c) {
       }
     V3<S> f = scale(sub(k.acc[b], lift<S>(m.grav)), mb);
     V3<S> tq = add(matvec(Iw, k.alp[b]), cross(k.w[b], matvec(Iw, k.w[b])));
-    for (int i = 0; i < nv; ++i)
+    for (int i : m.bdofs[b])
       for (int r = 0; r < 3; ++r) c[i] += Jp[r * nv + i] * f.x[r] + Jr[r * nv + i] * tq.x[r];
   }
 }
@@ -481,7 +483,8 @@ static void collide(const Model& m, const Kin<S>& k, std::vector<Contact<S>>& ou
 // ------------------------------------------------------------------ constraint rows
 template <class S>
 struct Row {
-  std::vector<S> J;  // nv
+  std::vector<S> J;   // nv
+  std::vector<int> nz;  // dofs of the contact's two bodies (J vanishes elsewhere)
   S aref, D;
 };
 
@@ -534,6 +537,11 @@ static void make_rows(const Model& m, const Kin<S>& k, const std::vector<Contact
     if (n_on == kMaxContacts) { if (overflow) *overflow = true; continue; }
     ++n_on;
     int b1 = m.gbody[m.pg1[p]], b2 = m.gbody[m.pg2[p]];
+    std::vector<int> nzd;
+    if (b1 >= 0) nzd = m.bdofs[b1];
+    if (b2 >= 0) nzd.insert(nzd.end(), m.bdofs[b2].begin(), m.bdofs[b2].end());
+    std::sort(nzd.begin(), nzd.end());
+    nzd.erase(std::unique(nzd.begin(), nzd.end()), nzd.end());
     for (int i = 0; i < 3 * nv; ++i) { J1[i] = S(0.0); J2[i] = S(0.0); }
     if (b1 >= 0) point_jac(m, k, b1, ct.pos, J1.data(), (S*)nullptr);
     if (b2 >= 0) point_jac(m, k, b2, ct.pos, J2.data(), (S*)nullptr);
@@ -558,6 +566,7 @@ static void make_rows(const Model& m, const Kin<S>& k, const std::vector<Contact
     for (int e = 0; e < 4; ++e) {
       Row<S> row;
       row.J.resize(nv);
+      row.nz = nzd;
       const std::vector<S>& Jt = (e < 2) ? Jt1 : Jt2;
       double sg = (e % 2 == 0) ? mu : -mu;
       S jv = S(0.0);
@@ -666,9 +675,9 @@ static NewtonOut newton(const std::vector<double>& M, const std::vector<double>&
       double jx = 0.0;
       for (int i = 0; i < nv; ++i) jx += rows[e].J[i] * o.x[i];
       double se = jx - rows[e].aref;
-      for (int i = 0; i < nv; ++i) {
+      for (int i : rows[e].nz) {
         g[i] += rows[e].D * se * rows[e].J[i];
-        for (int j = 0; j < nv; ++j) H[i * nv + j] += rows[e].D * rows[e].J[i] * rows[e].J[j];
+        for (int j : rows[e].nz) H[i * nv + j] += rows[e].D * rows[e].J[i] * rows[e].J[j];
       }
     }
     if (!cholesky(H, nv)) { o.ok = false; return o; }
@@ -753,6 +762,7 @@ static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, i
   std::vector<Row<double>> rd(rows.size());
   for (size_t e = 0; e < rows.size(); ++e) {
     rd[e].J.resize(nv);
+    rd[e].nz = rows[e].nz;
     for (int i = 0; i < nv; ++i) rd[e].J[i] = val(rows[e].J[i]);
     rd[e].aref = val(rows[e].aref); rd[e].D = val(rows[e].D);
   }
@@ -775,9 +785,9 @@ static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, i
   std::vector<S> H = M, b = f0;
   for (size_t e = 0; e < rows.size(); ++e) {
     if (!no.active[e]) continue;
-    for (int i = 0; i < nv; ++i) {
+    for (int i : rows[e].nz) {
       b[i] += rows[e].D * rows[e].aref * rows[e].J[i];
-      for (int j = 0; j < nv; ++j) H[i * nv + j] += rows[e].D * rows[e].J[i] * rows[e].J[j];
+      for (int j : rows[e].nz) H[i * nv + j] += rows[e].D * rows[e].J[i] * rows[e].J[j];
     }
   }
   if (!cholesky(H, nv)) st->status |= ORC_NONFINITE;
@@ -1053,6 +1063,15 @@ extern "C" void* orc_model_new(const orc_model_def* d) {
     da += d->jnt_type[j] == J_FREE ? 6 : 1;
   }
   m->nq = qa; m->nv = da;
+  m->bdofs.assign(m->nb, {});
+  for (int b = 0; b < m->nb; ++b) {
+    for (int c = b; c >= 0; c = m->bparent[c])
+      for (int j = m->bjnt0[c]; j < m->bjnt0[c] + m->bjntn[c]; ++j) {
+        const int n = m->jtype[j] == J_FREE ? 6 : 1;
+        for (int i = 0; i < n; ++i) m->bdofs[b].push_back(m->jdadr[j] + i);
+      }
+    std::sort(m->bdofs[b].begin(), m->bdofs[b].end());
+  }
   for (int g = 0; g < m->ng; ++g) {
     m->gbody.push_back(d->geom_body[g]); m->gtype.push_back(d->geom_type[g]);
     m->gsize.push_back(v3<double>(d->geom_size[3 * g], d->geom_size[3 * g + 1], d->geom_size[3 * g + 2]));

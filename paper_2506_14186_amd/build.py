@@ -11,7 +11,7 @@ LIB = os.path.join(HERE, "libdmx.so")
 # translation units, compiled in parallel and linked into one library: the
 # host side (C ABI, dispatch, tapes, server) and one unit per kernel family
 SOURCES = [os.path.join(HERE, "csrc", n) for n in ("dmx_lib.hip", "kern_free_small.hip", "kern_free.hip",
-                                                    "kern_free_wide.hip", "kern_tree.hip")]
+                                                    "kern_free_wide.hip", "kern_tree.hip", "kern_stack.hip")]
 OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,7 +25,8 @@ FLAGS = [
 ]
 
 
-KERNEL_SOURCES = ["dmx_common.hpp", "dmx_free.hpp", "dmx_tree.hpp", "dmx_rk.hpp"]
+KERNEL_SOURCES = ["dmx_common.hpp", "dmx_free.hpp", "dmx_tree.hpp", "dmx_rk.hpp", "dmx_geom.hpp", "dmx_stack.hpp",
+                  "dmx_stack_rk.hpp", "dmx_stack_adj.hpp"]
 
 
 def kernel_digest():

@@ -15,6 +15,7 @@
 #include "dmx_tree.hpp"
 #include "dmx_launch.hpp"
 #include "dmx_server.hpp"
+#include "dmx_stack_host.hpp"
 
 using namespace dmx_host;
 
@@ -102,16 +103,21 @@ int bucket(int n) {
   return b;
 }
 
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
 }  // namespace
 
 // ---------------------------------------------------------------- objects
 struct dmx_model {
-  int kind = 0;  // 0: single free body, 1: hinge/slide tree; plane contacts
+  int kind = 0;  // 0: single free body, 1: hinge/slide tree; plane contacts; 2: stack of free cubes
   int nq = 0, nv = 0, nu = 0, nc = 0, ncb = 0, nb = 1;
   dmx::FreeModel host{};
   dmx::TreeModel tree{};
   void* dev = nullptr;
   std::atomic<int> tuned_team{0};  // team size chosen by dmx_autotune (0: none)
+  bool stack_ok = false;           // the stack kernels cover the model (a stack of k >= 1 cubes)
+  dmx::StackModel stk{};
+  void* stk_dev = nullptr;
 };
 
 struct dmx_tape {
@@ -132,6 +138,15 @@ struct dmx_tape {
   int* tables = nullptr;  // [2][W]: per-world intervals and processing order, copied at each rollout
   int* queue = nullptr;   // [2] work counters of the forward and reverse launches
   bool use_queue = false;
+  // stack tapes (ragged worlds): per-world tables on the device and the
+  // arguments of the forward launch, reused by the reverse sweep
+  bool stack = false;
+  std::vector<const dmx_model*> models;  // the worlds' models (host)
+  std::vector<long long> t_off_h;        // per-world tape offsets (host copy)
+  std::vector<int> rec_h;                // per-world record lengths (host copy)
+  void* stk_tables = nullptr;            // device: models, x_off, u_off, t_off, cap, order
+  size_t stk_tables_bytes = 0;
+  dmx::StackArgs sa{};
 };
 
 extern "C" {
@@ -149,12 +164,130 @@ void dmx_default_opts(dmx_solver_opts* o) {
 
 static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out);
 
+// A stack of k free cubes on a plane, in the layout the stack kernels take:
+// k bodies (parent -1), each with one free joint and one box geom at its
+// origin; a world plane; the pairs (plane, cube b) for b in order, then
+// (cube i, cube j) for i < j in lexicographic order, all with the same
+// parameters; equal cubes with principal axes along the body axes.
+static bool make_stack_model(const dmx_model_desc* d, dmx::StackModel* st, std::string* why) {
+  auto no = [&](const char* w) { *why = w; return false; };
+  const int k = d->nbody;
+  if (k < 1 || k > dmx::kStackBodies) return no("stacks take 1..32 cubes");
+  if (d->njnt != k) return no("one free joint per cube");
+  for (int b = 0; b < k; ++b) {
+    if (d->body_parent[b] != -1 || d->jnt_body[b] != b || d->jnt_type[b] != DMX_JOINT_FREE) return no("one free joint per cube");
+    if (d->body_iner_type[b] != DMX_GEOM_BOX) return no("cube inertia");
+    const double* q = &d->body_iner_quat[4 * b];
+    if (q[0] != 1.0 || q[1] != 0.0 || q[2] != 0.0 || q[3] != 0.0) return no("inertia axes along the body axes");
+    for (int i = 0; i < 3; ++i)
+      if (d->body_iner_size[3 * b + i] != d->body_iner_size[i]) return no("equal cubes");
+    if (d->body_mass[b] != d->body_mass[0]) return no("equal cubes");
+  }
+  if (d->ngeom != k + 1) return no("one plane and one box per cube");
+  int plane = -1;
+  std::vector<int> box_of(k, -1);
+  for (int g = 0; g < d->ngeom; ++g) {
+    if (d->geom_type[g] == DMX_GEOM_PLANE && d->geom_body[g] == -1) { plane = g; continue; }
+    const int b = d->geom_body[g];
+    if (d->geom_type[g] != DMX_GEOM_BOX || b < 0 || b >= k || box_of[b] >= 0) return no("one box per cube");
+    for (int i = 0; i < 3; ++i)
+      if (d->geom_pos[3 * g + i] != 0.0 || d->geom_size[3 * g + i] != d->body_iner_size[i]) return no("box geom at the cube");
+    const double* q = &d->geom_quat[4 * g];
+    if (q[0] != 1.0 || q[1] != 0.0 || q[2] != 0.0 || q[3] != 0.0) return no("box geom at the cube");
+    box_of[b] = g;
+  }
+  if (plane < 0) return no("a world plane");
+  if (d->npair != k + k * (k - 1) / 2) return no("every cube-plane and cube-cube pair");
+  int p = 0;
+  for (int b = 0; b < k; ++b, ++p)
+    if (d->pair_g1[p] != plane || d->pair_g2[p] != box_of[b]) return no("pairs: plane-cube in cube order first");
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j, ++p)
+      if (d->pair_g1[p] != box_of[i] || d->pair_g2[p] != box_of[j]) return no("pairs: then cube pairs (i, j), i < j");
+  for (int q = 1; q < d->npair; ++q) {
+    if (d->pair_mu[q] != d->pair_mu[0]) return no("equal pair parameters");
+    for (int i = 0; i < 2; ++i) if (d->pair_solref[2 * q + i] != d->pair_solref[i]) return no("equal pair parameters");
+    for (int i = 0; i < 5; ++i)
+      if (d->pair_solimp[5 * q + i] != d->pair_solimp[i] || d->pair_cfd[5 * q + i] != d->pair_cfd[i])
+        return no("equal pair parameters");
+  }
+  if (d->nu < 0 || d->nu > 6) return no("at most 6 controls");
+  dmx::StackModel s{};
+  s.k = k;
+  s.nu = d->nu;
+  for (int i = 0; i < d->nu; ++i) {
+    if (d->ctrl_dof[i] < 0 || d->ctrl_dof[i] >= 6 * k) return no("bad ctrl dof");
+    s.ctrl[i] = d->ctrl_dof[i];
+  }
+  double mass, Ip[3];
+  if (!solid_inertia(DMX_GEOM_BOX, d->body_iner_size, d->body_mass[0], &mass, Ip)) return no("inertia");
+  s.mass = mass;
+  s.imass = 1.0 / mass;
+  double hn = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    s.I[i] = Ip[i];
+    s.Iinv[i] = 1.0 / Ip[i];
+    s.h[i] = d->body_iner_size[i];
+    s.grav[i] = d->gravity[i];
+    hn += s.h[i] * s.h[i];
+  }
+  s.rbound = std::sqrt(hn);
+  double Rp[9];
+  quat_to_mat(&d->geom_quat[4 * plane], Rp);
+  for (int i = 0; i < 3; ++i) { s.p0[i] = d->geom_pos[3 * plane + i]; s.pn[i] = Rp[i * 3 + 2]; }
+  dmx::PairF pr{};
+  for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[i]; pr.cf[i] = d->pair_cfd[i]; }
+  spline_scales(pr);
+  const double tc = d->pair_solref[0], dr = d->pair_solref[1], dw = pr.si[1];
+  if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0))
+    return no("solref/solimp/cfd out of range");
+  for (int i = 0; i < 5; ++i) { s.si[i] = pr.si[i]; s.cf[i] = pr.cf[i]; }
+  for (int i = 0; i < 4; ++i) s.ssc[i] = pr.ssc[i];
+  s.iwid[0] = pr.iwid[0];
+  s.iwid[1] = pr.iwid[1];
+  s.mu = d->pair_mu[0];
+  s.bcoef = 2.0 / (dw * tc);
+  s.kscale = 1.0 / (dw * dw * tc * tc * dr * dr);
+  // A = (1 + mu^2)(w_1 + w_2), w = 1/m for a free body, 0 for the world
+  s.ahat_plane = (1.0 + s.mu * s.mu) * s.imass;
+  s.ahat_box = (1.0 + s.mu * s.mu) * 2.0 * s.imass;
+  *st = s;
+  return true;
+}
+
+static dmx_status upload_stack(dmx_model* m) {
+  hipError_t e = hipMalloc(&m->stk_dev, sizeof(dmx::StackModel));
+  if (e == hipSuccess) e = hipMemcpy(m->stk_dev, &m->stk, sizeof(dmx::StackModel), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(DMX_ERR_HIP, std::string("stack model upload: ") + hipGetErrorString(e));
+  return DMX_OK;
+}
+
 dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
   if (!d || !out) return fail(DMX_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   bool any_free = false;
   for (int j = 0; j < d->njnt; ++j) any_free = any_free || d->jnt_type[j] == DMX_JOINT_FREE;
   if (!any_free) return create_tree_model(d, out);
+  dmx::StackModel stk{};
+  std::string why;
+  const bool stack_ok = make_stack_model(d, &stk, &why);
+  if (d->nbody > 1) {
+    if (!stack_ok)
+      return fail(DMX_ERR_UNSUPPORTED, "several free bodies are supported as a stack of cubes: " + why);
+    dmx_model* m = new dmx_model();
+    m->kind = 2;
+    m->nb = stk.k;
+    m->nq = 7 * stk.k;
+    m->nv = 6 * stk.k;
+    m->nu = d->nu;
+    m->nc = dmx::kStackContacts;
+    m->stack_ok = true;
+    m->stk = stk;
+    const dmx_status r = upload_stack(m);
+    if (r != DMX_OK) { delete m; return r; }
+    *out = m;
+    return DMX_OK;
+  }
   if (d->nbody != 1 || d->njnt != 1 || d->jnt_type[0] != DMX_JOINT_FREE || d->body_parent[0] != -1)
     return fail(DMX_ERR_UNSUPPORTED, "free joints are supported as the single joint of a single body");
   if (d->npair > dmx::kMaxPairs) return fail(DMX_ERR_UNSUPPORTED, "too many pairs");
@@ -252,6 +385,12 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     if (m->dev) (void)hipFree(m->dev);
     delete m;
     return fail(DMX_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+  }
+  if (stack_ok) {  // a one-cube stack: also runs in batches of stacks
+    m->stack_ok = true;
+    m->stk = stk;
+    const dmx_status r = upload_stack(m);
+    if (r != DMX_OK) { dmx_model_destroy(m); return r; }
   }
   *out = m;
   return DMX_OK;
@@ -493,6 +632,7 @@ dmx_status dmx_model_info(const dmx_model* m, int32_t* nq, int32_t* nv, int32_t*
 void dmx_model_destroy(dmx_model* m) {
   if (!m) return;
   if (m->dev) (void)hipFree(m->dev);
+  if (m->stk_dev) (void)hipFree(m->stk_dev);
   delete m;
 }
 
@@ -539,10 +679,280 @@ static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
   return s;
 }
 
+// Per-world layout of a batch of stack worlds: state offsets (13 k doubles
+// per world), control offsets (n_int nu), tape offsets (cap records of 3 +
+// 13 k (+ 36 k with stages) doubles), and the processing order (most cubes
+// first, index order among equals: the longest worlds start first).
+struct StackLayout {
+  std::vector<dmx::StackModel> models;
+  std::vector<long long> x_off, u_off, t_off;
+  std::vector<int> cap, order, rec;
+  long long nx = 0, nu = 0, tape_doubles = 0;
+};
+
+static void stack_layout(const std::vector<const dmx_model*>& ms, int n_int, long long cap, int stages, StackLayout* L) {
+  const int W = (int)ms.size();
+  L->models.resize(W); L->x_off.resize(W); L->u_off.resize(W); L->t_off.resize(W);
+  L->cap.assign(W, (int)cap); L->order.resize(W); L->rec.resize(W);
+  long long xo = 0, uo = 0, to = 0;
+  for (int w = 0; w < W; ++w) {
+    const dmx::StackModel& sm = ms[w]->stk;
+    L->models[w] = sm;
+    L->x_off[w] = xo; L->u_off[w] = uo; L->t_off[w] = to;
+    L->rec[w] = 3 + 13 * sm.k + (stages ? 36 * sm.k : 0);
+    xo += 13 * sm.k;
+    uo += (long long)n_int * sm.nu;
+    to += cap * L->rec[w];
+    L->order[w] = w;
+  }
+  std::stable_sort(L->order.begin(), L->order.end(), [&](int a, int b) { return ms[a]->stk.k > ms[b]->stk.k; });
+  L->nx = xo; L->nu = uo; L->tape_doubles = to;
+}
+
+// device tables of a stack batch: models, x_off, u_off, t_off, cap, order, queue[2]
+static size_t stack_tables_bytes(int W) {
+  return align256(sizeof(dmx::StackModel) * (size_t)W) + 3 * align256(sizeof(long long) * (size_t)W) +
+         2 * align256(sizeof(int) * (size_t)W) + 256;
+}
+static dmx_status stack_tables_upload(const StackLayout& L, void* dev, hipStream_t s, dmx::StackArgs* a) {
+  const int W = (int)L.models.size();
+  std::vector<char> host(stack_tables_bytes(W), 0);
+  size_t o = 0;
+  auto put = [&](const void* src, size_t n) { size_t at = o; std::memcpy(host.data() + o, src, n); o += align256(n); return at; };
+  const size_t om = put(L.models.data(), sizeof(dmx::StackModel) * W);
+  const size_t ox = put(L.x_off.data(), sizeof(long long) * W);
+  const size_t ou = put(L.u_off.data(), sizeof(long long) * W);
+  const size_t ot = put(L.t_off.data(), sizeof(long long) * W);
+  const size_t oc = put(L.cap.data(), sizeof(int) * W);
+  const size_t oo = put(L.order.data(), sizeof(int) * W);
+  const size_t oq = o;
+  // the host buffer must outlive the copy: copy in stream order, then wait
+  HIP_TRY(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  char* D = (char*)dev;
+  a->models = (const dmx::StackModel*)(D + om);
+  a->x_off = (const long long*)(D + ox);
+  a->u_off = (const long long*)(D + ou);
+  a->t_off = (const long long*)(D + ot);
+  a->cap_w = (const int*)(D + oc);
+  a->order = (const int*)(D + oo);
+  a->queue = (int*)(D + oq);
+  return DMX_OK;
+}
+
+// Stack batches.  A batch of one model (uniform) needs no per-world tables:
+// the kernels take the model and strides; otherwise the tables are uploaded
+// (owned by the tape, or temporary).  With scratch_queue (no tape, uniform
+// batches only) nothing is allocated: the work-queue counter lives there.
+static dmx_status stack_rollout(const std::vector<const dmx_model*>& ms, int n_int, double dt,
+                                const dmx_solver_opts& o, const double* x0, const double* u, double* x_out,
+                                int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
+                                hipStream_t s, int* scratch_queue = nullptr) {
+  const int W = (int)ms.size();
+  bool uniform = true;
+  for (const dmx_model* m : ms) uniform = uniform && m == ms[0];
+  if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
+  if (o.world_intervals) return fail(DMX_ERR_UNSUPPORTED, "ragged horizons are not taken by stack batches");
+  bool any_ctrl = false;
+  for (const dmx_model* m : ms) any_ctrl = any_ctrl || m->nu > 0;
+  if (any_ctrl && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  dmx_tape* reuse = tape ? *tape : nullptr;
+  if (reuse) {
+    const long long want = o.tape_steps > 0 ? o.tape_steps : reuse->cap;
+    if (!reuse->stack || reuse->models != ms || reuse->cap < want)
+      return fail(DMX_ERR_INVALID_ARG, "tape to reuse does not match the batch's models/capacity");
+  }
+  dmx::StackArgs a{};
+  a.W = W; a.n_int = n_int; a.dt = dt; a.x0 = x0; a.u = u; a.xout = x_out;
+  a.status = world_status; a.n_acc = n_accepted; a.n_rej = n_rejected;
+  a.counters = (long long*)o.fwd_counters;
+  a.forced = o.forced; a.forced_n = o.forced_n; a.forced_cap = o.forced_cap;
+  a.steplog = o.steplog; a.log_n = o.log_n; a.log_cap = o.log_cap;
+  a.o = to_solver(o);
+  const bool use_queue = o.launch_mode == 0 && o.work_queue != -1;
+  if (tape) {
+    dmx_tape* tp = reuse;
+    if (!tp) {
+      tp = new dmx_tape();
+      tp->stack = true;
+      tp->models = ms;
+      tp->W = W; tp->n_int = n_int; tp->dt = dt; tp->u = u;
+      tp->cap = o.tape_steps > 0 ? o.tape_steps : 4096;
+      StackLayout L0;
+      stack_layout(ms, n_int, tp->cap, 1, &L0);
+      bool stages = o.tape_stages != 0;
+      if (o.tape_stages < 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+          stages = (double)L0.tape_doubles * sizeof(double) <= 0.5 * (double)free_b;
+      }
+      StackLayout L;
+      stack_layout(ms, n_int, tp->cap, stages ? 1 : 0, &L);
+      tp->rec = L.rec[0];  // record length of world 0 (of every world when the models are equal)
+      tp->t_off_h = L.t_off;
+      tp->rec_h = L.rec;
+      tp->stk_tables_bytes = stack_tables_bytes(W);
+      hipError_t e = hipMalloc(&tp->records, sizeof(double) * (size_t)std::max(L.tape_doubles, 1ll));
+      if (e == hipSuccess) e = hipMalloc(&tp->n_acc, sizeof(int) * W);
+      if (e == hipSuccess) e = hipMalloc(&tp->status, sizeof(int) * W);
+      if (e == hipSuccess) e = hipMalloc(&tp->stk_tables, tp->stk_tables_bytes);
+      if (e != hipSuccess) {
+        dmx_tape_destroy(tp);
+        return fail(DMX_ERR_OUT_OF_MEMORY, std::string("tape allocation: ") + hipGetErrorString(e));
+      }
+      if (uniform) {
+        tp->sa.uniform = 1;
+        tp->sa.models = (const dmx::StackModel*)ms[0]->stk_dev;
+        tp->sa.x_stride = 13 * ms[0]->stk.k;
+        tp->sa.u_stride = (long long)n_int * ms[0]->stk.nu;
+        tp->sa.t_stride = tp->cap * L.rec[0];
+        tp->sa.cap_uniform = (int)tp->cap;
+        tp->sa.queue = (int*)((char*)tp->stk_tables + (tp->stk_tables_bytes - 256));
+      } else {
+        const dmx_status r = stack_tables_upload(L, tp->stk_tables, s, &tp->sa);
+        if (r != DMX_OK) { dmx_tape_destroy(tp); return r; }
+      }
+      tp->sa.stages = stages ? 1 : 0;
+      tp->model = ms[0];
+    }
+    tp->n_int = n_int; tp->dt = dt; tp->u = u;
+    tp->plain = o.launch_mode;
+    tp->adj_counters = o.adj_counters;
+    tp->use_queue = use_queue;
+    a.models = tp->sa.models; a.x_off = tp->sa.x_off; a.u_off = tp->sa.u_off; a.t_off = tp->sa.t_off;
+    a.cap_w = tp->sa.cap_w; a.order = tp->sa.order; a.stages = tp->sa.stages;
+    a.uniform = tp->sa.uniform; a.x_stride = tp->sa.x_stride; a.u_stride = tp->sa.u_stride;
+    a.t_stride = tp->sa.t_stride; a.cap_uniform = tp->sa.cap_uniform;
+    a.queue = use_queue ? tp->sa.queue : nullptr;
+    a.tape = tp->records; a.n_acc = tp->n_acc; a.status = tp->status;
+    dmx_host::stack_fwd(a, s, o.launch_mode);
+    HIP_TRY(hipGetLastError());
+    tp->sa = a;
+    tp->sa.queue = use_queue ? (int*)((char*)tp->stk_tables + (tp->stk_tables_bytes - 256)) : nullptr;
+    HIP_TRY(hipMemcpyAsync(world_status, tp->status, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+    if (n_accepted) HIP_TRY(hipMemcpyAsync(n_accepted, tp->n_acc, sizeof(int) * W, hipMemcpyDeviceToDevice, s));
+    *tape = tp;
+    return DMX_OK;
+  }
+  if (uniform) {
+    a.uniform = 1;
+    a.models = (const dmx::StackModel*)ms[0]->stk_dev;
+    a.x_stride = 13 * ms[0]->stk.k;
+    a.u_stride = (long long)n_int * ms[0]->stk.nu;
+    int* q = scratch_queue;
+    if (use_queue && !q) HIP_TRY(hipMallocAsync((void**)&q, sizeof(int), s));
+    a.queue = use_queue ? q : nullptr;
+    dmx_host::stack_fwd(a, s, o.launch_mode);
+    HIP_TRY(hipGetLastError());
+    if (use_queue && !scratch_queue) HIP_TRY(hipFreeAsync(q, s));
+    return DMX_OK;
+  }
+  if (scratch_queue) return fail(DMX_ERR_INVALID_ARG, "allocation-free rollouts take one model");
+  StackLayout L;
+  stack_layout(ms, n_int, 0, 0, &L);
+  void* tbl = nullptr;
+  HIP_TRY(hipMallocAsync(&tbl, stack_tables_bytes(W), s));
+  const dmx_status r = stack_tables_upload(L, tbl, s, &a);
+  if (r != DMX_OK) { (void)hipFreeAsync(tbl, s); return r; }
+  if (!use_queue) a.queue = nullptr;
+  a.cap_w = nullptr;
+  dmx_host::stack_fwd(a, s, o.launch_mode);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipFreeAsync(tbl, s));
+  return DMX_OK;
+}
+
+static dmx_status check_opts(const dmx_solver_opts& o) {
+  if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0 || o.h_levels < 0)
+    return fail(DMX_ERR_INVALID_ARG, "bad solver options");
+  if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
+  if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
+  if (o.work_queue < -1 || o.work_queue > 1) return fail(DMX_ERR_INVALID_ARG, "bad work_queue");
+  return DMX_OK;
+}
+
+dmx_status dmx_batch_layout(const dmx_batch* b, int64_t* x_off, int64_t* u_off, int64_t* nx_total,
+                            int64_t* nu_total) {
+  if (!b || (b->n_worlds > 0 && !b->models)) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  int64_t xo = 0, uo = 0;
+  for (int w = 0; w < b->n_worlds; ++w) {
+    const dmx_model* m = b->models[w];
+    if (!m) return fail(DMX_ERR_INVALID_ARG, "null model in batch");
+    if (x_off) x_off[w] = xo;
+    if (u_off) u_off[w] = uo;
+    xo += m->nq + m->nv;
+    uo += (int64_t)b->n_intervals * m->nu;
+  }
+  if (nx_total) *nx_total = xo;
+  if (nu_total) *nu_total = uo;
+  return DMX_OK;
+}
+
+dmx_status dmx_rollout_batch(const dmx_batch* b, const dmx_solver_opts* opts, const double* x0, const double* u,
+                             double* x_out, int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected,
+                             dmx_tape** tape, void* stream) {
+  if (!b || (b->n_worlds > 0 && !b->models)) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (b->n_worlds < 0 || b->n_intervals <= 0 || !(b->interval_dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
+  dmx_solver_opts o;
+  if (opts) o = *opts; else dmx_default_opts(&o);
+  const dmx_status oc = check_opts(o);
+  if (oc != DMX_OK) return oc;
+  if (b->n_worlds == 0) { if (tape && !*tape) *tape = nullptr; return DMX_OK; }
+  if (!x0 || !x_out || !world_status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  std::vector<const dmx_model*> ms(b->models, b->models + b->n_worlds);
+  for (const dmx_model* m : ms) {
+    if (!m) return fail(DMX_ERR_INVALID_ARG, "null model in batch");
+    if (!m->stack_ok) return fail(DMX_ERR_UNSUPPORTED, "batches of mixed models take stacks of cubes (k >= 1)");
+  }
+  return stack_rollout(ms, b->n_intervals, b->interval_dt, o, x0, u, x_out, world_status, n_accepted, n_rejected,
+                       tape, (hipStream_t)stream);
+}
+
+dmx_status dmx_tape_layout(const dmx_tape* tp, int64_t* t_off, int32_t* rec) {
+  if (!tp) return fail(DMX_ERR_INVALID_ARG, "null tape");
+  for (int w = 0; w < tp->W; ++w) {
+    if (tp->stack) {
+      if (t_off) t_off[w] = tp->t_off_h[w];
+      if (rec) rec[w] = tp->rec_h[w];
+    } else {
+      if (t_off) t_off[w] = (int64_t)w * tp->cap * tp->rec;
+      if (rec) rec[w] = tp->rec;
+    }
+  }
+  return DMX_OK;
+}
+
+static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, double dt,
+                               const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
+                               int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
+                               void* stream, int* scratch_queue);
+
 dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, const dmx_solver_opts* opts,
                        const double* x0, const double* u, double* x_out, int32_t* world_status,
                        int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape, void* stream) {
+  return rollout_impl(m, W, n_int, dt, opts, x0, u, x_out, world_status, n_accepted, n_rejected, tape, stream,
+                      nullptr);
+}
+
+}  // extern "C"
+
+static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, double dt,
+                               const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
+                               int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
+                               void* stream, int* scratch_queue) {
   if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
+  if (m->kind == 2) {
+    if (W < 0 || n_int <= 0 || !(dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
+    dmx_solver_opts o;
+    if (opts) o = *opts; else dmx_default_opts(&o);
+    const dmx_status oc = check_opts(o);
+    if (oc != DMX_OK) return oc;
+    if (W == 0) { if (tape && !*tape) *tape = nullptr; return DMX_OK; }
+    if (!x0 || !x_out || !world_status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+    std::vector<const dmx_model*> ms((size_t)W, m);
+    return stack_rollout(ms, n_int, dt, o, x0, u, x_out, world_status, n_accepted, n_rejected, tape,
+                         (hipStream_t)stream, scratch_queue);
+  }
   if (W < 0 || n_int <= 0 || !(dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
   if (W > 0 && (!x0 || !x_out || !world_status)) return fail(DMX_ERR_INVALID_ARG, "null argument");
   if (W > 0 && m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
@@ -636,8 +1046,12 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
     tp->use_queue = use_queue;
     if (use_queue) a.g.queue = tp->queue;
   } else if (use_queue) {
-    HIP_TRY(hipMallocAsync((void**)&tmp_queue, sizeof(int), s));
-    a.g.queue = tmp_queue;
+    if (scratch_queue) {
+      a.g.queue = scratch_queue;
+    } else {
+      HIP_TRY(hipMallocAsync((void**)&tmp_queue, sizeof(int), s));
+      a.g.queue = tmp_queue;
+    }
   }
   k->fwd(m->dev, a, s, o.launch_mode);
   HIP_TRY(hipGetLastError());
@@ -650,12 +1064,22 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
   return DMX_OK;
 }
 
+extern "C" {
+
 dmx_status dmx_accel(const dmx_model* m, int32_t n, const double* x, const double* tau, int32_t cfd, double* acc,
                      int32_t* status, void* stream) {
   if (!m) return fail(DMX_ERR_INVALID_ARG, "null model");
   if (n < 0) return fail(DMX_ERR_INVALID_ARG, "bad count");
   if (n == 0) return DMX_OK;
   if (!x || !acc || !status) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (m->kind == 2) {
+    dmx_solver_opts oo;
+    dmx_default_opts(&oo);
+    dmx_host::stack_accel((const dmx::StackModel*)m->stk_dev, n, x, tau, cfd, to_solver(oo), acc, status,
+                          (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return DMX_OK;
+  }
   const KernelEntry* k = find_kernel(m, 0);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
   dmx_solver_opts oo;
@@ -721,6 +1145,20 @@ dmx_status dmx_autotune(dmx_model* m, int32_t W, int32_t n_int, double dt, const
 
 dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp->stack) {
+    bool any_ctrl = false;
+    for (const dmx_model* m : tp->models) any_ctrl = any_ctrl || m->nu > 0;
+    if (any_ctrl && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+    dmx::StackArgs a = tp->sa;
+    a.u = tp->u;
+    a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
+    a.adj_counters = (long long*)tp->adj_counters;
+    a.counters = nullptr; a.steplog = nullptr; a.log_n = nullptr; a.forced = nullptr;
+    a.queue = tp->use_queue ? tp->sa.queue + 1 : nullptr;
+    dmx_host::stack_adj(a, (hipStream_t)stream, tp->plain);
+    HIP_TRY(hipGetLastError());
+    return DMX_OK;
+  }
   if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
   dmx::AdjArgs a{};
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
@@ -755,6 +1193,7 @@ void dmx_tape_destroy(dmx_tape* tp) {
   if (tp->status) (void)hipFree(tp->status);
   if (tp->queue) (void)hipFree(tp->queue);
   if (tp->tables) (void)hipFree(tp->tables);
+  if (tp->stk_tables) (void)hipFree(tp->stk_tables);
   delete tp;
 }
 
@@ -783,8 +1222,6 @@ struct SrvReq {
   int state = 0;        // 0 queued, 1 running, 2 done
   double t_submit = 0, t_start = 0, t_done = 0;
 };
-
-size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // Device and pinned layout of a batch.  The inputs (x0 per world, controls,
 // per-world tables) are one contiguous region copied host-to-device in one

@@ -24,7 +24,8 @@ _P = C.c_void_p
 
 JOINT = {"free": 0, "hinge": 1, "slide": 2}
 GEOM = {"plane": 0, "sphere": 1, "capsule": 2, "box": 3}
-STATUS = {"MAX_STEPS": 1, "DT_UNDERFLOW": 2, "NONFINITE": 4, "SOLVER_MAXIT": 8, "TAPE_OVERFLOW": 32}
+STATUS = {"MAX_STEPS": 1, "DT_UNDERFLOW": 2, "NONFINITE": 4, "SOLVER_MAXIT": 8, "CONTACT_OVERFLOW": 16,
+          "TAPE_OVERFLOW": 32, "CONTACT_GRAPH": 64}
 
 
 class ModelDesc(C.Structure):
@@ -64,13 +65,21 @@ _lib.dmx_autotune.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, _P, _P, _P, 
 _lib.dmx_tape_info.argtypes = [_P, _P, _P]
 _lib.dmx_tape_data.argtypes = [_P, _P, _P]
 _lib.dmx_tape_destroy.argtypes = [_P]
+_lib.dmx_tape_layout.argtypes = [_P, _P, _P]
+_lib.dmx_batch_layout.argtypes = [_P, _P, _P, _P, _P]
+_lib.dmx_rollout_batch.argtypes = [_P, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P, C.POINTER(_P), _P]
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
-           "dmx_tape_data", "dmx_accel", "dmx_autotune"):
+           "dmx_tape_data", "dmx_accel", "dmx_autotune", "dmx_tape_layout", "dmx_batch_layout",
+           "dmx_rollout_batch"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
            "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_autotune",
-           "dmx_last_error"]
+           "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout"]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_worlds", C.c_int32), ("models", _P), ("n_intervals", C.c_int32), ("interval_dt", C.c_double)]
 
 
 class DmxError(RuntimeError):
@@ -170,9 +179,39 @@ class Tape:
         _check(_lib.dmx_tape_info(self.h, C.byref(s), C.byref(r)))
         return s.value, r.value
 
+    def layout(self):
+        """Per-world record offsets and lengths (doubles)."""
+        off = np.zeros(self.W, np.int64)
+        rec = np.zeros(self.W, np.int32)
+        _check(_lib.dmx_tape_layout(self.h, off.ctypes.data, rec.ctypes.data))
+        return off, rec
+
+    def world_records(self):
+        """Ragged tapes: per world the records [n_steps][rec] (host), and n_steps [W]."""
+        cap, _ = self.info()
+        off, rec = self.layout()
+        rp, npp = C.c_void_p(), C.c_void_p()
+        _check(_lib.dmx_tape_data(self.h, C.byref(rp), C.byref(npp)))
+        torch.cuda.synchronize()
+        n = torch.as_tensor(_DevArray(npp.value, (self.W,), "<i4"), device="cuda").cpu().numpy()
+        total = int(off[-1] + cap * rec[-1]) if self.W else 0
+        flat = torch.as_tensor(_DevArray(rp.value, (max(total, 1),), "<f8"), device="cuda")
+        out = []
+        for w in range(self.W):
+            seg = flat[int(off[w]):int(off[w]) + int(n[w]) * int(rec[w])]
+            out.append(seg.cpu().numpy().reshape(int(n[w]), int(rec[w])))
+        return out, n
+
     def records(self):
         """(records [W][steps][rec] float64, n_steps [W] int32) copied to the host."""
         cap, rec = self.info()
+        if getattr(self, "ragged", False):
+            per, n = self.world_records()
+            width = max(r.shape[1] for r in per)
+            out = np.zeros((self.W, max(int(n.max()), 1), width))
+            for w, r in enumerate(per):
+                out[w, :r.shape[0], :r.shape[1]] = r
+            return out, n
         rp, npp = C.c_void_p(), C.c_void_p()
         _check(_lib.dmx_tape_data(self.h, C.byref(rp), C.byref(npp)))
         torch.cuda.synchronize()
@@ -241,6 +280,72 @@ def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False, reus
         res["tape"] = Tape(th, model, W, n_int)
         res["tape"].keep = (x0, u)
     return res
+
+
+def batch_layout(models, n_int):
+    """Offsets of each world's state and controls in the packed arrays of an
+    uneven batch, and the totals."""
+    arr = (_P * len(models))(*[m.h for m in models])
+    b = Batch(len(models), C.cast(arr, _P), int(n_int), 1.0)
+    xo = np.zeros(len(models), np.int64)
+    uo = np.zeros(len(models), np.int64)
+    nx, nu = C.c_int64(), C.c_int64()
+    _check(_lib.dmx_batch_layout(C.byref(b), xo.ctypes.data, uo.ctypes.data, C.byref(nx), C.byref(nu)))
+    return xo, uo, nx.value, nu.value
+
+
+class BatchTape(Tape):
+    """Tape of an uneven batch (per-world records of different lengths)."""
+
+    def __init__(self, h, models, n_int, xo, uo, nx, nu):
+        super().__init__(h, models[0], len(models), n_int)
+        self.models, self.ragged = models, True
+        self.xo, self.uo, self.nx, self.nu = xo, uo, nx, nu
+
+
+def rollout_batch(models, x0, u, n_int, dt, opts=None, tape=False, counters=False, reuse=None):
+    """Forward rollout of an uneven batch: models (list, one per world), x0
+    packed states [sum nx_w] and u packed controls [sum n_int nu_w] (or None),
+    CUDA float64.  Returns dict(x, status[, tape][, n_acc, n_rej])."""
+    W = len(models)
+    xo, uo, nx, nu = batch_layout(models, n_int)
+    x0 = x0.contiguous()
+    assert x0.dtype == torch.float64 and x0.is_cuda and x0.numel() == nx
+    if nu:
+        u = u.contiguous()
+        assert u.dtype == torch.float64 and u.numel() == nu
+    else:
+        u = None
+    arr = (_P * W)(*[m.h for m in models])
+    b = Batch(W, C.cast(arr, _P), int(n_int), float(dt))
+    x_out = torch.empty_like(x0)
+    status = torch.empty(W, dtype=torch.int32, device=x0.device)
+    nacc = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    nrej = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    o = opts if opts is not None else default_opts()
+    th = _P(reuse.h.value if isinstance(reuse.h, _P) else reuse.h) if reuse is not None else _P()
+    tape = tape or reuse is not None
+    _check(_lib.dmx_rollout_batch(C.byref(b), C.byref(o), _ptr(x0), _ptr(u), _ptr(x_out), _ptr(status),
+                                  _ptr(nacc), _ptr(nrej), C.byref(th) if tape else None, _stream()))
+    res = {"x": x_out, "status": status, "x_off": xo, "u_off": uo}
+    if counters:
+        res["n_acc"], res["n_rej"] = nacc, nrej
+    if reuse is not None:
+        reuse.keep = (x0, u)
+        res["tape"] = reuse
+    elif tape:
+        res["tape"] = BatchTape(th, models, n_int, xo, uo, nx, nu)
+        res["tape"].keep = (x0, u)
+    return res
+
+
+def rollout_batch_vjp(tape, x_out_bar):
+    """Packed x0_bar and u_bar of sum(x_out_bar * x_out) for an uneven batch."""
+    xb = x_out_bar.contiguous()
+    x0b = torch.empty_like(xb)
+    ub = torch.empty(tape.nu, dtype=torch.float64, device=xb.device) if tape.nu else None
+    _check(_lib.dmx_rollout_vjp(tape.h, _ptr(xb), _ptr(x0b), _ptr(ub), _stream()))
+    return x0b, ub
 
 
 def accel(model, x, tau=None, cfd=False):
