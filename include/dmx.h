@@ -264,6 +264,19 @@ dmx_status dmx_autotune(dmx_model* model, int32_t n_worlds, int32_t n_intervals,
  * any number of times on one tape. */
 dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
 
+/* Allocation-free forward rollout, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the arguments and results of dmx_rollout without a
+ * tape (no gradient), every buffer the caller's.  Its one scratch buffer,
+ * the work-queue counter of the persistent launch, is a static device array
+ * of the library (256 bytes per GPU, held until the process ends), cleared
+ * by a kernel at each call; there is no size limit on the batch.  Calls that
+ * overlap on one GPU race on that counter: issue them in stream order (one
+ * stream, or synchronized streams).  Never calls hipMalloc or hipFree. */
+dmx_status dmx_rollout_noalloc(const dmx_model* model, int32_t n_worlds, int32_t n_intervals, double interval_dt,
+                               const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
+                               int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, void* stream);
+
 /* Sizes of a tape: per-world capacity and record length in doubles. */
 dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t* record_doubles);
 /* Device pointer to the tape records [W][steps_per_world][record] with records

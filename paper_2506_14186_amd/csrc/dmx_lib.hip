@@ -936,6 +936,43 @@ dmx_status dmx_rollout(const dmx_model* m, int32_t W, int32_t n_int, double dt, 
 
 }  // extern "C"
 
+// Scratch memory of the allocation-free entry point: the work-queue counter
+// of a persistent launch.  A file-scope device array, one per GPU for the
+// life of the process; host code uses its device address from
+// hipGetSymbolAddress (taken once per device), never the array's name.
+constexpr size_t kScratchBytes = 256;
+static __device__ __align__(256) int scratch[kScratchBytes / sizeof(int)];
+
+static dmx_status scratch_address(int** out) {
+  static std::mutex mu;
+  static std::vector<int*> per_device;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)per_device.size() <= dev) per_device.resize(dev + 1, nullptr);
+  if (!per_device[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(DMX_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+    per_device[dev] = (int*)p;
+  }
+  *out = per_device[dev];
+  return DMX_OK;
+}
+
+extern "C" {
+
+dmx_status dmx_rollout_noalloc(const dmx_model* m, int32_t W, int32_t n_int, double dt, const dmx_solver_opts* opts,
+                               const double* x0, const double* u, double* x_out, int32_t* world_status,
+                               int32_t* n_accepted, int32_t* n_rejected, void* stream) {
+  int* q = nullptr;
+  const dmx_status r = scratch_address(&q);
+  if (r != DMX_OK) return r;
+  return rollout_impl(m, W, n_int, dt, opts, x0, u, x_out, world_status, n_accepted, n_rejected, nullptr, stream, q);
+}
+
+}  // extern "C"
+
 static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, double dt,
                                const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
                                int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,

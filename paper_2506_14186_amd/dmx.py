@@ -68,14 +68,16 @@ _lib.dmx_tape_destroy.argtypes = [_P]
 _lib.dmx_tape_layout.argtypes = [_P, _P, _P]
 _lib.dmx_batch_layout.argtypes = [_P, _P, _P, _P, _P]
 _lib.dmx_rollout_batch.argtypes = [_P, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P, C.POINTER(_P), _P]
+_lib.dmx_rollout_noalloc.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, C.POINTER(SolverOpts), _P, _P, _P, _P,
+                                     _P, _P, _P]
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
            "dmx_tape_data", "dmx_accel", "dmx_autotune", "dmx_tape_layout", "dmx_batch_layout",
-           "dmx_rollout_batch"):
+           "dmx_rollout_batch", "dmx_rollout_noalloc"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
            "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_autotune",
-           "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout"]
+           "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout", "dmx_rollout_noalloc"]
 
 
 class Batch(C.Structure):
@@ -280,6 +282,19 @@ def rollout(model, x0, u, n_int, dt, opts=None, tape=False, counters=False, reus
         res["tape"] = Tape(th, model, W, n_int)
         res["tape"].keep = (x0, u)
     return res
+
+
+def rollout_noalloc(model, x0, u, n_int, dt, x_out, status, opts=None, n_acc=None, n_rej=None):
+    """Forward rollout without a tape that allocates no device memory (the
+    library's static scratch holds its work-queue counter); every output
+    buffer is the caller's: x_out [W, nx] float64, status [W] int32 (and
+    optionally n_acc, n_rej [W] int32), CUDA tensors."""
+    W = x0.shape[0]
+    assert x0.is_contiguous() and x_out.is_contiguous() and status.is_contiguous()
+    o = opts if opts is not None else default_opts()
+    _check(_lib.dmx_rollout_noalloc(model.h, W, int(n_int), float(dt), C.byref(o), _ptr(x0),
+                                    _ptr(u) if model.nu else None, _ptr(x_out), _ptr(status), _ptr(n_acc),
+                                    _ptr(n_rej), _stream()))
 
 
 def batch_layout(models, n_int):
