@@ -1,153 +1,157 @@
-// Contact geometry of box worlds, templated on the scalar type: `double` for
-// values, `Dual1` (value + one tangent) for directional derivatives of the
-// contact set with respect to a body pose, with every discrete choice (the
-// separating axis, the faces, the clipping decisions, the top-four vertices)
-// taken on values, so a derivative holds the combinatorics fixed.
+// Contact geometry of box worlds and its reverse.
 //
 //  - plane-box: the smoothed four-deepest-vertex detection of App. C.1;
 //  - box-box: the separating-axis test over the 15 candidate axes with face
-//    clipping (Sutherland-Hodgman) or one crossing-edge contact (primitive-
-//    vs-primitive detection of Sec. 2.1).
+//    clipping or one crossing-edge contact (primitive-vs-primitive detection
+//    of Sec. 2.1).
+//
+// Every contact comes with a code: the discrete choices that made it (the
+// separating axis, the reference and incident faces, which corner, edge
+// crossing or corner line of the clipped face, the top-four vertex and
+// whether the skin threshold was on).  The reverse sweep rebuilds the
+// contact's construction from its code and the poses and differentiates
+// point, depth and normal along it, the choices held fixed as in any
+// derivative of a contact set.
 #pragma once
 #include "dmx_common.hpp"
 
 namespace dmx {
 
-// ------------------------------------------------------------ dual numbers
-struct Dual1 { double v, d; };
-DMX_DEV Dual1 mkd(double v, double d = 0.0) { Dual1 r; r.v = v; r.d = d; return r; }
-DMX_DEV Dual1 operator+(Dual1 a, Dual1 b) { return mkd(a.v + b.v, a.d + b.d); }
-DMX_DEV Dual1 operator-(Dual1 a, Dual1 b) { return mkd(a.v - b.v, a.d - b.d); }
-DMX_DEV Dual1 operator-(Dual1 a) { return mkd(-a.v, -a.d); }
-DMX_DEV Dual1 operator*(Dual1 a, Dual1 b) { return mkd(a.v * b.v, a.d * b.v + a.v * b.d); }
-DMX_DEV Dual1 operator/(Dual1 a, Dual1 b) {
-  const double q = a.v / b.v;
-  return mkd(q, (a.d - q * b.d) / b.v);
-}
-DMX_DEV Dual1 operator+(Dual1 a, double b) { return mkd(a.v + b, a.d); }
-DMX_DEV Dual1 operator+(double a, Dual1 b) { return mkd(a + b.v, b.d); }
-DMX_DEV Dual1 operator-(Dual1 a, double b) { return mkd(a.v - b, a.d); }
-DMX_DEV Dual1 operator-(double a, Dual1 b) { return mkd(a - b.v, -b.d); }
-DMX_DEV Dual1 operator*(Dual1 a, double b) { return mkd(a.v * b, a.d * b); }
-DMX_DEV Dual1 operator*(double a, Dual1 b) { return mkd(a * b.v, a * b.d); }
-DMX_DEV Dual1 operator/(Dual1 a, double b) { return mkd(a.v / b, a.d / b); }
-DMX_DEV Dual1& operator+=(Dual1& a, Dual1 b) { a = a + b; return a; }
-DMX_DEV Dual1& operator-=(Dual1& a, Dual1 b) { a = a - b; return a; }
+DMX_DEV V3 colv(const double* R, int j) { return mk3(R[j], R[3 + j], R[6 + j]); }
+DMX_DEV void col_add(double* Rb, int j, V3 v) { Rb[j] += v.x; Rb[3 + j] += v.y; Rb[6 + j] += v.z; }
 
-DMX_DEV double val(double x) { return x; }
-DMX_DEV double val(Dual1 x) { return x.v; }
-DMX_DEV double gsqrt(double x) { return sqrt(x); }
-DMX_DEV Dual1 gsqrt(Dual1 x) { const double s = sqrt(x.v); return mkd(s, 0.5 * x.d / s); }
-DMX_DEV double gabs(double x) { return fabs(x); }
-DMX_DEV Dual1 gabs(Dual1 x) { return x.v < 0.0 ? -x : x; }
-template <class T> DMX_DEV T lift(double x) { return T(x); }
-template <> DMX_DEV Dual1 lift<Dual1>(double x) { return mkd(x); }
+// Tangent frame of a unit normal (a = e_x unless |n_x| >= 0.5, then e_y):
+// t1 = normalized (a - (a.n) n), t2 = n x t1.
+DMX_DEV void make_frame(V3 n, V3* t1, V3* t2) {
+  const V3 a = fabs(n.x) < 0.5 ? mk3(1.0, 0.0, 0.0) : mk3(0.0, 1.0, 0.0);
+  const V3 t = a - dot(a, n) * n;
+  *t1 = (1.0 / sqrt(dot(t, t))) * t;
+  *t2 = cross(n, *t1);
+}
+// cotangent of n from those of t1 and t2
+DMX_DEV V3 make_frame_vjp(V3 n, V3 t1b, V3 t2b) {
+  const V3 a = fabs(n.x) < 0.5 ? mk3(1.0, 0.0, 0.0) : mk3(0.0, 1.0, 0.0);
+  const V3 t = a - dot(a, n) * n;
+  const double inv = 1.0 / sqrt(dot(t, t));
+  const V3 t1 = inv * t;
+  V3 nb = cross(t1, t2b);  // t2 = n x t1
+  const V3 t1t = t1b + cross(t2b, n);
+  const V3 tb = inv * (t1t - dot(t1, t1t) * t1);
+  nb -= dot(a, n) * tb + dot(n, tb) * a;  // t = a - (a.n) n
+  return nb;
+}
 
-template <class T> struct TV { T x, y, z; };
-template <class T> DMX_DEV TV<T> tv(T a, T b, T c) { TV<T> r; r.x = a; r.y = b; r.z = c; return r; }
-template <class T> DMX_DEV TV<T> liftv(const double* p) { return tv<T>(lift<T>(p[0]), lift<T>(p[1]), lift<T>(p[2])); }
-template <class T> DMX_DEV TV<T> operator+(TV<T> a, TV<T> b) { return tv<T>(a.x + b.x, a.y + b.y, a.z + b.z); }
-template <class T> DMX_DEV TV<T> operator-(TV<T> a, TV<T> b) { return tv<T>(a.x - b.x, a.y - b.y, a.z - b.z); }
-template <class T, class S> DMX_DEV TV<T> scl(TV<T> a, S s) { return tv<T>(a.x * s, a.y * s, a.z * s); }
-template <class T> DMX_DEV T tdot(TV<T> a, TV<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-template <class T> DMX_DEV TV<T> tcross(TV<T> a, TV<T> b) {
-  return tv<T>(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-// row-major 3x3; column j is the body axis j in the world
-template <class T> struct TM { T a[9]; };
-template <class T> DMX_DEV TV<T> tcol(const TM<T>& m, int j) { return tv<T>(m.a[j], m.a[3 + j], m.a[6 + j]); }
-template <class T> DMX_DEV TV<T> tmul(const TM<T>& m, TV<T> v) {
-  return tv<T>(m.a[0] * v.x + m.a[1] * v.y + m.a[2] * v.z, m.a[3] * v.x + m.a[4] * v.y + m.a[5] * v.z,
-               m.a[6] * v.x + m.a[7] * v.y + m.a[8] * v.z);
-}
-template <class T> DMX_DEV TV<T> tmulT(const TM<T>& m, TV<T> v) {
-  return tv<T>(m.a[0] * v.x + m.a[3] * v.y + m.a[6] * v.z, m.a[1] * v.x + m.a[4] * v.y + m.a[7] * v.z,
-               m.a[2] * v.x + m.a[5] * v.y + m.a[8] * v.z);
-}
-template <class T> DMX_DEV double cval(const TV<T>& v, int i) { return val(i == 0 ? v.x : (i == 1 ? v.y : v.z)); }
-template <class T> DMX_DEV T comp(const TV<T>& v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : v.z); }
-
-// Tangent frame of a unit normal: t1 = normalized (a - (a.n) n) with a = e_x
-// unless |n_x| >= 0.5 (then e_y), t2 = n x t1.
-template <class T>
-DMX_DEV void make_frame_t(TV<T> n, TV<T>* t1, TV<T>* t2) {
-  const bool ex = fabs(val(n.x)) < 0.5;
-  const TV<T> a = ex ? tv<T>(lift<T>(1.0), lift<T>(0.0), lift<T>(0.0)) : tv<T>(lift<T>(0.0), lift<T>(1.0), lift<T>(0.0));
-  const TV<T> t = a - scl(n, tdot(a, n));
-  *t1 = scl(t, lift<T>(1.0) / gsqrt(tdot(t, t)));
-  *t2 = tcross(n, *t1);
-}
+// ------------------------------------------------------------ contact codes
+// bits 0-2 kind, 3-5 and 6-8 two indices, 9 a flag, 10-13 the separating
+// axis (face 0-5 or edge 0-8), 14 set for an edge axis, 15-21 orientation
+// signs of the construction.
+enum { kRcCorner = 0, kRcCross = 1, kRcLine = 2, kRcVertex = 3, kRcEdges = 4 };
+DMX_DEV int rc_kind(int c) { return c & 7; }
+DMX_DEV int rc_i(int c) { return (c >> 3) & 7; }
+DMX_DEV int rc_j(int c) { return (c >> 6) & 7; }
+DMX_DEV bool rc_flag(int c) { return (c >> 9) & 1; }
+DMX_DEV int rc_axis(int c) { return (c >> 10) & 15; }
+DMX_DEV bool rc_bit(int c, int b) { return (c >> b) & 1; }
 
 // ------------------------------------------------------------ plane-box
-// Smoothed four-deepest-vertex detection (App. C.1).  Vertex k of the box
-// (centre c, rotation R, half sizes h; coordinate signs from the bits of k:
-// x bit 0, y bit 1, z bit 2) is x_k = c + R s_k and penetrates the plane
-// (point p0, normal n) by e_k = -n.(x_k - p0).  With the skin 1 mm and
-// tau = max(0, e_max - skin), the weight w_k = smoothstep((e_k - (tau - skin))
-// / skin) (C^1 smoothstep t^2 (3 - 2t) on [0, 1]), the weighted depth
-// z_k = w_k e_k, and the four largest z_k (ties to the lower vertex index)
-// are the candidates, with r = -z_k at x_k + (z_k / 2) n.  Candidates with
-// r >= margin are dropped (they make no rows).  Returns the count.
-template <class T>
-DMX_DEV T smoothstep_t(T u) {
-  if (val(u) <= 0.0) return lift<T>(0.0);
-  if (val(u) >= 1.0) return lift<T>(1.0);
+// Vertex k of the box (centre c, rotation R, half sizes h; coordinate signs
+// from the bits of k: x bit 0, y bit 1, z bit 2) is x_k = c + R s_k and
+// penetrates the plane (point p0, normal n) by e_k = -n.(x_k - p0).  With the
+// skin 1 mm and tau = max(0, e_max - skin), w_k = smoothstep((e_k - (tau -
+// skin)) / skin) (C^1 smoothstep t^2 (3 - 2t) on [0, 1]) and z_k = w_k e_k;
+// the four largest z_k (ties to the lower vertex index) give r = -z_k at
+// x_k + (z_k / 2) n.  Candidates with r >= margin are dropped.
+// Code: vertex k, the deepest vertex, the threshold flag.
+DMX_DEV V3 box_corner(const double* h, int k) {
+  return mk3((k & 1) ? h[0] : -h[0], (k & 2) ? h[1] : -h[1], (k & 4) ? h[2] : -h[2]);
+}
+DMX_DEV double smoothstep(double u, double* du) {
+  if (u <= 0.0) { *du = 0.0; return 0.0; }
+  if (u >= 1.0) { *du = 0.0; return 1.0; }
+  *du = 6.0 * u * (1.0 - u);
   return u * u * (3.0 - 2.0 * u);
 }
 
-template <class T>
-DMX_DEV int box_plane_t(const double* h, const double* p0, const double* pn, TV<T> c, const TM<T>& R, double margin,
-                        T* r_out, TV<T>* p_out) {
-  const double skin = 1e-3;
-  const TV<T> n = liftv<T>(pn), q0 = liftv<T>(p0);
-  TV<T> x[8];
-  T e[8];
+constexpr double kPlaneSkin = 1e-3;
+
+DMX_DEV int box_plane(const double* h, const double* p0, const double* pn, V3 c, const M3& R, double margin,
+                      double* r_out, V3* p_out, int* code) {
+  const V3 n = ld3(pn), q0 = ld3(p0);
+  double e[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) e[k] = -dot(n, c + mul(R, box_corner(h, k)) - q0);
+  int kmax = 0;
+  double emax = e[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (e[k] > emax) { emax = e[k]; kmax = k; }
+  const bool tau_on = emax > kPlaneSkin;
+  const double tau = tau_on ? emax - kPlaneSkin : 0.0;
+  double z[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) { double du; z[k] = smoothstep((e[k] - (tau - kPlaneSkin)) / kPlaneSkin, &du) * e[k]; }
+  int rk[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const TV<T> s = tv<T>(lift<T>((k & 1) ? h[0] : -h[0]), lift<T>((k & 2) ? h[1] : -h[1]),
-                          lift<T>((k & 4) ? h[2] : -h[2]));
-    x[k] = c + tmul(R, s);
-    e[k] = lift<T>(0.0) - tdot(n, x[k] - q0);
+    rk[k] = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rk[k] += (z[j] > z[k]) || (j < k && z[j] == z[k]);
   }
-  int kmax = 0;
-#pragma unroll
-  for (int k = 1; k < 8; ++k) kmax = val(e[k]) > val(e[kmax]) ? k : kmax;
-  T emax = e[0];
-#pragma unroll
-  for (int k = 1; k < 8; ++k) if (k == kmax) emax = e[k];
-  const T tau = val(emax) > skin ? emax - skin : lift<T>(0.0);
-  T z[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) z[k] = smoothstep_t<T>((e[k] - (tau - skin)) / skin) * e[k];
+  // the candidates that pass the margin are a prefix of the rank order
   int cnt = 0;
 #pragma unroll
-  for (int rank = 0; rank < 4; ++rank) {
+  for (int slot = 0; slot < 4; ++slot) {
+    int k = 0;
+    double zk = z[0];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int rk = 0;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) rk += (val(z[j]) > val(z[k])) || (j < k && val(z[j]) == val(z[k]));
-      if (rk == rank) {
-        const T r = lift<T>(0.0) - z[k];
-        if (val(r) < margin) {
-          r_out[cnt] = r;
-          p_out[cnt] = x[k] + scl(n, z[k] * 0.5);
-          ++cnt;
-        }
+    for (int q = 1; q < 8; ++q)
+      if (rk[q] == slot) { k = q; zk = z[q]; }
+    if (-zk < margin) {
+      if (r_out) {
+        r_out[slot] = -zk;
+        p_out[slot] = c + mul(R, box_corner(h, k)) + (0.5 * zk) * n;
       }
+      if (code) code[slot] = kRcVertex | (k << 3) | (kmax << 6) | (tau_on ? 1 << 9 : 0);
+      cnt = slot + 1;
     }
   }
   return cnt;
 }
 
+// cotangents of the box pose (c_bar += , R_bar += ) from those of one
+// plane-box contact (r_bar, p_bar); the normal is the plane's
+DMX_DEV void box_plane_vjp(const double* h, const double* p0, const double* pn, V3 c, const M3& R, int code,
+                           double rb, V3 pb, V3* cb, double* Rb) {
+  const V3 n = ld3(pn), q0 = ld3(p0);
+  const V3 sk = box_corner(h, rc_i(code)), sm = box_corner(h, rc_j(code));
+  const double ek = -dot(n, c + mul(R, sk) - q0);
+  const double em = -dot(n, c + mul(R, sm) - q0);
+  const bool tau_on = rc_flag(code);
+  const double tau = tau_on ? em - kPlaneSkin : 0.0;
+  double du;
+  const double w = smoothstep((ek - (tau - kPlaneSkin)) / kPlaneSkin, &du);
+  // r = -z, p = x_k + (z/2) n, z = w e_k
+  const double zb = -rb + 0.5 * dot(n, pb);
+  const double wb = zb * ek;
+  const double ekb = zb * w + wb * du / kPlaneSkin;
+  const double taub = -wb * du / kPlaneSkin;
+  const V3 xk = pb - ekb * n;                                    // x_k bar
+  const V3 xm = tau_on ? (-taub) * n : mk3(0.0, 0.0, 0.0);       // e_max = -n.(x_m - p0)
+  // x = c + R s: c_bar += x_bar, R_bar += x_bar s^T
+  *cb += xk + xm;
+  const double xs[3][2] = {{xk.x, xm.x}, {xk.y, xm.y}, {xk.z, xm.z}};
+  const double ss[3][2] = {{sk.x, sm.x}, {sk.y, sm.y}, {sk.z, sm.z}};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Rb[3 * i + j] += xs[i][0] * ss[j][0] + xs[i][1] * ss[j][1];
+}
+
 // ------------------------------------------------------------ box-box
-// The discrete choices of a box-box pair, taken on values and reused by
-// derivative passes.
 struct BoxChoice {
   int edge;  // -1: face axis `face` (0-2 of box A, 3-5 of box B); else edge axis 3 i + j
   int face;
 };
-
 constexpr int kBoxBoxMax = 8;
 
 // Separating-axis test over the 15 axes: the overlap of the projections on a
@@ -156,17 +160,17 @@ constexpr int kBoxBoxMax = 8;
 // of least overlap unless the least edge overlap (cross products shorter
 // than 1e-6 skipped) is smaller by more than 5% of its magnitude plus 1e-6.
 // Returns false if the boxes are apart by at least `margin` along some axis.
-DMX_DEV bool box_box_choose(const double* ha, const double* hb, const TV<double>& cA, const TM<double>& RA,
-                            const TV<double>& cB, const TM<double>& RB, double margin, BoxChoice* ch) {
-  TV<double> uA[3], uB[3];
+DMX_DEV bool box_box_choose(const double* ha, const double* hb, V3 cA, const M3& RA, V3 cB, const M3& RB,
+                            double margin, BoxChoice* ch) {
+  V3 uA[3], uB[3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) { uA[i] = tcol(RA, i); uB[i] = tcol(RB, i); }
-  const TV<double> d = cB - cA;
-  auto overlap = [&](const TV<double>& L) {
+  for (int i = 0; i < 3; ++i) { uA[i] = colv(RA.a, i); uB[i] = colv(RB.a, i); }
+  const V3 d = cB - cA;
+  auto overlap = [&](V3 L) {
     double pa = 0.0, pb = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { pa += fabs(tdot(L, uA[i])) * ha[i]; pb += fabs(tdot(L, uB[i])) * hb[i]; }
-    return pa + pb - fabs(tdot(L, d));
+    for (int i = 0; i < 3; ++i) { pa += fabs(dot(L, uA[i])) * ha[i]; pb += fabs(dot(L, uB[i])) * hb[i]; }
+    return pa + pb - fabs(dot(L, d));
   };
   int face = 0, edge = -1;
   double of = 1e300, oe = 1e300;
@@ -179,10 +183,10 @@ DMX_DEV bool box_box_choose(const double* ha, const double* hb, const TV<double>
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const TV<double> c = tcross(uA[i], uB[j]);
-      const double cn = sqrt(tdot(c, c));
+      const V3 c = cross(uA[i], uB[j]);
+      const double cn = sqrt(dot(c, c));
       if (cn < 1e-6) continue;
-      const double o = overlap(scl(c, 1.0 / cn));
+      const double o = overlap((1.0 / cn) * c);
       if (o < oe) { oe = o; edge = 3 * i + j; }
     }
   const bool use_edge = edge >= 0 && oe < of - (0.05 * fabs(of) + 1e-6);
@@ -191,96 +195,328 @@ DMX_DEV bool box_box_choose(const double* ha, const double* hb, const TV<double>
   return fmin(of, oe) > -margin;
 }
 
-// Contacts of a box-box pair for a given choice: up to 8 (face clipping) or 1
-// (crossing edges) with r below the margin; normal from A toward B.
-template <class T>
-DMX_DEV int box_box_contacts(const double* ha, const double* hb, TV<T> cA, const TM<T>& RA, TV<T> cB,
-                             const TM<T>& RB, double margin, const BoxChoice& ch, T* r_out, TV<T>* p_out,
-                             TV<T>* n_out) {
-  TV<T> uA[3], uB[3];
+// The face case's frame: reference box (the axis owner) and incident box,
+// the reference normal's sign (toward the incident box) and the incident
+// face (the incident axis most anti-parallel to the reference normal).
+struct FaceFrame {
+  bool refA;
+  int face, ax, fj, j1, j2, k1, k2;
+  double ns, sg;  // nR = ns u_R[ax]; incident face centre c_I + sg h_I[fj] u_I[fj]
+};
+DMX_DEV void face_frame_finish(FaceFrame& f) {
+  f.j1 = (f.fj + 1) % 3; f.j2 = (f.fj + 2) % 3;
+  f.k1 = (f.ax + 1) % 3; f.k2 = (f.ax + 2) % 3;
+}
+DMX_DEV FaceFrame face_frame(int face, V3 cA, const M3& RA, V3 cB, const M3& RB) {
+  FaceFrame f;
+  f.face = face;
+  f.refA = face < 3;
+  f.ax = face % 3;
+  const double* RR = f.refA ? RA.a : RB.a;
+  const double* RI = f.refA ? RB.a : RA.a;
+  const V3 cR = f.refA ? cA : cB, cI = f.refA ? cB : cA;
+  const V3 u = colv(RR, f.ax);
+  f.ns = dot(u, cI - cR) < 0.0 ? -1.0 : 1.0;
+  const V3 nR = f.ns * u;
+  f.fj = 0;
+  double best = -1.0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) { uA[i] = tcol(RA, i); uB[i] = tcol(RB, i); }
-  const TV<T> d = cB - cA;
+  for (int j = 0; j < 3; ++j) {
+    const double a = fabs(dot(nR, colv(RI, j)));
+    if (a > best) { best = a; f.fj = j; }
+  }
+  f.sg = dot(nR, colv(RI, f.fj)) > 0.0 ? -1.0 : 1.0;
+  face_frame_finish(f);
+  return f;
+}
+DMX_DEV int face_code(const FaceFrame& f) {
+  return (f.face << 10) | (f.ns < 0.0 ? 1 << 15 : 0) | (f.fj << 16) | (f.sg < 0.0 ? 1 << 18 : 0);
+}
+DMX_DEV FaceFrame face_frame_of(int code) {
+  FaceFrame f;
+  f.face = rc_axis(code);
+  f.refA = f.face < 3;
+  f.ax = f.face % 3;
+  f.ns = rc_bit(code, 15) ? -1.0 : 1.0;
+  f.fj = (code >> 16) & 3;
+  f.sg = rc_bit(code, 18) ? -1.0 : 1.0;
+  face_frame_finish(f);
+  return f;
+}
+
+constexpr double kS1[4] = {1.0, -1.0, -1.0, 1.0}, kS2[4] = {1.0, 1.0, -1.0, -1.0};
+
+// The face case's construction, shared by the contacts and their reverse:
+// reference box (R, c, h), incident box, the reference normal nR, the
+// incident face's centre fc and in-face axes, the reference face's point pf
+// and side axes.
+struct FaceGeo {
+  const double *RR, *RI, *hR, *hI;
+  V3 cR, cI, nR, uI1, uI2, uR1, uR2, fc, pf;
+};
+DMX_DEV FaceGeo face_geo(const FaceFrame& f, const double* ha, const double* hb, V3 cA, const M3& RA, V3 cB,
+                         const M3& RB) {
+  FaceGeo g;
+  g.RR = f.refA ? RA.a : RB.a;
+  g.RI = f.refA ? RB.a : RA.a;
+  g.hR = f.refA ? ha : hb;
+  g.hI = f.refA ? hb : ha;
+  g.cR = f.refA ? cA : cB;
+  g.cI = f.refA ? cB : cA;
+  g.nR = f.ns * colv(g.RR, f.ax);
+  g.uI1 = colv(g.RI, f.j1); g.uI2 = colv(g.RI, f.j2);
+  g.uR1 = colv(g.RR, f.k1); g.uR2 = colv(g.RR, f.k2);
+  g.fc = g.cI + (f.sg * g.hI[f.fj]) * colv(g.RI, f.fj);
+  g.pf = g.cR + g.hR[f.ax] * g.nR;
+  return g;
+}
+DMX_DEV V3 face_corner(const FaceFrame& f, const FaceGeo& g, int c) {
+  return g.fc + (kS1[c] * g.hI[f.j1]) * g.uI1 + (kS2[c] * g.hI[f.j2]) * g.uI2;
+}
+
+// Contacts of a box-box pair for a given choice: up to 8 (the clipped
+// incident face) or 1 (crossing edges) with r below the margin, and their
+// common normal from A toward B (outputs may be null: count only).  The clipped face's vertices are enumerated: (a) incident corners
+// inside the reference face's prism |u_k1.(p - cR)| <= h_k1,
+// |u_k2.(p - cR)| <= h_k2, (b) crossings of incident edges with the prism's
+// side planes inside the other slab, (c) points of the incident face on the
+// prism's corner lines strictly inside the face.  Each point P is projected
+// halfway to the reference face: r = nR.(P - pf), p = P - (r / 2) nR.
+// Crossing edges: the closest points PA, PB of the two supporting edge lines
+// give r = n.(PB - PA) at their midpoint.
+DMX_DEV int box_box_contacts(const double* ha, const double* hb, V3 cA, const M3& RA, V3 cB, const M3& RB,
+                             double margin, const BoxChoice& ch, double* r_out, V3* p_out, V3* n_out, int* code) {
+  // (r_out, p_out, n_out are all given or all null)
   if (ch.edge < 0) {
-    const bool refA = ch.face < 3;
-    const int ax = ch.face % 3;
-    const TV<T>* uR = refA ? uA : uB;
-    const TV<T>* uI = refA ? uB : uA;
-    const double* hR = refA ? ha : hb;
-    const double* hI = refA ? hb : ha;
-    const TV<T> cR = refA ? cA : cB, cI = refA ? cB : cA;
-    TV<T> nR = uR[ax];
-    if (val(tdot(nR, cI - cR)) < 0.0) nR = scl(nR, -1.0);
-    int fj = 0;
-    double best = -1.0;
+    const FaceFrame f = face_frame(ch.face, cA, RA, cB, RB);
+    const FaceGeo g = face_geo(f, ha, hb, cA, RA, cB, RB);
+    if (n_out) *n_out = f.refA ? g.nR : (-1.0) * g.nR;
+    const int base = face_code(f);
+    int cnt = 0;
+    auto emit = [&](V3 P, int cc) {
+      const double r = dot(g.nR, P - g.pf);
+      if (r >= margin || cnt >= kBoxBoxMax) return;
+      if (r_out) {
+        r_out[cnt] = r;
+        p_out[cnt] = P - (0.5 * r) * g.nR;
+      }
+      if (code) code[cnt] = base | cc;
+      ++cnt;
+    };
+    V3 C[4];
+    double g1[4], g2[4];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const double a = fabs(val(tdot(nR, uI[j])));
-      if (a > best) { best = a; fj = j; }
+    for (int c = 0; c < 4; ++c) {
+      C[c] = face_corner(f, g, c);
+      g1[c] = dot(g.uR1, C[c] - g.cR);
+      g2[c] = dot(g.uR2, C[c] - g.cR);
     }
-    const double sg = val(tdot(nR, uI[fj])) > 0.0 ? -1.0 : 1.0;
-    const TV<T> fc = cI + scl(uI[fj], sg * hI[fj]);
-    const int j1 = (fj + 1) % 3, j2 = (fj + 2) % 3;
-    TV<T> poly[2][kBoxBoxMax + 1];
-    int np = 4, cur = 0;
-    {
-      const double s1[4] = {1.0, -1.0, -1.0, 1.0}, s2[4] = {1.0, 1.0, -1.0, -1.0};
+    const double hk1 = g.hR[f.k1], hk2 = g.hR[f.k2];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) poly[0][c] = fc + scl(uI[j1], s1[c] * hI[j1]) + scl(uI[j2], s2[c] * hI[j2]);
-    }
+    for (int c = 0; c < 4; ++c)
+      if (fabs(g1[c]) <= hk1 && fabs(g2[c]) <= hk2) emit(C[c], kRcCorner | (c << 3));
 #pragma unroll
-    for (int kk = 1; kk <= 2; ++kk) {
-      const int k2 = (ax + kk) % 3;
+    for (int c = 0; c < 4; ++c) {
+      const int d = (c + 1) & 3;
 #pragma unroll
-      for (int sgn = 1; sgn >= -1; sgn -= 2) {
-        int nn = 0;
-        for (int i = 0; i < np; ++i) {
-          const TV<T> P = poly[cur][i];
-          const TV<T> Q = poly[cur][i + 1 < np ? i + 1 : 0];
-          const T fP = tdot(uR[k2], P - cR) * (double)sgn - hR[k2];
-          const T fQ = tdot(uR[k2], Q - cR) * (double)sgn - hR[k2];
-          const bool inP = val(fP) <= 0.0, inQ = val(fQ) <= 0.0;
-          if (inP && nn <= kBoxBoxMax) poly[1 - cur][nn++] = P;
-          if (inP != inQ && nn <= kBoxBoxMax) poly[1 - cur][nn++] = P + scl(Q - P, fP / (fP - fQ));
-        }
-        np = nn;
-        cur = 1 - cur;
+      for (int pl = 0; pl < 4; ++pl) {
+        const bool first = pl < 2;
+        const double lim = ((pl & 1) ? -1.0 : 1.0) * (first ? hk1 : hk2);
+        const double ga = first ? g1[c] : g2[c], gb = first ? g1[d] : g2[d];
+        const double dv = gb - ga;
+        if (dv == 0.0) continue;
+        const double t = (lim - ga) / dv;
+        if (!(t > 0.0 && t < 1.0)) continue;
+        const double go = first ? g2[c] + (g2[d] - g2[c]) * t : g1[c] + (g1[d] - g1[c]) * t;
+        if (fabs(go) <= (first ? hk2 : hk1)) emit(C[c] + t * (C[d] - C[c]), kRcCross | (c << 3) | (pl << 6));
       }
     }
-    const TV<T> pf = cR + scl(nR, hR[ax]);
-    int cnt = 0;
-    for (int i = 0; i < np; ++i) {
-      const TV<T> P = poly[cur][i];
-      const T r = tdot(nR, P - pf);
-      if (val(r) >= margin || cnt >= kBoxBoxMax) continue;
-      r_out[cnt] = r;
-      p_out[cnt] = P - scl(nR, r * 0.5);
-      n_out[cnt] = refA ? nR : scl(nR, -1.0);
-      ++cnt;
+    const double m11 = dot(g.uR1, g.uI1), m12 = dot(g.uR1, g.uI2), m21 = dot(g.uR2, g.uI1), m22 = dot(g.uR2, g.uI2);
+    const double o1 = dot(g.uR1, g.fc - g.cR), o2 = dot(g.uR2, g.fc - g.cR);
+    const double det = m11 * m22 - m12 * m21;
+    if (det != 0.0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double b1 = kS1[c] * hk1 - o1, b2 = kS2[c] * hk2 - o2;
+        const double a = (b1 * m22 - b2 * m12) / det, b = (m11 * b2 - m21 * b1) / det;
+        if (fabs(a) < g.hI[f.j1] && fabs(b) < g.hI[f.j2]) emit(g.fc + a * g.uI1 + b * g.uI2, kRcLine | (c << 3));
+      }
     }
     return cnt;
   }
   const int i = ch.edge / 3, j = ch.edge % 3;
-  TV<T> n = tcross(uA[i], uB[j]);
-  n = scl(n, lift<T>(1.0) / gsqrt(tdot(n, n)));
-  if (val(tdot(n, d)) < 0.0) n = scl(n, -1.0);
-  TV<T> pA = cA, pB = cB;
+  const V3 ui = colv(RA.a, i), uj = colv(RB.a, j);
+  V3 n = cross(ui, uj);
+  n = (1.0 / sqrt(dot(n, n))) * n;
+  const bool flip = dot(n, cB - cA) < 0.0;
+  if (flip) n = (-1.0) * n;
+  int signs = 0;
+  V3 pA = cA, pB = cB;
 #pragma unroll
-  for (int k2 = 0; k2 < 3; ++k2) {
-    if (k2 != i) pA = pA + scl(uA[k2], (val(tdot(n, uA[k2])) >= 0.0 ? 1.0 : -1.0) * ha[k2]);
-    if (k2 != j) pB = pB + scl(uB[k2], (val(tdot(n, uB[k2])) >= 0.0 ? -1.0 : 1.0) * hb[k2]);
+  for (int k = 0; k < 3; ++k) {
+    const bool na = dot(n, colv(RA.a, k)) < 0.0, nb = dot(n, colv(RB.a, k)) >= 0.0;
+    signs |= (na ? 1 << k : 0) | (nb ? 1 << (3 + k) : 0);
+    if (k != i) pA += ((na ? -1.0 : 1.0) * ha[k]) * colv(RA.a, k);
+    if (k != j) pB += ((nb ? -1.0 : 1.0) * hb[k]) * colv(RB.a, k);
   }
-  const TV<T> w = pA - pB;
-  const T b = tdot(uA[i], uB[j]), dd = tdot(uA[i], w), e = tdot(uB[j], w);
-  const T den = lift<T>(1.0) - b * b;
-  const T sA = (b * e - dd) / den, tB = (e - b * dd) / den;
-  const TV<T> PA = pA + scl(uA[i], sA), PB = pB + scl(uB[j], tB);
-  const T r = tdot(n, PB - PA);
-  if (val(r) >= margin) return 0;
-  r_out[0] = r;
-  p_out[0] = scl(PA + PB, 0.5);
-  n_out[0] = n;
+  const V3 w = pA - pB;
+  const double b = dot(ui, uj), dd = dot(ui, w), e = dot(uj, w);
+  const double den = 1.0 - b * b;
+  const double sA = (b * e - dd) / den, tB = (e - b * dd) / den;
+  const V3 PA = pA + sA * ui, PB = pB + tB * uj;
+  const double r = dot(n, PB - PA);
+  if (r >= margin) return 0;
+  if (r_out) {
+    r_out[0] = r;
+    p_out[0] = 0.5 * (PA + PB);
+    *n_out = n;
+  }
+  if (code) code[0] = kRcEdges | (i << 3) | (j << 6) | (ch.edge << 10) | (1 << 14) | (flip ? 1 << 15 : 0) | (signs << 16);
   return 1;
+}
+
+// Cotangents of the two box poses (c_bar, R_bar of A and B, accumulated) from
+// those of one contact (r_bar, p_bar, n_bar), along the construction its code
+// names.
+DMX_DEV void box_box_vjp(const double* ha, const double* hb, V3 cA, const M3& RA, V3 cB, const M3& RB, int code,
+                         double rb, V3 pb, V3 nb, V3* cAb, double* RAb, V3* cBb, double* RBb) {
+  if (!rc_bit(code, 14)) {
+    const FaceFrame f = face_frame_of(code);
+    const FaceGeo g = face_geo(f, ha, hb, cA, RA, cB, RB);
+    double* RRb = f.refA ? RAb : RBb;
+    double* RIb = f.refA ? RBb : RAb;
+    const int kind = rc_kind(code), c = rc_i(code);
+    const double hk1 = g.hR[f.k1], hk2 = g.hR[f.k2];
+    // the clipped point P
+    V3 P;
+    double t = 0.0, la = 0.0, lb = 0.0;
+    double m11 = 0.0, m12 = 0.0, m21 = 0.0, m22 = 0.0, det = 1.0;
+    if (kind == kRcCorner) {
+      P = face_corner(f, g, c);
+    } else if (kind == kRcCross) {
+      const int d = (c + 1) & 3, pl = rc_j(code);
+      const bool first = pl < 2;
+      const V3 uk = first ? g.uR1 : g.uR2;
+      const double lim = ((pl & 1) ? -1.0 : 1.0) * (first ? hk1 : hk2);
+      const V3 Cc = face_corner(f, g, c), Cd = face_corner(f, g, d);
+      const double gc = dot(uk, Cc - g.cR), gd = dot(uk, Cd - g.cR);
+      t = (lim - gc) / (gd - gc);
+      P = Cc + t * (Cd - Cc);
+    } else {
+      m11 = dot(g.uR1, g.uI1); m12 = dot(g.uR1, g.uI2); m21 = dot(g.uR2, g.uI1); m22 = dot(g.uR2, g.uI2);
+      const double o1 = dot(g.uR1, g.fc - g.cR), o2 = dot(g.uR2, g.fc - g.cR);
+      det = m11 * m22 - m12 * m21;
+      const double b1 = kS1[c] * hk1 - o1, b2 = kS2[c] * hk2 - o2;
+      la = (b1 * m22 - b2 * m12) / det;
+      lb = (m11 * b2 - m21 * b1) / det;
+      P = g.fc + la * g.uI1 + lb * g.uI2;
+    }
+    const double r = dot(g.nR, P - g.pf);
+    // p = P - (r/2) nR, r = nR.(P - pf), n = +-nR
+    const double rt = rb - 0.5 * dot(g.nR, pb);
+    V3 nRb = (-0.5 * r) * pb + (f.refA ? nb : (-1.0) * nb) + rt * (P - g.pf);
+    const V3 Pb = pb + rt * g.nR;
+    V3 cRb = (-rt) * g.nR;  // pf = cR + h_R[ax] nR
+    nRb += (-rt * g.hR[f.ax]) * g.nR;
+    V3 cIb = mk3(0.0, 0.0, 0.0), fcb = mk3(0.0, 0.0, 0.0);
+    V3 uR1b = mk3(0.0, 0.0, 0.0), uR2b = mk3(0.0, 0.0, 0.0), uI1b = mk3(0.0, 0.0, 0.0), uI2b = mk3(0.0, 0.0, 0.0);
+    auto corner_b = [&](int cc, V3 Cb) {
+      fcb += Cb;
+      uI1b += (kS1[cc] * g.hI[f.j1]) * Cb;
+      uI2b += (kS2[cc] * g.hI[f.j2]) * Cb;
+    };
+    if (kind == kRcCorner) {
+      corner_b(c, Pb);
+    } else if (kind == kRcCross) {
+      // P = Cc + t (Cd - Cc), t = (lim - gc) / (gd - gc), g = u_k.(C - cR)
+      const int d = (c + 1) & 3;
+      const bool first = rc_j(code) < 2;
+      const V3 uk = first ? g.uR1 : g.uR2;
+      const V3 Cc = face_corner(f, g, c), Cd = face_corner(f, g, d);
+      const double gc = dot(uk, Cc - g.cR), gd = dot(uk, Cd - g.cR);
+      const double D = gd - gc;
+      const double tb = dot(Pb, Cd - Cc);
+      const double gcb = tb * (t - 1.0) / D, gdb = -tb * t / D;
+      const V3 ukb = gcb * (Cc - g.cR) + gdb * (Cd - g.cR);
+      if (first) uR1b += ukb; else uR2b += ukb;
+      corner_b(c, (1.0 - t) * Pb + gcb * uk);
+      corner_b(d, t * Pb + gdb * uk);
+      cRb -= (gcb + gdb) * uk;
+    } else {
+      // P = fc + a u_I1 + b u_I2 with M (a, b) = (s1 h_k1 - o1, s2 h_k2 - o2),
+      // M_ij = u_Ri.u_Ij, o_i = u_Ri.(fc - cR)
+      const double ab = dot(Pb, g.uI1), bb = dot(Pb, g.uI2);
+      fcb += Pb;
+      uI1b += la * Pb;
+      uI2b += lb * Pb;
+      const double y1 = (m22 * ab - m21 * bb) / det, y2 = (-m12 * ab + m11 * bb) / det;  // M^-T (ab, bb)
+      // rhs_bar = y: o_bar = -y; M_bar = -y (a, b)^T
+      uR1b += (-y1) * (g.fc - g.cR);
+      uR2b += (-y2) * (g.fc - g.cR);
+      fcb -= y1 * g.uR1 + y2 * g.uR2;
+      cRb += y1 * g.uR1 + y2 * g.uR2;
+      uR1b -= y1 * (la * g.uI1 + lb * g.uI2);
+      uR2b -= y2 * (la * g.uI1 + lb * g.uI2);
+      uI1b -= la * (y1 * g.uR1 + y2 * g.uR2);
+      uI2b -= lb * (y1 * g.uR1 + y2 * g.uR2);
+    }
+    // fc = cI + sg h_I[fj] u_I[fj]
+    cIb += fcb;
+    col_add(RIb, f.fj, (f.sg * g.hI[f.fj]) * fcb);
+    col_add(RIb, f.j1, uI1b);
+    col_add(RIb, f.j2, uI2b);
+    col_add(RRb, f.ax, f.ns * nRb);
+    col_add(RRb, f.k1, uR1b);
+    col_add(RRb, f.k2, uR2b);
+    if (f.refA) { *cAb += cRb; *cBb += cIb; } else { *cBb += cRb; *cAb += cIb; }
+    return;
+  }
+  const int i = rc_i(code), j = rc_j(code);
+  const V3 ui = colv(RA.a, i), uj = colv(RB.a, j);
+  const V3 cr = cross(ui, uj);
+  const double cn = sqrt(dot(cr, cr));
+  const double sn = rc_bit(code, 15) ? -1.0 : 1.0;
+  const V3 n = (sn / cn) * cr;
+  double sgA[3], sgB[3];
+  V3 pA = cA, pB = cB;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    sgA[k] = rc_bit(code, 16 + k) ? -1.0 : 1.0;
+    sgB[k] = rc_bit(code, 19 + k) ? -1.0 : 1.0;
+    if (k != i) pA += (sgA[k] * ha[k]) * colv(RA.a, k);
+    if (k != j) pB += (sgB[k] * hb[k]) * colv(RB.a, k);
+  }
+  const V3 w = pA - pB;
+  const double b = dot(ui, uj), dd = dot(ui, w), e = dot(uj, w);
+  const double den = 1.0 - b * b;
+  const double sA = (b * e - dd) / den, tB = (e - b * dd) / den;
+  const V3 PA = pA + sA * ui, PB = pB + tB * uj;
+  // r = n.(PB - PA), p = (PA + PB)/2
+  const V3 PAb = 0.5 * pb - rb * n, PBb = 0.5 * pb + rb * n;
+  const V3 nbt = nb + rb * (PB - PA);
+  const double sAb = dot(PAb, ui), tBb = dot(PBb, uj);
+  V3 uib = sA * PAb, ujb = tB * PBb;
+  // sA = (b e - dd) / den, tB = (e - b dd) / den, den = 1 - b^2
+  const double bb = (sAb * (e + 2.0 * b * sA) + tBb * (-dd + 2.0 * b * tB)) / den;
+  const double eb = (sAb * b + tBb) / den;
+  const double ddb = -(sAb + tBb * b) / den;
+  uib += bb * uj + ddb * w;
+  ujb += bb * ui + eb * w;
+  const V3 wb = ddb * ui + eb * uj;
+  const V3 pAb = PAb + wb, pBb = PBb - wb;
+  *cAb += pAb;
+  *cBb += pBb;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (k != i) col_add(RAb, k, (sgA[k] * ha[k]) * pAb);
+    if (k != j) col_add(RBb, k, (sgB[k] * hb[k]) * pBb);
+  }
+  // n = sn c / |c|, c = u_i x u_j
+  const V3 cb = (sn / cn) * (nbt - dot(n, nbt) * n);
+  uib += cross(uj, cb);
+  ujb += cross(cb, ui);
+  col_add(RAb, i, uib);
+  col_add(RBb, j, ujb);
 }
 
 }  // namespace dmx

@@ -22,6 +22,9 @@ namespace dmx {
 
 constexpr int kStackBodies = 32;
 constexpr int kStackContacts = 256;  // contacts making rows, in pair order
+// couplings created by odd-even reduction of a block-tridiagonal matrix of
+// 32 blocks: sum over strides s = 1, 2, 4, 8, 16 of floor(31 / 2s)
+constexpr int kStackCoupled = 26;
 enum { kStOverflow = 16, kStGraph = 64 };
 
 // Per-world model: identical cubes, one plane, identical pair parameters.
@@ -90,11 +93,12 @@ struct StackLds {
   double R[kStackBodies][9];      // body rotations (body -> world)
   double P[kStackBodies][3];      // body origins
   double vec[3][kStackBodies][6]; // vectors over the bodies (world twists in the forward)
-  double cp[3][kStackContacts], cn[3][kStackContacts], cr[kStackContacts];  // contacts: point, normal, r
+  double cp[3][kStackContacts], cr[kStackContacts];  // contacts: point, r (the normal is the pair's)
   double Hd[kStackBodies][21];    // diagonal blocks (packed lower), then their Cholesky factors
-  double Ho[kStackBodies][36];    // block (i + 1, i), then L_(i+1, i)
+  double Ho[kStackBodies - 1][36];  // block (i + 1, i) (rows: body i + 1), then a reduction factor
+  double Hn[kStackCoupled][36];   // couplings created by the reduction, then its factors
   double gv[kStackBodies][6];     // block right-hand side / solution
-  double red[32];
+  int code[kStackContacts];       // contact codes (reverse sweep only)
 };
 enum { kVecX = 0, kVecV = 1, kVecD = 2 };
 
@@ -201,6 +205,15 @@ DMX_DEV double stack_softplus(double z, double beta, double* dsp) {
 }
 
 // ------------------------------------------------------------ contact rows
+// A pair lane's contacts: its slots in the pool, their common normal (the
+// plane's, or the box pair's contact axis from A toward B), active edges.
+struct PairSlots {
+  int off, cnt;     // this pair lane's contacts in the pool
+  unsigned act;     // 4 bits per contact: active edges
+  double ahat;
+  V3 n;
+};
+
 // Row data of one contact: frame, lever arms from the two bodies' origins,
 // impedance D, and the reference-acceleration parts a_n, a_t1, a_t2 with
 // aref_e = a_n +- mu a_t (edges +t1, -t1, +t2, -t2).
@@ -221,14 +234,13 @@ DMX_DEV V3 rel_vel(const StackLds& S, int vec, int b1, int b2, const CRow& c) {
   return u;
 }
 
-DMX_DEV void contact_row(const StackModel& m, const StackLds& S, int c, int b1, int b2, double ahat, bool cfd,
-                         double beta, CRow& w) {
+DMX_DEV void contact_row(const StackModel& m, const StackLds& S, const StackRole& ro, const PairSlots& ps, int j,
+                         bool cfd, double beta, CRow& w) {
+  const int c = ps.off + j, b1 = ro.pb1, b2 = ro.pb2;
+  const double ahat = ps.ahat;
   const V3 p = mk3(S.cp[0][c], S.cp[1][c], S.cp[2][c]);
-  w.n = mk3(S.cn[0][c], S.cn[1][c], S.cn[2][c]);
-  TV<double> t1, t2;
-  make_frame_t<double>(tv<double>(w.n.x, w.n.y, w.n.z), &t1, &t2);
-  w.t1 = mk3(t1.x, t1.y, t1.z);
-  w.t2 = mk3(t2.x, t2.y, t2.z);
+  w.n = ps.n;
+  make_frame(w.n, &w.t1, &w.t2);
   w.r2 = p - ld3(S.P[b2]);
   w.r1 = b1 >= 0 ? p - ld3(S.P[b1]) : mk3(0, 0, 0);
   w.r = S.cr[c];
@@ -375,118 +387,192 @@ DMX_DEV void add_grad(double* g, double sign, const double* f, const double* mo,
 }
 
 // ------------------------------------------------------------ block solve
-// In-place Cholesky of the block-tridiagonal H (diagonal blocks Hd, blocks
-// (i + 1, i) in Ho): L_00 = chol(H_00); L_(i+1,i) = H_(i+1,i) L_ii^-T;
-// L_(i+1,i+1) = chol(H_(i+1,i+1) - L_(i+1,i) L_(i+1,i)^T).  The packed
-// factors hold 1/L_jj on their diagonals.  Returns false (on every lane) if a
-// pivot is not positive.
-DMX_DEV bool block_chol(StackLds& S, int k) {
+// v <- L^-1 v and v <- L^-T v for a packed 6x6 Cholesky factor holding
+// 1/L_jj on its diagonal
+DMX_DEV void ltri_fwd(const double* L, double* v) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double s = v[j];
+#pragma unroll
+    for (int m = 0; m < j; ++m) s -= L[tri(j, m)] * v[m];
+    v[j] = s * L[tri(j, j)];
+  }
+}
+DMX_DEV void ltri_bwd(const double* L, double* v) {
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    double s = v[i];
+#pragma unroll
+    for (int m = i + 1; m < 6; ++m) s -= L[tri(m, i)] * v[m];
+    v[i] = s * L[tri(i, i)];
+  }
+}
+
+// Solve H x = g in place in S.gv for the block-tridiagonal SPD H (diagonal
+// blocks in S.Hd, couplings in S.Ho) by odd-even block cyclic reduction,
+// which is the block Cholesky factorization of H in nested-dissection order.
+// At stride s = 1, 2, 4, ... the blocks still present are the multiples of
+// s, at positions 0, 1, 2, ..; coupling j joins positions j and j + 1 (for
+// s = 1 the blocks H(i + 1, i) in S.Ho, rows of block i + 1; for s > 1 the
+// ones created at stride s / 2, stored in order in S.Hn).  The blocks at odd
+// positions p are eliminated together: with L = chol(D_p),
+// W_L = L^-1 H(p, p - 1), W_R = L^-1 H(p, p + 1) and w = L^-1 g_p, the
+// neighbours take D_(p-1) -= W_L^T W_L, D_(p+1) -= W_R^T W_R,
+// g_(p-1) -= W_L^T w, g_(p+1) -= W_R^T w, and couple through
+// H(p + 1, p - 1) = -W_R^T W_L.  Block 0 remains: x_0 = L_0^-T L_0^-1 g_0;
+// going back down the strides, x_p = L^-T (w - W_L x_(p-1) - W_R x_(p+1)).
+// The depth is log2(k) block steps, each spread over the wavefront; the
+// blocks are overwritten by the factors.  Returns false (on every lane) if
+// a pivot is not positive.
+DMX_DEV int bcr_positions(int k, int ls) { return ((k - 1) >> ls) + 1; }
+// first coupling in S.Hn of stride 2^ls (ls >= 1): those created before
+DMX_DEV int bcr_first(int k, int ls) {
+  int b = 0;
+  for (int l = 0; l + 1 < ls; ++l) b += (bcr_positions(k, l) - 1) / 2;
+  return b;
+}
+// d = sum_r X[r sx] Y[r sy]
+DMX_DEV double dot6s(const double* X, int sx, const double* Y, int sy) {
+  double d = 0.0;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) d += X[r * sx] * Y[r * sy];
+  return d;
+}
+// entry q of a packed symmetric 6x6 block: row tp, column tc
+DMX_DEV void tri_entry(int q, int* tp, int* tc) {
+  const int p = q >= 15 ? 5 : q >= 10 ? 4 : q >= 6 ? 3 : q >= 3 ? 2 : q >= 1 ? 1 : 0;
+  *tp = p;
+  *tc = q - tri(p, 0);
+}
+DMX_DEV bool block_factor_solve(StackLds& S, int k) {
   const int lane = threadIdx.x & 63;
   bool ok = true;
-  for (int b = 0; b < k; ++b) {
-    if (b > 0) {
-      // row r of L_(b, b-1) = row r of H_(b, b-1) solved against L_(b-1)^T
-      if (lane < 6) {
-        const double* L = S.Hd[b - 1];
-        double* row = &S.Ho[b - 1][6 * lane];
-        double y[6];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          double s = row[j];
-#pragma unroll
-          for (int m = 0; m < j; ++m) s -= L[tri(j, m)] * y[m];
-          y[j] = s * L[tri(j, j)];
-        }
-#pragma unroll
-        for (int j = 0; j < 6; ++j) row[j] = y[j];
-      }
-      wave_fence();
-      if (lane < 21) {
-        int i = 0;
-        while (tri(i + 1, 0) <= lane) ++i;
-        const int j = lane - tri(i, 0);
-        const double* C = S.Ho[b - 1];
-        double s = S.Hd[b][lane];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) s -= C[6 * i + m] * C[6 * j + m];
-        S.Hd[b][lane] = s;
-      }
-      wave_fence();
-    }
-    if (lane == 0) {
+  int ls = 0, made = 0;  // log2 stride; couplings created so far
+  for (; (1 << ls) < k; ++ls) {
+    const int np = bcr_positions(k, ls), ne = np / 2, nr = (np - 1) / 2;  // nr: eliminated with a right neighbour
+    double* Cp = ls == 0 ? &S.Ho[0][0] : &S.Hn[bcr_first(k, ls)][0];
+    double* Cn = &S.Hn[made][0];
+    bool okl = true;
+    if (lane < ne) {
+      double* D = S.Hd[(2 * lane + 1) << ls];
       double P[21];
 #pragma unroll
-      for (int i = 0; i < 21; ++i) P[i] = S.Hd[b][i];
-      const bool okb = chol_packed<6>(P);
+      for (int q = 0; q < 21; ++q) P[q] = D[q];
+      okl = chol_packed<6>(P);
 #pragma unroll
-      for (int i = 0; i < 21; ++i) S.Hd[b][i] = P[i];
-      S.red[0] = okb ? 1.0 : 0.0;
+      for (int q = 0; q < 21; ++q) D[q] = P[q];
+    }
+    ok = wave_all(okl) && ok;
+    wave_fence();
+    // W_L (columns, in place), W_R (stored transposed: rows, in place), w
+#pragma unroll 2
+    for (int t0 = 0; t0 < 13 * ne; t0 += 64) {
+      const int task = t0 + lane;
+      const int e = task / 13, col = task - 13 * e;
+      if (task < 13 * ne && (col < 6 || col == 12 || e < nr)) {
+        double* blk = Cp + 72 * e;
+        double* dst = col < 6 ? blk + col : col < 12 ? blk + 36 + 6 * (col - 6) : S.gv[(2 * e + 1) << ls];
+        const int stride = col < 6 ? 6 : 1;
+        double v[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) v[r] = dst[r * stride];
+        ltri_fwd(S.Hd[(2 * e + 1) << ls], v);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) dst[r * stride] = v[r];
+      }
     }
     wave_fence();
-    ok = ok && S.red[0] != 0.0;
+    // left neighbours: D -= W_L^T W_L (entries 0..20), g -= W_L^T w (21..26)
+#pragma unroll 2
+    for (int t0 = 0; t0 < 27 * ne; t0 += 64) {
+      const int task = t0 + lane;
+      const int e = task / 27, q = task - 27 * e;
+      if (task < 27 * ne) {
+        const double* WL = Cp + 72 * e;
+        const bool dq = q < 21;
+        int tp, tc;
+        tri_entry(q, &tp, &tc);
+        const double* X = WL + (dq ? tp : q - 21);
+        const double* Y = dq ? WL + tc : S.gv[(2 * e + 1) << ls];
+        double* T = dq ? &S.Hd[(2 * e) << ls][q] : &S.gv[(2 * e) << ls][q - 21];
+        *T -= dot6s(X, 6, Y, dq ? 6 : 1);
+      }
+    }
+    wave_fence();
+    // right neighbours: D -= W_R^T W_R, g -= W_R^T w; created couplings
+    // -W_R^T W_L (entries 27..62)
+#pragma unroll 2
+    for (int t0 = 0; t0 < 63 * nr; t0 += 64) {
+      const int task = t0 + lane;
+      const int e = task / 63, q = task - 63 * e;
+      if (task < 63 * nr) {
+        const double* WL = Cp + 72 * e;
+        const double* WR = WL + 36;
+        int tp, tc;
+        tri_entry(q, &tp, &tc);
+        const int pc = q - 27, pp = pc / 6, cc = pc - 6 * pp;
+        const double* X = WR + 6 * (q < 21 ? tp : q < 27 ? q - 21 : pp);
+        const double* Y = q < 21 ? WR + 6 * tc : q < 27 ? S.gv[(2 * e + 1) << ls] : WL + cc;
+        const int sy = q < 27 ? 1 : 6;
+        double* T = q < 21 ? &S.Hd[(2 * e + 2) << ls][q] : q < 27 ? &S.gv[(2 * e + 2) << ls][q - 21] : Cn + 36 * e + pc;
+        const double d = dot6s(X, 1, Y, sy);
+        *T = (q < 27 ? *T : 0.0) - d;
+      }
+    }
+    wave_fence();
+    made += nr;
+  }
+  bool ok0 = true;
+  if (lane == 0) {
+    double P[21], v[6];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) P[q] = S.Hd[0][q];
+    ok0 = chol_packed<6>(P);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) v[r] = S.gv[0][r];
+    ltri_fwd(P, v);
+    ltri_bwd(P, v);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) S.gv[0][r] = v[r];
+  }
+  ok = wave_all(ok0) && ok;
+  wave_fence();
+  for (--ls; ls >= 0; --ls) {
+    const int np = bcr_positions(k, ls), ne = np / 2;
+    const double* Cp = ls == 0 ? &S.Ho[0][0] : &S.Hn[bcr_first(k, ls)][0];
+    if (lane < ne) {
+      const int i = (2 * lane + 1) << ls;
+      const double* WL = Cp + 72 * lane;
+      const double* xl = S.gv[(2 * lane) << ls];
+      double v[6];
+#pragma unroll
+      for (int r = 0; r < 6; ++r) {
+        double d = S.gv[i][r];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) d -= WL[6 * r + c] * xl[c];
+        v[r] = d;
+      }
+      if (2 * lane + 2 < np) {
+        const double* WR = WL + 36;
+        const double* xr = S.gv[(2 * lane + 2) << ls];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          double d = v[r];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) d -= WR[6 * c + r] * xr[c];
+          v[r] = d;
+        }
+      }
+      ltri_bwd(S.Hd[i], v);
+#pragma unroll
+      for (int r = 0; r < 6; ++r) S.gv[i][r] = v[r];
+    }
     wave_fence();
   }
   return ok;
 }
 
-// Solve L L^T x = g in place in S.gv (forward then backward substitution over
-// the blocks; one lane).
-DMX_DEV void block_solve(StackLds& S, int k) {
-  if ((threadIdx.x & 63) == 0) {
-    for (int b = 0; b < k; ++b) {
-      double z[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) z[i] = S.gv[b][i];
-      if (b > 0) {
-        const double* C = S.Ho[b - 1];
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-          for (int m = 0; m < 6; ++m) z[i] -= C[6 * i + m] * S.gv[b - 1][m];
-      }
-      const double* L = S.Hd[b];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        double s = z[i];
-#pragma unroll
-        for (int m = 0; m < i; ++m) s -= L[tri(i, m)] * z[m];
-        z[i] = s * L[tri(i, i)];
-      }
-#pragma unroll
-      for (int i = 0; i < 6; ++i) S.gv[b][i] = z[i];
-    }
-    for (int b = k - 1; b >= 0; --b) {
-      double z[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) z[i] = S.gv[b][i];
-      if (b + 1 < k) {
-        const double* C = S.Ho[b];
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-          for (int m = 0; m < 6; ++m) z[i] -= C[6 * m + i] * S.gv[b + 1][m];
-      }
-      const double* L = S.Hd[b];
-#pragma unroll
-      for (int i = 5; i >= 0; --i) {
-        double s = z[i];
-#pragma unroll
-        for (int m = i + 1; m < 6; ++m) s -= L[tri(m, i)] * z[m];
-        z[i] = s * L[tri(i, i)];
-      }
-#pragma unroll
-      for (int i = 0; i < 6; ++i) S.gv[b][i] = z[i];
-    }
-  }
-  wave_fence();
-}
-
 // ------------------------------------------------------------ pair lane work
-struct PairSlots {
-  int off, cnt;     // this pair lane's contacts in the pool
-  unsigned act;     // 4 bits per contact: active edges
-  double ahat;
-};
 
 // Publish a dof vector (3 per dof lane) as world twists of the bodies:
 // lane 2b writes the linear part, lane 2b+1 R_b times the angular part.
@@ -511,7 +597,7 @@ DMX_DEV unsigned pair_activity(const StackModel& m, const StackLds& S, const Sta
   if (ro.pair) {
     for (int j = 0; j < ps.cnt; ++j) {
       CRow w;
-      contact_row(m, S, ps.off + j, ro.pb1, ro.pb2, ps.ahat, cfd, beta, w);
+      contact_row(m, S, ro, ps, j, cfd, beta, w);
       double s[4];
       edge_slack(S, vec, ro.pb1, ro.pb2, w, m.mu, s);
 #pragma unroll
@@ -521,23 +607,26 @@ DMX_DEV unsigned pair_activity(const StackModel& m, const StackLds& S, const Sta
   return act;
 }
 
-// Hessian blocks and gradient of the active set at x (in S.vec[kVecX]) into
-// S.Hd / S.Ho / S.gv, in a fixed order of phases: the plane pair of body b
-// (with M_b), then the box pairs' lower bodies, then their upper bodies; the
-// dof lanes then add M (x - a0).
-DMX_DEV void assemble(const StackModel& m, StackLds& S, const StackRole& ro, const PairSlots& ps, bool cfd,
+// The active set at x (in S.vec[kVecX]; into ps.act) and its Hessian blocks
+// and gradient into S.Hd / S.Ho / S.gv, in a fixed order of phases: the
+// plane pair of body b (with M_b), then the box pairs' lower bodies, then
+// their upper bodies; the dof lanes then add M (x - a0).
+DMX_DEV void assemble(const StackModel& m, StackLds& S, const StackRole& ro, PairSlots& ps, bool cfd,
                       double beta, const double* x, const double* a0) {
   PairSums a;
   pair_sums_zero(a);
+  ps.act = 0u;
   if (ro.pair) {
     for (int j = 0; j < ps.cnt; ++j) {
-      const unsigned act = (ps.act >> (4 * j)) & 15u;
-      if (!act) continue;
       CRow w;
-      contact_row(m, S, ps.off + j, ro.pb1, ro.pb2, ps.ahat, cfd, beta, w);
+      contact_row(m, S, ro, ps, j, cfd, beta, w);
       double s[4];
       edge_slack(S, kVecX, ro.pb1, ro.pb2, w, m.mu, s);
-      pair_sums_add(a, w, m.mu, act, s, ro.pair == 2);
+      unsigned act = 0u;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) act |= (s[e] < 0.0 ? 1u : 0u) << e;
+      ps.act |= act << (4 * j);
+      if (act) pair_sums_add(a, w, m.mu, act, s, ro.pair == 2);
     }
   }
   // phase 1: plane pair of body b (lane b) sets its diagonal block M_b + part
@@ -610,46 +699,29 @@ DMX_DEV void assemble(const StackModel& m, StackLds& S, const StackRole& ro, con
 }
 
 // ------------------------------------------------------------ collision
-// This lane's pair contacts (values), with r below the margin; for a box
-// pair its separating-axis choice.  Returns the count.
+// This lane's pair contacts (values), with r below the margin, their normal
+// and their codes if `code` is given.  Returns the count.
 DMX_DEV int pair_collide(const StackModel& m, const StackLds& S, const StackRole& ro, double margin, double* r,
-                         V3* p, V3* n) {
+                         V3* p, V3* n, int* code) {
   if (ro.pair == 1) {
     const int b = ro.pb2;
     const V3 c = ld3(S.P[b]);
     const double hgt = dot(ld3(m.pn), c - ld3(m.p0));
     if (!(hgt < m.rbound + margin)) return 0;
-    TM<double> R;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) R.a[i] = S.R[b][i];
-    double rr[4];
-    TV<double> pp[4];
-    const int cnt = box_plane_t<double>(m.h, m.p0, m.pn, tv<double>(c.x, c.y, c.z), R, margin, rr, pp);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (j < cnt) { r[j] = rr[j]; p[j] = mk3(pp[j].x, pp[j].y, pp[j].z); n[j] = ld3(m.pn); }
-    }
-    return cnt;
+    *n = ld3(m.pn);
+    return box_plane(m.h, m.p0, m.pn, c, *(const M3*)S.R[b], margin, r, p, code);
   }
   if (ro.pair == 2) {
     const int i = ro.pb1, j = ro.pb2;
     const V3 cA = ld3(S.P[i]), cB = ld3(S.P[j]);
     const V3 dc = cB - cA;
-    if (!(sqrt(dot(dc, dc)) < 2.0 * m.rbound + margin)) return 0;
-    TM<double> RA, RB;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) { RA.a[e] = S.R[i][e]; RB.a[e] = S.R[j][e]; }
+    const double reach = 2.0 * m.rbound + margin;
+    if (!(dot(dc, dc) < reach * reach)) return 0;
+    const M3& RA = *(const M3*)S.R[i];
+    const M3& RB = *(const M3*)S.R[j];
     BoxChoice ch;
-    const TV<double> a = tv<double>(cA.x, cA.y, cA.z), bb = tv<double>(cB.x, cB.y, cB.z);
-    if (!box_box_choose(m.h, m.h, a, RA, bb, RB, margin, &ch)) return 0;
-    double rr[kBoxBoxMax];
-    TV<double> pp[kBoxBoxMax], nn[kBoxBoxMax];
-    const int cnt = box_box_contacts<double>(m.h, m.h, a, RA, bb, RB, margin, ch, rr, pp, nn);
-#pragma unroll
-    for (int e = 0; e < kBoxBoxMax; ++e) {
-      if (e < cnt) { r[e] = rr[e]; p[e] = mk3(pp[e].x, pp[e].y, pp[e].z); n[e] = mk3(nn[e].x, nn[e].y, nn[e].z); }
-    }
-    return cnt;
+    if (!box_box_choose(m.h, m.h, cA, RA, cB, RB, margin, &ch)) return 0;
+    return box_box_contacts(m.h, m.h, cA, RA, cB, RB, margin, ch, r, p, n, code);
   }
   return 0;
 }
@@ -660,23 +732,17 @@ DMX_DEV bool nonneighbour_contact(const StackModel& m, const StackLds& S, double
   const int i = threadIdx.x & 63;
   bool hit = false;
   if (i + 2 < m.k) {
+    const double reach = 2.0 * m.rbound + margin;
     const V3 cA = ld3(S.P[i]);
-    TM<double> RA;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) RA.a[e] = S.R[i][e];
-    for (int j = i + 2; j < m.k; ++j) {
+    const M3& RA = *(const M3*)S.R[i];
+    for (int j = i + 2; j < m.k && !hit; ++j) {
       const V3 cB = ld3(S.P[j]);
       const V3 dc = cB - cA;
-      if (!(sqrt(dot(dc, dc)) < 2.0 * m.rbound + margin)) continue;
-      TM<double> RB;
-#pragma unroll
-      for (int e = 0; e < 9; ++e) RB.a[e] = S.R[j][e];
+      if (!(dot(dc, dc) < reach * reach)) continue;
+      const M3& RB = *(const M3*)S.R[j];
       BoxChoice ch;
-      const TV<double> a = tv<double>(cA.x, cA.y, cA.z), bb = tv<double>(cB.x, cB.y, cB.z);
-      if (!box_box_choose(m.h, m.h, a, RA, bb, RB, margin, &ch)) continue;
-      double rr[kBoxBoxMax];
-      TV<double> pp[kBoxBoxMax], nn[kBoxBoxMax];
-      if (box_box_contacts<double>(m.h, m.h, a, RA, bb, RB, margin, ch, rr, pp, nn) > 0) hit = true;
+      if (!box_box_choose(m.h, m.h, cA, RA, cB, RB, margin, &ch)) continue;
+      if (box_box_contacts(m.h, m.h, cA, RA, cB, RB, margin, ch, nullptr, nullptr, nullptr, nullptr) > 0) hit = true;
     }
   }
   return wave_any(hit);
@@ -688,7 +754,7 @@ DMX_DEV bool nonneighbour_contact(const StackModel& m, const StackLds& S, double
 // kStackContacts (the rest dropped, status bit 16).  Returns the pair lane's
 // slots.
 DMX_DEV PairSlots stack_setup(const StackModel& m, StackLds& S, const StackRole& ro, const double* yq,
-                              const double* yv, bool cfd, StackStat& st) {
+                              const double* yv, bool cfd, StackStat& st, bool codes = false) {
   if (ro.dof) {
     if (ro.half == 0) {
       S.P[ro.b][0] = yq[0]; S.P[ro.b][1] = yq[1]; S.P[ro.b][2] = yq[2];
@@ -707,8 +773,9 @@ DMX_DEV PairSlots stack_setup(const StackModel& m, StackLds& S, const StackRole&
   wave_fence();
   const double margin = cfd ? m.cf[2] : 0.0;
   double r[kBoxBoxMax];
-  V3 p[kBoxBoxMax], n[kBoxBoxMax];
-  int cnt = pair_collide(m, S, ro, margin, r, p, n);
+  V3 p[kBoxBoxMax], n = ld3(m.pn);
+  int cc[kBoxBoxMax];
+  int cnt = pair_collide(m, S, ro, margin, r, p, &n, codes ? cc : nullptr);
   if (nonneighbour_contact(m, S, margin)) st.status |= kStGraph;
   int total;
   const int off = wave_excl_scan(cnt, &total);
@@ -719,8 +786,8 @@ DMX_DEV PairSlots stack_setup(const StackModel& m, StackLds& S, const StackRole&
     if (j < keep) {
       const int c = off + j;
       S.cp[0][c] = p[j].x; S.cp[1][c] = p[j].y; S.cp[2][c] = p[j].z;
-      S.cn[0][c] = n[j].x; S.cn[1][c] = n[j].y; S.cn[2][c] = n[j].z;
       S.cr[c] = r[j];
+      if (codes) S.code[c] = cc[j];
     }
   }
   wave_fence();
@@ -729,6 +796,7 @@ DMX_DEV PairSlots stack_setup(const StackModel& m, StackLds& S, const StackRole&
   ps.cnt = keep;
   ps.act = 0u;
   ps.ahat = ro.pair == 2 ? m.ahat_box : m.ahat_plane;
+  ps.n = n;
   return ps;
 }
 
@@ -764,22 +832,20 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
 #pragma unroll
     for (int j = 0; j < 3; ++j) x[j] = xw[j];
     publish_twist(S, ro, kVecX, x);
-    ps.act = pair_activity(m, S, ro, ps, kVecX, cfd, beta);
   }
   const double Mj[2][3] = {{m.mass, m.mass, m.mass}, {m.I[0], m.I[1], m.I[2]}};
   for (int it = 0; it < maxit; ++it) {
     st.newton_it++;
     if (ro.lane == 0) st.u_nit++;
-    if (ro.pair) { st.u_nedge += __popc(ps.act); for (int j = 0; j < ps.cnt; ++j) st.u_ncon += ((ps.act >> (4 * j)) & 15u) != 0u; }
     assemble(m, S, ro, ps, cfd, beta, x, a0);
+    if (ro.pair) { st.u_nedge += __popc(ps.act); for (int j = 0; j < ps.cnt; ++j) st.u_ncon += ((ps.act >> (4 * j)) & 15u) != 0u; }
     // right-hand side -g
     if (ro.dof) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) S.gv[ro.b][3 * ro.half + j] = -S.gv[ro.b][3 * ro.half + j];
     }
     wave_fence();
-    if (!block_chol(S, m.k)) { st.status |= 4; return; }
-    block_solve(S, m.k);
+    if (!block_factor_solve(S, m.k)) { st.status |= 4; return; }
     double dl[3] = {0, 0, 0};
     if (ro.dof) {
 #pragma unroll
@@ -804,7 +870,7 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
     if (ro.pair) {
       for (int j = 0; j < ps.cnt; ++j) {
         CRow w;
-        contact_row(m, S, ps.off + j, ro.pb1, ro.pb2, ps.ahat, cfd, beta, w);
+        contact_row(m, S, ro, ps, j, cfd, beta, w);
         double s[4], t[4];
         edge_slack(S, kVecX, ro.pb1, ro.pb2, w, m.mu, s);
         edge_dir(S, kVecD, ro.pb1, ro.pb2, w, m.mu, t);
@@ -837,7 +903,7 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
       if (ro.pair) {
         for (int j = 0; j < ps.cnt; ++j) {
           CRow w;
-          contact_row(m, S, ps.off + j, ro.pb1, ro.pb2, ps.ahat, cfd, beta, w);
+          contact_row(m, S, ro, ps, j, cfd, beta, w);
           double s[4], t[4];
           edge_slack(S, kVecX, ro.pb1, ro.pb2, w, m.mu, s);
           edge_dir(S, kVecD, ro.pb1, ro.pb2, w, m.mu, t);
@@ -861,7 +927,7 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
       if (ro.pair) {
         for (int j = 0; j < ps.cnt; ++j) {
           CRow w;
-          contact_row(m, S, ps.off + j, ro.pb1, ro.pb2, ps.ahat, cfd, beta, w);
+          contact_row(m, S, ro, ps, j, cfd, beta, w);
           double s[4], t[4];
           edge_slack(S, kVecX, ro.pb1, ro.pb2, w, m.mu, s);
           edge_dir(S, kVecD, ro.pb1, ro.pb2, w, m.mu, t);
@@ -878,7 +944,6 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
 #pragma unroll
     for (int j = 0; j < 3; ++j) x[j] += al * dl[j];
     publish_twist(S, ro, kVecX, x);
-    ps.act = pair_activity(m, S, ro, ps, kVecX, cfd, beta);
   }
   st.status |= 8;
 }

@@ -9,114 +9,144 @@
 // constant in these coordinates, so the terms are the bias c = (-m g,
 // w x I w), and Phi = sum_A (J_e lambda) f_e, whose dependence on the body
 // poses runs through the contact geometry (points, normals, frames, depths,
-// impedances).  The pose derivatives of Phi are taken by dual-number passes,
-// one per pose direction of each body of a pair (translations and body-frame
-// rotations), through the same contact routine that produced the contact
-// set: its discrete choices (separating axis, faces, clipping, the top four
-// vertices) are fixed by the values, which every pass computes identically.
+// impedances) and on the velocities through aref = -b J_e v + ...  Each pair
+// lane reverses Phi over its own contacts: the partials of Phi in the edge
+// projections, depth and impedance, then the frame, the lever arms and the
+// world twists, then the contact's construction (its code) back to the two
+// body poses (centre c_b, rotation R_b).  A body-frame rotation
+// R <- R exp([theta]x) moves Phi by theta . (G21 - G12, G02 - G20, G10 - G01)
+// with G = R^T R_bar.
 #pragma once
 #include "dmx_stack_rk.hpp"
 
 namespace dmx {
 
-// Contacts of a pair at given (dual) poses.  One non-inlined instance serves
-// the value pass and every derivative pass, so the value arithmetic (and with
-// it every discrete choice) is the same in all of them.
-__device__ __noinline__ int pair_geom_dual(const StackModel& m, int pair, const TV<Dual1>* cA, const TM<Dual1>* RA,
-                                           const TV<Dual1>* cB, const TM<Dual1>* RB, double margin,
-                                           const BoxChoice* ch, Dual1* r, TV<Dual1>* p, TV<Dual1>* n) {
-  if (pair == 1) {
-    const int cnt = box_plane_t<Dual1>(m.h, m.p0, m.pn, *cB, *RB, margin, r, p);
-    for (int j = 0; j < cnt; ++j) n[j] = liftv<Dual1>(m.pn);
-    return cnt;
-  }
-  return box_box_contacts<Dual1>(m.h, m.h, *cA, *RA, *cB, *RB, margin, *ch, r, p, n);
-}
+// cotangents of one pair lane's bodies: pose (c_bar, R_bar) and generalized
+// velocity (linear, body-frame angular)
+struct PairBar {
+  V3 c1, c2;
+  double R1[9], R2[9];
+  double v1[6], v2[6];
+};
 
-DMX_DEV void load_pose_dual(const StackLds& S, int b, TV<Dual1>* c, TM<Dual1>* R) {
-  *c = tv<Dual1>(mkd(S.P[b][0]), mkd(S.P[b][1]), mkd(S.P[b][2]));
+// Reverse of Phi over contact c of this pair lane (active edges `act`) into
+// pb; S.vec[kVecD / kVecX / kVecV] hold the generalized lambda, x*, v.
+DMX_DEV void contact_phi_vjp(const StackModel& m, const StackLds& S, const StackRole& ro, const PairSlots& ps,
+                             int j, unsigned act, bool cfd, double beta, PairBar& pb) {
+  const int b1 = ro.pb1, b2 = ro.pb2, c = ps.off + j;
+  const bool two = b1 >= 0;
+  const double ahat = ps.ahat;
+  const V3 p = mk3(S.cp[0][c], S.cp[1][c], S.cp[2][c]);
+  const V3 n = ps.n;
+  const double r = S.cr[c];
+  V3 t1, t2;
+  make_frame(n, &t1, &t2);
+  const V3 c2 = ld3(S.P[b2]);
+  const V3 c1 = two ? ld3(S.P[b1]) : mk3(0.0, 0.0, 0.0);
+  const V3 r2 = p - c2, r1 = p - c1;
+  const M3& R2 = *(const M3*)S.R[b2];
+  const M3& R1 = *(const M3*)S.R[two ? b1 : b2];
+  // relative contact velocity of lambda, x*, v (index kVec*)
+  V3 om2[3], om1[3], u[3];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) R->a[i] = mkd(S.R[b][i]);
-}
-// seed direction j of a body pose: j < 3 translation e_j, else the body-frame
-// rotation R <- R exp([e_(j-3)]x), dR = R [e]x
-DMX_DEV void seed_pose(const StackLds& S, int b, int j, TV<Dual1>* c, TM<Dual1>* R) {
-  if (j < 3) {
-    if (j == 0) c->x.d = 1.0; else if (j == 1) c->y.d = 1.0; else c->z.d = 1.0;
-    return;
+  for (int g = 0; g < 3; ++g) {
+    const double* w2 = S.vec[g][b2];
+    om2[g] = mul(R2, mk3(w2[3], w2[4], w2[5]));
+    u[g] = mk3(w2[0], w2[1], w2[2]) + cross(om2[g], r2);
+    om1[g] = mk3(0.0, 0.0, 0.0);
+    if (two) {
+      const double* w1 = S.vec[g][b1];
+      om1[g] = mul(R1, mk3(w1[3], w1[4], w1[5]));
+      u[g] -= mk3(w1[0], w1[1], w1[2]) + cross(om1[g], r1);
+    }
   }
-  const int a = j - 3;
-  const double* Rv = S.R[b];
-#pragma unroll
-  for (int col = 0; col < 3; ++col) {
-    // column col of R [e_a]x is R (e_a x e_col)
-    double e[3] = {0.0, 0.0, 0.0};
-    const int c1 = (a + 1) % 3, c2 = (a + 2) % 3;
-    if (col == c1) e[c2] = 1.0;        // e_a x e_(a+1) = e_(a+2)
-    else if (col == c2) e[c1] = -1.0;  // e_a x e_(a+2) = -e_(a+1)
-#pragma unroll
-    for (int row = 0; row < 3; ++row)
-      R->a[3 * row + col].d = Rv[3 * row] * e[0] + Rv[3 * row + 1] * e[1] + Rv[3 * row + 2] * e[2];
-  }
-}
-
-// velocity at a contact of body b for a generalized vector (linear part,
-// body-frame angular part) given the body's (dual) rotation and lever arm
-DMX_DEV TV<Dual1> gen_vel(const double* w, const TM<Dual1>& R, const TV<Dual1>& rb) {
-  const TV<Dual1> om = tmul(R, tv<Dual1>(mkd(w[3]), mkd(w[4]), mkd(w[5])));
-  return tv<Dual1>(mkd(w[0]), mkd(w[1]), mkd(w[2])) + tcross(om, rb);
-}
-
-DMX_DEV Dual1 imp_dual(const StackModel& m, Dual1 r) {
   double ddr;
-  const double d = stack_imp(m, r.v, &ddr);
-  return mkd(d, ddr * r.d);
-}
-DMX_DEV Dual1 softplus_dual(Dual1 z, double beta) {
-  double dsp;
-  const double s = stack_softplus(z.v, beta, &dsp);
-  return mkd(s, dsp * z.d);
-}
-
-// Phi of a pair's contacts (edges active per `act`, 4 bits per contact) for
-// the generalized vectors lam, xs, v of the two bodies (S.vec[kVecD/X/V]).
-DMX_DEV Dual1 pair_phi(const StackModel& m, const StackLds& S, int b1, int b2, double ahat, bool cfd, double beta,
-                       int cnt, unsigned act, const Dual1* r, const TV<Dual1>* p, const TV<Dual1>* n,
-                       const TV<Dual1>& c1, const TM<Dual1>& R1, const TV<Dual1>& c2, const TM<Dual1>& R2) {
-  Dual1 phi = mkd(0.0);
-  for (int j = 0; j < cnt; ++j) {
-    const unsigned a = (act >> (4 * j)) & 15u;
-    if (!a) continue;
-    TV<Dual1> t1, t2;
-    make_frame_t<Dual1>(n[j], &t1, &t2);
-    const TV<Dual1> r2 = p[j] - c2;
-    TV<Dual1> ul = gen_vel(S.vec[kVecD][b2], R2, r2), ux = gen_vel(S.vec[kVecX][b2], R2, r2),
-              uv = gen_vel(S.vec[kVecV][b2], R2, r2);
-    if (b1 >= 0) {
-      const TV<Dual1> r1 = p[j] - c1;
-      ul = ul - gen_vel(S.vec[kVecD][b1], R1, r1);
-      ux = ux - gen_vel(S.vec[kVecX][b1], R1, r1);
-      uv = uv - gen_vel(S.vec[kVecV][b1], R1, r1);
-    }
-    const Dual1 d = imp_dual(m, r[j]);
-    const Dual1 D = d / (ahat * (1.0 - d));
-    const Dual1 kk = d * m.kscale;
-    const Dual1 pterm = cfd ? kk * softplus_dual(mkd(0.0) - r[j], beta) : mkd(0.0) - kk * r[j];
-    const Dual1 ln = tdot(n[j], ul), l1 = tdot(t1, ul), l2 = tdot(t2, ul);
-    const Dual1 xn = tdot(n[j], ux), x1 = tdot(t1, ux), x2 = tdot(t2, ux);
-    const Dual1 vn = tdot(n[j], uv), v1 = tdot(t1, uv), v2 = tdot(t2, uv);
+  const double d = stack_imp(m, r, &ddr);
+  const double D = d / (ahat * (1.0 - d));
+  const double dDdd = 1.0 / (ahat * (1.0 - d) * (1.0 - d));
+  double pterm, dpdr;
+  if (cfd) {
+    double dsp;
+    const double sp = stack_softplus(-r, beta, &dsp);
+    pterm = d * m.kscale * sp;
+    dpdr = m.kscale * (ddr * sp - d * dsp);
+  } else {
+    pterm = -d * m.kscale * r;
+    dpdr = -m.kscale * (ddr * r + d);
+  }
+  V3 ub[3] = {mk3(0.0, 0.0, 0.0), mk3(0.0, 0.0, 0.0), mk3(0.0, 0.0, 0.0)};
+  V3 nb = mk3(0.0, 0.0, 0.0), t1b = mk3(0.0, 0.0, 0.0), t2b = mk3(0.0, 0.0, 0.0);
+  double Pbar = 0.0, Dbar = 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (!((a >> e) & 1u)) continue;
-      const double sg = (e & 1) ? -m.mu : m.mu;
-      const Dual1 le = ln + sg * (e < 2 ? l1 : l2);
-      const Dual1 xe = xn + sg * (e < 2 ? x1 : x2);
-      const Dual1 ve = vn + sg * (e < 2 ? v1 : v2);
-      const Dual1 aref = pterm - m.bcoef * ve;
-      phi += le * (D * (aref - xe));
+  for (int e = 0; e < 4; ++e) {
+    if (!((act >> e) & 1u)) continue;
+    const double sg = (e & 1) ? -m.mu : m.mu;
+    const V3 de = n + sg * (e < 2 ? t1 : t2);
+    const double L = dot(de, u[kVecD]), X = dot(de, u[kVecX]), Vv = dot(de, u[kVecV]);
+    const double res = pterm - m.bcoef * Vv - X;  // aref_e - J_e x*
+    const double Lb = D * res, Xb = -D * L, Vb = -m.bcoef * D * L;
+    Pbar += D * L;
+    Dbar += L * res;
+    ub[kVecD] += Lb * de;
+    ub[kVecX] += Xb * de;
+    ub[kVecV] += Vb * de;
+    const V3 deb = Lb * u[kVecD] + Xb * u[kVecX] + Vb * u[kVecV];
+    nb += deb;
+    if (e < 2) t1b += sg * deb; else t2b += sg * deb;
+  }
+  const double rb = Pbar * dpdr + Dbar * dDdd * ddr;
+  nb += make_frame_vjp(n, t1b, t2b);
+  // u_g = v_g2 + om_g2 x r2 - (v_g1 + om_g1 x r1), om_gb = R_b w_gb
+  V3 r2b = mk3(0.0, 0.0, 0.0), r1b = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    r2b += cross(ub[g], om2[g]);
+    const V3 o2 = cross(r2, ub[g]);
+    const double* w2 = S.vec[g][b2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double oi = i == 0 ? o2.x : (i == 1 ? o2.y : o2.z);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) pb.R2[3 * i + j] += oi * w2[3 + j];
+    }
+    if (two) {
+      r1b -= cross(ub[g], om1[g]);
+      const V3 o1 = cross(r1, ub[g]);
+      const double* w1 = S.vec[g][b1];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double oi = i == 0 ? o1.x : (i == 1 ? o1.y : o1.z);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pb.R1[3 * i + j] -= oi * w1[3 + j];
+      }
     }
   }
-  return phi;
+  // velocity cotangents: the generalized v enters through u_V only
+  {
+    const V3 f = ub[kVecV];
+    const V3 m2 = mulT(R2, cross(r2, f));
+    pb.v2[0] += f.x; pb.v2[1] += f.y; pb.v2[2] += f.z; pb.v2[3] += m2.x; pb.v2[4] += m2.y; pb.v2[5] += m2.z;
+    if (two) {
+      const V3 m1 = mulT(R1, cross(r1, f));
+      pb.v1[0] -= f.x; pb.v1[1] -= f.y; pb.v1[2] -= f.z; pb.v1[3] -= m1.x; pb.v1[4] -= m1.y; pb.v1[5] -= m1.z;
+    }
+  }
+  // r_b = p - c_b
+  const V3 pbar = r2b + r1b;
+  pb.c2 -= r2b;
+  if (two) pb.c1 -= r1b;
+  if (two) box_box_vjp(m.h, m.h, c1, R1, c2, R2, S.code[c], rb, pbar, nb, &pb.c1, pb.R1, &pb.c2, pb.R2);
+  else box_plane_vjp(m.h, m.p0, m.pn, c2, R2, S.code[c], rb, pbar, &pb.c2, pb.R2);
+}
+
+// pose cotangent (translation, body-frame rotation) from c_bar and R_bar
+DMX_DEV void pose_bar(const double* R, V3 cb, const double* Rb, double* out) {
+  double G[9];
+  m3_RtA(R, Rb, G);
+  out[0] = cb.x; out[1] = cb.y; out[2] = cb.z;
+  out[3] = G[7] - G[5];
+  out[4] = G[2] - G[6];
+  out[5] = G[3] - G[1];
 }
 
 // VJP of the acceleration map at this lane's stage state (yq, yv) with the
@@ -126,66 +156,7 @@ DMX_DEV Dual1 pair_phi(const StackModel& m, const StackLds& S, int b1, int b2, d
 DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro, const double* yq,
                            const double* yv, const double* tau, const double* xs_in, const double* ab, bool cfd,
                            double beta, int maxit, double* qb, double* vb, double* tb, StackStat& st) {
-  // frames and velocity twists
-  if (ro.dof) {
-    if (ro.half == 0) {
-      S.P[ro.b][0] = yq[0]; S.P[ro.b][1] = yq[1]; S.P[ro.b][2] = yq[2];
-      double* t = S.vec[kVecV][ro.b];
-      t[0] = yv[0]; t[1] = yv[1]; t[2] = yv[2];
-    } else {
-      const Q4 qh = qnormalize(mkq(yq[0], yq[1], yq[2], yq[3]), nullptr);
-      const M3 R = quat2mat(qh);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) S.R[ro.b][i] = R.a[i];
-      const V3 w = mul(R, mk3(yv[0], yv[1], yv[2]));
-      double* t = S.vec[kVecV][ro.b] + 3;
-      t[0] = w.x; t[1] = w.y; t[2] = w.z;
-    }
-  }
-  wave_fence();
-  // value pass of the pair's contacts (the dual routine with zero seeds)
-  const double margin = cfd ? m.cf[2] : 0.0;
-  BoxChoice ch{-1, 0};
-  bool near = false;
-  TV<Dual1> cA, cB;
-  TM<Dual1> RA, RB;
-  int cnt = 0;
-  Dual1 r[kBoxBoxMax];
-  TV<Dual1> p[kBoxBoxMax], n[kBoxBoxMax];
-  if (ro.pair) {
-    load_pose_dual(S, ro.pb2, &cB, &RB);
-    if (ro.pair == 1) {
-      near = dot(ld3(m.pn), ld3(S.P[ro.pb2]) - ld3(m.p0)) < m.rbound + margin;
-    } else {
-      load_pose_dual(S, ro.pb1, &cA, &RA);
-      const V3 dc = ld3(S.P[ro.pb2]) - ld3(S.P[ro.pb1]);
-      near = sqrt(dot(dc, dc)) < 2.0 * m.rbound + margin;
-      if (near) {
-        TM<double> Ra, Rb;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) { Ra.a[i] = S.R[ro.pb1][i]; Rb.a[i] = S.R[ro.pb2][i]; }
-        near = box_box_choose(m.h, m.h, tv<double>(S.P[ro.pb1][0], S.P[ro.pb1][1], S.P[ro.pb1][2]), Ra,
-                              tv<double>(S.P[ro.pb2][0], S.P[ro.pb2][1], S.P[ro.pb2][2]), Rb, margin, &ch);
-      }
-    }
-    if (near) cnt = pair_geom_dual(m, ro.pair, &cA, &RA, &cB, &RB, margin, &ch, r, p, n);
-  }
-  if (nonneighbour_contact(m, S, margin)) st.status |= kStGraph;
-  int total;
-  const int off = wave_excl_scan(cnt, &total);
-  const int keep = max(0, min(cnt, kStackContacts - off));
-  for (int j = 0; j < keep; ++j) {
-    const int c = off + j;
-    S.cp[0][c] = p[j].x.v; S.cp[1][c] = p[j].y.v; S.cp[2][c] = p[j].z.v;
-    S.cn[0][c] = n[j].x.v; S.cn[1][c] = n[j].y.v; S.cn[2][c] = n[j].z.v;
-    S.cr[c] = r[j].v;
-  }
-  wave_fence();
-  PairSlots ps;
-  ps.off = off;
-  ps.cnt = keep;
-  ps.act = 0u;
-  ps.ahat = ro.pair == 2 ? m.ahat_box : m.ahat_plane;
+  PairSlots ps = stack_setup(m, S, ro, yq, yv, cfd, st, true);
   double a0[3], xs[3];
   stack_a0(m, ro, yv, tau, a0);
   if (cfd) {
@@ -196,17 +167,15 @@ DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro
   }
   // active set at x* and the Hessian there
   publish_twist(S, ro, kVecX, xs);
-  ps.act = pair_activity(m, S, ro, ps, kVecX, cfd, beta);
+  assemble(m, S, ro, ps, cfd, beta, xs, a0);
   if (ro.lane == 0) st.u_vjp++;
   if (ro.pair) { st.u_vedge += __popc(ps.act); for (int j = 0; j < ps.cnt; ++j) st.u_vcon += ((ps.act >> (4 * j)) & 15u) != 0u; }
-  assemble(m, S, ro, ps, cfd, beta, xs, a0);
   if (ro.dof) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) S.gv[ro.b][3 * ro.half + j] = ab[j];
   }
   wave_fence();
-  if (!block_chol(S, m.k)) st.status |= 4;
-  block_solve(S, m.k);
+  if (!block_factor_solve(S, m.k)) st.status |= 4;
   double lam[3] = {0.0, 0.0, 0.0};
   if (ro.dof) {
 #pragma unroll
@@ -223,81 +192,39 @@ DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro
     }
   }
   wave_fence();
-  // pair lanes: pose cotangents of their bodies (dual passes) and velocity
-  // cotangents (Phi is linear in v through aref = -b J v + ...)
-  double pose1[6] = {0, 0, 0, 0, 0, 0}, pose2[6] = {0, 0, 0, 0, 0, 0};
-  double vel1[6] = {0, 0, 0, 0, 0, 0}, vel2[6] = {0, 0, 0, 0, 0, 0};
-  if (ro.pair && ps.cnt > 0 && ps.act != 0u) {
-    const int nb = ro.pair == 2 ? 2 : 1;
-#pragma unroll 1
-    for (int pass = 0; pass < 6 * nb; ++pass) {
-      const int body = pass < 6 ? ro.pb2 : ro.pb1;
-      const int dir = pass % 6;
-      TV<Dual1> sA = cA, sB = cB;
-      TM<Dual1> tA = RA, tB = RB;
-      if (body == ro.pb2) seed_pose(S, body, dir, &sB, &tB);
-      else seed_pose(S, body, dir, &sA, &tA);
-      Dual1 rr[kBoxBoxMax];
-      TV<Dual1> pp[kBoxBoxMax], nn[kBoxBoxMax];
-      const int c2 = pair_geom_dual(m, ro.pair, &sA, &tA, &sB, &tB, margin, &ch, rr, pp, nn);
-      const int use = min(c2, ps.cnt);
-      const Dual1 phi = pair_phi(m, S, ro.pb1, ro.pb2, ps.ahat, cfd, beta, use, ps.act, rr, pp, nn, sA, tA, sB, tB);
-      if (body == ro.pb2) pose2[dir] = phi.d; else pose1[dir] = phi.d;
-    }
-    // d Phi / d v = sum_A (J_e lambda) D (-b) J_e^T
+  // pair lanes: Phi reversed over their contacts
+  PairBar pb;
+  pb.c1 = mk3(0.0, 0.0, 0.0);
+  pb.c2 = mk3(0.0, 0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { pb.R1[i] = 0.0; pb.R2[i] = 0.0; }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) { pb.v1[i] = 0.0; pb.v2[i] = 0.0; }
+  if (ro.pair) {
     for (int j = 0; j < ps.cnt; ++j) {
       const unsigned a = (ps.act >> (4 * j)) & 15u;
-      if (!a) continue;
-      CRow w;
-      const V3 pc = mk3(S.cp[0][ps.off + j], S.cp[1][ps.off + j], S.cp[2][ps.off + j]);
-      w.n = mk3(S.cn[0][ps.off + j], S.cn[1][ps.off + j], S.cn[2][ps.off + j]);
-      TV<double> t1, t2;
-      make_frame_t<double>(tv<double>(w.n.x, w.n.y, w.n.z), &t1, &t2);
-      w.t1 = mk3(t1.x, t1.y, t1.z);
-      w.t2 = mk3(t2.x, t2.y, t2.z);
-      w.r2 = pc - ld3(S.P[ro.pb2]);
-      w.r1 = ro.pb1 >= 0 ? pc - ld3(S.P[ro.pb1]) : mk3(0, 0, 0);
-      double ddr;
-      const double d = stack_imp(m, S.cr[ps.off + j], &ddr);
-      const double D = d / (ps.ahat * (1.0 - d));
-      // J_d lambda from the body twists of lambda
-      auto twist = [&](int b, V3 rb) {
-        const double* g = S.vec[kVecD][b];
-        const V3 om = mul(*(const M3*)S.R[b], mk3(g[3], g[4], g[5]));
-        return mk3(g[0], g[1], g[2]) + cross(om, rb);
-      };
-      V3 ul = twist(ro.pb2, w.r2);
-      if (ro.pb1 >= 0) ul -= twist(ro.pb1, w.r1);
-      V3 fv = mk3(0, 0, 0);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!((a >> e) & 1u)) continue;
-        const V3 de = edge_vec(w, m.mu, e);
-        fv += (-m.bcoef * D * dot(de, ul)) * de;
-      }
-      const V3 m2 = mulT(*(const M3*)S.R[ro.pb2], cross(w.r2, fv));
-      vel2[0] += fv.x; vel2[1] += fv.y; vel2[2] += fv.z; vel2[3] += m2.x; vel2[4] += m2.y; vel2[5] += m2.z;
-      if (ro.pb1 >= 0) {
-        const V3 m1 = mulT(*(const M3*)S.R[ro.pb1], cross(w.r1, fv));
-        vel1[0] -= fv.x; vel1[1] -= fv.y; vel1[2] -= fv.z; vel1[3] -= m1.x; vel1[4] -= m1.y; vel1[5] -= m1.z;
-      }
+      if (a) contact_phi_vjp(m, S, ro, ps, j, a, cfd, beta, pb);
     }
   }
-  // gather per body in a fixed order: plane pair, lower-body share of the box
-  // pair above... (S.gv: pose cotangent, S.Ho[b][0..5]: velocity cotangent)
+  double pose1[6] = {0, 0, 0, 0, 0, 0}, pose2[6] = {0, 0, 0, 0, 0, 0};
+  if (ro.pair) pose_bar(S.R[ro.pb2], pb.c2, pb.R2, pose2);
+  if (ro.pair == 2) pose_bar(S.R[ro.pb1], pb.c1, pb.R1, pose1);
+  // gather per body in a fixed order: plane pair, then the body's share of
+  // the box pair above it, then of the box pair below it (S.gv: pose
+  // cotangent, S.Hd[b][0..5]: velocity cotangent)
   if (ro.pair == 1) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { S.gv[ro.pb2][i] = pose2[i]; S.Ho[ro.pb2][i] = vel2[i]; }
+    for (int i = 0; i < 6; ++i) { S.gv[ro.pb2][i] = pose2[i]; S.Hd[ro.pb2][i] = pb.v2[i]; }
   }
   wave_fence();
   if (ro.pair == 2) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { S.gv[ro.pb1][i] += pose1[i]; S.Ho[ro.pb1][i] += vel1[i]; }
+    for (int i = 0; i < 6; ++i) { S.gv[ro.pb1][i] += pose1[i]; S.Hd[ro.pb1][i] += pb.v1[i]; }
   }
   wave_fence();
   if (ro.pair == 2) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { S.gv[ro.pb2][i] += pose2[i]; S.Ho[ro.pb2][i] += vel2[i]; }
+    for (int i = 0; i < 6; ++i) { S.gv[ro.pb2][i] += pose2[i]; S.Hd[ro.pb2][i] += pb.v2[i]; }
   }
   wave_fence();
 #pragma unroll
@@ -306,7 +233,7 @@ DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro
   for (int j = 0; j < 3; ++j) { vb[j] = 0.0; tb[j] = 0.0; }
   if (ro.dof) {
     const double* pg = S.gv[ro.b];
-    const double* vg = S.Ho[ro.b];
+    const double* vg = S.Hd[ro.b];
     if (ro.half == 0) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) { qb[j] = pg[j]; vb[j] = vg[j]; }

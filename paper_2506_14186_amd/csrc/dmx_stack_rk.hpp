@@ -174,9 +174,11 @@ DMX_DEV void stack_fwd_world(const StackModel& m, StackLds& S, const StackArgs& 
           for (int j = 0; j < 3; ++j) A[l][j] = (l == i) ? ai[j] : A[l][j];
         if (i == 0) {
           have_k1 = true;
-          if (st.status & 12 & fatal_bits) { fatal = true; break; }
+          if (st.status & (12 | kStGraph)) { fatal = true; break; }
         }
-        if (st.status & kStGraph) { fatal = true; break; }
+        // a trial stage that the solver cannot take (non-neighbour contact)
+        // fails like a failed solve: the attempt is rejected (below)
+        if (st.status & kStGraph) break;
       }
       if (fatal) break;
       // error estimate: v: h sum e_i a_i; position: h^2 sum (e a)_i a_i;
@@ -217,7 +219,7 @@ DMX_DEV void stack_fwd_world(const StackModel& m, StackLds& S, const StackArgs& 
       double e2[1] = {acc2};
       wave_sum<1>(e2);
       double err = sqrt(e2[0] / NX);
-      if ((st.status & 12) && !a.forced) {
+      if ((st.status & (12 | kStGraph)) && !a.forced) {
         st.status = status_before;
         err = __longlong_as_double(0x7ff0000000000000ll);
       }
@@ -262,7 +264,7 @@ DMX_DEV void stack_fwd_world(const StackModel& m, StackLds& S, const StackArgs& 
         ++nrej;
       }
       if (!a.forced && hprop < 1e-12 * fmax(1.0, fabs(t))) { st.status |= 2; break; }
-      if (st.status & 12) break;
+      if (st.status & (12 | kStGraph)) break;
     }
   }
   store_state(m, ro, a.xout + st_xoff(a, w), yq, yv);

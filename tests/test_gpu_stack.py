@@ -6,8 +6,10 @@ ten times the oracle's own change under 4-ulp state perturbations, where the
 contact detection is ill-conditioned: top-four vertex ties of the plane-box
 rule, clipping points on a side plane); a GPU step fed the oracle's state and
 step 1e-10; free runs checked through the oracle replay of the GPU's accepted
-steps: end state 1e-6, gradient 1e-5 normwise and element by element; worlds
-of different sizes in one launch bitwise equal to separate launches.
+steps: end state 1e-6 (or ten times the oracle's own change under 4-ulp
+perturbations of the start state, for stacks settling on stiff contacts),
+gradient 1e-5 normwise and element by element; worlds of different sizes in
+one launch bitwise equal to separate launches.
 """
 import numpy as np
 import pytest
@@ -172,7 +174,16 @@ def _free_and_replay(D, oracle, descs, xs, horizon, xbar_fn):
         es = rel_state(xg[xo[w]:xo[w] + nx], ref["x"][0], 7 * k)[0]
         eg = rel_grad(gg[xo[w]:xo[w] + nx], ref["x0bar"][0])[0]
         ee = elementwise_grad(gg[xo[w]:xo[w] + nx], ref["x0bar"][0])[0]
-        return (k, int(n[w]), es, eg, ee)
+        # the oracle's own replay under 4-ulp perturbations of the start state:
+        # near rest the velocities are tiny and the steps sit at the stiff
+        # contacts' stability limit, so rounding of the contact forces shows
+        rng = np.random.default_rng(17 + w)
+        sens = 0.0
+        for _ in range(2):
+            xp = x * (1.0 + 4.4e-16 * rng.choice([-1.0, 1.0], size=x.shape))
+            xr = om.rollout(xp, None, 1, horizon, forced=forced[:n[w]])["x"]
+            sens = max(sens, rel_state(xr, ref["x"][0], 7 * k)[0])
+        return (k, int(n[w]), es, eg, ee, sens)
 
     from concurrent.futures import ThreadPoolExecutor
     with ThreadPoolExecutor(max_workers=8) as ex:  # the oracle releases the interpreter lock
@@ -202,9 +213,11 @@ def test_stack_free_runs_replayed(D, oracle):
     descs.append(W.model_stack(4, tc=0.0015))
     xs.append(_stacked(4, 7))
     out, _ = _free_and_replay(D, oracle, descs, xs, 0.5, _sum_positions)
-    for k, n, es, eg, ee in out:
-        print(f"k={k}: {n} accepted steps, state {es:.2e}, gradient {eg:.2e} (element-wise {ee:.2e})")
-    assert max(o[2] for o in out) <= STATE_TOL
+    for k, n, es, eg, ee, sens in out:
+        print(f"k={k}: {n} accepted steps, state {es:.2e} (oracle's 4-ulp sensitivity {sens:.1e}), "
+              f"gradient {eg:.2e} (element-wise {ee:.2e})")
+    # end state: 1e-6, or ten times the oracle's own 4-ulp sensitivity
+    assert all(o[2] <= max(STATE_TOL, 10.0 * o[5]) for o in out)
     assert max(o[3] for o in out) <= GRAD_TOL and max(o[4] for o in out) <= GRAD_TOL
 
 
