@@ -176,13 +176,21 @@ def timed_steps(step, steps, warmup, stream):
     """W untimed warm-up steps, then K timed steps between synchronizations;
     per-step forward/reverse times from events on the library's stream."""
     import torch
-    for _ in range(warmup):
+    for i in range(warmup):
         step(None)
+        torch.cuda.synchronize()
+        print(f"bench:   warm-up step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         step(evs[k])
+        if steps > 1:
+            # progress after each step: the event of the step before it
+            # completes without draining the queue of this one
+            if k > 0:
+                evs[k - 1][2].synchronize()
+                print(f"bench:   timed step {k}/{steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
@@ -214,20 +222,22 @@ def stack_leg(D, W, args, dev):
     xbar = torch.tensor(xb, dtype=torch.float64, device=dev)
     fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
     adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
-    copts = D.default_opts(tape_steps=args.stack_tape, fwd_counters=fwd_cnt.data_ptr(),
-                           adj_counters=adj_cnt.data_ptr())
+    copts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts,
+                           fwd_counters=fwd_cnt.data_ptr(), adj_counters=adj_cnt.data_ptr())
     r = D.rollout_batch(models, x0, None, 1, T, opts=copts, tape=True, counters=True)
     tape = r["tape"]
     D.rollout_batch_vjp(tape, xbar)
     torch.cuda.synchronize()
+    print("bench:   counted pass done", file=sys.stderr, flush=True)
     status = r["status"].cpu().numpy()
     n_acc = r["n_acc"].cpu().numpy()
     n_att = n_acc + r["n_rej"].cpu().numpy()
     fu, au = stack_units(fwd_cnt.cpu().numpy(), adj_cnt.cpu().numpy(), ks)
     fwd_flops = algorithmic_flops(fu, STACK_FWD_FLOPS, 0)
     adj_flops = algorithmic_flops(au, STACK_ADJ_FLOPS, 0)
-    opts = D.default_opts(tape_steps=args.stack_tape)
+    opts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts)
     stream = torch.cuda.current_stream()
+    failed = (status & ~D.STATUS["CONTACT_OVERFLOW"]) != 0
 
     def step(ev):
         if ev:
@@ -240,14 +250,18 @@ def stack_leg(D, W, args, dev):
             ev[2].record(stream)
 
     ms, fwd_ms, adj_ms = timed_steps(step, args.steps, args.warmup, stream)
-    value = float(nW * T / (ms / 1e3))
+    # only worlds that reach the horizon count as simulated time
+    value = float((nW - int(failed.sum())) * T / (ms / 1e3))
     out = {"value": value, "ms_per_step": ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms, "worlds": nW, "horizon": T,
            "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
                                    "hbm_traffic_stacks_1024.md"),
            "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
                     "accepted_steps_max": int(n_acc.max()), "attempts_max": int(n_att.max()),
                     "cubes_mean": float(ks.mean()), "cubes_total": int(ks.sum()),
-                    "failed_worlds": int(((status & ~D.STATUS["CONTACT_OVERFLOW"]) != 0).sum()),
+                    "failed_worlds": int(failed.sum()),
+                    "failed_world_status": {int(w): int(status[w]) for w in np.nonzero(failed)[0][:16]},
+                    "failed_world_attempts": {int(w): int(n_att[w]) for w in np.nonzero(failed)[0][:16]},
+                    "max_attempts_per_world": args.max_attempts,
                     "overflow_worlds": int(((status & D.STATUS["CONTACT_OVERFLOW"]) != 0).sum()),
                     "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}}
     if not args.no_plain:
@@ -258,7 +272,7 @@ def stack_leg(D, W, args, dev):
         px = torch.tensor(np.concatenate([cfg["x0"][w] for w in sel]), dtype=torch.float64, device=dev)
         pxb = torch.tensor(np.concatenate([xb[int(sum(13 * ks[:w])):int(sum(13 * ks[:w + 1]))] for w in sel]),
                            dtype=torch.float64, device=dev)
-        popts = D.default_opts(tape_steps=args.stack_tape, launch_mode=1)
+        popts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts, launch_mode=1)
         rp = D.rollout_batch(pm, px, None, 1, T, opts=popts, tape=True)
         D.rollout_batch_vjp(rp["tape"], pxb)
         torch.cuda.synchronize()
@@ -281,14 +295,15 @@ def stack_leg(D, W, args, dev):
 def stack_cpu_baseline(cfg, budget_s):
     """The oracle (forward plus forward-mode gradient of the same loss) on
     a bounded sample of the stack batch: worlds in a seeded random order, the
-    first 0.02 s of each, on the host's threads, until the time budget is
-    spent; the rate is simulated seconds per wall second."""
+    first 2 ms of each, on the host's threads, until the time budget is spent
+    (worlds in flight then finish); the rate is simulated seconds per wall
+    second."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     nthreads = min(16, os.cpu_count() or 1)
     rng = np.random.default_rng(17)
     order = rng.permutation(len(cfg["models"]))
-    T = 0.02
+    T = 0.002
     done, sim, ks = [], 0.0, []
     t0 = time.perf_counter()
 
@@ -441,6 +456,8 @@ def main():
     ap.add_argument("--kmax", type=int, default=32)
     ap.add_argument("--stack-horizon", type=float, default=1.0)
     ap.add_argument("--stack-tape", type=int, default=4096)
+    ap.add_argument("--max-attempts", type=int, default=4096,
+                    help="step attempts per world before it stops with status 1")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the cube and sphere legs")
     ap.add_argument("--plain-worlds", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -157,36 +157,48 @@ constexpr int kBoxBoxMax = 8;
 // Separating-axis test over the 15 axes: the overlap of the projections on a
 // unit axis L is o(L) = sum a_i |L.u_i| + sum b_j |L.w_j| - |L.(cB - cA)|
 // (u, w the box axes, a, b the half sizes); the contact axis is the face axis
-// of least overlap unless the least edge overlap (cross products shorter
+// of least overlap unless the least edge overlap (axes u_i x w_j shorter
 // than 1e-6 skipped) is smaller by more than 5% of its magnitude plus 1e-6.
 // Returns false if the boxes are apart by at least `margin` along some axis.
+// Evaluated in the boxes' frames: with C_ij = u_i.w_j, dA = (u_i.d),
+// dB = (w_j.d), a face axis u_i has o = a_i + sum_j b_j |C_ij| - |dA_i|; the
+// edge axis u_i x w_j has length s = sqrt(1 - C_ij^2) and
+// s o = a_(i+1) |C_(i+2)j| + a_(i+2) |C_(i+1)j| + b_(j+1) |C_i(j+2)|
+//       + b_(j+2) |C_i(j+1)| - |dA_(i+2) C_(i+1)j - dA_(i+1) C_(i+2)j|.
 DMX_DEV bool box_box_choose(const double* ha, const double* hb, V3 cA, const M3& RA, V3 cB, const M3& RB,
                             double margin, BoxChoice* ch) {
-  V3 uA[3], uB[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) { uA[i] = colv(RA.a, i); uB[i] = colv(RB.a, i); }
+  double C[3][3], dA[3], dB[3];
   const V3 d = cB - cA;
-  auto overlap = [&](V3 L) {
-    double pa = 0.0, pb = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { pa += fabs(dot(L, uA[i])) * ha[i]; pb += fabs(dot(L, uB[i])) * hb[i]; }
-    return pa + pb - fabs(dot(L, d));
-  };
+  for (int i = 0; i < 3; ++i) {
+    const V3 u = colv(RA.a, i), w = colv(RB.a, i);
+    dA[i] = dot(u, d);
+    dB[i] = dot(w, d);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[i][j] = dot(u, colv(RB.a, j));
+  }
   int face = 0, edge = -1;
   double of = 1e300, oe = 1e300;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const double o = overlap(i < 3 ? uA[i] : uB[i - 3]);
+  for (int i = 0; i < 3; ++i) {
+    const double o = ha[i] + hb[0] * fabs(C[i][0]) + hb[1] * fabs(C[i][1]) + hb[2] * fabs(C[i][2]) - fabs(dA[i]);
     if (o < of) { of = o; face = i; }
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double o = hb[j] + ha[0] * fabs(C[0][j]) + ha[1] * fabs(C[1][j]) + ha[2] * fabs(C[2][j]) - fabs(dB[j]);
+    if (o < of) { of = o; face = 3 + j; }
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const V3 c = cross(uA[i], uB[j]);
-      const double cn = sqrt(dot(c, c));
-      if (cn < 1e-6) continue;
-      const double o = overlap((1.0 / cn) * c);
+      const double s2 = 1.0 - C[i][j] * C[i][j];
+      if (!(s2 >= 1e-12)) continue;
+      const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+      const double so = ha[i1] * fabs(C[i2][j]) + ha[i2] * fabs(C[i1][j]) + hb[j1] * fabs(C[i][j2]) +
+                        hb[j2] * fabs(C[i][j1]) - fabs(dA[i2] * C[i1][j] - dA[i1] * C[i2][j]);
+      const double o = so * rsqrt_nr(s2);
       if (o < oe) { oe = o; edge = 3 * i + j; }
     }
   const bool use_edge = edge >= 0 && oe < of - (0.05 * fabs(of) + 1e-6);

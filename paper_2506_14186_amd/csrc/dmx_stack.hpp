@@ -14,6 +14,8 @@
 // H = M + sum_e D_e J_e^T J_e is then block tridiagonal over the bodies, and
 // its Cholesky factor has the same pattern (no fill).
 #pragma once
+#include <cstddef>
+
 #include "dmx_free.hpp"
 #include "dmx_geom.hpp"
 #include "dmx_rk.hpp"
@@ -446,77 +448,82 @@ DMX_DEV void tri_entry(int q, int* tp, int* tc) {
 }
 DMX_DEV bool block_factor_solve(StackLds& S, int k) {
   const int lane = threadIdx.x & 63;
+  // offsets below are in doubles from the start of the LDS block
+  double* const base = reinterpret_cast<double*>(&S);
+  constexpr int oHd = offsetof(StackLds, Hd) / 8, oHo = offsetof(StackLds, Ho) / 8, oHn = offsetof(StackLds, Hn) / 8,
+                oGv = offsetof(StackLds, gv) / 8;
+  // fixed lane roles of the triangular solves: eliminated block slot es
+  // (4 per round) and column tc of [W_L | W_R | w]
+  const int es = lane / 13, col = lane - 13 * es;
+  // fixed lane roles of the update pass: entry q of a surviving block's
+  // packed D (0..20) or g (21..26), or of a created coupling (27..62)
+  const int q = lane;
+  int tp, tc;
+  tri_entry(q < 21 ? q : 0, &tp, &tc);
+  const int pg = q - 21, pc = q - 27, pp = pc / 6, cc = pc - 6 * (pc / 6);
   bool ok = true;
   int ls = 0, made = 0;  // log2 stride; couplings created so far
   for (; (1 << ls) < k; ++ls) {
     const int np = bcr_positions(k, ls), ne = np / 2, nr = (np - 1) / 2;  // nr: eliminated with a right neighbour
-    double* Cp = ls == 0 ? &S.Ho[0][0] : &S.Hn[bcr_first(k, ls)][0];
-    double* Cn = &S.Hn[made][0];
+    const int oC = ls == 0 ? oHo : oHn + 36 * bcr_first(k, ls);        // coupling j at oC + 36 j
+    const int oN = oHn + 36 * made;                                     // created coupling e at oN + 36 e
     bool okl = true;
     if (lane < ne) {
       double* D = S.Hd[(2 * lane + 1) << ls];
       double P[21];
 #pragma unroll
-      for (int q = 0; q < 21; ++q) P[q] = D[q];
+      for (int t = 0; t < 21; ++t) P[t] = D[t];
       okl = chol_packed<6>(P);
 #pragma unroll
-      for (int q = 0; q < 21; ++q) D[q] = P[q];
+      for (int t = 0; t < 21; ++t) D[t] = P[t];
     }
     ok = wave_all(okl) && ok;
     wave_fence();
-    // W_L (columns, in place), W_R (stored transposed: rows, in place), w
-#pragma unroll 2
-    for (int t0 = 0; t0 < 13 * ne; t0 += 64) {
-      const int task = t0 + lane;
-      const int e = task / 13, col = task - 13 * e;
-      if (task < 13 * ne && (col < 6 || col == 12 || e < nr)) {
-        double* blk = Cp + 72 * e;
-        double* dst = col < 6 ? blk + col : col < 12 ? blk + 36 + 6 * (col - 6) : S.gv[(2 * e + 1) << ls];
+    // W_L = L^-1 H(p, p-1) (columns, in place), W_R = L^-1 H(p, p+1)
+    // (stored transposed: rows, in place), w = L^-1 g_p
+    for (int e0 = 0; e0 < ne; e0 += 4) {
+      const int e = e0 + es;
+      if (lane < 52 && e < ne && (col < 6 || col == 12 || e < nr)) {
+        const int i = (2 * e + 1) << ls;
+        const int o = col < 6 ? oC + 72 * e + col : col < 12 ? oC + 72 * e + 36 + 6 * (col - 6) : oGv + 6 * i;
         const int stride = col < 6 ? 6 : 1;
+        double* dst = base + o;
         double v[6];
 #pragma unroll
         for (int r = 0; r < 6; ++r) v[r] = dst[r * stride];
-        ltri_fwd(S.Hd[(2 * e + 1) << ls], v);
+        ltri_fwd(S.Hd[i], v);
 #pragma unroll
         for (int r = 0; r < 6; ++r) dst[r * stride] = v[r];
       }
     }
     wave_fence();
-    // left neighbours: D -= W_L^T W_L (entries 0..20), g -= W_L^T w (21..26)
-#pragma unroll 2
-    for (int t0 = 0; t0 < 27 * ne; t0 += 64) {
-      const int task = t0 + lane;
-      const int e = task / 27, q = task - 27 * e;
-      if (task < 27 * ne) {
-        const double* WL = Cp + 72 * e;
-        const bool dq = q < 21;
-        int tp, tc;
-        tri_entry(q, &tp, &tc);
-        const double* X = WL + (dq ? tp : q - 21);
-        const double* Y = dq ? WL + tc : S.gv[(2 * e + 1) << ls];
-        double* T = dq ? &S.Hd[(2 * e) << ls][q] : &S.gv[(2 * e) << ls][q - 21];
-        *T -= dot6s(X, 6, Y, dq ? 6 : 1);
+    // surviving positions j = 2e: D_j -= W_L(e)^T W_L(e) + W_R(e-1)^T W_R(e-1),
+    // g_j -= W_L(e)^T w(e) + W_R(e-1)^T w(e-1); the coupling created by
+    // position 2e + 1: -W_R(e)^T W_L(e)
+    const int na = (np + 1) / 2;
+    for (int e = 0; e < na; ++e) {
+      const int eL = min(e, ne - 1), eR = max(e - 1, 0);
+      const bool fL = q < 27 ? e < ne : e < nr, fR = q < 27 && e >= 1;
+      const int oWL = oC + 72 * eL, oWR = oC + 72 * eR + 36;
+      int x1, sx1, y1, sy1, x2, y2, t;
+      if (q < 21) {
+        x1 = oWL + tp; sx1 = 6; y1 = oWL + tc; sy1 = 6;
+        x2 = oWR + 6 * tp; y2 = oWR + 6 * tc;
+        t = oHd + 21 * ((2 * e) << ls) + q;
+      } else if (q < 27) {
+        x1 = oWL + pg; sx1 = 6; y1 = oGv + 6 * ((2 * eL + 1) << ls); sy1 = 1;
+        x2 = oWR + 6 * pg; y2 = oGv + 6 * ((2 * eR + 1) << ls);
+        t = oGv + 6 * ((2 * e) << ls) + pg;
+      } else {
+        x1 = oC + 72 * eL + 36 + 6 * pp; sx1 = 1; y1 = oWL + cc; sy1 = 6;
+        x2 = x1; y2 = x1;
+        t = oN + 36 * eL + pc;
       }
-    }
-    wave_fence();
-    // right neighbours: D -= W_R^T W_R, g -= W_R^T w; created couplings
-    // -W_R^T W_L (entries 27..62)
-#pragma unroll 2
-    for (int t0 = 0; t0 < 63 * nr; t0 += 64) {
-      const int task = t0 + lane;
-      const int e = task / 63, q = task - 63 * e;
-      if (task < 63 * nr) {
-        const double* WL = Cp + 72 * e;
-        const double* WR = WL + 36;
-        int tp, tc;
-        tri_entry(q, &tp, &tc);
-        const int pc = q - 27, pp = pc / 6, cc = pc - 6 * pp;
-        const double* X = WR + 6 * (q < 21 ? tp : q < 27 ? q - 21 : pp);
-        const double* Y = q < 21 ? WR + 6 * tc : q < 27 ? S.gv[(2 * e + 1) << ls] : WL + cc;
-        const int sy = q < 27 ? 1 : 6;
-        double* T = q < 21 ? &S.Hd[(2 * e + 2) << ls][q] : q < 27 ? &S.gv[(2 * e + 2) << ls][q - 21] : Cn + 36 * e + pc;
-        const double d = dot6s(X, 1, Y, sy);
-        *T = (q < 27 ? *T : 0.0) - d;
+      if (lane < 63 && (fL || fR)) {
+        double d = 0.0;
+        if (fL) d = dot6s(base + x1, sx1, base + y1, sy1);
+        if (fR) d += dot6s(base + x2, 1, base + y2, 1);
+        base[t] = (q < 27 ? base[t] : 0.0) - d;
       }
     }
     wave_fence();
@@ -726,23 +733,39 @@ DMX_DEV int pair_collide(const StackModel& m, const StackLds& S, const StackRole
   return 0;
 }
 
-// True if cubes that are not neighbours in the model's order touch (lane i
-// checks pairs (i, j), j >= i + 2).
+// True if cubes that are not neighbours in the model's order touch.  Pairs
+// (i, j), j >= i + 2: row i is split between lanes i (first half) and
+// 32 + i (second half); bounding spheres are tested first, and the
+// narrow phase runs only if some pair's spheres overlap.
 DMX_DEV bool nonneighbour_contact(const StackModel& m, const StackLds& S, double margin) {
-  const int i = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  const int k = m.k;
+  const double reach = 2.0 * m.rbound + margin;
+  const int i = lane & 31;
+  const int row = max(0, k - 2 - i), half = (row + 1) / 2;
+  const int j0 = i + 2 + (lane < 32 ? 0 : half), j1 = i + 2 + (lane < 32 ? half : row);
+  bool near = false;
+  if (i < k) {
+    const V3 cA = ld3(S.P[i]);
+    for (int j = j0; j < j1; ++j) {
+      const V3 dc = ld3(S.P[j]) - cA;
+      near = near || dot(dc, dc) < reach * reach;
+    }
+  }
+  if (!wave_any(near)) return false;
   bool hit = false;
-  if (i + 2 < m.k) {
-    const double reach = 2.0 * m.rbound + margin;
+  if (near) {
     const V3 cA = ld3(S.P[i]);
     const M3& RA = *(const M3*)S.R[i];
-    for (int j = i + 2; j < m.k && !hit; ++j) {
+    for (int j = j0; j < j1 && !hit; ++j) {
       const V3 cB = ld3(S.P[j]);
       const V3 dc = cB - cA;
       if (!(dot(dc, dc) < reach * reach)) continue;
       const M3& RB = *(const M3*)S.R[j];
       BoxChoice ch;
-      if (!box_box_choose(m.h, m.h, cA, RA, cB, RB, margin, &ch)) continue;
-      if (box_box_contacts(m.h, m.h, cA, RA, cB, RB, margin, ch, nullptr, nullptr, nullptr, nullptr) > 0) hit = true;
+      if (box_box_choose(m.h, m.h, cA, RA, cB, RB, margin, &ch) &&
+          box_box_contacts(m.h, m.h, cA, RA, cB, RB, margin, ch, nullptr, nullptr, nullptr, nullptr) > 0)
+        hit = true;
     }
   }
   return wave_any(hit);
