@@ -106,70 +106,109 @@ def algorithmic_flops(counters, table, nc):
     return total
 
 
-def serve_leg(D, W, rate, seconds, seed=5, drain_s=240.0):
-    """MPC requests arriving as a Poisson stream: each picks the controlled
-    corner-sphere cube, the legged chain or the box-geom cube (the one-level
-    stack), N ~ U{16..256} candidate control sequences
+def serve_leg(D, W, rate, seconds, seed=5, grace_s=10.0, budget=200 * 10 ** 9):
+    """MPC requests arriving as a Poisson stream over a fixed window: each
+    picks (uniformly) the controlled corner-sphere cube, the legged chain or a
+    stack of k ~ U{1..16} cubes (t_c 3 ms, the control on the top cube,
+    lateral offsets zero), N ~ U{16..256} candidate control sequences
     u ~ U(-1, 1) over H ~ U{50..500} intervals of 10 ms, and asks for the
     candidates' costs and control gradients.  Latency = completion - arrival
-    (submission happens at the arrival time)."""
+    (submission happens at the arrival time).  After the window, requests in
+    the server get grace_s more seconds; the rest count as unfinished.  Only
+    worlds that reach their horizon (status 0) count as served work."""
     rng = np.random.default_rng(seed)
-    models = {"cube": D.Model(W.model_cube_corners(ctrl=True)), "chain": D.Model(W.model_chain()),
-              "box": D.Model(W.model_box(ctrl=True, mu=0.6, tc=0.003))}
+    models = {"cube": D.Model(W.model_cube_corners(ctrl=True)), "chain": D.Model(W.model_chain())}
+    stacks = {k: D.Model(W.model_stack(k, tc=0.003, ctrl=True)) for k in range(1, 17)}
+    stack_x0 = {k: W.stack_state(np.zeros((k, 2))) for k in range(1, 17)}
     chain_x0 = W.chain_walk(n_worlds=1, n_intervals=1)["x0"][0]
+    cube_x0 = np.zeros(13)
+    cube_x0[2], cube_x0[3] = 0.111, 1.0
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 2) + 16))
     arrivals = arrivals[arrivals < seconds]
-    srv = D.Server(hbm_budget_bytes=200 * 10 ** 9, max_batch_worlds=16384)
-    pending, lat, done_kinds, work = {}, [], [], 0.0
+    # batches of at most 2048 worlds: two wavefronts' worth of stack worlds per
+    # slot, so that one batch's latency stays bounded under overload
+    srv = D.Server(hbm_budget_bytes=budget, max_batch_worlds=2048, n_streams=8, max_inflight=8)
+    pending, lat, done_kinds, work, failed_worlds, arr_done = {}, [], [], 0.0, 0, []
     t0 = time.perf_counter()
     nxt = 0
     backlog_at_end = None
-    t_last = t0
     try:
         while nxt < len(arrivals) or pending:
             now = time.perf_counter() - t0
             while nxt < len(arrivals) and arrivals[nxt] <= now:
-                kind = ("cube", "chain", "box")[int(rng.integers(3))]
-                m = models[kind]
-                N, H = int(rng.integers(16, 257)), int(rng.integers(50, 501))
-                if kind == "cube":
-                    x0 = W.cube_toss(seed=int(rng.integers(1 << 30)), n_worlds=1, horizon=0.1)["x0"][0]
-                elif kind == "box":
-                    x0 = W.box_toss(seed=int(rng.integers(1 << 30)), n_worlds=1, horizon=0.1)["x0"][0]
+                kind = ("cube", "chain", "stack")[int(rng.integers(3))]
+                if kind == "stack":
+                    k = int(rng.integers(1, 17))
+                    m, x0 = stacks[k], stack_x0[k]
                 else:
-                    x0 = chain_x0
+                    m, x0 = models[kind], (cube_x0 if kind == "cube" else chain_x0)
+                N, H = int(rng.integers(16, 257)), int(rng.integers(50, 501))
                 u = rng.uniform(-1.0, 1.0, size=(N, H, m.nu))
-                target = [float(rng.normal(0, 0.2)), float(rng.normal(0, 0.2)), 0.3]
-                pending[srv.submit(m, x0, u, 0.01, target, ctrl_weight=1e-3)] = (arrivals[nxt], kind, N * H * 0.01)
+                target = [float(rng.normal(0, 0.1)), float(rng.normal(0, 0.1)), 0.3]
+                pending[srv.submit(m, x0, u, 0.01, target, ctrl_weight=1e-3)] = (arrivals[nxt], kind, H * 0.01)
                 nxt += 1
             if backlog_at_end is None and now >= seconds:
                 backlog_at_end = len(pending)
             for t in list(pending):
                 r = srv.poll(t)
                 if r is not None:
-                    arr, kind, ws = pending.pop(t)
+                    arr, kind, horizon = pending.pop(t)
                     lat.append(time.perf_counter() - t0 - arr)
+                    arr_done.append(arr)
                     done_kinds.append(kind)
-                    work += ws
-                    t_last = time.perf_counter()
-            if now > seconds + drain_s:
+                    ok = r["status"] == 0
+                    work += horizon * int(ok.sum())
+                    failed_worlds += int((~ok).sum())
+            if now > seconds + grace_s:
                 break
             time.sleep(0.0005)
+        t_end = time.perf_counter() - t0
     finally:
         srv.close()
     if backlog_at_end is None:
-        backlog_at_end = len(pending)
-    elapsed = t_last - t0
+        backlog_at_end = 0
+    span = max(t_end, 1e-9)
+    arr_done = np.array(arr_done)
+    halves = [np.array(lat)[arr_done < seconds / 2], np.array(lat)[arr_done >= seconds / 2]]
+    p50_halves = [round(float(np.median(h)) * 1e3, 1) if len(h) else None for h in halves]
     lat = np.array(lat) if lat else np.array([np.nan])
     return {"offered_rate_per_s": rate, "arrival_window_s": seconds, "requests": int(len(arrivals)),
             "completed": int(len(done_kinds)), "unfinished": len(pending),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
-            "served_req_per_s": round(len(done_kinds) / elapsed, 2) if elapsed > 0 else None,
-            "served_world_sim_s_per_s": round(work / elapsed, 1) if elapsed > 0 else None,
+            "served_req_per_s": round(len(done_kinds) / span, 2),
+            "served_world_sim_s_per_s": round(work / span, 1),
+            "failed_worlds": failed_worlds,
             "backlog_at_window_end": int(backlog_at_end),
-            "mix": {k: done_kinds.count(k) for k in ("cube", "chain", "box")},
+            "p50_ms_first_second_half_arrivals": p50_halves,
+            "measured_over_s": round(span, 2),
+            "mix": {k: done_kinds.count(k) for k in ("cube", "chain", "stack")},
             "requests_shape": "N~U{16..256} candidates, H~U{50..500} x 10 ms, cost+control gradient"}
+
+
+def serve_capacity(D, W, burst, seconds, seed=60):
+    """The sustainable request rate: a burst of requests submitted at once
+    gives the service capacity (requests completed per second until the last
+    one is done); an open-loop Poisson window at half that rate then checks
+    that the queue keeps up: every request of the window completes within a
+    grace period as long as the window, and requests arriving in its second
+    half wait no longer than 1.5 times the median of the first half plus one
+    second."""
+    print(f"bench:   serving capacity: burst of {burst} requests ...", file=sys.stderr, flush=True)
+    b = serve_leg(D, W, burst / 1e-3, 1e-3 * (burst - 0.5), seed=seed, grace_s=150.0)
+    cap = b["completed"] / max(b["measured_over_s"], 1e-9)
+    rate = round(0.5 * cap, 3)
+    print(f"bench:   serving at {rate} req/s (half the burst capacity) ...", file=sys.stderr, flush=True)
+    r = serve_leg(D, W, rate, seconds, seed=seed + 1, grace_s=seconds)
+    h1, h2 = r["p50_ms_first_second_half_arrivals"]
+    sustained = bool(r["unfinished"] == 0 and h1 is not None and h2 is not None and h2 <= 1.5 * h1 + 1e3)
+    keys = ("offered_rate_per_s", "requests", "completed", "unfinished", "p50_ms", "p99_ms", "served_req_per_s",
+            "served_world_sim_s_per_s", "backlog_at_window_end", "p50_ms_first_second_half_arrivals", "failed_worlds")
+    return {"burst": {"requests": b["requests"], "completed": b["completed"], "seconds": b["measured_over_s"],
+                      "capacity_req_per_s": round(cap, 3), "served_world_sim_s_per_s": b["served_world_sim_s_per_s"],
+                      "mix": b["mix"]},
+            "half_capacity_window": dict({k: r[k] for k in keys}, window_s=seconds, sustained=sustained),
+            "highest_sustained_rate_per_s": rate if sustained else None}
 
 
 def timed_steps(step, steps, warmup, stream):
@@ -416,6 +455,63 @@ def chain_leg(D, W, args, dev):
             "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}
 
 
+def graph_ab_leg(D, W, dev, reps=200):
+    """A/B timing of one short receding-horizon segment (one 10 ms interval,
+    forward + reverse sweep) issued as eager library calls with a reused tape
+    versus a replay of its captured graph; the two alternate in blocks of
+    `reps` segments, each block timed between synchronizations."""
+    import torch
+    out = {}
+    cases = {
+        "cube_64_worlds": ([D.Model(W.model_cube_corners(ctrl=True))] * 64,
+                           W.cube_toss(seed=7, n_worlds=64, horizon=0.01)["x0"].reshape(-1)),
+        "stack_8_worlds_k4": ([D.Model(W.model_stack(4, tc=0.003, ctrl=True))] * 8,
+                              np.concatenate([W.stack_state(np.zeros((4, 2)))] * 8)),
+    }
+    rng = np.random.default_rng(3)
+    for name, (models, x0) in cases.items():
+        n_int, dt = 1, 0.01
+        nu = sum(n_int * m.nu for m in models)
+        x0t = torch.tensor(x0, dtype=torch.float64, device=dev)
+        ut = torch.tensor(rng.uniform(-1, 1, nu), dtype=torch.float64, device=dev)
+        xb = torch.ones_like(x0t)
+        g = D.Graph(models, x0t, ut, n_int, dt)
+        g.xbar.copy_(xb)
+        uniform_free = models[0].nx == 13 and all(m is models[0] for m in models)
+        if uniform_free:
+            Wn = len(models)
+            r = D.rollout(models[0], x0t.view(Wn, -1), ut.view(Wn, n_int, -1), n_int, dt, tape=True)
+            tape = r["tape"]
+
+            def eager():
+                D.rollout(models[0], x0t.view(Wn, -1), ut.view(Wn, n_int, -1), n_int, dt, reuse=tape)
+                D.rollout_vjp(tape, xb.view(Wn, -1))
+        else:
+            r = D.rollout_batch(models, x0t, ut, n_int, dt, tape=True)
+            tape = r["tape"]
+
+            def eager():
+                D.rollout_batch(models, x0t, ut, n_int, dt, reuse=tape)
+                D.rollout_batch_vjp(tape, xb)
+        times = {"eager": [], "graph": []}
+        for block in range(4):
+            for kind in ("eager", "graph"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    if kind == "eager":
+                        eager()
+                    else:
+                        g.replay()
+                torch.cuda.synchronize()
+                times[kind].append((time.perf_counter() - t0) / reps * 1e6)
+        g.close()
+        out[name] = {"eager_us_per_segment": round(float(np.median(times["eager"])), 1),
+                     "graph_us_per_segment": round(float(np.median(times["graph"])), 1),
+                     "blocks_us": {k: [round(v, 1) for v in vs] for k, vs in times.items()}}
+    return out
+
+
 def sphere_leg(D, W, args, dev):
     """One sphere dropped onto a plane, 1 s: latency of forward + adjoint."""
     import torch
@@ -468,7 +564,11 @@ def main():
     ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the serving leg, s")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window of the serving leg, s")
+    ap.add_argument("--capacity-burst", type=int, default=16,
+                    help="requests of the serving capacity burst (0: skip the capacity check)")
+    ap.add_argument("--capacity-seconds", type=float, default=30.0,
+                    help="arrival window of the open-loop check at half the burst capacity, s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -504,10 +604,14 @@ def main():
         if not args.no_chain:
             print("bench: legged chains ...", file=sys.stderr, flush=True)
             others["chain_walk"] = chain_leg(D, W, args, dev)
+        print("bench: captured segments (graph) A/B ...", file=sys.stderr, flush=True)
+        others["graph_segments"] = graph_ab_leg(D, W, dev)
     serving = None
     if not args.no_serve:
         print("bench: serving ...", file=sys.stderr, flush=True)
         serving = serve_leg(D, W, args.serve_rate, args.serve_seconds)
+        if args.capacity_burst > 0:
+            serving["sustainable"] = serve_capacity(D, W, args.capacity_burst, args.capacity_seconds)
     out = {
         "metric": "sim-seconds/s fwd+adjoint at rtol 1e-6 vs plain GPU form; p99 request latency",
         "value": round(st["value"], 3),

@@ -264,6 +264,31 @@ dmx_status dmx_autotune(dmx_model* model, int32_t n_worlds, int32_t n_intervals,
  * any number of times on one tape. */
 dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
 
+/* Captured rollout segments (HIP graphs), for callers that run the same
+ * batch repeatedly with new inputs at the same addresses (receding-horizon
+ * control loops, where each planning step is one short segment: App. D's
+ * batched rollouts, used as in Sec. 5.2).  dmx_graph_create runs the forward
+ * rollout of the batch once (as dmx_rollout_batch, or dmx_rollout when every
+ * world has the same free-body or tree model), keeping its tape, then
+ * records the same forward launch sequence and, if x_out_bar is given, the
+ * reverse sweep (as dmx_rollout_vjp) into a graph over the given DEVICE
+ * buffers: x0, u (inputs), x_out, world_status (outputs), x_out_bar (input),
+ * x0_bar, u_bar (outputs); layouts as for those calls.  The buffers are the
+ * caller's and must stay allocated while the graph lives.  dmx_graph_launch
+ * replays the whole sequence on a stream after the caller has written new
+ * x0 / u / x_out_bar values into the same buffers; its results are bitwise
+ * those of the eager calls.  Nothing is allocated at launch.  Errors:
+ * DMX_ERR_INVALID_ARG for null or mismatched arguments, DMX_ERR_HIP if
+ * capture or instantiation fails (nothing is left allocated then). */
+typedef struct dmx_graph dmx_graph;
+dmx_status dmx_graph_create(const dmx_batch* batch, const dmx_solver_opts* opts, const double* x0, const double* u,
+                            double* x_out, int32_t* world_status, const double* x_out_bar, double* x0_bar,
+                            double* u_bar, void* stream, dmx_graph** out);
+dmx_status dmx_graph_launch(dmx_graph* graph, void* stream);
+/* The tape the graph writes (valid while the graph lives). */
+const dmx_tape* dmx_graph_tape(const dmx_graph* graph);
+void dmx_graph_destroy(dmx_graph* graph);
+
 /* Allocation-free forward rollout, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): the arguments and results of dmx_rollout without a
@@ -300,8 +325,9 @@ dmx_status dmx_accel(const dmx_model* model, int32_t n, const double* x, const d
  * gradients per planning step): each request is N candidate control
  * sequences of one model from one initial state over H intervals; the result
  * is each candidate's cost
- *   cost = |q_T[0:3] - target|^2 + ctrl_weight * sum_k |u_k|^2 * interval_dt
- * (q_T[0:3]: the first three position coordinates of the final state) and
+ *   cost = |p_T - target|^2 + ctrl_weight * sum_k |u_k|^2 * interval_dt
+ * (p_T: the position of the controlled body in the final state: the first
+ * three position coordinates, or for a stack of cubes the top cube's) and
  * its gradient with respect to the controls.
  *
  * Continuous batching: whenever one of the server's streams is free, the
@@ -321,6 +347,9 @@ typedef struct {
   int32_t n_streams;         /* HIP streams, default priority (default 4) */
   int32_t steps_per_interval;/* tape capacity per world = this * n_intervals + 64 (default 40) */
   int32_t max_batch_worlds;  /* worlds merged into one batch (default 16384) */
+  int32_t stack_steps_per_interval; /* the same for cube-stack models (default 128); their tapes hold
+                                       checkpoints (3 + 13 k doubles per step) and the reverse sweep solves
+                                       each step's stages again */
 } dmx_server_opts;
 
 typedef struct {

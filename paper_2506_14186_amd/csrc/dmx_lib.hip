@@ -1236,6 +1236,92 @@ void dmx_tape_destroy(dmx_tape* tp) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- graphs
+struct dmx_graph {
+  dmx_tape* tape = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+// One forward call (and optionally its reverse sweep) over the batch with the
+// given tape: a uniform batch of a free-body or tree model goes through
+// dmx_rollout, every other batch through dmx_rollout_batch.
+static dmx_status graph_segment(const dmx_batch* b, const dmx_solver_opts* opts, const double* x0, const double* u,
+                                double* x_out, int32_t* status, const double* xbar, double* x0bar, double* ubar,
+                                dmx_tape** tape, hipStream_t s) {
+  const dmx_model* m0 = b->models[0];
+  bool uniform = true;
+  for (int w = 1; w < b->n_worlds; ++w) uniform = uniform && b->models[w] == m0;
+  dmx_status r;
+  if (uniform && m0->kind != 2)
+    r = rollout_impl(m0, b->n_worlds, b->n_intervals, b->interval_dt, opts, x0, u, x_out, status, nullptr, nullptr,
+                     tape, s, nullptr);
+  else
+    r = dmx_rollout_batch(b, opts, x0, u, x_out, status, nullptr, nullptr, tape, s);
+  if (r != DMX_OK || !xbar) return r;
+  return dmx_rollout_vjp(*tape, xbar, x0bar, ubar, s);
+}
+
+dmx_status dmx_graph_create(const dmx_batch* b, const dmx_solver_opts* opts, const double* x0, const double* u,
+                            double* x_out, int32_t* world_status, const double* x_out_bar, double* x0_bar,
+                            double* u_bar, void* stream, dmx_graph** out) {
+  if (!b || !out || !b->models || b->n_worlds <= 0 || !x0 || !x_out || !world_status)
+    return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (x_out_bar && !x0_bar) return fail(DMX_ERR_INVALID_ARG, "x0_bar required with x_out_bar");
+  for (int w = 0; w < b->n_worlds; ++w)
+    if (!b->models[w]) return fail(DMX_ERR_INVALID_ARG, "null model in batch");
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  dmx_graph* g = new dmx_graph();
+  // eager first run: allocates the tape and uploads the per-world tables
+  dmx_status r = graph_segment(b, opts, x0, u, x_out, world_status, x_out_bar, x0_bar, u_bar, &g->tape, s);
+  if (r == DMX_OK && hipStreamSynchronize(s) != hipSuccess) r = fail(DMX_ERR_HIP, "graph warm-up failed");
+  hipStream_t cs = nullptr;
+  if (r == DMX_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)  // default priority
+    r = fail(DMX_ERR_HIP, "capture stream");
+  if (r == DMX_OK) {
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      r = fail(DMX_ERR_HIP, "stream capture did not begin");
+    } else {
+      // with the tape reused, the calls only launch kernels and copy device
+      // to device: nothing allocates or synchronizes while capturing
+      const dmx_status rc = graph_segment(b, opts, x0, u, x_out, world_status, x_out_bar, x0_bar, u_bar, &g->tape, cs);
+      const hipError_t e = hipStreamEndCapture(cs, &g->graph);
+      if (rc != DMX_OK) r = rc;
+      else if (e != hipSuccess || !g->graph) r = fail(DMX_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+      else if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        r = fail(DMX_ERR_HIP, "graph instantiation failed");
+    }
+  }
+  if (cs) (void)hipStreamDestroy(cs);
+  if (r != DMX_OK) {
+    dmx_graph_destroy(g);
+    return r;
+  }
+  *out = g;
+  return DMX_OK;
+}
+
+dmx_status dmx_graph_launch(dmx_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(DMX_ERR_INVALID_ARG, "null graph");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return DMX_OK;
+}
+
+const dmx_tape* dmx_graph_tape(const dmx_graph* g) { return g ? g->tape : nullptr; }
+
+void dmx_graph_destroy(dmx_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->tape) dmx_tape_destroy(g->tape);
+  delete g;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- serving
 namespace {
 double now_s() {
@@ -1270,7 +1356,10 @@ struct SrvBatch {
   long long n_u = 0, n_rec = 0;
   std::vector<SrvReq*> reqs;
   size_t off = 0, bytes = 0;
-  size_t o_x0, o_u, o_nint, o_uoff, o_toff, o_cap, o_order, o_target, o_cw, in_end;
+  bool stack = false;  // served by the cube-stack kernels (requests of any cube count merge)
+  long long n_x = 0;   // state doubles of all worlds (13 k_w each for stacks)
+  long long n_recd = 0;  // tape doubles (records x their lengths)
+  size_t o_x0, o_u, o_nint, o_uoff, o_toff, o_xoff, o_cap, o_order, o_target, o_cw, o_models, o_pos, o_nxw, in_end;
   size_t o_cost, o_ubar, o_status, out_end;
   size_t o_xout, o_nacc, o_xbar, o_x0bar, o_queue, o_tape;
   void* pin_in = nullptr;
@@ -1281,40 +1370,56 @@ struct SrvBatch {
   void layout() {
     size_t o = 0;
     auto take = [&](size_t n) { size_t at = o; o += align256(n); return at; };
-    o_x0 = take(sizeof(double) * (size_t)W * nx);
+    o_x0 = take(sizeof(double) * (size_t)n_x);
     o_u = take(sizeof(double) * (size_t)(n_u + 1));
     o_nint = take(sizeof(int) * W);
     o_uoff = take(sizeof(long long) * W);
     o_toff = take(sizeof(long long) * W);
+    o_xoff = take(sizeof(long long) * W);
     o_cap = take(sizeof(int) * W);
     o_order = take(sizeof(int) * W);
     o_target = take(sizeof(double) * 3 * W);
     o_cw = take(sizeof(double) * W);
+    o_models = take(stack ? sizeof(dmx::StackModel) * W : 0);
+    o_pos = take(sizeof(int) * W);
+    o_nxw = take(sizeof(int) * W);
     in_end = o;
     o_cost = take(sizeof(double) * W);
     o_ubar = take(sizeof(double) * (size_t)(n_u + 1));
     o_status = take(sizeof(int) * W);
     out_end = o;
-    o_xout = take(sizeof(double) * (size_t)W * nx);
+    o_xout = take(sizeof(double) * (size_t)n_x);
     o_nacc = take(sizeof(int) * W);
-    o_xbar = take(sizeof(double) * (size_t)W * nx);
-    o_x0bar = take(sizeof(double) * (size_t)W * nx);
+    o_xbar = take(sizeof(double) * (size_t)n_x);
+    o_x0bar = take(sizeof(double) * (size_t)n_x);
     o_queue = take(2 * sizeof(int));
-    o_tape = take(sizeof(double) * (size_t)n_rec * rec);
+    o_tape = take(sizeof(double) * (size_t)std::max(n_recd, 1ll));
     bytes = o;
   }
 };
 
-long long request_records(const SrvReq& r, int steps_per_interval) {
-  return (long long)r.N * ((long long)steps_per_interval * r.H + 64);
+// served by the cube-stack kernels (a stack of two or more cubes)
+bool served_as_stack(const dmx_model* m) { return !find_kernel(m, 0) && m->stack_ok; }
+// tape record of one accepted step: with the stage accelerations, or for
+// stacks a checkpoint whose stages the reverse sweep solves again
+int served_record(const dmx_model* m) {
+  return served_as_stack(m) ? 3 + 13 * m->stk.k : 3 + m->nq + m->nv + 6 * m->nv;
 }
+int steps_per_interval(const dmx_model* m, const dmx_server_opts& o) {
+  return served_as_stack(m) ? o.stack_steps_per_interval : o.steps_per_interval;
+}
+long long world_records(const SrvReq& r, const dmx_server_opts& o) {
+  return (long long)steps_per_interval(r.model, o) * r.H + 64;
+}
+long long request_records(const SrvReq& r, const dmx_server_opts& o) { return (long long)r.N * world_records(r, o); }
 
 // device bytes a request adds to a batch (its share of every array, with the
 // per-array alignment of the batch layout as slack)
-size_t request_bytes(const SrvReq& r, int steps_per_interval) {
-  const size_t W = r.N, nu_tot = (size_t)r.N * r.H * r.nu, rec = 3 + r.nx + 6 * r.model->nv;
-  return sizeof(double) * (W * r.nx * 4 + nu_tot * 2 + W * 5) + sizeof(long long) * 2 * W + sizeof(int) * 5 * W +
-         sizeof(double) * rec * (size_t)request_records(r, steps_per_interval) + 20 * 256;
+size_t request_bytes(const SrvReq& r, const dmx_server_opts& o) {
+  const size_t W = r.N, nu_tot = (size_t)r.N * r.H * r.nu, rec = served_record(r.model);
+  return sizeof(double) * (W * r.nx * 4 + nu_tot * 2 + W * 5) + sizeof(long long) * 3 * W + sizeof(int) * 7 * W +
+         (served_as_stack(r.model) ? sizeof(dmx::StackModel) * W : 0) +
+         sizeof(double) * rec * (size_t)request_records(r, o) + 20 * 256;
 }
 }  // namespace
 
@@ -1340,17 +1445,23 @@ struct dmx_server {
     SrvReq* head = queue.front();
     SrvBatch* b = new SrvBatch();
     b->model = head->model; b->dt = head->dt; b->want_grad = head->want_grad;
-    b->nx = head->nx; b->nu = head->nu; b->rec = 3 + head->nx + 6 * head->model->nv;
+    b->nx = head->nx; b->nu = head->nu; b->rec = served_record(head->model);
+    b->stack = served_as_stack(head->model);
     size_t need = 0;
     for (SrvReq* r : queue) {
-      if (r->model != b->model || r->dt != b->dt || r->want_grad != b->want_grad) continue;
+      // stacks of any cube count share the stack kernels (and the control
+      // count of the top cube); other models batch with themselves
+      const bool family = b->stack ? served_as_stack(r->model) && r->nu == b->nu : r->model == b->model;
+      if (!family || r->dt != b->dt || r->want_grad != b->want_grad) continue;
       if (!b->reqs.empty() && b->W + r->N > opts.max_batch_worlds) break;
       if (need + r->bytes > arena.largest_free()) break;
       need += r->bytes;
       r->w0 = b->W; r->u0 = b->n_u;
       b->W += r->N;
       b->n_u += (long long)r->N * r->H * r->nu;
-      b->n_rec += request_records(*r, opts.steps_per_interval);
+      b->n_rec += request_records(*r, opts);
+      b->n_recd += request_records(*r, opts) * served_record(r->model);
+      b->n_x += (long long)r->N * r->nx;
       b->reqs.push_back(r);
     }
     if (b->reqs.empty()) { delete b; return nullptr; }  // the head waits for budget
@@ -1383,21 +1494,32 @@ struct dmx_server {
     int* nint = (int*)(pin + b->o_nint);
     long long* uoff = (long long*)(pin + b->o_uoff);
     long long* toff = (long long*)(pin + b->o_toff);
+    long long* xoff = (long long*)(pin + b->o_xoff);
+    dmx::StackModel* smod = (dmx::StackModel*)(pin + b->o_models);
+    int* pos = (int*)(pin + b->o_pos);
+    int* nxw = (int*)(pin + b->o_nxw);
+    long long x_at = 0;
     int* cap = (int*)(pin + b->o_cap);
     int* order = (int*)(pin + b->o_order);
     double* target = (double*)(pin + b->o_target);
     double* cw = (double*)(pin + b->o_cw);
     long long rec0 = 0;
     for (SrvReq* r : b->reqs) {
-      const long long wcap = (long long)opts.steps_per_interval * r->H + 64;
+      const long long wcap = world_records(*r, opts);
+      const int rlen = served_record(r->model);
       for (int i = 0; i < r->N; ++i) {
         const int w = r->w0 + i;
-        std::memcpy(x0 + (size_t)w * b->nx, r->x0.data(), sizeof(double) * b->nx);
+        std::memcpy(x0 + x_at, r->x0.data(), sizeof(double) * r->nx);
+        xoff[w] = x_at;
+        nxw[w] = r->nx;
+        pos[w] = b->stack ? 7 * (r->model->stk.k - 1) : 0;  // the controlled body: the top cube of a stack
+        if (b->stack) smod[w] = r->model->stk;
+        x_at += r->nx;
         nint[w] = r->H;
         uoff[w] = r->u0 + (long long)i * r->H * r->nu;
-        toff[w] = rec0;
+        toff[w] = b->stack ? rec0 : rec0 / b->rec;  // stack kernels take offsets in doubles, the others in records
         cap[w] = (int)wcap;
-        rec0 += wcap;
+        rec0 += wcap * rlen;
         for (int j = 0; j < 3; ++j) target[3 * w + j] = r->target[j];
         cw[w] = r->cw;
       }
@@ -1410,19 +1532,52 @@ struct dmx_server {
     char* d = arena.base + b->off;
     if (hipMemcpyAsync(d, pin, b->in_end, hipMemcpyHostToDevice, s) != hipSuccess) return false;
     auto D = [&](size_t o) { return (void*)(d + o); };
-    const KernelEntry* k = find_kernel(b->model, 0);
     dmx_solver_opts oo;
     dmx_default_opts(&oo);
+    int max_h = 0;
+    for (SrvReq* r : b->reqs) max_h = std::max(max_h, r->H);
+    const bool has_u = b->nu > 0;
+    if (b->stack) {
+      // cube stacks: every world is the batch's model; offsets from the tables
+      dmx::StackArgs a{};
+      a.W = b->W; a.n_int = max_h; a.dt = b->dt;
+      a.models = (const dmx::StackModel*)D(b->o_models);
+      a.x_off = (const long long*)D(b->o_xoff); a.u_off = (const long long*)D(b->o_uoff);
+      a.t_off = (const long long*)D(b->o_toff); a.cap_w = (const int*)D(b->o_cap);
+      a.n_int_w = (const int*)D(b->o_nint); a.order = (const int*)D(b->o_order);
+      a.stages = 0;
+      a.x0 = (const double*)D(b->o_x0); a.u = has_u ? (const double*)D(b->o_u) : nullptr;
+      a.xout = (double*)D(b->o_xout); a.status = (int*)D(b->o_status); a.n_acc = (int*)D(b->o_nacc);
+      a.tape = (double*)D(b->o_tape); a.o = to_solver(oo);
+      a.queue = (int*)D(b->o_queue);
+      dmx_host::stack_fwd(a, s, 0);
+      hipLaunchKernelGGL(srv::cost_kernel, dim3((b->W + 63) / 64), dim3(64), 0, s, a.xout, a.status,
+                         (const double*)D(b->o_u), b->W, a.x_off, (const int*)D(b->o_nxw), (const int*)D(b->o_pos), 3,
+                         b->nu, a.n_int_w, a.u_off, (const double*)D(b->o_target), (const double*)D(b->o_cw), b->dt,
+                         (double*)D(b->o_cost), (double*)D(b->o_xbar));
+      if (b->want_grad) {
+        a.xbar = (const double*)D(b->o_xbar);
+        a.x0bar = (double*)D(b->o_x0bar);
+        a.ubar = has_u ? (double*)D(b->o_ubar) : nullptr;
+        a.queue = (int*)D(b->o_queue) + 1;
+        dmx_host::stack_adj(a, s, 0);
+        if (has_u)
+          hipLaunchKernelGGL(srv::ctrl_grad_kernel, dim3(b->W), dim3(64), 0, s, (double*)D(b->o_ubar),
+                             (const double*)D(b->o_u), b->nu, a.n_int_w, a.u_off, (const double*)D(b->o_cw), b->dt);
+      }
+      if (hipMemcpyAsync(b->pin_out, D(b->o_cost), b->out_end - b->o_cost, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return false;
+      if (hipEventRecord(b->ev, s) != hipSuccess) return false;
+      return hipGetLastError() == hipSuccess;
+    }
+    const KernelEntry* k = find_kernel(b->model, 0);
     dmx::Ragged g{};
     g.n_int_w = (const int*)D(b->o_nint);
     g.u_off = (const long long*)D(b->o_uoff);
     g.tape_off = (const long long*)D(b->o_toff);
     g.cap_w = (const int*)D(b->o_cap);
     g.order = (const int*)D(b->o_order);
-    const bool has_u = b->nu > 0;
     dmx::FwdArgs a{};
-    int max_h = 0;
-    for (SrvReq* r : b->reqs) max_h = std::max(max_h, r->H);
     a.W = b->W; a.n_int = max_h; a.nu = b->nu; a.dt = b->dt; a.x0 = (const double*)D(b->o_x0);
     a.u = has_u ? (const double*)D(b->o_u) : nullptr; a.xout = (double*)D(b->o_xout);
     a.status = (int*)D(b->o_status); a.n_acc = (int*)D(b->o_nacc); a.tape = (double*)D(b->o_tape);
@@ -1430,7 +1585,8 @@ struct dmx_server {
     a.g = g; a.g.queue = (int*)D(b->o_queue);
     k->fwd(b->model->dev, a, s, 0);
     hipLaunchKernelGGL(srv::cost_kernel, dim3((b->W + 63) / 64), dim3(64), 0, s, a.xout, a.status,
-                       (const double*)D(b->o_u), b->W, b->nx, b->model->nq, b->nu, g.n_int_w, g.u_off,
+                       (const double*)D(b->o_u), b->W, (const long long*)D(b->o_xoff), (const int*)D(b->o_nxw),
+                       (const int*)D(b->o_pos), std::min(3, b->model->nq), b->nu, g.n_int_w, g.u_off,
                        (const double*)D(b->o_target), (const double*)D(b->o_cw), b->dt, (double*)D(b->o_cost),
                        (double*)D(b->o_xbar));
     if (b->want_grad) {
@@ -1507,6 +1663,7 @@ void dmx_default_server_opts(dmx_server_opts* o) {
   o->n_streams = 4;
   o->steps_per_interval = 40;
   o->max_batch_worlds = 16384;
+  o->stack_steps_per_interval = 128;
 }
 
 dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out) {
@@ -1514,7 +1671,7 @@ dmx_status dmx_server_create(const dmx_server_opts* opts, dmx_server** out) {
   dmx_server_opts o;
   if (opts) o = *opts; else dmx_default_server_opts(&o);
   if (o.hbm_budget_bytes <= 0 || o.max_inflight <= 0 || o.n_streams <= 0 || o.steps_per_interval <= 0 ||
-      o.max_batch_worlds <= 0)
+      o.max_batch_worlds <= 0 || o.stack_steps_per_interval <= 0)
     return fail(DMX_ERR_INVALID_ARG, "bad server options");
   dmx_server* sv = new dmx_server();
   sv->opts = o;
@@ -1540,8 +1697,9 @@ dmx_status dmx_submit(dmx_server* sv, const dmx_request* q, uint64_t* ticket) {
   if (q->n_worlds <= 0 || q->n_intervals <= 0 || !(q->interval_dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad sizes");
   const dmx_model* m = q->model;
   if (m->nu > 0 && !q->u) return fail(DMX_ERR_INVALID_ARG, "controls required");
-  if (!find_kernel(m, 0)) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
-  if ((long long)sv->opts.steps_per_interval * q->n_intervals + 64 > INT32_MAX)
+  if (!find_kernel(m, 0) && !m->stack_ok) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  if ((long long)std::max(sv->opts.steps_per_interval, sv->opts.stack_steps_per_interval) * q->n_intervals + 64 >
+      INT32_MAX)
     return fail(DMX_ERR_INVALID_ARG, "horizon too long");
   SrvReq* r = new SrvReq();
   r->model = m; r->N = q->n_worlds; r->H = q->n_intervals; r->nu = m->nu; r->nx = m->nq + m->nv;
@@ -1549,7 +1707,7 @@ dmx_status dmx_submit(dmx_server* sv, const dmx_request* q, uint64_t* ticket) {
   for (int i = 0; i < 3; ++i) r->target[i] = q->target[i];
   r->x0.assign(q->x0, q->x0 + r->nx);
   if (m->nu > 0) r->u.assign(q->u, q->u + (size_t)r->N * r->H * r->nu);
-  r->bytes = request_bytes(*r, sv->opts.steps_per_interval);
+  r->bytes = request_bytes(*r, sv->opts);
   if (r->bytes > sv->arena.size) { delete r; return fail(DMX_ERR_BUDGET, "request larger than the device budget"); }
   r->t_submit = now_s();
   {

@@ -16,22 +16,25 @@
 namespace srv {
 
 // ---------------------------------------------------------------- kernels
-// Per-world cost of a batch: |q_T[0:3] - target_w|^2 + cw_w * dt * sum |u|^2
-// over the world's own intervals, and the final-state cotangent for the
-// gradient; NaN cost for failed worlds.
-__global__ void cost_kernel(const double* xout, const int* status, const double* u, int W, int nx, int nq, int nu,
-                            const int* n_int_w, const long long* u_off, const double* target, const double* cw,
-                            double dt, double* cost, double* xbar) {
+// Per-world cost of a batch: |p_T - target_w|^2 + cw_w * dt * sum |u|^2 over
+// the world's own intervals, p_T the 3 coordinates of the world's final
+// state (x_off[w], nx[w] doubles) from index pos[w] (the controlled body's
+// position; npos <= 3 coordinates for models with fewer), and the
+// final-state cotangent for the gradient; NaN cost for failed worlds.
+__global__ void cost_kernel(const double* xout, const int* status, const double* u, int W, const long long* x_off,
+                            const int* nx, const int* pos, int npos, int nu, const int* n_int_w, const long long* u_off,
+                            const double* target, const double* cw, double dt, double* cost, double* xbar) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= W) return;
-  const double* x = xout + (size_t)w * nx;
+  const double* x = xout + x_off[w];
+  double* xb = xbar + x_off[w];
   double c = 0.0;
-  for (int i = 0; i < nx; ++i) xbar[(size_t)w * nx + i] = 0.0;
-  const int np = nq < 3 ? nq : 3;
-  for (int i = 0; i < np; ++i) {
-    const double d = x[i] - target[3 * w + i];
+  for (int i = 0; i < nx[w]; ++i) xb[i] = 0.0;
+  const int p = pos[w];
+  for (int i = 0; i < npos; ++i) {
+    const double d = x[p + i] - target[3 * w + i];
     c += d * d;
-    xbar[(size_t)w * nx + i] = 2.0 * d;
+    xb[p + i] = 2.0 * d;
   }
   double cu = 0.0;
   if (nu > 0) {

@@ -78,12 +78,15 @@ struct StackArgs {
   // uniform batches (every world of one model, dense layout): the tables
   // above are null and world w's offsets are w times these
   int uniform;
+  int one_model;  // every world is models[0], offsets from the tables
   long long x_stride, u_stride, t_stride;
   int cap_uniform;
 };
 
 // per-world layout of a batch (tables, or the uniform strides)
-DMX_DEV const StackModel& st_model(const StackArgs& a, int w) { return a.uniform ? a.models[0] : a.models[w]; }
+DMX_DEV const StackModel& st_model(const StackArgs& a, int w) {
+  return (a.uniform || a.one_model) ? a.models[0] : a.models[w];
+}
 DMX_DEV long long st_xoff(const StackArgs& a, int w) { return a.uniform ? w * a.x_stride : a.x_off[w]; }
 DMX_DEV long long st_uoff(const StackArgs& a, int w) { return a.uniform ? w * a.u_stride : a.u_off[w]; }
 DMX_DEV long long st_toff(const StackArgs& a, int w) { return a.uniform ? w * a.t_stride : a.t_off[w]; }

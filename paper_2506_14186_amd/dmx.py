@@ -404,7 +404,8 @@ class Rollout(torch.autograd.Function):
 # ------------------------------------------------------------------ serving
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
-                ("steps_per_interval", C.c_int32), ("max_batch_worlds", C.c_int32)]
+                ("steps_per_interval", C.c_int32), ("max_batch_worlds", C.c_int32),
+                ("stack_steps_per_interval", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -481,6 +482,64 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             _lib.dmx_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_lib.dmx_graph_create.argtypes = [C.POINTER(Batch), C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P, _P, _P,
+                                  C.POINTER(_P)]
+_lib.dmx_graph_create.restype = C.c_int32
+_lib.dmx_graph_launch.argtypes = [_P, _P]
+_lib.dmx_graph_launch.restype = C.c_int32
+_lib.dmx_graph_tape.argtypes = [_P]
+_lib.dmx_graph_tape.restype = _P
+_lib.dmx_graph_destroy.argtypes = [_P]
+EXPORTS += ["dmx_graph_create", "dmx_graph_launch", "dmx_graph_tape", "dmx_graph_destroy"]
+
+
+class Graph:
+    """A captured rollout segment (wraps dmx_graph_*): the forward rollout of
+    `models` (one per world) over n_int intervals of dt and, with grad, its
+    reverse sweep, recorded once over fixed device buffers.  Write new inputs
+    into .x0, .u and .xbar in place (e.g. x0.copy_(...)), then replay(); the
+    results appear in .x, .status, .x0bar and .ubar."""
+
+    def __init__(self, models, x0, u, n_int, dt, opts=None, grad=True):
+        W = len(models)
+        nx = sum(m.nx for m in models)
+        nu = sum(int(n_int) * m.nu for m in models)
+        self.x0 = x0.contiguous().clone()
+        assert self.x0.dtype == torch.float64 and self.x0.is_cuda and self.x0.numel() == nx
+        self.u = None
+        if nu:
+            self.u = u.contiguous().clone()
+            assert self.u.dtype == torch.float64 and self.u.numel() == nu
+        self.x = torch.empty_like(self.x0)
+        self.status = torch.empty(W, dtype=torch.int32, device=self.x0.device)
+        self.xbar = torch.zeros_like(self.x0) if grad else None
+        self.x0bar = torch.empty_like(self.x0) if grad else None
+        self.ubar = torch.empty_like(self.u) if (grad and nu) else None
+        self._arr = (_P * W)(*[m.h for m in models])
+        self.models = models
+        b = Batch(W, C.cast(self._arr, _P), int(n_int), float(dt))
+        o = opts if opts is not None else default_opts()
+        h = _P()
+        _check(_lib.dmx_graph_create(C.byref(b), C.byref(o), _ptr(self.x0), _ptr(self.u), _ptr(self.x),
+                                     _ptr(self.status), _ptr(self.xbar), _ptr(self.x0bar), _ptr(self.ubar),
+                                     _stream(), C.byref(h)))
+        self.h = h
+
+    def replay(self):
+        _check(_lib.dmx_graph_launch(self.h, _stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.dmx_graph_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -134,3 +134,90 @@ def test_budget_admission_and_errors(D):
             srv.poll(10 ** 9)
     finally:
         srv.close()
+
+
+def _mixed_requests(rng, n):
+    """Requests over the three served model families: the controlled cube,
+    the legged chain and stacks of 1, 3 and 5 cubes (control on the top cube)."""
+    cube = W.model_cube_corners(ctrl=True)
+    chain = W.model_chain()
+    chain_x0 = W.chain_walk(n_worlds=1, n_intervals=1)["x0"][0]
+    stacks = {k: W.model_stack(k, tc=0.003, ctrl=True) for k in (1, 3, 5)}
+    out = []
+    for i in range(n):
+        kind = ("cube", "chain", "stack")[i % 3]
+        if kind == "cube":
+            desc, x0, nu = cube, W.cube_toss(seed=100 + i, n_worlds=1, horizon=0.1)["x0"][0], 6
+        elif kind == "chain":
+            desc, x0, nu = chain, chain_x0, 4
+        else:
+            k = (1, 3, 5)[(i // 3) % 3]
+            desc, x0, nu = stacks[k], W.stack_state(np.zeros((k, 2))), 6
+        N, H = int(rng.integers(8, 25)), int(rng.integers(5, 16))
+        u = rng.uniform(-1.0, 1.0, size=(N, H, nu))
+        target = [float(rng.normal(0, 0.1)), float(rng.normal(0, 0.1)), 0.3]
+        out.append((kind, desc, x0, u, target))
+    return out
+
+
+def test_mixed_models_identical_alone_and_in_mix(D):
+    """Cube, chain and stack requests submitted together (batched by model,
+    running concurrently on several streams) give bitwise the results each
+    gives alone."""
+    rng = np.random.default_rng(21)
+    reqs = _mixed_requests(rng, 18)
+    cache = {}
+
+    def model(desc):
+        key = id(desc)
+        if key not in cache:
+            cache[key] = D.Model(desc)
+        return cache[key]
+
+    srv = D.Server(hbm_budget_bytes=8 << 30, max_inflight=16, n_streams=8)
+    try:
+        mix = _wait(srv, [srv.submit(model(d), x0, u, 0.01, t, ctrl_weight=1e-3) for (_, d, x0, u, t) in reqs],
+                    timeout=300.0)
+        for r, (kind, d, *_rest) in zip(mix, reqs):
+            assert (r["status"] == 0).all(), (kind, d["name"], r["status"])
+            assert np.isfinite(r["cost"]).all() and np.isfinite(r["grad_u"]).all(), kind
+        for i in range(len(reqs)):
+            kind, d, x0, u, t = reqs[i]
+            alone = _wait(srv, [srv.submit(model(d), x0, u, 0.01, t, ctrl_weight=1e-3)], timeout=300.0)[0]
+            np.testing.assert_array_equal(alone["cost"], mix[i]["cost"])
+            np.testing.assert_array_equal(alone["grad_u"], mix[i]["grad_u"])
+        print(f"{len(reqs)} mixed requests (cube, chain, stacks of 1/3/5 cubes) equal alone and in the mix")
+    finally:
+        srv.close()
+
+
+def test_served_stack_matches_batched_rollout(D):
+    """A served stack request's costs and control gradients equal a direct
+    batched rollout (top-cube position cost) and its reverse sweep."""
+    import torch
+    rng = np.random.default_rng(23)
+    k, N, H = 4, 12, 8
+    desc = W.model_stack(k, tc=0.003, ctrl=True)
+    m = D.Model(desc)
+    x0 = W.stack_state(np.zeros((k, 2)))
+    u = rng.uniform(-1.0, 1.0, size=(N, H, 6))
+    target = np.array([0.05, -0.03, 0.75])
+    srv = D.Server(hbm_budget_bytes=2 << 30)
+    try:
+        r = _wait(srv, [srv.submit(m, x0, u, 0.01, list(target), ctrl_weight=1e-3)], timeout=300.0)[0]
+    finally:
+        srv.close()
+    assert (r["status"] == 0).all()
+    X0 = torch.tensor(np.tile(x0, N), device="cuda")
+    res = D.rollout_batch([m] * N, X0, torch.tensor(u.reshape(-1), device="cuda"), H, 0.01, tape=True, counters=True)
+    assert (res["status"].cpu().numpy() == 0).all()
+    xT = res["x"].cpu().numpy().reshape(N, 13 * k)
+    top = 7 * (k - 1)
+    cost = ((xT[:, top:top + 3] - target) ** 2).sum(1) + 1e-3 * 0.01 * (u ** 2).sum((1, 2))
+    np.testing.assert_allclose(r["cost"], cost, rtol=1e-12)
+    xbar = np.zeros_like(xT)
+    xbar[:, top:top + 3] = 2 * (xT[:, top:top + 3] - target)
+    _, ub = D.rollout_batch_vjp(res["tape"], torch.tensor(xbar.reshape(-1), device="cuda"))
+    g = ub.cpu().numpy().reshape(N, H, 6) + 2e-3 * 0.01 * u
+    np.testing.assert_allclose(r["grad_u"], g, rtol=1e-10, atol=1e-14)
+    print(f"served stack request ({N} candidates, {k} cubes, {H} intervals) equals the batched rollout")
