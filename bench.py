@@ -26,6 +26,13 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """One progress line on stderr, with the seconds since the start."""
+    print(f"bench: [{time.perf_counter() - T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/clk)
 PEAK_HBM_GBS = 8000.0
@@ -194,11 +201,11 @@ def serve_capacity(D, W, burst, seconds, seed=60):
     grace period as long as the window, and requests arriving in its second
     half wait no longer than 1.5 times the median of the first half plus one
     second."""
-    print(f"bench:   serving capacity: burst of {burst} requests ...", file=sys.stderr, flush=True)
+    progress(f"serving capacity: burst of {burst} requests ...")
     b = serve_leg(D, W, burst / 1e-3, 1e-3 * (burst - 0.5), seed=seed, grace_s=150.0)
     cap = b["completed"] / max(b["measured_over_s"], 1e-9)
     rate = round(0.5 * cap, 3)
-    print(f"bench:   serving at {rate} req/s (half the burst capacity) ...", file=sys.stderr, flush=True)
+    progress(f"serving at {rate} req/s (half the burst capacity) ...")
     r = serve_leg(D, W, rate, seconds, seed=seed + 1, grace_s=seconds)
     h1, h2 = r["p50_ms_first_second_half_arrivals"]
     sustained = bool(r["unfinished"] == 0 and h1 is not None and h2 is not None and h2 <= 1.5 * h1 + 1e3)
@@ -218,7 +225,7 @@ def timed_steps(step, steps, warmup, stream):
     for i in range(warmup):
         step(None)
         torch.cuda.synchronize()
-        print(f"bench:   warm-up step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+        progress(f"warm-up step {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
@@ -229,7 +236,7 @@ def timed_steps(step, steps, warmup, stream):
             # completes without draining the queue of this one
             if k > 0:
                 evs[k - 1][2].synchronize()
-                print(f"bench:   timed step {k}/{steps} done", file=sys.stderr, flush=True)
+                progress(f"timed step {k}/{steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
@@ -261,20 +268,27 @@ def stack_leg(D, W, args, dev):
     xbar = torch.tensor(xb, dtype=torch.float64, device=dev)
     fwd_cnt = torch.zeros((nW, len(D.FWD_COUNTERS)), dtype=torch.int64, device=dev)
     adj_cnt = torch.zeros((nW, len(D.ADJ_COUNTERS)), dtype=torch.int64, device=dev)
+    # launch choices (tape policy, work distribution) tuned on the same
+    # worlds over a 50 ms horizon
+    tuning, tried = (None, [])
+    if not args.no_autotune:
+        tuning, tried = D.autotune_batch(models, x0, None, 1, 0.05)
+        progress(f"autotuned: {tuning}")
+    choice = {} if tuning is None else {"tape_stages": tuning["tape_stages"], "work_queue": tuning["work_queue"]}
     copts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts,
-                           fwd_counters=fwd_cnt.data_ptr(), adj_counters=adj_cnt.data_ptr())
+                           fwd_counters=fwd_cnt.data_ptr(), adj_counters=adj_cnt.data_ptr(), **choice)
     r = D.rollout_batch(models, x0, None, 1, T, opts=copts, tape=True, counters=True)
     tape = r["tape"]
     D.rollout_batch_vjp(tape, xbar)
     torch.cuda.synchronize()
-    print("bench:   counted pass done", file=sys.stderr, flush=True)
+    progress("counted pass done")
     status = r["status"].cpu().numpy()
     n_acc = r["n_acc"].cpu().numpy()
     n_att = n_acc + r["n_rej"].cpu().numpy()
     fu, au = stack_units(fwd_cnt.cpu().numpy(), adj_cnt.cpu().numpy(), ks)
     fwd_flops = algorithmic_flops(fu, STACK_FWD_FLOPS, 0)
     adj_flops = algorithmic_flops(au, STACK_ADJ_FLOPS, 0)
-    opts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts)
+    opts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts, **choice)
     stream = torch.cuda.current_stream()
     failed = (status & ~D.STATUS["CONTACT_OVERFLOW"]) != 0
 
@@ -292,6 +306,7 @@ def stack_leg(D, W, args, dev):
     # only worlds that reach the horizon count as simulated time
     value = float((nW - int(failed.sum())) * T / (ms / 1e3))
     out = {"value": value, "ms_per_step": ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms, "worlds": nW, "horizon": T,
+           "autotune": {"choice": tuning, "tried": tried},
            "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
                                    "hbm_traffic_stacks_1024.md"),
            "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
@@ -565,8 +580,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate of MPC requests, 1/s")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window of the serving leg, s")
-    ap.add_argument("--capacity-burst", type=int, default=16,
-                    help="requests of the serving capacity burst (0: skip the capacity check)")
+    ap.add_argument("--capacity-burst", type=int, default=0,
+                    help="requests of a serving capacity burst followed by an open-loop check at half the measured "
+                         "capacity (0: skip; the saturated C5 window already measures the service rate)")
     ap.add_argument("--capacity-seconds", type=float, default=30.0,
                     help="arrival window of the open-loop check at half the burst capacity, s")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -594,21 +610,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
         return
-    print(f"bench: stack batch ({args.stack_worlds} worlds) ...", file=sys.stderr, flush=True)
+    progress(f"stack batch ({args.stack_worlds} worlds) ...")
     st = stack_leg(D, W, args, dev)
     others = {}
     if not args.no_others:
-        print("bench: sphere latency, cube tosses ...", file=sys.stderr, flush=True)
+        progress(f"sphere latency, cube tosses ...")
         others["sphere_latency"] = sphere_leg(D, W, args, dev)
         others["cube_toss"] = cube_leg(D, W, args, dev)
         if not args.no_chain:
-            print("bench: legged chains ...", file=sys.stderr, flush=True)
+            progress(f"legged chains ...")
             others["chain_walk"] = chain_leg(D, W, args, dev)
-        print("bench: captured segments (graph) A/B ...", file=sys.stderr, flush=True)
+        progress(f"captured segments (graph) A/B ...")
         others["graph_segments"] = graph_ab_leg(D, W, dev)
     serving = None
     if not args.no_serve:
-        print("bench: serving ...", file=sys.stderr, flush=True)
+        progress(f"serving ...")
         serving = serve_leg(D, W, args.serve_rate, args.serve_seconds)
         if args.capacity_burst > 0:
             serving["sustainable"] = serve_capacity(D, W, args.capacity_burst, args.capacity_seconds)
@@ -635,6 +651,7 @@ def main():
         "cpu_baseline": st.get("cpu"),
         "plain_gpu": st.get("plain"),
         "work": st["work"],
+        "autotune": st.get("autotune"),
         "other_workloads": others,
         "serving": serving,
     }

@@ -257,6 +257,28 @@ dmx_status dmx_autotune(dmx_model* model, int32_t n_worlds, int32_t n_intervals,
                         const double* x0, const double* u, void* stream, int32_t* best_lanes, int32_t* n_tried,
                         int32_t* lanes_tried, double* ms_tried);
 
+/* Autotuner over a batch's launch choices (App. D: the batched, persistent
+ * form of the rollouts): the tape policy (stage accelerations stored, or
+ * checkpoints whose stages the reverse sweep solves again), the work
+ * distribution (a device work queue taking the worlds with the most work
+ * first, or one world per workgroup) and, for batches of one free-body or
+ * tree model, every compiled team size (lanes per world, i.e. worlds packed
+ * per wavefront).  Each candidate runs the forward rollout and the reverse
+ * sweep (cotangent 1 on every final-state coordinate) of the caller's batch
+ * (DEVICE x0, u, packed as for dmx_rollout_batch) twice; the second run, on
+ * the tape of the first, is timed with events on the stream.  *best receives
+ * the fastest; tried (host, may be NULL) up to 32 candidates, n_tried their
+ * count.  Pass a representative batch with a short horizon.  Allocates its
+ * own buffers and synchronizes the stream. */
+typedef struct {
+  int32_t lanes_per_world;  /* team size (0 for stack batches: one wavefront per world) */
+  int32_t tape_stages;      /* dmx_solver_opts.tape_stages of the choice (1 or 0) */
+  int32_t work_queue;       /* dmx_solver_opts.work_queue of the choice (1 or -1) */
+  double ms;                /* forward + reverse milliseconds on the tuning batch */
+} dmx_tuning;
+dmx_status dmx_autotune_batch(const dmx_batch* batch, const double* x0, const double* u, void* stream,
+                              dmx_tuning* best, int32_t* n_tried, dmx_tuning* tried);
+
 /* Gradient of sum(x_out_bar * x_out) with respect to x0 and u through the
  * recorded discretization (step sizes held fixed; rejected attempts play no
  * part).  x0_bar [W][nx] and u_bar [W][n_intervals][nu] are overwritten.

@@ -1304,6 +1304,84 @@ dmx_status dmx_graph_create(const dmx_batch* b, const dmx_solver_opts* opts, con
   return DMX_OK;
 }
 
+dmx_status dmx_autotune_batch(const dmx_batch* b, const double* x0, const double* u, void* stream,
+                              dmx_tuning* best, int32_t* n_tried, dmx_tuning* tried) {
+  if (!b || !b->models || b->n_worlds <= 0 || !x0 || !best) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  const int W = b->n_worlds;
+  long long nx = 0, nu = 0;
+  bool uniform = true;
+  for (int w = 0; w < W; ++w) {
+    const dmx_model* m = b->models[w];
+    if (!m) return fail(DMX_ERR_INVALID_ARG, "null model in batch");
+    nx += m->nq + m->nv;
+    nu += (long long)b->n_intervals * m->nu;
+    uniform = uniform && m == b->models[0];
+  }
+  if (nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
+  const dmx_model* m0 = b->models[0];
+  std::vector<int> teams;
+  if (uniform && m0->kind != 2) {
+    for (const KernelEntry* kp : all_kernels())
+      if (kp->kind == m0->kind && kp->nc == m0->ncb && (m0->kind != 1 || (kp->nv == m0->nv && kp->nb == m0->nb)))
+        teams.push_back(kp->team);
+    if (teams.empty()) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model");
+  } else {
+    teams.push_back(0);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double *xo = nullptr, *xb = nullptr, *x0b = nullptr, *ub = nullptr;
+  int* st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&xo, sizeof(double) * nx);
+  if (e == hipSuccess) e = hipMalloc(&xb, sizeof(double) * nx);
+  if (e == hipSuccess) e = hipMalloc(&x0b, sizeof(double) * nx);
+  if (e == hipSuccess && nu) e = hipMalloc(&ub, sizeof(double) * nu);
+  if (e == hipSuccess) e = hipMalloc(&st, sizeof(int) * W);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto cleanup = [&]() {
+    for (void* p : {(void*)xo, (void*)xb, (void*)x0b, (void*)ub, (void*)st}) if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (e != hipSuccess) { cleanup(); return fail(DMX_ERR_OUT_OF_MEMORY, "autotune buffers"); }
+  {
+    std::vector<double> ones((size_t)nx, 1.0);
+    if (hipMemcpy(xb, ones.data(), sizeof(double) * nx, hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail(DMX_ERR_HIP, "autotune cotangent");
+    }
+  }
+  int count = 0;
+  bool have = false;
+  for (int team : teams)
+    for (int stages : {1, 0})
+      for (int queue : {1, -1}) {
+        dmx_solver_opts o;
+        dmx_default_opts(&o);
+        o.lanes_per_world = team;
+        o.tape_stages = stages;
+        o.work_queue = queue;
+        dmx_tape* tape = nullptr;
+        float ms = 0.0f;
+        dmx_status r = graph_segment(b, &o, x0, u, xo, st, xb, x0b, ub, &tape, s);  // allocates the tape
+        if (r == DMX_OK && hipEventRecord(e0, s) != hipSuccess) r = fail(DMX_ERR_HIP, "event record");
+        if (r == DMX_OK) r = graph_segment(b, &o, x0, u, xo, st, xb, x0b, ub, &tape, s);
+        if (r == DMX_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          r = fail(DMX_ERR_HIP, "autotune timing");
+        if (tape) dmx_tape_destroy(tape);
+        if (r != DMX_OK) { cleanup(); return r; }
+        const dmx_tuning t{team, stages, queue, (double)ms};
+        if (tried && count < 32) tried[count] = t;
+        ++count;
+        if (!have || t.ms < best->ms) { *best = t; have = true; }
+      }
+  cleanup();
+  if (n_tried) *n_tried = count;
+  return DMX_OK;
+}
+
 dmx_status dmx_graph_launch(dmx_graph* g, void* stream) {
   if (!g || !g->exec) return fail(DMX_ERR_INVALID_ARG, "null graph");
   HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));

@@ -547,3 +547,29 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class Tuning(C.Structure):
+    _fields_ = [("lanes_per_world", C.c_int32), ("tape_stages", C.c_int32), ("work_queue", C.c_int32),
+                ("ms", C.c_double)]
+
+
+_lib.dmx_autotune_batch.argtypes = [C.POINTER(Batch), _P, _P, _P, C.POINTER(Tuning), C.POINTER(C.c_int32),
+                                    C.POINTER(Tuning)]
+_lib.dmx_autotune_batch.restype = C.c_int32
+EXPORTS += ["dmx_autotune_batch"]
+
+
+def autotune_batch(models, x0, u, n_int, dt):
+    """Launch choices (tape policy, work distribution, team size) timed on
+    this batch (dmx_autotune_batch).  Returns (best, tried): dicts with
+    lanes_per_world, tape_stages, work_queue and ms."""
+    W = len(models)
+    arr = (_P * W)(*[m.h for m in models])
+    b = Batch(W, C.cast(arr, _P), int(n_int), float(dt))
+    x0 = x0.contiguous()
+    u = u.contiguous() if u is not None else None
+    best, tried, n = Tuning(), (Tuning * 32)(), C.c_int32()
+    _check(_lib.dmx_autotune_batch(C.byref(b), _ptr(x0), _ptr(u), _stream(), C.byref(best), C.byref(n), tried))
+    as_dict = lambda t: {f[0]: getattr(t, f[0]) for f in Tuning._fields_}  # noqa: E731
+    return as_dict(best), [as_dict(tried[i]) for i in range(min(n.value, 32))]

@@ -76,3 +76,25 @@ def test_graph_replays_equal_eager_calls(D, case):
         print(f"{case}: 4 replays bitwise equal to the eager calls")
     finally:
         g.close()
+
+
+def test_autotune_batch_choices(D):
+    """The batch autotuner times every candidate (tape policy x work
+    distribution, x team size for one free-body model) and its choice runs."""
+    import torch
+    ks = [4, 2, 6, 1, 3]
+    models = [D.Model(W.model_stack(k, tc=0.003)) for k in ks]
+    rng = np.random.default_rng(41)
+    x0 = _t(np.concatenate([W.stack_state(rng.normal(0, 0.01, (k, 2))) for k in ks]))
+    best, tried = D.autotune_batch(models, x0, None, 1, 0.02)
+    assert len(tried) == 4 and {(t["tape_stages"], t["work_queue"]) for t in tried} == {(1, 1), (1, -1), (0, 1), (0, -1)}
+    assert best["ms"] == min(t["ms"] for t in tried) and best["lanes_per_world"] == 0
+    opts = D.default_opts(tape_stages=best["tape_stages"], work_queue=best["work_queue"])
+    r = D.rollout_batch(models, x0, None, 1, 0.02, opts=opts, tape=True)
+    assert (r["status"].cpu().numpy() == 0).all()
+    cube = D.Model(W.model_cube_corners())
+    xc = _t(W.cube_toss(seed=3, n_worlds=256, horizon=0.02)["x0"].reshape(-1))
+    best_c, tried_c = D.autotune_batch([cube] * 256, xc, None, 1, 0.02)
+    teams = sorted({t["lanes_per_world"] for t in tried_c})
+    assert len(tried_c) == 4 * len(teams) and best_c["lanes_per_world"] in teams
+    print(f"stack batch: {best}; cube batch: {best_c} (teams {teams})")
