@@ -1,9 +1,11 @@
 """Benchmark: batched forward + adjoint rollouts on one MI355X.
 
-A step is one pass of the whole hot path over one batch: dmx_rollout_batch
-(adaptive Dormand-Prince 5(4) with the soft-contact Newton solve, tape of
-accepted steps) followed by dmx_rollout_vjp (discrete adjoint of the summed
-final cube positions), on the uneven stack batch: 1024 worlds, each a stack of
+A step is one pass of the whole hot path over one batch: dmx_rollout_batch_grad,
+the forward rollout (adaptive Dormand-Prince 5(4) with the soft-contact Newton
+solve, tape of accepted steps) and the discrete adjoint of the summed final
+cube positions in one launch, each world's reverse sweep run by its wavefront
+right after its forward rollout (the same step as two launches, forwards then
+reverses, is timed beside it), on the uneven stack batch: 1024 worlds, each a stack of
 k ~ U{1..32} free cubes (edge 0.2 m, 1 kg) with plane-box and box-box
 contacts, lateral offsets N(0, 0.02) m, mu 0.6, t_c ~ U(1, 5) ms per world,
 1 s horizon, rtol 1e-6, atol 1e-8, FP64 throughout, all worlds in one
@@ -256,6 +258,14 @@ def roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, fwd_name, adj_name, traffi
                              "achieved_tflops": round(oth_flops / (oth_ms / 1e3) / 1e12, 4)}}
 
 
+def roofline_single(ms, flops, name, traffic_file):
+    achieved = flops / (ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 6), "traffic": recorded_traffic(name, traffic_file),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": name, "kernel_ms": round(ms, 3), "flops_per_launch": flops}
+
+
 def stack_leg(D, W, args, dev):
     """The uneven stack batch (headline): 1024 worlds of 1..32 cubes."""
     import torch
@@ -277,9 +287,8 @@ def stack_leg(D, W, args, dev):
     choice = {} if tuning is None else {"tape_stages": tuning["tape_stages"], "work_queue": tuning["work_queue"]}
     copts = D.default_opts(tape_steps=args.stack_tape, max_attempts=args.max_attempts,
                            fwd_counters=fwd_cnt.data_ptr(), adj_counters=adj_cnt.data_ptr(), **choice)
-    r = D.rollout_batch(models, x0, None, 1, T, opts=copts, tape=True, counters=True)
+    r = D.rollout_batch_grad(models, x0, None, 1, T, xbar, opts=copts, counters=True)
     tape = r["tape"]
-    D.rollout_batch_vjp(tape, xbar)
     torch.cuda.synchronize()
     progress("counted pass done")
     status = r["status"].cpu().numpy()
@@ -292,7 +301,20 @@ def stack_leg(D, W, args, dev):
     stream = torch.cuda.current_stream()
     failed = (status & ~D.STATUS["CONTACT_OVERFLOW"]) != 0
 
+    # one step: every world's forward rollout and, right after it on the same
+    # wavefront, its reverse sweep (dmx_rollout_batch_grad: one launch)
     def step(ev):
+        if ev:
+            ev[0].record(stream)
+        D.rollout_batch_grad(models, x0, None, 1, T, xbar, opts=opts, reuse=tape)
+        if ev:
+            ev[1].record(stream)
+            ev[2].record(stream)
+
+    ms, grad_ms, _ = timed_steps(step, args.steps, args.warmup, stream)
+
+    # the same step as two launches (all forwards, then all reverses), for comparison
+    def step2(ev):
         if ev:
             ev[0].record(stream)
         D.rollout_batch(models, x0, None, 1, T, opts=opts, reuse=tape)
@@ -302,13 +324,21 @@ def stack_leg(D, W, args, dev):
         if ev:
             ev[2].record(stream)
 
-    ms, fwd_ms, adj_ms = timed_steps(step, args.steps, args.warmup, stream)
+    two_ms, fwd_ms, adj_ms = (None, None, None)
+    if args.two_launch_steps > 0:
+        progress("two-launch form ...")
+        two_ms, fwd_ms, adj_ms = timed_steps(step2, args.two_launch_steps, 0, stream)
     # only worlds that reach the horizon count as simulated time
     value = float((nW - int(failed.sum())) * T / (ms / 1e3))
-    out = {"value": value, "ms_per_step": ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms, "worlds": nW, "horizon": T,
+    out = {"value": value, "ms_per_step": ms, "grad_ms": grad_ms, "worlds": nW, "horizon": T,
            "autotune": {"choice": tuning, "tried": tried},
-           "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
-                                   "hbm_traffic_stacks_1024.md"),
+           "roofline": roofline_single(grad_ms, fwd_flops + adj_flops, "stack_grad_kernel",
+                                       "hbm_traffic_stacks_1024.md"),
+           "two_launch": None if two_ms is None else {
+               "ms_per_step": round(two_ms, 3), "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3),
+               "value": round(float((nW - int(failed.sum())) * T / (two_ms / 1e3)), 3),
+               "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
+                                       "hbm_traffic_stacks_1024.md")},
            "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
                     "accepted_steps_max": int(n_acc.max()), "attempts_max": int(n_att.max()),
                     "cubes_mean": float(ks.mean()), "cubes_total": int(ks.sum()),
@@ -317,7 +347,7 @@ def stack_leg(D, W, args, dev):
                     "failed_world_attempts": {int(w): int(n_att[w]) for w in np.nonzero(failed)[0][:16]},
                     "max_attempts_per_world": args.max_attempts,
                     "overflow_worlds": int(((status & D.STATUS["CONTACT_OVERFLOW"]) != 0).sum()),
-                    "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}}
+                    "fwd_flops": fwd_flops, "adj_flops": adj_flops, "grad_ms": round(grad_ms, 3)}}
     if not args.no_plain:
         # plain GPU form: the same kernels, one world per launch, on a seeded sample
         rng = np.random.default_rng(11)
@@ -571,6 +601,8 @@ def main():
                     help="step attempts per world before it stops with status 1")
     ap.add_argument("--other-steps", type=int, default=3, help="timed steps of the cube and sphere legs")
     ap.add_argument("--plain-worlds", type=int, default=16)
+    ap.add_argument("--two-launch-steps", type=int, default=2,
+                    help="timed steps of the stack batch as two launches (forwards, then reverses); 0 skips")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -644,12 +676,14 @@ def main():
         "config": {"workload": f"cube_stacks: {st['worlds']} worlds of k ~ U{{1..{args.kmax}}} free cubes "
                                f"(plane-box and box-box contacts), lateral offsets N(0, 0.02) m, mu 0.6, "
                                f"t_c ~ U(1, 5) ms, {st['horizon']} s, rtol 1e-6 atol 1e-8, fwd + adjoint of the "
-                               f"summed final cube positions, one persistent launch",
+                               f"summed final cube positions, one persistent launch (each world's reverse "
+                               f"sweep right after its forward rollout)",
                    "worlds": st["worlds"], "horizon_s": st["horizon"], "cubes_total": st["work"]["cubes_total"],
                    "parallelism": "1 GPU, one wavefront per world, device work queue (most cubes first)"},
         "roofline": st["roofline"],
         "cpu_baseline": st.get("cpu"),
         "plain_gpu": st.get("plain"),
+        "two_launch": st.get("two_launch"),
         "work": st["work"],
         "autotune": st.get("autotune"),
         "other_workloads": others,

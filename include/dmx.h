@@ -239,6 +239,26 @@ dmx_status dmx_rollout_batch(const dmx_batch* batch, const dmx_solver_opts* opts
                              const double* u, double* x_out, int32_t* world_status, int32_t* n_accepted,
                              int32_t* n_rejected, dmx_tape** tape, void* stream);
 
+/* Forward rollout and reverse sweep of an uneven batch in one persistent
+ * launch, for a final-state cotangent known before the rollout (a loss linear
+ * in the final state, as the summed final positions, or a fixed direction):
+ * each wavefront runs its world's forward rollout and then, on the tape it
+ * has just written, that world's reverse sweep (the discrete adjoint of
+ * Sec. 3 with the steps of App. D's batched rollouts), so the launch lasts as
+ * long as the slowest world's forward plus reverse instead of the slowest
+ * forward plus the slowest reverse.  Arguments as for dmx_rollout_batch
+ * followed by dmx_rollout_vjp on its tape: x_out_bar (DEVICE, packed, input),
+ * x0_bar and u_bar (DEVICE, packed, overwritten; u_bar required when a model
+ * has controls); tape is required (created or reused as for
+ * dmx_rollout_batch) and may be passed to dmx_rollout_vjp afterwards for
+ * other cotangents.  Results equal those two calls bitwise; worlds whose
+ * forward status is nonzero get NaN gradients.  fwd_counters and
+ * adj_counters of opts both count. */
+dmx_status dmx_rollout_batch_grad(const dmx_batch* batch, const dmx_solver_opts* opts, const double* x0,
+                                  const double* u, const double* x_out_bar, double* x_out, int32_t* world_status,
+                                  int32_t* n_accepted, int32_t* n_rejected, double* x0_bar, double* u_bar,
+                                  dmx_tape** tape, void* stream);
+
 /* Per-world layout of a tape's records (host arrays [n_worlds]): world w's
  * records start at records + t_off[w] and are rec[w] doubles long (t_n, h_n,
  * interval, y_n, then the stage accelerations a_1..a_6 unless the tape holds

@@ -747,7 +747,8 @@ static dmx_status stack_tables_upload(const StackLayout& L, void* dev, hipStream
 static dmx_status stack_rollout(const std::vector<const dmx_model*>& ms, int n_int, double dt,
                                 const dmx_solver_opts& o, const double* x0, const double* u, double* x_out,
                                 int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, dmx_tape** tape,
-                                hipStream_t s, int* scratch_queue = nullptr) {
+                                hipStream_t s, int* scratch_queue = nullptr, const double* x_out_bar = nullptr,
+                                double* x0_bar = nullptr, double* u_bar = nullptr) {
   const int W = (int)ms.size();
   bool uniform = true;
   for (const dmx_model* m : ms) uniform = uniform && m == ms[0];
@@ -825,7 +826,14 @@ static dmx_status stack_rollout(const std::vector<const dmx_model*>& ms, int n_i
     a.t_stride = tp->sa.t_stride; a.cap_uniform = tp->sa.cap_uniform;
     a.queue = use_queue ? tp->sa.queue : nullptr;
     a.tape = tp->records; a.n_acc = tp->n_acc; a.status = tp->status;
-    dmx_host::stack_fwd(a, s, o.launch_mode);
+    if (x_out_bar) {  // each world's reverse sweep right after its forward rollout
+      a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
+      a.adj_counters = (long long*)o.adj_counters;
+      dmx_host::stack_grad(a, s, o.launch_mode);
+      a.xbar = nullptr; a.x0bar = nullptr; a.ubar = nullptr; a.adj_counters = nullptr;
+    } else {
+      dmx_host::stack_fwd(a, s, o.launch_mode);
+    }
     HIP_TRY(hipGetLastError());
     tp->sa = a;
     tp->sa.queue = use_queue ? (int*)((char*)tp->stk_tables + (tp->stk_tables_bytes - 256)) : nullptr;
@@ -906,6 +914,30 @@ dmx_status dmx_rollout_batch(const dmx_batch* b, const dmx_solver_opts* opts, co
   }
   return stack_rollout(ms, b->n_intervals, b->interval_dt, o, x0, u, x_out, world_status, n_accepted, n_rejected,
                        tape, (hipStream_t)stream);
+}
+
+dmx_status dmx_rollout_batch_grad(const dmx_batch* b, const dmx_solver_opts* opts, const double* x0,
+                                  const double* u, const double* x_out_bar, double* x_out, int32_t* world_status,
+                                  int32_t* n_accepted, int32_t* n_rejected, double* x0_bar, double* u_bar,
+                                  dmx_tape** tape, void* stream) {
+  if (!b || (b->n_worlds > 0 && !b->models) || !tape) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (b->n_worlds < 0 || b->n_intervals <= 0 || !(b->interval_dt > 0.0)) return fail(DMX_ERR_INVALID_ARG, "bad batch sizes");
+  dmx_solver_opts o;
+  if (opts) o = *opts; else dmx_default_opts(&o);
+  const dmx_status oc = check_opts(o);
+  if (oc != DMX_OK) return oc;
+  if (b->n_worlds == 0) { if (!*tape) *tape = nullptr; return DMX_OK; }
+  if (!x0 || !x_out || !world_status || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  std::vector<const dmx_model*> ms(b->models, b->models + b->n_worlds);
+  bool any_ctrl = false;
+  for (const dmx_model* m : ms) {
+    if (!m) return fail(DMX_ERR_INVALID_ARG, "null model in batch");
+    if (!m->stack_ok) return fail(DMX_ERR_UNSUPPORTED, "batches of mixed models take stacks of cubes (k >= 1)");
+    any_ctrl = any_ctrl || m->nu > 0;
+  }
+  if (any_ctrl && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  return stack_rollout(ms, b->n_intervals, b->interval_dt, o, x0, u, x_out, world_status, n_accepted, n_rejected,
+                       tape, (hipStream_t)stream, nullptr, x_out_bar, x0_bar, u_bar);
 }
 
 dmx_status dmx_tape_layout(const dmx_tape* tp, int64_t* t_off, int32_t* rec) {

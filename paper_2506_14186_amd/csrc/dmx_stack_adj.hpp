@@ -448,4 +448,27 @@ __global__ void __launch_bounds__(64) stack_adj_kernel(StackArgs a) {
   }
 }
 
+// Forward rollout and reverse sweep of each world in one persistent launch,
+// for a final-state cotangent given before the rollout: a wavefront that has
+// finished a world's forward rollout runs that world's reverse sweep on the
+// tape it has just written, so the launch lasts as long as the slowest world's
+// forward plus reverse rather than the slowest forward plus the slowest
+// reverse (worlds differ by orders of magnitude in work, App. D).
+template <bool RECOMPUTE>
+__global__ void __launch_bounds__(64) stack_grad_kernel(StackArgs a) {
+  __shared__ StackLds S;
+  for (bool first = true;; first = false) {
+    const int w = stack_take(a, nullptr, first);
+    if (w < 0) break;
+    const StackModel& m = st_model(a, w);
+    stack_fwd_world(m, S, a, w);
+    // the tape records, step count and status just stored by the lanes are
+    // read back by other lanes of the wavefront
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    stack_adj_world<RECOMPUTE>(m, S, a, w);
+  }
+}
+
 }  // namespace dmx

@@ -70,14 +70,17 @@ _lib.dmx_batch_layout.argtypes = [_P, _P, _P, _P, _P]
 _lib.dmx_rollout_batch.argtypes = [_P, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P, C.POINTER(_P), _P]
 _lib.dmx_rollout_noalloc.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, C.POINTER(SolverOpts), _P, _P, _P, _P,
                                      _P, _P, _P]
+_lib.dmx_rollout_batch_grad.argtypes = [_P, C.POINTER(SolverOpts), _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        C.POINTER(_P), _P]
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
            "dmx_tape_data", "dmx_accel", "dmx_autotune", "dmx_tape_layout", "dmx_batch_layout",
-           "dmx_rollout_batch", "dmx_rollout_noalloc"):
+           "dmx_rollout_batch", "dmx_rollout_noalloc", "dmx_rollout_batch_grad"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
            "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_autotune",
-           "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout", "dmx_rollout_noalloc"]
+           "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout", "dmx_rollout_noalloc",
+           "dmx_rollout_batch_grad"]
 
 
 class Batch(C.Structure):
@@ -349,6 +352,47 @@ def rollout_batch(models, x0, u, n_int, dt, opts=None, tape=False, counters=Fals
         reuse.keep = (x0, u)
         res["tape"] = reuse
     elif tape:
+        res["tape"] = BatchTape(th, models, n_int, xo, uo, nx, nu)
+        res["tape"].keep = (x0, u)
+    return res
+
+
+def rollout_batch_grad(models, x0, u, n_int, dt, x_out_bar, opts=None, counters=False, reuse=None):
+    """Forward rollout and reverse sweep of an uneven batch in one launch for
+    a final-state cotangent x_out_bar given up front (packed, CUDA float64).
+    Returns dict(x, status, x0_bar, u_bar, tape[, n_acc, n_rej]); the tape
+    serves later rollout_batch_vjp calls and reuse=."""
+    W = len(models)
+    xo, uo, nx, nu = batch_layout(models, n_int)
+    x0 = x0.contiguous()
+    assert x0.dtype == torch.float64 and x0.is_cuda and x0.numel() == nx
+    xb = x_out_bar.contiguous()
+    assert xb.dtype == torch.float64 and xb.is_cuda and xb.numel() == nx
+    if nu:
+        u = u.contiguous()
+        assert u.dtype == torch.float64 and u.numel() == nu
+    else:
+        u = None
+    arr = (_P * W)(*[m.h for m in models])
+    b = Batch(W, C.cast(arr, _P), int(n_int), float(dt))
+    x_out = torch.empty_like(x0)
+    x0b = torch.empty_like(x0)
+    ub = torch.empty(nu, dtype=torch.float64, device=x0.device) if nu else None
+    status = torch.empty(W, dtype=torch.int32, device=x0.device)
+    nacc = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    nrej = torch.zeros(W, dtype=torch.int32, device=x0.device) if counters else None
+    o = opts if opts is not None else default_opts()
+    th = _P(reuse.h.value if isinstance(reuse.h, _P) else reuse.h) if reuse is not None else _P()
+    _check(_lib.dmx_rollout_batch_grad(C.byref(b), C.byref(o), _ptr(x0), _ptr(u), _ptr(xb), _ptr(x_out),
+                                       _ptr(status), _ptr(nacc), _ptr(nrej), _ptr(x0b), _ptr(ub), C.byref(th),
+                                       _stream()))
+    res = {"x": x_out, "status": status, "x0_bar": x0b, "u_bar": ub, "x_off": xo, "u_off": uo}
+    if counters:
+        res["n_acc"], res["n_rej"] = nacc, nrej
+    if reuse is not None:
+        reuse.keep = (x0, u)
+        res["tape"] = reuse
+    else:
         res["tape"] = BatchTape(th, models, n_int, xo, uo, nx, nu)
         res["tape"].keep = (x0, u)
     return res

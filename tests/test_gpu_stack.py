@@ -242,6 +242,65 @@ def test_uneven_batch_equals_separate_launches(D):
         assert int(res["n_acc"][w]) == int(r1["n_acc"][0])
 
 
+@pytest.mark.parametrize("stages,queue,plain", [(1, 1, 0), (0, 1, 0), (1, -1, 0), (1, 1, 1)],
+                         ids=["stages-queue", "checkpoints-queue", "stages-per-block", "plain"])
+def test_fused_grad_equals_rollout_then_vjp(D, stages, queue, plain):
+    """Forward and reverse of each world in one launch (the cotangent given up
+    front) give bitwise the end states, step counts and gradients of the
+    forward launch followed by the reverse launch, for every tape policy and
+    work distribution; the tape it leaves serves further cotangents and is
+    reused in place."""
+    descs, xs = _stacks([3, 1, 6, 2, 5, 4, 7, 1, 2], seed=21)
+    xs[2] = _tossed(6, 5)
+    xs[6] = _tossed(7, 8)
+    models = [D.Model(d) for d in descs]
+    x0 = _t(np.concatenate(xs))
+    xb = _t(np.concatenate([_sum_positions(d, x) for d, x in zip(descs, xs)]))
+    xb2 = _t(np.random.default_rng(3).normal(size=xb.numel()))
+    opts = D.default_opts(max_attempts=MAXATT, tape_steps=4096, tape_stages=stages, work_queue=queue,
+                          launch_mode=plain)
+    ref = D.rollout_batch(models, x0, None, 1, 0.2, opts=opts, tape=True, counters=True)
+    g_ref, _ = D.rollout_batch_vjp(ref["tape"], xb)
+    g2_ref, _ = D.rollout_batch_vjp(ref["tape"], xb2)
+    f = D.rollout_batch_grad(models, x0, None, 1, 0.2, xb, opts=opts, counters=True)
+    assert int(f["status"].abs().sum()) == 0, f["status"]
+    for key in ("x", "status", "n_acc", "n_rej"):
+        np.testing.assert_array_equal(f[key].cpu().numpy(), ref[key].cpu().numpy())
+    np.testing.assert_array_equal(f["x0_bar"].cpu().numpy(), g_ref.cpu().numpy())
+    g2, _ = D.rollout_batch_vjp(f["tape"], xb2)
+    np.testing.assert_array_equal(g2.cpu().numpy(), g2_ref.cpu().numpy())
+    again = D.rollout_batch_grad(models, x0, None, 1, 0.2, xb2, opts=opts, reuse=f["tape"])
+    np.testing.assert_array_equal(again["x0_bar"].cpu().numpy(), g2_ref.cpu().numpy())
+    print(f"fused forward+reverse bitwise equal to two launches ({len(models)} worlds, "
+          f"{int(ref['n_acc'].sum())} accepted steps)")
+
+
+def test_fused_grad_stopped_worlds_get_nan(D):
+    """Worlds stopped by the attempt cap get NaN gradients in the fused launch,
+    as in the reverse launch, the others finite gradients; null arguments are
+    refused."""
+    descs, xs = _stacks([4, 1, 3], seed=22)
+    xs[0] = _tossed(4, 9)
+    models = [D.Model(d) for d in descs]
+    x0 = _t(np.concatenate(xs))
+    xb = _t(np.concatenate([_sum_positions(d, x) for d, x in zip(descs, xs)]))
+    opts = D.default_opts(max_attempts=40, tape_steps=4096)
+    ref = D.rollout_batch(models, x0, None, 1, 0.2, opts=opts, tape=True, counters=True)
+    g_ref, _ = D.rollout_batch_vjp(ref["tape"], xb)
+    f = D.rollout_batch_grad(models, x0, None, 1, 0.2, xb, opts=opts, counters=True)
+    st = f["status"].cpu().numpy()
+    assert st[0] != 0, st
+    np.testing.assert_array_equal(st, ref["status"].cpu().numpy())
+    g = f["x0_bar"].cpu().numpy()
+    np.testing.assert_array_equal(g, g_ref.cpu().numpy())
+    xo = f["x_off"]
+    for w, x in enumerate(xs):
+        gw = g[xo[w]:xo[w] + x.size]
+        assert np.isnan(gw).all() if st[w] != 0 else np.isfinite(gw).all(), (w, st[w])
+    rc = D._lib.dmx_rollout_batch_grad(None, None, None, None, None, None, None, None, None, None, None, None, None)
+    assert rc < 0
+
+
 def test_stack_batch_api_errors(D):
     """Models that are not stacks of cubes are refused by the batch call."""
     sphere = D.Model(W.model_sphere())
