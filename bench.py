@@ -59,16 +59,27 @@ ADJ_FLOPS = {
 }
 
 
-# Cube-stack worlds: per-unit algorithmic FP64 operations; units counted by
-# the kernels per world and scaled by the world's cube count k on the host.
+# Cube-stack worlds: per-unit algorithmic FP64 operations of the forward,
+# fitted to the oracle's operation counter (orc_flop_count: the oracle's own
+# rollout in a counting scalar, structural zeros of J, M and H skipped) over
+# 28 worlds of 1..31 cubes, settled and tossed (largest deviation per phase:
+# step 1%, right-hand side 2%, Newton iterations with their line searches 6%;
+# tests/test_flop_table.py checks held-out worlds within 10%).  Units are
+# counted by the kernels per world; per-body and per-pair units are scaled by
+# the world's cube count k and neighbour-pair count k - 1 on the host.
 STACK_FWD_FLOPS = {
-    "body_attempts": 1650,     # 6 stage combinations of 6 dofs, 6 (+)-maps, error terms of 13 coordinates
-    "body_rhs": 850,           # frame, twist, a0; the neighbour pair's separating-axis test and face clipping
-    "rhs_contacts": 100,       # frame, impedance, reference acceleration of a contact
-    "body_newton_iters": 1300, # block assembly, 6x6 block Cholesky step, forward and backward block solves
-    "newton_contacts": 500,    # rows, edge slacks, Hessian and gradient sums of an active contact
-    "ls_contacts": 250,        # line-search slopes of a contact per iteration
+    "body_attempts": 1190,         # stage combinations, (+)-maps, error estimate of one body
+    "body_rhs": 730,               # frames, mass-matrix blocks, bias, a0 of one body
+    "pair_rhs": 1050,              # separating-axis test and face clipping of one neighbour pair
+    "rhs_contacts_plane": 145,     # frame, Jacobian rows, impedance, reference acceleration (plane-box contact)
+    "rhs_contacts_pair": 470,      # the same for a box-box contact (two bodies' Jacobian blocks)
+    "body_newton_iters": 210,      # gradient, 6x6 block factorization and solves, line-search terms of a body
+    "pair_newton_iters": 180,      # coupling block of a neighbour pair in the factorization and solves
+    "newton_contacts_plane": 590,  # Hessian and gradient terms, activity and line-search slopes (plane-box)
+    "newton_contacts_pair": 2650,  # the same for a box-box contact (12 x 12 Hessian terms per edge)
 }
+# The reverse sweep: planning figures (the oracle differentiates in forward
+# mode, so it has no reverse sweep to count).
 STACK_ADJ_FLOPS = {
     "body_steps": 2000,        # 7 stage rebuilds, (+)-map VJPs and tableau distribution of 6 dofs
     "body_vjps": 2300,         # frames, contacts, Hessian assembly, block Cholesky and solve for lambda, bias VJP
@@ -77,11 +88,14 @@ STACK_ADJ_FLOPS = {
 
 
 def stack_units(fc, ac, ks):
-    """Per-world counters [W][7] and [W][4] to the stack units."""
+    """Per-world counters [W][9] and [W][4] to the stack units."""
     fc, ac, ks = np.asarray(fc, float), np.asarray(ac, float), np.asarray(ks, float)
     return ({"body_attempts": float((fc[:, 0] * ks).sum()), "body_rhs": float((fc[:, 1] * ks).sum()),
-             "rhs_contacts": float(fc[:, 2].sum()), "body_newton_iters": float((fc[:, 3] * ks).sum()),
-             "newton_contacts": float(fc[:, 4].sum()), "ls_contacts": float(fc[:, 6].sum())},
+             "pair_rhs": float((fc[:, 1] * (ks - 1)).sum()),
+             "rhs_contacts_plane": float((fc[:, 2] - fc[:, 7]).sum()), "rhs_contacts_pair": float(fc[:, 7].sum()),
+             "body_newton_iters": float((fc[:, 3] * ks).sum()), "pair_newton_iters": float((fc[:, 3] * (ks - 1)).sum()),
+             "newton_contacts_plane": float((fc[:, 4] - fc[:, 8]).sum()),
+             "newton_contacts_pair": float(fc[:, 8].sum()), "ls_contacts": float(fc[:, 6].sum())},
             {"body_steps": float((ac[:, 0] * ks).sum()), "body_vjps": float((ac[:, 1] * ks).sum()),
              "vjp_contacts": float(ac[:, 2].sum())})
 

@@ -135,9 +135,11 @@ typedef struct {
   int32_t* log_n;
   int32_t log_cap;
   /* instrumentation (device pointers, may be NULL): per-world work units of
-   * the forward, [n_worlds][7] = attempts, rhs evaluations, active contacts
+   * the forward, [n_worlds][9] = attempts, rhs evaluations, active contacts
    * over rhs evaluations, Newton iterations, active contacts and active edges
-   * over Newton iterations, line-search contact evaluations; and of the
+   * over Newton iterations, line-search contact evaluations, then the active
+   * contacts over rhs evaluations and over Newton iterations of those
+   * contacts that join two bodies (box-box pairs of stacks); and of the
    * reverse sweep, [n_worlds][4] = steps, acceleration vjps, active contacts
    * and active edges over vjps (written by dmx_rollout_vjp on this tape). */
   int64_t* fwd_counters;

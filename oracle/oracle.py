@@ -34,6 +34,12 @@ def build(force=True):
     return LIB_PATH
 
 
+def flop_cholesky(A):
+    """Counted operations of the oracle's Cholesky factorization and solve of A."""
+    A = np.ascontiguousarray(np.asarray(A, np.float64))
+    return int(lib().orc_flop_cholesky(_p(A), A.shape[0]))
+
+
 class _ModelDef(C.Structure):
     _fields_ = [("nb", C.c_int), ("nj", C.c_int), ("ng", C.c_int), ("npair", C.c_int), ("nu", C.c_int)] + [
         (n, C.c_void_p) for n in (
@@ -87,6 +93,9 @@ def lib():
         L.orc_rollout_jvp_forced.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, C.c_int, C.c_int,
                                              P, P, P, P]
         L.orc_attempt.argtypes = [P, P, P, C.c_double, C.POINTER(_Opts), P, P]
+        L.orc_flop_count.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P]
+        L.orc_flop_cholesky.argtypes = [P, C.c_int]
+        L.orc_flop_cholesky.restype = C.c_longlong
         L.orc_next_step.argtypes = [C.POINTER(_Opts), C.c_double, C.c_double, C.c_double, C.c_int, P]
         L.orc_next_step.restype = C.c_double
         _lib = L
@@ -237,6 +246,23 @@ class Model:
             res["tape"] = tape[:min(tape_cap, res["n_acc"])]
         if log is not None:
             res["log"] = log[:min(log_cap, res["n_acc"] + res["n_rej"])]
+        return res
+
+    FLOP_PHASES = ("step", "rhs", "newton", "line_search", "other")
+
+    def flop_count(self, x0, u, n_int, dt, **opts):
+        """Floating-point operations of the forward rollout by phase, and its
+        work units (attempts, rhs, newton_iters, contacts per rhs, active
+        contacts per Newton iteration, contacts per line-search segment)."""
+        o = make_opts(**opts)
+        x0 = _f64(x0)
+        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        out = np.zeros(16, np.int64)
+        lib().orc_flop_count(self.h, _p(x0), _p(u), int(n_int), float(dt), C.byref(o), _p(out))
+        res = {f"flops_{p}": int(out[i]) for i, p in enumerate(self.FLOP_PHASES)}
+        res.update(attempts=int(out[5]), rhs=int(out[6]), newton_iters=int(out[7]), rhs_contacts=int(out[8]),
+                   newton_contacts=int(out[9]), ls_contacts=int(out[10]), n_acc=int(out[11]), status=int(out[12]),
+                   rhs_contacts_box=int(out[13]), newton_contacts_box=int(out[14]), ls_contacts_box=int(out[15]))
         return res
 
     def rollout_jvp(self, x0, u, n_int, dt, dx0, du=None, **opts):

@@ -94,6 +94,24 @@ int orc_rhs_jvp(const void* m, const double* x, const double* u, int st, double 
 int orc_rollout(const void* m, const double* x0, const double* u, int n_int, double dt_int,
                 const orc_opts* o, const double* forced, int n_forced, double* x_out, long long* counters,
                 int tape_cap, double* tape, int log_cap, double* steplog);
+/* operation count of one world's forward rollout (the rollout of orc_rollout,
+ * run in a counting scalar, one thread).  out[16]: floating-point operations
+ * by phase (0 the attempt's stage combinations, (+)-maps and error estimate,
+ * 1 the right-hand side outside the contact solve: kinematics, mass matrix,
+ * collision, contact rows, 2 Newton iterations: gradient, Hessian assembly,
+ * factorization, solve, activity tests, 3 line searches, 4 other), then
+ * attempts, right-hand sides, Newton iterations, contacts summed over
+ * right-hand sides, contacts with an active edge summed over Newton
+ * iterations, contacts summed over line-search segments, accepted steps,
+ * status, then the three contact sums again for contacts between two bodies
+ * only.  Operations with a structurally zero or unit operand are not
+ * counted. */
+int orc_flop_count(const void* m, const double* x0, const double* u, int n_int, double dt_int,
+                   const orc_opts* o, long long* out);  /* out[16] */
+/* operation count of the oracle's Cholesky factorization and two triangular
+ * solves of the n x n row-major matrix A (zero entries structural); -1 if A
+ * is not positive definite. */
+long long orc_flop_cholesky(const double* A, int n);
 /* forward-mode tangents of the rollout with frozen steps (taken from its own
  * adaptive run).  dx0: n_dir*nx, du: n_dir*n_int*nu, tx: n_dir*nx. */
 int orc_rollout_jvp(const void* m, const double* x0, const double* u, int n_int, double dt_int,

@@ -76,6 +76,96 @@ template <int N> inline Dual<N> pow_(const Dual<N>& a, double p) {
   double fp = (a.v == 0.0) ? (p == 1.0 ? 1.0 : 0.0) : p * std::pow(a.v, p - 1.0);
   return chain(a, f, fp); }
 
+// ---------------------------------------------------------------- operation counter
+// Flop: a double that tallies the floating-point operations made on it, by
+// phase of the method, for the algorithmic operation counts of a rollout (a
+// fused multiply-add counts as a multiply and an add; a division, a square
+// root or an elementary function as one).  Operations with a structurally
+// trivial operand are not counted: adding a structural zero, multiplying by a
+// structural zero or by a constant +-1, dividing by a constant +-1.  A
+// structural zero is a literal zero of the code (an accumulator's start, the
+// zero blocks of J, M and H that the oracle's dense loops visit, a zero
+// coefficient of the tableau) or a result computed only from such zeros;
+// values that come from the inputs (Flop::data) are never trivial, whatever
+// their value.  The dense loops then count what the same steps cost when they
+// skip the zero blocks (the body-block structure a batched implementation
+// exploits).  Comparisons and absolute values are not counted.
+enum { kPhStep = 0, kPhRhs = 1, kPhNewton = 2, kPhLineSearch = 3, kPhOther = 4, kPhases = 5 };
+struct FlopTally { long long n[kPhases]; };
+inline FlopTally& flop_tally() { static thread_local FlopTally t{}; return t; }
+inline int& flop_phase() { static thread_local int p = kPhOther; return p; }
+inline void flop_count() { flop_tally().n[flop_phase()] += 1; }
+// sets the phase for the lifetime of the object, then restores the previous one
+struct FlopPhase {
+  int prev;
+  explicit FlopPhase(int p) : prev(flop_phase()) { flop_phase() = p; }
+  ~FlopPhase() { flop_phase() = prev; }
+};
+
+struct Flop {
+  double v;
+  bool zero;  // structural zero
+  bool unit;  // constant +-1
+  Flop() : v(0.0), zero(true), unit(false) {}
+  Flop(double x) : v(x), zero(x == 0.0), unit(x == 1.0 || x == -1.0) {}  // NOLINT: a constant of the code
+  static Flop data(double x) { Flop f(x); f.zero = false; f.unit = false; return f; }
+  static Flop result(double x, bool z) { Flop f(x); f.zero = z; f.unit = false; return f; }
+};
+inline double val(const Flop& x) { return x.v; }
+inline Flop operator+(const Flop& a, const Flop& b) {
+  if (a.zero) return b;
+  if (b.zero) return a;
+  flop_count();
+  return Flop::result(a.v + b.v, false);
+}
+inline Flop operator-(const Flop& a) { Flop r = a; r.v = -a.v; return r; }
+inline Flop operator-(const Flop& a, const Flop& b) {
+  if (b.zero) return a;
+  if (a.zero) return -b;
+  flop_count();
+  return Flop::result(a.v - b.v, false);
+}
+inline Flop operator*(const Flop& a, const Flop& b) {
+  if (a.zero || b.zero) return Flop::result(a.v * b.v, true);
+  if (a.unit) return a.v > 0.0 ? b : -b;
+  if (b.unit) return b.v > 0.0 ? a : -a;
+  flop_count();
+  return Flop::result(a.v * b.v, false);
+}
+inline Flop operator/(const Flop& a, const Flop& b) {
+  if (a.zero) return Flop::result(a.v / b.v, true);
+  if (b.unit) return b.v > 0.0 ? a : -a;
+  flop_count();
+  return Flop::result(a.v / b.v, false);
+}
+inline Flop operator+(const Flop& a, double b) { return a + Flop(b); }
+inline Flop operator+(double a, const Flop& b) { return Flop(a) + b; }
+inline Flop operator-(const Flop& a, double b) { return a - Flop(b); }
+inline Flop operator-(double a, const Flop& b) { return Flop(a) - b; }
+inline Flop operator*(const Flop& a, double b) { return a * Flop(b); }
+inline Flop operator*(double a, const Flop& b) { return Flop(a) * b; }
+inline Flop operator/(const Flop& a, double b) { return a / Flop(b); }
+inline Flop operator/(double a, const Flop& b) { return Flop(a) / b; }
+inline Flop& operator+=(Flop& a, const Flop& b) { a = a + b; return a; }
+inline Flop& operator-=(Flop& a, const Flop& b) { a = a - b; return a; }
+inline Flop& operator*=(Flop& a, const Flop& b) { a = a * b; return a; }
+inline Flop& operator/=(Flop& a, const Flop& b) { a = a / b; return a; }
+inline Flop flop_fn(const Flop& a, double r) { if (a.zero) return Flop::result(r, r == 0.0); flop_count(); return Flop::result(r, false); }
+inline Flop sqrt_(const Flop& a) { return flop_fn(a, std::sqrt(a.v)); }
+inline Flop sin_(const Flop& a) { return flop_fn(a, std::sin(a.v)); }
+inline Flop cos_(const Flop& a) { flop_count(); return Flop::result(std::cos(a.v), false); }
+inline Flop exp_(const Flop& a) { flop_count(); return Flop::result(std::exp(a.v), false); }
+inline Flop log1p_(const Flop& a) { return flop_fn(a, std::log1p(a.v)); }
+inline Flop pow_(const Flop& a, double p) { return flop_fn(a, std::pow(a.v, p)); }
+
+// value of a scalar in the value-only scalar T (double, or Flop keeping the
+// counting scalar's structure), and a data value in T
+inline double to_value(const double& x, const double*) { return x; }
+template <int N> inline double to_value(const Dual<N>& x, const double*) { return x.v; }
+inline Flop to_value(const Flop& x, const Flop*) { return x; }
+inline Flop to_value(const double& x, const Flop*) { return Flop::data(x); }
+template <class T, class S> inline T value_as(const S& x) { return to_value(x, (const T*)nullptr); }
+
 // ---------------------------------------------------------------- 3-vectors
 template <class S> struct V3 { S x[3]; };
 template <class S> struct M3 { S a[3][3]; };  // a[row][col]

@@ -21,6 +21,14 @@ using DualT = Dual<kDir>;
 
 inline void set_val(double& x, double v) { x = v; }
 template <int N> inline void set_val(Dual<N>& x, double v) { x.v = v; }
+inline void set_val(Flop& x, double v) { x.v = v; }
+// scalar of the value-only parts (Newton iterations, error estimate): double,
+// or the counting scalar when the rollout is counted
+template <class S> struct ValueOf { using type = double; };
+template <> struct ValueOf<Flop> { using type = Flop; };
+// a value-only result back in the rollout's scalar
+template <class S> struct FromValue { static S get(double x) { return S(x); } };
+template <> struct FromValue<Flop> { static Flop get(const Flop& x) { return x; } };
 template <class S> inline bool is_dual() { return false; }
 template <> inline bool is_dual<DualT>() { return true; }
 
@@ -616,49 +624,71 @@ static void chol_solve(const std::vector<S>& L, int n, std::vector<S>& x) {
 // Newton direction of the current active set and the exact minimizer of the
 // convex piecewise quadratic along it (breakpoints sorted, segments scanned),
 // and stops when the active set no longer changes.
-struct NewtonOut { std::vector<double> x; std::vector<char> active; int iters; bool ok; };
+template <class T>
+struct NewtonOut {
+  std::vector<T> x;
+  std::vector<char> active;
+  int iters;
+  bool ok;
+  long long active_contacts = 0;    // contacts with an active edge, summed over iterations
+  long long contact_segments = 0;   // contacts times line-search segments scanned
+  long long active_box = 0, segments_box = 0;  // the same for contacts between two bodies
+};
 
-static double line_search(const std::vector<double>& M, const std::vector<double>& a0,
-                          const std::vector<Row<double>>& rows, const std::vector<double>& x,
-                          const std::vector<double>& dl, int nv) {
-  double dMd = 0.0, xMd = 0.0;
-  for (int i = 0; i < nv; ++i)
-    for (int j = 0; j < nv; ++j) { dMd += dl[i] * M[i * nv + j] * dl[j]; xMd += (x[i] - a0[i]) * M[i * nv + j] * dl[j]; }
+template <class T>
+static T line_search(const std::vector<T>& M, const std::vector<T>& a0, const std::vector<Row<T>>& rows,
+                     const std::vector<T>& x, const std::vector<T>& dl, int nv, long long* contact_segments,
+                     long long* segments_box) {
+  FlopPhase phase(kPhLineSearch);
+  T dMd = 0.0, xMd = 0.0;
+  for (int i = 0; i < nv; ++i) {
+    const T dxi = x[i] - a0[i];
+    for (int j = 0; j < nv; ++j) { dMd += dl[i] * M[i * nv + j] * dl[j]; xMd += dxi * M[i * nv + j] * dl[j]; }
+  }
   size_t nr = rows.size();
-  std::vector<double> s(nr), t(nr), bp;
+  std::vector<T> s(nr), t(nr);
+  std::vector<double> bp;
   for (size_t e = 0; e < nr; ++e) {
-    double jx = 0.0, jd = 0.0;
+    T jx = 0.0, jd = 0.0;
     for (int i = 0; i < nv; ++i) { jx += rows[e].J[i] * x[i]; jd += rows[e].J[i] * dl[i]; }
     s[e] = jx - rows[e].aref; t[e] = jd;
-    if (jd != 0.0 && -s[e] / jd > 0.0) bp.push_back(-s[e] / jd);
+    if (val(jd) != 0.0) {
+      const double b = val(-(s[e] / jd));
+      if (b > 0.0) bp.push_back(b);
+    }
   }
   std::sort(bp.begin(), bp.end());
   double lo = 0.0;
   for (size_t seg = 0; seg <= bp.size(); ++seg) {
     bool last = seg == bp.size();
     double hi = last ? 0.0 : bp[seg];
-    double mid = last ? lo + 1.0 : 0.5 * (lo + hi);
-    double c2 = dMd, c1 = xMd;
+    const T tlo = value_as<T>(lo);
+    T mid = last ? tlo + 1.0 : T(0.5) * (tlo + value_as<T>(hi));
+    T c2 = dMd, c1 = xMd;
+    *contact_segments += (long long)(nr / 4);
+    for (size_t c = 0; c + 3 < nr; c += 4) *segments_box += rows[c].nz.size() > 6 ? 1 : 0;
     for (size_t e = 0; e < nr; ++e)
-      if (s[e] + mid * t[e] < 0.0) { c2 += rows[e].D * t[e] * t[e]; c1 += rows[e].D * t[e] * s[e]; }
-    double ar = -c1 / c2;
-    if (last || ar <= hi) return std::max(ar, lo);
+      if (val(s[e] + mid * t[e]) < 0.0) { c2 += rows[e].D * t[e] * t[e]; c1 += rows[e].D * t[e] * s[e]; }
+    T ar = -(c1 / c2);
+    if (last || val(ar) <= hi) return val(ar) < lo ? T(lo) : ar;
     lo = hi;
   }
-  return lo;
+  return T(lo);
 }
 
-static NewtonOut newton(const std::vector<double>& M, const std::vector<double>& a0,
-                        const std::vector<Row<double>>& rows, int nv, int maxit) {
-  NewtonOut o;
+template <class T>
+static NewtonOut<T> newton(const std::vector<T>& M, const std::vector<T>& a0, const std::vector<Row<T>>& rows, int nv,
+                           int maxit) {
+  FlopPhase phase(kPhNewton);
+  NewtonOut<T> o;
   o.x = a0; o.iters = 0; o.ok = true;
   size_t nr = rows.size();
-  auto act = [&](const std::vector<double>& x) {
+  auto act = [&](const std::vector<T>& x) {
     std::vector<char> a(nr);
     for (size_t e = 0; e < nr; ++e) {
-      double jx = 0.0;
+      T jx = 0.0;
       for (int i = 0; i < nv; ++i) jx += rows[e].J[i] * x[i];
-      a[e] = (jx - rows[e].aref) < 0.0;
+      a[e] = val(jx - rows[e].aref) < 0.0;
     }
     return a;
   };
@@ -667,24 +697,31 @@ static NewtonOut newton(const std::vector<double>& M, const std::vector<double>&
   for (char c : o.active) any = any || c;
   if (!any) return o;  // no force: x = a0 is optimal
   for (int it = 0; it < maxit; ++it) {
-    std::vector<double> g(nv, 0.0), H = M;
+    for (size_t c = 0; c + 3 < nr; c += 4)
+    {
+      const bool on = o.active[c] | o.active[c + 1] | o.active[c + 2] | o.active[c + 3];
+      o.active_contacts += on ? 1 : 0;
+      o.active_box += (on && rows[c].nz.size() > 6) ? 1 : 0;
+    }
+    std::vector<T> g(nv, T(0.0)), H = M, dx(nv);
+    for (int j = 0; j < nv; ++j) dx[j] = o.x[j] - a0[j];
     for (int i = 0; i < nv; ++i)
-      for (int j = 0; j < nv; ++j) g[i] += M[i * nv + j] * (o.x[j] - a0[j]);
+      for (int j = 0; j < nv; ++j) g[i] += M[i * nv + j] * dx[j];
     for (size_t e = 0; e < nr; ++e) {
       if (!o.active[e]) continue;
-      double jx = 0.0;
+      T jx = 0.0;
       for (int i = 0; i < nv; ++i) jx += rows[e].J[i] * o.x[i];
-      double se = jx - rows[e].aref;
+      T se = jx - rows[e].aref;
       for (int i : rows[e].nz) {
         g[i] += rows[e].D * se * rows[e].J[i];
         for (int j : rows[e].nz) H[i * nv + j] += rows[e].D * rows[e].J[i] * rows[e].J[j];
       }
     }
     if (!cholesky(H, nv)) { o.ok = false; return o; }
-    std::vector<double> dl(nv);
+    std::vector<T> dl(nv);
     for (int i = 0; i < nv; ++i) dl[i] = -g[i];
     chol_solve(H, nv, dl);
-    double alpha = line_search(M, a0, rows, o.x, dl, nv);
+    T alpha = line_search(M, a0, rows, o.x, dl, nv, &o.contact_segments, &o.segments_box);
     for (int i = 0; i < nv; ++i) o.x[i] += alpha * dl[i];
     o.iters = it + 1;
     std::vector<char> na = act(o.x);
@@ -720,7 +757,15 @@ static double quantize_step(double h, int levels) {
   return std::ldexp(k / (2.0 * levels), e);
 }
 
-struct Stats { long long rhs = 0, newton_it = 0; int status = 0; int nrows = 0, nactive = 0; };
+struct Stats {
+  long long rhs = 0, newton_it = 0;
+  int status = 0;
+  int nrows = 0, nactive = 0;
+  // work units: contacts per right-hand side, contacts with an active edge
+  // per Newton iteration, contacts per line-search segment scanned (summed)
+  long long contacts = 0, newton_contacts = 0, ls_contacts = 0;
+  long long contacts_box = 0, newton_contacts_box = 0, ls_contacts_box = 0;  // between two bodies
+};
 
 // F(t, x) = (v, qacc) with qacc the minimizer of the primal problem, i.e. the
 // acceleration of eq. EOM under the soft contact forces (Sec. 2 and App. C.2
@@ -731,6 +776,7 @@ struct Stats { long long rhs = 0, newton_it = 0; int status = 0; int nrows = 0, 
 template <class S>
 static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, int maxit, S* kout,
                 Stats* st, std::vector<double>* forces = nullptr) {
+  FlopPhase phase(kPhRhs);
   int nv = m.nv;
   const S* q = y;
   const S* v = y + m.nq;
@@ -752,34 +798,41 @@ static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, i
   make_rows(m, kin, cons, v, cfd, beta, rows, &overflow);
   if (overflow) st->status |= ORC_CONTACT_OVERFLOW;
   st->rhs += 1;
+  st->contacts += (long long)(rows.size() / 4);
+  for (size_t c = 0; c + 3 < rows.size(); c += 4) st->contacts_box += rows[c].nz.size() > 6 ? 1 : 0;
   st->nrows = (int)rows.size();
   for (int i = 0; i < nv; ++i) kout[i] = v[i];
   if (forces) forces->assign(rows.size(), 0.0);
   if (rows.empty()) { for (int i = 0; i < nv; ++i) kout[nv + i] = a0[i]; st->nactive = 0; return; }
-  std::vector<double> Md(nv * nv), a0d(nv);
-  for (int i = 0; i < nv * nv; ++i) Md[i] = val(M[i]);
-  for (int i = 0; i < nv; ++i) a0d[i] = val(a0[i]);
-  std::vector<Row<double>> rd(rows.size());
+  using T = typename ValueOf<S>::type;
+  std::vector<T> Md(nv * nv), a0d(nv);
+  for (int i = 0; i < nv * nv; ++i) Md[i] = value_as<T>(M[i]);
+  for (int i = 0; i < nv; ++i) a0d[i] = value_as<T>(a0[i]);
+  std::vector<Row<T>> rd(rows.size());
   for (size_t e = 0; e < rows.size(); ++e) {
     rd[e].J.resize(nv);
     rd[e].nz = rows[e].nz;
-    for (int i = 0; i < nv; ++i) rd[e].J[i] = val(rows[e].J[i]);
-    rd[e].aref = val(rows[e].aref); rd[e].D = val(rows[e].D);
+    for (int i = 0; i < nv; ++i) rd[e].J[i] = value_as<T>(rows[e].J[i]);
+    rd[e].aref = value_as<T>(rows[e].aref); rd[e].D = value_as<T>(rows[e].D);
   }
-  NewtonOut no = newton(Md, a0d, rd, nv, maxit);
+  NewtonOut<T> no = newton(Md, a0d, rd, nv, maxit);
   st->newton_it += no.iters;
+  st->newton_contacts += no.active_contacts;
+  st->ls_contacts += no.contact_segments;
+  st->newton_contacts_box += no.active_box;
+  st->ls_contacts_box += no.segments_box;
   if (!no.ok) st->status |= ORC_SOLVER_MAXIT;
   int na = 0;
   for (char a : no.active) na += a;
   st->nactive = na;
   if (forces)
     for (size_t e = 0; e < rows.size(); ++e) {
-      double jx = 0.0;
+      T jx = 0.0;
       for (int i = 0; i < nv; ++i) jx += rd[e].J[i] * no.x[i];
-      (*forces)[e] = no.active[e] ? rd[e].D * (rd[e].aref - jx) : 0.0;
+      (*forces)[e] = no.active[e] ? val(rd[e].D * (rd[e].aref - jx)) : 0.0;
     }
   if (!is_dual<S>() || na == 0) {
-    for (int i = 0; i < nv; ++i) { kout[nv + i] = na == 0 ? a0[i] : S(no.x[i]); set_val(kout[nv + i], no.x[i]); }
+    for (int i = 0; i < nv; ++i) { kout[nv + i] = na == 0 ? a0[i] : FromValue<S>::get(no.x[i]); set_val(kout[nv + i], val(no.x[i])); }
     return;
   }
   std::vector<S> H = M, b = f0;
@@ -792,7 +845,7 @@ static void rhs(const Model& m, const S* y, const S* u, bool cfd, double beta, i
   }
   if (!cholesky(H, nv)) st->status |= ORC_NONFINITE;
   chol_solve(H, nv, b);
-  for (int i = 0; i < nv; ++i) { kout[nv + i] = b[i]; set_val(kout[nv + i], no.x[i]); }
+  for (int i = 0; i < nv; ++i) { kout[nv + i] = b[i]; set_val(kout[nv + i], val(no.x[i])); }
 }
 
 // Straight-through rule at the ODE level (Sec. 4): the value is F (no CFD),
@@ -862,6 +915,7 @@ struct Log {
 template <class S>
 static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::vector<S>& k1, double h,
                             const Opts& o, bool want_err, S* ynew, std::vector<S>& k7, Stats* st) {
+  FlopPhase phase(kPhStep);
   int nq = m.nq, nv = m.nv, nx = nq + nv;
   std::vector<std::vector<S>> K(7, std::vector<S>(2 * nv));
   K[0] = k1;
@@ -879,40 +933,39 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
   for (int i = 0; i < nx; ++i) ynew[i] = Y[i];  // stage 7 is evaluated at y_new (FSAL)
   k7 = K[6];
   if (!want_err) return 0.0;
-  std::vector<double> e(nx, 0.0), dqh(nv);
-  std::vector<double> yhat(nq);
+  using T = typename ValueOf<S>::type;
+  std::vector<T> e(nx, T(0.0)), dqh(nv);
+  std::vector<T> yhat(nq);
   for (int d = 0; d < nv; ++d) {
-    double sh = 0.0, se = 0.0, sa = 0.0;
+    T sh = 0.0, sa = 0.0;
     for (int i = 0; i < 7; ++i) {
-      sh += val(K[i][d]) * RK_BH[i];
-      se += val(K[i][d]) * (RK_B[i] - RK_BH[i]);
-      sa += val(K[i][nv + d]) * (RK_B[i] - RK_BH[i]);
+      sh += value_as<T>(K[i][d]) * RK_BH[i];
+      sa += value_as<T>(K[i][nv + d]) * (RK_B[i] - RK_BH[i]);
     }
     dqh[d] = sh * h;
     e[nq + d] = sa * h;
-    (void)se;
   }
-  std::vector<double> yv(nq);
-  for (int i = 0; i < nq; ++i) yv[i] = val(y[i]);
+  std::vector<T> yv(nq);
+  for (int i = 0; i < nq; ++i) yv[i] = value_as<T>(y[i]);
   qplus(m, yv.data(), dqh.data(), yhat.data());
-  for (int i = 0; i < nq; ++i) e[i] = val(ynew[i]) - yhat[i];
+  for (int i = 0; i < nq; ++i) e[i] = value_as<T>(ynew[i]) - yhat[i];
   // scalar coordinates: use the difference form h sum (b - bh) k directly
   for (int j = 0; j < m.nj; ++j) {
     int qa = m.jqadr[j], da = m.jdadr[j];
     int nlin = m.jtype[j] == J_FREE ? 3 : 1;
     for (int i = 0; i < nlin; ++i) {
-      double se = 0.0;
-      for (int s = 0; s < 7; ++s) se += val(K[s][da + i]) * (RK_B[s] - RK_BH[s]);
+      T se = 0.0;
+      for (int s = 0; s < 7; ++s) se += value_as<T>(K[s][da + i]) * (RK_B[s] - RK_BH[s]);
       e[qa + i] = se * h;
     }
   }
-  double acc = 0.0;
+  T acc = 0.0;
   for (int i = 0; i < nx; ++i) {
-    double sc = o.atol + o.rtol * std::max(std::fabs(val(y[i])), std::fabs(val(ynew[i])));
-    double r = e[i] / sc;
+    T sc = T(o.atol) + T(o.rtol) * value_as<T>(std::max(std::fabs(val(y[i])), std::fabs(val(ynew[i]))));
+    T r = e[i] / sc;
     acc += r * r;
   }
-  return std::sqrt(acc / nx);
+  return val(sqrt_(acc / T((double)nx)));
 }
 
 static bool finite_vec(const double* x, int n) {
@@ -1245,6 +1298,51 @@ extern "C" int orc_rollout(const void* mp, const double* x0, const double* u, in
   }
   if (counters) { counters[0] = lg.n_acc; counters[1] = lg.n_rej; counters[2] = st.rhs; counters[3] = st.newton_it; counters[4] = st.status; }
   return st.status;
+}
+
+// Operation count of a forward rollout: the same rollout in the counting
+// scalar (values equal those of orc_rollout), per phase of the method.
+extern "C" int orc_flop_count(const void* mp, const double* x0, const double* u, int n_int, double dt_int,
+                              const orc_opts* op, long long* out) {
+  const Model& m = *static_cast<const Model*>(mp);
+  Opts o = to_opts(op);
+  const int nx = m.nq + m.nv;
+  std::vector<Flop> X(nx), U, Y(nx);
+  for (int i = 0; i < nx; ++i) X[i] = Flop::data(x0[i]);
+  for (size_t i = 0; i < (size_t)n_int * m.nu; ++i) U.push_back(Flop::data(u[i]));
+  if (U.empty()) U.assign(1, Flop(0.0));
+  Log lg;
+  Stats st;
+  FlopTally& t = flop_tally();
+  const FlopTally before = t;
+  rollout<Flop>(m, X.data(), U.data(), n_int, dt_int, o, nullptr, 0, Y.data(), &lg, &st);
+  for (int p = 0; p < kPhases; ++p) out[p] = t.n[p] - before.n[p];
+  out[5] = lg.n_acc + lg.n_rej;
+  out[6] = st.rhs;
+  out[7] = st.newton_it;
+  out[8] = st.contacts;
+  out[9] = st.newton_contacts;
+  out[10] = st.ls_contacts;
+  out[11] = lg.n_acc;
+  out[12] = st.status;
+  out[13] = st.contacts_box;
+  out[14] = st.newton_contacts_box;
+  out[15] = st.ls_contacts_box;
+  return st.status;
+}
+
+// Operation count of the oracle's Cholesky factorization and solve of an n x n
+// matrix (row-major; zero entries are taken as structural zeros, the others
+// as data), for checking the counting rules against closed forms.
+extern "C" long long orc_flop_cholesky(const double* A, int n) {
+  std::vector<Flop> L(n * n), x(n);
+  for (int i = 0; i < n * n; ++i) L[i] = A[i] == 0.0 ? Flop(0.0) : Flop::data(A[i]);
+  for (int i = 0; i < n; ++i) x[i] = Flop::data(1.0 + i);
+  FlopPhase phase(kPhOther);
+  const long long before = flop_tally().n[kPhOther];
+  if (!cholesky(L, n)) return -1;
+  chol_solve(L, n, x);
+  return flop_tally().n[kPhOther] - before;
 }
 
 // forward-mode pass with frozen steps: y tangents for up to kDir directions

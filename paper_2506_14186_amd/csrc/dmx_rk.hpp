@@ -81,7 +81,9 @@ DMX_DEV double quantize_step(double h, int levels) {
   return ldexp(k / (2.0 * levels), e);
 }
 
-constexpr int kFwdCounters = 7;  // attempts, rhs, contacts, newton its, newton contacts, edges, line search
+// attempts, rhs, contacts, newton its, newton contacts, edges, line search,
+// then contacts and newton contacts between two bodies (stacks)
+constexpr int kFwdCounters = 9;
 constexpr int kAdjCounters = 4;  // steps, vjps, vjp contacts, vjp edges
 
 // Per-world layout of a batch and its work distribution.  Null arrays mean
@@ -529,7 +531,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
   team_store<NX, L>(a.xout + (size_t)w * NX, y, tl);
   if (a.counters) {
     double c[kFwdCounters] = {(double)st.u_att, (double)st.u_rhs, (double)st.u_con, (double)st.u_nit,
-                              (double)st.u_ncon, (double)st.u_nedge, (double)st.u_ls};
+                              (double)st.u_ncon, (double)st.u_nedge, (double)st.u_ls, 0.0, 0.0};
     team_sum_arr<L, kFwdCounters>(c);
     if (tl == 0)
       for (int i = 0; i < kFwdCounters; ++i) a.counters[(size_t)w * kFwdCounters + i] = (long long)c[i];

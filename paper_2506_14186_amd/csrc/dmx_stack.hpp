@@ -110,6 +110,7 @@ enum { kVecX = 0, kVecV = 1, kVecD = 2 };
 struct StackStat {
   int status, newton_it;
   long long u_att, u_rhs, u_con, u_nit, u_ncon, u_nedge, u_ls;
+  long long u_con2, u_ncon2;  // contacts and Newton contacts of box pairs
   long long u_step, u_vjp, u_vcon, u_vedge;
 };
 
@@ -864,7 +865,13 @@ DMX_DEV void stack_newton(const StackModel& m, StackLds& S, const StackRole& ro,
     st.newton_it++;
     if (ro.lane == 0) st.u_nit++;
     assemble(m, S, ro, ps, cfd, beta, x, a0);
-    if (ro.pair) { st.u_nedge += __popc(ps.act); for (int j = 0; j < ps.cnt; ++j) st.u_ncon += ((ps.act >> (4 * j)) & 15u) != 0u; }
+    if (ro.pair) {
+      st.u_nedge += __popc(ps.act);
+      int nc = 0;
+      for (int j = 0; j < ps.cnt; ++j) nc += ((ps.act >> (4 * j)) & 15u) != 0u;
+      st.u_ncon += nc;
+      if (ro.pair == 2) st.u_ncon2 += nc;
+    }
     // right-hand side -g
     if (ro.dof) {
 #pragma unroll
@@ -983,6 +990,7 @@ DMX_DEV void stack_acc(const StackModel& m, StackLds& S, const StackRole& ro, co
   PairSlots ps = stack_setup(m, S, ro, yq, yv, cfd, st);
   if (ro.lane == 0) st.u_rhs++;
   if (ro.pair) st.u_con += ps.cnt;
+  if (ro.pair == 2) st.u_con2 += ps.cnt;
   double a0[3];
   stack_a0(m, ro, yv, tau, a0);
   if (st.status & kStGraph) {

@@ -270,7 +270,8 @@ DMX_DEV void stack_fwd_world(const StackModel& m, StackLds& S, const StackArgs& 
   store_state(m, ro, a.xout + st_xoff(a, w), yq, yv);
   if (a.counters) {
     double c[kFwdCounters] = {(double)st.u_att, (double)st.u_rhs, (double)st.u_con, (double)st.u_nit,
-                              (double)st.u_ncon, (double)st.u_nedge, (double)st.u_ls};
+                              (double)st.u_ncon, (double)st.u_nedge, (double)st.u_ls, (double)st.u_con2,
+                              (double)st.u_ncon2};
     wave_sum<kFwdCounters>(c);
     if (ro.lane == 0)
       for (int i = 0; i < kFwdCounters; ++i) a.counters[(size_t)w * kFwdCounters + i] = (long long)c[i];

@@ -48,7 +48,7 @@ class SolverOpts(C.Structure):
         ("work_queue", C.c_int32), ("tape_stages", C.c_int32)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
-                "ls_contacts")
+                "ls_contacts", "rhs_contacts_pair", "newton_contacts_pair")
 ADJ_COUNTERS = ("steps", "vjps", "vjp_contacts", "vjp_edges")
 
 
