@@ -301,6 +301,39 @@ def test_fused_grad_stopped_worlds_get_nan(D):
     assert rc < 0
 
 
+def test_work_counters_match_oracle_units(D, oracle):
+    """The kernels' work counters, which the benchmark multiplies by the
+    per-unit operation counts fitted to the oracle's counter, count the same
+    units as the oracle on the same worlds: attempts, right-hand sides and
+    contacts (all, and those between two cubes) equal where the step
+    sequences are equal; Newton iterations at most the oracle's (the kernels
+    start each stage's solve from the previous stage's solution)."""
+    descs, xs = _stacks([1, 3, 5], seed=31)
+    xs.append(_tossed(4, 12))
+    descs.append(W.model_stack(4, tc=0.003, mu=0.6))
+    models = [D.Model(d) for d in descs]
+    x0 = _t(np.concatenate(xs))
+    import torch
+    fc = torch.zeros((len(models), len(D.FWD_COUNTERS)), dtype=torch.int64, device="cuda")
+    opts = D.default_opts(max_attempts=MAXATT, tape_steps=4096, fwd_counters=fc.data_ptr())
+    res = D.rollout_batch(models, x0, None, 1, 0.05, opts=opts, counters=True)
+    assert int(res["status"].abs().sum()) == 0
+    c = {n: fc[:, i].cpu().numpy() for i, n in enumerate(D.FWD_COUNTERS)}
+    for w, (d, x) in enumerate(zip(descs, xs)):
+        r = oracle.Model(d).flop_count(x, None, 1, 0.05)
+        gpu_att = int(res["n_acc"][w]) + int(res["n_rej"][w])
+        print(f"world {w} (k={x.size // 13}): attempts {c['attempts'][w]}/{r['attempts']}, rhs {c['rhs'][w]}/{r['rhs']}, "
+              f"contacts {c['rhs_contacts'][w]}/{r['rhs_contacts']} (pairs {c['rhs_contacts_pair'][w]}/"
+              f"{r['rhs_contacts_box']}), newton {c['newton_iters'][w]}/{r['newton_iters']}  (GPU/oracle)")
+        assert c["attempts"][w] == gpu_att
+        if gpu_att != r["attempts"]:
+            continue  # step sequences split: units differ with them
+        assert c["rhs"][w] == r["rhs"]
+        assert abs(int(c["rhs_contacts"][w]) - r["rhs_contacts"]) <= 0.01 * r["rhs_contacts"] + 2
+        assert abs(int(c["rhs_contacts_pair"][w]) - r["rhs_contacts_box"]) <= 0.01 * r["rhs_contacts_box"] + 2
+        assert c["newton_iters"][w] <= r["newton_iters"]
+
+
 def test_stack_batch_api_errors(D):
     """Models that are not stacks of cubes are refused by the batch call."""
     sphere = D.Model(W.model_sphere())
