@@ -34,6 +34,13 @@ def build(force=True):
     return LIB_PATH
 
 
+def dense_weights(theta):
+    """Weights of the stage slopes in the Dormand-Prince continuous extension."""
+    w = np.zeros(7)
+    lib().orc_dense_weights(float(theta), _p(w))
+    return w
+
+
 def flop_cholesky(A):
     """Counted operations of the oracle's Cholesky factorization and solve of A."""
     A = np.ascontiguousarray(np.asarray(A, np.float64))
@@ -95,6 +102,10 @@ def lib():
         L.orc_attempt.argtypes = [P, P, P, C.c_double, C.POINTER(_Opts), P, P]
         L.orc_flop_count.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P]
         L.orc_flop_cholesky.argtypes = [P, C.c_int]
+        L.orc_otd_grad_batch.argtypes = [P, C.c_int, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, P, P, P, P,
+                                         C.c_int]
+        L.orc_dense_weights.argtypes = [C.c_double, P]
+        L.orc_dense_states.argtypes = [P, P, P, C.c_int, C.c_double, C.POINTER(_Opts), P, C.c_int, C.c_int, P, P]
         L.orc_flop_cholesky.restype = C.c_longlong
         L.orc_next_step.argtypes = [C.POINTER(_Opts), C.c_double, C.c_double, C.c_double, C.c_int, P]
         L.orc_next_step.restype = C.c_double
@@ -247,6 +258,37 @@ class Model:
         if log is not None:
             res["log"] = log[:min(log_cap, res["n_acc"] + res["n_rej"])]
         return res
+
+    def otd_grad_batch(self, x0, u, n_int, dt, xbar, n_threads=8, **opts):
+        """Optimize-then-discretize gradients of sum(xbar * x(T)): x0bar [W, nx]
+        (quaternion parts tangent at q0), ubar [W, n_int, nu], and the adjoint's
+        attempts and accepted steps."""
+        o = make_opts(**opts)
+        x0 = np.ascontiguousarray(np.asarray(x0, np.float64).reshape(-1, self.nx))
+        W = x0.shape[0]
+        nut = n_int * self.nu
+        u = _f64(u) if u is not None and np.size(u) else np.zeros(max(1, W * nut))
+        xb = np.ascontiguousarray(np.asarray(xbar, np.float64).reshape(W, self.nx))
+        xo, x0b = np.zeros((W, self.nx)), np.zeros((W, self.nx))
+        ub = np.zeros(max(1, W * nut))
+        cnt = np.zeros((W, 4), np.int64)
+        lib().orc_otd_grad_batch(self.h, W, _p(x0), _p(u), int(n_int), float(dt), C.byref(o), _p(xb), _p(xo), _p(x0b),
+                                 _p(ub), _p(cnt), int(n_threads))
+        return dict(x=xo, x0bar=x0b, ubar=ub[:W * nut].reshape(W, n_int, self.nu), adj_attempts=cnt[:, 0],
+                    adj_accepted=cnt[:, 1], n_acc=cnt[:, 2], status=cnt[:, 3])
+
+    def dense_states(self, x0, u, n_int, dt, taus, forced=None, **opts):
+        """x(tau) at the given times from the continuous extension of the rollout's accepted steps."""
+        o = make_opts(**opts)
+        taus = _f64(taus)
+        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        fz = _f64(forced) if forced is not None else None
+        nf = 0 if forced is None else len(fz) // 2
+        out = np.zeros((taus.size, self.nx))
+        st = lib().orc_dense_states(self.h, _p(_f64(x0)), _p(u), int(n_int), float(dt), C.byref(o), _p(fz), nf,
+                                    taus.size, _p(taus), _p(out))
+        assert st == 0, st
+        return out
 
     FLOP_PHASES = ("step", "rhs", "newton", "line_search", "other")
 

@@ -108,6 +108,23 @@ int orc_rollout(const void* m, const double* x0, const double* u, int n_int, dou
  * counted. */
 int orc_flop_count(const void* m, const double* x0, const double* u, int n_int, double dt_int,
                    const orc_opts* o, long long* out);  /* out[16] */
+/* optimize-then-discretize gradients (App. C.2 eq. adjoint-equations; with
+ * cfd, the straight-through adjoint of App. C.4): per world the forward
+ * rollout, then the continuous adjoint equations solved backwards with the
+ * adaptive Dormand-Prince pair (rtol, atol, controller of o) along the
+ * forward's continuous extension.  x0bar [W][nx] (quaternion parts tangent at
+ * q0), ubar [W][n_int][nu]; counters [W][4] = adjoint attempts, adjoint
+ * accepted steps, forward accepted steps, status. */
+int orc_otd_grad_batch(const void* m, int W, const double* x0, const double* u, int n_int, double dt_int,
+                       const orc_opts* o, const double* xbar, double* x_out, double* x0bar, double* ubar,
+                       long long* counters, int n_threads);
+/* weights w[7] of the stage slopes in the Dormand-Prince continuous extension
+ * at the fraction theta of a step. */
+void orc_dense_weights(double theta, double* w);
+/* x(tau) [n_tau][nx] of one world's rollout (forced steps as for orc_rollout)
+ * from the continuous extension of its accepted steps. */
+int orc_dense_states(const void* m, const double* x0, const double* u, int n_int, double dt_int, const orc_opts* o,
+                     const double* forced, int n_forced, int n_tau, const double* tau, double* out);
 /* operation count of the oracle's Cholesky factorization and two triangular
  * solves of the n x n row-major matrix A (zero entries structural); -1 if A
  * is not positive definite. */

@@ -914,7 +914,8 @@ struct Log {
 // nq + nv components of e_j / (atol + rtol max(|y_j|, |y_new_j|)).
 template <class S>
 static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::vector<S>& k1, double h,
-                            const Opts& o, bool want_err, S* ynew, std::vector<S>& k7, Stats* st) {
+                            const Opts& o, bool want_err, S* ynew, std::vector<S>& k7, Stats* st,
+                            std::vector<std::vector<S>>* stages = nullptr) {
   FlopPhase phase(kPhStep);
   int nq = m.nq, nv = m.nv, nx = nq + nv;
   std::vector<std::vector<S>> K(7, std::vector<S>(2 * nv));
@@ -932,6 +933,7 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
   }
   for (int i = 0; i < nx; ++i) ynew[i] = Y[i];  // stage 7 is evaluated at y_new (FSAL)
   k7 = K[6];
+  if (stages) *stages = K;
   if (!want_err) return 0.0;
   using T = typename ValueOf<S>::type;
   std::vector<T> e(nx, T(0.0)), dqh(nv);
@@ -1300,6 +1302,226 @@ extern "C" int orc_rollout(const void* mp, const double* x0, const double* u, in
   return st.status;
 }
 
+// ------------------------------------------------------------------ optimize-then-discretize adjoint
+// The continuous adjoint equations (App. C.2, eq. adjoint-equations; with the
+// straight-through rule, App. C.4: the Jacobian of the CFD field F~ taken at
+// the trajectory of F): for a loss on the final state, a(T) = dL/dx(T) and
+// da/dt = -(dF/dx)^T a, and the controls' gradient a_u = integral over each
+// interval of (dF/du)^T a; dL/dx(0) = a(0).  They are solved backwards in
+// time with the same adaptive Dormand-Prince pair and PI controller as the
+// forward ODE, with its own steps.
+// reading: the state is taken in its raw coordinates, x = (q, v) with the
+// quaternions as 4-vectors, dq/dt = v for positions and hinge/slide joints and
+// (1/2) q (x) (0, omega) for a free joint's quaternion (omega in the body
+// frame); the returned quaternion gradient is projected onto the tangent
+// space of the unit sphere at q(0), as the discrete adjoint's is (its (+) map
+// normalizes).
+// reading: x(t) between the forward's accepted steps is that step's
+// fourth-order continuous extension (Hairer, Norsett and Wanner's dense output
+// of the Dormand-Prince pair), applied to the tangent increment and mapped
+// through (+), rather than the forward ODE solved backwards together with the
+// adjoint (unstable for dissipative contacts); the continuous extension's
+// coefficients are those of that published scheme.
+// reading: the adjoint's error estimate is the RMS over the nq + nv components
+// of a, scaled by atol + rtol max(|a_j|, |a_new_j|) (the forward's norm); its
+// first step is the forward's last step size; its steps land on the control
+// interval ends as the forward's do.
+// reading: the adjoint's steps are floored at 1e-12 max(1, |t|), and a step at
+// the floor is accepted whatever its error estimate: where a contact switches
+// on, dF/dx jumps (by the damping and stiffness terms, up to ~1e4 here), and
+// no step size resolves a jump to a tight tolerance; a floor step carries
+// that jump's error, of order the floor times the jump.
+static const double RK_D[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                               -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                               -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
+
+// weights of the stage slopes in the continuous extension: the increment over
+// the fraction th of a step of size h is h sum_i w_i(th) k_i, with
+// w(th) = th b + th (1 - th) (e_1 - b) + th^2 (1 - th) (2 b - e_1 - e_7)
+//         + th^2 (1 - th)^2 d
+static void dense_weights(double th, double* w) {
+  for (int i = 0; i < 7; ++i) {
+    const double e1 = i == 0 ? 1.0 : 0.0, e7 = i == 6 ? 1.0 : 0.0;
+    w[i] = th * RK_B[i] + th * (1.0 - th) * (e1 - RK_B[i]) + th * th * (1.0 - th) * (2.0 * RK_B[i] - e1 - e7) +
+           th * th * (1.0 - th) * (1.0 - th) * RK_D[i];
+  }
+}
+
+// rates of the raw coordinates from the tangent-form right-hand side k = (v, qacc)
+template <class S>
+static void raw_rates(const Model& m, const S* x, const S* k, S* out) {
+  for (int j = 0; j < m.nj; ++j) {
+    const int qa = m.jqadr[j], da = m.jdadr[j];
+    if (m.jtype[j] == J_FREE) {
+      for (int i = 0; i < 3; ++i) out[qa + i] = k[da + i];
+      Q4<S> q; q.w = x[qa + 3]; q.x = x[qa + 4]; q.y = x[qa + 5]; q.z = x[qa + 6];
+      Q4<S> w; w.w = S(0.0); w.x = k[da + 3]; w.y = k[da + 4]; w.z = k[da + 5];
+      const Q4<S> r = qmul(q, w);
+      out[qa + 3] = r.w * 0.5; out[qa + 4] = r.x * 0.5; out[qa + 5] = r.y * 0.5; out[qa + 6] = r.z * 0.5;
+    } else {
+      out[qa] = k[da];
+    }
+  }
+  for (int d = 0; d < m.nv; ++d) out[m.nq + d] = k[m.nv + d];
+}
+
+// g = (dF/dx)^T lam and gu = (dF/du)^T lam at (x, u) in raw coordinates,
+// from the forward-mode tangents of F (of F~ with CFD on), kDir directions at
+// a time
+static void raw_vjp(const Model& m, const double* x, const double* u, const Opts& o, const double* lam, double* g,
+                    double* gu, Stats* st) {
+  const int nx = m.nq + m.nv, nd = nx + m.nu;
+  std::vector<DualT> X(nx), U(std::max(m.nu, 1)), K(2 * m.nv), R(nx);
+  for (int d0 = 0; d0 < nd; d0 += kDir) {
+    for (int i = 0; i < nx; ++i) { X[i] = DualT(x[i]); if (i >= d0 && i < d0 + kDir) X[i].d[i - d0] = 1.0; }
+    for (int i = 0; i < m.nu; ++i) {
+      U[i] = DualT(u[i]);
+      if (nx + i >= d0 && nx + i < d0 + kDir) U[i].d[nx + i - d0] = 1.0;
+    }
+    rhs_st(m, X.data(), U.data(), o, K.data(), st);
+    raw_rates(m, X.data(), K.data(), R.data());
+    for (int c = d0; c < std::min(nd, d0 + kDir); ++c) {
+      double s = 0.0;
+      for (int r = 0; r < nx; ++r) s += R[r].d[c - d0] * lam[r];
+      if (c < nx) g[c] = s; else gu[c - nx] = s;
+    }
+  }
+}
+
+// One world: the forward rollout (kept: accepted steps), then the adjoint
+// solved backwards.  counters: adjoint attempts, adjoint accepted steps.
+static int otd_world(const Model& m, const double* x0, const double* u, int n_int, double dt, const Opts& o,
+                     const double* xbar, double* x_out, double* x0bar, double* ubar, long long* counters) {
+  const int nq = m.nq, nv = m.nv, nx = nq + nv, nu = m.nu;
+  Log lg;
+  lg.keep_tape = true;
+  Stats st;
+  rollout<double>(m, x0, u, n_int, dt, o, nullptr, 0, x_out, &lg, &st);
+  const size_t nut = (size_t)n_int * nu;
+  if (st.status & ~ORC_CONTACT_OVERFLOW) {
+    for (int i = 0; i < nx; ++i) x0bar[i] = NAN;
+    for (size_t i = 0; i < nut; ++i) ubar[i] = NAN;
+    return st.status;
+  }
+  const int N = (int)lg.n_acc;
+  const size_t rl = 2 + nx;
+  auto t_of = [&](int n) { return lg.tape[n * rl]; };
+  auto h_of = [&](int n) { return lg.tape[n * rl + 1]; };
+  std::vector<double> uz(1, 0.0);
+  auto u_of = [&](int kk) { return nu > 0 ? u + (size_t)kk * nu : uz.data(); };
+  auto interval_of = [&](int n) {
+    int kk = (int)std::floor((t_of(n) + 0.5 * h_of(n)) / dt);
+    return std::min(std::max(kk, 0), n_int - 1);
+  };
+  // stage slopes of accepted step n, solved again (the forward's right-hand
+  // sides are functions of the state: the same values)
+  std::vector<std::vector<std::vector<double>>> slopes(N);
+  auto step_slopes = [&](int n) -> const std::vector<std::vector<double>>& {
+    if (slopes[n].empty()) {
+      const double* y = &lg.tape[n * rl + 2];
+      const double* uk = u_of(interval_of(n));
+      std::vector<double> k1(2 * nv), yn(nx), k7(2 * nv);
+      Stats s2;
+      rhs_st(m, y, uk, o, k1.data(), &s2);
+      dopri_attempt(m, y, uk, k1, h_of(n), o, false, yn.data(), k7, &s2, &slopes[n]);
+    }
+    return slopes[n];
+  };
+  // x(tau) from the continuous extension of the step that holds tau
+  auto dense = [&](double tau, double* xo) {
+    int n = N - 1;
+    for (int i = 0; i < N; ++i)
+      if (tau < t_of(i) + h_of(i)) { n = i; break; }
+    const double h = h_of(n);
+    const double th = std::min(1.0, std::max(0.0, (tau - t_of(n)) / h));
+    double w[7];
+    dense_weights(th, w);
+    const std::vector<std::vector<double>>& K = step_slopes(n);
+    const double* y = &lg.tape[n * rl + 2];
+    std::vector<double> dq(nv);
+    for (int d = 0; d < nv; ++d) {
+      double sq = 0.0, sv = 0.0;
+      for (int i = 0; i < 7; ++i) { sq += w[i] * K[i][d]; sv += w[i] * K[i][nv + d]; }
+      dq[d] = h * sq;
+      xo[nq + d] = y[nq + d] + h * sv;
+    }
+    qplus(m, y, dq.data(), xo);
+  };
+  std::vector<double> lam(xbar, xbar + nx), lamn(nx), Lam(nx), xs(nx), e(nx);
+  std::vector<std::vector<double>> G(7, std::vector<double>(nx)), GU(7, std::vector<double>(std::max(nu, 1)));
+  for (size_t i = 0; i < nut; ++i) ubar[i] = 0.0;
+  double hprop = N > 0 ? h_of(N - 1) : std::min(o.h0, dt), eprev = 1.0;
+  long long attempts = 0, accepted = 0;
+  int status = 0;
+  for (int kk = n_int - 1; kk >= 0 && !status; --kk) {
+    const double* uk = u_of(kk);
+    const double tlo = (double)kk * dt;
+    double t = (double)(kk + 1) * dt;
+    bool have_g1 = false;
+    while (t > tlo) {
+      const bool landing = t - 1.01 * hprop <= tlo;
+      const double H = landing ? t - tlo : hprop;
+      if (attempts >= o.max_attempts) { status |= ORC_MAX_STEPS; break; }
+      ++attempts;
+      for (int i = 0; i < 7; ++i) {
+        if (i == 0 && have_g1) continue;
+        for (int r = 0; r < nx; ++r) {
+          double s = 0.0;
+          for (int j = 0; j < i; ++j) s += RK_A[i][j] * G[j][r];
+          Lam[r] = lam[r] + H * s;
+        }
+        dense(t - RK_C[i] * H, xs.data());
+        Stats s2;
+        raw_vjp(m, xs.data(), uk, o, Lam.data(), G[i].data(), GU[i].data(), &s2);
+        if (s2.status & (ORC_NONFINITE | ORC_SOLVER_MAXIT)) status |= s2.status & (ORC_NONFINITE | ORC_SOLVER_MAXIT);
+      }
+      if (status) break;
+      double acc = 0.0;
+      for (int r = 0; r < nx; ++r) {
+        double s5 = 0.0, se = 0.0;
+        for (int i = 0; i < 7; ++i) { s5 += RK_B[i] * G[i][r]; se += (RK_B[i] - RK_BH[i]) * G[i][r]; }
+        lamn[r] = lam[r] + H * s5;
+        e[r] = H * se;
+        const double sc = o.atol + o.rtol * std::max(std::fabs(lam[r]), std::fabs(lamn[r]));
+        acc += (e[r] / sc) * (e[r] / sc);
+      }
+      const double err = std::sqrt(acc / nx);
+      const double hmin = 1e-12 * std::max(1.0, std::fabs(t));
+      const bool accept = err <= 1.0 || H <= hmin;
+      const double hnext = next_step(o, err, eprev, H, accept, &eprev);
+      if (accept) {
+        for (int i = 0; i < nu; ++i) {
+          double s = 0.0;
+          for (int j = 0; j < 7; ++j) s += RK_B[j] * GU[j][i];
+          ubar[(size_t)kk * nu + i] += H * s;
+        }
+        lam = lamn;
+        G[0] = G[6];
+        GU[0] = GU[6];
+        have_g1 = true;
+        t = landing ? tlo : t - H;
+        ++accepted;
+      }
+      hprop = std::max(hnext, hmin);
+    }
+  }
+  for (int i = 0; i < nx; ++i) x0bar[i] = lam[i];
+  for (int j = 0; j < m.nj; ++j) {  // quaternion gradients: tangent part at q(0)
+    if (m.jtype[j] != J_FREE) continue;
+    const int qa = m.jqadr[j] + 3;
+    double nn = 0.0, dp = 0.0;
+    for (int i = 0; i < 4; ++i) nn += x0[qa + i] * x0[qa + i];
+    for (int i = 0; i < 4; ++i) dp += x0bar[qa + i] * x0[qa + i];
+    for (int i = 0; i < 4; ++i) x0bar[qa + i] -= dp / nn * x0[qa + i];
+  }
+  if (status) {
+    for (int i = 0; i < nx; ++i) x0bar[i] = NAN;
+    for (size_t i = 0; i < nut; ++i) ubar[i] = NAN;
+  }
+  if (counters) { counters[0] = attempts; counters[1] = accepted; counters[2] = N; counters[3] = status; }
+  return status;
+}
+
 // Operation count of a forward rollout: the same rollout in the counting
 // scalar (values equal those of orc_rollout), per phase of the method.
 extern "C" int orc_flop_count(const void* mp, const double* x0, const double* u, int n_int, double dt_int,
@@ -1329,6 +1551,54 @@ extern "C" int orc_flop_count(const void* mp, const double* x0, const double* u,
   out[14] = st.newton_contacts_box;
   out[15] = st.ls_contacts_box;
   return st.status;
+}
+
+extern "C" void orc_dense_weights(double theta, double* w) { dense_weights(theta, w); }
+
+// The forward trajectory x(tau) of one world at n_tau times, from the
+// continuous extension of its accepted steps (forced: replayed steps, as for
+// orc_rollout).
+extern "C" int orc_dense_states(const void* mp, const double* x0, const double* u, int n_int, double dt_int,
+                                const orc_opts* op, const double* forced, int n_forced, int n_tau, const double* tau,
+                                double* out) {
+  const Model& m = *static_cast<const Model*>(mp);
+  Opts o = to_opts(op);
+  const int nq = m.nq, nv = m.nv, nx = nq + nv, nu = m.nu;
+  Log lg;
+  lg.keep_tape = true;
+  Stats st;
+  std::vector<double> xo(nx);
+  rollout<double>(m, x0, u, n_int, dt_int, o, forced, n_forced, xo.data(), &lg, &st);
+  if (st.status & ~ORC_CONTACT_OVERFLOW) return st.status;
+  const int N = (int)lg.n_acc;
+  const size_t rl = 2 + nx;
+  std::vector<double> uz(1, 0.0);
+  for (int k = 0; k < n_tau; ++k) {
+    int n = N - 1;
+    for (int i = 0; i < N; ++i)
+      if (tau[k] < lg.tape[i * rl] + lg.tape[i * rl + 1]) { n = i; break; }
+    const double t0 = lg.tape[n * rl], h = lg.tape[n * rl + 1];
+    const double* y = &lg.tape[n * rl + 2];
+    int kk = std::min(std::max((int)std::floor((t0 + 0.5 * h) / dt_int), 0), n_int - 1);
+    const double* uk = nu > 0 ? u + (size_t)kk * nu : uz.data();
+    std::vector<double> k1(2 * nv), yn(nx), k7(2 * nv);
+    std::vector<std::vector<double>> K;
+    Stats s2;
+    rhs_st(m, y, uk, o, k1.data(), &s2);
+    dopri_attempt(m, y, uk, k1, h, o, false, yn.data(), k7, &s2, &K);
+    double w[7];
+    dense_weights(std::min(1.0, std::max(0.0, (tau[k] - t0) / h)), w);
+    std::vector<double> dq(nv);
+    double* xk = out + (size_t)k * nx;
+    for (int d = 0; d < nv; ++d) {
+      double sq = 0.0, sv = 0.0;
+      for (int i = 0; i < 7; ++i) { sq += w[i] * K[i][d]; sv += w[i] * K[i][nv + d]; }
+      dq[d] = h * sq;
+      xk[nq + d] = y[nq + d] + h * sv;
+    }
+    qplus(m, y, dq.data(), xk);
+  }
+  return 0;
 }
 
 // Operation count of the oracle's Cholesky factorization and solve of an n x n
@@ -1529,4 +1799,18 @@ extern "C" double orc_next_step(const orc_opts* op, double err, double eprev, do
                                 double* eprev_out) {
   Opts o = to_opts(op);
   return next_step(o, err, eprev, h, accepted != 0, eprev_out);
+}
+
+extern "C" int orc_otd_grad_batch(const void* mp, int W, const double* x0, const double* u, int n_int,
+                                  double dt_int, const orc_opts* op, const double* xbar, double* x_out,
+                                  double* x0bar, double* ubar, long long* counters, int n_threads) {
+  const Model& m = *static_cast<const Model*>(mp);
+  Opts o = to_opts(op);
+  const int nx = m.nq + m.nv;
+  const size_t nut = (size_t)n_int * m.nu;
+  parallel_for(W, n_threads, [&](int w) {
+    otd_world(m, x0 + (size_t)w * nx, u + w * nut, n_int, dt_int, o, xbar + (size_t)w * nx,
+              x_out + (size_t)w * nx, x0bar + (size_t)w * nx, ubar + w * nut, counters + 4 * (size_t)w);
+  });
+  return 0;
 }

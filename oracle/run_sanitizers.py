@@ -2,7 +2,8 @@
 (host code, g++) over every model family it simulates: sphere, corner-sphere
 cube, box geom, legged chain, stacks of cubes with box-box contacts (and the
 contact-capacity overflow), rollouts, right-hand sides and their directional
-derivatives, forward-mode gradients on several threads, the CFD field.
+derivatives, forward-mode gradients and optimize-then-discretize gradients on
+several threads, the CFD field.
 
     python3 oracle/run_sanitizers.py
 
@@ -32,6 +33,7 @@ def run(desc, x0, u, n_int, dt, grad=True, cfd=0):
         xb = np.ones((2, y.size))
         uu = None if u is None else np.stack([u, u])
         m.grad_batch(np.stack([y, y]), uu, n_int, dt, xb, n_threads=2, cfd=cfd)
+        m.otd_grad_batch(np.stack([y, y]), uu, n_int, dt, xb, n_threads=2, cfd=cfd)
     return r["status"]
 sphere = W.sphere_drop(seed=1, n_worlds=1, horizon=0.05)
 print("sphere", run(W.model_sphere(), sphere["x0"][0], None, 1, 0.05))
