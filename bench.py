@@ -514,6 +514,55 @@ def chain_leg(D, W, args, dev):
             "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3)}
 
 
+def otd_leg(D, W, dev, reps=3):
+    """Optimize-then-discretize adjoint (dmx_rollout_vjp_otd) beside the
+    discrete adjoint on the same tape: the cube-toss batch (4096 corner-
+    sphere cubes, 0.5 s, 16-lane teams), loss = the summed final positions;
+    and the straight-through CFD gradient of a sphere skimming the plane
+    (never touching), where the discrete adjoint unrolls the forward's few
+    large steps."""
+    import torch
+    cfg = W.cube_toss(seed=2, n_worlds=4096)
+    model = D.Model(cfg["model"])
+    x0 = torch.tensor(cfg["x0"], dtype=torch.float64, device=dev)
+    xbar = torch.zeros_like(x0)
+    xbar[:, :3] = 1.0
+    opts = D.default_opts(tape_steps=2048, tape_stages=1, lanes_per_world=16)
+    stream = torch.cuda.current_stream()
+    r = D.rollout(model, x0, None, 1, 0.5, opts=opts, tape=True, counters=True)
+    D.rollout_vjp(r["tape"], xbar)
+    D.rollout_vjp_otd(r["tape"], xbar)
+    torch.cuda.synchronize()
+    dto_ms, otd_ms = [], []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        g_dto, _ = D.rollout_vjp(r["tape"], xbar)
+        ev[1].record(stream)
+        g_otd, _ = D.rollout_vjp_otd(r["tape"], xbar)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        dto_ms.append(ev[0].elapsed_time(ev[1]))
+        otd_ms.append(ev[1].elapsed_time(ev[2]))
+    diff = (g_otd - g_dto).abs().max(dim=1).values / g_dto.abs().max(dim=1).values
+    out = {"workload": "cube_toss: 4096 corner-sphere cubes, 0.5 s, rtol 1e-6, adjoint of the summed final positions",
+           "dto_adj_ms": round(float(np.median(dto_ms)), 3), "otd_adj_ms": round(float(np.median(otd_ms)), 3),
+           "otd_vs_dto_rel_diff_median": float(diff.median()), "forward_accepted_steps_mean": float(r["n_acc"].double().mean())}
+    # skimming sphere with CFD (5 mm above the plane, inside the CFD width)
+    sph = D.Model(W.model_sphere())
+    xs = torch.tensor([[0.0, 0.0, 0.105, 1, 0, 0, 0, 0.3, 0.0, 0.0, 0, 0, 0]], dtype=torch.float64, device=dev)
+    xb = torch.zeros_like(xs)
+    xb[0, 2] = 1.0
+    rs = D.rollout(sph, xs, None, 1, 0.03, opts=D.default_opts(cfd=1, rtol=1e-10, atol=1e-10, tape_stages=1),
+                   tape=True, counters=True)
+    gd, _ = D.rollout_vjp(rs["tape"], xb)
+    go, _ = D.rollout_vjp_otd(rs["tape"], xb)
+    out["skimming_sphere_cfd"] = {"forward_steps": int(rs["n_acc"][0]),
+                                  "dz_dz0_dto": float(gd[0, 2]), "dz_dz0_otd": float(go[0, 2]),
+                                  "dz_dvz0_dto": float(gd[0, 9]), "dz_dvz0_otd": float(go[0, 9])}
+    return out
+
+
 def graph_ab_leg(D, W, dev, reps=200):
     """A/B timing of one short receding-horizon segment (one 10 ms interval,
     forward + reverse sweep) issued as eager library calls with a reused tape
@@ -668,6 +717,8 @@ def main():
             others["chain_walk"] = chain_leg(D, W, args, dev)
         progress(f"captured segments (graph) A/B ...")
         others["graph_segments"] = graph_ab_leg(D, W, dev)
+        progress(f"optimize-then-discretize adjoint ...")
+        others["otd_adjoint"] = otd_leg(D, W, dev)
     serving = None
     if not args.no_serve:
         progress(f"serving ...")

@@ -308,6 +308,20 @@ dmx_status dmx_autotune_batch(const dmx_batch* batch, const double* x0, const do
  * any number of times on one tape. */
 dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
 
+/* Optimize-then-discretize gradient of sum(x_out_bar * x_out) (App. C.2, eq.
+ * adjoint-equations; with opts.cfd of the forward, the straight-through
+ * adjoint of App. C.4, whose Jacobian is that of the CFD field at the
+ * trajectory of F): the continuous adjoint equations solved backwards in time
+ * with the forward's Dormand-Prince pair and PI controller (rtol, atol,
+ * h_levels of the forward's options) but their own steps, along the
+ * continuous extension of the forward's accepted steps; each adjoint stage
+ * solves the contact problem at the interpolated state.  Raw coordinates;
+ * x0_bar's quaternion components are projected onto the tangent space at the
+ * initial quaternion.  Layouts, outputs and NaN rule as for dmx_rollout_vjp.
+ * Free-body and tree models whose tape holds stage accelerations
+ * (opts.tape_stages != 0 at the rollout); DMX_ERR_UNSUPPORTED otherwise. */
+dmx_status dmx_rollout_vjp_otd(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
+
 /* Captured rollout segments (HIP graphs), for callers that run the same
  * batch repeatedly with new inputs at the same addresses (receding-horizon
  * control loops, where each planning step is one short segment: App. D's

@@ -1485,6 +1485,7 @@ static int otd_world(const Model& m, const double* x0, const double* u, int n_in
         const double sc = o.atol + o.rtol * std::max(std::fabs(lam[r]), std::fabs(lamn[r]));
         acc += (e[r] / sc) * (e[r] / sc);
       }
+      if (!finite_vec(lamn.data(), nx)) { status |= ORC_NONFINITE; break; }
       const double err = std::sqrt(acc / nx);
       const double hmin = 1e-12 * std::max(1.0, std::fabs(t));
       const bool accept = err <= 1.0 || H <= hmin;

@@ -848,6 +848,32 @@ struct FreePhys {
     dqb[5] = s * eb.z + g * th.z;
   }
 
+  // Cotangent of the raw coordinate rates dq/dt = (v_lin, (1/2) q (x) (0, w))
+  // at x = (q, v), for the adjoint ODE in raw coordinates: xbar[NQ + d] +=
+  // (d(dq/dt)/dv)^T lq and xbar[0..NQ) += (d(dq/dt)/dq)^T lq.  Right
+  // multiplication by (0, w) has the transpose right multiplication by
+  // (0, -w); left multiplication by q has the transpose left multiplication by
+  // conj(q).
+  DMX_DEV static void kin_vjp(const double* x, const double* lq, double* xbar) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) xbar[NQ + i] += lq[i];
+    const Q4 q = mkq(x[3], x[4], x[5], x[6]);
+    const Q4 l = mkq(lq[3], lq[4], lq[5], lq[6]);
+    const Q4 qb = qmul(l, mkq(0.0, -x[NQ + 3], -x[NQ + 4], -x[NQ + 5]));
+    const Q4 wb = qmul(qconj(q), l);
+    xbar[3] += 0.5 * qb.w; xbar[4] += 0.5 * qb.x; xbar[5] += 0.5 * qb.y; xbar[6] += 0.5 * qb.z;
+    xbar[NQ + 3] += 0.5 * wb.x; xbar[NQ + 4] += 0.5 * wb.y; xbar[NQ + 5] += 0.5 * wb.z;
+  }
+  // the quaternion part of a raw-coordinate gradient projected onto the
+  // tangent space of the unit sphere at q0 (the radial part is not a
+  // direction of the state space)
+  DMX_DEV static void tangent_project(const double* q0, double* g) {
+    const double nn = q0[3] * q0[3] + q0[4] * q0[4] + q0[5] * q0[5] + q0[6] * q0[6];
+    const double dp = g[3] * q0[3] + g[4] * q0[4] + g[5] * q0[5] + g[6] * q0[6];
+#pragma unroll
+    for (int i = 3; i < 7; ++i) g[i] -= dp / nn * q0[i];
+  }
+
   // coordinates of q integrated as plain sums (positions); the rest are quaternion components
   DMX_DEV static bool q_is_linear(int i) { return i < 3; }
   DMX_DEV static int q_dof(int i) { return i; }

@@ -100,6 +100,33 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
   }
 }
 
+// optimize-then-discretize adjoint: one launch, one team per world (the
+// plain form launches world by world)
+template <class P>
+void launch_otd(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
+  if (!plain) {
+    const int blocks = grid_blocks<P>(dmx::otd_kernel<P>, a.W, a.g.queue != nullptr);
+    if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
+    hipLaunchKernelGGL(dmx::otd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+    return;
+  }
+  constexpr int NX = P::NQ + P::NV;
+  const size_t nut = (size_t)a.n_int * a.nu;
+  for (int w = 0; w < a.W; ++w) {
+    dmx::AdjArgs b = a;
+    b.W = 1;
+    b.tape = a.tape + (size_t)w * a.cap * a.rec;
+    b.n_acc = a.n_acc + w;
+    b.status = a.status + w;
+    b.u = a.u ? a.u + (size_t)w * nut : nullptr;
+    b.xbar = a.xbar + (size_t)w * NX;
+    b.x0bar = a.x0bar + (size_t)w * NX;
+    b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
+    b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
+    hipLaunchKernelGGL(dmx::otd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
+  }
+}
+
 using AccFn = void (*)(const void*, int, const double*, const double*, int, const dmx::SolverOpts&, double*, int*,
                        hipStream_t);
 
@@ -117,15 +144,17 @@ struct KernelEntry {
   FwdFn fwd;
   AdjFn adj;
   AccFn acc;
+  AdjFn otd;
   long long (*resident)();
 };
 
 #define FREE_ENTRY(NC, L) \
   {0, NC, L, 6, 1, &launch_fwd<dmx::FreePhys<NC, L>>, &launch_adj<dmx::FreePhys<NC, L>>, \
-   &launch_acc<dmx::FreePhys<NC, L>>, &fwd_resident_teams<dmx::FreePhys<NC, L>>}
+   &launch_acc<dmx::FreePhys<NC, L>>, &launch_otd<dmx::FreePhys<NC, L>>, &fwd_resident_teams<dmx::FreePhys<NC, L>>}
 #define TREE_ENTRY(NV, NB, NC, L) \
   {1, NC, L, NV, NB, &launch_fwd<dmx::TreePhys<NV, NB, NC, L>>, &launch_adj<dmx::TreePhys<NV, NB, NC, L>>, \
-   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>, &fwd_resident_teams<dmx::TreePhys<NV, NB, NC, L>>}
+   &launch_acc<dmx::TreePhys<NV, NB, NC, L>>, &launch_otd<dmx::TreePhys<NV, NB, NC, L>>, \
+   &fwd_resident_teams<dmx::TreePhys<NV, NB, NC, L>>}
 
 
 struct KernelTable {

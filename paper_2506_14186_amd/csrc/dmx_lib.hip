@@ -131,6 +131,7 @@ struct dmx_tape {
   const double* u = nullptr;
   dmx::SolverOpts o{};
   AdjFn adj = nullptr;
+  AdjFn otd = nullptr;  // the optimize-then-discretize adjoint of the same kernel family
   int64_t* adj_counters = nullptr;
   int plain = 0;
   const int32_t* world_intervals = nullptr;  // tape-owned copies of the caller's tables (or null)
@@ -1061,7 +1062,7 @@ static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, dou
   int* tmp_queue = nullptr;
   if (reuse) {
     tp = reuse;
-    tp->n_int = n_int; tp->dt = dt; tp->u = u; tp->o = a.o; tp->adj = k->adj; tp->team = k->team;
+    tp->n_int = n_int; tp->dt = dt; tp->u = u; tp->o = a.o; tp->adj = k->adj; tp->otd = k->otd; tp->team = k->team;
     tp->adj_counters = o.adj_counters; tp->plain = o.launch_mode;
     a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
     a.n_acc = tp->n_acc; a.status = tp->status;
@@ -1081,6 +1082,7 @@ static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, dou
     tp->rec = 3 + NX + (stages ? 6 * m->nv : 0);
     tp->o = a.o;
     tp->adj = k->adj;
+    tp->otd = k->otd;
     tp->team = k->team;
     tp->adj_counters = o.adj_counters;
     tp->plain = o.launch_mode;
@@ -1237,6 +1239,27 @@ dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
   a.g.queue = tp->use_queue ? tp->queue + 1 : nullptr;
   tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->plain);
+  HIP_TRY(hipGetLastError());
+  return DMX_OK;
+}
+
+dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
+  if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp->stack || !tp->otd)
+    return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint takes free-body and tree models");
+  if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  const int nx = tp->model->nq + tp->model->nv;
+  if (tp->rec < 3 + nx + 6 * tp->model->nv)
+    return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint needs a tape with stage accelerations");
+  dmx::AdjArgs a{};
+  a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.dt = tp->dt; a.tape = tp->records; a.cap = tp->cap;
+  a.rec = tp->rec; a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar;
+  a.ubar = u_bar;
+  a.o = tp->o;
+  a.counters = (long long*)tp->adj_counters;
+  a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
+  a.g.queue = tp->use_queue ? tp->queue + 1 : nullptr;
+  tp->otd(tp->model->dev, a, (hipStream_t)stream, tp->plain);
   HIP_TRY(hipGetLastError());
   return DMX_OK;
 }

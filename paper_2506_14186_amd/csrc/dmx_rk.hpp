@@ -155,6 +155,7 @@ struct FwdArgs {
 
 struct AdjArgs {
   int W, n_int, nu;
+  double dt;            // control interval length (the optimize-then-discretize adjoint's grid)
   long long* counters;  // [W][kAdjCounters] or null
   const double* tape;
   long long cap;
@@ -710,6 +711,273 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
     adj_world<P, RECOMPUTE>(*model, a, w, tl, A, Ab);
+  }
+}
+
+// ------------------------------------------------------------ optimize-then-discretize
+// The continuous adjoint equations (App. C.2, eq. adjoint-equations): for a
+// loss on the final state, lam(T) = dL/dx(T), dlam/dt = -(dF/dx)^T lam, and
+// each control interval's gradient is the integral of (dF/du)^T lam over it;
+// with the straight-through rule (App. C.4) dF/dx is that of the CFD field at
+// the trajectory of F.  They are solved backwards in time with the forward's
+// Dormand-Prince pair and PI controller but their own steps, in raw
+// coordinates (dq/dt = v, a free joint's quaternion (1/2) q (x) (0, w)), along
+// x(t) from the continuous extension of the forward's accepted steps; each
+// stage solves the contact problem at x(t) and applies acc_vjp and the
+// kinematic VJP.  The adjoint's steps land on the interval ends, start from the
+// forward's last step size and are floored at 1e-12 max(1, |t|) (a floor step
+// is accepted: dF/dx jumps where a contact switches on).  The returned
+// quaternion gradient is projected onto the tangent space at q(0).
+
+// weights of the stage slopes in the fourth-order continuous extension of the
+// Dormand-Prince pair (Hairer, Norsett and Wanner): over the fraction th of a
+// step the increment is h sum_i w_i k_i with
+// w = th b + th (1 - th) (e_1 - b) + th^2 (1 - th) (2 b - e_1 - e_7) + th^2 (1 - th)^2 d
+constexpr double kDenseD[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                               -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                               -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
+DMX_DEV void dense_weights(double th, double* w) {
+  const double p1 = th * (1.0 - th), p2 = th * p1, p3 = p2 * (1.0 - th);
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const double b = i < 6 ? kTab.a[6][i] : 0.0;
+    const double e1 = i == 0 ? 1.0 : 0.0, e7 = i == 6 ? 1.0 : 0.0;
+    w[i] = th * b + p1 * (e1 - b) + p2 * (2.0 * b - e1 - e7) + p3 * kDenseD[i];
+  }
+}
+
+// A: stage accelerations and V: stage velocities (LDS, [7][NV]) of the
+// forward step the continuous extension currently reads; G, TB: the adjoint's
+// stage slopes (raw state cotangent rates, generalized-force cotangents).
+template <class P>
+DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
+                       double (*V)[P::NV], double (*G)[P::NQ + P::NV], double (*TB)[P::NV]) {
+  constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
+  const SolverOpts& o = a.o;
+  const int N = a.n_acc[w];
+  const int n_int = world_intervals(a.g, a.n_int, w);
+  const size_t nut = (size_t)(a.g.u_off ? n_int : a.n_int) * a.nu;
+  const size_t uoff = world_u(a.g, a.n_int, a.nu, w);
+  const double* uw = a.u ? a.u + uoff : nullptr;
+  double* ubw = a.ubar ? a.ubar + uoff : nullptr;
+  const double* tape_w = a.tape + world_tape(a.g, a.cap, w) * a.rec;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  if (a.status[w] != 0 || N <= 0) {
+    for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
+    for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
+    return;
+  }
+  double lam[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) lam[i] = a.xbar[(size_t)w * NX + i];
+  Stat st{};
+  // the forward step read by the continuous extension
+  int cur = -1, nguess = N - 1;
+  double yc[NX], tc = 0.0, hc = 1.0;
+  double xw[NV];
+  bool have_xw = false;
+  auto rec_end = [&](int n) { return tape_w[(size_t)n * a.rec] + tape_w[(size_t)n * a.rec + 1]; };
+  auto load_step = [&](int n) {
+    const double* r = tape_w + (size_t)n * a.rec;
+    tc = r[0];
+    hc = r[1];
+    const int kn = (int)r[2];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) yc[i] = r[3 + i];
+    double* Af = &A[0][0];
+#pragma unroll
+    for (int rr = 0; rr < (6 * NV + L - 1) / L; ++rr) {
+      const int j = tl + rr * L;
+      if (j < 6 * NV) Af[j] = r[3 + NX + j];
+    }
+    wave_fence();
+#pragma unroll
+    for (int d = 0; d < NV; ++d) V[0][d] = yc[NQ + d];
+    double Y[NX], dq[NV];
+#pragma unroll 1
+    for (int i = 1; i < 7; ++i) {
+      stage_state<P>(yc, A, i, hc, Y, dq);
+#pragma unroll
+      for (int d = 0; d < NV; ++d) V[i][d] = Y[NQ + d];
+    }
+    // slope at y_{n+1} under this step's control: the next record's first
+    // stage when it continues the same interval, else solved here
+    if (n + 1 < N && (int)tape_w[(size_t)(n + 1) * a.rec + 2] == kn) {
+      const double* r1 = tape_w + (size_t)(n + 1) * a.rec + 3 + NX;
+#pragma unroll
+      for (int d = 0; d < NV; ++d) A[6][d] = r1[d];
+    } else {
+      double taun[NV], a7[NV];
+      load_tau<P>(m, uw, kn, a.nu, taun);
+      P::acc(m, Y, taun, false, o.beta, o.newton_maxit, A[5], a7, st);
+#pragma unroll
+      for (int d = 0; d < NV; ++d) A[6][d] = a7[d];
+    }
+    wave_fence();
+  };
+  // x(tau): the first step with tau < t_n + h_n (the last one otherwise)
+  auto dense = [&](double tau, double* x) {
+    int n = nguess;
+    while (n > 0 && tau < rec_end(n - 1)) --n;
+    while (n < N - 1 && !(tau < rec_end(n))) ++n;
+    nguess = n;
+    if (n != cur) { load_step(n); cur = n; }
+    double wt[7], dq[NV];
+    dense_weights(fmin(1.0, fmax(0.0, (tau - tc) / hc)), wt);
+#pragma unroll
+    for (int d = 0; d < NV; ++d) {
+      double sq = 0.0, sv = 0.0;
+#pragma unroll
+      for (int i = 0; i < 7; ++i) { sq += wt[i] * V[i][d]; sv += wt[i] * A[i][d]; }
+      dq[d] = hc * sq;
+      x[NQ + d] = yc[NQ + d] + hc * sv;
+    }
+    P::qplus(yc, dq, x);
+  };
+  double hprop = tape_w[(size_t)(N - 1) * a.rec + 1], eprev = 1.0;
+  long long attempts = 0;
+  bool failed = false;
+  for (int kk = n_int - 1; kk >= 0 && !failed; --kk) {
+    double tau[NV], tb_acc[NV];
+    load_tau<P>(m, uw, kk, a.nu, tau);
+#pragma unroll
+    for (int d = 0; d < NV; ++d) tb_acc[d] = 0.0;
+    const double tlo = (double)kk * a.dt;
+    double t = (double)(kk + 1) * a.dt;
+    bool have_g1 = false;
+    while (t > tlo) {
+      const bool landing = t - 1.01 * hprop <= tlo;
+      const double H = landing ? t - tlo : hprop;
+      if (attempts >= o.max_attempts) { failed = true; break; }
+      ++attempts;
+#pragma unroll 1
+      for (int i = 0; i < 7; ++i) {
+        if (i == 0 && have_g1) continue;
+        double Lam[NX];
+        if (i == 0) {
+#pragma unroll
+          for (int r = 0; r < NX; ++r) Lam[r] = lam[r];
+        } else {
+          const StageCoef k = stage_coef(i);
+#pragma unroll
+          for (int r = 0; r < NX; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s += k.a[j] * (j < i ? G[j][r] : 0.0);
+            Lam[r] = lam[r] + H * s;
+          }
+        }
+        double x[NX], xs[NV], tb[NV], ybar[NX];
+        dense(t - kTab.c[i] * H, x);
+        P::acc(m, x, tau, false, o.beta, o.newton_maxit, have_xw ? xw : nullptr, xs, st);
+#pragma unroll
+        for (int d = 0; d < NV; ++d) xw[d] = xs[d];
+        have_xw = true;
+#pragma unroll
+        for (int r = 0; r < NX; ++r) ybar[r] = 0.0;
+        P::acc_vjp(m, x, tau, xs, Lam + NQ, o.cfd != 0, o.beta, o.newton_maxit, ybar, tb, st);
+        P::kin_vjp(x, Lam, ybar);
+#pragma unroll
+        for (int r = 0; r < NX; ++r) G[i][r] = ybar[r];
+#pragma unroll
+        for (int d = 0; d < NV; ++d) TB[i][d] = tb[d];
+        wave_fence();
+      }
+      if (st.status & 12) { failed = true; break; }
+      double lamn[NX], acc2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) {
+        double s5 = 0.0, se = 0.0;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+          const double g = G[i][r];
+          s5 += (i < 6 ? kTab.a[6][i] : 0.0) * g;
+          se += kTab.e[i] * g;
+        }
+        lamn[r] = lam[r] + H * s5;
+        const double q = (H * se) / (o.atol + o.rtol * fmax(fabs(lam[r]), fabs(lamn[r])));
+        acc2 += q * q;
+      }
+      bool fin = true;
+#pragma unroll
+      for (int r = 0; r < NX; ++r) fin = fin && isfinite(lamn[r]);
+      if (!fin) { failed = true; break; }  // a non-finite cotangent ends the world (NaN gradients)
+      const double err = sqrt(acc2 / NX);
+      const double hmin = 1e-12 * fmax(1.0, fabs(t));
+      const bool accept = err <= 1.0 || H <= hmin;
+      const double et = isfinite(err) ? fmax(err, o.err_floor) : 1e300;
+      double fac = o.safety * pow(et, -(o.kP + o.kI) / o.err_order) * pow(eprev, o.kP / o.err_order);
+      fac = fmin(o.facmax, fmax(o.facmin, fac));
+      double hnext;
+      if (accept) {
+#pragma unroll
+        for (int d = 0; d < NV; ++d) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) s += kTab.a[6][j] * TB[j][d];
+          tb_acc[d] += H * s;
+        }
+#pragma unroll
+        for (int r = 0; r < NX; ++r) { lam[r] = lamn[r]; G[0][r] = G[6][r]; }
+#pragma unroll
+        for (int d = 0; d < NV; ++d) TB[0][d] = TB[6][d];
+        wave_fence();
+        have_g1 = true;
+        t = landing ? tlo : t - H;
+        eprev = et;
+        hnext = quantize_step(fac * H, o.h_levels);
+        if (tl == 0) st.u_step++;
+      } else {
+        hnext = quantize_step(fmin(1.0, fac) * H, o.h_levels);
+      }
+      hprop = fmax(hnext, hmin);
+    }
+    if (!failed && ubw && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)kk * a.nu, a.nu);
+  }
+  if (failed) {
+    for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
+    for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
+  } else {
+    P::tangent_project(tape_w + 3, lam);
+    team_store<NX, L>(a.x0bar + (size_t)w * NX, lam, tl);
+  }
+  if (a.counters) {
+    double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
+    team_sum_arr<L, kAdjCounters>(c);
+    if (tl == 0)
+      for (int i = 0; i < kAdjCounters; ++i) a.counters[(size_t)w * kAdjCounters + i] = (long long)c[i];
+  }
+}
+
+// One team per world; the stage slopes of teams of two or more lanes sit in
+// LDS, those of one-lane teams (64 worlds per wavefront) in private memory.
+template <class P>
+__global__ void __launch_bounds__(64) otd_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
+  constexpr int L = P::TEAM, NV = P::NV, NX = P::NQ + P::NV;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int team = gt / L, tl = gt & (L - 1);
+  __shared__ double sA[64 / L][7][NV];
+  __shared__ double sV[64 / L][7][NV];
+  double (*A)[NV] = sA[(threadIdx.x & 63) / L];
+  double (*V)[NV] = sV[(threadIdx.x & 63) / L];
+  stage_pairs(*model);
+  if constexpr (L == 1) {
+    double Gp[7][NX], Tp[7][NV];
+    for (bool first = true;; first = false) {
+      const int w = take_world<L>(a.g, a.W, team, first);
+      if (w < 0) break;
+      otd_world<P>(*model, a, w, tl, A, V, Gp, Tp);
+    }
+  } else {
+    __shared__ double sG[64 / L][7][NX];
+    __shared__ double sT[64 / L][7][NV];
+    double (*G)[NX] = sG[(threadIdx.x & 63) / L];
+    double (*T)[NV] = sT[(threadIdx.x & 63) / L];
+    for (bool first = true;; first = false) {
+      const int w = take_world<L>(a.g, a.W, team, first);
+      if (w < 0) break;
+      otd_world<P>(*model, a, w, tl, A, V, G, T);
+    }
   }
 }
 

@@ -994,6 +994,12 @@ struct TreePhys {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) { qbar[i] += ob[i]; dqb[i] = ob[i]; }
   }
+  // cotangent of the raw rates dq/dt = v (hinge and slide coordinates)
+  DMX_DEV static void kin_vjp(const double*, const double* lq, double* xbar) {
+#pragma unroll
+    for (int d = 0; d < NV; ++d) xbar[NQ + d] += lq[d];
+  }
+  DMX_DEV static void tangent_project(const double*, double*) {}
   DMX_DEV static bool q_is_linear(int) { return true; }
   DMX_DEV static int q_dof(int i) { return i; }
 };

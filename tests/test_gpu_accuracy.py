@@ -12,7 +12,9 @@ so the discrete gradient converges slowly near those instants).  The GPU
 path (forward rollout, discrete adjoint) runs at rtol = atol from 1e-2 to
 1e-9; the gradient error must fall with the tolerance (the paper's claim:
 the tolerance sets the gradient error) and so must the loss error.  Runtime
-of the batch is measured with events on the stream.
+of the batch is measured with events on the stream.  The optimize-then-
+discretize gradient of the same rollouts (dmx_rollout_vjp_otd) is measured
+beside it (App. C.2: the adjoint picks its own steps).
 """
 import numpy as np
 import pytest
@@ -84,19 +86,25 @@ def test_gradient_error_follows_tolerance(D, oracle):
         ev[1].record(stream)
         g, _ = D.rollout_vjp(r["tape"], xbt)
         ev[2].record(stream)
+        go, _ = D.rollout_vjp_otd(r["tape"], xbt)
+        ev2 = torch.cuda.Event(enable_timing=True)
+        ev2.record(stream)
         torch.cuda.synchronize()
+        go = go.cpu().numpy()
+        rel_otd = np.abs(go[:, 7] - g_true[:, 7]) / np.abs(g_true[:, 7])
         assert int(r["status"].abs().sum()) == 0
         gg = g.cpu().numpy()
         xg = r["x"].cpu().numpy()
         rel = np.abs(gg[:, 7] - g_true[:, 7]) / np.abs(g_true[:, 7])
         err_l = float(np.max(np.abs(xg[:, 0] - x_true[:, 0])))
         rows.append((rtol, err_l, float(np.median(rel)), float(rel.max()), ev[0].elapsed_time(ev[1]),
-                     ev[1].elapsed_time(ev[2]), int(r["n_acc"].max()), int((r["n_acc"] + r["n_rej"]).max())))
+                     ev[1].elapsed_time(ev[2]), int(r["n_acc"].max()), int((r["n_acc"] + r["n_rej"]).max()),
+                     float(np.median(rel_otd)), float(rel_otd.max()), ev[2].elapsed_time(ev2)))
     print("\n| rtol | loss error (m, max) | dL/dv_x rel. error (median) | (max) | fwd ms | adj ms | "
-          "max accepted | max attempts |")
+          "max accepted | max attempts | OTD error (median) | (max) | OTD adj ms |")
     for row in rows:
         print(f"| {row[0]:.0e} | {row[1]:.2e} | {row[2]:.2e} | {row[3]:.2e} | {row[4]:.3f} | {row[5]:.3f} | "
-              f"{row[6]} | {row[7]} |")
+              f"{row[6]} | {row[7]} | {row[8]:.2e} | {row[9]:.2e} | {row[10]:.3f} |")
     loss = {r[0]: r[1] for r in rows}
     med = {r[0]: r[2] for r in rows}
     assert loss[1e-9] <= 1e-5 and loss[1e-9] <= 1e-3 * loss[1e-3]
