@@ -177,6 +177,11 @@ typedef struct {
    * work); -1 (default) = stages unless the tape would take more than half of
    * the free device memory. */
   int32_t tape_stages;
+  /* Runge-Kutta pair: 0 = Dormand-Prince 5(4) (default); 1 = Tsitouras 5(4)
+   * (Tsit5, the solver of the paper's experiments, App. E.1), for free-body
+   * and tree models (stack batches and the optimize-then-discretize adjoint
+   * take 0 only: DMX_ERR_UNSUPPORTED). */
+  int32_t tableau;
 } dmx_solver_opts;
 
 void dmx_default_opts(dmx_solver_opts* opts);

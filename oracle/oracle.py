@@ -60,12 +60,12 @@ class _Opts(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("rtol", "atol", "h0", "safety", "facmin", "facmax", "kP", "kI",
                                            "err_order", "err_floor")] + [
         ("max_attempts", C.c_longlong), ("newton_maxit", C.c_int), ("cfd", C.c_int), ("softplus_beta", C.c_double),
-        ("h_levels", C.c_int)]
+        ("h_levels", C.c_int), ("tableau", C.c_int)]
 
 
 DEFAULT_OPTS = dict(rtol=1e-6, atol=1e-8, h0=1e-3, safety=0.9, facmin=0.2, facmax=10.0, kP=0.2, kI=0.4,
                     err_order=5.0, err_floor=1e-6, max_attempts=1_000_000, newton_maxit=100, cfd=0,
-                    softplus_beta=1e4, h_levels=0)
+                    softplus_beta=1e4, h_levels=0, tableau=0)
 
 _lib = None
 

@@ -52,11 +52,14 @@ typedef struct {
   double softplus_beta; /* sharpness of the softplus position term of the CFD force */
   int h_levels;         /* proposed step sizes rounded down to this many mantissa levels per octave (0: off,
                            the default: the continuous controller) */
+  int tableau;          /* 0: Dormand-Prince 5(4) (default), 1: Tsitouras 5(4) (Tsit5, the paper's solver,
+                           App. E.1); optimize-then-discretize takes 0 only */
 } orc_opts;
 
 /* CONTACT_OVERFLOW: more than 256 contacts within reach at some evaluation; the
  * first 256 in pair order were used (not fatal: the world continues). */
-enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8, ORC_CONTACT_OVERFLOW = 16 };
+enum { ORC_MAX_STEPS = 1, ORC_DT_UNDERFLOW = 2, ORC_NONFINITE = 4, ORC_SOLVER_MAXIT = 8, ORC_CONTACT_OVERFLOW = 16,
+       ORC_UNSUPPORTED = 64 };
 
 void* orc_model_new(const orc_model_def* def);
 void orc_model_free(void* m);

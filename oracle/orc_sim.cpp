@@ -742,6 +742,7 @@ struct Opts {
   bool cfd = false;
   double beta = 1e4;
   int h_levels = 0;
+  int tableau = 0;
 };
 
 // reading: the controller's proposed step is rounded down to a grid of
@@ -880,6 +881,37 @@ static const double RK_B[7] = {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0,
 static const double RK_BH[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
                                 187.0 / 2100.0, 1.0 / 40.0};
 
+// Tsitouras 5(4) (Tsit5, the solver of the paper's experiments, App. E.1): the
+// FSAL pair of Tsitouras (2011), whose coefficients satisfy only the first
+// column simplifying assumption.  b-hat = b - btilde with btilde the published
+// error weights.
+static const double T5_C[7] = {0.0, 0.161, 0.327, 0.9, 0.9800255409045097, 1.0, 1.0};
+static const double T5_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0.161, 0, 0, 0, 0, 0},
+    {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0},
+    {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0},
+    {5.325864828439257, -11.748883564062828, 7.4955393428898365, -0.09249506636175525, 0, 0},
+    {5.86145544294642, -12.92096931784711, 8.159367898576159, -0.071584973281401, -0.028269050394068383, 0},
+    {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742, -3.290069515436081, 2.324710524099774}};
+static const double T5_B[7] = {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742,
+                               -3.290069515436081, 2.324710524099774, 0.0};
+static const double T5_BT[7] = {-0.00178001105222577714, -0.0008164344596567469, 0.007880878010261995,
+                                -0.1447110071732629, 0.5823571654525552, -0.45808210592918697,
+                                0.015151515151515152};
+struct Tab { const double (*A)[6]; const double* B; double BH[7]; };
+static Tab tableau_of(int which) {
+  Tab t;
+  if (which == 1) {
+    t.A = T5_A; t.B = T5_B;
+    for (int i = 0; i < 7; ++i) t.BH[i] = T5_B[i] - T5_BT[i];
+  } else {
+    t.A = RK_A; t.B = RK_B;
+    for (int i = 0; i < 7; ++i) t.BH[i] = RK_BH[i];
+  }
+  return t;
+}
+
 // q (+) dq: positions integrate the tangent; free-joint quaternions are
 // integrated exactly, quat <- quat * exp(dtheta/2) with dtheta the body-frame
 // rotation vector, and renormalized (App. C.2: quaternion-aware solvers).
@@ -917,6 +949,7 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
                             const Opts& o, bool want_err, S* ynew, std::vector<S>& k7, Stats* st,
                             std::vector<std::vector<S>>* stages = nullptr) {
   FlopPhase phase(kPhStep);
+  const Tab tb = tableau_of(o.tableau);
   int nq = m.nq, nv = m.nv, nx = nq + nv;
   std::vector<std::vector<S>> K(7, std::vector<S>(2 * nv));
   K[0] = k1;
@@ -924,7 +957,7 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
   for (int i = 1; i < 7; ++i) {
     for (int d = 0; d < nv; ++d) {
       S sq = S(0.0), sv = S(0.0);
-      for (int j = 0; j < i; ++j) { sq += K[j][d] * RK_A[i][j]; sv += K[j][nv + d] * RK_A[i][j]; }
+      for (int j = 0; j < i; ++j) { sq += K[j][d] * tb.A[i][j]; sv += K[j][nv + d] * tb.A[i][j]; }
       dq[d] = sq * h;
       Y[nq + d] = y[nq + d] + sv * h;
     }
@@ -941,8 +974,8 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
   for (int d = 0; d < nv; ++d) {
     T sh = 0.0, sa = 0.0;
     for (int i = 0; i < 7; ++i) {
-      sh += value_as<T>(K[i][d]) * RK_BH[i];
-      sa += value_as<T>(K[i][nv + d]) * (RK_B[i] - RK_BH[i]);
+      sh += value_as<T>(K[i][d]) * tb.BH[i];
+      sa += value_as<T>(K[i][nv + d]) * (tb.B[i] - tb.BH[i]);
     }
     dqh[d] = sh * h;
     e[nq + d] = sa * h;
@@ -957,7 +990,7 @@ static double dopri_attempt(const Model& m, const S* y, const S* uk, const std::
     int nlin = m.jtype[j] == J_FREE ? 3 : 1;
     for (int i = 0; i < nlin; ++i) {
       T se = 0.0;
-      for (int s = 0; s < 7; ++s) se += value_as<T>(K[s][da + i]) * (RK_B[s] - RK_BH[s]);
+      for (int s = 0; s < 7; ++s) se += value_as<T>(K[s][da + i]) * (tb.B[s] - tb.BH[s]);
       e[qa + i] = se * h;
     }
   }
@@ -1082,7 +1115,7 @@ static Opts to_opts(const orc_opts* p) {
   o.rtol = p->rtol; o.atol = p->atol; o.h0 = p->h0; o.safety = p->safety; o.facmin = p->facmin;
   o.facmax = p->facmax; o.kP = p->kP; o.kI = p->kI; o.err_order = p->err_order; o.err_floor = p->err_floor;
   o.max_attempts = p->max_attempts; o.newton_maxit = p->newton_maxit; o.cfd = p->cfd != 0;
-  o.beta = p->softplus_beta; o.h_levels = p->h_levels;
+  o.beta = p->softplus_beta; o.h_levels = p->h_levels; o.tableau = p->tableau == 1 ? 1 : 0;
   return o;
 }
 
@@ -1398,6 +1431,7 @@ static int otd_world(const Model& m, const double* x0, const double* u, int n_in
   Stats st;
   rollout<double>(m, x0, u, n_int, dt, o, nullptr, 0, x_out, &lg, &st);
   const size_t nut = (size_t)n_int * nu;
+  if (o.tableau != 0) st.status |= ORC_UNSUPPORTED;  // the continuous extension is the Dormand-Prince pair's
   if (st.status & ~ORC_CONTACT_OVERFLOW) {
     for (int i = 0; i < nx; ++i) x0bar[i] = NAN;
     for (size_t i = 0; i < nut; ++i) ubar[i] = NAN;

@@ -677,6 +677,7 @@ static dmx::SolverOpts to_solver(const dmx_solver_opts& o) {
   s.rtol = o.rtol; s.atol = o.atol; s.h0 = o.h0; s.safety = o.safety; s.facmin = o.facmin; s.facmax = o.facmax;
   s.kP = o.kP; s.kI = o.kI; s.err_order = o.err_order; s.err_floor = o.err_floor; s.beta = o.softplus_beta;
   s.max_attempts = o.max_attempts; s.newton_maxit = o.newton_maxit; s.cfd = o.cfd; s.h_levels = o.h_levels;
+  s.tableau = o.tableau;
   return s;
 }
 
@@ -755,6 +756,7 @@ static dmx_status stack_rollout(const std::vector<const dmx_model*>& ms, int n_i
   for (const dmx_model* m : ms) uniform = uniform && m == ms[0];
   if (o.launch_mode != 0 && o.launch_mode != 1) return fail(DMX_ERR_INVALID_ARG, "bad launch_mode");
   if (o.world_intervals) return fail(DMX_ERR_UNSUPPORTED, "ragged horizons are not taken by stack batches");
+  if (o.tableau != 0) return fail(DMX_ERR_UNSUPPORTED, "stack batches take the Dormand-Prince pair");
   bool any_ctrl = false;
   for (const dmx_model* m : ms) any_ctrl = any_ctrl || m->nu > 0;
   if (any_ctrl && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
@@ -877,6 +879,7 @@ static dmx_status check_opts(const dmx_solver_opts& o) {
   if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
   if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
   if (o.work_queue < -1 || o.work_queue > 1) return fail(DMX_ERR_INVALID_ARG, "bad work_queue");
+  if (o.tableau < 0 || o.tableau > 1) return fail(DMX_ERR_INVALID_ARG, "bad tableau");
   return DMX_OK;
 }
 
@@ -1028,10 +1031,8 @@ static dmx_status rollout_impl(const dmx_model* m, int32_t W, int32_t n_int, dou
   if (W > 0 && m->nu > 0 && !u) return fail(DMX_ERR_INVALID_ARG, "controls required");
   dmx_solver_opts o;
   if (opts) o = *opts; else dmx_default_opts(&o);
-  if (!(o.rtol >= 0.0) || !(o.atol > 0.0) || !(o.h0 > 0.0) || o.newton_maxit <= 0 || o.h_levels < 0)
-    return fail(DMX_ERR_INVALID_ARG, "bad solver options");
-  if (o.forced && (!o.forced_n || o.forced_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "forced steps need counts");
-  if (o.steplog && (!o.log_n || o.log_cap <= 0)) return fail(DMX_ERR_INVALID_ARG, "step log needs counts");
+  const dmx_status oc = check_opts(o);
+  if (oc != DMX_OK) return oc;
   const KernelEntry* k = find_kernel(m, o.lanes_per_world);
   if (!k) return fail(DMX_ERR_UNSUPPORTED, "no kernel for this model and lanes_per_world");
   dmx_tape* reuse = tape ? *tape : nullptr;
@@ -1248,6 +1249,8 @@ dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0
   if (tp->stack || !tp->otd)
     return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint takes free-body and tree models");
   if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  if (tp->o.tableau != 0)
+    return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint reads the Dormand-Prince continuous extension");
   const int nx = tp->model->nq + tp->model->nv;
   if (tp->rec < 3 + nx + 6 * tp->model->nv)
     return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint needs a tape with stage accelerations");

@@ -28,18 +28,9 @@ struct Tableau {
   double bh_sum;
 };
 
-constexpr Tableau make_tableau() {
+// the derived coefficients of a pair from its A (row 6 = b, FSAL) and b-hat
+constexpr Tableau tableau_from(const double (&A)[7][7], const double (&BH)[7]) {
   Tableau t{};
-  const double A[7][7] = {
-      {0, 0, 0, 0, 0, 0, 0},
-      {1.0 / 5.0, 0, 0, 0, 0, 0, 0},
-      {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0, 0},
-      {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0, 0},
-      {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0, 0},
-      {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0, 0},
-      {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0}};
-  const double BH[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
-                        187.0 / 2100.0, 1.0 / 40.0};
   for (int i = 0; i < 7; ++i) {
     double s = 0.0;
     for (int j = 0; j < 7; ++j) { t.a[i][j] = A[i][j]; s += A[i][j]; }
@@ -60,14 +51,50 @@ constexpr Tableau make_tableau() {
   }
   return t;
 }
+
+// Dormand-Prince 5(4)
+constexpr Tableau make_tableau() {
+  const double A[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {1.0 / 5.0, 0, 0, 0, 0, 0, 0},
+      {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0, 0, 0},
+      {44.0 / 45.0, -56.0 / 15.0, 32.0 / 9.0, 0, 0, 0, 0},
+      {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0, -212.0 / 729.0, 0, 0, 0},
+      {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0, -5103.0 / 18656.0, 0, 0},
+      {35.0 / 384.0, 0.0, 500.0 / 1113.0, 125.0 / 192.0, -2187.0 / 6784.0, 11.0 / 84.0, 0}};
+  const double BH[7] = {5179.0 / 57600.0, 0.0, 7571.0 / 16695.0, 393.0 / 640.0, -92097.0 / 339200.0,
+                        187.0 / 2100.0, 1.0 / 40.0};
+  return tableau_from(A, BH);
+}
+
+// Tsitouras 5(4) (Tsit5, the solver of the paper's experiments, App. E.1):
+// the FSAL pair of Tsitouras (2011); b-hat = b - btilde, btilde the published
+// error weights
+constexpr Tableau make_tableau_tsit5() {
+  const double A[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {0.161, 0, 0, 0, 0, 0, 0},
+      {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0, 0},
+      {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0, 0},
+      {5.325864828439257, -11.748883564062828, 7.4955393428898365, -0.09249506636175525, 0, 0, 0},
+      {5.86145544294642, -12.92096931784711, 8.159367898576159, -0.071584973281401, -0.028269050394068383, 0, 0},
+      {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742, -3.290069515436081, 2.324710524099774, 0}};
+  const double BT[7] = {-0.00178001105222577714, -0.0008164344596567469, 0.007880878010261995,
+                        -0.1447110071732629, 0.5823571654525552, -0.45808210592918697, 0.015151515151515152};
+  double BH[7] = {};
+  for (int j = 0; j < 7; ++j) BH[j] = (j < 6 ? A[6][j] : 0.0) - BT[j];
+  return tableau_from(A, BH);
+}
 // compile-time tableau: stage-specialized code reads it with constant
 // indices, so every coefficient is an immediate operand
 constexpr Tableau kTab = make_tableau();
+constexpr Tableau kTab5 = make_tableau_tsit5();
 
 struct SolverOpts {
   double rtol, atol, h0, safety, facmin, facmax, kP, kI, err_order, err_floor, beta;
   long long max_attempts;
   int newton_maxit, cfd, h_levels;
+  int tableau;  // 0: Dormand-Prince 5(4), 1: Tsitouras 5(4)
 };
 
 // Proposed steps rounded down to h_levels mantissa values per octave (exact
@@ -212,24 +239,28 @@ DMX_DEV void team_store(double* dst, const double* src, int tl) {
 struct StageCoef {
   double a[6], a2[6], c;
 };
-template <int I>
+template <int I, int T>
 DMX_DEV StageCoef stage_coef_c() {
+  constexpr const Tableau& tb = T ? kTab5 : kTab;
   StageCoef k;
 #pragma unroll
-  for (int l = 0; l < 6; ++l) { k.a[l] = kTab.a[I][l]; k.a2[l] = kTab.a2[I][l]; }
-  k.c = kTab.c[I];
+  for (int l = 0; l < 6; ++l) { k.a[l] = tb.a[I][l]; k.a2[l] = tb.a2[I][l]; }
+  k.c = tb.c[I];
   return k;
 }
-DMX_DEV StageCoef stage_coef(int i) {
+template <int T>
+DMX_DEV StageCoef stage_coef_t(int i) {
   switch (i) {
-    case 1: return stage_coef_c<1>();
-    case 2: return stage_coef_c<2>();
-    case 3: return stage_coef_c<3>();
-    case 4: return stage_coef_c<4>();
-    case 5: return stage_coef_c<5>();
-    default: return stage_coef_c<6>();
+    case 1: return stage_coef_c<1, T>();
+    case 2: return stage_coef_c<2, T>();
+    case 3: return stage_coef_c<3, T>();
+    case 4: return stage_coef_c<4, T>();
+    case 5: return stage_coef_c<5, T>();
+    default: return stage_coef_c<6, T>();
   }
 }
+// tab: 0 Dormand-Prince, 1 Tsitouras (uniform across the wavefront)
+DMX_DEV StageCoef stage_coef(int i, int tab = 0) { return tab ? stage_coef_t<1>(i) : stage_coef_t<0>(i); }
 
 // Teams of at least four lanes split per-component work of the tableau
 // combinations over their lanes (component d on lane d mod L) and share the
@@ -261,9 +292,9 @@ DMX_DEV void stage_sums(const double (*A)[P::NV], int i, const StageCoef& k, int
 // with keep, the (+) map's exponential coefficients for its VJP
 template <class P>
 DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, double h, double* Y, double* dq,
-                         typename P::QPlusKeep* keep = nullptr) {
+                         typename P::QPlusKeep* keep = nullptr, int tab = 0) {
   constexpr int NQ = P::NQ, NV = P::NV, L = P::TEAM;
-  const StageCoef k = stage_coef(i);
+  const StageCoef k = stage_coef(i, tab);
   double sv[NV], sq[NV];
   if constexpr (kSplitDofs<P>) {
     double* buf = lds_dof_area<L, 3 * NV>();
@@ -293,9 +324,10 @@ DMX_DEV void stage_state(const double* y, const double (*A)[P::NV], int i, doubl
 // cotangents of stage i's combination: v_bar from its velocity part and the
 // (+) increment's velocity term, A_bar[l] for the earlier stages
 template <class P>
-DMX_DEV void stage_distribute(int i, const double* Ybar, const double* dqb, double h, double* vb, double (*Ab)[P::NV]) {
+DMX_DEV void stage_distribute(int i, const double* Ybar, const double* dqb, double h, double* vb, double (*Ab)[P::NV],
+                              int tab = 0) {
   constexpr int NQ = P::NQ, NV = P::NV, L = P::TEAM;
-  const StageCoef k = stage_coef(i);
+  const StageCoef k = stage_coef(i, tab);
 #pragma unroll
   for (int d = 0; d < NV; ++d) vb[d] += Ybar[NQ + d] + h * k.c * dqb[d];
   // a[i][l] = (A A)[i][l] = 0 for l >= i (explicit tableau): every entry is
@@ -410,7 +442,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
 #pragma unroll
           for (int j = 0; j < NX; ++j) Y[j] = y[j];
         } else {
-          stage_state<P>(y, A, i, h, Y, dq);
+          stage_state<P>(y, A, i, h, Y, dq, nullptr, o.tableau);
         }
         double ai[NV];
         const int before = st.status;
@@ -434,10 +466,15 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
       double err = 0.0;
       {
         double dqh[NV], ev[NV], eq[NV], s1[NV], s2[NV], s3[NV];
+        const bool t5 = o.tableau != 0;
         auto comb = [&](int d, double* s1d, double* s2d, double* s3d) {
           double a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-          for (int l = 0; l < 7; ++l) { a1 += kTab.e[l] * A[l][d]; a2 += kTab.bhA[l] * A[l][d]; a3 += kTab.eA[l] * A[l][d]; }
+          for (int l = 0; l < 7; ++l) {
+            const double ce = t5 ? kTab5.e[l] : kTab.e[l], cb = t5 ? kTab5.bhA[l] : kTab.bhA[l];
+            const double cea = t5 ? kTab5.eA[l] : kTab.eA[l];
+            a1 += ce * A[l][d]; a2 += cb * A[l][d]; a3 += cea * A[l][d];
+          }
           *s1d = a1; *s2d = a2; *s3d = a3;
         };
         if constexpr (kSplitDofs<P>) {  // component d on lane d mod L, shared through LDS
@@ -458,7 +495,7 @@ DMX_DEV void fwd_world(const typename P::Model& m, const FwdArgs& a, int w, int 
 #pragma unroll
         for (int d = 0; d < NV; ++d) {
           ev[d] = h * s1[d];
-          dqh[d] = h * (kTab.bh_sum * y[NQ + d] + h * s2[d]);
+          dqh[d] = h * ((t5 ? kTab5.bh_sum : kTab.bh_sum) * y[NQ + d] + h * s2[d]);
           eq[d] = h * h * s3[d];
         }
         double qh[NQ];
@@ -625,7 +662,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll
           for (int j = 0; j < NX; ++j) Y[j] = y[j];
         } else {
-          stage_state<P>(y, A, i, h, Y, dq);
+          stage_state<P>(y, A, i, h, Y, dq, nullptr, o.tableau);
         }
         P::acc(m, Y, tau, false, o.beta, o.newton_maxit, i > 0 ? A[i - 1] : nullptr, ai, st);
 #pragma unroll
@@ -656,7 +693,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
       typename P::QPlusKeep qk;
       if (i < 6) {
         if (i > 0) {
-          stage_state<P>(y, A, i, h, Y, dq, &qk);
+          stage_state<P>(y, A, i, h, Y, dq, &qk, o.tableau);
         } else {  // stage 0 is the step's start state
 #pragma unroll
           for (int j = 0; j < NX; ++j) Y[j] = y[j];
@@ -668,7 +705,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 #pragma unroll
         for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
       } else {
-        stage_state<P>(y, A, 6, h, Y, dq, &qk);
+        stage_state<P>(y, A, 6, h, Y, dq, &qk, o.tableau);
       }
       if (i == 0) {
 #pragma unroll
@@ -678,7 +715,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
       } else {
         double dqb[NV];
         P::qplus_vjp(y, dq, Ybar, qb, dqb, &qk);
-        stage_distribute<P>(i, Ybar, dqb, h, vb, Ab);
+        stage_distribute<P>(i, Ybar, dqb, h, vb, Ab, o.tableau);
       }
     }
 #pragma unroll

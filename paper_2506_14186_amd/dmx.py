@@ -45,7 +45,7 @@ class SolverOpts(C.Structure):
         ("forced", _P), ("forced_n", _P), ("forced_cap", C.c_int32), ("steplog", _P), ("log_n", _P),
         ("log_cap", C.c_int32), ("fwd_counters", _P), ("adj_counters", _P), ("launch_mode", C.c_int32),
         ("h_levels", C.c_int32), ("fail_state", _P), ("world_intervals", _P), ("world_order", _P),
-        ("work_queue", C.c_int32), ("tape_stages", C.c_int32)]
+        ("work_queue", C.c_int32), ("tape_stages", C.c_int32), ("tableau", C.c_int32)]
 
 FWD_COUNTERS = ("attempts", "rhs", "rhs_contacts", "newton_iters", "newton_contacts", "newton_edges",
                 "ls_contacts", "rhs_contacts_pair", "newton_contacts_pair")
