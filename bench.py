@@ -472,7 +472,29 @@ def cube_leg(D, W, args, dev):
     ms, fwd_ms, adj_ms = timed_steps(step, args.other_steps, 1, stream)
     fwd_flops = algorithmic_flops(fc, FWD_FLOPS, model.ncon)
     adj_flops = algorithmic_flops(ac, ADJ_FLOPS, model.ncon)
+    # the same step with the Tsitouras 5(4) pair (the paper's solver)
+    t5 = D.default_opts(tape_steps=2048, tableau=1)
+    r5 = D.rollout(model, x0, None, 1, horizon, opts=t5, tape=True, counters=True)
+    D.rollout_vjp(r5["tape"], xbar)
+    torch.cuda.synchronize()
+
+    def step5(ev):
+        if ev:
+            ev[0].record(stream)
+        D.rollout(model, x0, None, 1, horizon, opts=t5, reuse=r5["tape"])
+        if ev:
+            ev[1].record(stream)
+        D.rollout_vjp(r5["tape"], xbar)
+        if ev:
+            ev[2].record(stream)
+
+    ms5, fwd5, adj5 = timed_steps(step5, args.other_steps, 0, stream)
+    tsit5 = {"ms_per_step": round(ms5, 3), "fwd_ms": round(fwd5, 3), "adj_ms": round(adj5, 3),
+             "value": round(nW * horizon / (ms5 / 1e3), 2),
+             "attempts_mean": float((r5["n_acc"] + r5["n_rej"]).double().mean()),
+             "attempts_mean_dormand_prince": float((r["n_acc"] + r["n_rej"]).double().mean())}
     return {"workload": "cube_toss: 4096 free cubes x 8 corner contacts, 0.5 s, t_c 1 ms",
+            "tsit5": tsit5,
             "value": round(nW * horizon / (ms / 1e3), 2), "unit": "world-sim-s/s", "ms_per_step": round(ms, 3),
             "autotune": {"lanes_per_world": best, "fwd_ms_by_lanes": {str(k): round(v, 3) for k, v in times.items()}}
             if times else None,
