@@ -25,19 +25,35 @@ FLAGS = [
 ]
 
 
-KERNEL_SOURCES = ["dmx_common.hpp", "dmx_free.hpp", "dmx_tree.hpp", "dmx_rk.hpp", "dmx_geom.hpp", "dmx_stack.hpp",
-                  "dmx_stack_rk.hpp", "dmx_stack_adj.hpp"]
+DIGEST = os.path.join(HERE, "kern_stack.digest")
+LLVM = os.environ.get("ROCM_LLVM", "/opt/rocm/llvm/bin")
+
+
+def machine_code_digest(obj):
+    """sha256 prefix of the gfx950 machine code (.text of the device code
+    object) built into a HIP object file: unchanged by edits that leave the
+    kernels' instructions as they were."""
+    import hashlib
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        fat, co, text = (os.path.join(d, n) for n in ("fat.bin", "dev.co", "text.bin"))
+        subprocess.check_call(["objcopy", "-O", "binary", "--only-section=.hip_fatbin", obj, fat])
+        subprocess.check_call([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o",
+                               f"--input={fat}", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"])
+        subprocess.check_call([os.path.join(LLVM, "llvm-objcopy"), "-O", "binary", "--only-section=.text", co, text])
+        with open(text, "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def kernel_digest():
-    """sha256 of the device-code headers (the forward/reverse kernels), used to
-    tell whether recorded hardware counters still describe the built kernels."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    """Digest of the built cube-stack kernels' machine code (written by build()
+    next to the library), used to tell whether recorded hardware counters still
+    describe the built kernels; None if the library was built without it."""
+    try:
+        with open(DIGEST) as f:
+            return f.read().strip() or None
+    except OSError:
+        return None
 
 
 def build(verbose=False, extra=()):
@@ -58,6 +74,8 @@ def build(verbose=False, extra=()):
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
+    with open(DIGEST, "w") as f:
+        f.write(machine_code_digest(os.path.join(OBJ_DIR, "kern_stack.hip.o")) + "\n")
     return LIB
 
 
