@@ -313,6 +313,16 @@ dmx_status dmx_autotune_batch(const dmx_batch* batch, const double* x0, const do
  * any number of times on one tape. */
 dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
 
+/* dmx_rollout_vjp plus the gradient of the same loss with respect to the half
+ * sizes of the model's box geom (a model parameter: the cube side length that
+ * the paper's system identification recovers, Sec. 5.1 and App. E.2), through
+ * the same recorded discretization: geom_size_bar [W][3] (DEVICE, overwritten;
+ * world w's gradient, NaN for worlds whose forward status is nonzero).
+ * Single free bodies whose contacts come from one box geom against planes;
+ * DMX_ERR_UNSUPPORTED otherwise. */
+dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                double* geom_size_bar, void* stream);
+
 /* Optimize-then-discretize gradient of sum(x_out_bar * x_out) (App. C.2, eq.
  * adjoint-equations; with opts.cfd of the forward, the straight-through
  * adjoint of App. C.4, whose Jacobian is that of the CFD field at the

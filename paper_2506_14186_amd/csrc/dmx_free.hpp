@@ -632,9 +632,11 @@ struct FreePhys {
   // J_bar_e = f_e lam - D_e (J_e lam) x*; then back through a_ref, d(r), the
   // contact geometry and the body frame to (q, v).  For the CFD field x* is
   // solved here (its rows differ from the forward's).
+  // hbar (optional, [3]): += the cotangent of the box geom's half sizes
+  // (model parameters: the contact vertices are l + gR (s * h))
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
-                              Stat& st) {
+                              Stat& st, double* hbar = nullptr) {
     V3 p; M3 R; Q4 qh; double inv;
     frame(y, &p, &R, &qh, &inv);
     const double* v = y + NQ;
@@ -666,6 +668,7 @@ struct FreePhys {
     double acc_[18];  // pb[3], Rb[9], vb[6]
 #pragma unroll
     for (int i = 0; i < 18; ++i) acc_[i] = 0.0;
+    double hb_[3] = {0.0, 0.0, 0.0};  // box half sizes
     const int tl = threadIdx.x & (L - 1);
     (void)tl;
 #pragma unroll
@@ -766,6 +769,21 @@ struct FreePhys {
         const V3 cm = (rbar * bs.drdgmax) * n;  // the deepest vertex, through the skin threshold
         pb += cm;
         outer_add(Rb2, cm, box_vertex(pr, bs.kmax));
+        if (hbar) {  // vertex k: d/dh of gR (s * h) in the body frame, s the vertex's signs
+          const V3 ceb0 = Pb + gbar * n;
+          const double* g = pr.gR;
+          const int kv[2] = {bs.k, bs.kmax};
+          const V3 wb[2] = {mulT(R, ceb0), mulT(R, cm)};
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const V3 lb = mk3(g[0] * wb[q].x + g[3] * wb[q].y + g[6] * wb[q].z,
+                              g[1] * wb[q].x + g[4] * wb[q].y + g[7] * wb[q].z,
+                              g[2] * wb[q].x + g[5] * wb[q].y + g[8] * wb[q].z);
+            hb_[0] += (kv[q] & 1) ? lb.x : -lb.x;
+            hb_[1] += (kv[q] & 2) ? lb.y : -lb.y;
+            hb_[2] += (kv[q] & 4) ? lb.z : -lb.z;
+          }
+        }
       }
       V3 ceb = Pb + gbar * n;
       pb += ceb;
@@ -775,6 +793,11 @@ struct FreePhys {
       for (int i = 0; i < 9; ++i) acc_[3 + i] += Rb2.a[i];
     }
     team_sum_big<L, LIVE, 18>(acc_);
+    if (hbar) {
+      team_sum_big<L, LIVE, 3>(hb_);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) hbar[i] += hb_[i];
+    }
     // bias c = (-m g, w x I w) with c_bar = -lam
     V3 w = mk3(v[3], v[4], v[5]);
     V3 Iw = mk3(m.I[0] * w.x + m.I[1] * w.y + m.I[2] * w.z, m.I[3] * w.x + m.I[4] * w.y + m.I[5] * w.z,

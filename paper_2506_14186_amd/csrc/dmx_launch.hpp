@@ -96,6 +96,7 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
     b.x0bar = a.x0bar + (size_t)w * NX;
     b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
     b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
+    b.hbar = a.hbar ? a.hbar + (size_t)w * 3 : nullptr;
     hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }

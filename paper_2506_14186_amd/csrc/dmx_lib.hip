@@ -116,6 +116,7 @@ struct dmx_model {
   void* dev = nullptr;
   std::atomic<int> tuned_team{0};  // team size chosen by dmx_autotune (0: none)
   bool stack_ok = false;           // the stack kernels cover the model (a stack of k >= 1 cubes)
+  int box_geom = -1;               // single free body: the one box geom its contacts use (-2: several)
   dmx::StackModel stk{};
   void* stk_dev = nullptr;
 };
@@ -345,6 +346,7 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     }
     dmx::PairF& pr = f.pair[p];
     pr.gtype = t2;
+    if (t2 == DMX_GEOM_BOX) m->box_geom = (m->box_geom == -1 || m->box_geom == g2) ? g2 : -2;
     pr.ncon = (t2 == DMX_GEOM_CAPSULE) ? 2 : (t2 == DMX_GEOM_BOX) ? 4 : 1;
     double Rg[9], Rp[9];
     quat_to_mat(&d->geom_quat[4 * g2], Rg);
@@ -1263,6 +1265,25 @@ dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0
   a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
   a.g.queue = tp->use_queue ? tp->queue + 1 : nullptr;
   tp->otd(tp->model->dev, a, (hipStream_t)stream, tp->plain);
+  HIP_TRY(hipGetLastError());
+  return DMX_OK;
+}
+
+dmx_status dmx_rollout_vjp_geom(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                double* geom_size_bar, void* stream) {
+  if (!tp || !x_out_bar || !x0_bar || !geom_size_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp->stack || tp->model->kind != 0 || tp->model->box_geom < 0)
+    return fail(DMX_ERR_UNSUPPORTED, "geom size gradients take single free bodies with one box geom");
+  if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  dmx::AdjArgs a{};
+  a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.dt = tp->dt; a.tape = tp->records; a.cap = tp->cap;
+  a.rec = tp->rec; a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar;
+  a.ubar = u_bar; a.hbar = geom_size_bar;
+  a.o = tp->o;
+  a.counters = (long long*)tp->adj_counters;
+  a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
+  a.g.queue = tp->use_queue ? tp->queue + 1 : nullptr;
+  tp->adj(tp->model->dev, a, (hipStream_t)stream, tp->plain);
   HIP_TRY(hipGetLastError());
   return DMX_OK;
 }

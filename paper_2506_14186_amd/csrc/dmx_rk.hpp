@@ -183,6 +183,7 @@ struct FwdArgs {
 struct AdjArgs {
   int W, n_int, nu;
   double dt;            // control interval length (the optimize-then-discretize adjoint's grid)
+  double* hbar;         // [W][3] cotangent of the box geom's half sizes (discrete adjoint), or null
   long long* counters;  // [W][kAdjCounters] or null
   const double* tape;
   long long cap;
@@ -618,9 +619,13 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
+    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
     return;
   }
   for (size_t i = tl; i < nut; i += L) ubw[i] = 0.0;
+  // the model parameters' cotangent: every stage's acceleration map uses the
+  // same half sizes, so their cotangents add up over all stages and steps
+  double hb[3] = {0.0, 0.0, 0.0};
   double yb[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) yb[i] = a.xbar[(size_t)w * NX + i];
@@ -701,7 +706,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         double tb[NV], xs[NV], ab[NV];
 #pragma unroll
         for (int d = 0; d < NV; ++d) { xs[d] = A[i][d]; ab[d] = Ab[i][d]; }
-        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st);
+        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st, a.hbar ? hb : nullptr);
 #pragma unroll
         for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
       } else {
@@ -726,6 +731,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
   if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
+  if (a.hbar) team_store<3, L>(a.hbar + (size_t)w * 3, hb, tl);
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
     team_sum_arr<L, kAdjCounters>(c);

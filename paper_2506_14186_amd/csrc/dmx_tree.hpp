@@ -581,7 +581,8 @@ struct TreePhys {
 
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
-                              Stat& st) {
+                              Stat& st, double* hbar = nullptr) {
+    (void)hbar;  // no box geoms in tree models
     TreeWs<NV, NB>& w = ws();
     const double* q = y;
     const double* v = y + NQ;
