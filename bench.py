@@ -106,6 +106,8 @@ def recorded_traffic(kernel, fname):
     device-code digest)."""
     import re
     from paper_2506_14186_amd import build as B
+    if fname is None:
+        return None
     path = os.path.join(ROOT, "profiles", fname)
     try:
         text = open(path).read()
@@ -342,17 +344,19 @@ def stack_leg(D, W, args, dev):
     if args.two_launch_steps > 0:
         progress("two-launch form ...")
         two_ms, fwd_ms, adj_ms = timed_steps(step2, args.two_launch_steps, 0, stream)
+    # the recorded counters describe the default batch only
+    default_batch = (args.stack_worlds, args.kmax, args.stack_horizon, args.max_attempts) == (1024, 32, 1.0, 4096)
+    traffic_file = "hbm_traffic_stacks_1024.md" if default_batch else None
     # only worlds that reach the horizon count as simulated time
     value = float((nW - int(failed.sum())) * T / (ms / 1e3))
     out = {"value": value, "ms_per_step": ms, "grad_ms": grad_ms, "worlds": nW, "horizon": T,
            "autotune": {"choice": tuning, "tried": tried},
-           "roofline": roofline_single(grad_ms, fwd_flops + adj_flops, "stack_grad_kernel",
-                                       "hbm_traffic_stacks_1024.md"),
+           "roofline": roofline_single(grad_ms, fwd_flops + adj_flops, "stack_grad_kernel", traffic_file),
            "two_launch": None if two_ms is None else {
                "ms_per_step": round(two_ms, 3), "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3),
                "value": round(float((nW - int(failed.sum())) * T / (two_ms / 1e3)), 3),
                "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
-                                       "hbm_traffic_stacks_1024.md")},
+                                       traffic_file)},
            "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
                     "accepted_steps_max": int(n_acc.max()), "attempts_max": int(n_att.max()),
                     "cubes_mean": float(ks.mean()), "cubes_total": int(ks.sum()),

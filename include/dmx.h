@@ -336,6 +336,13 @@ dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double*
  * Free-body and tree models whose tape holds stage accelerations
  * (opts.tape_stages != 0 at the rollout); DMX_ERR_UNSUPPORTED otherwise. */
 dmx_status dmx_rollout_vjp_otd(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream);
+/* dmx_rollout_vjp_otd plus the box geom half sizes' gradient (the parameter
+ * adjoint a_theta of eq. adjoint-equations: the integral of
+ * (dF/dtheta)^T a_x over the horizon, by the adjoint's own quadrature):
+ * geom_size_bar [W][3] (DEVICE, overwritten), models as for
+ * dmx_rollout_vjp_geom. */
+dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                    double* geom_size_bar, void* stream);
 
 /* Captured rollout segments (HIP graphs), for callers that run the same
  * batch repeatedly with new inputs at the same addresses (receding-horizon

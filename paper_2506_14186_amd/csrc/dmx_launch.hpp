@@ -76,7 +76,8 @@ template <class P>
 void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
   constexpr int NXS = P::NQ + P::NV + 3;
   const bool recompute = a.rec < NXS + 6 * P::NV;  // checkpoint-only tape
-  auto kernel = recompute ? dmx::adj_kernel<P, true> : dmx::adj_kernel<P, false>;
+  auto kernel = recompute ? (a.hbar ? dmx::adj_kernel<P, true, true> : dmx::adj_kernel<P, true, false>)
+                          : (a.hbar ? dmx::adj_kernel<P, false, true> : dmx::adj_kernel<P, false, false>);
   if (!plain) {
     const int blocks = grid_blocks<P>(kernel, a.W, a.g.queue != nullptr);
     if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
@@ -124,6 +125,7 @@ void launch_otd(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
     b.x0bar = a.x0bar + (size_t)w * NX;
     b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
     b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
+    b.hbar = a.hbar ? a.hbar + (size_t)w * 3 : nullptr;
     hipLaunchKernelGGL(dmx::otd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }

@@ -1246,7 +1246,23 @@ dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   return DMX_OK;
 }
 
+static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                           double* geom_size_bar, void* stream);
+
 dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
+  return otd_impl(tp, x_out_bar, x0_bar, u_bar, nullptr, stream);
+}
+
+dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                    double* geom_size_bar, void* stream) {
+  if (!geom_size_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp && (tp->stack || tp->model->kind != 0 || tp->model->box_geom < 0))
+    return fail(DMX_ERR_UNSUPPORTED, "geom size gradients take single free bodies with one box geom");
+  return otd_impl(tp, x_out_bar, x0_bar, u_bar, geom_size_bar, stream);
+}
+
+static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                           double* geom_size_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
   if (tp->stack || !tp->otd)
     return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint takes free-body and tree models");
@@ -1259,7 +1275,7 @@ dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0
   dmx::AdjArgs a{};
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.dt = tp->dt; a.tape = tp->records; a.cap = tp->cap;
   a.rec = tp->rec; a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar;
-  a.ubar = u_bar;
+  a.ubar = u_bar; a.hbar = geom_size_bar;
   a.o = tp->o;
   a.counters = (long long*)tp->adj_counters;
   a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;

@@ -602,7 +602,9 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
 // RECOMPUTE: the tape holds only the accepted steps' start states
 // (checkpoints); each step's stage accelerations are solved again, in the
 // forward's order and with its warm starts, before the step is reversed.
-template <class P, bool RECOMPUTE>
+// HB: the box half sizes' cotangent is accumulated (a.hbar set); a template
+// flag, so that the plain reverse sweep carries none of its registers
+template <class P, bool RECOMPUTE, bool HB = false>
 DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
                        double (*Ab)[P::NV]) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
@@ -619,7 +621,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
-    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
+    if (HB && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
     return;
   }
   for (size_t i = tl; i < nut; i += L) ubw[i] = 0.0;
@@ -706,7 +708,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         double tb[NV], xs[NV], ab[NV];
 #pragma unroll
         for (int d = 0; d < NV; ++d) { xs[d] = A[i][d]; ab[d] = Ab[i][d]; }
-        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st, a.hbar ? hb : nullptr);
+        P::acc_vjp(m, Y, tau, xs, ab, o.cfd != 0, o.beta, o.newton_maxit, Ybar, tb, st, HB ? hb : nullptr);
 #pragma unroll
         for (int d = 0; d < NV; ++d) tb_acc[d] += tb[d];
       } else {
@@ -731,7 +733,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
   if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
-  if (a.hbar) team_store<3, L>(a.hbar + (size_t)w * 3, hb, tl);
+  if (HB) team_store<3, L>(a.hbar + (size_t)w * 3, hb, tl);
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
     team_sum_arr<L, kAdjCounters>(c);
@@ -740,7 +742,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
 }
 
-template <class P, bool RECOMPUTE = false>
+template <class P, bool RECOMPUTE = false, bool HB = false>
 __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
   constexpr int L = P::TEAM, NV = P::NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -753,7 +755,7 @@ __global__ void __launch_bounds__(64) adj_kernel(const typename P::Model* __rest
   for (bool first = true;; first = false) {
     const int w = take_world<L>(a.g, a.W, team, first);
     if (w < 0) break;
-    adj_world<P, RECOMPUTE>(*model, a, w, tl, A, Ab);
+    adj_world<P, RECOMPUTE, HB>(*model, a, w, tl, A, Ab);
   }
 }
 
@@ -808,8 +810,12 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   if (a.status[w] != 0 || N <= 0) {
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
+    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
     return;
   }
+  // the box half sizes' adjoint (a_theta of the adjoint equations): stage
+  // slopes HB and its quadrature, accumulated only when asked for
+  double HB[7][3], hacc[3] = {0.0, 0.0, 0.0};
   double lam[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) lam[i] = a.xbar[(size_t)w * NX + i];
@@ -918,7 +924,11 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         have_xw = true;
 #pragma unroll
         for (int r = 0; r < NX; ++r) ybar[r] = 0.0;
-        P::acc_vjp(m, x, tau, xs, Lam + NQ, o.cfd != 0, o.beta, o.newton_maxit, ybar, tb, st);
+        double hbi[3] = {0.0, 0.0, 0.0};
+        P::acc_vjp(m, x, tau, xs, Lam + NQ, o.cfd != 0, o.beta, o.newton_maxit, ybar, tb, st,
+                   a.hbar ? hbi : nullptr);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) HB[i][q] = hbi[q];
         P::kin_vjp(x, Lam, ybar);
 #pragma unroll
         for (int r = 0; r < NX; ++r) G[i][r] = ybar[r];
@@ -961,6 +971,14 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
           tb_acc[d] += H * s;
         }
 #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < 6; ++j) s += kTab.a[6][j] * HB[j][q];
+          hacc[q] += H * s;
+          HB[0][q] = HB[6][q];
+        }
+#pragma unroll
         for (int r = 0; r < NX; ++r) { lam[r] = lamn[r]; G[0][r] = G[6][r]; }
 #pragma unroll
         for (int d = 0; d < NV; ++d) TB[0][d] = TB[6][d];
@@ -980,9 +998,11 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   if (failed) {
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
+    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
   } else {
     P::tangent_project(tape_w + 3, lam);
     team_store<NX, L>(a.x0bar + (size_t)w * NX, lam, tl);
+    if (a.hbar) team_store<3, L>(a.hbar + (size_t)w * 3, hacc, tl);
   }
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
