@@ -239,10 +239,20 @@ class Model:
         return xd, dxd
 
     # -------------------------------------------------------------- rollouts
+    def _controls(self, u, n_int, W):
+        """Contiguous controls [W][n_int][nu]: zeros when u is None (every
+        routine reads n_int * nu values per world), at least one element."""
+        n = W * n_int * self.nu
+        if u is None or not np.size(u):
+            return np.zeros(max(1, n))
+        u = _f64(u)
+        assert u.size == n, (u.size, n)
+        return u
+
     def rollout(self, x0, u, n_int, dt, forced=None, tape_cap=0, log_cap=0, **opts):
         o = make_opts(**opts)
         x0 = _f64(x0)
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        u = self._controls(u, n_int, 1)
         xo = np.zeros(self.nx)
         cnt = np.zeros(5, np.int64)
         tape = np.zeros((tape_cap, 2 + self.nx)) if tape_cap else None
@@ -267,7 +277,7 @@ class Model:
         x0 = np.ascontiguousarray(np.asarray(x0, np.float64).reshape(-1, self.nx))
         W = x0.shape[0]
         nut = n_int * self.nu
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(max(1, W * nut))
+        u = self._controls(u, n_int, W)
         xb = np.ascontiguousarray(np.asarray(xbar, np.float64).reshape(W, self.nx))
         xo, x0b = np.zeros((W, self.nx)), np.zeros((W, self.nx))
         ub = np.zeros(max(1, W * nut))
@@ -281,7 +291,7 @@ class Model:
         """x(tau) at the given times from the continuous extension of the rollout's accepted steps."""
         o = make_opts(**opts)
         taus = _f64(taus)
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        u = self._controls(u, n_int, 1)
         fz = _f64(forced) if forced is not None else None
         nf = 0 if forced is None else len(fz) // 2
         out = np.zeros((taus.size, self.nx))
@@ -298,7 +308,7 @@ class Model:
         contacts per Newton iteration, contacts per line-search segment)."""
         o = make_opts(**opts)
         x0 = _f64(x0)
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        u = self._controls(u, n_int, 1)
         out = np.zeros(16, np.int64)
         lib().orc_flop_count(self.h, _p(x0), _p(u), int(n_int), float(dt), C.byref(o), _p(out))
         res = {f"flops_{p}": int(out[i]) for i, p in enumerate(self.FLOP_PHASES)}
@@ -313,7 +323,7 @@ class Model:
         nd = dx0.shape[0]
         nut = n_int * self.nu
         du = _f64(du) if du is not None else np.zeros(nd * max(nut, 1))
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        u = self._controls(u, n_int, 1)
         xo, tx = np.zeros(self.nx), np.zeros((nd, self.nx))
         cnt = np.zeros(5, np.int64)
         lib().orc_rollout_jvp(self.h, _p(_f64(x0)), _p(u), int(n_int), float(dt), C.byref(o), nd, _p(_f64(dx0)),
@@ -328,7 +338,7 @@ class Model:
         nd = dx0.shape[0]
         nut = n_int * self.nu
         du = _f64(du) if du is not None else np.zeros(nd * max(nut, 1))
-        u = _f64(u) if u is not None and np.size(u) else np.zeros(1)
+        u = self._controls(u, n_int, 1)
         fz = np.ascontiguousarray(forced, np.float64)
         xo, tx = np.zeros(self.nx), np.zeros((nd, self.nx))
         st = lib().orc_rollout_jvp_forced(self.h, _p(_f64(x0)), _p(u), int(n_int), float(dt), C.byref(o), _p(fz),
@@ -340,7 +350,7 @@ class Model:
         o = make_opts(**opts)
         x0 = np.ascontiguousarray(x0, np.float64)
         W = x0.shape[0]
-        u = np.ascontiguousarray(u, np.float64) if u is not None and np.size(u) else np.zeros((W, 1))
+        u = self._controls(u, n_int, W)
         xo = np.zeros_like(x0)
         cnt = np.zeros((W, 5), np.int64)
         lib().orc_rollout_batch(self.h, W, _p(x0), _p(u), int(n_int), float(dt), C.byref(o), _p(xo), _p(cnt),
@@ -352,7 +362,7 @@ class Model:
         x0 = np.ascontiguousarray(x0, np.float64)
         W = x0.shape[0]
         nut = n_int * self.nu
-        u = np.ascontiguousarray(u, np.float64) if nut else np.zeros((W, 1))
+        u = self._controls(u, n_int, W)
         xbar = np.ascontiguousarray(np.broadcast_to(xbar, x0.shape), np.float64)
         xo, x0b = np.zeros_like(x0), np.zeros_like(x0)
         ub = np.zeros((W, max(nut, 1)))
@@ -369,7 +379,7 @@ class Model:
         x0 = np.ascontiguousarray(x0, np.float64)
         W = x0.shape[0]
         nut = n_int * self.nu
-        u = np.ascontiguousarray(u, np.float64) if nut else np.zeros((W, 1))
+        u = self._controls(u, n_int, W)
         xbar = np.ascontiguousarray(np.broadcast_to(xbar, x0.shape), np.float64)
         fz = np.ascontiguousarray(forced, np.float64)
         fn = _i32(forced_n)

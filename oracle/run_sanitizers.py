@@ -3,7 +3,8 @@
 cube, box geom, legged chain, stacks of cubes with box-box contacts (and the
 contact-capacity overflow), rollouts, right-hand sides and their directional
 derivatives, forward-mode gradients and optimize-then-discretize gradients on
-several threads, the CFD field.
+several threads, the CFD field, the continuous extension, both Runge-Kutta
+pairs and the operation counter.
 
     python3 oracle/run_sanitizers.py
 
@@ -57,6 +58,16 @@ xs = W.stack_state(np.zeros((40, 2)))
 for i in range(40):
     xs[7 * i + 2] = 0.1  # coincident cubes: more contacts than the capacity
 print("overflow contacts", over.contacts(xs[:7 * 40]).shape)
+pend = O.Model(W.model_pendulum())
+xp = np.zeros(pend.nx)
+xp[0], xp[pend.nq] = 1.2, 0.5
+fz = np.array([[i * 0.05, 0.05] for i in range(8)]).ravel()
+print("dense states", pend.dense_states(xp, None, 1, 0.4, np.linspace(0.0, 0.4, 9), forced=fz).shape)
+for tab in (0, 1):
+    print("tableau", tab, pend.rollout(xp, None, 1, 0.2, tableau=tab)["status"])
+print("flop count", O.Model(W.model_stack(3, tc=0.003)).flop_count(W.stack_state(np.zeros((3, 2))), None, 1, 0.01)["status"])
+A = np.eye(6) * 2.0
+print("flop cholesky", O.flop_cholesky(A))
 print("sanitized oracle run: done")
 '''
 
