@@ -158,8 +158,12 @@ def serve_leg(D, W, rate, seconds, seed=5, grace_s=10.0, budget=200 * 10 ** 9):
     nxt = 0
     backlog_at_end = None
     try:
+        next_note = 15.0
         while nxt < len(arrivals) or pending:
             now = time.perf_counter() - t0
+            if now >= next_note:  # a progress line from the loop itself, every 15 s
+                progress(f"serving: {nxt} submitted, {len(lat)} completed, {len(pending)} pending")
+                next_note += 15.0
             while nxt < len(arrivals) and arrivals[nxt] <= now:
                 kind = ("cube", "chain", "stack")[int(rng.integers(3))]
                 if kind == "stack":
@@ -220,7 +224,7 @@ def serve_capacity(D, W, burst, seconds, seed=60):
     half wait no longer than 1.5 times the median of the first half plus one
     second."""
     progress(f"serving capacity: burst of {burst} requests ...")
-    b = serve_leg(D, W, burst / 1e-3, 1e-3 * (burst - 0.5), seed=seed, grace_s=150.0)
+    b = serve_leg(D, W, burst / 1e-3, 1e-3, seed=seed, grace_s=150.0)  # about `burst` arrivals within 1 ms
     cap = b["completed"] / max(b["measured_over_s"], 1e-9)
     rate = round(0.5 * cap, 3)
     progress(f"serving at {rate} req/s (half the burst capacity) ...")
