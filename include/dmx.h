@@ -322,6 +322,19 @@ dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_b
  * DMX_ERR_UNSUPPORTED otherwise. */
 dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                 double* geom_size_bar, void* stream);
+/* dmx_rollout_vjp plus the gradient of the same loss with respect to the
+ * model parameters that Sec. 2.1 and App. E.2 name as identifiable: param_bar
+ * [W][6] (DEVICE, overwritten; NaN for worlds whose forward status is
+ * nonzero) holds, in order, the box geom's three half sizes (0 for models
+ * without a box geom), the friction coefficient mu, the solref time constant
+ * t_c and the solref damping ratio.  The last three are each taken as one value
+ * that every contact pair shares: the entry is the derivative under the same
+ * shift of that parameter in every pair.  mu enters the pyramid edges
+ * J_n +- mu J_t and the regularizer R (through (1 + mu^2)); t_c and the
+ * damping ratio enter a_ref's stiffness and damping (Sec. 2.1).  Single free
+ * bodies; DMX_ERR_UNSUPPORTED otherwise. */
+dmx_status dmx_rollout_vjp_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                  double* param_bar, void* stream);
 
 /* Optimize-then-discretize gradient of sum(x_out_bar * x_out) (App. C.2, eq.
  * adjoint-equations; with opts.cfd of the forward, the straight-through
@@ -343,6 +356,12 @@ dmx_status dmx_rollout_vjp_otd(dmx_tape* tape, const double* x_out_bar, double* 
  * dmx_rollout_vjp_geom. */
 dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                     double* geom_size_bar, void* stream);
+/* dmx_rollout_vjp_otd plus the six model-parameter gradients of
+ * dmx_rollout_vjp_params (same layout and meaning), by the parameter adjoint
+ * of eq. adjoint-equations.  Single free bodies; DMX_ERR_UNSUPPORTED
+ * otherwise. */
+dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                      double* param_bar, void* stream);
 
 /* Captured rollout segments (HIP graphs), for callers that run the same
  * batch repeatedly with new inputs at the same addresses (receding-horizon

@@ -12,6 +12,11 @@
 
 namespace dmx {
 
+// model parameters whose cotangents the free-body reverse sweeps accumulate:
+// the box geom's half sizes (3), then the friction coefficient, the solref
+// time constant and the damping ratio shared by the contact pairs
+constexpr int kParams = 6;
+
 struct V3 { double x, y, z; };
 DMX_DEV V3 mk3(double a, double b, double c) { V3 r; r.x = a; r.y = b; r.z = c; return r; }
 DMX_DEV V3 operator+(V3 a, V3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }

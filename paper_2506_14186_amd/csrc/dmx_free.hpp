@@ -28,6 +28,7 @@ struct PairF {
   double rad;
   double p0[3], n[3], t1[3], t2[3];  // world plane point, contact normal and tangents
   double mu, bcoef, kscale, ahat;
+  double solref[2];  // (t_c, damping ratio) that bcoef and kscale come from
   double si[5], cf[5];
   double ssc[4];  // spline scales 1/mid^(p-1), 1/(1-mid)^(p-1): penetration (0, 1) and CFD (2, 3)
   double iwid[2]; // 1/width of the penetration and CFD splines
@@ -632,8 +633,10 @@ struct FreePhys {
   // J_bar_e = f_e lam - D_e (J_e lam) x*; then back through a_ref, d(r), the
   // contact geometry and the body frame to (q, v).  For the CFD field x* is
   // solved here (its rows differ from the forward's).
-  // hbar (optional, [3]): += the cotangent of the box geom's half sizes
-  // (model parameters: the contact vertices are l + gR (s * h))
+  // hbar (optional, [kParams]): += the cotangents of the model parameters:
+  // the box geom's half sizes (the contact vertices are l + gR (s * h)), then
+  // the friction coefficient, the solref time constant and damping ratio, each
+  // as one value shared by every contact pair (a common shift of all pairs)
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
                               Stat& st, double* hbar = nullptr) {
@@ -668,7 +671,9 @@ struct FreePhys {
     double acc_[18];  // pb[3], Rb[9], vb[6]
 #pragma unroll
     for (int i = 0; i < 18; ++i) acc_[i] = 0.0;
-    double hb_[3] = {0.0, 0.0, 0.0};  // box half sizes
+    double hb_[kParams];
+#pragma unroll
+    for (int i = 0; i < kParams; ++i) hb_[i] = 0.0;
     const int tl = threadIdx.x & (L - 1);
     (void)tl;
 #pragma unroll
@@ -683,12 +688,15 @@ struct FreePhys {
       double dD = ddr / (pr.ahat * (1.0 - dimp) * (1.0 - dimp));
       double kk = dimp * pr.kscale;
       double dpt;  // d pterm / dr
+      double ptk;  // d pterm / d kscale
       if (cfd) {
         double dsp;
         double sp = softplus(-rw.r[k], beta, &dsp);
         dpt = pr.kscale * ddr * sp - kk * dsp;
+        ptk = dimp * sp;
       } else {
         dpt = -(pr.kscale * ddr * rw.r[k] + kk);
+        ptk = -dimp * rw.r[k];
       }
       // Per edge e (J_e = J_n + s_e J_t(e), force f_e = D (aref_e - J_e x)):
       // J_e_bar = f_e lam - arb_e (x + bcoef v) with arb_e = D J_e lam, and
@@ -700,6 +708,7 @@ struct FreePhys {
 #pragma unroll
       for (int a = 0; a < NT; ++a) { la[a] = dot6(rw.Jt[k][a], lam); xa[a] = dot6(rw.Jt[k][a], xs); }
       double fe[NE], ae[NE];
+      double dsum = 0.0;  // sum of the edges' D cotangents
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
         const bool on = (act[k] >> e) & 1u;
@@ -711,12 +720,32 @@ struct FreePhys {
         ae[e] = De * sl;
         const double Dbar = on ? sl * gap : 0.0;
         rbar += ae[e] * dpt + Dbar * dD;
+        dsum += Dbar;
       }
       const double Fn = NT == 2 ? (fe[0] + fe[1]) + (fe[NE - 2] + fe[NE - 1]) : fe[0] + fe[1];
       const double An = NT == 2 ? (ae[0] + ae[1]) + (ae[NE - 2] + ae[NE - 1]) : ae[0] + ae[1];
       double Fa[NT], Aa[NT];
 #pragma unroll
       for (int a = 0; a < NT; ++a) { Fa[a] = mu * (fe[2 * a] - fe[2 * a + 1]); Aa[a] = mu * (ae[2 * a] - ae[2 * a + 1]); }
+      if (hbar) {
+        // friction: J_e = J_n +- mu J_t (in the force and in a_ref's damping
+        // term) and D = d / (Ahat (1 - d)) with Ahat = (1 + mu^2) w; solref:
+        // a_ref = -bcoef J_e v + kscale (d(r) times the position term), with
+        // bcoef = 2 / (dw t_c) and kscale = 1 / (dw^2 t_c^2 dr^2)
+        const double vn = dot6(Jn, v);
+        double mub = dsum * (-2.0 * mu * D / (1.0 + mu * mu)), bb = 0.0;
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+          const double vt = dot6(rw.Jt[k][a], v);
+          const double fd = fe[2 * a] - fe[2 * a + 1], ad = ae[2 * a] - ae[2 * a + 1];
+          mub += fd * la[a] - ad * (xa[a] + pr.bcoef * vt);
+          bb -= (ae[2 * a] + ae[2 * a + 1]) * vn + mu * ad * vt;
+        }
+        const double kb = An * ptk;
+        hb_[3] += mub;
+        hb_[4] -= (pr.bcoef * bb + 2.0 * pr.kscale * kb) / pr.solref[0];
+        hb_[5] -= 2.0 * pr.kscale * kb / pr.solref[1];
+      }
       double Jb[1 + NT][6];  // cotangents of J_n and the lane's tangent rows
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
@@ -794,9 +823,9 @@ struct FreePhys {
     }
     team_sum_big<L, LIVE, 18>(acc_);
     if (hbar) {
-      team_sum_big<L, LIVE, 3>(hb_);
+      team_sum_big<L, LIVE, kParams>(hb_);
 #pragma unroll
-      for (int i = 0; i < 3; ++i) hbar[i] += hb_[i];
+      for (int i = 0; i < kParams; ++i) hbar[i] += hb_[i];
     }
     // bias c = (-m g, w x I w) with c_bar = -lam
     V3 w = mk3(v[3], v[4], v[5]);

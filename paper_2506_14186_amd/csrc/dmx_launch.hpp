@@ -97,7 +97,7 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
     b.x0bar = a.x0bar + (size_t)w * NX;
     b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
     b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
-    b.hbar = a.hbar ? a.hbar + (size_t)w * 3 : nullptr;
+    b.hbar = a.hbar ? a.hbar + (size_t)w * a.npar : nullptr;
     hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }
@@ -106,10 +106,11 @@ void launch_adj(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
 // plain form launches world by world)
 template <class P>
 void launch_otd(const void* model, const dmx::AdjArgs& a, hipStream_t s, int plain) {
+  auto kernel = a.hbar ? dmx::otd_kernel<P, true> : dmx::otd_kernel<P, false>;
   if (!plain) {
-    const int blocks = grid_blocks<P>(dmx::otd_kernel<P>, a.W, a.g.queue != nullptr);
+    const int blocks = grid_blocks<P>(kernel, a.W, a.g.queue != nullptr);
     if (a.g.queue) hipLaunchKernelGGL(dmx::reset_queue, dim3(1), dim3(64), 0, s, a.g.queue);
-    hipLaunchKernelGGL(dmx::otd_kernel<P>, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64), 0, s, (const typename P::Model*)model, a);
     return;
   }
   constexpr int NX = P::NQ + P::NV;
@@ -125,8 +126,8 @@ void launch_otd(const void* model, const dmx::AdjArgs& a, hipStream_t s, int pla
     b.x0bar = a.x0bar + (size_t)w * NX;
     b.ubar = a.ubar ? a.ubar + (size_t)w * nut : nullptr;
     b.counters = a.counters ? a.counters + (size_t)w * dmx::kAdjCounters : nullptr;
-    b.hbar = a.hbar ? a.hbar + (size_t)w * 3 : nullptr;
-    hipLaunchKernelGGL(dmx::otd_kernel<P>, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
+    b.hbar = a.hbar ? a.hbar + (size_t)w * a.npar : nullptr;
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(64), 0, s, (const typename P::Model*)model, b);
   }
 }
 

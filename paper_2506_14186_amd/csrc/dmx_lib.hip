@@ -372,6 +372,8 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     pr.bcoef = 2.0 / (dw * tc);
     pr.kscale = 1.0 / (dw * dw * tc * tc * dr * dr);
     pr.ahat = (1.0 + pr.mu * pr.mu) * invw;
+    pr.solref[0] = tc;
+    pr.solref[1] = dr;
     for (int c = 0; c < pr.ncon; ++c) {
       if (nc >= dmx::kMaxSlots) { delete m; return fail(DMX_ERR_UNSUPPORTED, "too many contact slots"); }
       f.cpair[nc] = p;
@@ -602,6 +604,8 @@ static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out) {
     pr.bcoef = 2.0 / (dw * tc);
     pr.kscale = 1.0 / (dw * dw * tc * tc * dr * dr);
     pr.ahat = (1.0 + pr.mu * pr.mu) * invw[t.pbody[p]];
+    pr.solref[0] = tc;
+    pr.solref[1] = dr;
     for (int c = 0; c < pr.ncon; ++c) {
       if (nc >= dmx::kMaxSlots) { delete m; return fail(DMX_ERR_UNSUPPORTED, "too many contact slots"); }
       t.cpair[nc] = p;
@@ -1247,10 +1251,10 @@ dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar
 }
 
 static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
-                           double* geom_size_bar, void* stream);
+                           double* param_bar, int npar, void* stream);
 
 dmx_status dmx_rollout_vjp_otd(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
-  return otd_impl(tp, x_out_bar, x0_bar, u_bar, nullptr, stream);
+  return otd_impl(tp, x_out_bar, x0_bar, u_bar, nullptr, 0, stream);
 }
 
 dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
@@ -1258,11 +1262,19 @@ dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tp, const double* x_out_bar, doubl
   if (!geom_size_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
   if (tp && (tp->stack || tp->model->kind != 0 || tp->model->box_geom < 0))
     return fail(DMX_ERR_UNSUPPORTED, "geom size gradients take single free bodies with one box geom");
-  return otd_impl(tp, x_out_bar, x0_bar, u_bar, geom_size_bar, stream);
+  return otd_impl(tp, x_out_bar, x0_bar, u_bar, geom_size_bar, 3, stream);
+}
+
+dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                      double* param_bar, void* stream) {
+  if (!param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp && (tp->stack || tp->model->kind != 0))
+    return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take single free bodies");
+  return otd_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
 }
 
 static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
-                           double* geom_size_bar, void* stream) {
+                           double* param_bar, int npar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
   if (tp->stack || !tp->otd)
     return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint takes free-body and tree models");
@@ -1275,7 +1287,7 @@ static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   dmx::AdjArgs a{};
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.dt = tp->dt; a.tape = tp->records; a.cap = tp->cap;
   a.rec = tp->rec; a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar;
-  a.ubar = u_bar; a.hbar = geom_size_bar;
+  a.ubar = u_bar; a.hbar = param_bar; a.npar = npar;
   a.o = tp->o;
   a.counters = (long long*)tp->adj_counters;
   a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;
@@ -1285,16 +1297,32 @@ static dmx_status otd_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar
   return DMX_OK;
 }
 
+static dmx_status params_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                              double* param_bar, int npar, void* stream);
+
 dmx_status dmx_rollout_vjp_geom(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
                                 double* geom_size_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar || !geom_size_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
   if (tp->stack || tp->model->kind != 0 || tp->model->box_geom < 0)
     return fail(DMX_ERR_UNSUPPORTED, "geom size gradients take single free bodies with one box geom");
+  return params_impl(tp, x_out_bar, x0_bar, u_bar, geom_size_bar, 3, stream);
+}
+
+dmx_status dmx_rollout_vjp_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                                  double* param_bar, void* stream) {
+  if (!tp || !x_out_bar || !x0_bar || !param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
+  if (tp->stack || tp->model->kind != 0)
+    return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take single free bodies");
+  return params_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
+}
+
+static dmx_status params_impl(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                              double* param_bar, int npar, void* stream) {
   if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
   dmx::AdjArgs a{};
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.dt = tp->dt; a.tape = tp->records; a.cap = tp->cap;
   a.rec = tp->rec; a.n_acc = tp->n_acc; a.status = tp->status; a.u = tp->u; a.xbar = x_out_bar; a.x0bar = x0_bar;
-  a.ubar = u_bar; a.hbar = geom_size_bar;
+  a.ubar = u_bar; a.hbar = param_bar; a.npar = npar;
   a.o = tp->o;
   a.counters = (long long*)tp->adj_counters;
   a.g.n_int_w = tp->world_intervals; a.g.order = tp->world_order;

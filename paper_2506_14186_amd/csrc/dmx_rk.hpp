@@ -183,7 +183,8 @@ struct FwdArgs {
 struct AdjArgs {
   int W, n_int, nu;
   double dt;            // control interval length (the optimize-then-discretize adjoint's grid)
-  double* hbar;         // [W][3] cotangent of the box geom's half sizes (discrete adjoint), or null
+  double* hbar;         // [W][npar] model-parameter cotangents (the first npar of kParams), or null
+  int npar;             // 3 (box half sizes) or kParams
   long long* counters;  // [W][kAdjCounters] or null
   const double* tape;
   long long cap;
@@ -602,7 +603,14 @@ __global__ void __launch_bounds__(64) fwd_kernel(const typename P::Model* __rest
 // RECOMPUTE: the tape holds only the accepted steps' start states
 // (checkpoints); each step's stage accelerations are solved again, in the
 // forward's order and with its warm starts, before the step is reversed.
-// HB: the box half sizes' cotangent is accumulated (a.hbar set); a template
+// the first a.npar model-parameter cotangents of world w
+template <int L>
+DMX_DEV void store_params(const AdjArgs& a, int w, const double* hb, int tl) {
+  if (a.npar == kParams) team_store<kParams, L>(a.hbar + (size_t)w * kParams, hb, tl);
+  else team_store<3, L>(a.hbar + (size_t)w * 3, hb, tl);
+}
+
+// HB: the model parameters' cotangent is accumulated (a.hbar set); a template
 // flag, so that the plain reverse sweep carries none of its registers
 template <class P, bool RECOMPUTE, bool HB = false>
 DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
@@ -621,13 +629,15 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
-    if (HB && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
+    if (HB) for (int i = tl; i < a.npar; i += L) a.hbar[(size_t)w * a.npar + i] = nan;
     return;
   }
   for (size_t i = tl; i < nut; i += L) ubw[i] = 0.0;
   // the model parameters' cotangent: every stage's acceleration map uses the
-  // same half sizes, so their cotangents add up over all stages and steps
-  double hb[3] = {0.0, 0.0, 0.0};
+  // same parameters, so their cotangents add up over all stages and steps
+  double hb[HB ? kParams : 1];
+#pragma unroll
+  for (int i = 0; i < (HB ? kParams : 1); ++i) hb[i] = 0.0;
   double yb[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) yb[i] = a.xbar[(size_t)w * NX + i];
@@ -733,7 +743,7 @@ DMX_DEV void adj_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   }
   if (cur_k >= 0 && tl == 0) store_ubar<P>(m, tb_acc, ubw + (size_t)cur_k * a.nu, a.nu);
   team_store<NX, L>(a.x0bar + (size_t)w * NX, yb, tl);
-  if (HB) team_store<3, L>(a.hbar + (size_t)w * 3, hb, tl);
+  if (HB) store_params<L>(a, w, hb, tl);
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
     team_sum_arr<L, kAdjCounters>(c);
@@ -794,7 +804,8 @@ DMX_DEV void dense_weights(double th, double* w) {
 // A: stage accelerations and V: stage velocities (LDS, [7][NV]) of the
 // forward step the continuous extension currently reads; G, TB: the adjoint's
 // stage slopes (raw state cotangent rates, generalized-force cotangents).
-template <class P>
+// HB: the model parameters' cotangent is accumulated (a.hbar set).
+template <class P, bool HB = false>
 DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int tl, double (*A)[P::NV],
                        double (*V)[P::NV], double (*G)[P::NQ + P::NV], double (*TB)[P::NV]) {
   constexpr int L = P::TEAM, NQ = P::NQ, NV = P::NV, NX = NQ + NV;
@@ -810,12 +821,18 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   if (a.status[w] != 0 || N <= 0) {
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
-    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
+    if (HB) for (int i = tl; i < a.npar; i += L) a.hbar[(size_t)w * a.npar + i] = nan;
     return;
   }
-  // the box half sizes' adjoint (a_theta of the adjoint equations): stage
-  // slopes HB and its quadrature, accumulated only when asked for
-  double HB[7][3], hacc[3] = {0.0, 0.0, 0.0};
+  // a dense control row longer than the world's horizon: the intervals it
+  // never reaches get 0 (its own intervals are written as the sweep leaves them)
+  for (size_t i = (size_t)n_int * a.nu + tl; i < nut; i += L) ubw[i] = 0.0;
+  // the model parameters' adjoint (a_theta of the adjoint equations): stage
+  // slopes PB and its quadrature, accumulated only when asked for
+  constexpr int NPH = HB ? kParams : 1;
+  double PB[7][NPH], hacc[NPH];
+#pragma unroll
+  for (int q = 0; q < NPH; ++q) hacc[q] = 0.0;
   double lam[NX];
 #pragma unroll
   for (int i = 0; i < NX; ++i) lam[i] = a.xbar[(size_t)w * NX + i];
@@ -924,11 +941,13 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         have_xw = true;
 #pragma unroll
         for (int r = 0; r < NX; ++r) ybar[r] = 0.0;
-        double hbi[3] = {0.0, 0.0, 0.0};
-        P::acc_vjp(m, x, tau, xs, Lam + NQ, o.cfd != 0, o.beta, o.newton_maxit, ybar, tb, st,
-                   a.hbar ? hbi : nullptr);
+        double hbi[NPH];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) HB[i][q] = hbi[q];
+        for (int q = 0; q < NPH; ++q) hbi[q] = 0.0;
+        P::acc_vjp(m, x, tau, xs, Lam + NQ, o.cfd != 0, o.beta, o.newton_maxit, ybar, tb, st,
+                   HB ? hbi : nullptr);
+#pragma unroll
+        for (int q = 0; q < NPH; ++q) PB[i][q] = hbi[q];
         P::kin_vjp(x, Lam, ybar);
 #pragma unroll
         for (int r = 0; r < NX; ++r) G[i][r] = ybar[r];
@@ -970,13 +989,15 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
           for (int j = 0; j < 6; ++j) s += kTab.a[6][j] * TB[j][d];
           tb_acc[d] += H * s;
         }
+        if (HB) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          double s = 0.0;
+          for (int q = 0; q < NPH; ++q) {
+            double s = 0.0;
 #pragma unroll
-          for (int j = 0; j < 6; ++j) s += kTab.a[6][j] * HB[j][q];
-          hacc[q] += H * s;
-          HB[0][q] = HB[6][q];
+            for (int j = 0; j < 6; ++j) s += kTab.a[6][j] * PB[j][q];
+            hacc[q] += H * s;
+            PB[0][q] = PB[6][q];
+          }
         }
 #pragma unroll
         for (int r = 0; r < NX; ++r) { lam[r] = lamn[r]; G[0][r] = G[6][r]; }
@@ -998,11 +1019,11 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
   if (failed) {
     for (int i = tl; i < NX; i += L) a.x0bar[(size_t)w * NX + i] = nan;
     for (size_t i = tl; i < nut; i += L) ubw[i] = nan;
-    if (a.hbar && tl < 3) a.hbar[(size_t)w * 3 + tl] = nan;
+    if (HB) for (int i = tl; i < a.npar; i += L) a.hbar[(size_t)w * a.npar + i] = nan;
   } else {
     P::tangent_project(tape_w + 3, lam);
     team_store<NX, L>(a.x0bar + (size_t)w * NX, lam, tl);
-    if (a.hbar) team_store<3, L>(a.hbar + (size_t)w * 3, hacc, tl);
+    if (HB) store_params<L>(a, w, hacc, tl);
   }
   if (a.counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
@@ -1014,7 +1035,7 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
 
 // One team per world; the stage slopes of teams of two or more lanes sit in
 // LDS, those of one-lane teams (64 worlds per wavefront) in private memory.
-template <class P>
+template <class P, bool HB = false>
 __global__ void __launch_bounds__(64) otd_kernel(const typename P::Model* __restrict__ model, AdjArgs a) {
   constexpr int L = P::TEAM, NV = P::NV, NX = P::NQ + P::NV;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1029,7 +1050,7 @@ __global__ void __launch_bounds__(64) otd_kernel(const typename P::Model* __rest
     for (bool first = true;; first = false) {
       const int w = take_world<L>(a.g, a.W, team, first);
       if (w < 0) break;
-      otd_world<P>(*model, a, w, tl, A, V, Gp, Tp);
+      otd_world<P, HB>(*model, a, w, tl, A, V, Gp, Tp);
     }
   } else {
     __shared__ double sG[64 / L][7][NX];
@@ -1039,7 +1060,7 @@ __global__ void __launch_bounds__(64) otd_kernel(const typename P::Model* __rest
     for (bool first = true;; first = false) {
       const int w = take_world<L>(a.g, a.W, team, first);
       if (w < 0) break;
-      otd_world<P>(*model, a, w, tl, A, V, G, T);
+      otd_world<P, HB>(*model, a, w, tl, A, V, G, T);
     }
   }
 }

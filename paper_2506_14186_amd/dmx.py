@@ -63,6 +63,8 @@ _lib.dmx_rollout_vjp.argtypes = [_P, _P, _P, _P, _P]
 _lib.dmx_rollout_vjp_otd.argtypes = [_P, _P, _P, _P, _P]
 _lib.dmx_rollout_vjp_geom.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.dmx_rollout_vjp_otd_geom.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.dmx_rollout_vjp_params.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.dmx_rollout_vjp_otd_params.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.dmx_accel.argtypes = [_P, C.c_int32, _P, _P, C.c_int32, _P, _P, _P]
 _lib.dmx_autotune.argtypes = [_P, C.c_int32, C.c_int32, C.c_double, _P, _P, _P, _P, _P, _P, _P]
 _lib.dmx_tape_info.argtypes = [_P, _P, _P]
@@ -78,14 +80,15 @@ _lib.dmx_rollout_batch_grad.argtypes = [_P, C.POINTER(SolverOpts), _P, _P, _P, _
 for _f in ("dmx_model_create", "dmx_model_info", "dmx_rollout", "dmx_rollout_vjp", "dmx_tape_info",
            "dmx_tape_data", "dmx_accel", "dmx_autotune", "dmx_tape_layout", "dmx_batch_layout",
            "dmx_rollout_batch", "dmx_rollout_noalloc", "dmx_rollout_batch_grad", "dmx_rollout_vjp_otd",
-           "dmx_rollout_vjp_geom", "dmx_rollout_vjp_otd_geom"):
+           "dmx_rollout_vjp_geom", "dmx_rollout_vjp_otd_geom", "dmx_rollout_vjp_params",
+           "dmx_rollout_vjp_otd_params"):
     getattr(_lib, _f).restype = C.c_int32
 
 EXPORTS = ["dmx_default_opts", "dmx_model_create", "dmx_model_info", "dmx_model_destroy", "dmx_rollout",
            "dmx_rollout_vjp", "dmx_tape_info", "dmx_tape_data", "dmx_tape_destroy", "dmx_accel", "dmx_autotune",
            "dmx_last_error", "dmx_batch_layout", "dmx_rollout_batch", "dmx_tape_layout", "dmx_rollout_noalloc",
            "dmx_rollout_batch_grad", "dmx_rollout_vjp_otd", "dmx_rollout_vjp_geom",
-           "dmx_rollout_vjp_otd_geom"]
+           "dmx_rollout_vjp_otd_geom", "dmx_rollout_vjp_params", "dmx_rollout_vjp_otd_params"]
 
 
 class Batch(C.Structure):
@@ -454,6 +457,30 @@ def rollout_vjp_otd_geom(tape, x_out_bar):
     ub = torch.empty((tape.W, tape.n_int, m.nu), dtype=torch.float64, device=xb.device) if m.nu else None
     _check(_lib.dmx_rollout_vjp_otd_geom(tape.h, _ptr(xb), _ptr(x0b), _ptr(ub), _ptr(hb), _stream()))
     return x0b, ub, hb
+
+
+PARAMS = ("half_x", "half_y", "half_z", "friction", "solref_timeconst", "solref_dampratio")
+
+
+def _params(fn, tape, x_out_bar):
+    xb = x_out_bar.contiguous()
+    m = tape.model
+    x0b = torch.empty_like(xb)
+    pb = torch.empty((tape.W, len(PARAMS)), dtype=torch.float64, device=xb.device)
+    ub = torch.empty((tape.W, tape.n_int, m.nu), dtype=torch.float64, device=xb.device) if m.nu else None
+    _check(fn(tape.h, _ptr(xb), _ptr(x0b), _ptr(ub), _ptr(pb), _stream()))
+    return x0b, ub, pb
+
+
+def rollout_vjp_params(tape, x_out_bar):
+    """x0_bar, u_bar and the model-parameter gradient [W, 6] (columns PARAMS)
+    of sum(x_out_bar * x_out) through the recorded discretization."""
+    return _params(_lib.dmx_rollout_vjp_params, tape, x_out_bar)
+
+
+def rollout_vjp_otd_params(tape, x_out_bar):
+    """Optimize-then-discretize x0_bar, u_bar and model-parameter gradient [W, 6]."""
+    return _params(_lib.dmx_rollout_vjp_otd_params, tape, x_out_bar)
 
 
 def rollout_vjp_otd(tape, x_out_bar):

@@ -1,0 +1,156 @@
+"""Model-parameter gradients beyond the side length (App. E.2 identifies mass,
+solref, solimp and friction alongside it): the gradient of a final-state loss
+with respect to the contact pairs' friction coefficient and solref (time
+constant, damping ratio), with the box half sizes, through the recorded
+discretization (dmx_rollout_vjp_params) and by the parameter adjoint of the
+continuous adjoint equations (dmx_rollout_vjp_otd_params).
+
+Parity: central differences of the oracle's frozen-step map (the GPU's own
+accepted steps replayed by the oracle with every pair's parameter shifted by
++-eps, the model rebuilt each time), 1e-4 relative (to the parameter's largest gradient over the worlds) where the
+differences have converged (relative steps 1e-6 and 1e-7 agree to 2e-5: no
+contact or friction state switches within the perturbation), 2e-3 elsewhere.
+Cases: a box and a corner cube (eight sphere-plane pairs) sliding and tipping
+on the plane on persistent contact, the corner cube under controls.  The
+continuous form is checked against central differences of the oracle's
+forward at rtol 1e-12."""
+import copy
+
+import numpy as np
+import pytest
+
+from paper_2506_14186_amd import workloads as W
+from replay_check import tape_steps
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_14186_amd import dmx
+    return dmx
+
+
+def _t(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _shifted(desc, j, delta):
+    """desc with parameter column j (3 friction, 4 solref t_c, 5 damping
+    ratio) shifted by delta in every contact pair."""
+    d = copy.deepcopy(desc)
+    for p in d["pairs"]:
+        if j == 3:
+            p["mu"] += delta
+        else:
+            p["solref"][j - 4] += delta
+    return d
+
+
+def _base_value(desc, j):
+    p = desc["pairs"][0]
+    return p["mu"] if j == 3 else p["solref"][j - 4]
+
+
+def _sliding_states(n, seed, height):
+    rng = np.random.default_rng(seed)
+    x0 = np.zeros((n, 13))
+    x0[:, 2] = height
+    tilt = rng.uniform(0.0, 0.1, n)
+    x0[:, 3] = np.cos(tilt / 2)
+    x0[:, 4] = np.sin(tilt / 2)
+    x0[:, 7] = rng.uniform(-1.0, 1.0, n)
+    x0[:, 8] = rng.uniform(-1.0, 1.0, n)
+    x0[:, 12] = rng.uniform(-2.0, 2.0, n)
+    return x0
+
+
+CASES = {
+    "box": (lambda: W.model_box(tc=0.005, mu=0.5), 0.0995, False),
+    "corner_cube": (lambda: W.model_cube_corners(tc=0.005, mu=0.5, ctrl=True), 0.1095, True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_contact_parameter_gradient_matches_oracle_differences(D, oracle, case):
+    make, height, ctrl = CASES[case]
+    desc = make()
+    x0 = _sliding_states(6, 3, height)
+    T, n_int = 0.08, 2
+    rng = np.random.default_rng(4)
+    model = D.Model(desc)
+    u = rng.uniform(-2.0, 2.0, (x0.shape[0], n_int, model.nu)) if ctrl else None
+    xb = np.zeros_like(x0)
+    xb[:, 0], xb[:, 1], xb[:, 2], xb[:, 5] = 1.0, -0.5, 2.0, 1.0
+    r = D.rollout(model, _t(x0), None if u is None else _t(u), n_int, T / n_int,
+                  opts=D.default_opts(tape_steps=8192), tape=True)
+    assert int(r["status"].abs().sum()) == 0
+    gx, gu, gp = D.rollout_vjp_params(r["tape"], _t(xb))
+    gp = gp.cpu().numpy()
+    gx_plain, gu_plain = D.rollout_vjp(r["tape"], _t(xb))
+    np.testing.assert_array_equal(gx.cpu().numpy(), gx_plain.cpu().numpy())
+    if ctrl:
+        np.testing.assert_array_equal(gu.cpu().numpy(), gu_plain.cpu().numpy())
+    else:
+        _, _, gh = D.rollout_vjp_geom(r["tape"], _t(xb))
+        np.testing.assert_array_equal(gp[:, :3], gh.cpu().numpy())
+    if ctrl:
+        assert not gp[:, :3].any()  # no box geom
+    forced, n = tape_steps(r["tape"])
+
+    def central(rel):
+        fd = np.zeros((x0.shape[0], 3))
+        for c, j in enumerate((3, 4, 5)):
+            eps = rel * abs(_base_value(desc, j))
+            vals = []
+            for s in (+1, -1):
+                om = oracle.Model(_shifted(desc, j, s * eps))
+                res = om.grad_forced_batch(x0, u, n_int, T / n_int, xb, forced, n, n_threads=6)
+                vals.append(np.sum(xb * res["x"], axis=1))
+            fd[:, c] = (vals[0] - vals[1]) / (2 * eps)
+        return fd
+
+    fd6, fd7 = central(1e-6), central(1e-7)
+    g = gp[:, 3:]
+    scale = np.maximum(np.abs(fd7).max(axis=0, keepdims=True), 1e-12)  # per parameter: units differ
+    smooth = np.abs(fd6 - fd7) / scale <= 2e-5
+    err = np.abs(g - fd7) / scale
+    print(f"{case}: friction/solref gradient vs oracle differences: max rel err {err[smooth].max():.2e} over "
+          f"{int(smooth.sum())}/{smooth.size} converged entries (all entries {err.max():.2e})\n{g}\n{fd7}")
+    assert smooth.mean() >= 0.8
+    assert err[smooth].max() <= 1e-4
+    assert err.max() <= 2e-3
+
+
+def test_otd_contact_parameter_gradient_is_the_continuous_derivative(D, oracle):
+    desc = W.model_box(tc=0.005, mu=0.5)
+    x0 = _sliding_states(4, 5, 0.0995)
+    T = 0.08
+    xb = np.zeros_like(x0)
+    xb[:, 0], xb[:, 2] = 1.0, 2.0
+    model = D.Model(desc)
+    opts = D.default_opts(rtol=1e-10, atol=1e-10, tape_steps=65536, tape_stages=1)
+    r = D.rollout(model, _t(x0), None, 1, T, opts=opts, tape=True)
+    assert int(r["status"].abs().sum()) == 0
+    _, _, p_otd = D.rollout_vjp_otd_params(r["tape"], _t(xb))
+    _, _, h_otd = D.rollout_vjp_otd_geom(r["tape"], _t(xb))
+    p_otd = p_otd.cpu().numpy()
+    np.testing.assert_array_equal(p_otd[:, :3], h_otd.cpu().numpy())
+    fd = np.zeros((x0.shape[0], 3))
+    for c, j in enumerate((3, 4, 5)):
+        eps = 1e-5 * abs(_base_value(desc, j))
+        vals = []
+        for s in (+1, -1):
+            om = oracle.Model(_shifted(desc, j, s * eps))
+            res = om.rollout_batch(x0, None, 1, T, n_threads=4, rtol=1e-12, atol=1e-12)
+            vals.append(np.sum(xb * res["x"], axis=1))
+        fd[:, c] = (vals[0] - vals[1]) / (2 * eps)
+    scale = np.maximum(np.abs(fd).max(axis=0, keepdims=True), 1e-12)
+    err = np.abs(p_otd[:, 3:] - fd) / scale
+    print(f"friction/solref gradient (continuous adjoint) vs differences at rtol 1e-12: max rel err {err.max():.2e}"
+          f"\n{p_otd[:, 3:]}\n{fd}")
+    assert err.max() <= 5e-3
