@@ -636,7 +636,8 @@ struct FreePhys {
   // hbar (optional, [kParams]): += the cotangents of the model parameters:
   // the box geom's half sizes (the contact vertices are l + gR (s * h)), then
   // the friction coefficient, the solref time constant and damping ratio, each
-  // as one value shared by every contact pair (a common shift of all pairs)
+  // as one value shared by every contact pair (a common shift of all pairs),
+  // and the body's mass
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
                               Stat& st, double* hbar = nullptr) {
@@ -826,6 +827,10 @@ struct FreePhys {
       team_sum_big<L, LIVE, kParams>(hb_);
 #pragma unroll
       for (int i = 0; i < kParams; ++i) hbar[i] += hb_[i];
+      // mass: the inertia of a uniform solid, the bias (-m g, w x I w) and D
+      // (through Ahat = (1 + mu^2) / m) all scale with m, so H x* = rhs keeps
+      // x* = H^-1 tau + (a part free of m) and m_bar = -lam . tau / m
+      hbar[6] -= dot6(lam, tau) * m.imass;
     }
     // bias c = (-m g, w x I w) with c_bar = -lam
     V3 w = mk3(v[3], v[4], v[5]);
