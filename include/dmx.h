@@ -323,17 +323,19 @@ dmx_status dmx_rollout_vjp(dmx_tape* tape, const double* x_out_bar, double* x0_b
 dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                 double* geom_size_bar, void* stream);
 /* dmx_rollout_vjp plus the gradient of the same loss with respect to the
- * model parameters that App. E.2 identifies: param_bar [W][7] (DEVICE,
+ * model parameters that App. E.2 identifies: param_bar [W][12] (DEVICE,
  * overwritten; NaN for worlds whose forward status is nonzero) holds, in
  * order, the box geom's three half sizes (0 for models without a box geom),
  * the friction coefficient mu, the solref time constant t_c, the solref
- * damping ratio and the body's mass.  mu, t_c and the damping ratio are each
- * taken as one value that every contact pair shares: the entry is the
+ * damping ratio, the body's mass, and the solimp parameters (d0, dwidth,
+ * width, midpoint, power).  The contact parameters (mu, solref, solimp) are
+ * each taken as one value that every contact pair shares: the entry is the
  * derivative under the same shift of that parameter in every pair.  mu enters
  * the pyramid edges J_n +- mu J_t and the regularizer R (through (1 + mu^2));
- * t_c and the damping ratio enter a_ref's stiffness and damping (Sec. 2.1);
- * the mass moves the body's inertia with it (a uniform solid).  Single free
- * bodies; DMX_ERR_UNSUPPORTED otherwise. */
+ * t_c and the damping ratio enter a_ref's stiffness and damping; solimp
+ * shapes the impedance d(r) in R and a_ref (Sec. 2.1; dwidth also scales
+ * a_ref's stiffness and damping); the mass moves the body's inertia with it
+ * (a uniform solid).  Single free bodies; DMX_ERR_UNSUPPORTED otherwise. */
 dmx_status dmx_rollout_vjp_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                   double* param_bar, void* stream);
 
@@ -357,7 +359,7 @@ dmx_status dmx_rollout_vjp_otd(dmx_tape* tape, const double* x_out_bar, double* 
  * dmx_rollout_vjp_geom. */
 dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                     double* geom_size_bar, void* stream);
-/* dmx_rollout_vjp_otd plus the seven model-parameter gradients of
+/* dmx_rollout_vjp_otd plus the twelve model-parameter gradients of
  * dmx_rollout_vjp_params (same layout and meaning), by the parameter adjoint
  * of eq. adjoint-equations.  Single free bodies; DMX_ERR_UNSUPPORTED
  * otherwise. */

@@ -14,9 +14,9 @@ namespace dmx {
 
 // model parameters whose cotangents the free-body reverse sweeps accumulate:
 // the box geom's half sizes (3), then the friction coefficient, the solref
-// time constant and the damping ratio shared by the contact pairs, then the
-// body's mass
-constexpr int kParams = 7;
+// time constant and the damping ratio shared by the contact pairs, the body's
+// mass, then the five solimp parameters shared by the pairs
+constexpr int kParams = 12;
 
 struct V3 { double x, y, z; };
 DMX_DEV V3 mk3(double a, double b, double c) { V3 r; r.x = a; r.y = b; r.z = c; return r; }

@@ -128,6 +128,32 @@ DMX_DEV double impedance(const PairF& p, double r, double* ddr) {
   return p.cf[1] + y * (p.cf[0] - p.cf[1]);
 }
 
+// Derivatives of the penetration impedance d(r) (r < 0) with respect to the
+// solimp parameters (d0, dwidth, width, midpoint, power); zero for r >= 0,
+// where the contacts-from-distance spline (its own parameters) or no row
+// applies.  With x = -r / width and the power spline y(x):
+// d = d0 + y (dwidth - d0); dy/dmid and dy/dpower from y = x^p / mid^(p-1)
+// below the midpoint and y = 1 - (1-x)^p / (1-mid)^(p-1) above it.
+DMX_DEV void impedance_solimp_grad(const PairF& p, double r, double* g) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) g[i] = 0.0;
+  if (r >= 0.0) return;
+  const double x = -r * p.iwid[0], mid = p.si[3], pw = p.si[4], span = p.si[1] - p.si[0];
+  double dy;
+  const double y = imp_spline(x, mid, pw, p.ssc[0], p.ssc[1], &dy);
+  g[0] = 1.0 - y;
+  g[1] = y;
+  if (x >= 1.0) return;
+  g[2] = -span * dy * x * p.iwid[0];
+  if (x <= mid) {
+    g[3] = -span * (pw - 1.0) * y / mid;
+    g[4] = span * y * log(x / mid);
+  } else {
+    g[3] = -span * (pw - 1.0) * (1.0 - y) / (1.0 - mid);
+    g[4] = -span * (1.0 - y) * log((1.0 - x) / (1.0 - mid));
+  }
+}
+
 DMX_DEV double softplus(double z, double beta, double* dsp) {
   double bz = beta * z;
   if (bz > 30.0) {
@@ -637,7 +663,7 @@ struct FreePhys {
   // the box geom's half sizes (the contact vertices are l + gR (s * h)), then
   // the friction coefficient, the solref time constant and damping ratio, each
   // as one value shared by every contact pair (a common shift of all pairs),
-  // and the body's mass
+  // the body's mass, and the five solimp parameters (shared likewise)
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
                               Stat& st, double* hbar = nullptr) {
@@ -689,15 +715,15 @@ struct FreePhys {
       double dD = ddr / (pr.ahat * (1.0 - dimp) * (1.0 - dimp));
       double kk = dimp * pr.kscale;
       double dpt;  // d pterm / dr
-      double ptk;  // d pterm / d kscale
+      double ptd;  // d pterm / d(impedance) / kscale
       if (cfd) {
         double dsp;
         double sp = softplus(-rw.r[k], beta, &dsp);
         dpt = pr.kscale * ddr * sp - kk * dsp;
-        ptk = dimp * sp;
+        ptd = sp;
       } else {
         dpt = -(pr.kscale * ddr * rw.r[k] + kk);
-        ptk = -dimp * rw.r[k];
+        ptd = -rw.r[k];
       }
       // Per edge e (J_e = J_n + s_e J_t(e), force f_e = D (aref_e - J_e x)):
       // J_e_bar = f_e lam - arb_e (x + bcoef v) with arb_e = D J_e lam, and
@@ -742,10 +768,19 @@ struct FreePhys {
           mub += fd * la[a] - ad * (xa[a] + pr.bcoef * vt);
           bb -= (ae[2 * a] + ae[2 * a + 1]) * vn + mu * ad * vt;
         }
-        const double kb = An * ptk;
+        const double kb = An * dimp * ptd;
+        const double sb = pr.bcoef * bb + 2.0 * pr.kscale * kb;  // b and k go as 1/t_c, 1/t_c^2 (and dwidth)
         hb_[3] += mub;
-        hb_[4] -= (pr.bcoef * bb + 2.0 * pr.kscale * kb) / pr.solref[0];
+        hb_[4] -= sb / pr.solref[0];
         hb_[5] -= 2.0 * pr.kscale * kb / pr.solref[1];
+        // solimp: through d(r) (in D and the position term) and, for dwidth,
+        // through b and k as well
+        const double dbar = dsum / (pr.ahat * (1.0 - dimp) * (1.0 - dimp)) + An * pr.kscale * ptd;
+        double gs[5];
+        impedance_solimp_grad(pr, rw.r[k], gs);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) hb_[7 + i] += dbar * gs[i];
+        hb_[8] -= sb / pr.si[1];
       }
       double Jb[1 + NT][6];  // cotangents of J_n and the lane's tangent rows
 #pragma unroll

@@ -459,7 +459,8 @@ def rollout_vjp_otd_geom(tape, x_out_bar):
     return x0b, ub, hb
 
 
-PARAMS = ("half_x", "half_y", "half_z", "friction", "solref_timeconst", "solref_dampratio", "mass")
+PARAMS = ("half_x", "half_y", "half_z", "friction", "solref_timeconst", "solref_dampratio", "mass",
+          "solimp_d0", "solimp_dwidth", "solimp_width", "solimp_midpoint", "solimp_power")
 
 
 def _params(fn, tape, x_out_bar):
@@ -473,13 +474,13 @@ def _params(fn, tape, x_out_bar):
 
 
 def rollout_vjp_params(tape, x_out_bar):
-    """x0_bar, u_bar and the model-parameter gradient [W, 7] (columns PARAMS)
+    """x0_bar, u_bar and the model-parameter gradient [W, 12] (columns PARAMS)
     of sum(x_out_bar * x_out) through the recorded discretization."""
     return _params(_lib.dmx_rollout_vjp_params, tape, x_out_bar)
 
 
 def rollout_vjp_otd_params(tape, x_out_bar):
-    """Optimize-then-discretize x0_bar, u_bar and model-parameter gradient [W, 7]."""
+    """Optimize-then-discretize x0_bar, u_bar and model-parameter gradient [W, 12]."""
     return _params(_lib.dmx_rollout_vjp_otd_params, tape, x_out_bar)
 
 

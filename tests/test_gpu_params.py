@@ -1,7 +1,7 @@
 """Model-parameter gradients beyond the side length (App. E.2 identifies mass,
 solref, solimp and friction alongside it): the gradient of a final-state loss
 with respect to the contact pairs' friction coefficient and solref (time
-constant, damping ratio) and the body's mass, with the box half sizes, through the recorded
+constant, damping ratio), solimp and the body's mass, with the box half sizes, through the recorded
 discretization (dmx_rollout_vjp_params) and by the parameter adjoint of the
 continuous adjoint equations (dmx_rollout_vjp_otd_params).
 
@@ -14,8 +14,8 @@ Cases: a box and a corner cube (eight sphere-plane pairs) sliding and tipping
 on the plane on persistent contact, the corner cube under controls (without
 controls the accelerations do not depend on the mass: its gradient is 0).  The
 continuous form is checked against the discrete adjoint on the same tape at
-rtol 1e-10 (1e-3 relative) and against central differences of the oracle's
-forward at rtol 1e-12 where those have converged."""
+rtol 1e-10 (1e-3 relative; solimp d0 excepted) and against central differences
+of the oracle's forward at rtol 1e-12 where those have converged."""
 import copy
 
 import numpy as np
@@ -43,7 +43,8 @@ def _t(a):
 
 def _shifted(desc, j, delta):
     """desc with parameter column j (3 friction, 4 solref t_c, 5 damping
-    ratio: in every contact pair; 6 the body's mass) shifted by delta."""
+    ratio, 7-11 solimp: in every contact pair; 6 the body's mass) shifted by
+    delta."""
     d = copy.deepcopy(desc)
     if j == 6:
         d["bodies"][0]["inertial"]["mass"] += delta
@@ -51,8 +52,10 @@ def _shifted(desc, j, delta):
     for p in d["pairs"]:
         if j == 3:
             p["mu"] += delta
-        else:
+        elif j < 6:
             p["solref"][j - 4] += delta
+        else:
+            p["solimp"][j - 7] += delta
     return d
 
 
@@ -60,10 +63,16 @@ def _base_value(desc, j):
     if j == 6:
         return desc["bodies"][0]["inertial"]["mass"]
     p = desc["pairs"][0]
-    return p["mu"] if j == 3 else p["solref"][j - 4]
+    return p["mu"] if j == 3 else p["solref"][j - 4] if j < 6 else p["solimp"][j - 7]
 
 
-COLS = (3, 4, 5, 6)
+COLS = (3, 4, 5, 6, 7, 8, 9, 10, 11)
+
+
+def _step(desc, j, rel):
+    """Difference step for column j: relative to the value, absolute (rel)
+    for the solimp d0 of the cube-toss setting, which is 0."""
+    return rel * max(abs(_base_value(desc, j)), 1.0 if j == 7 else 0.0)
 
 
 def _sliding_states(n, seed, height):
@@ -79,6 +88,8 @@ def _sliding_states(n, seed, height):
     return x0
 
 
+# the cube-toss contact setting (solimp (0, 0.95, 0.001, 0.5, 2): resting
+# contacts sit inside the impedance spline, on both sides of its midpoint)
 CASES = {
     "box": (lambda: W.model_box(tc=0.005, mu=0.5), 0.0995, False),
     "corner_cube": (lambda: W.model_cube_corners(tc=0.005, mu=0.5, ctrl=True), 0.1095, True),
@@ -115,7 +126,7 @@ def test_contact_parameter_gradient_matches_oracle_differences(D, oracle, case):
     def central(rel):
         fd = np.zeros((x0.shape[0], len(COLS)))
         for c, j in enumerate(COLS):
-            eps = rel * abs(_base_value(desc, j))
+            eps = _step(desc, j, rel)
             vals = []
             for s in (+1, -1):
                 om = oracle.Model(_shifted(desc, j, s * eps))
@@ -129,11 +140,12 @@ def test_contact_parameter_gradient_matches_oracle_differences(D, oracle, case):
     if not ctrl:  # mass: 0 without applied forces, the differences at rounding level
         assert not g[:, 3].any()
         assert np.abs(fd6[:, 3]).max() <= 1e-8, fd6[:, 3]
-        g, fd6, fd7 = g[:, :3], fd6[:, :3], fd7[:, :3]
+        keep = [c for c in range(len(COLS)) if c != 3]
+        g, fd6, fd7 = g[:, keep], fd6[:, keep], fd7[:, keep]
     scale = np.maximum(np.abs(fd7).max(axis=0, keepdims=True), 1e-12)  # per parameter: units differ
     smooth = np.abs(fd6 - fd7) / scale <= 2e-5
     err = np.abs(g - fd7) / scale
-    print(f"{case}: friction/solref/mass gradient vs oracle differences: max rel err {err[smooth].max():.2e} over "
+    print(f"{case}: friction/solref/mass/solimp gradient vs oracle differences: max rel err {err[smooth].max():.2e} over "
           f"{int(smooth.sum())}/{smooth.size} converged entries (all entries {err.max():.2e})\n{g}\n{fd7}")
     assert smooth.mean() >= 0.8
     assert err[smooth].max() <= 1e-4
@@ -160,17 +172,17 @@ def test_otd_contact_parameter_gradient_is_the_continuous_derivative(D, oracle, 
         _, _, h_otd = D.rollout_vjp_otd_geom(r["tape"], _t(xb))
         np.testing.assert_array_equal(p_otd[:, :3], h_otd.cpu().numpy())
         assert not p_otd[:, 6].any()  # no applied forces
-    cols = COLS if ctrl else COLS[:3]
-    g = p_otd[:, 3:3 + len(cols)]
+    cols = COLS if ctrl else tuple(j for j in COLS if j != 6)
+    g = p_otd[:, list(cols)]
     # the discrete adjoint on the same tape (its parameter gradient is pinned
     # to the oracle above): at rtol 1e-10 both are the continuous derivative
     _, _, p_dto = D.rollout_vjp_params(r["tape"], _t(xb))
-    g_dto = p_dto.cpu().numpy()[:, 3:3 + len(cols)]
+    g_dto = p_dto.cpu().numpy()[:, list(cols)]
 
     def central(rel):
         fd = np.zeros((x0.shape[0], len(cols)))
         for c, j in enumerate(cols):
-            eps = rel * abs(_base_value(desc, j))
+            eps = _step(desc, j, rel)
             vals = []
             for s in (+1, -1):
                 om = oracle.Model(_shifted(desc, j, s * eps))
@@ -181,7 +193,12 @@ def test_otd_contact_parameter_gradient_is_the_continuous_derivative(D, oracle, 
 
     fd5, fd6 = central(1e-5), central(1e-6)
     scale = np.maximum(np.abs(g_dto).max(axis=0, keepdims=True), 1e-12)
-    e_dto = np.abs(g - g_dto) / scale
+    # solimp d0 at 0 acts through the force step at each contact activation,
+    # which the frozen steps of the discrete map resolve differently (that map's
+    # d0 derivative, pinned above, departs from the converged differences of
+    # the tight forward by up to 0.7%): d0 is held to the differences only
+    not_d0 = [c for c, j in enumerate(cols) if j != 7]
+    e_dto = np.abs(g - g_dto)[:, not_d0] / scale[:, not_d0]
     # differences of the adaptive forward converge only where no contact or
     # friction state switches within the perturbation
     smooth = np.abs(fd5 - fd6) / scale <= 1e-3
@@ -193,5 +210,5 @@ def test_otd_contact_parameter_gradient_is_the_continuous_derivative(D, oracle, 
     # the corner cube under controls: the adaptive forward's differences
     # converge for one world of four (3 of 4 change their contact sequence
     # within a relative shift of 1e-5), so the discrete adjoint is the bar there
-    assert smooth.sum() >= 4
+    assert smooth.sum() >= len(cols)
     assert e_fd[smooth].max() <= 5e-3
