@@ -335,7 +335,9 @@ dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double*
  * t_c and the damping ratio enter a_ref's stiffness and damping; solimp
  * shapes the impedance d(r) in R and a_ref (Sec. 2.1; dwidth also scales
  * a_ref's stiffness and damping); the mass moves the body's inertia with it
- * (a uniform solid).  Single free bodies; DMX_ERR_UNSUPPORTED otherwise. */
+ * (a uniform solid).  Single free bodies and trees; for a tree the half
+ * sizes are 0 and the mass entry is NaN (a tree has one mass per body).
+ * DMX_ERR_UNSUPPORTED for stacks. */
 dmx_status dmx_rollout_vjp_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                   double* param_bar, void* stream);
 
@@ -361,8 +363,7 @@ dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tape, const double* x_out_bar, dou
                                     double* geom_size_bar, void* stream);
 /* dmx_rollout_vjp_otd plus the twelve model-parameter gradients of
  * dmx_rollout_vjp_params (same layout and meaning), by the parameter adjoint
- * of eq. adjoint-equations.  Single free bodies; DMX_ERR_UNSUPPORTED
- * otherwise. */
+ * of eq. adjoint-equations.  Models as for dmx_rollout_vjp_params. */
 dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                       double* param_bar, void* stream);
 

@@ -85,6 +85,18 @@ void spline_scales(dmx::PairF& pr) {
   pr.iwid[1] = 1.0 / pr.cf[2];
 }
 
+// solref and the impedance splines within their domain: t_c and the damping
+// ratio positive; impedances in [0, 1) (dwidth in (0, 1): it divides the
+// stiffness); widths positive; midpoints in [0, 1]; powers at least 1 (the
+// spline and its slope stay finite at 0)
+static bool contact_params_ok(double tc, double dr, const dmx::PairF& pr) {
+  auto spline_ok = [](const double* s) {
+    return s[0] >= 0.0 && s[0] < 1.0 && s[1] >= 0.0 && s[1] < 1.0 && s[2] > 0.0 && s[3] >= 0.0 && s[3] <= 1.0 &&
+           s[4] >= 1.0;
+  };
+  return tc > 0.0 && dr > 0.0 && pr.si[1] > 0.0 && spline_ok(pr.si) && spline_ok(pr.cf);
+}
+
 void make_tangents(const double* n, double* t1, double* t2) {
   double a[3] = {0, 0, 0};
   if (std::fabs(n[0]) < 0.5) a[0] = 1.0; else a[1] = 1.0;
@@ -241,8 +253,7 @@ static bool make_stack_model(const dmx_model_desc* d, dmx::StackModel* st, std::
   for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[i]; pr.cf[i] = d->pair_cfd[i]; }
   spline_scales(pr);
   const double tc = d->pair_solref[0], dr = d->pair_solref[1], dw = pr.si[1];
-  if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0))
-    return no("solref/solimp/cfd out of range");
+  if (!contact_params_ok(tc, dr, pr)) return no("solref/solimp/cfd out of range");
   for (int i = 0; i < 5; ++i) { s.si[i] = pr.si[i]; s.cf[i] = pr.cf[i]; }
   for (int i = 0; i < 4; ++i) s.ssc[i] = pr.ssc[i];
   s.iwid[0] = pr.iwid[0];
@@ -365,7 +376,7 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
     spline_scales(pr);
     const double dw = pr.si[1];
-    if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
+    if (!contact_params_ok(tc, dr, pr)) {
       delete m;
       return fail(DMX_ERR_INVALID_ARG, "solref/solimp/cfd out of range");
     }
@@ -597,7 +608,7 @@ static dmx_status create_tree_model(const dmx_model_desc* d, dmx_model** out) {
     for (int i = 0; i < 5; ++i) { pr.si[i] = d->pair_solimp[5 * p + i]; pr.cf[i] = d->pair_cfd[5 * p + i]; }
     spline_scales(pr);
     const double dw = pr.si[1];
-    if (!(tc > 0.0) || !(dw > 0.0 && dw < 1.0) || !(pr.si[2] > 0.0) || !(pr.cf[2] > 0.0)) {
+    if (!contact_params_ok(tc, dr, pr)) {
       delete m;
       return fail(DMX_ERR_INVALID_ARG, "solref/solimp/cfd out of range");
     }
@@ -1268,8 +1279,7 @@ dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tp, const double* x_out_bar, doubl
 dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
                                       double* param_bar, void* stream) {
   if (!param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  if (tp && (tp->stack || tp->model->kind != 0))
-    return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take single free bodies");
+  if (tp && tp->stack) return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take free-body and tree models");
   return otd_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
 }
 
@@ -1311,8 +1321,7 @@ dmx_status dmx_rollout_vjp_geom(dmx_tape* tp, const double* x_out_bar, double* x
 dmx_status dmx_rollout_vjp_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
                                   double* param_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar || !param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  if (tp->stack || tp->model->kind != 0)
-    return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take single free bodies");
+  if (tp->stack) return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take free-body and tree models");
   return params_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
 }
 

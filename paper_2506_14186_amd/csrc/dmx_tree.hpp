@@ -582,7 +582,10 @@ struct TreePhys {
   DMX_DEV static void acc_vjp(const Model& m, const double* y, const double* tau, const double* xs_in,
                               const double* abar, bool cfd, double beta, int maxit, double* ybar, double* taubar,
                               Stat& st, double* hbar = nullptr) {
-    (void)hbar;  // no box geoms in tree models
+    // hbar (optional, [kParams]): += the contact parameters' cotangents
+    // (friction, solref, solimp as one value shared by every pair, as for
+    // single free bodies); no box geom (half sizes stay 0), and the mass entry
+    // is NaN: a tree has one mass per body
     TreeWs<NV, NB>& w = ws();
     const double* q = y;
     const double* v = y + NQ;
@@ -646,6 +649,9 @@ struct TreePhys {
     for (int j = 0; j < NV; ++j)
 #pragma unroll
       for (int i = 0; i < 3; ++i) { cab[j][i] = 0.0; cob[j][i] = 0.0; }
+    double hb_[kParams];
+#pragma unroll
+    for (int i = 0; i < kParams; ++i) hb_[i] = 0.0;
 #pragma unroll
     for (int k = 0; k < CPL; ++k) {
       if (!rw.on[k] || act[k] == 0u) continue;
@@ -655,9 +661,16 @@ struct TreePhys {
       const double dimp = impedance(pr, rw.r[k], &ddr);
       const double dD = ddr / (pr.ahat * (1.0 - dimp) * (1.0 - dimp));
       const double kk = dimp * pr.kscale;
-      double dpt;
-      if (cfd) { double dsp; const double sp = softplus(-rw.r[k], beta, &dsp); dpt = pr.kscale * ddr * sp - kk * dsp; }
-      else dpt = -(pr.kscale * ddr * rw.r[k] + kk);
+      double dpt, ptd;  // d pterm / dr, d pterm / d(impedance) / kscale
+      if (cfd) {
+        double dsp;
+        const double sp = softplus(-rw.r[k], beta, &dsp);
+        dpt = pr.kscale * ddr * sp - kk * dsp;
+        ptd = sp;
+      } else {
+        dpt = -(pr.kscale * ddr * rw.r[k] + kk);
+        ptd = -rw.r[k];
+      }
       // per-edge reverse summed over the lane's edges as combinations of its
       // frame rows (as in the free-body reverse; inactive edges weigh 0)
       constexpr int NE = 2 * NTG;
@@ -667,6 +680,7 @@ struct TreePhys {
 #pragma unroll
       for (int a = 0; a < NTG; ++a) { la[a] = dotn<NV>(rw.Jt[k][a], lam); xa[a] = dotn<NV>(rw.Jt[k][a], xs); }
       double fe[NE], ae[NE];
+      double dsum = 0.0;  // sum of the edges' D cotangents
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
         const bool on = (act[k] >> e) & 1u;
@@ -678,9 +692,35 @@ struct TreePhys {
         ae[e] = De * sl;
         const double Dbar = on ? sl * gap : 0.0;
         rbar += ae[e] * dpt + Dbar * dD;
+        dsum += Dbar;
       }
       const double Fn = NTG == 2 ? (fe[0] + fe[1]) + (fe[NE - 2] + fe[NE - 1]) : fe[0] + fe[1];
       const double An = NTG == 2 ? (ae[0] + ae[1]) + (ae[NE - 2] + ae[NE - 1]) : ae[0] + ae[1];
+      if (hbar) {
+        // the contact parameters, as in the free-body reverse: friction in the
+        // edges J_n +- mu J_t and in Ahat = (1 + mu^2) w, solref in a_ref's b
+        // and k, solimp in d(r) (and dwidth in b and k)
+        const double vn = dotn<NV>(Jn, v);
+        double mub = dsum * (-2.0 * mu * D / (1.0 + mu * mu)), bb = 0.0;
+#pragma unroll
+        for (int a = 0; a < NTG; ++a) {
+          const double vt = dotn<NV>(rw.Jt[k][a], v);
+          const double fd = fe[2 * a] - fe[2 * a + 1], ad = ae[2 * a] - ae[2 * a + 1];
+          mub += fd * la[a] - ad * (xa[a] + pr.bcoef * vt);
+          bb -= (ae[2 * a] + ae[2 * a + 1]) * vn + mu * ad * vt;
+        }
+        const double kb = An * dimp * ptd;
+        const double sb = pr.bcoef * bb + 2.0 * pr.kscale * kb;
+        hb_[3] += mub;
+        hb_[4] -= sb / pr.solref[0];
+        hb_[5] -= 2.0 * pr.kscale * kb / pr.solref[1];
+        const double dbar = dsum / (pr.ahat * (1.0 - dimp) * (1.0 - dimp)) + An * pr.kscale * ptd;
+        double gs[5];
+        impedance_solimp_grad(pr, rw.r[k], gs);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) hb_[7 + i] += dbar * gs[i];
+        hb_[8] -= sb / pr.si[1];
+      }
       double Fa[NTG], Aa[NTG];
 #pragma unroll
       for (int a = 0; a < NTG; ++a) { Fa[a] = mu * (fe[2 * a] - fe[2 * a + 1]); Aa[a] = mu * (ae[2 * a] - ae[2 * a + 1]); }
@@ -745,6 +785,12 @@ struct TreePhys {
 #pragma unroll
           for (int i = 0; i < 9; ++i) cRb[bb][i] += Rb2.a[i];
         }
+    }
+    if (hbar) {
+      team_sum_arr<L, kParams>(hb_);
+#pragma unroll
+      for (int i = 0; i < kParams; ++i) hbar[i] += hb_[i];
+      hbar[6] = __longlong_as_double(0x7ff8000000000000ll);
     }
     // team sums; the contact term enters Psi with a minus sign, Ybar = -grad Psi
     team_sum_arr<L, NV>(vb);

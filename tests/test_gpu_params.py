@@ -261,3 +261,65 @@ def test_side_length_and_friction_identification(D):
         print(f"iteration {it}: half size {pp[0]:.5f} m, friction {pp[1]:.4f}, loss {loss:.3e}")
     err = np.abs(p - true) / true
     assert err.max() < 1e-2, p
+
+
+def test_contact_parameters_outside_their_domain_are_refused(D):
+    """Damping ratio 0, a spline power below 1, a midpoint above 1 or an
+    impedance of 1 have no finite impedance, stiffness or parameter
+    derivatives: model creation refuses them (the free-body and the stack
+    paths alike)."""
+    bad = [("solref", 1, 0.0), ("solimp", 4, 0.5), ("solimp", 3, 1.5), ("solimp", 0, 1.0), ("cfd", 2, 0.0)]
+    for make in (lambda: W.model_box(), lambda: W.model_stack(2)):
+        D.Model(make())  # the unmodified model is accepted
+        for key, i, v in bad:
+            d = make()
+            d["pairs"][0][key][i] = v
+            with pytest.raises(D.DmxError):
+                D.Model(d)
+
+
+def test_tree_contact_parameter_gradient_matches_oracle_differences(D, oracle):
+    """The legged chain (hinge/slide tree, capsule feet on the plane) under
+    hinge torques: friction, solref and solimp gradients against the oracle's
+    frozen-step differences, as for single bodies; the half-size entries are
+    0 (no box geom) and the mass entry NaN (a tree has one mass per body)."""
+    n_int, dt = 30, 0.01
+    cfg = W.chain_walk(seed=3, n_worlds=6, n_intervals=n_int, interval_dt=dt)
+    desc, x0, u = cfg["model"], cfg["x0"], cfg["u"]
+    model = D.Model(desc)
+    xb = np.zeros_like(x0)
+    xb[:, 0], xb[:, 1], xb[:, 2] = 1.0, 2.0, 0.5
+    r = D.rollout(model, _t(x0), _t(u), n_int, dt, opts=D.default_opts(tape_steps=8192), tape=True)
+    assert int(r["status"].abs().sum()) == 0
+    gx, gu, gp = D.rollout_vjp_params(r["tape"], _t(xb))
+    gx_plain, gu_plain = D.rollout_vjp(r["tape"], _t(xb))
+    np.testing.assert_array_equal(gx.cpu().numpy(), gx_plain.cpu().numpy())
+    np.testing.assert_array_equal(gu.cpu().numpy(), gu_plain.cpu().numpy())
+    gp = gp.cpu().numpy()
+    assert not gp[:, :3].any() and np.isnan(gp[:, 6]).all()
+    cols = (3, 4, 5, 7, 8, 9, 10, 11)
+    forced, n = tape_steps(r["tape"])
+
+    def central(rel):
+        fd = np.zeros((x0.shape[0], len(cols)))
+        for c, j in enumerate(cols):
+            eps = _step(desc, j, rel)
+            vals = []
+            for s in (+1, -1):
+                om = oracle.Model(_shifted(desc, j, s * eps))
+                res = om.grad_forced_batch(x0, u, n_int, dt, xb, forced, n, n_threads=6)
+                vals.append(np.sum(xb * res["x"], axis=1))
+            fd[:, c] = (vals[0] - vals[1]) / (2 * eps)
+        return fd
+
+    fd6, fd7 = central(1e-6), central(1e-7)
+    g = gp[:, list(cols)]
+    scale = np.maximum(np.abs(fd7).max(axis=0, keepdims=True), 1e-12)
+    assert (np.abs(fd7).max(axis=0) > 0).all()  # every parameter acts on the loss
+    smooth = np.abs(fd6 - fd7) / scale <= 2e-5
+    err = np.abs(g - fd7) / scale
+    print(f"chain: friction/solref/solimp gradient vs oracle differences: max rel err {err[smooth].max():.2e} over "
+          f"{int(smooth.sum())}/{smooth.size} converged entries (all entries {err.max():.2e})\n{g}\n{fd7}")
+    assert smooth.mean() >= 0.8
+    assert err[smooth].max() <= 1e-4
+    assert err.max() <= 2e-3
