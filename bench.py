@@ -551,8 +551,9 @@ def chain_leg(D, W, args, dev):
 
 
 def otd_leg(D, W, dev, reps=3):
-    """Optimize-then-discretize adjoint (dmx_rollout_vjp_otd) beside the
-    discrete adjoint on the same tape: the cube-toss batch (4096 corner-
+    """Optimize-then-discretize adjoint (dmx_rollout_vjp_otd) and the discrete
+    adjoint with the model-parameter gradient (dmx_rollout_vjp_params) beside
+    the discrete adjoint on the same tape: the cube-toss batch (4096 corner-
     sphere cubes, 0.5 s, 16-lane teams), loss = the summed final positions;
     and the straight-through CFD gradient of a sphere skimming the plane
     (never touching), where the discrete adjoint unrolls the forward's few
@@ -568,21 +569,28 @@ def otd_leg(D, W, dev, reps=3):
     r = D.rollout(model, x0, None, 1, 0.5, opts=opts, tape=True, counters=True)
     D.rollout_vjp(r["tape"], xbar)
     D.rollout_vjp_otd(r["tape"], xbar)
+    D.rollout_vjp_params(r["tape"], xbar)
     torch.cuda.synchronize()
-    dto_ms, otd_ms = [], []
+    dto_ms, otd_ms, par_ms = [], [], []
     for _ in range(reps):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         g_dto, _ = D.rollout_vjp(r["tape"], xbar)
         ev[1].record(stream)
         g_otd, _ = D.rollout_vjp_otd(r["tape"], xbar)
         ev[2].record(stream)
+        g_par, _, _ = D.rollout_vjp_params(r["tape"], xbar)
+        ev[3].record(stream)
         torch.cuda.synchronize()
         dto_ms.append(ev[0].elapsed_time(ev[1]))
         otd_ms.append(ev[1].elapsed_time(ev[2]))
+        par_ms.append(ev[2].elapsed_time(ev[3]))
+    if not torch.equal(g_par, g_dto):
+        raise RuntimeError("the parameter-gradient sweep changed the state gradient")
     diff = (g_otd - g_dto).abs().max(dim=1).values / g_dto.abs().max(dim=1).values
     out = {"workload": "cube_toss: 4096 corner-sphere cubes, 0.5 s, rtol 1e-6, adjoint of the summed final positions",
            "dto_adj_ms": round(float(np.median(dto_ms)), 3), "otd_adj_ms": round(float(np.median(otd_ms)), 3),
+           "dto_adj_with_params_ms": round(float(np.median(par_ms)), 3),
            "otd_vs_dto_rel_diff_median": float(diff.median()), "forward_accepted_steps_mean": float(r["n_acc"].double().mean())}
     # skimming sphere with CFD (5 mm above the plane, inside the CFD width)
     sph = D.Model(W.model_sphere())
