@@ -187,10 +187,17 @@ typedef struct {
 void dmx_default_opts(dmx_solver_opts* opts);
 
 /* Compile a model (inertia, inverse weights, pair tables) and upload it to
- * the current device.  Returns DMX_ERR_UNSUPPORTED for model shapes the
- * compiled kernels do not cover. */
+ * the current device: the simulator model of Sec. 2.1 (mass matrix, contact
+ * pairs with their friction, solref and solimp, the regularizer's A-hat) with
+ * the collision pairs of Sec. 2.1 and App. C.1.  The description is read
+ * during the call only; the returned model is owned by the caller
+ * (dmx_model_destroy).  Returns DMX_ERR_INVALID_ARG for parameters outside
+ * their domain and DMX_ERR_UNSUPPORTED for model shapes the compiled kernels
+ * do not cover. */
 dmx_status dmx_model_create(const dmx_model_desc* desc, dmx_model** out);
-/* nq, nv, nu, max_contacts */
+/* Sizes of the model: nq, nv of the ODE state x = (q, v) (App. C.2), the
+ * control count nu and the most contacts one state can have (host outputs,
+ * each may be NULL). */
 dmx_status dmx_model_info(const dmx_model* model, int32_t* nq, int32_t* nv, int32_t* nu, int32_t* max_contacts);
 void dmx_model_destroy(dmx_model* model);
 
@@ -266,14 +273,17 @@ dmx_status dmx_rollout_batch_grad(const dmx_batch* batch, const dmx_solver_opts*
                                   int32_t* n_accepted, int32_t* n_rejected, double* x0_bar, double* u_bar,
                                   dmx_tape** tape, void* stream);
 
-/* Per-world layout of a tape's records (host arrays [n_worlds]): world w's
+/* The tape is the record of accepted steps that the discretize-then-optimize
+ * gradient reverses (App. C.2), owned by the caller (dmx_tape_destroy).
+ * Per-world layout of a tape's records (host arrays [n_worlds]): world w's
  * records start at records + t_off[w] and are rec[w] doubles long (t_n, h_n,
  * interval, y_n, then the stage accelerations a_1..a_6 unless the tape holds
  * checkpoints only); dmx_tape_info's steps_per_world is each world's
  * capacity. */
 dmx_status dmx_tape_layout(const dmx_tape* tape, int64_t* t_off, int32_t* rec);
 
-/* Autotuner: times the forward rollout of this batch (device x0, u) with
+/* Autotuner for the batched rollouts of App. D ("Parallelizing DiffMJX
+ * simulations"): times the forward rollout of this batch (device x0, u) with
  * every team size (lanes per world) compiled for the model, on the stream,
  * and makes the fastest (a wider team must win by 2%) the model's default
  * (used when lanes_per_world is 0).
@@ -405,7 +415,8 @@ dmx_status dmx_rollout_noalloc(const dmx_model* model, int32_t n_worlds, int32_t
                                const dmx_solver_opts* opts, const double* x0, const double* u, double* x_out,
                                int32_t* world_status, int32_t* n_accepted, int32_t* n_rejected, void* stream);
 
-/* Sizes of a tape: per-world capacity and record length in doubles. */
+/* Sizes of a tape (App. C.2's record of accepted steps): per-world capacity
+ * and record length in doubles (host outputs). */
 dmx_status dmx_tape_info(const dmx_tape* tape, int64_t* steps_per_world, int32_t* record_doubles);
 /* Device pointer to the tape records [W][steps_per_world][record] with records
  * (t_n, h_n, interval, y_n[nx], then a_1..a_6[nv] unless the tape holds
