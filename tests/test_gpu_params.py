@@ -323,3 +323,53 @@ def test_tree_contact_parameter_gradient_matches_oracle_differences(D, oracle):
     assert smooth.mean() >= 0.8
     assert err[smooth].max() <= 1e-4
     assert err.max() <= 2e-3
+
+
+def test_tree_otd_contact_parameter_gradient(D, oracle):
+    """The legged chain's contact-parameter gradient by the parameter adjoint
+    of the continuous adjoint equations (rtol 1e-10) against central
+    differences of the oracle's forward at rtol 1e-12 where those converge
+    (5e-3 relative to each parameter's largest gradient, as for single
+    bodies), and beside the discrete adjoint on the same tape (whose solimp
+    derivatives depart from the continuous ones by up to ~2e-3 at contact
+    activations; 5e-3); the mass entry is NaN, the half sizes 0."""
+    n_int, dt = 30, 0.01
+    cfg = W.chain_walk(seed=5, n_worlds=4, n_intervals=n_int, interval_dt=dt)
+    desc, x0, u = cfg["model"], cfg["x0"], cfg["u"]
+    model = D.Model(desc)
+    xb = np.zeros_like(x0)
+    xb[:, 0], xb[:, 1] = 1.0, 2.0
+    opts = D.default_opts(rtol=1e-10, atol=1e-10, tape_steps=65536, tape_stages=1)
+    r = D.rollout(model, _t(x0), _t(u), n_int, dt, opts=opts, tape=True)
+    assert int(r["status"].abs().sum()) == 0
+    _, _, p_otd = D.rollout_vjp_otd_params(r["tape"], _t(xb))
+    _, _, p_dto = D.rollout_vjp_params(r["tape"], _t(xb))
+    p_otd, p_dto = p_otd.cpu().numpy(), p_dto.cpu().numpy()
+    assert not p_otd[:, :3].any() and np.isnan(p_otd[:, 6]).all()
+    cols = [3, 4, 5, 7, 8, 9, 10, 11]
+
+    def central(rel):
+        fd = np.zeros((x0.shape[0], len(cols)))
+        for c, j in enumerate(cols):
+            eps = _step(desc, j, rel)
+            vals = []
+            for sg in (+1, -1):
+                om = oracle.Model(_shifted(desc, j, sg * eps))
+                res = om.rollout_batch(x0, u, n_int, dt, n_threads=4, rtol=1e-12, atol=1e-12)
+                vals.append(np.sum(xb * res["x"], axis=1))
+            fd[:, c] = (vals[0] - vals[1]) / (2 * eps)
+        return fd
+
+    fd5, fd6 = central(1e-5), central(1e-6)
+    g = p_otd[:, cols]
+    scale = np.maximum(np.abs(p_dto[:, cols]).max(axis=0, keepdims=True), 1e-12)
+    smooth = np.abs(fd5 - fd6) / scale <= 1e-3
+    e_fd = np.abs(g - fd6) / scale
+    not_d0 = [c for c, j in enumerate(cols) if j != 7]
+    e_dto = (np.abs(g - p_dto[:, cols]) / scale)[:, not_d0]
+    print(f"chain: parameter gradient (continuous adjoint) vs differences at rtol 1e-12: "
+          f"{e_fd[smooth].max() if smooth.any() else float('nan'):.2e} over {int(smooth.sum())}/{smooth.size} "
+          f"converged entries; vs the discrete adjoint: {e_dto.max():.2e}\n{g}\n{fd6}")
+    assert smooth.sum() >= len(cols)
+    assert e_fd[smooth].max() <= 5e-3
+    assert e_dto.max() <= 5e-3
