@@ -345,9 +345,11 @@ dmx_status dmx_rollout_vjp_geom(dmx_tape* tape, const double* x_out_bar, double*
  * t_c and the damping ratio enter a_ref's stiffness and damping; solimp
  * shapes the impedance d(r) in R and a_ref (Sec. 2.1; dwidth also scales
  * a_ref's stiffness and damping); the mass moves the body's inertia with it
- * (a uniform solid).  Single free bodies and trees; for a tree the half
- * sizes are 0 and the mass entry is NaN (a tree has one mass per body).
- * DMX_ERR_UNSUPPORTED for stacks. */
+ * (a uniform solid).  Free bodies, trees and stack batches (tapes of
+ * dmx_rollout_batch, param_bar [n_worlds][12]): for a tree the half sizes are
+ * 0 and the mass entry is NaN (a tree has one mass per body); for a stack
+ * the half sizes are NaN (not differentiated there) and the mass is the one
+ * all its cubes share. */
 dmx_status dmx_rollout_vjp_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                   double* param_bar, void* stream);
 
@@ -373,7 +375,8 @@ dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tape, const double* x_out_bar, dou
                                     double* geom_size_bar, void* stream);
 /* dmx_rollout_vjp_otd plus the twelve model-parameter gradients of
  * dmx_rollout_vjp_params (same layout and meaning), by the parameter adjoint
- * of eq. adjoint-equations.  Models as for dmx_rollout_vjp_params. */
+ * of eq. adjoint-equations.  Free bodies and trees (as for
+ * dmx_rollout_vjp_params); DMX_ERR_UNSUPPORTED for stack batches. */
 dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tape, const double* x_out_bar, double* x0_bar, double* u_bar,
                                       double* param_bar, void* stream);
 

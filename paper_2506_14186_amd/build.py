@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libdmx.so")
 # translation units, compiled in parallel and linked into one library: the
 # host side (C ABI, dispatch, tapes, server) and one unit per kernel family
 SOURCES = [os.path.join(HERE, "csrc", n) for n in ("dmx_lib.hip", "kern_free_small.hip", "kern_free.hip",
-                                                    "kern_free_wide.hip", "kern_tree.hip", "kern_stack.hip")]
+                                                    "kern_free_wide.hip", "kern_tree.hip", "kern_stack.hip",
+                                                    "kern_stack_params.hip")]
 OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1232,22 +1232,29 @@ dmx_status dmx_autotune(dmx_model* m, int32_t W, int32_t n_int, double dt, const
   return DMX_OK;
 }
 
+// reverse sweep of a stack batch's tape (with the model parameters'
+// cotangents into param_bar when given)
+static dmx_status stack_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
+                            double* param_bar, void* stream) {
+  bool any_ctrl = false;
+  for (const dmx_model* m : tp->models) any_ctrl = any_ctrl || m->nu > 0;
+  if (any_ctrl && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
+  dmx::StackArgs a = tp->sa;
+  a.u = tp->u;
+  a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
+  a.adj_counters = (long long*)tp->adj_counters;
+  a.counters = nullptr; a.steplog = nullptr; a.log_n = nullptr; a.forced = nullptr;
+  a.queue = tp->use_queue ? tp->sa.queue + 1 : nullptr;
+  a.pbar = param_bar;
+  if (param_bar) dmx_host::stack_adj_params(a, (hipStream_t)stream, tp->plain);
+  else dmx_host::stack_adj(a, (hipStream_t)stream, tp->plain);
+  HIP_TRY(hipGetLastError());
+  return DMX_OK;
+}
+
 dmx_status dmx_rollout_vjp(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  if (tp->stack) {
-    bool any_ctrl = false;
-    for (const dmx_model* m : tp->models) any_ctrl = any_ctrl || m->nu > 0;
-    if (any_ctrl && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
-    dmx::StackArgs a = tp->sa;
-    a.u = tp->u;
-    a.xbar = x_out_bar; a.x0bar = x0_bar; a.ubar = u_bar;
-    a.adj_counters = (long long*)tp->adj_counters;
-    a.counters = nullptr; a.steplog = nullptr; a.log_n = nullptr; a.forced = nullptr;
-    a.queue = tp->use_queue ? tp->sa.queue + 1 : nullptr;
-    dmx_host::stack_adj(a, (hipStream_t)stream, tp->plain);
-    HIP_TRY(hipGetLastError());
-    return DMX_OK;
-  }
+  if (tp->stack) return stack_vjp(tp, x_out_bar, x0_bar, u_bar, nullptr, stream);
   if (tp->nu > 0 && !u_bar) return fail(DMX_ERR_INVALID_ARG, "u_bar required");
   dmx::AdjArgs a{};
   a.W = tp->W; a.n_int = tp->n_int; a.nu = tp->nu; a.tape = tp->records; a.cap = tp->cap; a.rec = tp->rec;
@@ -1279,7 +1286,8 @@ dmx_status dmx_rollout_vjp_otd_geom(dmx_tape* tp, const double* x_out_bar, doubl
 dmx_status dmx_rollout_vjp_otd_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
                                       double* param_bar, void* stream) {
   if (!param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  if (tp && tp->stack) return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take free-body and tree models");
+  if (tp && tp->stack)
+    return fail(DMX_ERR_UNSUPPORTED, "the optimize-then-discretize adjoint takes free-body and tree models");
   return otd_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
 }
 
@@ -1321,7 +1329,7 @@ dmx_status dmx_rollout_vjp_geom(dmx_tape* tp, const double* x_out_bar, double* x
 dmx_status dmx_rollout_vjp_params(dmx_tape* tp, const double* x_out_bar, double* x0_bar, double* u_bar,
                                   double* param_bar, void* stream) {
   if (!tp || !x_out_bar || !x0_bar || !param_bar) return fail(DMX_ERR_INVALID_ARG, "null argument");
-  if (tp->stack) return fail(DMX_ERR_UNSUPPORTED, "model-parameter gradients take free-body and tree models");
+  if (tp->stack) return stack_vjp(tp, x_out_bar, x0_bar, u_bar, param_bar, stream);
   return params_impl(tp, x_out_bar, x0_bar, u_bar, param_bar, dmx::kParams, stream);
 }
 

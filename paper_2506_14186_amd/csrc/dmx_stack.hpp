@@ -81,6 +81,8 @@ struct StackArgs {
   int one_model;  // every world is models[0], offsets from the tables
   long long x_stride, u_stride, t_stride;
   int cap_uniform;
+  // model-parameter cotangents [W][kParams] of the reverse sweep, or null
+  double* pbar;
 };
 
 // per-world layout of a batch (tables, or the uniform strides)
@@ -197,6 +199,29 @@ DMX_DEV double stack_imp(const StackModel& m, double r, double* ddr) {
   const double y = spline01(x, m.cf[3], m.cf[4], m.ssc[2], m.ssc[3], &dy);
   *ddr = dy * m.iwid[1] * (m.cf[0] - m.cf[1]);
   return m.cf[1] + y * (m.cf[0] - m.cf[1]);
+}
+// d(r) of the penetration spline (r < 0) in the solimp parameters (d0,
+// dwidth, width, midpoint, power); zero for r >= 0 (the contacts-from-distance
+// spline has its own parameters): d = d0 + y (dwidth - d0), x = -r / width,
+// y = x^p / mid^(p-1) below the midpoint, 1 - (1-x)^p / (1-mid)^(p-1) above
+DMX_DEV void stack_imp_solimp_grad(const StackModel& m, double r, double* g) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) g[i] = 0.0;
+  if (r >= 0.0) return;
+  const double x = -r * m.iwid[0], mid = m.si[3], pw = m.si[4], span = m.si[1] - m.si[0];
+  double dy;
+  const double y = spline01(x, mid, pw, m.ssc[0], m.ssc[1], &dy);
+  g[0] = 1.0 - y;
+  g[1] = y;
+  if (x >= 1.0) return;
+  g[2] = -span * dy * x * m.iwid[0];
+  if (x <= mid) {
+    g[3] = -span * (pw - 1.0) * y / mid;
+    g[4] = span * y * log(x / mid);
+  } else {
+    g[3] = -span * (pw - 1.0) * (1.0 - y) / (1.0 - mid);
+    g[4] = -span * (1.0 - y) * log((1.0 - x) / (1.0 - mid));
+  }
 }
 DMX_DEV double stack_softplus(double z, double beta, double* dsp) {
   const double bz = beta * z;

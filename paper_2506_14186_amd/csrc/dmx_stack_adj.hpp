@@ -31,8 +31,10 @@ struct PairBar {
 
 // Reverse of Phi over contact c of this pair lane (active edges `act`) into
 // pb; S.vec[kVecD / kVecX / kVecV] hold the generalized lambda, x*, v.
+// hp (optional, [kParams]): += the contact parameters' cotangents (friction,
+// solref, solimp, one value for every pair of the world).
 DMX_DEV void contact_phi_vjp(const StackModel& m, const StackLds& S, const StackRole& ro, const PairSlots& ps,
-                             int j, unsigned act, bool cfd, double beta, PairBar& pb) {
+                             int j, unsigned act, bool cfd, double beta, PairBar& pb, double* hp = nullptr) {
   const int b1 = ro.pb1, b2 = ro.pb2, c = ps.off + j;
   const bool two = b1 >= 0;
   const double ahat = ps.ahat;
@@ -64,16 +66,19 @@ DMX_DEV void contact_phi_vjp(const StackModel& m, const StackLds& S, const Stack
   const double d = stack_imp(m, r, &ddr);
   const double D = d / (ahat * (1.0 - d));
   const double dDdd = 1.0 / (ahat * (1.0 - d) * (1.0 - d));
-  double pterm, dpdr;
+  double pterm, dpdr, ptd;  // ptd: d pterm / d(impedance) / kscale
   if (cfd) {
     double dsp;
     const double sp = stack_softplus(-r, beta, &dsp);
     pterm = d * m.kscale * sp;
     dpdr = m.kscale * (ddr * sp - d * dsp);
+    ptd = sp;
   } else {
     pterm = -d * m.kscale * r;
     dpdr = -m.kscale * (ddr * r + d);
+    ptd = -r;
   }
+  double mub = 0.0, bb = 0.0;  // friction and damping-coefficient cotangents
   V3 ub[3] = {mk3(0.0, 0.0, 0.0), mk3(0.0, 0.0, 0.0), mk3(0.0, 0.0, 0.0)};
   V3 nb = mk3(0.0, 0.0, 0.0), t1b = mk3(0.0, 0.0, 0.0), t2b = mk3(0.0, 0.0, 0.0);
   double Pbar = 0.0, Dbar = 0.0;
@@ -93,6 +98,30 @@ DMX_DEV void contact_phi_vjp(const StackModel& m, const StackLds& S, const Stack
     const V3 deb = Lb * u[kVecD] + Xb * u[kVecX] + Vb * u[kVecV];
     nb += deb;
     if (e < 2) t1b += sg * deb; else t2b += sg * deb;
+    if (hp) {
+      const double tdeb = dot(e < 2 ? t1 : t2, deb);
+      mub += (e & 1) ? -tdeb : tdeb;  // the edge direction n +- mu t
+      bb -= D * L * Vv;
+    }
+  }
+  if (hp) {
+    // friction also through D (A-hat = (1 + mu^2) w); solref through a_ref's
+    // b = 2 / (dwidth t_c) and k = 1 / (dwidth^2 t_c^2 dr^2); solimp through
+    // d(r) in D and the position term, dwidth also through b and k
+    const double dw = m.si[1];
+    const double tc = 2.0 / (dw * m.bcoef);
+    const double dr = 1.0 / (dw * tc * sqrt(m.kscale));
+    const double kb = Pbar * d * ptd;
+    const double sb = m.bcoef * bb + 2.0 * m.kscale * kb;
+    hp[3] += mub + Dbar * (-2.0 * m.mu * D / (1.0 + m.mu * m.mu));
+    hp[4] -= sb / tc;
+    hp[5] -= 2.0 * m.kscale * kb / dr;
+    const double dbar = Dbar * dDdd + Pbar * m.kscale * ptd;
+    double gs[5];
+    stack_imp_solimp_grad(m, r, gs);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) hp[7 + i] += dbar * gs[i];
+    hp[8] -= sb / dw;
   }
   const double rb = Pbar * dpdr + Dbar * dDdd * ddr;
   nb += make_frame_vjp(n, t1b, t2b);
@@ -153,9 +182,13 @@ DMX_DEV void pose_bar(const double* R, V3 cb, const double* Rb, double* out) {
 // stage acceleration xs (unless cfd: then the contacts-from-distance field's
 // own acceleration, solved here) and the cotangent ab: cotangents of the
 // state (qb: 3 or 4, vb: 3) and of this lane's generalized forces (tb).
+// hp (optional, [kParams]): += this lane's share of the model parameters'
+// cotangents (contact parameters on pair lanes; the cubes' common mass on dof
+// lanes: inertia, bias and D all scale with it, so m_bar = -lam . tau / m).
 DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro, const double* yq,
                            const double* yv, const double* tau, const double* xs_in, const double* ab, bool cfd,
-                           double beta, int maxit, double* qb, double* vb, double* tb, StackStat& st) {
+                           double beta, int maxit, double* qb, double* vb, double* tb, StackStat& st,
+                           double* hp = nullptr) {
   PairSlots ps = stack_setup(m, S, ro, yq, yv, cfd, st, true);
   double a0[3], xs[3];
   stack_a0(m, ro, yv, tau, a0);
@@ -203,7 +236,7 @@ DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro
   if (ro.pair) {
     for (int j = 0; j < ps.cnt; ++j) {
       const unsigned a = (ps.act >> (4 * j)) & 15u;
-      if (a) contact_phi_vjp(m, S, ro, ps, j, a, cfd, beta, pb);
+      if (a) contact_phi_vjp(m, S, ro, ps, j, a, cfd, beta, pb, hp);
     }
   }
   double pose1[6] = {0, 0, 0, 0, 0, 0}, pose2[6] = {0, 0, 0, 0, 0, 0};
@@ -254,6 +287,7 @@ DMX_DEV void stack_acc_vjp(const StackModel& m, StackLds& S, const StackRole& ro
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) tb[j] = lam[j];
+    if (hp) hp[6] -= (lam[0] * tau[0] + lam[1] * tau[1] + lam[2] * tau[2]) * m.imass;
   }
   wave_fence();
 }
@@ -285,7 +319,9 @@ DMX_DEV void stack_qplus_vjp(const StackRole& ro, const double* yq, const double
   dqb[2] = s * eb.z + g * th.z;
 }
 
-template <bool RECOMPUTE>
+// PAR: the model parameters' cotangents are accumulated and stored to a.pbar
+// (a template flag: the plain reverse sweep carries none of their registers).
+template <bool RECOMPUTE, bool PAR = false>
 DMX_DEV void stack_adj_world(const StackModel& m, StackLds& S, const StackArgs& a, int w) {
   const StackRole ro = stack_role(m);
   const SolverOpts& o = a.o;
@@ -302,8 +338,14 @@ DMX_DEV void stack_adj_world(const StackModel& m, StackLds& S, const StackArgs& 
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     for (int i = ro.lane; i < NX; i += 64) x0b[i] = nan;
     if (ubw) for (size_t i = ro.lane; i < nut; i += 64) ubw[i] = nan;
+    if (PAR && ro.lane < kParams) a.pbar[(size_t)w * kParams + ro.lane] = nan;
     return;
   }
+  // this lane's share of the model parameters' cotangents, summed over all
+  // stages and steps (one wavefront sum at the end)
+  double hacc[PAR ? kParams : 1];
+#pragma unroll
+  for (int i = 0; i < (PAR ? kParams : 1); ++i) hacc[i] = 0.0;
   if (ubw) for (size_t i = ro.lane; i < nut; i += 64) ubw[i] = 0.0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
@@ -402,7 +444,8 @@ DMX_DEV void stack_adj_world(const StackModel& m, StackLds& S, const StackArgs& 
           xs[j] = v;
           abi[j] = g;
         }
-        stack_acc_vjp(m, S, ro, Yq, Yv, tau, xs, abi, o.cfd != 0, o.beta, o.newton_maxit, Yb_q, Yb_v, tb, st);
+        stack_acc_vjp(m, S, ro, Yq, Yv, tau, xs, abi, o.cfd != 0, o.beta, o.newton_maxit, Yb_q, Yb_v, tb, st,
+                      PAR ? hacc : nullptr);
 #pragma unroll
         for (int j = 0; j < 3; ++j) tbacc[j] += tb[j];
       }
@@ -430,6 +473,14 @@ DMX_DEV void stack_adj_world(const StackModel& m, StackLds& S, const StackArgs& 
   }
   if (cur_k >= 0) flush_ubar(cur_k);
   store_state(m, ro, x0b, ybq, ybv);
+  if constexpr (PAR) {
+    wave_sum<kParams>(hacc);
+    // the cubes' half sizes are not differentiated in stack worlds
+    hacc[0] = hacc[1] = hacc[2] = __longlong_as_double(0x7ff8000000000000ll);
+#pragma unroll
+    for (int i = 0; i < kParams; ++i)
+      if (ro.lane == i) a.pbar[(size_t)w * kParams + i] = hacc[i];
+  }
   if (a.adj_counters) {
     double c[kAdjCounters] = {(double)st.u_step, (double)st.u_vjp, (double)st.u_vcon, (double)st.u_vedge};
     wave_sum<kAdjCounters>(c);
@@ -438,13 +489,13 @@ DMX_DEV void stack_adj_world(const StackModel& m, StackLds& S, const StackArgs& 
   }
 }
 
-template <bool RECOMPUTE>
+template <bool RECOMPUTE, bool PAR = false>
 __global__ void __launch_bounds__(64) stack_adj_kernel(StackArgs a) {
   __shared__ StackLds S;
   for (bool first = true;; first = false) {
     const int w = stack_take(a, nullptr, first);
     if (w < 0) break;
-    stack_adj_world<RECOMPUTE>(st_model(a, w), S, a, w);
+    stack_adj_world<RECOMPUTE, PAR>(st_model(a, w), S, a, w);
   }
 }
 

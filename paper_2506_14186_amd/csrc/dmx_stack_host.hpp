@@ -11,6 +11,9 @@ long long stack_resident();
 // launch (work queue when a.queue is set), or one launch per world (plain)
 void stack_fwd(const dmx::StackArgs& a, hipStream_t s, int plain);
 void stack_adj(const dmx::StackArgs& a, hipStream_t s, int plain);
+// reverse sweep that also accumulates the model parameters' cotangents into
+// a.pbar (kern_stack_params.hip)
+void stack_adj_params(const dmx::StackArgs& a, hipStream_t s, int plain);
 // forward rollout then reverse sweep of each world in one launch (a.xbar given)
 void stack_grad(const dmx::StackArgs& a, hipStream_t s, int plain);
 // accelerations at n independent states of one model

@@ -298,6 +298,10 @@ DMX_DEV int stack_take(const StackArgs& a, int* next_static, bool first) {
   return a.order ? a.order[idx] : idx;
 }
 
+// The two plain (non-template) kernels below are defined in one translation
+// unit only (kern_stack.hip); other units that use these headers define
+// DMX_STACK_KERNELS_ELSEWHERE.
+#ifndef DMX_STACK_KERNELS_ELSEWHERE
 __global__ void __launch_bounds__(64) stack_fwd_kernel(StackArgs a) {
   __shared__ StackLds S;
   for (bool first = true;; first = false) {
@@ -332,5 +336,6 @@ __global__ void __launch_bounds__(64) stack_acc_kernel(const StackModel* __restr
   }
   if (ro.lane == 0) status[w] = st.status;
 }
+#endif  // DMX_STACK_KERNELS_ELSEWHERE
 
 }  // namespace dmx

@@ -415,6 +415,17 @@ def rollout_batch_vjp(tape, x_out_bar):
     return x0b, ub
 
 
+def rollout_batch_vjp_params(tape, x_out_bar):
+    """Packed x0_bar, u_bar and the model-parameter gradient [W, 12] (columns
+    PARAMS) of sum(x_out_bar * x_out) for an uneven batch."""
+    xb = x_out_bar.contiguous()
+    x0b = torch.empty_like(xb)
+    ub = torch.empty(tape.nu, dtype=torch.float64, device=xb.device) if tape.nu else None
+    pb = torch.empty((tape.W, len(PARAMS)), dtype=torch.float64, device=xb.device)
+    _check(_lib.dmx_rollout_vjp_params(tape.h, _ptr(xb), _ptr(x0b), _ptr(ub), _ptr(pb), _stream()))
+    return x0b, ub, pb
+
+
 def accel(model, x, tau=None, cfd=False):
     """Accelerations F(x) at independent states x [n, nx] (and generalized forces tau [n, nv])."""
     x = x.contiguous()

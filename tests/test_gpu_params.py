@@ -46,8 +46,9 @@ def _shifted(desc, j, delta):
     ratio, 7-11 solimp: in every contact pair; 6 the body's mass) shifted by
     delta."""
     d = copy.deepcopy(desc)
-    if j == 6:
-        d["bodies"][0]["inertial"]["mass"] += delta
+    if j == 6:  # every body (the cubes of a stack share one mass)
+        for b in d["bodies"]:
+            b["inertial"]["mass"] += delta
         return d
     for p in d["pairs"]:
         if j == 3:
@@ -373,3 +374,58 @@ def test_tree_otd_contact_parameter_gradient(D, oracle):
     assert smooth.sum() >= len(cols)
     assert e_fd[smooth].max() <= 5e-3
     assert e_dto.max() <= 5e-3
+
+
+def test_stack_parameter_gradient_matches_oracle_differences(D, oracle):
+    """Stack worlds (an uneven batch of 2- and 3-cube stacks, a control force
+    and torque on the top cube): friction, solref, solimp and the cubes'
+    common mass through the stack reverse sweep, against the oracle's
+    frozen-step differences as for single bodies; the half sizes are NaN (not
+    differentiated in stack worlds), the state and control gradients are
+    bitwise the plain sweep's."""
+    ks = (2, 3)
+    rng = np.random.default_rng(9)
+    descs = [W.model_stack(k, ctrl=True) for k in ks]
+    xs = [W.stack_state(rng.normal(0.0, 0.02, size=(k, 2))) for k in ks]
+    us = [rng.uniform(-2.0, 2.0, size=(1, 6)) for _ in ks]
+    T = 0.05
+    models = [D.Model(d) for d in descs]
+    res = D.rollout_batch(models, _t(np.concatenate(xs)), _t(np.concatenate([u.ravel() for u in us])), 1, T,
+                          opts=D.default_opts(tape_steps=8192), tape=True)
+    assert (res["status"].cpu().numpy() == 0).all()
+    xbs = [np.concatenate([np.tile([1.0, 0.5, 2.0, 0, 0, 0, 0], k), np.zeros(6 * k)]) for k in ks]
+    xb = _t(np.concatenate(xbs))
+    gx, gu, gp = D.rollout_batch_vjp_params(res["tape"], xb)
+    gx0, gu0 = D.rollout_batch_vjp(res["tape"], xb)
+    np.testing.assert_array_equal(gx.cpu().numpy(), gx0.cpu().numpy())
+    np.testing.assert_array_equal(gu.cpu().numpy(), gu0.cpu().numpy())
+    gp = gp.cpu().numpy()
+    assert np.isnan(gp[:, :3]).all()
+    recs, n = res["tape"].world_records()
+    cols = (3, 4, 5, 6, 7, 8, 9, 10, 11)
+
+    def central(rel):
+        fd = np.zeros((len(ks), len(cols)))
+        for w in range(len(ks)):
+            forced = np.ascontiguousarray(recs[w][:, :2])[None]
+            for c, j in enumerate(cols):
+                eps = _step(descs[w], j, rel)
+                vals = []
+                for sg in (+1, -1):
+                    om = oracle.Model(_shifted(descs[w], j, sg * eps))
+                    r = om.grad_forced_batch(xs[w][None], us[w][None], 1, T, xbs[w][None], forced,
+                                             np.array([n[w]], np.int32), n_threads=1)
+                    vals.append(float(np.sum(xbs[w] * r["x"][0])))
+                fd[w, c] = (vals[0] - vals[1]) / (2 * eps)
+        return fd
+
+    fd6, fd7 = central(1e-6), central(1e-7)
+    g = gp[:, list(cols)]
+    scale = np.maximum(np.abs(fd7).max(axis=0, keepdims=True), 1e-12)
+    smooth = np.abs(fd6 - fd7) / scale <= 2e-5
+    err = np.abs(g - fd7) / scale
+    print(f"stacks: friction/solref/mass/solimp gradient vs oracle differences: max rel err {err[smooth].max():.2e} "
+          f"over {int(smooth.sum())}/{smooth.size} converged entries (all entries {err.max():.2e})\n{g}\n{fd7}")
+    assert smooth.mean() >= 0.8
+    assert err[smooth].max() <= 1e-4
+    assert err.max() <= 2e-3
