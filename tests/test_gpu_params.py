@@ -429,3 +429,47 @@ def test_stack_parameter_gradient_matches_oracle_differences(D, oracle):
     assert smooth.mean() >= 0.8
     assert err[smooth].max() <= 1e-4
     assert err.max() <= 2e-3
+
+
+def test_stack_friction_identification(D):
+    """Friction identified from stacks (the parameter-gradient path of stack
+    batches in use): 2-cube stacks whose top cube is pushed sideways past the
+    friction limit; synthetic final positions generated at mu 0.6; a
+    sign-based step (Rprop: the step grows by 1.2 while the gradient keeps its
+    sign and halves when it flips) on their mean squared error recovers mu
+    within 1% from 0.4."""
+    import torch
+    rng = np.random.default_rng(21)
+    n, T, true_mu = 16, 0.3, 0.6
+    xs = [W.stack_state(rng.normal(0.0, 0.005, size=(2, 2))) for _ in range(n)]
+    u = np.zeros((n, 6))
+    ang = rng.uniform(0.0, 2.0 * np.pi, n)
+    mag = rng.uniform(7.0, 10.0, n)  # past mu m g = 5.9 N at the true friction
+    u[:, 0], u[:, 1] = mag * np.cos(ang), mag * np.sin(ang)
+    x0t, ut = _t(np.concatenate(xs)), _t(u.ravel())
+    top = (7, 8, 9)  # the top cube's position in a world's 26 state doubles
+    sel = torch.tensor([26 * w + t for w in range(n) for t in top], device="cuda")
+
+    def run(mu, tape=False):
+        models = [D.Model(W.model_stack(2, mu=mu, ctrl=True))] * n
+        return D.rollout_batch(models, x0t, ut, 1, T, opts=D.default_opts(tape_steps=8192), tape=tape)
+
+    obs = run(true_mu)["x"][sel].clone()
+    mu, step, g_prev = 0.4, 0.05, 0.0
+    hist = []
+    for it in range(1, 41):
+        r = run(mu, tape=True)
+        assert int(r["status"].abs().sum()) == 0
+        d = r["x"][sel] - obs
+        loss = float((d * d).sum() / n)
+        xb = torch.zeros_like(x0t)
+        xb[sel] = 2.0 * d / n
+        _, _, gp = D.rollout_batch_vjp_params(r["tape"], xb)
+        g = float(gp[:, 3].sum())
+        step = step * 0.5 if g * g_prev < 0.0 else step * 1.2
+        mu -= np.sign(g) * step
+        g_prev = g
+        hist.append((it, mu, loss))
+    for it, mm, loss in hist[::10] + [hist[-1]]:
+        print(f"iteration {it}: friction {mm:.4f}, loss {loss:.3e}")
+    assert abs(mu - true_mu) / true_mu < 1e-2, mu
