@@ -109,3 +109,45 @@ def test_gradient_error_follows_tolerance(D, oracle):
     med = {r[0]: r[2] for r in rows}
     assert loss[1e-9] <= 1e-5 and loss[1e-9] <= 1e-3 * loss[1e-3]
     assert med[1e-9] <= 2e-2 and med[1e-9] <= 0.1 * med[1e-5]
+
+
+def test_friction_gradient_error_follows_tolerance(D, oracle):
+    """The same tosses and loss, the gradient with respect to the friction
+    coefficient (a model parameter, App. E.2): ground truth from central
+    differences of the oracle's adaptive solve at rtol = atol = 1e-12; the
+    GPU's discrete-adjoint and continuous-adjoint parameter gradients at
+    rtol = atol from 1e-2 to 1e-9.  The error must fall with the tolerance."""
+    import copy
+    import torch
+    desc = toss_model()
+    x0 = toss_states()
+    xb = np.zeros((N, 13))
+    xb[:, 0] = 1.0
+    mu = desc["pairs"][0]["mu"]
+    vals = []
+    for s in (+1, -1):
+        d = copy.deepcopy(desc)
+        d["pairs"][0]["mu"] = mu + s * 1e-6
+        vals.append(oracle.Model(d).rollout_batch(x0, None, 1, 1.0, n_threads=16, rtol=1e-12, atol=1e-12)["x"][:, 0])
+    g_true = (vals[0] - vals[1]) / 2e-6
+    model = D.Model(desc)
+    x0t = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    xbt = torch.tensor(xb, dtype=torch.float64, device="cuda")
+    rows = []
+    for rtol in RTOLS:
+        opts = D.default_opts(rtol=rtol, atol=rtol, tape_steps=65536, max_attempts=1000000, tape_stages=1)
+        r = D.rollout(model, x0t, None, 1, 1.0, opts=opts, tape=True)
+        assert int(r["status"].abs().sum()) == 0
+        _, _, pd = D.rollout_vjp_params(r["tape"], xbt)
+        _, _, po = D.rollout_vjp_otd_params(r["tape"], xbt)
+        scale = np.abs(g_true).max()
+        e_d = np.abs(pd.cpu().numpy()[:, 3] - g_true) / scale
+        e_o = np.abs(po.cpu().numpy()[:, 3] - g_true) / scale
+        rows.append((rtol, float(np.median(e_d)), float(e_d.max()), float(np.median(e_o)), float(e_o.max())))
+    print("\n| rtol | dL/dmu error, discrete adjoint (median) | (max) | continuous adjoint (median) | (max) |")
+    for row in rows:
+        print(f"| {row[0]:.0e} | {row[1]:.2e} | {row[2]:.2e} | {row[3]:.2e} | {row[4]:.2e} |")
+    med = {r[0]: r[1] for r in rows}
+    last = rows[-1]
+    assert med[1e-9] <= 1e-2 * med[1e-3]
+    assert last[3] <= 1e-5 and last[2] <= 1e-3 and last[4] <= 1e-3
