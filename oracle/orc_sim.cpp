@@ -1481,6 +1481,17 @@ static int otd_world(const Model& m, const double* x0, const double* u, int n_in
     }
     qplus(m, y, dq.data(), xo);
   };
+  // start of the last accepted forward step that begins before t: the
+  // adjoint's steps end on the forward's step boundaries, never across them
+  // (reading of App. C.2: the adjoint chooses its own steps, within each step
+  // of the forward whose continuous extension it reads, so that the short
+  // steps the forward took through a contact phase are never skipped)
+  auto step_start = [&](double t) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i)
+      if (t_of(i) < t) s = t_of(i);
+    return s;
+  };
   std::vector<double> lam(xbar, xbar + nx), lamn(nx), Lam(nx), xs(nx), e(nx);
   std::vector<std::vector<double>> G(7, std::vector<double>(nx)), GU(7, std::vector<double>(std::max(nu, 1)));
   for (size_t i = 0; i < nut; ++i) ubar[i] = 0.0;
@@ -1493,8 +1504,9 @@ static int otd_world(const Model& m, const double* x0, const double* u, int n_in
     double t = (double)(kk + 1) * dt;
     bool have_g1 = false;
     while (t > tlo) {
-      const bool landing = t - 1.01 * hprop <= tlo;
-      const double H = landing ? t - tlo : hprop;
+      const double lo = std::max(tlo, step_start(t));
+      const bool landing = t - 1.01 * hprop <= lo;
+      const double H = landing ? t - lo : hprop;
       if (attempts >= o.max_attempts) { status |= ORC_MAX_STEPS; break; }
       ++attempts;
       for (int i = 0; i < 7; ++i) {
@@ -1534,7 +1546,7 @@ static int otd_world(const Model& m, const double* x0, const double* u, int n_in
         G[0] = G[6];
         GU[0] = GU[6];
         have_g1 = true;
-        t = landing ? tlo : t - H;
+        t = landing ? lo : t - H;
         ++accepted;
       }
       hprop = std::max(hnext, hmin);

@@ -900,6 +900,18 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     }
     P::qplus(yc, dq, x);
   };
+  // start of the last accepted forward step that begins before tt: the
+  // adjoint's steps end on the forward's step boundaries, never across them,
+  // so the short steps the forward took through a contact phase are never
+  // skipped by one long adjoint step
+  int nlo = N - 1;
+  auto step_start = [&](double tt) {
+    int n = nlo;
+    while (n > 0 && !(tape_w[(size_t)n * a.rec] < tt)) --n;
+    while (n < N - 1 && tape_w[(size_t)(n + 1) * a.rec] < tt) ++n;
+    nlo = n;
+    return tape_w[(size_t)n * a.rec];
+  };
   double hprop = tape_w[(size_t)(N - 1) * a.rec + 1], eprev = 1.0;
   long long attempts = 0;
   bool failed = false;
@@ -912,8 +924,9 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
     double t = (double)(kk + 1) * a.dt;
     bool have_g1 = false;
     while (t > tlo) {
-      const bool landing = t - 1.01 * hprop <= tlo;
-      const double H = landing ? t - tlo : hprop;
+      const double lo = fmax(tlo, step_start(t));
+      const bool landing = t - 1.01 * hprop <= lo;
+      const double H = landing ? t - lo : hprop;
       if (attempts >= o.max_attempts) { failed = true; break; }
       ++attempts;
 #pragma unroll 1
@@ -1005,7 +1018,7 @@ DMX_DEV void otd_world(const typename P::Model& m, const AdjArgs& a, int w, int 
         for (int d = 0; d < NV; ++d) TB[0][d] = TB[6][d];
         wave_fence();
         have_g1 = true;
-        t = landing ? tlo : t - H;
+        t = landing ? lo : t - H;
         eprev = et;
         hnext = quantize_step(fac * H, o.h_levels);
         if (tl == 0) st.u_step++;

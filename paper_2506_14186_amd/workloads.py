@@ -82,6 +82,22 @@ def model_sphere(radius=0.1, mass=1.0, mu=1.0, tc=0.002, solimp=(0.9, 0.95, 0.00
     }
 
 
+def model_capsule(radius=0.05, half_length=0.1, mass=1.0, mu=0.8, tc=0.005, solimp=None):
+    """Single free capsule (axis along its body z) above a plane (capsule toss)."""
+    return {
+        "name": "capsule",
+        "gravity": list(GRAVITY),
+        "bodies": [{"parent": -1, "pos": [0.0, 0.0, 0.0], "quat": [1.0, 0.0, 0.0, 0.0],
+                    "inertial": {"type": "capsule", "size": [radius, half_length, 0.0], "mass": mass},
+                    "joints": [{"type": "free", "axis": [0.0, 0.0, 1.0], "pos": [0.0, 0.0, 0.0]}]}],
+        "geoms": [_plane(),
+                  {"body": 0, "type": "capsule", "size": [radius, half_length, 0.0], "pos": [0.0, 0.0, 0.0],
+                   "quat": [1.0, 0.0, 0.0, 0.0]}],
+        "pairs": [_pair(0, 1, mu, tc, solimp)],
+        "ctrl": {"dofs": []},
+    }
+
+
 def model_cube_corners(half=0.1, mass=1.0, corner_radius=0.01, mu=0.8, tc=0.001, solimp=None,
                        ctrl=False):
     """Free cube whose contacts are 8 corner spheres against a plane."""

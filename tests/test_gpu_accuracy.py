@@ -151,3 +151,50 @@ def test_friction_gradient_error_follows_tolerance(D, oracle):
     last = rows[-1]
     assert med[1e-9] <= 1e-2 * med[1e-3]
     assert last[3] <= 1e-5 and last[2] <= 1e-3 and last[4] <= 1e-3
+
+
+
+TOSS_SOLIMP = (0.0, 0.95, 0.001, 0.5, 2.0)
+PRIMITIVES = {
+    "sphere": lambda: W.model_sphere(radius=0.1, mu=0.8, tc=0.005, solimp=TOSS_SOLIMP),
+    "capsule": lambda: W.model_capsule(radius=0.05, half_length=0.1, mu=0.8, tc=0.005, solimp=TOSS_SOLIMP),
+}
+
+
+@pytest.mark.parametrize("prim", sorted(PRIMITIVES))
+def test_primitive_toss_gradient_error_follows_tolerance(D, oracle, prim):
+    """The object tosses of the other primitives (sphere, capsule; the paper's
+    tosses of several primitives, Fig. 13) with the same contact setting,
+    throws and loss as the box toss above: the toss distance's gradient with
+    respect to v_x against the oracle's at rtol 1e-12, for both adjoints, at
+    rtol = atol from 1e-2 to 1e-9."""
+    import torch
+    desc = PRIMITIVES[prim]()
+    x0 = toss_states()
+    xb = np.zeros((N, 13))
+    xb[:, 0] = 1.0
+    ref = oracle.Model(desc).grad_batch(x0, None, 1, 1.0, xb, n_threads=16, rtol=1e-12, atol=1e-12)
+    assert (np.asarray(ref["status"]) == 0).all()
+    g_true, x_true = ref["x0bar"][:, 7], ref["x"][:, 0]
+    model = D.Model(desc)
+    x0t = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    xbt = torch.tensor(xb, dtype=torch.float64, device="cuda")
+    rows = []
+    for rtol in RTOLS:
+        opts = D.default_opts(rtol=rtol, atol=rtol, tape_steps=65536, max_attempts=1000000, tape_stages=1)
+        r = D.rollout(model, x0t, None, 1, 1.0, opts=opts, tape=True)
+        assert int(r["status"].abs().sum()) == 0
+        g, _ = D.rollout_vjp(r["tape"], xbt)
+        go, _ = D.rollout_vjp_otd(r["tape"], xbt)
+        e_d = np.abs(g.cpu().numpy()[:, 7] - g_true) / np.abs(g_true)
+        e_o = np.abs(go.cpu().numpy()[:, 7] - g_true) / np.abs(g_true)
+        err_l = float(np.max(np.abs(r["x"].cpu().numpy()[:, 0] - x_true)))
+        rows.append((rtol, err_l, float(np.median(e_d)), float(e_d.max()), float(np.median(e_o)), float(e_o.max())))
+    print(f"\n{prim}: | rtol | loss error (m, max) | discrete adjoint (median) | (max) | continuous adjoint (median) "
+          f"| (max) |")
+    for row in rows:
+        print(f"| {row[0]:.0e} | {row[1]:.2e} | {row[2]:.2e} | {row[3]:.2e} | {row[4]:.2e} | {row[5]:.2e} |")
+    loss = {r[0]: r[1] for r in rows}
+    med = {r[0]: r[2] for r in rows}
+    assert loss[1e-9] <= 1e-5 and loss[1e-9] <= 1e-3 * loss[1e-3]
+    assert med[1e-9] <= 2e-2 and med[1e-9] <= max(0.1 * med[1e-5], 1e-8)
