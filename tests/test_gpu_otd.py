@@ -11,8 +11,9 @@ moves both results by their discretization error, which for these contact-
 rich tumbles is 1e-3 to 1 at rtol 1e-6 (the cube toss prints the GPU-oracle
 difference at 1e-6, 1e-8 and 1e-10: it shrinks about 100x per two decades).  Cases: the paper's cube toss
 (box geom), the corner-sphere cube of the benchmark batch with 16-lane
-teams, the legged chain with controls (state and control gradients), and
-the straight-through CFD adjoint of a sphere skimming the plane, which also
+teams, the legged chain with controls (state and control gradients),
+bouncing sphere tosses with spin, and the straight-through CFD adjoint of a
+sphere skimming the plane, which also
 matches the small-step limit of the discrete straight-through gradient
 (where the discrete adjoint along the forward's few large steps does not).
 """
@@ -130,3 +131,21 @@ def test_otd_refuses_unsupported_tapes(D):
     with pytest.raises(D.DmxError):
         D._check(D._lib.dmx_rollout_vjp_otd(rb["tape"].h, D._ptr(x), D._ptr(torch.empty_like(x)), None,
                                             D._stream()))
+
+
+def test_otd_bouncing_sphere_tosses_match_oracle(D, oracle):
+    """Spheres thrown onto the plane (bounces between free flights, where the
+    adjoint's steps end on the forward's step boundaries on both sides), at
+    rtol 1e-10: GPU against the oracle's continuous adjoint."""
+    desc = W.model_sphere(radius=0.1, mu=0.8, tc=0.005, solimp=(0.0, 0.95, 0.001, 0.5, 2.0))
+    n = 8
+    x0 = np.zeros((n, 13))
+    x0[:, 2] = 0.3
+    x0[:, 3] = 1.0
+    x0[:, 7] = np.linspace(-3.0, -1.0, n)
+    x0[:, 10] = np.linspace(-5.0, 5.0, n)  # some spin
+    xb = np.zeros((n, 13))
+    xb[:, 0], xb[:, 1], xb[:, 2] = 1.0, 0.5, 2.0
+    _, g, _ = _run(D, desc, x0, None, 1, 1.0, xb, rtol=1e-10, atol=1e-10)
+    ref = oracle.Model(desc).otd_grad_batch(x0, None, 1, 1.0, xb, n_threads=8, rtol=1e-10, atol=1e-10)
+    _compare("bouncing sphere tosses", g, ref["x0bar"])
