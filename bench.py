@@ -777,8 +777,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: worlds are independent and this build runs on a single MI355X; "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: worlds are independent, so a batch shards across GPUs with no exchange "
+              "during a rollout, and the benchmark reports the single-MI355X rate; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

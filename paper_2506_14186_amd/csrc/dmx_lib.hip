@@ -353,7 +353,7 @@ dmx_status dmx_model_create(const dmx_model_desc* d, dmx_model** out) {
     const int t2 = d->geom_type[g2];
     if (t2 != DMX_GEOM_SPHERE && t2 != DMX_GEOM_CAPSULE && t2 != DMX_GEOM_BOX) {
       delete m;
-      return fail(DMX_ERR_UNSUPPORTED, "plane pairs with sphere, capsule or box geoms only in this build");
+      return fail(DMX_ERR_UNSUPPORTED, "contact pairs are a world plane against a sphere, capsule or box geom");
     }
     dmx::PairF& pr = f.pair[p];
     pr.gtype = t2;
