@@ -1,4 +1,5 @@
-"""The newer gradient paths under the batch engine's launch variants: the
+"""The newer gradient paths under the batch engine's launch variants (the
+stack batch's parameter gradient among them): the
 optimize-then-discretize adjoint with ragged horizons and a work queue equals
 each world's own uniform run bit for bit, and the plain one-world-per-launch
 form equals the persistent launch; the box half-size gradient is the same on
@@ -94,3 +95,28 @@ def test_tsit5_adjoint_on_checkpoint_tapes(D):
     err = np.abs(out[0] - out[1]).max() / np.abs(out[1]).max()
     print(f"Tsitouras adjoint, checkpoints vs stages: {err:.2e}")
     assert err <= 1e-10
+
+
+def test_stack_parameter_gradient_on_checkpoint_tapes_and_plain_launches(D):
+    """The stack batch's model-parameter gradient (friction, solref, mass,
+    solimp) on checkpoint tapes (stages solved again in the reverse sweep)
+    against stage tapes, and in the one-world-per-launch form against the
+    persistent launch (bitwise)."""
+    ks = (1, 2, 3)
+    rng = np.random.default_rng(31)
+    descs = [W.model_stack(k, ctrl=True) for k in ks]
+    xs = np.concatenate([W.stack_state(rng.normal(0.0, 0.02, size=(k, 2))) for k in ks])
+    u = rng.uniform(-2.0, 2.0, size=6 * len(ks))
+    xb = np.concatenate([np.concatenate([np.tile([1.0, 0.5, 2.0, 0, 0, 0, 0], k), np.zeros(6 * k)]) for k in ks])
+    models = [D.Model(d) for d in descs]
+    out = {}
+    for name, kw in (("stages", dict(tape_stages=1)), ("checkpoints", dict(tape_stages=0)),
+                     ("plain", dict(tape_stages=1, launch_mode=1))):
+        r = D.rollout_batch(models, _t(xs), _t(u), 1, 0.05, opts=D.default_opts(tape_steps=8192, **kw), tape=True)
+        assert (r["status"].cpu().numpy() == 0).all()
+        _, _, gp = D.rollout_batch_vjp_params(r["tape"], _t(xb))
+        out[name] = gp.cpu().numpy()[:, 3:]
+    np.testing.assert_array_equal(out["plain"], out["stages"])
+    err = np.abs(out["checkpoints"] - out["stages"]).max(axis=0) / np.abs(out["stages"]).max(axis=0)
+    print(f"stack parameter gradient, checkpoints vs stages: {err.max():.2e}")
+    assert err.max() <= 1e-10
