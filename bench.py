@@ -351,9 +351,19 @@ def stack_leg(D, W, args, dev):
             ev[2].record(stream)
 
     two_ms, fwd_ms, adj_ms = (None, None, None)
+    params_ms = None
     if args.two_launch_steps > 0:
         progress("two-launch form ...")
         two_ms, fwd_ms, adj_ms = timed_steps(step2, args.two_launch_steps, 0, stream)
+        # the reverse sweep with the model-parameter cotangents on the tape the
+        # last step left (one launch, events on the stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        D.rollout_batch_vjp_params(tape, xbar)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        params_ms = ev[0].elapsed_time(ev[1])
+        progress(f"reverse sweep with parameter cotangents: {params_ms:.1f} ms")
     # the recorded counters describe the default batch only
     default_batch = (args.stack_worlds, args.kmax, args.stack_horizon, args.max_attempts) == (1024, 32, 1.0, 4096)
     traffic_file = "hbm_traffic_stacks_1024.md" if default_batch else None
@@ -365,6 +375,7 @@ def stack_leg(D, W, args, dev):
            "two_launch": None if two_ms is None else {
                "ms_per_step": round(two_ms, 3), "fwd_ms": round(fwd_ms, 3), "adj_ms": round(adj_ms, 3),
                "value": round(float((nW - int(failed.sum())) * T / (two_ms / 1e3)), 3),
+               "adj_with_params_ms": round(params_ms, 3),
                "roofline": roofline_of(fwd_ms, adj_ms, fwd_flops, adj_flops, "stack_fwd_kernel", "stack_adj_kernel",
                                        traffic_file)},
            "work": {"fwd": fu, "adj": au, "accepted_steps_mean": float(n_acc.mean()),
